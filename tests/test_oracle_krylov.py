@@ -1,0 +1,128 @@
+"""Pins of the oracle's solvers and convergence criteria."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import cfill, efie, krylov, sampling
+from paper_2606_13482_amd.inputs import complex_gaussian, planewave_set
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _c1_like(ico, level=1, k=2.0):
+    rwg = ico(level)
+    Z = cfill.fill(rwg, k)
+    d, e = planewave_set(np.array([[0.0, 0.0, 1.0]]), "theta")
+    b = efie.rhs(rwg, k, d, e)[0]
+    return rwg, Z, b
+
+
+def test_splitmix64_published_vector():
+    want = [int(l, 16) for l in open(os.path.join(GOLDEN, "splitmix64_seed0.txt")) if l.startswith("0x")]
+    g = sampling.SplitMix64(0)
+    assert [g.next() for _ in range(3)] == want
+
+
+def test_floyd_sample_properties():
+    for n, s, seed in ((7680, 512, 1234), (480, 480, 1), (480, 479, 9), (1000, 1, 77)):
+        rows = sampling.sample_rows(n, s, seed)
+        assert len(rows) == min(n, s) and rows == sorted(set(rows))
+        assert rows[0] >= 0 and rows[-1] < n
+    # deterministic per seed, different across seeds
+    assert sampling.sample_rows(7680, 512, 5) == sampling.sample_rows(7680, 512, 5)
+    assert sampling.sample_rows(7680, 512, 5) != sampling.sample_rows(7680, 512, 6)
+
+
+def test_floyd_uniform_marginals():
+    """Every index is drawn with probability S/N (chi-square over 4000 draws)."""
+    n, s, reps = 40, 10, 4000
+    counts = np.zeros(n)
+    for r in range(reps):
+        counts[sampling.sample_rows(n, s, 1000 + r)] += 1
+    expect = reps * s / n
+    chi2 = np.sum((counts - expect) ** 2 / expect)
+    assert chi2 < 80          # 39 dof, p ~ 1e-4
+
+
+def test_full_gmres_equals_lu(ico):
+    """GMRES with m >= N and a tiny tolerance is the exact Krylov solution (N = 120)."""
+    rwg, Z, b = _c1_like(ico, 1)
+    x_lu = krylov.lu_solve(Z, b)
+    x, st = krylov.gmres(Z, b, m=rwg["N"], tol=1e-13)
+    assert st.converged
+    assert np.linalg.norm(x - x_lu) / np.linalg.norm(x_lu) < 1e-11
+    # the Givens estimate tracks the true residual in FP64
+    h = np.array(st.history)
+    assert np.all(np.diff(h) <= 1e-15 * h[0])            # non-increasing within the cycle
+
+
+def test_givens_estimate_matches_true_residual(ico):
+    rwg, Z, b = _c1_like(ico, 2)
+    for m in (5, 12):
+        x, st = krylov.gmres(Z, b, m=m, tol=1e-30, max_mvp=m)
+        true = np.linalg.norm(b - Z @ x) / np.linalg.norm(b)
+        assert abs(st.relres_est - true) < 1e-12
+
+
+def test_restarted_gmres_and_cgnr_reach_lu(ico):
+    rwg, Z, b = _c1_like(ico, 2)
+    x_lu = krylov.lu_solve(Z, b)
+    x, st = krylov.gmres(Z, b, m=30, tol=1e-10)
+    assert st.converged and st.relres_true <= 1e-10
+    assert np.linalg.norm(x - x_lu) / np.linalg.norm(x_lu) < 1e-7
+    x2, st2 = krylov.cgnr(Z, b, tol=1e-10, max_mvp=20000)
+    assert st2.converged and st2.relres_true <= 1e-10
+    assert np.linalg.norm(x2 - x_lu) / np.linalg.norm(x_lu) < 1e-7
+    h = np.array(st2.history)
+    # CGNR minimises ||r|| over nested spaces: non-increasing up to rounding
+    assert np.all(np.diff(h) <= 1e-12)
+
+
+def test_rscc_full_sample_equals_scc(ico):
+    rwg, Z, b = _c1_like(ico, 2)
+    x, _ = krylov.gmres(Z, b, m=30, tol=1e-3)
+    n = b.shape[0]
+    assert abs(krylov.rscc(Z, b, x, n, 1234) - krylov.scc(Z, b, x)) < 1e-15
+
+
+def test_rscc_unbiased(ico):
+    """E[eta^2] over seeds equals the squared standard residual ratio."""
+    rwg, Z, b = _c1_like(ico, 2)
+    x, _ = krylov.gmres(Z, b, m=30, tol=1e-2)
+    s2 = krylov.scc(Z, b, x) ** 2
+    vals = [krylov.rscc(Z, b, x, 48, seed) ** 2 for seed in range(3000)]
+    assert abs(np.mean(vals) / s2 - 1.0) < 0.05
+
+
+def test_zero_rhs_and_stops(ico):
+    rwg, Z, b = _c1_like(ico, 1)
+    x, st = krylov.gmres(Z, np.zeros_like(b))
+    assert st.converged and st.iters == 0 and not np.any(x)
+    x, st = krylov.gmres(Z, b, m=10, tol=1e-14, max_mvp=25)
+    assert not st.converged and st.mvps <= 26
+    x, st = krylov.cgnr(Z, np.zeros_like(b))
+    assert st.converged and not np.any(x)
+
+
+def test_gmres_rscc_criterion(ico):
+    rwg, Z, b = _c1_like(ico, 2)
+    x, st = krylov.gmres(Z, b, m=30, tol=1e-6, crit="rscc", rscc_rows=96)
+    assert st.converged
+    assert krylov.scc(Z, b, x) < 3e-6
+
+
+def test_reciprocity(ico):
+    """e_s . F(r; d, e_i) = e_i . F(-d; -r, e_s) since Z = Z^T (far field of Sec. II)."""
+    rwg, Z, _ = _c1_like(ico, 2)
+    k = 2.0
+    d = np.array([0.3, -0.4, 0.866]); d /= np.linalg.norm(d)
+    ei = np.cross(d, [1.0, 0, 0]); ei /= np.linalg.norm(ei)
+    r = np.array([-0.6, 0.5, 0.2]); r /= np.linalg.norm(r)
+    es = np.cross(r, [0, 0, 1.0]); es /= np.linalg.norm(es)
+    x1 = krylov.lu_solve(Z, efie.rhs(rwg, k, d[None], ei[None])[0])
+    x2 = krylov.lu_solve(Z, efie.rhs(rwg, k, -r[None], es[None])[0])
+    f1 = efie.radiation_vector(rwg, k, x1, r[None])[0] @ es
+    f2 = efie.radiation_vector(rwg, k, x2, -d[None])[0] @ ei
+    assert abs(f1 - f2) / abs(f1) < 1e-12
