@@ -1,0 +1,176 @@
+/* bie.h -- C ABI of the dense EFIE method-of-moments library (libbie.so, gfx950).
+ *
+ * The library follows the paper's statement of the problem (Sec. II): a closed
+ * PEC surface Gamma, meshed by triangles, and a wavenumber k define the
+ * discretised EFIE  T j = e  (eq:discretizedEFIE) with
+ *     T = jk T_A - (jk)^-1 T_Phi                               (eq:efie)
+ *     [T_A]_mn   =  int int f_m(x) . g(x,y) f_n(y)              (eq:matTA)
+ *     [T_Phi]_mn = -int int div f_m(x) g(x,y) div f_n(y)        (eq:matTPhi)
+ *     g(x,y) = exp(-jk|x-y|)/(4 pi |x-y|), time factor exp(+j w t),
+ * in RWG functions without edge-length normalisation, and the excitation
+ * [e]_m = int f_m . e_inc (Sec. II).  "After solving ... using an iterative
+ * solver, the scattered fields are obtained by evaluating the radiation
+ * potentials" (Sec. II): hence the calls operator -> apply -> solve -> far field.
+ *
+ * Conventions for every call
+ *   - Host arrays (const pointers named host) are read during the call only.
+ *   - Device arrays are caller-owned allocations on the operator's device
+ *     (e.g. torch tensors); the library never frees them.
+ *   - Complex data are interleaved (re, im): complex128 = 2 x double,
+ *     complex64 = 2 x float, as in torch.complex128 / torch.complex64.
+ *   - A block of R vectors of length N is stored R x N, each vector
+ *     contiguous (row r starts at offset r*N).
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue
+ *     their kernels on it; calls that return host results synchronise it.
+ *   - Return value: BIE_OK (0), BIE_NOT_CONVERGED (1, a warning: outputs are
+ *     valid), or a negative error code; bie_last_error() returns a message for
+ *     the calling thread.  No C++ exception crosses this interface.
+ *
+ * RWG numbering (a reading; the paper only draws the basis in Sec. VI-A):
+ * one unknown per interior edge, edges sorted lexicographically by
+ * (lower vertex index, higher vertex index); c+ is the triangle that traverses
+ * the edge from the lower to the higher vertex index, c- the other one.
+ */
+#ifndef BIE_H
+#define BIE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    BIE_OK = 0,
+    BIE_NOT_CONVERGED = 1,   /* warning: best iterate returned, see stats */
+    BIE_EINVAL = -1,         /* bad argument (NULL pointer, size, option) */
+    BIE_EMESH = -2,          /* open / non-manifold / mis-oriented mesh, zero-area triangle */
+    BIE_ENOMEM = -3,         /* device allocation failed */
+    BIE_EDEVICE = -4,        /* HIP runtime error */
+    BIE_ENUMERIC = -5        /* NaN or Inf in an input vector */
+};
+
+/* Storage of the impedance matrix. */
+typedef enum {
+    BIE_C128 = 0,   /* complex FP64 fill and storage */
+    BIE_C64 = 1     /* complex FP32 storage; regular pairs integrated in FP32,
+                       touching / near pairs always in FP64 */
+} bie_dtype;
+
+typedef struct bie_op bie_op;   /* opaque: owns the device matrix and workspaces */
+
+typedef struct {
+    int storage;          /* bie_dtype, default BIE_C128 */
+    double near_factor;   /* pairs with centroid distance < near_factor * longest edge
+                             (or sharing a vertex) get singularity subtraction; default 2.0 */
+    int keep_fp64;        /* with storage BIE_C64: also keep the FP64 matrix (for FP64
+                             residuals / iterative refinement); default 0 */
+} bie_fill_opts;
+
+/* Operator: mesh + wavenumber -> dense impedance matrix T on the current device.
+ * (Sec. II, eq:discretizedEFIE, eq:matTA, eq:matTPhi.)
+ *   verts  host, nv x 3 double, vertex coordinates (m)
+ *   tris   host, nt x 3 int32, vertex indices, counter-clockwise seen from outside
+ *   k      wavenumber (rad/m), > 0
+ *   opts   NULL for defaults
+ * Quadrature: Radon's 7-point degree-5 rule on both triangles of every pair;
+ * flagged pairs use subtraction of the static kernel with closed-form inner
+ * integrals, averaged over both orderings, so T is exactly symmetric.
+ * Errors: BIE_EMESH for an invalid mesh, BIE_ENOMEM when N x N does not fit.
+ * The matrix is complete when the call returns (it synchronises `stream`). */
+int bie_op_create(const double *verts, int64_t nv, const int32_t *tris, int64_t nt,
+                  double k, const bie_fill_opts *opts, void *stream, bie_op **out);
+void bie_op_destroy(bie_op *op);
+
+/* Number of unknowns N (= number of edges = 3 nt / 2). */
+int64_t bie_op_n(const bie_op *op);
+
+/* RWG table, host out N x 4 int32: (lower vertex, higher vertex, c+, c-). */
+int bie_op_edges(const bie_op *op, int32_t *out);
+
+/* Flagged (touching or near) triangle pairs p <= q used by the fill.
+ * host out: up to cap pairs as 2 x int32 each; returns the total count
+ * (>= 0) or a negative error code. */
+int64_t bie_op_near_pairs(const bie_op *op, int32_t *out, int64_t cap);
+
+/* Copy of the matrix into a caller buffer.  dst: device, N x N row-major
+ * (T_mn at m*N + n), complex128 if dtype == BIE_C128 (converted from the
+ * stored precision), complex64 if dtype == BIE_C64 (only for BIE_C64 storage). */
+int bie_op_matrix(const bie_op *op, void *dst, int dtype, void *stream);
+
+/* Plane-wave excitation (Sec. II, right-hand side):
+ *   [e]_m = int f_m . p exp(-jk d . r) dS  for R waves.
+ *   dirs  host R x 3, unit propagation directions d
+ *   pols  host R x 3, real unit polarisation vectors p (p . d = 0)
+ *   B     device R x N complex128 (output). */
+int bie_rhs_planewave(const bie_op *op, const double *dirs, const double *pols, int64_t R,
+                      void *B, void *stream);
+
+/* Matrix-vector / matrix-block product (the solver's MVP):
+ *   Y = T X   (conj = 0)   or   Y = T^H X = conj(T conj(X))   (conj = 1, T = T^T)
+ *   X, Y  device R x N, complex128 (vec = BIE_C128) or complex64 (vec = BIE_C64);
+ *         X and Y must not overlap.  Arithmetic in the storage precision with
+ *         accumulation in that precision. */
+int bie_apply(const bie_op *op, const void *X, void *Y, int64_t R, int vec, int conj,
+              void *stream);
+
+typedef enum { BIE_GMRES = 0, BIE_CGNR = 1 } bie_method;
+typedef enum { BIE_SCC = 0, BIE_RSCC = 1 } bie_crit;
+
+typedef struct {
+    int method;          /* bie_method; default BIE_GMRES */
+    int restart;         /* GMRES restart length m (1..500); default 30 */
+    double tol;          /* relative to ||b||_2; default 1e-6 */
+    int64_t max_mvp;     /* cap on products per right-hand side; default 10000 */
+    int crit;            /* bie_crit; default BIE_SCC */
+    int64_t rscc_rows;   /* S, default 512 (min(S, N) used) */
+    uint64_t rscc_seed;  /* default 1234 */
+    int use_x0;          /* 1: X holds the initial guess on entry */
+} bie_solve_opts;
+
+typedef struct {
+    int64_t iters;        /* Krylov iterations */
+    int64_t mvps;         /* products with T or T^H (RSCC checks count S/N, rounded up) */
+    double relres_est;    /* last recursive estimate |g_{j+1}|/||b|| (GMRES) or ||r||/||b|| (CGNR) */
+    double relres_true;   /* last criterion value on the true residual */
+    int converged;        /* criterion met */
+    int checks;           /* criterion evaluations */
+} bie_solve_stat;
+
+/* Solve T x = b for R right-hand sides to the selected criterion.
+ * Criteria (named in the paper's acronym list, not defined there; readings):
+ *   SCC:  ||b - T x||_2 / ||b||_2 <= tol;
+ *   RSCC: sqrt((N/S) sum_{i in S} |b_i - (T x)_i|^2) / ||b||_2 <= tol over S
+ *         rows drawn by Floyd's algorithm from SplitMix64 seeded with
+ *         rscc_seed + (number of earlier checks of that right-hand side).
+ * GMRES(m): Arnoldi with classical Gram-Schmidt applied twice, FP64 Givens
+ * rotations; a cycle ends when the estimate <= tol or j = m, then the
+ * criterion is evaluated on the true residual.  CGNR: CG on T^H T x = T^H b.
+ *   B      device R x N complex128
+ *   X      device R x N complex128 (in: initial guess if use_x0; out: solution)
+ *   stats  host array of R entries (may be NULL)
+ * Returns BIE_NOT_CONVERGED if any right-hand side missed the criterion
+ * within max_mvp, BIE_ENUMERIC if B or X0 holds NaN/Inf.  ||b|| = 0 gives x = 0. */
+int bie_solve(const bie_op *op, const void *B, void *X, int64_t R, const bie_solve_opts *opts,
+              bie_solve_stat *stats, void *stream);
+
+/* Radiation vector F(r) = int j(y) exp(jk r . y) dS of the solutions X for M
+ * unit directions (Sec. II, scattered field from the radiation potentials);
+ * the far field is E_s ~ -jk exp(-jkr)/(4 pi r) (I - r r) . F and the bistatic
+ * RCS (k^2/(4 pi)) |r x F|^2.
+ *   X    device R x N complex128;  obs  host M x 3;  F  device R x M x 3 complex128. */
+int bie_farfield(const bie_op *op, const void *X, int64_t R, const double *obs, int64_t M,
+                 void *F, void *stream);
+
+/* Row sample of the random-sampling criterion: S distinct sorted indices in
+ * [0, N) for `seed` (host out, S int64).  Exposed so callers can reproduce the
+ * rows a given check used. */
+int bie_rscc_rows(int64_t N, int64_t S, uint64_t seed, int64_t *out);
+
+const char *bie_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BIE_H */

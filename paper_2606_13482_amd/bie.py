@@ -1,0 +1,227 @@
+"""ctypes binding of libbie.so (include/bie.h).
+
+Argument marshalling only: every step of fill, excitation, products, solve
+and far field runs in the library's HIP kernels.  torch supplies device
+memory (tensors) and the current stream.  Importing this module loads the
+library and raises if it has not been built (there is no fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch  # noqa: F401  (loads the HIP runtime the library shares)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbie.so")
+
+BIE_OK, BIE_NOT_CONVERGED = 0, 1
+BIE_EINVAL, BIE_EMESH, BIE_ENOMEM, BIE_EDEVICE, BIE_ENUMERIC = -1, -2, -3, -4, -5
+BIE_C128, BIE_C64 = 0, 1
+BIE_GMRES, BIE_CGNR = 0, 1
+BIE_SCC, BIE_RSCC = 0, 1
+
+_ERRNAMES = {BIE_EINVAL: "EINVAL", BIE_EMESH: "EMESH", BIE_ENOMEM: "ENOMEM",
+             BIE_EDEVICE: "EDEVICE", BIE_ENUMERIC: "ENUMERIC"}
+
+
+class BieError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class FillOpts(ctypes.Structure):
+    _fields_ = [("storage", ctypes.c_int), ("near_factor", ctypes.c_double), ("keep_fp64", ctypes.c_int)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int), ("restart", ctypes.c_int), ("tol", ctypes.c_double),
+                ("max_mvp", ctypes.c_int64), ("crit", ctypes.c_int), ("rscc_rows", ctypes.c_int64),
+                ("rscc_seed", ctypes.c_uint64), ("use_x0", ctypes.c_int)]
+
+
+class SolveStat(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int64), ("mvps", ctypes.c_int64), ("relres_est", ctypes.c_double),
+                ("relres_true", ctypes.c_double), ("converged", ctypes.c_int), ("checks", ctypes.c_int)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+# (name, restype, argtypes) for every symbol declared in include/bie.h
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+SYMBOLS = [
+    ("bie_op_create", ctypes.c_int, [_P, _I64, _P, _I64, ctypes.c_double, _P, _P, ctypes.POINTER(_P)]),
+    ("bie_op_destroy", None, [_P]),
+    ("bie_op_n", _I64, [_P]),
+    ("bie_op_edges", ctypes.c_int, [_P, _P]),
+    ("bie_op_near_pairs", _I64, [_P, _P, _I64]),
+    ("bie_op_matrix", ctypes.c_int, [_P, _P, ctypes.c_int, _P]),
+    ("bie_rhs_planewave", ctypes.c_int, [_P, _P, _P, _I64, _P, _P]),
+    ("bie_apply", ctypes.c_int, [_P, _P, _P, _I64, ctypes.c_int, ctypes.c_int, _P]),
+    ("bie_solve", ctypes.c_int, [_P, _P, _P, _I64, _P, _P, _P]),
+    ("bie_farfield", ctypes.c_int, [_P, _P, _I64, _P, _I64, _P, _P]),
+    ("bie_rscc_rows", ctypes.c_int, [_I64, _I64, ctypes.c_uint64, _P]),
+    ("bie_last_error", ctypes.c_char_p, []),
+]
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"{path} not built: run `python -m paper_2606_13482_amd.build` "
+                          "(or __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    for name, res, args in SYMBOLS:
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = load()
+
+
+def _check(rc: int, allow_nc: bool = False) -> int:
+    if rc < 0 or (rc == BIE_NOT_CONVERGED and not allow_nc):
+        raise BieError(rc, _lib.bie_last_error().decode())
+    return rc
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _host(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _dev(t: torch.Tensor, dtype, shape=None):
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise ValueError(f"need a contiguous {dtype} device tensor, got {t.dtype} on {t.device}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"need shape {shape}, got {tuple(t.shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def rscc_rows(n: int, s: int, seed: int) -> np.ndarray:
+    out = np.zeros(min(n, s), np.int64)
+    _check(_lib.bie_rscc_rows(n, s, ctypes.c_uint64(seed), out.ctypes.data_as(ctypes.c_void_p)))
+    return out
+
+
+@dataclass
+class Solve:
+    method: str = "gmres"
+    restart: int = 30
+    tol: float = 1e-6
+    max_mvp: int = 10000
+    crit: str = "scc"
+    rscc_rows: int = 512
+    rscc_seed: int = 1234
+
+    def c(self, use_x0: bool) -> SolveOpts:
+        return SolveOpts({"gmres": BIE_GMRES, "cgnr": BIE_CGNR}[self.method], self.restart, self.tol,
+                         self.max_mvp, {"scc": BIE_SCC, "rscc": BIE_RSCC}[self.crit], self.rscc_rows,
+                         self.rscc_seed, int(use_x0))
+
+
+class Operator:
+    """Dense EFIE operator T of a closed PEC surface at wavenumber k (Sec. II)."""
+
+    def __init__(self, V, T, k: float, storage: str = "c128", near_factor: float = 2.0,
+                 keep_fp64: bool = False, stream=None):
+        V, pv = _host(V, np.float64)
+        T, pt = _host(T, np.int32)
+        opts = FillOpts({"c128": BIE_C128, "c64": BIE_C64}[storage], near_factor, int(keep_fp64))
+        h = ctypes.c_void_p()
+        _check(_lib.bie_op_create(pv, V.shape[0], pt, T.shape[0], float(k), ctypes.byref(opts),
+                                  _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self.k = float(k)
+        self.storage = storage
+        self.N = int(_lib.bie_op_n(h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.bie_op_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def edges(self) -> np.ndarray:
+        out = np.zeros((self.N, 4), np.int32)
+        _check(_lib.bie_op_edges(self._h, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def near_pairs(self) -> np.ndarray:
+        n = int(_lib.bie_op_near_pairs(self._h, None, 0))
+        out = np.zeros((n, 2), np.int32)
+        _lib.bie_op_near_pairs(self._h, out.ctypes.data_as(ctypes.c_void_p), n)
+        return out
+
+    def matrix(self, dtype=torch.complex128, stream=None) -> torch.Tensor:
+        out = torch.empty((self.N, self.N), dtype=dtype, device="cuda")
+        code = BIE_C128 if dtype == torch.complex128 else BIE_C64
+        _check(_lib.bie_op_matrix(self._h, _dev(out, dtype), code, _stream(stream)))
+        return out
+
+    def rhs(self, dirs, pols, stream=None) -> torch.Tensor:
+        d, pd = _host(np.atleast_2d(dirs), np.float64)
+        p, pp = _host(np.atleast_2d(pols), np.float64)
+        R = d.shape[0]
+        B = torch.empty((R, self.N), dtype=torch.complex128, device="cuda")
+        _check(_lib.bie_rhs_planewave(self._h, pd, pp, R, _dev(B, torch.complex128), _stream(stream)))
+        return B
+
+    def apply(self, X: torch.Tensor, conj: bool = False, out: torch.Tensor | None = None, stream=None):
+        X2 = X.reshape(-1, self.N)
+        Y = torch.empty_like(X2) if out is None else out
+        code = BIE_C128 if X2.dtype == torch.complex128 else BIE_C64
+        _check(_lib.bie_apply(self._h, _dev(X2, X2.dtype), _dev(Y, X2.dtype, X2.shape), X2.shape[0], code,
+                              int(conj), _stream(stream)))
+        return Y.reshape(X.shape)
+
+    def solve(self, B: torch.Tensor, opts: Solve | None = None, x0: torch.Tensor | None = None,
+              stream=None, out: torch.Tensor | None = None):
+        opts = opts or Solve()
+        B2 = B.reshape(-1, self.N)
+        R = B2.shape[0]
+        if out is not None:
+            X = out
+        elif x0 is not None:
+            X = x0.reshape(-1, self.N).clone()
+        else:
+            X = torch.empty_like(B2)
+        if x0 is not None and out is not None:
+            X.copy_(x0.reshape(-1, self.N))
+        st = (SolveStat * R)()
+        co = opts.c(x0 is not None)
+        rc = _lib.bie_solve(self._h, _dev(B2, torch.complex128), _dev(X, torch.complex128, B2.shape), R,
+                            ctypes.byref(co), st, _stream(stream))
+        _check(rc, allow_nc=True)
+        return X.reshape(B.shape), [s.as_dict() for s in st]
+
+    def farfield(self, X: torch.Tensor, obs, stream=None) -> torch.Tensor:
+        X2 = X.reshape(-1, self.N)
+        o, po = _host(np.atleast_2d(obs), np.float64)
+        F = torch.empty((X2.shape[0], o.shape[0], 3), dtype=torch.complex128, device="cuda")
+        _check(_lib.bie_farfield(self._h, _dev(X2, torch.complex128), X2.shape[0], po, o.shape[0],
+                                 _dev(F, torch.complex128), _stream(stream)))
+        return F
+
+    def rcs(self, X: torch.Tensor, obs) -> np.ndarray:
+        """Bistatic RCS (k^2/4pi)|r x F|^2 for unit-amplitude incidence."""
+        obs = np.atleast_2d(np.asarray(obs, np.float64))
+        F = self.farfield(X, obs).cpu().numpy()
+        tang = F - np.sum(obs[None] * F, axis=2, keepdims=True) * obs[None]
+        return self.k ** 2 / (4 * np.pi) * np.sum(np.abs(tang) ** 2, axis=2)

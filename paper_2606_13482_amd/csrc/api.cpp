@@ -1,0 +1,224 @@
+// C ABI of libbie (include/bie.h): argument checks, error codes, dispatch.
+#include <cmath>
+#include <cstring>
+#include <utility>
+#include <string>
+
+#include "bie_internal.hpp"
+
+namespace {
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+template <typename F>
+int guarded(F &&f)
+{
+    try {
+        return f();
+    } catch (const bie::Error &e) {
+        return fail(e.code, e.what());
+    } catch (const std::bad_alloc &) {
+        return fail(BIE_ENOMEM, "host allocation failed");
+    } catch (const std::exception &e) {
+        return fail(BIE_EDEVICE, e.what());
+    } catch (...) {
+        return fail(BIE_EDEVICE, "unknown error");
+    }
+}
+
+hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
+
+void destroy_op(bie_op *op)
+{
+    if (!op) return;
+    bie::free_workspace(op);
+    void *ptrs[] = { op->Z64, op->Z32, op->tri.cent, op->tri.loc, op->tri.vfree, op->tri.verts,
+                     op->tri.area, op->tri.sgn, op->tri.slot_m, op->tri.edges };
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    delete op;
+}
+}  // namespace
+
+extern "C" {
+
+const char *bie_last_error(void) { return g_err.c_str(); }
+
+int bie_op_create(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, double k,
+                  const bie_fill_opts *opts, void *stream, bie_op **out)
+{
+    return guarded([&]() -> int {
+        if (!out) return fail(BIE_EINVAL, "out is NULL");
+        *out = nullptr;
+        if (!verts || !tris) return fail(BIE_EINVAL, "NULL mesh array");
+        if (!(k > 0.0) || !std::isfinite(k)) return fail(BIE_EINVAL, "wavenumber must be positive and finite");
+        bie_fill_opts o{ BIE_C128, 2.0, 0 };
+        if (opts) o = *opts;
+        if (o.storage != BIE_C128 && o.storage != BIE_C64) return fail(BIE_EINVAL, "unknown storage");
+        if (!(o.near_factor >= 0.0)) return fail(BIE_EINVAL, "near_factor must be >= 0");
+        bie::Mesh mesh = bie::build_mesh(verts, nv, tris, nt, o.near_factor);   // host only: EMESH first
+        bie_op *op = new bie_op();
+        try {
+            op->mesh = std::move(mesh);
+            BIE_HIP(hipGetDevice(&op->device));
+            op->k = k;
+            op->storage = o.storage;
+            const int64_t N = op->mesh.N;
+            hipStream_t s = as_stream(stream);
+            bie::upload_triangles(op, s);
+            const bool want64 = o.storage == BIE_C128 || o.keep_fp64;
+            const bool want32 = o.storage == BIE_C64;
+            if (want64) BIE_HIP(hipMalloc(&op->Z64, size_t(N) * size_t(N) * 16));
+            if (want32) BIE_HIP(hipMalloc(&op->Z32, size_t(N) * size_t(N) * 8));
+            if (o.storage == BIE_C128) {
+                bie::fill_matrix(op, true, true, false, s);
+            } else {
+                bie::fill_matrix(op, false, false, true, s);          // FP32 regular, FP64 singular
+                if (o.keep_fp64) bie::fill_matrix(op, true, true, false, s);
+            }
+        } catch (...) {
+            destroy_op(op);
+            throw;
+        }
+        *out = op;
+        return BIE_OK;
+    });
+}
+
+void bie_op_destroy(bie_op *op) { destroy_op(op); }
+
+int64_t bie_op_n(const bie_op *op) { return op ? op->mesh.N : int64_t(BIE_EINVAL); }
+
+int bie_op_edges(const bie_op *op, int32_t *out)
+{
+    if (!op || !out) return fail(BIE_EINVAL, "NULL argument");
+    std::memcpy(out, op->mesh.edges.data(), op->mesh.edges.size() * sizeof(int32_t));
+    return BIE_OK;
+}
+
+int64_t bie_op_near_pairs(const bie_op *op, int32_t *out, int64_t cap)
+{
+    if (!op) return fail(BIE_EINVAL, "NULL operator");
+    const int64_t n = int64_t(op->mesh.near.size() / 2);
+    if (out && cap > 0) std::memcpy(out, op->mesh.near.data(), size_t(std::min(n, cap)) * 2 * sizeof(int32_t));
+    return n;
+}
+
+int bie_op_matrix(const bie_op *op, void *dst, int dtype, void *stream)
+{
+    return guarded([&]() -> int {
+        if (!op || !dst) return fail(BIE_EINVAL, "NULL argument");
+        const int64_t NN = op->mesh.N * op->mesh.N;
+        hipStream_t s = as_stream(stream);
+        if (dtype == BIE_C128) {
+            if (op->Z64) BIE_HIP(hipMemcpyAsync(dst, op->Z64, size_t(NN) * 16, hipMemcpyDeviceToDevice, s));
+            else bie::convert_c64_to_c128(op->Z32, dst, NN, s);
+        } else if (dtype == BIE_C64) {
+            if (!op->Z32) return fail(BIE_EINVAL, "no FP32 matrix stored");
+            BIE_HIP(hipMemcpyAsync(dst, op->Z32, size_t(NN) * 8, hipMemcpyDeviceToDevice, s));
+        } else {
+            return fail(BIE_EINVAL, "unknown dtype");
+        }
+        BIE_HIP(hipStreamSynchronize(s));
+        return BIE_OK;
+    });
+}
+
+int bie_rhs_planewave(const bie_op *op, const double *dirs, const double *pols, int64_t R, void *B, void *stream)
+{
+    return guarded([&]() -> int {
+        if (!op || !dirs || !pols || !B) return fail(BIE_EINVAL, "NULL argument");
+        if (R < 0 || R > 65535) return fail(BIE_EINVAL, "R out of range (0..65535)");
+        if (R == 0) return BIE_OK;
+        for (int64_t i = 0; i < 3 * R; ++i)
+            if (!std::isfinite(dirs[i]) || !std::isfinite(pols[i])) return fail(BIE_ENUMERIC, "non-finite direction");
+        bie::rhs_planewave(op, dirs, pols, R, B, as_stream(stream));
+        return BIE_OK;
+    });
+}
+
+int bie_apply(const bie_op *op, const void *X, void *Y, int64_t R, int vec, int conj, void *stream)
+{
+    return guarded([&]() -> int {
+        if (!op || !X || !Y) return fail(BIE_EINVAL, "NULL argument");
+        if (R < 0 || R > 65535) return fail(BIE_EINVAL, "R out of range (0..65535)");
+        if (R == 0) return BIE_OK;
+        const int64_t N = op->mesh.N;
+        hipStream_t s = as_stream(stream);
+        if (vec == BIE_C128) {
+            if (op->Z64) {
+                bie::gemv_c128(op->Z64, N, X, Y, R, conj != 0, s);
+            } else {
+                // FP32 matrix, FP64 vectors: round the vectors, multiply, widen.
+                void *x32 = nullptr, *y32 = nullptr;
+                BIE_HIP(hipMalloc(&x32, size_t(R) * N * 8));
+                BIE_HIP(hipMalloc(&y32, size_t(R) * N * 8));
+                bie::convert_c128_to_c64(X, x32, R * N, s);
+                bie::gemv_c64(op->Z32, N, x32, y32, R, conj != 0, s);
+                bie::convert_c64_to_c128(y32, Y, R * N, s);
+                BIE_HIP(hipStreamSynchronize(s));
+                hipFree(x32);
+                hipFree(y32);
+            }
+        } else if (vec == BIE_C64) {
+            if (!op->Z32) return fail(BIE_EINVAL, "complex64 vectors need BIE_C64 storage");
+            bie::gemv_c64(op->Z32, N, X, Y, R, conj != 0, s);
+        } else {
+            return fail(BIE_EINVAL, "unknown vector dtype");
+        }
+        return BIE_OK;
+    });
+}
+
+int bie_solve(const bie_op *op, const void *B, void *X, int64_t R, const bie_solve_opts *opts,
+              bie_solve_stat *stats, void *stream)
+{
+    return guarded([&]() -> int {
+        if (!op || !B || !X) return fail(BIE_EINVAL, "NULL argument");
+        if (R < 0 || R > 4096) return fail(BIE_EINVAL, "R out of range (0..4096)");
+        if (R == 0) return BIE_OK;
+        bie_solve_opts o{ BIE_GMRES, 30, 1e-6, 10000, BIE_SCC, 512, 1234, 0 };
+        if (opts) o = *opts;
+        if (o.method != BIE_GMRES && o.method != BIE_CGNR) return fail(BIE_EINVAL, "unknown method");
+        if (o.crit != BIE_SCC && o.crit != BIE_RSCC) return fail(BIE_EINVAL, "unknown criterion");
+        if (o.method == BIE_GMRES && (o.restart < 1 || o.restart > 128)) return fail(BIE_EINVAL, "restart must be 1..128");
+        if (!(o.tol > 0.0)) return fail(BIE_EINVAL, "tol must be > 0");
+        if (o.max_mvp < 1) return fail(BIE_EINVAL, "max_mvp must be >= 1");
+        if (o.rscc_rows < 1) return fail(BIE_EINVAL, "rscc_rows must be >= 1");
+        const int64_t N = op->mesh.N;
+        hipStream_t s = as_stream(stream);
+        if (bie::has_nonfinite(B, 2 * R * N, s)) return fail(BIE_ENUMERIC, "non-finite right-hand side");
+        if (o.use_x0 && bie::has_nonfinite(X, 2 * R * N, s)) return fail(BIE_ENUMERIC, "non-finite initial guess");
+        const int rc = bie::solve(op, B, X, R, o, stats, s);
+        if (rc == BIE_NOT_CONVERGED) g_err = "not converged within max_mvp";
+        return rc;
+    });
+}
+
+int bie_farfield(const bie_op *op, const void *X, int64_t R, const double *obs, int64_t M, void *F, void *stream)
+{
+    return guarded([&]() -> int {
+        if (!op || !X || !obs || !F) return fail(BIE_EINVAL, "NULL argument");
+        if (R < 0 || R > 65535 || M < 0 || M > (int64_t(1) << 31)) return fail(BIE_EINVAL, "size out of range");
+        if (R == 0 || M == 0) return BIE_OK;
+        bie::farfield(op, X, R, obs, M, F, as_stream(stream));
+        return BIE_OK;
+    });
+}
+
+int bie_rscc_rows(int64_t N, int64_t S, uint64_t seed, int64_t *out)
+{
+    return guarded([&]() -> int {
+        if (!out || N < 1 || S < 1) return fail(BIE_EINVAL, "bad argument");
+        auto v = bie::rscc_rows(N, S, seed);
+        std::memcpy(out, v.data(), v.size() * sizeof(int64_t));
+        return BIE_OK;
+    });
+}
+
+}  // extern "C"

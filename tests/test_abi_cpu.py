@@ -1,0 +1,71 @@
+"""C-ABI checks that need no GPU: symbols, host-side error paths, row sampling."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import sampling
+from paper_2606_13482_amd.inputs import icosphere
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "bie.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(bie_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2606_13482_amd import bie
+    lib = ctypes.CDLL(bie.LIB_PATH)
+    names = _declared()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(n for n, _, _ in bie.SYMBOLS) == names
+
+
+def test_rscc_rows_match_oracle():
+    """Both sides implement SplitMix64 + Floyd independently; index sets must be identical."""
+    from paper_2606_13482_amd import bie
+    for n, s, seed in ((7680, 512, 1234), (7680, 512, 1235), (480, 512, 1234), (30720, 512, 99), (100, 7, 0)):
+        assert list(bie.rscc_rows(n, s, seed)) == sampling.sample_rows(n, s, seed)
+
+
+def _create(V, T, k=2.0):
+    from paper_2606_13482_amd import bie
+    h = ctypes.c_void_p()
+    V = np.ascontiguousarray(V, np.float64); T = np.ascontiguousarray(T, np.int32)
+    rc = bie._lib.bie_op_create(V.ctypes.data_as(ctypes.c_void_p), V.shape[0], T.ctypes.data_as(ctypes.c_void_p),
+                                T.shape[0], k, None, None, ctypes.byref(h))
+    return rc, bie._lib.bie_last_error().decode()
+
+
+def test_mesh_errors_are_reported_before_device_work():
+    from paper_2606_13482_amd import bie
+    V, T = icosphere(1)
+    rc, msg = _create(V, T[:-1])
+    assert rc == bie.BIE_EMESH
+    T2 = T.copy(); T2[0] = T2[0][[0, 2, 1]]
+    rc, msg = _create(V, T2)
+    assert rc == bie.BIE_EMESH and "orientation" in msg
+    V2 = V.copy(); V2[T[0, 1]] = V2[T[0, 0]]
+    rc, msg = _create(V2, T)
+    assert rc == bie.BIE_EMESH and "zero-area" in msg
+    T3 = T.copy(); T3[0, 0] = 10 ** 6
+    rc, _ = _create(V, T3)
+    assert rc == bie.BIE_EMESH
+    rc, _ = _create(V, T, k=-1.0)
+    assert rc == bie.BIE_EINVAL
+    rc = bie._lib.bie_op_create(None, 0, None, 0, 1.0, None, None, ctypes.byref(ctypes.c_void_p()))
+    assert rc == bie.BIE_EINVAL
+
+
+def test_null_arguments():
+    from paper_2606_13482_amd import bie
+    assert bie._lib.bie_apply(None, None, None, 1, 0, 0, None) == bie.BIE_EINVAL
+    assert bie._lib.bie_solve(None, None, None, 1, None, None, None) == bie.BIE_EINVAL
+    assert bie._lib.bie_rscc_rows(10, 0, 1, None) == bie.BIE_EINVAL
