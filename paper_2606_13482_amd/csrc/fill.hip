@@ -358,9 +358,25 @@ __global__ __launch_bounds__(128) void k_pairs_singular(int64_t npairs, int64_t 
     R *out = LB + tile_index(I, J, nT) * (9 * 256 * 2);
     const int tid = int((p % TT) * TT + (q % TT));
     const double k4 = 0.25 * k, ik = 1.0 / k;
+    double Jr_[3][3], Ji_[3][3];
     for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b) {
-            const double Jr = jr[a][b] + 0.5 * sr[a][b], Ji = ji[a][b];
+            Jr_[a][b] = jr[a][b] + 0.5 * sr[a][b];
+            Ji_[a][b] = ji[a][b];
+        }
+    if (p == q) {
+        // J_ab = J_ba for a self pair (swap the two integration variables);
+        // take the mean so the stored block is symmetric to the last bit.
+        for (int a = 0; a < 3; ++a)
+            for (int b = a + 1; b < 3; ++b) {
+                const double mr = 0.5 * (Jr_[a][b] + Jr_[b][a]), mi = 0.5 * (Ji_[a][b] + Ji_[b][a]);
+                Jr_[a][b] = Jr_[b][a] = mr;
+                Ji_[a][b] = Ji_[b][a] = mi;
+            }
+    }
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            const double Jr = Jr_[a][b], Ji = Ji_[a][b];
             const double ss = double(sgn[p * 3 + a] * sgn[q * 3 + b]);
             out[((a * 3 + b) * 256 + tid) * 2 + 0] = R(ss * (-k4 * Ji + ik * j0i));
             out[((a * 3 + b) * 256 + tid) * 2 + 1] = R(ss * (k4 * Jr - ik * j0r));
