@@ -8,9 +8,10 @@
  *     [T_Phi]_mn = -int int div f_m(x) g(x,y) div f_n(y)        (eq:matTPhi)
  *     g(x,y) = exp(-jk|x-y|)/(4 pi |x-y|), time factor exp(+j w t),
  * in RWG functions without edge-length normalisation, and the excitation
- * [e]_m = int f_m . e_inc (Sec. II).  "After solving ... using an iterative
- * solver, the scattered fields are obtained by evaluating the radiation
- * potentials" (Sec. II): hence the calls operator -> apply -> solve -> far field.
+ * [e]_m = int f_m . e_inc (Sec. II).  The paper solves this system with an
+ * iterative method and then evaluates the scattered field from the radiation
+ * potentials of the current (Sec. II): hence the calls operator -> apply ->
+ * solve -> far field.
  *
  * Conventions for every call
  *   - Host arrays (const pointers named host) are read during the call only.
@@ -119,7 +120,7 @@ typedef enum { BIE_SCC = 0, BIE_RSCC = 1 } bie_crit;
 
 typedef struct {
     int method;          /* bie_method; default BIE_GMRES */
-    int restart;         /* GMRES restart length m (1..500); default 30 */
+    int restart;         /* GMRES restart length m (1..128); default 30 */
     double tol;          /* relative to ||b||_2; default 1e-6 */
     int64_t max_mvp;     /* cap on products per right-hand side; default 10000 */
     int crit;            /* bie_crit; default BIE_SCC */
@@ -166,6 +167,14 @@ int bie_farfield(const bie_op *op, const void *X, int64_t R, const double *obs, 
  * [0, N) for `seed` (host out, S int64).  Exposed so callers can reproduce the
  * rows a given check used. */
 int bie_rscc_rows(int64_t N, int64_t S, uint64_t seed, int64_t *out);
+
+/* Measurement support (not part of the method): with on != 0 every launch of
+ * the dense product kernel (from bie_apply and inside bie_solve) is bracketed
+ * by HIP events on the stream it runs on.  bie_prof_read waits for the
+ * recorded events and returns the number of launches and their summed
+ * duration in ms since the previous read, then clears the record. */
+int bie_prof_enable(int on);
+int bie_prof_read(int64_t *launches, double *total_ms);
 
 const char *bie_last_error(void);
 

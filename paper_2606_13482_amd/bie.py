@@ -66,6 +66,8 @@ SYMBOLS = [
     ("bie_solve", ctypes.c_int, [_P, _P, _P, _I64, _P, _P, _P]),
     ("bie_farfield", ctypes.c_int, [_P, _P, _I64, _P, _I64, _P, _P]),
     ("bie_rscc_rows", ctypes.c_int, [_I64, _I64, ctypes.c_uint64, _P]),
+    ("bie_prof_enable", ctypes.c_int, [ctypes.c_int]),
+    ("bie_prof_read", ctypes.c_int, [ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_double)]),
     ("bie_last_error", ctypes.c_char_p, []),
 ]
 
@@ -113,6 +115,17 @@ def rscc_rows(n: int, s: int, seed: int) -> np.ndarray:
     out = np.zeros(min(n, s), np.int64)
     _check(_lib.bie_rscc_rows(n, s, ctypes.c_uint64(seed), out.ctypes.data_as(ctypes.c_void_p)))
     return out
+
+
+def prof_enable(on: bool = True):
+    _check(_lib.bie_prof_enable(int(on)))
+
+
+def prof_read():
+    """(launches, total_ms) of the dense product kernel since the last read."""
+    n = ctypes.c_int64(); ms = ctypes.c_double()
+    _check(_lib.bie_prof_read(ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value
 
 
 @dataclass

@@ -211,6 +211,23 @@ int bie_farfield(const bie_op *op, const void *X, int64_t R, const double *obs, 
     });
 }
 
+int bie_prof_enable(int on)
+{
+    return guarded([&]() -> int {
+        bie::prof_enable(on != 0);
+        return BIE_OK;
+    });
+}
+
+int bie_prof_read(int64_t *launches, double *total_ms)
+{
+    return guarded([&]() -> int {
+        if (!launches || !total_ms) return fail(BIE_EINVAL, "NULL argument");
+        bie::prof_read(launches, total_ms);
+        return BIE_OK;
+    });
+}
+
 int bie_rscc_rows(int64_t N, int64_t S, uint64_t seed, int64_t *out)
 {
     return guarded([&]() -> int {

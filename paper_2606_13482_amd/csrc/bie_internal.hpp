@@ -90,6 +90,8 @@ void gemv_c64(const void *Z, int64_t N, const void *X, void *Y, int64_t R, bool 
 void convert_c128_to_c64(const void *src, void *dst, int64_t n, hipStream_t s);
 void convert_c64_to_c128(const void *src, void *dst, int64_t n, hipStream_t s);
 bool has_nonfinite(const void *x, int64_t n_doubles, hipStream_t s);
+void prof_enable(bool enable);
+void prof_read(int64_t *launches, double *total_ms);
 
 // krylov.hip
 int solve(const bie_op *op, const void *B, void *X, int64_t R, const bie_solve_opts &o,

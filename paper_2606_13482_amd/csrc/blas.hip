@@ -10,9 +10,53 @@
 // shuffles.  Y = T X, Y = T^H X = conj(T conj X) (T = T^T), or Y = B - T X.
 #include <hip/hip_runtime.h>
 
+#include <utility>
+#include <vector>
+
 #include "bie_internal.hpp"
 
 namespace bie {
+
+// Optional timing of the product kernel: events recorded on the launch stream.
+namespace prof {
+bool on = false;
+std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+size_t used = 0;
+
+void begin(hipStream_t s)
+{
+    if (!on) return;
+    if (used == ev.size()) {
+        hipEvent_t a, b;
+        BIE_HIP(hipEventCreate(&a));
+        BIE_HIP(hipEventCreate(&b));
+        ev.emplace_back(a, b);
+    }
+    BIE_HIP(hipEventRecord(ev[used].first, s));
+}
+void end(hipStream_t s)
+{
+    if (!on) return;
+    BIE_HIP(hipEventRecord(ev[used].second, s));
+    ++used;
+}
+}  // namespace prof
+
+void prof_enable(bool enable) { prof::on = enable; }
+
+void prof_read(int64_t *launches, double *total_ms)
+{
+    double t = 0.0;
+    for (size_t i = 0; i < prof::used; ++i) {
+        BIE_HIP(hipEventSynchronize(prof::ev[i].second));
+        float ms = 0.f;
+        BIE_HIP(hipEventElapsedTime(&ms, prof::ev[i].first, prof::ev[i].second));
+        t += ms;
+    }
+    *launches = int64_t(prof::used);
+    *total_ms = t;
+    prof::used = 0;
+}
 
 namespace {
 
@@ -141,6 +185,7 @@ void launch_gemv(const void *Z, int64_t N, const void *X, int64_t ldx, void *Y, 
 {
     // Rows per wave / vectors per pass chosen for enough loads in flight per CU.
     constexpr int ROWS = 4;
+    prof::begin(s);
     if (R >= 4) {
         constexpr int NV = 4;
         dim3 grid(unsigned((N + 4 * ROWS - 1) / (4 * ROWS)), unsigned((R + NV - 1) / NV));
@@ -153,6 +198,7 @@ void launch_gemv(const void *Z, int64_t N, const void *X, int64_t ldx, void *Y, 
                            ldx, (T *)Y, ldy, (const T *)B, ldb, R, skip, sks);
     }
     BIE_HIP(hipGetLastError());
+    prof::end(s);
 }
 
 __global__ void k_convert_d2f(const double *__restrict__ a, float *__restrict__ b, int64_t n)
