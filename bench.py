@@ -46,7 +46,7 @@ def parse():
     return ap.parse_args()
 
 
-def gemv_source_hash() -> str:
+def product_source_hash() -> str:
     with open(os.path.join(ROOT, "paper_2606_13482_amd", "csrc", "blas.hip"), "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
@@ -164,9 +164,11 @@ def main():
     op.close()
 
     gemv_avg_ms = gemv_ms / max(1, launches)
-    alg_bytes = N * N * 16 + 2 * N * 16          # matrix once + x read + y written (R = 1)
+    # the matrix is symmetric: a product reads each of the N(N+1)/2 distinct
+    # entries once (complex128), plus x read and y written
+    alg_bytes = N * (N + 1) // 2 * 16 + 2 * N * 16
     achieved = alg_bytes / (gemv_avg_ms * 1e-3) / 1e9
-    khash = gemv_source_hash()
+    khash = product_source_hash()
     traffic = traffic_from_profiles(khash, N)
 
     mvps = float(np.mean([s["mvps"] for s in stats]))
@@ -189,7 +191,7 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "k_gemv<double,4,1> (dense complex128 product)",
+                     "kernel": "packed symmetric complex128 product (tile pass + reduce)",
                      "alg_bytes_per_launch": alg_bytes, "avg_launch_us": round(gemv_avg_ms * 1e3, 2),
                      "launches": launches},
         "solve": {"iters": int(stats[-1]["iters"]), "mvps": int(stats[-1]["mvps"]),

@@ -110,8 +110,9 @@ int bie_rhs_planewave(const bie_op *op, const double *dirs, const double *pols, 
 /* Matrix-vector / matrix-block product (the solver's MVP):
  *   Y = T X   (conj = 0)   or   Y = T^H X = conj(T conj(X))   (conj = 1, T = T^T)
  *   X, Y  device R x N, complex128 (vec = BIE_C128) or complex64 (vec = BIE_C64);
- *         X and Y must not overlap.  Arithmetic in the storage precision with
- *         accumulation in that precision. */
+ *         X and Y must not overlap.  Complex128 vectors use the FP64 matrix when
+ *         stored (else the FP32 matrix with FP64 accumulation); complex64 vectors
+ *         use the FP32 matrix with FP32 accumulation. */
 int bie_apply(const bie_op *op, const void *X, void *Y, int64_t R, int vec, int conj,
               void *stream);
 
@@ -120,7 +121,7 @@ typedef enum { BIE_SCC = 0, BIE_RSCC = 1 } bie_crit;
 
 typedef struct {
     int method;          /* bie_method; default BIE_GMRES */
-    int restart;         /* GMRES restart length m (1..128); default 30 */
+    int restart;         /* GMRES restart length m (1..64); default 30 */
     double tol;          /* relative to ||b||_2; default 1e-6 */
     int64_t max_mvp;     /* cap on products per right-hand side; default 10000 */
     int crit;            /* bie_crit; default BIE_SCC */
@@ -144,8 +145,9 @@ typedef struct {
  *   RSCC: sqrt((N/S) sum_{i in S} |b_i - (T x)_i|^2) / ||b||_2 <= tol over S
  *         rows drawn by Floyd's algorithm from SplitMix64 seeded with
  *         rscc_seed + (number of earlier checks of that right-hand side).
- * GMRES(m): Arnoldi with classical Gram-Schmidt applied twice, FP64 Givens
- * rotations; a cycle ends when the estimate <= tol or j = m, then the
+ * GMRES(m): Arnoldi with classical Gram-Schmidt and selective
+ * reorthogonalisation (a second pass when the first removes more than half of
+ * ||w||^2), FP64 Givens rotations; a cycle ends when the estimate <= tol or j = m, then the
  * criterion is evaluated on the true residual.  CGNR: CG on T^H T x = T^H b.
  *   B      device R x N complex128
  *   X      device R x N complex128 (in: initial guess if use_x0; out: solution)

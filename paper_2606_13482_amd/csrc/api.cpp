@@ -37,6 +37,7 @@ void destroy_op(bie_op *op)
 {
     if (!op) return;
     bie::free_workspace(op);
+    bie::packed_free(op);
     void *ptrs[] = { op->Z64, op->Z32, op->tri.cent, op->tri.loc, op->tri.vfree, op->tri.verts,
                      op->tri.area, op->tri.sgn, op->tri.slot_m, op->tri.edges };
     for (void *p : ptrs)
@@ -71,10 +72,13 @@ int bie_op_create(const double *verts, int64_t nv, const int32_t *tris, int64_t 
             const int64_t N = op->mesh.N;
             hipStream_t s = as_stream(stream);
             bie::upload_triangles(op, s);
+            bie::packed_setup(op);
+            (void)N;
+            const size_t tile_elems = size_t(op->pk.ntiles) * bie::TB * bie::TB;
             const bool want64 = o.storage == BIE_C128 || o.keep_fp64;
             const bool want32 = o.storage == BIE_C64;
-            if (want64) BIE_HIP(hipMalloc(&op->Z64, size_t(N) * size_t(N) * 16));
-            if (want32) BIE_HIP(hipMalloc(&op->Z32, size_t(N) * size_t(N) * 8));
+            if (want64) BIE_HIP(hipMalloc(&op->Z64, tile_elems * 16));
+            if (want32) BIE_HIP(hipMalloc(&op->Z32, tile_elems * 8));
             if (o.storage == BIE_C128) {
                 bie::fill_matrix(op, true, true, false, s);
             } else {
@@ -113,14 +117,18 @@ int bie_op_matrix(const bie_op *op, void *dst, int dtype, void *stream)
 {
     return guarded([&]() -> int {
         if (!op || !dst) return fail(BIE_EINVAL, "NULL argument");
-        const int64_t NN = op->mesh.N * op->mesh.N;
         hipStream_t s = as_stream(stream);
         if (dtype == BIE_C128) {
-            if (op->Z64) BIE_HIP(hipMemcpyAsync(dst, op->Z64, size_t(NN) * 16, hipMemcpyDeviceToDevice, s));
-            else bie::convert_c64_to_c128(op->Z32, dst, NN, s);
+            bie::unpack_c128(op, op->Z64 != nullptr, dst, s);
         } else if (dtype == BIE_C64) {
             if (!op->Z32) return fail(BIE_EINVAL, "no FP32 matrix stored");
-            BIE_HIP(hipMemcpyAsync(dst, op->Z32, size_t(NN) * 8, hipMemcpyDeviceToDevice, s));
+            void *tmp = nullptr;
+            const int64_t NN = op->mesh.N * op->mesh.N;
+            BIE_HIP(hipMalloc(&tmp, size_t(NN) * 16));
+            bie::unpack_c128(op, false, tmp, s);
+            bie::convert_c128_to_c64(tmp, dst, NN, s);
+            BIE_HIP(hipStreamSynchronize(s));
+            (void)hipFree(tmp);
         } else {
             return fail(BIE_EINVAL, "unknown dtype");
         }
@@ -151,23 +159,11 @@ int bie_apply(const bie_op *op, const void *X, void *Y, int64_t R, int vec, int 
         const int64_t N = op->mesh.N;
         hipStream_t s = as_stream(stream);
         if (vec == BIE_C128) {
-            if (op->Z64) {
-                bie::gemv_c128(op->Z64, N, X, Y, R, conj != 0, s);
-            } else {
-                // FP32 matrix, FP64 vectors: round the vectors, multiply, widen.
-                void *x32 = nullptr, *y32 = nullptr;
-                BIE_HIP(hipMalloc(&x32, size_t(R) * N * 8));
-                BIE_HIP(hipMalloc(&y32, size_t(R) * N * 8));
-                bie::convert_c128_to_c64(X, x32, R * N, s);
-                bie::gemv_c64(op->Z32, N, x32, y32, R, conj != 0, s);
-                bie::convert_c64_to_c128(y32, Y, R * N, s);
-                BIE_HIP(hipStreamSynchronize(s));
-                hipFree(x32);
-                hipFree(y32);
-            }
+            // FP64 matrix if stored, else the FP32 matrix with FP64 accumulation
+            bie::product(op, op->Z64 != nullptr, true, X, N, Y, N, nullptr, 0, R, nullptr, 1, conj != 0, s);
         } else if (vec == BIE_C64) {
             if (!op->Z32) return fail(BIE_EINVAL, "complex64 vectors need BIE_C64 storage");
-            bie::gemv_c64(op->Z32, N, X, Y, R, conj != 0, s);
+            bie::product(op, false, false, X, N, Y, N, nullptr, 0, R, nullptr, 1, conj != 0, s);
         } else {
             return fail(BIE_EINVAL, "unknown vector dtype");
         }
@@ -186,7 +182,7 @@ int bie_solve(const bie_op *op, const void *B, void *X, int64_t R, const bie_sol
         if (opts) o = *opts;
         if (o.method != BIE_GMRES && o.method != BIE_CGNR) return fail(BIE_EINVAL, "unknown method");
         if (o.crit != BIE_SCC && o.crit != BIE_RSCC) return fail(BIE_EINVAL, "unknown criterion");
-        if (o.method == BIE_GMRES && (o.restart < 1 || o.restart > 128)) return fail(BIE_EINVAL, "restart must be 1..128");
+        if (o.method == BIE_GMRES && (o.restart < 1 || o.restart > 64)) return fail(BIE_EINVAL, "restart must be 1..64");
         if (!(o.tol > 0.0)) return fail(BIE_EINVAL, "tol must be > 0");
         if (o.max_mvp < 1) return fail(BIE_EINVAL, "max_mvp must be >= 1");
         if (o.rscc_rows < 1) return fail(BIE_EINVAL, "rscc_rows must be >= 1");

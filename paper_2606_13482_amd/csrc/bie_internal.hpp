@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 #include <stdexcept>
 #include <string>
@@ -61,6 +62,36 @@ struct TriDev {
 
 struct Workspace;  // solver workspaces (krylov.hip)
 
+// Packed symmetric storage of T (T = T^T exactly): only tiles (I, J) with
+// I <= J of TB x TB entries are stored, each tile row-major and contiguous,
+// tiles in row-major order over the upper triangle; entries beyond N are 0.
+constexpr int TB = 64;
+struct Packed {
+    int64_t N = 0, nT = 0, ntiles = 0, nunits = 0;
+    int32_t *units = nullptr;      // device, nunits x 3: (I, J0, J1) = tiles J0..J1-1 of tile row I
+    int32_t *unit_ptr = nullptr;   // device, nT + 1: units of tile row I are unit_ptr[I] .. unit_ptr[I+1]-1
+    int64_t *seg = nullptr;        // device, nT + 1: partial vectors of row block I occupy slots seg[I]..seg[I+1]-1
+    int64_t nslots = 0;            // partial vectors per product vector (= seg[nT])
+    void *part = nullptr;          // device partial sums of the product, sized for part_R vectors
+    int64_t part_R = 0;
+    size_t part_elem = 0;          // bytes per complex element of the partials buffer
+};
+__host__ __device__ inline int64_t tile_of(int64_t I, int64_t J, int64_t nT)
+{
+    return I * nT - I * (I - 1) / 2 + (J - I);
+}
+// inverse of tile_of: linear index b -> (I, J), I <= J
+__host__ __device__ inline void tile_decode(int64_t b, int64_t nT, int64_t &I, int64_t &J)
+{
+    const double n2 = 2.0 * double(nT) + 1.0;
+    I = int64_t((n2 - sqrt(n2 * n2 - 8.0 * double(b))) * 0.5);
+    if (I < 0) I = 0;
+    if (I > nT - 1) I = nT - 1;
+    while (I > 0 && tile_of(I, I, nT) > b) --I;
+    while (I + 1 < nT && tile_of(I + 1, I + 1, nT) <= b) ++I;
+    J = I + (b - tile_of(I, I, nT));
+}
+
 }  // namespace bie
 
 struct bie_op {
@@ -69,8 +100,9 @@ struct bie_op {
     int storage = BIE_C128;
     bie::Mesh mesh;
     bie::TriDev tri;
-    void *Z64 = nullptr;   // N x N complex128 row-major (storage C128 or keep_fp64)
-    void *Z32 = nullptr;   // N x N complex64 row-major (storage C64)
+    void *Z64 = nullptr;   // packed symmetric tiles, complex128 (storage C128 or keep_fp64)
+    void *Z32 = nullptr;   // packed symmetric tiles, complex64 (storage C64)
+    bie::Packed pk;
     bie::Workspace *ws = nullptr;
 };
 
@@ -84,9 +116,19 @@ void rhs_planewave(const bie_op *op, const double *dirs, const double *pols, int
 void farfield(const bie_op *op, const void *X, int64_t R, const double *obs, int64_t M, void *F,
               hipStream_t s);
 
-// blas.hip: Y = Z X (R vectors), complex128 or complex64 vectors and matrix.
-void gemv_c128(const void *Z, int64_t N, const void *X, void *Y, int64_t R, bool conj, hipStream_t s);
-void gemv_c64(const void *Z, int64_t N, const void *X, void *Y, int64_t R, bool conj, hipStream_t s);
+// blas.hip: products with the packed symmetric matrix.
+void packed_setup(bie_op *op);        // unit table (host -> device)
+void packed_free(bie_op *op);
+// Y = T X, T^H X (conj) or B - T X (B != NULL) for R vectors with the FP64
+// (mat64) or FP32 matrix; vectors complex128 (vec64, FP64 accumulation) or
+// complex64 (FP32 matrix only).
+void product(const bie_op *op, bool mat64, bool vec64, const void *X, int64_t ldx, void *Y, int64_t ldy,
+             const void *B, int64_t ldb, int64_t R, const int *skip, int64_t sks, bool conj, hipStream_t s);
+// packed -> full row-major complex128
+void unpack_c128(const bie_op *op, bool from64, void *dst, hipStream_t s);
+// sampled rows of T x (complex128): out[r*S + i] = |b_i - (T x_r)_i|^2, i in rows[r*S ..]
+void sampled_residual(const bie_op *op, const void *B, const void *X, int64_t R, int64_t S, const int64_t *rows,
+                      double *out, const int *mask, hipStream_t s);
 void convert_c128_to_c64(const void *src, void *dst, int64_t n, hipStream_t s);
 void convert_c64_to_c128(const void *src, void *dst, int64_t n, hipStream_t s);
 bool has_nonfinite(const void *x, int64_t n_doubles, hipStream_t s);

@@ -1,15 +1,27 @@
-// Dense complex matrix-vector products with the impedance matrix.
+// Products with the dense impedance matrix in packed symmetric storage.
 //
 // The matrix-vector product is the O(N^2) operation of every Krylov
-// iteration (Sec. I and II: dense storage and MVP cost).  T is stored
-// row-major, N x N, interleaved complex (FP64: 16 B, FP32: 8 B per entry).
-// The product streams T from HBM exactly once per call: every lane issues
-// 16-byte loads of consecutive columns (a wave covers 1 KiB of a row per
-// step), ROWS rows per wave share each load of x (x stays in L2), NV vectors
-// share each load of T, and each row's partial sums are combined with wave
-// shuffles.  Y = T X, Y = T^H X = conj(T conj X) (T = T^T), or Y = B - T X.
+// iteration (Sec. I and II: dense storage and MVP cost).  The Galerkin EFIE
+// matrix is symmetric (identical test and basis functions), and the fill makes
+// it exactly so, which halves the bytes a product must stream: only the tiles
+// (I, J), I <= J, of 64 x 64 entries are stored.  One pass over the tiles
+// applies every off-diagonal tile twice,
+//     y_I += T_IJ x_J     (row sums, kept in registers along a tile row)
+//     y_J += T_IJ^T x_I   (column sums, one 64-entry partial per tile),
+// and a second small kernel adds the partials of each 64-row block in a fixed
+// order (deterministic, no atomics).
+//
+// Tile pass: one block of 4 waves walks a run of consecutive tiles of one tile
+// row; wave w owns rows 16w..16w+15 of the row block, lane c owns column c.
+// Every tile row (1 KiB in FP64) is read by one wave with one load per lane,
+// 16 rows in flight per wave, and the next tile's loads are issued before the
+// current tile's arithmetic.  Column sums of the 4 waves are combined through
+// double-buffered LDS with one barrier per tile; x of the wave's 16 rows sits in
+// scalar registers.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstdlib>
 #include <utility>
 #include <vector>
 
@@ -17,7 +29,7 @@
 
 namespace bie {
 
-// Optional timing of the product kernel: events recorded on the launch stream.
+// Optional timing of the product kernels: events recorded on the launch stream.
 namespace prof {
 bool on = false;
 std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
@@ -60,145 +72,259 @@ void prof_read(int64_t *launches, double *total_ms)
 
 namespace {
 
+// tiles per work unit of the tile pass (BIE_SYM_UNIT overrides)
+int unit_tiles()
+{
+    static int v = [] {
+        const char *e = getenv("BIE_SYM_UNIT");
+        const int u = e ? atoi(e) : 8;
+        return u >= 1 && u <= 64 ? u : 8;
+    }();
+    return v;
+}
+
 typedef double nd2 __attribute__((ext_vector_type(2)));
-typedef float nf4 __attribute__((ext_vector_type(4)));
+typedef float nf2 __attribute__((ext_vector_type(2)));
 
 template <typename T>
-struct Packet;   // 16-byte load unit (native vector type)
+struct Cx;   // complex element as a native 2-vector (one load instruction)
 template <>
-struct Packet<double> {
-    using type = nd2;       // one complex128
-    static constexpr int C = 1;
+struct Cx<double> {
+    using type = nd2;
 };
 template <>
-struct Packet<float> {
-    using type = nf4;       // two complex64
-    static constexpr int C = 2;
+struct Cx<float> {
+    using type = nf2;
 };
 
 template <typename T>
-__device__ inline T wave_sum(T v)
+__device__ inline T wsum(T v)
 {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
 
+// Sums 8 complex values over a wave: each exchange halves what a lane carries
+// (4+2+1 exchanges, then 3 plain steps).  pr[0], pi[0] of lane L end with the
+// total of value (L >> 3) & 7.
 template <typename T>
-__device__ inline void unpack(const typename Packet<T>::type &p, T re[], T im[]);
-template <>
-__device__ inline void unpack<double>(const nd2 &p, double re[], double im[])
+__device__ inline void wave_sum8(T pr[8], T pi[8])
 {
-    re[0] = p.x; im[0] = p.y;
-}
-template <>
-__device__ inline void unpack<float>(const nf4 &p, float re[], float im[])
-{
-    re[0] = p.x; im[0] = p.y; re[1] = p.z; im[1] = p.w;
-}
-
-// One wave: ROWS consecutive rows x NV vectors.  Block: 4 waves.
-// X, Y: vector v at offset v*ld (complex elements); B (optional): Y = B - T X.
-template <typename T, int ROWS, int NV, bool CONJ, bool SUB>
-__global__ __launch_bounds__(256) void k_gemv(const T *__restrict__ Z, int64_t N, const T *__restrict__ X,
-                                              int64_t ldx, T *__restrict__ Y, int64_t ldy,
-                                              const T *__restrict__ B, int64_t ldb, int64_t R,
-                                              const int *__restrict__ skip, int64_t sks)
-{
-    using P = typename Packet<T>::type;
-    constexpr int C = Packet<T>::C;
     const int lane = threadIdx.x & 63;
-    const int64_t row0 = (int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6)) * ROWS;
-    const int64_t v0 = int64_t(blockIdx.y) * NV;
-    if (row0 >= N) return;
-    if (skip) {
-        bool any = false;
-        for (int v = 0; v < NV; ++v)
-            if (v0 + v < R && !skip[(v0 + v) * sks]) any = true;
-        if (!any) return;
-    }
-    int64_t rows[ROWS];
+    {
+        const bool b = lane & 32;
 #pragma unroll
-    for (int r = 0; r < ROWS; ++r) rows[r] = (row0 + r < N) ? row0 + r : N - 1;
-    const T *xs[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) xs[v] = X + 2 * ((v0 + v < R ? v0 + v : R - 1) * ldx);
-
-    T ar[ROWS][NV], ai[ROWS][NV];
-#pragma unroll
-    for (int r = 0; r < ROWS; ++r)
-#pragma unroll
-        for (int v = 0; v < NV; ++v) { ar[r][v] = 0; ai[r][v] = 0; }
-
-    for (int64_t c = int64_t(lane) * C; c < N; c += 64 * C) {
-        T xr[NV][C], xi[NV][C];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) unpack<T>(*reinterpret_cast<const P *>(xs[v] + 2 * c), xr[v], xi[v]);
-#pragma unroll
-        for (int r = 0; r < ROWS; ++r) {
-            T zr[C], zi[C];
-            unpack<T>(__builtin_nontemporal_load(reinterpret_cast<const P *>(Z + 2 * (rows[r] * N + c))), zr, zi);
-#pragma unroll
-            for (int v = 0; v < NV; ++v)
-#pragma unroll
-                for (int e = 0; e < C; ++e) {
-                    if (!CONJ) {
-                        ar[r][v] += zr[e] * xr[v][e] - zi[e] * xi[v][e];
-                        ai[r][v] += zr[e] * xi[v][e] + zi[e] * xr[v][e];
-                    } else {
-                        ar[r][v] += zr[e] * xr[v][e] + zi[e] * xi[v][e];
-                        ai[r][v] += zr[e] * xi[v][e] - zi[e] * xr[v][e];
-                    }
-                }
+        for (int i = 0; i < 4; ++i) {
+            const T sr = b ? pr[i] : pr[i + 4], si = b ? pi[i] : pi[i + 4];
+            const T kr = b ? pr[i + 4] : pr[i], ki = b ? pi[i + 4] : pi[i];
+            pr[i] = kr + __shfl_xor(sr, 32, 64);
+            pi[i] = ki + __shfl_xor(si, 32, 64);
         }
     }
+    {
+        const bool b = lane & 16;
 #pragma unroll
-    for (int r = 0; r < ROWS; ++r)
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            ar[r][v] = wave_sum(ar[r][v]);
-            ai[r][v] = wave_sum(ai[r][v]);
+        for (int i = 0; i < 2; ++i) {
+            const T sr = b ? pr[i] : pr[i + 2], si = b ? pi[i] : pi[i + 2];
+            const T kr = b ? pr[i + 2] : pr[i], ki = b ? pi[i + 2] : pi[i];
+            pr[i] = kr + __shfl_xor(sr, 16, 64);
+            pi[i] = ki + __shfl_xor(si, 16, 64);
         }
-    if (lane == 0) {
+    }
+    {
+        const bool b = lane & 8;
+        const T sr = b ? pr[0] : pr[1], si = b ? pi[0] : pi[1];
+        const T kr = b ? pr[1] : pr[0], ki = b ? pi[1] : pi[0];
+        pr[0] = kr + __shfl_xor(sr, 8, 64);
+        pi[0] = ki + __shfl_xor(si, 8, 64);
+    }
 #pragma unroll
-        for (int r = 0; r < ROWS; ++r) {
-            if (row0 + r >= N) continue;
+    for (int o = 4; o > 0; o >>= 1) {
+        pr[0] += __shfl_xor(pr[0], o, 64);
+        pi[0] += __shfl_xor(pi[0], o, 64);
+    }
+}
+
+// Tile pass.  Writes 64-entry partial vectors (complex T) into the slots of the
+// row block they belong to (see k_sym_reduce).
+// M: matrix storage type, T: vector and accumulation type (T >= M).
+template <typename M, typename T, bool CONJ, bool PREFETCH>
+__global__ __launch_bounds__(256) void k_sym_tiles(const M *__restrict__ Zp, int64_t N, int64_t nT,
+                                                   const int32_t *__restrict__ units,
+                                                   const int32_t *__restrict__ unit_ptr,
+                                                   const int64_t *__restrict__ seg, int64_t nslots,
+                                                   const T *__restrict__ X, int64_t ldx, T *__restrict__ part,
+                                                   const int *__restrict__ skip, int64_t sks)
+{
+    using V2 = typename Cx<T>::type;
+    using MV = typename Cx<M>::type;
+    const int64_t u = blockIdx.x, v = blockIdx.y;
+    if (skip && skip[v * sks]) return;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: x rows in scalar registers
+    const int32_t I = units[3 * u], J0 = units[3 * u + 1], J1 = units[3 * u + 2];
+    const V2 *x = reinterpret_cast<const V2 *>(X) + v * ldx;
+    // partials of row block K live in slots seg[K]..: first the column sums of
+    // tiles (0..K-1, K), then the row sums of the units of tile row K
+    V2 *pv = reinterpret_cast<V2 *>(part) + v * nslots * TB;
+    const MV *Z = reinterpret_cast<const MV *>(Zp);
+
+    // x of this wave's 16 rows (the same for every lane)
+    T xir[16], xii[16];
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                const int64_t vv = v0 + v;
-                if (vv >= R || (skip && skip[vv * sks])) continue;
-                T yr = ar[r][v], yi = ai[r][v];
-                if (SUB) {
-                    yr = B[2 * (vv * ldb + row0 + r)] - yr;
-                    yi = B[2 * (vv * ldb + row0 + r) + 1] - yi;
-                }
-                Y[2 * (vv * ldy + row0 + r)] = yr;
-                Y[2 * (vv * ldy + row0 + r) + 1] = yi;
+    for (int i = 0; i < 16; ++i) {
+        const int64_t m = int64_t(I) * TB + wave * 16 + i;
+        V2 xv = { 0, 0 };
+        if (m < N) xv = x[m];
+        xir[i] = xv.x;
+        xii[i] = xv.y;
+    }
+    T rar[16], rai[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) { rar[i] = 0; rai[i] = 0; }
+    __shared__ V2 red[2][4][TB];
+
+    MV t[16];
+    if (PREFETCH) {
+        const MV *tile = Z + tile_of(I, J0, nT) * TB * TB + (wave * 16) * TB + lane;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) t[i] = __builtin_nontemporal_load(tile + i * TB);
+    }
+    for (int32_t J = J0; J < J1; ++J) {
+        const int64_t n = int64_t(J) * TB + lane;
+        V2 xj = { 0, 0 };
+        if (n < N) xj = x[n];
+        MV cur[16];
+        if (PREFETCH) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) cur[i] = t[i];
+            if (J + 1 < J1) {   // next tile's loads go out before this tile's arithmetic
+                const MV *tile = Z + tile_of(I, J + 1, nT) * TB * TB + (wave * 16) * TB + lane;
+#pragma unroll
+                for (int i = 0; i < 16; ++i) t[i] = __builtin_nontemporal_load(tile + i * TB);
+            }
+        } else {
+            const MV *tile = Z + tile_of(I, J, nT) * TB * TB + (wave * 16) * TB + lane;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) cur[i] = __builtin_nontemporal_load(tile + i * TB);
+        }
+        T car = 0, cai = 0;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const T zr = T(cur[i].x), zi = CONJ ? -T(cur[i].y) : T(cur[i].y);
+            rar[i] += zr * xj.x - zi * xj.y;
+            rai[i] += zr * xj.y + zi * xj.x;
+            car += zr * xir[i] - zi * xii[i];
+            cai += zr * xii[i] + zi * xir[i];
+        }
+        if (J != I) {   // uniform over the block
+            // double-buffered by tile parity: one barrier per tile; the barrier of
+            // the next tile orders this tile's reads before the buffer is reused
+            const int par = (J - J0) & 1;
+            red[par][wave][lane] = V2{ car, cai };
+            __syncthreads();
+            if (wave == ((J - J0) & 3)) {
+                V2 a = red[par][0][lane];
+#pragma unroll
+                for (int w = 1; w < 4; ++w) a += red[par][w][lane];
+                pv[(seg[J] + I) * TB + lane] = a;
             }
         }
     }
+    // row sums: 16 values per wave, two groups of 8
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+        T pr[8], pi[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) { pr[i] = rar[8 * g + i]; pi[i] = rai[8 * g + i]; }
+        wave_sum8(pr, pi);
+        if ((lane & 7) == 0)
+            pv[(seg[I] + I + (u - unit_ptr[I])) * TB + wave * 16 + 8 * g + (lane >> 3)] = V2{ pr[0], pi[0] };
+    }
 }
 
-template <typename T, bool CONJ, bool SUB>
-void launch_gemv(const void *Z, int64_t N, const void *X, int64_t ldx, void *Y, int64_t ldy, const void *B,
-                 int64_t ldb, int64_t R, const int *skip, int64_t sks, hipStream_t s)
+// y_I = sum of the partial vectors of row block I (column sums of tiles
+// (J < I, I), then row sums of the units of tile row I), stored contiguously.
+// Eight waves split the vectors (every eighth one) and their sums are added in
+// wave order (deterministic).
+template <typename T, bool SUB>
+__global__ __launch_bounds__(512) void k_sym_reduce(int64_t N, const int64_t *__restrict__ seg, int64_t nslots,
+                                                    const T *__restrict__ part, T *__restrict__ Y, int64_t ldy,
+                                                    const T *__restrict__ B, int64_t ldb,
+                                                    const int *__restrict__ skip, int64_t sks)
 {
-    // Rows per wave / vectors per pass chosen for enough loads in flight per CU.
-    constexpr int ROWS = 4;
-    prof::begin(s);
-    if (R >= 4) {
-        constexpr int NV = 4;
-        dim3 grid(unsigned((N + 4 * ROWS - 1) / (4 * ROWS)), unsigned((R + NV - 1) / NV));
-        hipLaunchKernelGGL((k_gemv<T, ROWS, NV, CONJ, SUB>), grid, dim3(256), 0, s, (const T *)Z, N, (const T *)X,
-                           ldx, (T *)Y, ldy, (const T *)B, ldb, R, skip, sks);
-    } else {
-        constexpr int NV = 1;
-        dim3 grid(unsigned((N + 4 * ROWS - 1) / (4 * ROWS)), unsigned(R));
-        hipLaunchKernelGGL((k_gemv<T, ROWS, NV, CONJ, SUB>), grid, dim3(256), 0, s, (const T *)Z, N, (const T *)X,
-                           ldx, (T *)Y, ldy, (const T *)B, ldb, R, skip, sks);
+    using V2 = typename Cx<T>::type;
+    const int64_t I = blockIdx.x, v = blockIdx.y;
+    if (skip && skip[v * sks]) return;
+    const int r = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const V2 *pv = reinterpret_cast<const V2 *>(part) + (v * nslots + seg[I]) * TB;
+    const int64_t K = seg[I + 1] - seg[I];
+    V2 a = { 0, 0 };
+#pragma unroll 4
+    for (int64_t q = w; q < K; q += 8) a += pv[q * TB + r];
+    __shared__ V2 red[8][TB];
+    red[w][r] = a;
+    __syncthreads();
+    if (w != 0) return;
+    a = red[0][r];
+#pragma unroll
+    for (int q = 1; q < 8; ++q) a += red[q][r];
+    const int64_t m = I * TB + r;
+    if (m < N) {
+        V2 *y = reinterpret_cast<V2 *>(Y) + v * ldy;
+        if (SUB) y[m] = reinterpret_cast<const V2 *>(B)[v * ldb + m] - a;
+        else y[m] = a;
     }
-    BIE_HIP(hipGetLastError());
-    prof::end(s);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_unpack(const T *__restrict__ Zp, int64_t N, int64_t nT,
+                                                double2 *__restrict__ out)
+{
+    using V2 = typename Cx<T>::type;
+    const int64_t n = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    const int64_t m = blockIdx.y;
+    if (n >= N) return;
+    const int64_t I = m / TB, J = n / TB;
+    const V2 *Z = reinterpret_cast<const V2 *>(Zp);
+    const V2 z = I <= J ? Z[tile_of(I, J, nT) * TB * TB + (m % TB) * TB + (n % TB)]
+                        : Z[tile_of(J, I, nT) * TB * TB + (n % TB) * TB + (m % TB)];
+    out[m * N + n] = make_double2(double(z.x), double(z.y));
+}
+
+// One wave per sampled row i: (T x)_i from the packed tiles (row i of tiles
+// (I, J >= I), column i of tiles (J < I, I)), then |b_i - (T x)_i|^2.
+__global__ __launch_bounds__(256) void k_sampled_rows(const double2 *__restrict__ Zp, int64_t N, int64_t nT,
+                                                      int64_t S, const int64_t *__restrict__ rows,
+                                                      const double2 *__restrict__ B, const double2 *__restrict__ X,
+                                                      double *__restrict__ out, const int *__restrict__ mask)
+{
+    const int64_t v = blockIdx.y;
+    if (!mask[v]) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t s = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    if (s >= S) return;
+    const int64_t i = rows[v * S + s];
+    const int64_t I = i / TB, rr = i % TB;
+    const double2 *x = X + v * N;
+    double ar = 0.0, ai = 0.0;
+    for (int64_t J = 0; J < nT; ++J) {
+        const int64_t n = J * TB + lane;
+        if (n >= N) continue;
+        const double2 z = J >= I ? Zp[tile_of(I, J, nT) * TB * TB + rr * TB + lane]
+                                 : Zp[tile_of(J, I, nT) * TB * TB + lane * TB + rr];
+        const double2 xv = x[n];
+        ar += z.x * xv.x - z.y * xv.y;
+        ai += z.x * xv.y + z.y * xv.x;
+    }
+    ar = wsum(ar);
+    ai = wsum(ai);
+    if (lane == 0) {
+        const double2 b = B[v * N + i];
+        const double dr = b.x - ar, di = b.y - ai;
+        out[v * S + s] = dr * dr + di * di;
+    }
 }
 
 __global__ void k_convert_d2f(const double *__restrict__ a, float *__restrict__ b, int64_t n)
@@ -217,33 +343,130 @@ __global__ void k_nonfinite(const double *__restrict__ a, int64_t n, int *__rest
         if (!isfinite(a[i])) *flag = 1;
 }
 
+// Tile-pass variant: register double buffering of the next tile (default) or
+// not; BIE_SYM_PREFETCH=0 selects the plain form (kept for measurement).
+int sym_prefetch()
+{
+    static int v = [] {
+        const char *e = getenv("BIE_SYM_PREFETCH");
+        return e ? atoi(e) : 1;
+    }();
+    return v;
+}
+
+template <typename M, typename T, bool CONJ, bool SUB>
+void launch_product(const bie_op *op, const void *Z, const void *X, int64_t ldx, void *Y, int64_t ldy, const void *B,
+                    int64_t ldb, int64_t R, const int *skip, int64_t sks, hipStream_t s)
+{
+    const Packed &pk = op->pk;
+    const dim3 grid(unsigned(pk.nunits), unsigned(R));
+    prof::begin(s);
+    if (sym_prefetch())
+        hipLaunchKernelGGL((k_sym_tiles<M, T, CONJ, true>), grid, dim3(256), 0, s, (const M *)Z, pk.N, pk.nT,
+                           pk.units, pk.unit_ptr, pk.seg, pk.nslots, (const T *)X, ldx, (T *)pk.part, skip, sks);
+    else
+        hipLaunchKernelGGL((k_sym_tiles<M, T, CONJ, false>), grid, dim3(256), 0, s, (const M *)Z, pk.N, pk.nT,
+                           pk.units, pk.unit_ptr, pk.seg, pk.nslots, (const T *)X, ldx, (T *)pk.part, skip, sks);
+    hipLaunchKernelGGL((k_sym_reduce<T, SUB>), dim3(unsigned(pk.nT), unsigned(R)), dim3(512), 0, s, pk.N, pk.seg,
+                       pk.nslots, (const T *)pk.part, (T *)Y, ldy, (const T *)B, ldb, skip, sks);
+    BIE_HIP(hipGetLastError());
+    prof::end(s);
+}
+
 }  // namespace
 
-void gemv_c128(const void *Z, int64_t N, const void *X, void *Y, int64_t R, bool conj, hipStream_t s)
+void packed_setup(bie_op *op)
 {
-    if (conj) launch_gemv<double, true, false>(Z, N, X, N, Y, N, nullptr, 0, R, nullptr, 1, s);
-    else launch_gemv<double, false, false>(Z, N, X, N, Y, N, nullptr, 0, R, nullptr, 1, s);
-}
-
-void gemv_c64(const void *Z, int64_t N, const void *X, void *Y, int64_t R, bool conj, hipStream_t s)
-{
-    if (conj) launch_gemv<float, true, false>(Z, N, X, N, Y, N, nullptr, 0, R, nullptr, 1, s);
-    else launch_gemv<float, false, false>(Z, N, X, N, Y, N, nullptr, 0, R, nullptr, 1, s);
-}
-
-// Strided forms used by the solvers (declared in krylov.hip).
-void gemv_strided(bool fp64, const void *Z, int64_t N, const void *X, int64_t ldx, void *Y, int64_t ldy,
-                  const void *B, int64_t ldb, int64_t R, const int *skip, int64_t sks, bool conj, hipStream_t s)
-{
-    if (fp64) {
-        if (B) launch_gemv<double, false, true>(Z, N, X, ldx, Y, ldy, B, ldb, R, skip, sks, s);
-        else if (conj) launch_gemv<double, true, false>(Z, N, X, ldx, Y, ldy, nullptr, 0, R, skip, sks, s);
-        else launch_gemv<double, false, false>(Z, N, X, ldx, Y, ldy, nullptr, 0, R, skip, sks, s);
-    } else {
-        if (B) launch_gemv<float, false, true>(Z, N, X, ldx, Y, ldy, B, ldb, R, skip, sks, s);
-        else if (conj) launch_gemv<float, true, false>(Z, N, X, ldx, Y, ldy, nullptr, 0, R, skip, sks, s);
-        else launch_gemv<float, false, false>(Z, N, X, ldx, Y, ldy, nullptr, 0, R, skip, sks, s);
+    Packed &pk = op->pk;
+    pk.N = op->mesh.N;
+    pk.nT = (pk.N + TB - 1) / TB;
+    pk.ntiles = pk.nT * (pk.nT + 1) / 2;
+    std::vector<int32_t> units, uptr(pk.nT + 1, 0);
+    for (int64_t I = 0; I < pk.nT; ++I) {
+        uptr[I] = int32_t(units.size() / 3);
+        const int ut = unit_tiles();
+        for (int64_t J0 = I; J0 < pk.nT; J0 += ut) {
+            units.push_back(int32_t(I));
+            units.push_back(int32_t(J0));
+            units.push_back(int32_t(std::min<int64_t>(pk.nT, J0 + ut)));
+        }
     }
+    uptr[pk.nT] = int32_t(units.size() / 3);
+    pk.nunits = int64_t(units.size() / 3);
+    std::vector<int64_t> seg(pk.nT + 1, 0);
+    for (int64_t I = 0; I < pk.nT; ++I) seg[I + 1] = seg[I] + I + (uptr[I + 1] - uptr[I]);
+    pk.nslots = seg[pk.nT];
+    BIE_HIP(hipMalloc(&pk.seg, seg.size() * sizeof(int64_t)));
+    BIE_HIP(hipMemcpy(pk.seg, seg.data(), seg.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    BIE_HIP(hipMalloc(&pk.units, units.size() * sizeof(int32_t)));
+    BIE_HIP(hipMalloc(&pk.unit_ptr, uptr.size() * sizeof(int32_t)));
+    BIE_HIP(hipMemcpy(pk.units, units.data(), units.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    BIE_HIP(hipMemcpy(pk.unit_ptr, uptr.data(), uptr.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+}
+
+void packed_free(bie_op *op)
+{
+    Packed &pk = op->pk;
+    if (pk.units) (void)hipFree(pk.units);
+    if (pk.unit_ptr) (void)hipFree(pk.unit_ptr);
+    if (pk.seg) (void)hipFree(pk.seg);
+    pk.seg = nullptr;
+    if (pk.part) (void)hipFree(pk.part);
+    pk.units = pk.unit_ptr = nullptr;
+    pk.part = nullptr;
+    pk.part_R = 0;
+}
+
+template <typename M, typename T>
+void dispatch(const bie_op *op, const void *Z, const void *X, int64_t ldx, void *Y, int64_t ldy, const void *B,
+              int64_t ldb, int64_t R, const int *skip, int64_t sks, bool conj, hipStream_t s)
+{
+    if (B) launch_product<M, T, false, true>(op, Z, X, ldx, Y, ldy, B, ldb, R, skip, sks, s);
+    else if (conj) launch_product<M, T, true, false>(op, Z, X, ldx, Y, ldy, nullptr, 0, R, skip, sks, s);
+    else launch_product<M, T, false, false>(op, Z, X, ldx, Y, ldy, nullptr, 0, R, skip, sks, s);
+}
+
+void product(const bie_op *opc, bool mat64, bool vec64, const void *X, int64_t ldx, void *Y, int64_t ldy,
+             const void *B, int64_t ldb, int64_t R, const int *skip, int64_t sks, bool conj, hipStream_t s)
+{
+    bie_op *op = const_cast<bie_op *>(opc);
+    Packed &pk = op->pk;
+    const void *Z = mat64 ? op->Z64 : op->Z32;
+    if (!Z) throw Error(BIE_EINVAL, "matrix not stored in the requested precision");
+    if (mat64 && !vec64) throw Error(BIE_EINVAL, "complex64 vectors need the FP32 matrix");
+    if (pk.part_R < R) {   // partial sums, sized for complex128
+        BIE_HIP(hipStreamSynchronize(s));
+        if (pk.part) (void)hipFree(pk.part);
+        pk.part = nullptr;
+        pk.part_R = 0;
+        BIE_HIP(hipMalloc(&pk.part, size_t(R) * size_t(pk.nslots) * TB * 16));
+        pk.part_R = R;
+    }
+    if (mat64) dispatch<double, double>(op, Z, X, ldx, Y, ldy, B, ldb, R, skip, sks, conj, s);
+    else if (vec64) dispatch<float, double>(op, Z, X, ldx, Y, ldy, B, ldb, R, skip, sks, conj, s);
+    else dispatch<float, float>(op, Z, X, ldx, Y, ldy, B, ldb, R, skip, sks, conj, s);
+}
+
+void unpack_c128(const bie_op *op, bool from64, void *dst, hipStream_t s)
+{
+    const Packed &pk = op->pk;
+    const dim3 grid(unsigned((pk.N + 255) / 256), unsigned(pk.N));
+    if (from64) hipLaunchKernelGGL(k_unpack<double>, grid, dim3(256), 0, s, (const double *)op->Z64, pk.N, pk.nT,
+                                   (double2 *)dst);
+    else hipLaunchKernelGGL(k_unpack<float>, grid, dim3(256), 0, s, (const float *)op->Z32, pk.N, pk.nT,
+                            (double2 *)dst);
+    BIE_HIP(hipGetLastError());
+}
+
+void sampled_residual(const bie_op *op, const void *B, const void *X, int64_t R, int64_t S, const int64_t *rows,
+                      double *out, const int *mask, hipStream_t s)
+{
+    if (!op->Z64) throw Error(BIE_EINVAL, "the random-sampling criterion needs the FP64 matrix");
+    const Packed &pk = op->pk;
+    hipLaunchKernelGGL(k_sampled_rows, dim3(unsigned((S + 3) / 4), unsigned(R)), dim3(256), 0, s,
+                       (const double2 *)op->Z64, pk.N, pk.nT, S, rows, (const double2 *)B, (const double2 *)X, out,
+                       mask);
+    BIE_HIP(hipGetLastError());
 }
 
 void convert_c128_to_c64(const void *src, void *dst, int64_t n, hipStream_t s)

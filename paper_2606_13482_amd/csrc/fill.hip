@@ -17,7 +17,8 @@
 //      g = g_r + 1/(4 pi R), g_r on the product rule, the static part with the
 //      inner integral in closed form, mean of both orderings; overwrites L.
 //   3. k_assemble: T_mn = (L(c+m,c+n) + L(c-m,c-n)) + (L(c+m,c-n) + L(c-m,c+n));
-//      the grouping makes T_mn and T_nm the same sum, so T = T^T exactly.
+//      the grouping makes T_mn and T_nm the same sum, so T = T^T exactly, and
+//      only the upper-triangular 64 x 64 tiles are written (packed storage).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -399,25 +400,34 @@ __device__ inline void read_local(const R *__restrict__ LB, int64_t nT, int32_t 
     im = src[1];
 }
 
-// rwg4[m] = (c+, c-, slot in c+, slot in c-)
+// rwg4[m] = (c+, c-, slot in c+, slot in c-).  One block per stored tile
+// (I, J), I <= J, of the packed symmetric matrix; 16 entries per thread.
 template <typename R>
-__global__ __launch_bounds__(256) void k_assemble(int64_t N, int64_t nT, const int4 *__restrict__ rwg4,
+__global__ __launch_bounds__(256) void k_assemble(int64_t N, int64_t nT, int64_t nTz, const int4 *__restrict__ rwg4,
                                                   const R *__restrict__ LB, double2 *__restrict__ Z64,
                                                   float2 *__restrict__ Z32)
 {
-    const int64_t n = int64_t(blockIdx.x) * 64 + (threadIdx.x & 63);
-    const int64_t m = int64_t(blockIdx.y) * 4 + (threadIdx.x >> 6);
-    if (m >= N || n >= N) return;
-    const int4 em = rwg4[m], en = rwg4[n];
-    R r1, i1, r2, i2, r3, i3, r4, i4;
-    read_local(LB, nT, em.x, em.z, en.x, en.z, r1, i1);   // (+,+)
-    read_local(LB, nT, em.y, em.w, en.y, en.w, r2, i2);   // (-,-)
-    read_local(LB, nT, em.x, em.z, en.y, en.w, r3, i3);   // (+,-)
-    read_local(LB, nT, em.y, em.w, en.x, en.z, r4, i4);   // (-,+)
-    const R zr = (r1 + r2) + (r3 + r4);
-    const R zi = (i1 + i2) + (i3 + i4);
-    if (Z64) Z64[m * N + n] = make_double2(double(zr), double(zi));
-    if (Z32) Z32[m * N + n] = make_float2(float(zr), float(zi));
+    int64_t I, J;
+    tile_decode(blockIdx.x, nTz, I, J);
+    const int64_t base = int64_t(blockIdx.x) * TB * TB;
+#pragma unroll 4
+    for (int q = 0; q < TB * TB / 256; ++q) {
+        const int e = threadIdx.x + 256 * q;
+        const int64_t m = I * TB + e / TB, n = J * TB + e % TB;
+        R zr = 0, zi = 0;
+        if (m < N && n < N) {
+            const int4 em = rwg4[m], en = rwg4[n];
+            R r1, i1, r2, i2, r3, i3, r4, i4;
+            read_local(LB, nT, em.x, em.z, en.x, en.z, r1, i1);   // (+,+)
+            read_local(LB, nT, em.y, em.w, en.y, en.w, r2, i2);   // (-,-)
+            read_local(LB, nT, em.x, em.z, en.y, en.w, r3, i3);   // (+,-)
+            read_local(LB, nT, em.y, em.w, en.x, en.z, r4, i4);   // (-,+)
+            zr = (r1 + r2) + (r3 + r4);
+            zi = (i1 + i2) + (i3 + i4);
+        }
+        if (Z64) Z64[base + e] = make_double2(double(zr), double(zi));
+        if (Z32) Z32[base + e] = make_float2(float(zr), float(zi));
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -595,8 +605,8 @@ void fill_matrix(bie_op *op, bool fp64_regular, bool want64, bool want32, hipStr
                 hipLaunchKernelGGL(k_pairs_singular<double>, dim3(unsigned((npairs + 127) / 128)), dim3(128), 0, s,
                                    npairs, nT, pairs, D.cent, D.loc, D.vfree, D.verts, D.area, D.sgn, op->k,
                                    (double *)LB);
-            hipLaunchKernelGGL(k_assemble<double>, dim3(unsigned((N + 63) / 64), unsigned((N + 3) / 4)), dim3(256), 0, s,
-                               N, nT, (const int4 *)D.edges, (const double *)LB,
+            hipLaunchKernelGGL(k_assemble<double>, dim3(unsigned(op->pk.ntiles)), dim3(256), 0, s, N, nT, op->pk.nT,
+                               (const int4 *)D.edges, (const double *)LB,
                                want64 ? (double2 *)op->Z64 : nullptr, want32 ? (float2 *)op->Z32 : nullptr);
         } else {
             hipLaunchKernelGGL(k_pairs_regular<float>, dim3(unsigned(ntiles)), dim3(256), 0, s, F, nT, ntiles,
@@ -605,8 +615,8 @@ void fill_matrix(bie_op *op, bool fp64_regular, bool want64, bool want32, hipStr
                 hipLaunchKernelGGL(k_pairs_singular<float>, dim3(unsigned((npairs + 127) / 128)), dim3(128), 0, s,
                                    npairs, nT, pairs, D.cent, D.loc, D.vfree, D.verts, D.area, D.sgn, op->k,
                                    (float *)LB);
-            hipLaunchKernelGGL(k_assemble<float>, dim3(unsigned((N + 63) / 64), unsigned((N + 3) / 4)), dim3(256), 0, s,
-                               N, nT, (const int4 *)D.edges, (const float *)LB,
+            hipLaunchKernelGGL(k_assemble<float>, dim3(unsigned(op->pk.ntiles)), dim3(256), 0, s, N, nT, op->pk.nT,
+                               (const int4 *)D.edges, (const float *)LB,
                                want64 ? (double2 *)op->Z64 : nullptr, want32 ? (float2 *)op->Z32 : nullptr);
         }
         BIE_HIP(hipGetLastError());

@@ -4,8 +4,9 @@
 // The paper solves eq:discretizedEFIE "using an iterative solver" (Sec. II)
 // and names GMRES, CG and the two criteria only in its acronym list; the
 // readings implemented:
-//   GMRES(m): Arnoldi with classical Gram-Schmidt applied twice (CGS2),
-//     complex Givens rotations kept in FP64 on the device, tolerance relative
+//   GMRES(m): Arnoldi with classical Gram-Schmidt and selective
+//     reorthogonalisation (DGKS), complex Givens rotations kept in FP64 on the
+//     device, tolerance relative
 //     to ||b||; a cycle ends when |g_{j+1}|/||b|| <= tol, on breakdown, or at
 //     j = m; the criterion is then evaluated on the true residual, and the
 //     method restarts from the true residual if it fails.
@@ -33,15 +34,13 @@
 
 namespace bie {
 
-void gemv_strided(bool fp64, const void *Z, int64_t N, const void *X, int64_t ldx, void *Y, int64_t ldy,
-                  const void *B, int64_t ldb, int64_t R, const int *skip, int64_t sks, bool conj, hipStream_t s);
 
 namespace {
 
 constexpr int BT = 256;          // threads per block
 constexpr int EPT = 4;           // elements per thread in vector kernels
 constexpr int BE = BT * EPT;     // elements per block
-constexpr int MAXM = 128;        // largest restart length
+constexpr int MAXM = 64;         // largest restart length
 
 struct ColStat {
     double bnorm;    // ||b||
@@ -58,7 +57,8 @@ struct ColStat {
     int brk;         // breakdown
     int active;      // column still solving
     int check;       // CGNR: recursive estimate met the tolerance
-    int pad[2];
+    int reorth;      // GMRES: second Gram-Schmidt pass taken in this iteration
+    int pad;
 };
 static_assert(sizeof(ColStat) == 96, "ColStat layout");
 
@@ -73,6 +73,64 @@ __device__ inline double wsum(double v)
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
+}
+
+// Sums 8 complex values p[0..7] over the 64 lanes of a wave at once.  Each
+// exchange step halves the number of values a lane carries (it keeps one half,
+// sends the other to its partner), so 8 sums cost 4+2+1+3 exchanges instead of
+// 8x6.  On return p[0] of lane L holds the total of value (L >> 3) & 7.
+__device__ inline void wave_sum8(double2 p[8])
+{
+    const int lane = threadIdx.x & 63;
+    {
+        const bool b = lane & 32;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const double2 snd = b ? p[i] : p[i + 4];
+            const double2 kp = b ? p[i + 4] : p[i];
+            p[i] = make_double2(kp.x + __shfl_xor(snd.x, 32, 64), kp.y + __shfl_xor(snd.y, 32, 64));
+        }
+    }
+    {
+        const bool b = lane & 16;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const double2 snd = b ? p[i] : p[i + 2];
+            const double2 kp = b ? p[i + 2] : p[i];
+            p[i] = make_double2(kp.x + __shfl_xor(snd.x, 16, 64), kp.y + __shfl_xor(snd.y, 16, 64));
+        }
+    }
+    {
+        const bool b = lane & 8;
+        const double2 snd = b ? p[0] : p[1];
+        const double2 kp = b ? p[1] : p[0];
+        p[0] = make_double2(kp.x + __shfl_xor(snd.x, 8, 64), kp.y + __shfl_xor(snd.y, 8, 64));
+    }
+#pragma unroll
+    for (int o = 4; o > 0; o >>= 1) {
+        p[0].x += __shfl_xor(p[0].x, o, 64);
+        p[0].y += __shfl_xor(p[0].y, o, 64);
+    }
+}
+
+// Block partial of conj(V[k][e]) * w for k = 0..nk-1 (e = this thread's element),
+// written to red[k][wave]; wave-level sums use wave_sum8 over groups of 8 k.
+__device__ inline void block_dots(const double2 *__restrict__ V, int64_t N, int64_t e, bool in, double2 w, int nk,
+                                  double2 (*red)[4])
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int k0 = 0; k0 < nk; k0 += 8) {
+        double2 p[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int k = k0 + i;
+            p[i] = make_double2(0.0, 0.0);
+            if (in && k < nk) p[i] = cmulc(V[int64_t(k) * N + e], w);
+        }
+        wave_sum8(p);
+        const int kk = k0 + ((lane >> 3) & 7);
+        if ((lane & 7) == 0 && kk < nk) red[kk][wave] = p[0];
+    }
 }
 
 // Last-block election: returns true in every thread of the block that
@@ -115,94 +173,191 @@ __device__ inline void chunk_dots(const double2 *__restrict__ V, int64_t N, int6
     }
 }
 
-// Arnoldi pass 1: h1 = V_{0..j}^H w and ||w||.
-__global__ __launch_bounds__(BT) void k_arn_dot1(int64_t N, int m, int j, const double2 *__restrict__ Vall,
-                                                 const double2 *__restrict__ Wall, double2 *__restrict__ partall,
-                                                 double2 *__restrict__ h1all, unsigned *__restrict__ counters,
-                                                 ColStat *__restrict__ st)
+// ---------------------------------------------------------------------------
+// Arnoldi step j: classical Gram-Schmidt with selective reorthogonalisation
+// (Daniel, Gragg, Kaufman & Stewart, Math. Comp. 30, 1976): after the first
+// pass w' = w - V h1, a second pass is made only if ||w'||^2 < ||w||^2 / 2,
+// judged from ||w||^2 - ||h1||^2 (accurate whenever the test passes).  Every
+// block evaluates the test from the same sums in the same order, so all blocks
+// agree.  One element per thread; blocks write partial sums, the next launch
+// adds the partials of all blocks itself, in block order (no atomics).
+//   pass1:  P1 = partial V_{0..j}^H w (2-D grid: 8 basis vectors per block
+//           column), ||w||^2 partials
+//   pass2:  h1 = sum P1; w' = w - V h1; PN = partial ||w'||^2; if the test
+//           fails also P2 = partial V^H w'
+//   pass3:  only after a failed test: h2 = sum P2; w'' = w' - V h2; PN again
+//   finish: h_{j+1,j} = sqrt(sum PN); v_{j+1} = w / h_{j+1,j}; Givens update
+//           and the cycle test (block 0).
+constexpr int AB = 256;   // elements (threads) per block in the Arnoldi kernels
+constexpr int KG = 8;     // basis vectors per block in the first pass
+
+__global__ __launch_bounds__(AB) void k_cgs_pass1(int64_t N, int m, int j, const double2 *__restrict__ Vall,
+                                                  const double2 *__restrict__ Wall, double2 *__restrict__ P1all,
+                                                  double *__restrict__ PWall, const ColStat *__restrict__ st)
 {
-    const int r = blockIdx.y;
+    const int r = blockIdx.z;
     if (st[r].done) return;
-    const unsigned nblk = gridDim.x;
-    const int64_t e0 = int64_t(blockIdx.x) * BE;
+    const int k0 = blockIdx.y * KG;
+    if (k0 > j) return;
+    const int nb = gridDim.x;
+    const int64_t e = int64_t(blockIdx.x) * AB + threadIdx.x;
+    const bool in = e < N;
     const double2 *V = Vall + int64_t(r) * (m + 1) * N;
-    const double2 *W = Wall + int64_t(r) * N;
-    double2 *part = partall + int64_t(r) * nblk * (m + 2);
-    __shared__ double2 sw[BE];
-    double nn = 0.0;
-    for (int t = threadIdx.x; t < BE; t += BT) {
-        const int64_t e = e0 + t;
-        const double2 w = e < N ? W[e] : make_double2(0.0, 0.0);
-        sw[t] = w;
-        nn += w.x * w.x + w.y * w.y;
+    const double2 w = in ? Wall[int64_t(r) * N + e] : make_double2(0.0, 0.0);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double2 p[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        p[i] = make_double2(0.0, 0.0);
+        if (in && k0 + i <= j) p[i] = cmulc(V[int64_t(k0 + i) * N + e], w);
+    }
+    wave_sum8(p);
+    __shared__ double2 red[KG][AB / 64];
+    __shared__ double rn[AB / 64];
+    if ((lane & 7) == 0) red[lane >> 3][wave] = p[0];
+    if (blockIdx.y == 0) {
+        const double nn = wsum(w.x * w.x + w.y * w.y);
+        if (lane == 0) rn[wave] = nn;
     }
     __syncthreads();
-    chunk_dots(V, N, e0, j + 1, sw, part + int64_t(blockIdx.x) * (m + 2));
-    __shared__ double red[BT / 64];
-    nn = wsum(nn);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nn;
-    __syncthreads();
-    if (threadIdx.x == 0) part[int64_t(blockIdx.x) * (m + 2) + m + 1] = make_double2(red[0] + red[1] + red[2] + red[3], 0.0);
-    if (!last_block(counters + r, nblk)) return;
-    for (int k = threadIdx.x; k <= j + 1; k += BT) {
-        const int kk = (k == j + 1) ? m + 1 : k;
+    double2 *P1 = P1all + (int64_t(r) * nb + blockIdx.x) * (m + 1);
+    if (threadIdx.x < KG && k0 + int(threadIdx.x) <= j) {
+        double2 a = red[threadIdx.x][0];
+        for (int q = 1; q < AB / 64; ++q) { a.x += red[threadIdx.x][q].x; a.y += red[threadIdx.x][q].y; }
+        P1[k0 + threadIdx.x] = a;
+    }
+    if (blockIdx.y == 0 && threadIdx.x == 0) PWall[int64_t(r) * nb + blockIdx.x] = rn[0] + rn[1] + rn[2] + rn[3];
+}
+
+// h[k] = sum over blocks of P[b][k], k <= kmax, into LDS (block order)
+__device__ inline void sum_partials(const double2 *__restrict__ P, int nb, int stride, int kmax, double2 *h)
+{
+    for (int k = threadIdx.x; k <= kmax; k += AB) {
         double ar = 0.0, ai = 0.0;
-        for (unsigned b = 0; b < nblk; ++b) {
-            const double2 p = part[int64_t(b) * (m + 2) + kk];
-            ar += p.x;
-            ai += p.y;
+#pragma unroll 8
+        for (int b = 0; b < nb; ++b) {
+            const double2 v = P[int64_t(b) * stride + k];
+            ar += v.x;
+            ai += v.y;
         }
-        if (k <= j) h1all[int64_t(r) * (m + 1) + k] = make_double2(ar, ai);
-        else st[r].wnorm0 = sqrt(ar);
+        h[k] = make_double2(ar, ai);
     }
 }
 
-// Arnoldi pass 2: w -= V h1, then h2 = V^H w; H(:,j) = h1 + h2.
-__global__ __launch_bounds__(BT) void k_arn_upd_dot2(int64_t N, int m, int j, const double2 *__restrict__ Vall,
-                                                     double2 *__restrict__ Wall, double2 *__restrict__ partall,
-                                                     const double2 *__restrict__ h1all, double2 *__restrict__ h2all,
-                                                     double2 *__restrict__ Hall, unsigned *__restrict__ counters,
-                                                     ColStat *__restrict__ st)
+// sum over blocks of real partials, by wave 0 (lanes load in parallel, fixed tree)
+__device__ inline double sum_real_partials(const double *__restrict__ P, int nb)
+{
+    double a = 0.0;
+    for (int b = threadIdx.x & 63; b < nb; b += 64) a += P[b];
+    return wsum(a);
+}
+
+// w -= V_{0..j} h (h in LDS), loads batched 8 basis vectors at a time
+__device__ inline double2 cgs_update(const double2 *__restrict__ V, int64_t N, int64_t e, int j, double2 w,
+                                     const double2 *h)
+{
+    for (int k0 = 0; k0 <= j; k0 += 8) {
+        double2 vv[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) vv[i] = k0 + i <= j ? V[int64_t(k0 + i) * N + e] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            if (k0 + i > j) break;
+            const double2 p = cmul(vv[i], h[k0 + i]);
+            w.x -= p.x;
+            w.y -= p.y;
+        }
+    }
+    return w;
+}
+
+__global__ __launch_bounds__(AB) void k_cgs_pass2(int64_t N, int m, int j, const double2 *__restrict__ Vall,
+                                                  double2 *__restrict__ Wall, const double2 *__restrict__ P1all,
+                                                  const double *__restrict__ PWall, double2 *__restrict__ P2all,
+                                                  double *__restrict__ PNall, double2 *__restrict__ Hall,
+                                                  ColStat *__restrict__ st)
 {
     const int r = blockIdx.y;
     if (st[r].done) return;
-    const unsigned nblk = gridDim.x;
-    const int64_t e0 = int64_t(blockIdx.x) * BE;
+    const int nb = gridDim.x;
+    __shared__ double2 h[MAXM + 1];
+    __shared__ int s_reorth;
+    __shared__ double s_w2;
+    sum_partials(P1all + int64_t(r) * nb * (m + 1), nb, m + 1, j, h);
+    if (threadIdx.x < 64) {
+        const double w2 = sum_real_partials(PWall + int64_t(r) * nb, nb);
+        if (threadIdx.x == 0) s_w2 = w2;
+    }
+    __syncthreads();
+    // DGKS test from ||w||^2 and ||h1||^2 (same sums, same order in every block)
+    if (threadIdx.x == 0) {
+        double h2 = 0.0;
+        for (int k = 0; k <= j; ++k) h2 += h[k].x * h[k].x + h[k].y * h[k].y;
+        s_reorth = (s_w2 - h2) < 0.5 * s_w2;
+    }
+    __syncthreads();
+    const bool reorth = s_reorth != 0;
+    if (blockIdx.x == 0) {
+        for (int k = threadIdx.x; k <= j; k += AB) Hall[(int64_t(r) * m + j) * (m + 1) + k] = h[k];
+        if (threadIdx.x == 0) st[r].reorth = reorth;
+    }
+    const int64_t e = int64_t(blockIdx.x) * AB + threadIdx.x;
+    const bool in = e < N;
     const double2 *V = Vall + int64_t(r) * (m + 1) * N;
-    double2 *W = Wall + int64_t(r) * N;
-    double2 *part = partall + int64_t(r) * nblk * (m + 2);
-    __shared__ double2 sh[MAXM];
-    __shared__ double2 sw[BE];
-    if (threadIdx.x <= j) sh[threadIdx.x] = h1all[int64_t(r) * (m + 1) + threadIdx.x];
-    __syncthreads();
-    for (int t = threadIdx.x; t < BE; t += BT) {
-        const int64_t e = e0 + t;
-        double2 w = make_double2(0.0, 0.0);
-        if (e < N) {
-            w = W[e];
-            for (int k = 0; k <= j; ++k) {
-                const double2 p = cmul(V[int64_t(k) * N + e], sh[k]);
-                w.x -= p.x;
-                w.y -= p.y;
-            }
-            W[e] = w;
-        }
-        sw[t] = w;
+    double2 w = make_double2(0.0, 0.0);
+    if (in) {
+        w = cgs_update(V, N, e, j, Wall[int64_t(r) * N + e], h);
+        Wall[int64_t(r) * N + e] = w;
     }
-    __syncthreads();
-    chunk_dots(V, N, e0, j + 1, sw, part + int64_t(blockIdx.x) * (m + 2));
-    if (!last_block(counters + r, nblk)) return;
-    for (int k = threadIdx.x; k <= j; k += BT) {
-        double ar = 0.0, ai = 0.0;
-        for (unsigned b = 0; b < nblk; ++b) {
-            const double2 p = part[int64_t(b) * (m + 2) + k];
-            ar += p.x;
-            ai += p.y;
+    __shared__ double rn[AB / 64];
+    const double nn = wsum(w.x * w.x + w.y * w.y);
+    if ((threadIdx.x & 63) == 0) rn[threadIdx.x >> 6] = nn;
+    if (reorth) {
+        __shared__ double2 red[MAXM + 1][AB / 64];
+        block_dots(V, N, e, in, w, j + 1, red);
+        __syncthreads();
+        double2 *P2 = P2all + (int64_t(r) * nb + blockIdx.x) * (m + 1);
+        for (int k = threadIdx.x; k <= j; k += AB) {
+            double2 a = red[k][0];
+            for (int q = 1; q < AB / 64; ++q) { a.x += red[k][q].x; a.y += red[k][q].y; }
+            P2[k] = a;
         }
-        h2all[int64_t(r) * (m + 1) + k] = make_double2(ar, ai);
-        const double2 h1 = sh[k];
-        Hall[(int64_t(r) * m + j) * (m + 1) + k] = make_double2(h1.x + ar, h1.y + ai);
+    } else {
+        __syncthreads();
     }
+    if (threadIdx.x == 0) PNall[int64_t(r) * nb + blockIdx.x] = rn[0] + rn[1] + rn[2] + rn[3];
+}
+
+__global__ __launch_bounds__(AB) void k_cgs_pass3(int64_t N, int m, int j, const double2 *__restrict__ Vall,
+                                                  double2 *__restrict__ Wall, const double2 *__restrict__ P2all,
+                                                  double *__restrict__ PNall, double2 *__restrict__ Hall,
+                                                  const ColStat *__restrict__ st)
+{
+    const int r = blockIdx.y;
+    if (st[r].done || !st[r].reorth) return;
+    const int nb = gridDim.x;
+    __shared__ double2 h[MAXM + 1];
+    sum_partials(P2all + int64_t(r) * nb * (m + 1), nb, m + 1, j, h);
+    __syncthreads();
+    if (blockIdx.x == 0)
+        for (int k = threadIdx.x; k <= j; k += AB) {
+            double2 *hc = Hall + (int64_t(r) * m + j) * (m + 1) + k;
+            const double2 a = *hc;
+            *hc = make_double2(a.x + h[k].x, a.y + h[k].y);
+        }
+    const int64_t e = int64_t(blockIdx.x) * AB + threadIdx.x;
+    double nn = 0.0;
+    if (e < N) {
+        const double2 *V = Vall + int64_t(r) * (m + 1) * N;
+        const double2 w = cgs_update(V, N, e, j, Wall[int64_t(r) * N + e], h);
+        Wall[int64_t(r) * N + e] = w;
+        nn = w.x * w.x + w.y * w.y;
+    }
+    __shared__ double red[AB / 64];
+    nn = wsum(nn);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nn;
+    __syncthreads();
+    if (threadIdx.x == 0) PNall[int64_t(r) * nb + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
 // Givens rotation [c s; -conj(s) c], c real, mapping (a, b) to (rho, 0).
@@ -217,115 +372,103 @@ __device__ inline void givens(double2 a, double2 b, double &c, double2 &s)
     s = make_double2((ph.x * b.x + ph.y * b.y) / t, (ph.y * b.x - ph.x * b.y) / t);   // (a/|a|) conj(b) / t
 }
 
-// Arnoldi pass 3: w -= V h2, h_{j+1,j} = ||w||; Givens update of column j.
-__global__ __launch_bounds__(BT) void k_arn_upd_norm(int64_t N, int m, int j, double tol,
-                                                     const double2 *__restrict__ Vall, double2 *__restrict__ Wall,
-                                                     double2 *__restrict__ partall, const double2 *__restrict__ h2all,
-                                                     double2 *__restrict__ Hall, double *__restrict__ csall,
-                                                     double2 *__restrict__ snall, double2 *__restrict__ gall,
-                                                     unsigned *__restrict__ counters, ColStat *__restrict__ st)
+__global__ __launch_bounds__(AB) void k_cgs_finish(int64_t N, int m, int j, double tol, double2 *__restrict__ Vall,
+                                                   const double2 *__restrict__ Wall, const double *__restrict__ PNall,
+                                                   const double *__restrict__ PWall, double2 *__restrict__ Hall,
+                                                   double *__restrict__ csall, double2 *__restrict__ snall,
+                                                   double2 *__restrict__ gall, ColStat *__restrict__ st)
 {
     const int r = blockIdx.y;
     if (st[r].done) return;
-    const unsigned nblk = gridDim.x;
-    const int64_t e0 = int64_t(blockIdx.x) * BE;
-    const double2 *V = Vall + int64_t(r) * (m + 1) * N;
-    double2 *W = Wall + int64_t(r) * N;
-    double2 *part = partall + int64_t(r) * nblk * (m + 2);
-    __shared__ double2 sh[MAXM];
-    if (threadIdx.x <= j) sh[threadIdx.x] = h2all[int64_t(r) * (m + 1) + threadIdx.x];
-    __syncthreads();
-    double nn = 0.0;
-    for (int t = threadIdx.x; t < BE; t += BT) {
-        const int64_t e = e0 + t;
-        if (e < N) {
-            double2 w = W[e];
-            for (int k = 0; k <= j; ++k) {
-                const double2 p = cmul(V[int64_t(k) * N + e], sh[k]);
-                w.x -= p.x;
-                w.y -= p.y;
-            }
-            W[e] = w;
-            nn += w.x * w.x + w.y * w.y;
+    const int nb = gridDim.x;
+    __shared__ double s_hn, s_w2;
+    __shared__ double2 Hc[MAXM + 2], sn[MAXM];
+    __shared__ double cs[MAXM];
+    if (threadIdx.x < 64) {
+        const double a = sum_real_partials(PNall + int64_t(r) * nb, nb);
+        const double b = sum_real_partials(PWall + int64_t(r) * nb, nb);
+        if (threadIdx.x == 0) { s_hn = sqrt(a); s_w2 = b; }
+    }
+    if (blockIdx.x == 0) {
+        for (int k = threadIdx.x; k <= j; k += AB) Hc[k] = Hall[(int64_t(r) * m + j) * (m + 1) + k];
+        for (int k = threadIdx.x; k < j; k += AB) {
+            cs[k] = csall[int64_t(r) * m + k];
+            sn[k] = snall[int64_t(r) * m + k];
         }
     }
-    __shared__ double red[BT / 64];
-    nn = wsum(nn);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nn;
     __syncthreads();
-    if (threadIdx.x == 0) part[int64_t(blockIdx.x) * (m + 2)] = make_double2(red[0] + red[1] + red[2] + red[3], 0.0);
-    if (!last_block(counters + r, nblk)) return;
-    if (threadIdx.x != 0) return;
-    double s2 = 0.0;
-    for (unsigned b = 0; b < nblk; ++b) s2 += part[int64_t(b) * (m + 2)].x;
-    const double hn = sqrt(s2);
+    const double hn = s_hn;
+    const int64_t e = int64_t(blockIdx.x) * AB + threadIdx.x;
+    if (e < N && hn > 0.0) {
+        const double inv = 1.0 / hn;
+        const double2 w = Wall[int64_t(r) * N + e];
+        Vall[(int64_t(r) * (m + 1) + j + 1) * N + e] = make_double2(w.x * inv, w.y * inv);
+    }
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
     ColStat &S = st[r];
     S.hn = hn;
-    double2 *H = Hall + (int64_t(r) * m + j) * (m + 1);
-    double *cs = csall + int64_t(r) * m;
-    double2 *sn = snall + int64_t(r) * m;
-    double2 *g = gall + int64_t(r) * (m + 1);
-    H[j + 1] = make_double2(hn, 0.0);
+    S.wnorm0 = sqrt(s_w2);
+    Hc[j + 1] = make_double2(hn, 0.0);
     for (int i = 0; i < j; ++i) {
-        const double2 a = H[i], b = H[i + 1];
+        const double2 a = Hc[i], b = Hc[i + 1];
         const double2 sb = cmul(sn[i], b);
         const double2 csa = cmul(make_double2(sn[i].x, -sn[i].y), a);
-        H[i] = make_double2(cs[i] * a.x + sb.x, cs[i] * a.y + sb.y);
-        H[i + 1] = make_double2(-csa.x + cs[i] * b.x, -csa.y + cs[i] * b.y);
+        Hc[i] = make_double2(cs[i] * a.x + sb.x, cs[i] * a.y + sb.y);
+        Hc[i + 1] = make_double2(-csa.x + cs[i] * b.x, -csa.y + cs[i] * b.y);
     }
     double c;
     double2 s;
-    givens(H[j], H[j + 1], c, s);
-    cs[j] = c;
-    sn[j] = s;
-    const double2 sb = cmul(s, H[j + 1]);
-    H[j] = make_double2(c * H[j].x + sb.x, c * H[j].y + sb.y);
-    H[j + 1] = make_double2(0.0, 0.0);
+    givens(Hc[j], Hc[j + 1], c, s);
+    const double2 sb = cmul(s, Hc[j + 1]);
+    Hc[j] = make_double2(c * Hc[j].x + sb.x, c * Hc[j].y + sb.y);
+    Hc[j + 1] = make_double2(0.0, 0.0);
+    double2 *H = Hall + (int64_t(r) * m + j) * (m + 1);
+    for (int i = 0; i <= j + 1; ++i) H[i] = Hc[i];
+    csall[int64_t(r) * m + j] = c;
+    snall[int64_t(r) * m + j] = s;
+    double2 *g = gall + int64_t(r) * (m + 1);
     const double2 gj = g[j];
     const double2 t = cmul(make_double2(s.x, -s.y), gj);
     g[j + 1] = make_double2(-t.x, -t.y);
     g[j] = make_double2(c * gj.x, c * gj.y);
-    S.est = hypot(g[j + 1].x, g[j + 1].y) / S.bnorm;
+    S.est = hypot(t.x, t.y) / S.bnorm;
     const bool brk = hn <= 64.0 * 2.220446049250313e-16 * S.wnorm0;
     S.jend = j + 1;
     if (brk) S.brk = 1;
     if (S.est <= tol || brk || j + 1 >= S.jcap) S.done = 1;
 }
 
-// v_{j+1} = w / h_{j+1,j}
-__global__ __launch_bounds__(BT) void k_arn_normalize(int64_t N, int m, int j, double2 *__restrict__ Vall,
-                                                      const double2 *__restrict__ Wall, const ColStat *__restrict__ st)
+// Upper-triangular solve H y = g for the iterations of the cycle: one block
+// per column, H and g staged in LDS, column-oriented back substitution.
+__global__ __launch_bounds__(64) void k_lsq(int m, const double2 *__restrict__ Hall, const double2 *__restrict__ gall,
+                                            double2 *__restrict__ yall, const ColStat *__restrict__ st)
 {
-    const int r = blockIdx.y;
-    if (st[r].done) return;
-    const double inv = 1.0 / st[r].hn;
-    const double2 *W = Wall + int64_t(r) * N;
-    double2 *v = Vall + (int64_t(r) * (m + 1) + j + 1) * N;
-    for (int64_t e = int64_t(blockIdx.x) * BT + threadIdx.x; e < N; e += int64_t(gridDim.x) * BT) {
-        const double2 w = W[e];
-        v[e] = make_double2(w.x * inv, w.y * inv);
-    }
-}
-
-// Upper-triangular solve H y = g for the iterations of the cycle (one thread per column).
-__global__ void k_lsq(int R, int m, const double2 *__restrict__ Hall, const double2 *__restrict__ gall,
-                      double2 *__restrict__ yall, const ColStat *__restrict__ st)
-{
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= R || !st[r].active) return;
+    const int r = blockIdx.x;
+    if (!st[r].active) return;
     const int je = st[r].jend;
-    const double2 *g = gall + int64_t(r) * (m + 1);
-    double2 *y = yall + int64_t(r) * m;
+    extern __shared__ double2 Hs[];          // Hs[k*m + i] = H(i, k), upper part, m*m entries
+    __shared__ double2 g[MAXM + 1];
+    for (int idx = threadIdx.x; idx < je * je; idx += 64) {
+        const int k = idx / je, i = idx % je;
+        if (i <= k) Hs[k * m + i] = Hall[(int64_t(r) * m + k) * (m + 1) + i];
+    }
+    for (int i = threadIdx.x; i < je; i += 64) g[i] = gall[int64_t(r) * (m + 1) + i];
+    __syncthreads();
     for (int i = je - 1; i >= 0; --i) {
-        double2 acc = g[i];
-        for (int k = i + 1; k < je; ++k) {
-            const double2 p = cmul(Hall[(int64_t(r) * m + k) * (m + 1) + i], y[k]);
-            acc.x -= p.x;
-            acc.y -= p.y;
+        __shared__ double2 yi;
+        if (threadIdx.x == 0) {
+            const double2 d = Hs[i * m + i], a = g[i];
+            const double dd = d.x * d.x + d.y * d.y;
+            yi = make_double2((a.x * d.x + a.y * d.y) / dd, (a.y * d.x - a.x * d.y) / dd);
+            yall[int64_t(r) * m + i] = yi;
         }
-        const double2 d = Hall[(int64_t(r) * m + i) * (m + 1) + i];
-        const double dd = d.x * d.x + d.y * d.y;
-        y[i] = make_double2((acc.x * d.x + acc.y * d.y) / dd, (acc.y * d.x - acc.x * d.y) / dd);
+        __syncthreads();
+        for (int q = threadIdx.x; q < i; q += 64) {
+            const double2 p = cmul(Hs[i * m + q], yi);
+            g[q].x -= p.x;
+            g[q].y -= p.y;
+        }
+        __syncthreads();
     }
 }
 
@@ -377,35 +520,6 @@ __global__ __launch_bounds__(BT) void k_norm(int64_t N, const double2 *__restric
     for (unsigned b = 0; b < nblk; ++b) s += part[int64_t(r) * nblk + b];
     double *f = reinterpret_cast<double *>(&st[r]);
     f[field] = sqrt(s);
-}
-
-// Sampled residual rows (RSCC): one wave per sampled row.
-__global__ __launch_bounds__(BT) void k_rscc_rows(int64_t N, int S, const double2 *__restrict__ Z,
-                                                  const double2 *__restrict__ B, const double2 *__restrict__ X,
-                                                  const int64_t *__restrict__ rows, double *__restrict__ out,
-                                                  const int *__restrict__ mask)
-{
-    const int r = blockIdx.y;
-    if (!mask[r]) return;
-    const int lane = threadIdx.x & 63;
-    const int s = blockIdx.x * (BT / 64) + (threadIdx.x >> 6);
-    if (s >= S) return;
-    const int64_t i = rows[int64_t(r) * S + s];
-    const double2 *z = Z + i * N;
-    const double2 *x = X + int64_t(r) * N;
-    double ar = 0.0, ai = 0.0;
-    for (int64_t c = lane; c < N; c += 64) {
-        const double2 p = cmul(z[c], x[c]);
-        ar += p.x;
-        ai += p.y;
-    }
-    ar = wsum(ar);
-    ai = wsum(ai);
-    if (lane == 0) {
-        const double2 b = B[int64_t(r) * N + i];
-        const double dr = b.x - ar, di = b.y - ai;
-        out[int64_t(r) * S + s] = dr * dr + di * di;
-    }
 }
 
 // Start a cycle from the residual: v0 = res/||res||, g = (||res||, 0, ...).
@@ -563,7 +677,8 @@ struct Workspace {
     int m = 0;
     unsigned nblk = 0;
     double2 *V = nullptr, *W = nullptr, *Res = nullptr, *H = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr;
-    double2 *h1 = nullptr, *h2 = nullptr, *part = nullptr;
+    double2 *h1 = nullptr, *h2 = nullptr, *part = nullptr, *P1 = nullptr, *P2 = nullptr;
+    double *PN = nullptr, *PW = nullptr;
     double *cs = nullptr, *dpart = nullptr, *rs = nullptr;
     unsigned *counters = nullptr;
     ColStat *st = nullptr;
@@ -611,6 +726,11 @@ static Workspace *get_ws(bie_op *op, int64_t R, int m)
         w->h1 = w->alloc<double2>(size_t(R) * (m + 1));
         w->h2 = w->alloc<double2>(size_t(R) * (m + 1));
         w->part = w->alloc<double2>(size_t(R) * w->nblk * (m + 2));
+        const size_t ab = size_t((N + AB - 1) / AB);
+        w->P1 = w->alloc<double2>(size_t(R) * ab * (m + 1));
+        w->P2 = w->alloc<double2>(size_t(R) * ab * (m + 1));
+        w->PN = w->alloc<double>(size_t(R) * ab);
+        w->PW = w->alloc<double>(size_t(R) * ab);
         w->dpart = w->alloc<double>(size_t(R) * std::max<unsigned>(w->nblk, 1));
         w->rs = w->alloc<double>(size_t(R) * MAX_RSCC_ROWS);
         w->counters = w->alloc<unsigned>(size_t(R));
@@ -640,7 +760,6 @@ int solve(const bie_op *opc, const void *Bv, void *Xv, int64_t R, const bie_solv
     bie_op *op = const_cast<bie_op *>(opc);
     const int64_t N = op->mesh.N;
     const bool fp64 = op->Z64 != nullptr;
-    const void *Z = fp64 ? op->Z64 : op->Z32;
     const int m = o.method == BIE_GMRES ? o.restart : 1;
     Workspace *w = get_ws(op, R, m);
     const double2 *B = static_cast<const double2 *>(Bv);
@@ -695,7 +814,7 @@ int solve(const bie_op *opc, const void *Bv, void *Xv, int64_t R, const bie_solv
         std::vector<int> sk(R);
         for (int64_t r = 0; r < R; ++r) sk[r] = need[r] ? 0 : 1;
         push_skip(sk);
-        gemv_strided(fp64, Z, N, X, N, w->Res, N, B, N, R, dskip, 1, false, s);
+        product(op, fp64, true, X, N, w->Res, N, B, N, R, dskip, 1, false, s);
         // k_norm mask: need
         push_skip(need);
         hipLaunchKernelGGL(k_norm, vgrid, dim3(BT), 0, s, N, w->Res, N, w->dpart, w->counters, w->st, field_rnorm,
@@ -730,12 +849,7 @@ int solve(const bie_op *opc, const void *Bv, void *Xv, int64_t R, const bie_solv
                 }
             BIE_HIP(hipMemcpyAsync(w->rows, rows.data(), rows.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
             push_skip(need);
-            if (fp64) {
-                hipLaunchKernelGGL(k_rscc_rows, dim3(unsigned((S + 3) / 4), unsigned(R)), dim3(BT), 0, s, N, int(S),
-                                   (const double2 *)Z, B, X, w->rows, w->rs, dskip);
-            } else {
-                throw Error(BIE_EINVAL, "random-sampling criterion needs the FP64 matrix");
-            }
+            sampled_residual(op, B, X, R, S, w->rows, w->rs, dskip, s);
             BIE_HIP(hipGetLastError());
             std::vector<double> rs(R * S);
             BIE_HIP(hipMemcpyAsync(rs.data(), w->rs, rs.size() * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -803,20 +917,22 @@ int solve(const bie_op *opc, const void *Bv, void *Xv, int64_t R, const bie_solv
             int jmax = 0;
             for (int64_t r = 0; r < R; ++r)
                 if (active[r]) jmax = std::max(jmax, st[r].jcap);
+            const dim3 agrid(unsigned((N + AB - 1) / AB), unsigned(R));
+            const dim3 pgrid(unsigned((N + AB - 1) / AB), unsigned((m + 1 + KG - 1) / KG), unsigned(R));
             for (int j = 0; j < jmax; ++j) {
-                // skip array for the product = done flags, taken from the device status
-                gemv_strided(fp64, Z, N, w->V + int64_t(j) * N, int64_t(m + 1) * N, w->W, N, nullptr, 0, R,
-                             done_flags, done_stride, false, s);
-                hipLaunchKernelGGL(k_arn_dot1, vgrid, dim3(BT), 0, s, N, m, j, w->V, w->W, w->part, w->h1,
-                                   w->counters, w->st);
-                hipLaunchKernelGGL(k_arn_upd_dot2, vgrid, dim3(BT), 0, s, N, m, j, w->V, w->W, w->part, w->h1,
-                                   w->h2, w->H, w->counters, w->st);
-                hipLaunchKernelGGL(k_arn_upd_norm, vgrid, dim3(BT), 0, s, N, m, j, o.tol, w->V, w->W, w->part,
-                                   w->h2, w->H, w->cs, w->sn, w->g, w->counters, w->st);
-                hipLaunchKernelGGL(k_arn_normalize, egrid, dim3(BT), 0, s, N, m, j, w->V, w->W, w->st);
+                product(op, fp64, true, w->V + int64_t(j) * N, int64_t(m + 1) * N, w->W, N, nullptr, 0, R,
+                        done_flags, done_stride, false, s);
+                hipLaunchKernelGGL(k_cgs_pass1, pgrid, dim3(AB), 0, s, N, m, j, w->V, w->W, w->P1, w->PW, w->st);
+                hipLaunchKernelGGL(k_cgs_pass2, agrid, dim3(AB), 0, s, N, m, j, w->V, w->W, w->P1, w->PW, w->P2,
+                                   w->PN, w->H, w->st);
+                hipLaunchKernelGGL(k_cgs_pass3, agrid, dim3(AB), 0, s, N, m, j, w->V, w->W, w->P2, w->PN, w->H,
+                                   w->st);
+                hipLaunchKernelGGL(k_cgs_finish, agrid, dim3(AB), 0, s, N, m, j, o.tol, w->V, w->W, w->PN, w->PW,
+                                   w->H, w->cs, w->sn, w->g, w->st);
                 BIE_HIP(hipGetLastError());
             }
-            hipLaunchKernelGGL(k_lsq, dim3(unsigned((R + 63) / 64)), dim3(64), 0, s, int(R), m, w->H, w->g, w->y, w->st);
+            hipLaunchKernelGGL(k_lsq, dim3(unsigned(R)), dim3(64), size_t(m) * m * sizeof(double2), s, m, w->H, w->g,
+                               w->y, w->st);
             hipLaunchKernelGGL(k_xupd, egrid, dim3(BT), 0, s, N, m, w->V, w->y, X, w->st);
             BIE_HIP(hipGetLastError());
             pull_st();
@@ -865,7 +981,7 @@ int solve(const bie_op *opc, const void *Bv, void *Xv, int64_t R, const bie_solv
             std::vector<int> sk(R);
             for (int64_t r = 0; r < R; ++r) sk[r] = msk[r] ? 0 : 1;
             push_skip(sk);
-            gemv_strided(fp64, Z, N, w->Res, N, Zv, N, nullptr, 0, R, dskip, 1, true, s);
+            product(op, fp64, true, w->Res, N, Zv, N, nullptr, 0, R, dskip, 1, true, s);
             push_skip(msk);
             hipLaunchKernelGGL(k_cg_beta, vgrid, dim3(BT), 0, s, N, Zv, w->dpart, w->counters, w->st, 1,
                                (const int *)dskip);
@@ -885,11 +1001,11 @@ int solve(const bie_op *opc, const void *Bv, void *Xv, int64_t R, const bie_solv
             for (int64_t r = 0; r < R; ++r) any = any || active[r];
             if (!any) break;
             for (int it = 0; it < chunk; ++it) {
-                gemv_strided(fp64, Z, N, Pv, N, w->W, N, nullptr, 0, R, done_flags, done_stride, false, s);
+                product(op, fp64, true, Pv, N, w->W, N, nullptr, 0, R, done_flags, done_stride, false, s);
                 hipLaunchKernelGGL(k_cg_alpha, vgrid, dim3(BT), 0, s, N, w->W, w->dpart, w->counters, w->st);
                 hipLaunchKernelGGL(k_cg_step, vgrid, dim3(BT), 0, s, N, o.tol, Pv, w->W, X, w->Res, w->dpart,
                                    w->counters, w->st, w->iters);
-                gemv_strided(fp64, Z, N, w->Res, N, Zv, N, nullptr, 0, R, done_flags, done_stride, true, s);
+                product(op, fp64, true, w->Res, N, Zv, N, nullptr, 0, R, done_flags, done_stride, true, s);
                 hipLaunchKernelGGL(k_cg_beta, vgrid, dim3(BT), 0, s, N, Zv, w->dpart, w->counters, w->st, 0,
                                    (const int *)nullptr);
                 hipLaunchKernelGGL(k_cg_dir, egrid, dim3(BT), 0, s, N, Zv, Pv, w->st, (const int *)nullptr);

@@ -231,3 +231,16 @@ def test_cube_sphere_family(bie):
         op = bie.Operator(V, T, k)
         emax, efro = rel_err(op.matrix().cpu().numpy(), Zo)
         assert emax <= 1e-10 and efro <= 1e-10
+
+
+def test_fp32_matrix_solve(bie):
+    """FP32-stored matrix, FP64 vectors and accumulation: converged on the FP32
+    matrix; the FP64 residual is limited by the FP32 rounding of the entries."""
+    V, T, rwg, Zo = case(2, 2.0)
+    op = bie.Operator(V, T, 2.0, storage="c64")
+    d, e = planewave_set(np.array([[0.0, 0.0, 1.0]]), "theta")
+    B = op.rhs(d, e)
+    X, st = op.solve(B, bie.Solve(restart=30, tol=1e-6))
+    assert st[0]["converged"]
+    x = X.cpu().numpy()[0]; b = B.cpu().numpy()[0]
+    assert np.linalg.norm(b - Zo @ x) / np.linalg.norm(b) < 2e-6
