@@ -128,6 +128,12 @@ typedef struct {
     int64_t rscc_rows;   /* S, default 512 (min(S, N) used) */
     uint64_t rscc_seed;  /* default 1234 */
     int use_x0;          /* 1: X holds the initial guess on entry */
+    int precision;       /* 0: products with the stored matrix (FP64 if stored);
+                            1: mixed precision with iterative refinement: outer FP64
+                               residual and criterion (SCC), inner GMRES on the FP32
+                               matrix (needs storage BIE_C64 with keep_fp64) */
+    double inner_tol;    /* precision 1: inner tolerance relative to the outer residual
+                            (0: default 1e-3) */
 } bie_solve_opts;
 
 typedef struct {

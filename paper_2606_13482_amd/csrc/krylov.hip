@@ -753,13 +753,16 @@ void free_workspace(bie_op *op)
     op->ws = nullptr;
 }
 
-// Solve driver shared by GMRES and CGNR (FP64 vectors, FP64 or FP32 matrix).
-int solve(const bie_op *opc, const void *Bv, void *Xv, int64_t R, const bie_solve_opts &o, bie_solve_stat *stats,
-          hipStream_t s)
+// Solve driver shared by GMRES and CGNR (FP64 vectors).  mat64 selects the
+// matrix of the products.  inner: the solve is the inner step of iterative
+// refinement, its cycles end on the recursive estimate alone (no criterion on
+// the true residual of this system).
+static int solve_impl(const bie_op *opc, const void *Bv, void *Xv, int64_t R, const bie_solve_opts &o,
+                      bie_solve_stat *stats, hipStream_t s, bool mat64, bool inner)
 {
     bie_op *op = const_cast<bie_op *>(opc);
     const int64_t N = op->mesh.N;
-    const bool fp64 = op->Z64 != nullptr;
+    const bool fp64 = mat64;
     const int m = o.method == BIE_GMRES ? o.restart : 1;
     Workspace *w = get_ws(op, R, m);
     const double2 *B = static_cast<const double2 *>(Bv);
@@ -829,6 +832,14 @@ int solve(const bie_op *opc, const void *Bv, void *Xv, int64_t R, const bie_solv
         bool any = false;
         for (int64_t r = 0; r < R; ++r) { met[r] = 0; if (cand[r]) { need[r] = 1; any = true; } }
         if (!any) return;
+        if (inner) {   // estimate only
+            for (int64_t r = 0; r < R; ++r)
+                if (need[r]) {
+                    met[r] = 1;
+                    hs[r].relres_true = hs[r].relres_est;
+                }
+            return;
+        }
         if (o.crit == BIE_SCC) {
             full_residual(need);
             pull_st();
@@ -954,7 +965,10 @@ int solve(const bie_op *opc, const void *Bv, void *Xv, int64_t R, const bie_solv
             std::vector<int> nd(R, 0);
             bool anyr = false;
             for (int64_t r = 0; r < R; ++r)
-                if (active[r] && hs[r].mvps < o.max_mvp && !(o.crit == BIE_SCC && cand[r])) { nd[r] = 1; anyr = true; }
+                if (active[r] && hs[r].mvps < o.max_mvp && !(o.crit == BIE_SCC && !inner && cand[r])) {
+                    nd[r] = 1;
+                    anyr = true;
+                }
             if (anyr) full_residual(nd);
             pull_st();
             for (int64_t r = 0; r < R; ++r)
@@ -1054,6 +1068,147 @@ int solve(const bie_op *opc, const void *Bv, void *Xv, int64_t R, const bie_solv
         if (stats) stats[r] = hs[r];
     }
     return status;
+}
+
+
+namespace {
+
+__global__ void k_axpy_cols(int64_t n, const double2 *__restrict__ d, double2 *__restrict__ x)
+{
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+        const double2 a = d[i];
+        double2 b = x[i];
+        b.x += a.x;
+        b.y += a.y;
+        x[i] = b;
+    }
+}
+
+// ||v_r|| for R vectors into out[r] (deterministic: per-block partials, one wave adds them)
+__global__ __launch_bounds__(BT) void k_colnorm_part(int64_t N, const double2 *__restrict__ v, double *__restrict__ part)
+{
+    const int r = blockIdx.y;
+    double nn = 0.0;
+    for (int t = threadIdx.x; t < BE; t += BT) {
+        const int64_t e = int64_t(blockIdx.x) * BE + t;
+        if (e < N) nn += v[int64_t(r) * N + e].x * v[int64_t(r) * N + e].x + v[int64_t(r) * N + e].y * v[int64_t(r) * N + e].y;
+    }
+    __shared__ double red[BT / 64];
+    nn = wsum(nn);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nn;
+    __syncthreads();
+    if (threadIdx.x == 0) part[int64_t(r) * gridDim.x + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+__global__ void k_colnorm_fin(int nb, const double *__restrict__ part, double *__restrict__ out)
+{
+    const int r = blockIdx.x;
+    double a = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 64) a += part[int64_t(r) * nb + b];
+    a = wsum(a);
+    if (threadIdx.x == 0) out[r] = sqrt(a);
+}
+
+struct IRBuf {
+    double2 *res = nullptr, *d = nullptr;
+    double *part = nullptr, *nrm = nullptr;
+    ~IRBuf()
+    {
+        for (void *p : { (void *)res, (void *)d, (void *)part, (void *)nrm })
+            if (p) (void)hipFree(p);
+    }
+};
+
+}  // namespace
+
+// Mixed precision with iterative refinement: the outer residual b - T x uses
+// the FP64 matrix and decides convergence (standard criterion in FP64); each
+// correction solves T_32 d = r with GMRES on the FP32-rounded matrix (FP64
+// vectors and accumulation) to a relative tolerance inner_tol; x += d.
+static int solve_mixed(const bie_op *op, const void *Bv, void *Xv, int64_t R, const bie_solve_opts &o,
+                       bie_solve_stat *stats, hipStream_t s)
+{
+    if (!op->Z64 || !op->Z32) throw Error(BIE_EINVAL, "mixed precision needs both the FP64 and the FP32 matrix "
+                                                      "(storage BIE_C64 with keep_fp64)");
+    if (o.method != BIE_GMRES) throw Error(BIE_EINVAL, "mixed precision uses GMRES");
+    const int64_t N = op->mesh.N;
+    const double2 *B = static_cast<const double2 *>(Bv);
+    double2 *X = static_cast<double2 *>(Xv);
+    IRBuf b;
+    const unsigned nb = unsigned((N + BE - 1) / BE);
+    BIE_HIP(hipMalloc(&b.res, size_t(R) * N * sizeof(double2)));
+    BIE_HIP(hipMalloc(&b.d, size_t(R) * N * sizeof(double2)));
+    BIE_HIP(hipMalloc(&b.part, size_t(R) * nb * sizeof(double)));
+    BIE_HIP(hipMalloc(&b.nrm, size_t(R) * sizeof(double)));
+    auto norms = [&](const double2 *v, std::vector<double> &out) {
+        hipLaunchKernelGGL(k_colnorm_part, dim3(nb, unsigned(R)), dim3(BT), 0, s, N, v, b.part);
+        hipLaunchKernelGGL(k_colnorm_fin, dim3(unsigned(R)), dim3(64), 0, s, int(nb), b.part, b.nrm);
+        BIE_HIP(hipGetLastError());
+        out.resize(R);
+        BIE_HIP(hipMemcpyAsync(out.data(), b.nrm, R * sizeof(double), hipMemcpyDeviceToHost, s));
+        BIE_HIP(hipStreamSynchronize(s));
+    };
+    std::vector<double> bn, rn;
+    norms(B, bn);
+    if (!o.use_x0) hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, s, R * N, X);
+    std::vector<bie_solve_stat> hs(R, bie_solve_stat{ 0, 0, NAN, NAN, 0, 0 });
+    std::vector<int> active(R, 1);
+    const double itol = o.inner_tol > 0.0 ? o.inner_tol : 1e-3;
+    bie_solve_opts io = o;
+    io.use_x0 = 0;
+    io.crit = BIE_SCC;
+    std::vector<bie_solve_stat> ist(R);
+    for (int outer = 0; outer < 100; ++outer) {
+        product(op, true, true, X, N, b.res, N, B, N, R, nullptr, 1, false, s);   // r = b - T64 x
+        norms(b.res, rn);
+        bool any = false;
+        for (int64_t r = 0; r < R; ++r) {
+            if (!active[r]) continue;
+            hs[r].mvps += 1;
+            hs[r].checks += 1;
+            hs[r].relres_true = bn[r] > 0.0 ? rn[r] / bn[r] : 0.0;
+            if (bn[r] == 0.0 || hs[r].relres_true <= o.tol) {
+                active[r] = 0;
+                hs[r].converged = 1;
+            } else if (hs[r].mvps >= o.max_mvp) {
+                active[r] = 0;
+            } else {
+                any = true;
+            }
+        }
+        if (!any) break;
+        for (int64_t r = 0; r < R; ++r)
+            if (!active[r]) hipLaunchKernelGGL(k_zero, dim3(64), dim3(256), 0, s, N, b.res + r * N);
+        // correction on the FP32 matrix: tolerance relative to ||r|| (inner mode)
+        int64_t budget = o.max_mvp;
+        for (int64_t r = 0; r < R; ++r)
+            if (active[r]) budget = std::min<int64_t>(budget, o.max_mvp - hs[r].mvps);
+        io.tol = itol;
+        io.max_mvp = std::max<int64_t>(1, budget);
+        solve_impl(op, b.res, b.d, R, io, ist.data(), s, false, true);
+        for (int64_t r = 0; r < R; ++r)
+            if (active[r]) {
+                hs[r].iters += ist[r].iters;
+                hs[r].mvps += ist[r].mvps;
+                hs[r].relres_est = ist[r].relres_est * (bn[r] > 0.0 ? rn[r] / bn[r] : 0.0);
+            }
+        hipLaunchKernelGGL(k_axpy_cols, dim3(2048), dim3(256), 0, s, R * N, b.d, X);
+        BIE_HIP(hipGetLastError());
+    }
+    BIE_HIP(hipStreamSynchronize(s));
+    int status = BIE_OK;
+    for (int64_t r = 0; r < R; ++r) {
+        if (!hs[r].converged) status = BIE_NOT_CONVERGED;
+        if (stats) stats[r] = hs[r];
+    }
+    return status;
+}
+
+int solve(const bie_op *op, const void *B, void *X, int64_t R, const bie_solve_opts &o, bie_solve_stat *stats,
+          hipStream_t s)
+{
+    if (o.precision == 1) return solve_mixed(op, B, X, R, o, stats, s);
+    if (!op->Z64 && o.crit == BIE_RSCC) throw Error(BIE_EINVAL, "the random-sampling criterion needs the FP64 matrix");
+    return solve_impl(op, B, X, R, o, stats, s, op->Z64 != nullptr, false);
 }
 
 }  // namespace bie

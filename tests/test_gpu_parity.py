@@ -244,3 +244,29 @@ def test_fp32_matrix_solve(bie):
     assert st[0]["converged"]
     x = X.cpu().numpy()[0]; b = B.cpu().numpy()[0]
     assert np.linalg.norm(b - Zo @ x) / np.linalg.norm(b) < 2e-6
+
+
+@pytest.mark.parametrize("level,k,inner", [(2, 2.0, 1e-3), (3, 6.0, 1e-3), (3, 6.0, 1e-6)])
+def test_mixed_precision_refinement(bie, level, k, inner):
+    """FP32 inner GMRES + FP64 iterative refinement reaches the FP64 criterion;
+    the residual is checked with the oracle matrix and the solution against LU."""
+    V, T, rwg, Zo = case(level, k)
+    op = bie.Operator(V, T, k, storage="c64", keep_fp64=True)
+    inc = np.array([[0.0, 0.0, 1.0], [0.4, -0.2, 0.9]])
+    d, e = planewave_set(inc, "theta")
+    B = op.rhs(d, e)
+    X, st = op.solve(B, bie.Solve(restart=30, tol=1e-6, precision="mixed", inner_tol=inner))
+    Bn = B.cpu().numpy(); Xn = X.cpu().numpy()
+    for r in range(2):
+        assert st[r]["converged"], st[r]
+        res = np.linalg.norm(Bn[r] - Zo @ Xn[r]) / np.linalg.norm(Bn[r])
+        assert res <= 1e-6 * (1 + 1e-6), res
+        assert abs(res - st[r]["relres_true"]) <= 1e-9
+        x_lu = krylov.lu_solve(Zo, Bn[r])
+        xp, stp = krylov.gmres(Zo, Bn[r], m=30, tol=1e-6)
+        fwd = np.linalg.norm(Xn[r] - x_lu) / np.linalg.norm(x_lu)
+        fwd_p = np.linalg.norm(xp - x_lu) / np.linalg.norm(x_lu)
+        assert fwd < 10 * fwd_p + 1e-9
+    # the FP32 matrix is the rounding of the FP64 one
+    Z32 = op.matrix(torch.complex64).cpu().numpy()
+    assert np.array_equal(Z32, Zo.astype(np.complex64)) or np.max(np.abs(Z32 - Zo)) / np.max(np.abs(Zo)) < 1e-7
