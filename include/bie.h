@@ -54,8 +54,10 @@ enum {
 /* Storage of the impedance matrix. */
 typedef enum {
     BIE_C128 = 0,   /* complex FP64 fill and storage */
-    BIE_C64 = 1     /* complex FP32 storage; regular pairs integrated in FP32,
+    BIE_C64 = 1,    /* complex FP32 storage; regular pairs integrated in FP32,
                        touching / near pairs always in FP64 */
+    BIE_SPLIT_BF16 = 2  /* FP64 matrix plus a split-BF16 copy (hi + lo pairs) for the
+                           block product on the matrix cores (FP32 accumulation) */
 } bie_dtype;
 
 typedef struct bie_op bie_op;   /* opaque: owns the device matrix and workspaces */
@@ -110,6 +112,8 @@ int bie_rhs_planewave(const bie_op *op, const double *dirs, const double *pols, 
 /* Matrix-vector / matrix-block product (the solver's MVP):
  *   Y = T X   (conj = 0)   or   Y = T^H X = conj(T conj(X))   (conj = 1, T = T^T)
  *   X, Y  device R x N, complex128 (vec = BIE_C128) or complex64 (vec = BIE_C64);
+ *         vec = BIE_SPLIT_BF16: complex128 vectors through the split-BF16 block
+ *         product on the matrix cores (storage BIE_SPLIT_BF16, conj = 0);
  *         X and Y must not overlap.  Complex128 vectors use the FP64 matrix when
  *         stored (else the FP32 matrix with FP64 accumulation); complex64 vectors
  *         use the FP32 matrix with FP32 accumulation. */
@@ -130,8 +134,9 @@ typedef struct {
     int use_x0;          /* 1: X holds the initial guess on entry */
     int precision;       /* 0: products with the stored matrix (FP64 if stored);
                             1: mixed precision with iterative refinement: outer FP64
-                               residual and criterion (SCC), inner GMRES on the FP32
-                               matrix (needs storage BIE_C64 with keep_fp64) */
+                               residual and criterion (SCC), inner GMRES on the
+                               split-BF16 matrix (storage BIE_SPLIT_BF16) or on the
+                               FP32 matrix (storage BIE_C64 with keep_fp64) */
     double inner_tol;    /* precision 1: inner tolerance relative to the outer residual
                             (0: default 1e-3) */
 } bie_solve_opts;
@@ -177,12 +182,13 @@ int bie_farfield(const bie_op *op, const void *X, int64_t R, const double *obs, 
 int bie_rscc_rows(int64_t N, int64_t S, uint64_t seed, int64_t *out);
 
 /* Measurement support (not part of the method): with on != 0 every launch of
- * the dense product kernel (from bie_apply and inside bie_solve) is bracketed
+ * the dense product kernels (from bie_apply and inside bie_solve) is bracketed
  * by HIP events on the stream it runs on.  bie_prof_read waits for the
- * recorded events and returns the number of launches and their summed
- * duration in ms since the previous read, then clears the record. */
+ * recorded events of `kernel` (0: packed symmetric product, 1: split-BF16
+ * block product) and returns the number of launches and their summed
+ * duration in ms since the previous read, then clears that record. */
 int bie_prof_enable(int on);
-int bie_prof_read(int64_t *launches, double *total_ms);
+int bie_prof_read(int kernel, int64_t *launches, double *total_ms);
 
 const char *bie_last_error(void);
 

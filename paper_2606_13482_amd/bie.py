@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libbie.so")
 
 BIE_OK, BIE_NOT_CONVERGED = 0, 1
 BIE_EINVAL, BIE_EMESH, BIE_ENOMEM, BIE_EDEVICE, BIE_ENUMERIC = -1, -2, -3, -4, -5
-BIE_C128, BIE_C64 = 0, 1
+BIE_C128, BIE_C64, BIE_SPLIT_BF16 = 0, 1, 2
 BIE_GMRES, BIE_CGNR = 0, 1
 BIE_SCC, BIE_RSCC = 0, 1
 
@@ -68,7 +68,7 @@ SYMBOLS = [
     ("bie_farfield", ctypes.c_int, [_P, _P, _I64, _P, _I64, _P, _P]),
     ("bie_rscc_rows", ctypes.c_int, [_I64, _I64, ctypes.c_uint64, _P]),
     ("bie_prof_enable", ctypes.c_int, [ctypes.c_int]),
-    ("bie_prof_read", ctypes.c_int, [ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_double)]),
+    ("bie_prof_read", ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_double)]),
     ("bie_last_error", ctypes.c_char_p, []),
 ]
 
@@ -122,10 +122,11 @@ def prof_enable(on: bool = True):
     _check(_lib.bie_prof_enable(int(on)))
 
 
-def prof_read():
-    """(launches, total_ms) of the dense product kernel since the last read."""
+def prof_read(kernel: int = 0):
+    """(launches, total_ms) of a dense product kernel since the last read
+    (0: packed symmetric product, 1: split-BF16 block product)."""
     n = ctypes.c_int64(); ms = ctypes.c_double()
-    _check(_lib.bie_prof_read(ctypes.byref(n), ctypes.byref(ms)))
+    _check(_lib.bie_prof_read(int(kernel), ctypes.byref(n), ctypes.byref(ms)))
     return n.value, ms.value
 
 
@@ -155,7 +156,8 @@ class Operator:
                  keep_fp64: bool = False, stream=None):
         V, pv = _host(V, np.float64)
         T, pt = _host(T, np.int32)
-        opts = FillOpts({"c128": BIE_C128, "c64": BIE_C64}[storage], near_factor, int(keep_fp64))
+        opts = FillOpts({"c128": BIE_C128, "c64": BIE_C64, "split_bf16": BIE_SPLIT_BF16}[storage], near_factor,
+                        int(keep_fp64))
         h = ctypes.c_void_p()
         _check(_lib.bie_op_create(pv, V.shape[0], pt, T.shape[0], float(k), ctypes.byref(opts),
                                   _stream(stream), ctypes.byref(h)))
@@ -200,10 +202,13 @@ class Operator:
         _check(_lib.bie_rhs_planewave(self._h, pd, pp, R, _dev(B, torch.complex128), _stream(stream)))
         return B
 
-    def apply(self, X: torch.Tensor, conj: bool = False, out: torch.Tensor | None = None, stream=None):
+    def apply(self, X: torch.Tensor, conj: bool = False, out: torch.Tensor | None = None, stream=None,
+              block: bool = False):
+        """Y = T X (or T^H X); block=True: complex128 vectors through the split-BF16
+        block product on the matrix cores (storage "split_bf16")."""
         X2 = X.reshape(-1, self.N)
         Y = torch.empty_like(X2) if out is None else out
-        code = BIE_C128 if X2.dtype == torch.complex128 else BIE_C64
+        code = BIE_SPLIT_BF16 if block else (BIE_C128 if X2.dtype == torch.complex128 else BIE_C64)
         _check(_lib.bie_apply(self._h, _dev(X2, X2.dtype), _dev(Y, X2.dtype, X2.shape), X2.shape[0], code,
                               int(conj), _stream(stream)))
         return Y.reshape(X.shape)

@@ -38,7 +38,7 @@ void destroy_op(bie_op *op)
     if (!op) return;
     bie::free_workspace(op);
     bie::packed_free(op);
-    void *ptrs[] = { op->Z64, op->Z32, op->tri.cent, op->tri.loc, op->tri.vfree, op->tri.verts,
+    void *ptrs[] = { op->Z64, op->Z32, op->Abf, op->Bbf, op->tri.cent, op->tri.loc, op->tri.vfree, op->tri.verts,
                      op->tri.area, op->tri.sgn, op->tri.slot_m, op->tri.edges };
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -60,7 +60,8 @@ int bie_op_create(const double *verts, int64_t nv, const int32_t *tris, int64_t 
         if (!(k > 0.0) || !std::isfinite(k)) return fail(BIE_EINVAL, "wavenumber must be positive and finite");
         bie_fill_opts o{ BIE_C128, 2.0, 0 };
         if (opts) o = *opts;
-        if (o.storage != BIE_C128 && o.storage != BIE_C64) return fail(BIE_EINVAL, "unknown storage");
+        if (o.storage != BIE_C128 && o.storage != BIE_C64 && o.storage != BIE_SPLIT_BF16)
+            return fail(BIE_EINVAL, "unknown storage");
         if (!(o.near_factor >= 0.0)) return fail(BIE_EINVAL, "near_factor must be >= 0");
         bie::Mesh mesh = bie::build_mesh(verts, nv, tris, nt, o.near_factor);   // host only: EMESH first
         bie_op *op = new bie_op();
@@ -75,12 +76,15 @@ int bie_op_create(const double *verts, int64_t nv, const int32_t *tris, int64_t 
             bie::packed_setup(op);
             (void)N;
             const size_t tile_elems = size_t(op->pk.ntiles) * bie::TB * bie::TB;
-            const bool want64 = o.storage == BIE_C128 || o.keep_fp64;
+            const bool want64 = o.storage == BIE_C128 || o.storage == BIE_SPLIT_BF16 || o.keep_fp64;
             const bool want32 = o.storage == BIE_C64;
             if (want64) BIE_HIP(hipMalloc(&op->Z64, tile_elems * 16));
             if (want32) BIE_HIP(hipMalloc(&op->Z32, tile_elems * 8));
             if (o.storage == BIE_C128) {
                 bie::fill_matrix(op, true, true, false, s);
+            } else if (o.storage == BIE_SPLIT_BF16) {
+                bie::fill_matrix(op, true, true, false, s);
+                bie::split_matrix(op, s);
             } else if (o.keep_fp64) {
                 // FP64 fill; the FP32 matrix is its rounding (the best FP32 representation)
                 bie::fill_matrix(op, true, true, false, s);
@@ -164,10 +168,16 @@ int bie_apply(const bie_op *op, const void *X, void *Y, int64_t R, int vec, int 
         hipStream_t s = as_stream(stream);
         if (vec == BIE_C128) {
             // FP64 matrix if stored, else the FP32 matrix with FP64 accumulation
-            bie::product(op, op->Z64 != nullptr, true, X, N, Y, N, nullptr, 0, R, nullptr, 1, conj != 0, s);
+            bie::product(op, op->Z64 ? bie::MAT64 : bie::MAT32, true, X, N, Y, N, nullptr, 0, R, nullptr, 1, conj != 0,
+                         s);
         } else if (vec == BIE_C64) {
             if (!op->Z32) return fail(BIE_EINVAL, "complex64 vectors need BIE_C64 storage");
-            bie::product(op, false, false, X, N, Y, N, nullptr, 0, R, nullptr, 1, conj != 0, s);
+            bie::product(op, bie::MAT32, false, X, N, Y, N, nullptr, 0, R, nullptr, 1, conj != 0, s);
+        } else if (vec == BIE_SPLIT_BF16) {
+            // complex128 vectors through the split-BF16 block product
+            if (!op->Abf) return fail(BIE_EINVAL, "no split-BF16 matrix stored");
+            if (conj) return fail(BIE_EINVAL, "the block product has no conjugate form");
+            bie::product(op, bie::MATBF16, true, X, N, Y, N, nullptr, 0, R, nullptr, 1, false, s);
         } else {
             return fail(BIE_EINVAL, "unknown vector dtype");
         }
@@ -221,11 +231,11 @@ int bie_prof_enable(int on)
     });
 }
 
-int bie_prof_read(int64_t *launches, double *total_ms)
+int bie_prof_read(int kernel, int64_t *launches, double *total_ms)
 {
     return guarded([&]() -> int {
         if (!launches || !total_ms) return fail(BIE_EINVAL, "NULL argument");
-        bie::prof_read(launches, total_ms);
+        bie::prof_read(kernel, launches, total_ms);
         return BIE_OK;
     });
 }

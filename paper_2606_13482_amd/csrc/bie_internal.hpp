@@ -103,6 +103,10 @@ struct bie_op {
     void *Z64 = nullptr;   // packed symmetric tiles, complex128 (storage C128 or keep_fp64)
     void *Z32 = nullptr;   // packed symmetric tiles, complex64 (storage C64)
     bie::Packed pk;
+    void *Abf = nullptr;          // split-BF16 matrix for the block product: hi plane, lo plane, [Mp][Kp]
+    int64_t gemm_Mp = 0, gemm_Kp = 0;
+    void *Bbf = nullptr;          // split-BF16 staging of the right-hand block, [NCp][Kp] x 2
+    int64_t bstage_cols = 0;
     bie::Workspace *ws = nullptr;
 };
 
@@ -122,7 +126,10 @@ void packed_free(bie_op *op);
 // Y = T X, T^H X (conj) or B - T X (B != NULL) for R vectors with the FP64
 // (mat64) or FP32 matrix; vectors complex128 (vec64, FP64 accumulation) or
 // complex64 (FP32 matrix only).
-void product(const bie_op *op, bool mat64, bool vec64, const void *X, int64_t ldx, void *Y, int64_t ldy,
+// mat: MAT64 (packed FP64), MAT32 (packed FP32), MATBF16 (split-BF16 block product,
+// complex128 vectors only, no conj).
+enum { MAT64 = 0, MAT32 = 1, MATBF16 = 2 };
+void product(const bie_op *op, int mat, bool vec64, const void *X, int64_t ldx, void *Y, int64_t ldy,
              const void *B, int64_t ldb, int64_t R, const int *skip, int64_t sks, bool conj, hipStream_t s);
 // packed -> full row-major complex128
 void unpack_c128(const bie_op *op, bool from64, void *dst, hipStream_t s);
@@ -133,7 +140,13 @@ void convert_c128_to_c64(const void *src, void *dst, int64_t n, hipStream_t s);
 void convert_c64_to_c128(const void *src, void *dst, int64_t n, hipStream_t s);
 bool has_nonfinite(const void *x, int64_t n_doubles, hipStream_t s);
 void prof_enable(bool enable);
-void prof_read(int64_t *launches, double *total_ms);
+void prof_read(int kernel, int64_t *launches, double *total_ms);
+void prof_gemm_begin(hipStream_t s);
+void prof_gemm_end(hipStream_t s);
+// gemm.hip
+void split_matrix(bie_op *op, hipStream_t s);
+void gemm_product(const bie_op *op, const void *X, int64_t ldx, void *Y, int64_t ldy, const void *Bsub, int64_t ldb,
+                  int64_t R, hipStream_t s);
 
 // krylov.hip
 int solve(const bie_op *op, const void *B, void *X, int64_t R, const bie_solve_opts &o,

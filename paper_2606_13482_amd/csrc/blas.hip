@@ -29,45 +29,55 @@
 
 namespace bie {
 
-// Optional timing of the product kernels: events recorded on the launch stream.
+// Optional timing of the dense product kernels: events recorded on the launch
+// stream around every launch (record 0: packed product, 1: block GEMM).
 namespace prof {
 bool on = false;
-std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
-size_t used = 0;
+struct Rec {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    size_t used = 0;
+};
+Rec rec[2];
 
-void begin(hipStream_t s)
+void begin(int k, hipStream_t s)
 {
     if (!on) return;
-    if (used == ev.size()) {
+    Rec &r = rec[k];
+    if (r.used == r.ev.size()) {
         hipEvent_t a, b;
         BIE_HIP(hipEventCreate(&a));
         BIE_HIP(hipEventCreate(&b));
-        ev.emplace_back(a, b);
+        r.ev.emplace_back(a, b);
     }
-    BIE_HIP(hipEventRecord(ev[used].first, s));
+    BIE_HIP(hipEventRecord(r.ev[r.used].first, s));
 }
-void end(hipStream_t s)
+void end(int k, hipStream_t s)
 {
     if (!on) return;
-    BIE_HIP(hipEventRecord(ev[used].second, s));
-    ++used;
+    Rec &r = rec[k];
+    BIE_HIP(hipEventRecord(r.ev[r.used].second, s));
+    ++r.used;
 }
 }  // namespace prof
 
 void prof_enable(bool enable) { prof::on = enable; }
+void prof_gemm_begin(hipStream_t s) { prof::begin(1, s); }
+void prof_gemm_end(hipStream_t s) { prof::end(1, s); }
 
-void prof_read(int64_t *launches, double *total_ms)
+void prof_read(int kernel, int64_t *launches, double *total_ms)
 {
+    if (kernel < 0 || kernel > 1) throw Error(BIE_EINVAL, "unknown kernel record");
+    prof::Rec &r = prof::rec[kernel];
     double t = 0.0;
-    for (size_t i = 0; i < prof::used; ++i) {
-        BIE_HIP(hipEventSynchronize(prof::ev[i].second));
+    for (size_t i = 0; i < r.used; ++i) {
+        BIE_HIP(hipEventSynchronize(r.ev[i].second));
         float ms = 0.f;
-        BIE_HIP(hipEventElapsedTime(&ms, prof::ev[i].first, prof::ev[i].second));
+        BIE_HIP(hipEventElapsedTime(&ms, r.ev[i].first, r.ev[i].second));
         t += ms;
     }
-    *launches = int64_t(prof::used);
+    *launches = int64_t(r.used);
     *total_ms = t;
-    prof::used = 0;
+    r.used = 0;
 }
 
 namespace {
@@ -360,7 +370,7 @@ void launch_product(const bie_op *op, const void *Z, const void *X, int64_t ldx,
 {
     const Packed &pk = op->pk;
     const dim3 grid(unsigned(pk.nunits), unsigned(R));
-    prof::begin(s);
+    prof::begin(0, s);
     if (sym_prefetch())
         hipLaunchKernelGGL((k_sym_tiles<M, T, CONJ, true>), grid, dim3(256), 0, s, (const M *)Z, pk.N, pk.nT,
                            pk.units, pk.unit_ptr, pk.seg, pk.nslots, (const T *)X, ldx, (T *)pk.part, skip, sks);
@@ -370,7 +380,7 @@ void launch_product(const bie_op *op, const void *Z, const void *X, int64_t ldx,
     hipLaunchKernelGGL((k_sym_reduce<T, SUB>), dim3(unsigned(pk.nT), unsigned(R)), dim3(512), 0, s, pk.N, pk.seg,
                        pk.nslots, (const T *)pk.part, (T *)Y, ldy, (const T *)B, ldb, skip, sks);
     BIE_HIP(hipGetLastError());
-    prof::end(s);
+    prof::end(0, s);
 }
 
 }  // namespace
@@ -426,10 +436,17 @@ void dispatch(const bie_op *op, const void *Z, const void *X, int64_t ldx, void 
     else launch_product<M, T, false, false>(op, Z, X, ldx, Y, ldy, nullptr, 0, R, skip, sks, s);
 }
 
-void product(const bie_op *opc, bool mat64, bool vec64, const void *X, int64_t ldx, void *Y, int64_t ldy,
+void product(const bie_op *opc, int mat, bool vec64, const void *X, int64_t ldx, void *Y, int64_t ldy,
              const void *B, int64_t ldb, int64_t R, const int *skip, int64_t sks, bool conj, hipStream_t s)
 {
     bie_op *op = const_cast<bie_op *>(opc);
+    if (mat == MATBF16) {
+        if (!op->Abf) throw Error(BIE_EINVAL, "no split-BF16 matrix stored");
+        if (!vec64 || conj) throw Error(BIE_EINVAL, "the block product takes complex128 vectors, no conjugate");
+        gemm_product(op, X, ldx, Y, ldy, B, ldb, R, s);
+        return;
+    }
+    const bool mat64 = mat == MAT64;
     Packed &pk = op->pk;
     const void *Z = mat64 ? op->Z64 : op->Z32;
     if (!Z) throw Error(BIE_EINVAL, "matrix not stored in the requested precision");

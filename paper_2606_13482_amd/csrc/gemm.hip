@@ -1,0 +1,246 @@
+// Block product Y = T X for many right-hand sides on the matrix cores.
+//
+// The complex product is one real GEMM with re/im interleaved along K:
+//   A[m][2n] = Re T_mn, A[m][2n+1] = Im T_mn                      (M = N, K = 2N)
+//   B[2n][r] = Re x_rn, B[2n+1][r] = -Im x_rn    (column r      -> Re y_r)
+//   B[2n][R+r] = Im x_rn, B[2n+1][R+r] = Re x_rn (column R + r  -> Im y_r)
+// Both operands are split into BF16 pairs (hi = rne(v), lo = rne(v - hi)) and
+// C = Ah Bh + Ah Bl + Al Bh is accumulated in FP32 with
+// v_mfma_f32_32x32x16_bf16 (about 16 significant bits per product entry; the
+// dropped lo*lo term is below the FP32 accumulation error).
+//
+// Tiling: a block of 8 waves computes a 256 x 256 tile of C; wave (wm, wn)
+// owns rows 128 wm .. +128 and columns 64 wn .. +64 as 4 x 2 MFMA tiles of
+// 32 x 32 (12 fragment reads from LDS feed 24 MFMAs per 16-deep step).  K advances in stages of 32; both planes of the A and B stage sit
+// in LDS, double-buffered (128 KiB of the 160 KiB LDS), rows padded to 40
+// BF16 to spread banks.  While a stage is computed (24 MFMAs per wave over 4
+// independent accumulators at a time), the next stage goes from registers to
+// the other buffer and the one after it is loaded from memory into registers:
+// one barrier per stage, loads issued two stages ahead.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "bie_internal.hpp"
+
+namespace bie {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int GBM = 256, GBN = 256, GBK = 32, PK = GBK + 8;
+constexpr int TI = 4, TJ = 2;   // 32x32 MFMA tiles per wave (128 rows x 64 columns)
+
+__device__ inline void split_bf16(float v, __bf16 &hi, __bf16 &lo)
+{
+    hi = (__bf16)v;
+    lo = (__bf16)(v - (float)hi);
+}
+
+// A planes [Mp][Kp] from the packed symmetric FP64 tiles (zero padding).
+__global__ __launch_bounds__(256) void k_split_matrix(const double2 *__restrict__ Zp, int64_t N, int64_t nT,
+                                                      int64_t Kp, __bf16 *__restrict__ Ah, __bf16 *__restrict__ Al)
+{
+    const int64_t m = blockIdx.y;
+    for (int64_t n = int64_t(blockIdx.x) * 256 + threadIdx.x; 2 * n < Kp; n += int64_t(gridDim.x) * 256) {
+        double2 z = make_double2(0.0, 0.0);
+        if (m < N && n < N) {
+            const int64_t I = m / TB, J = n / TB;
+            z = I <= J ? Zp[tile_of(I, J, nT) * TB * TB + (m % TB) * TB + (n % TB)]
+                       : Zp[tile_of(J, I, nT) * TB * TB + (n % TB) * TB + (m % TB)];
+        }
+        __bf16 h0, l0, h1, l1;
+        split_bf16(float(z.x), h0, l0);
+        split_bf16(float(z.y), h1, l1);
+        Ah[m * Kp + 2 * n] = h0;
+        Ah[m * Kp + 2 * n + 1] = h1;
+        Al[m * Kp + 2 * n] = l0;
+        Al[m * Kp + 2 * n + 1] = l1;
+    }
+}
+
+// B planes [NCp][Kp] from R complex vectors (vector r at X + r*ldx).
+__global__ __launch_bounds__(256) void k_split_vectors(const double2 *__restrict__ X, int64_t ldx, int64_t N,
+                                                       int64_t R, int64_t Kp, __bf16 *__restrict__ Bh,
+                                                       __bf16 *__restrict__ Bl)
+{
+    const int64_t c = blockIdx.y;
+    for (int64_t n = int64_t(blockIdx.x) * 256 + threadIdx.x; 2 * n < Kp; n += int64_t(gridDim.x) * 256) {
+        float a = 0.f, b = 0.f;
+        if (n < N && c < 2 * R) {
+            const double2 x = X[(c < R ? c : c - R) * ldx + n];
+            if (c < R) { a = float(x.x); b = float(-x.y); }
+            else { a = float(x.y); b = float(x.x); }
+        }
+        __bf16 h0, l0, h1, l1;
+        split_bf16(a, h0, l0);
+        split_bf16(b, h1, l1);
+        Bh[c * Kp + 2 * n] = h0;
+        Bh[c * Kp + 2 * n + 1] = h1;
+        Bl[c * Kp + 2 * n] = l0;
+        Bl[c * Kp + 2 * n + 1] = l1;
+    }
+}
+
+// C = Ah Bh + Ah Bl + Al Bh; epilogue: Y[r][m] = (C[m][r], C[m][R + r]), or B - that.
+__global__ __launch_bounds__(512) void k_gemm_split(const __bf16 *__restrict__ Ah, const __bf16 *__restrict__ Al,
+                                                    const __bf16 *__restrict__ Bh, const __bf16 *__restrict__ Bl,
+                                                    int64_t Kp, int64_t N, int64_t R, double *__restrict__ Y,
+                                                    int64_t ldy, const double *__restrict__ Bsub, int64_t ldb)
+{
+    __shared__ __attribute__((aligned(16))) __bf16 sA[2][2][GBM][PK];   // [buffer][plane][row][k]
+    __shared__ __attribute__((aligned(16))) __bf16 sB[2][2][GBN][PK];   // [buffer][plane][col][k]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 2, wn = wave & 3;   // wave tile: rows 128 wm .. +128, columns 64 wn .. +64
+    const int64_t m0 = int64_t(blockIdx.x) * GBM, c0 = int64_t(blockIdx.y) * GBN;
+
+    // global -> register staging (16-byte chunks): per plane, A 256 x 32 and
+    // B 256 x 32 = 1024 chunks each (2 per thread)
+    constexpr int CPR = GBK / 8;   // chunks per row
+    u32x4 ra[2][2], rb[2][2];
+    auto gload = [&](int64_t k0) {
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int c = tid + 512 * q;
+                ra[p][q] = *reinterpret_cast<const u32x4 *>((p ? Al : Ah) + (m0 + c / CPR) * Kp + k0 + (c % CPR) * 8);
+                rb[p][q] = *reinterpret_cast<const u32x4 *>((p ? Bl : Bh) + (c0 + c / CPR) * Kp + k0 + (c % CPR) * 8);
+            }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int c = tid + 512 * q;
+                *reinterpret_cast<u32x4 *>(&sA[buf][p][c / CPR][(c % CPR) * 8]) = ra[p][q];
+                *reinterpret_cast<u32x4 *>(&sB[buf][p][c / CPR][(c % CPR) * 8]) = rb[p][q];
+            }
+    };
+
+    f32x16 acc[TI][TJ];
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc[i][j][q] = 0.f;
+
+    const int fr = lane & 31, fk = (lane >> 5) * 8;
+    // pipeline: stage s is computed from LDS buffer s%2 while stage s+1 is
+    // stored into the other buffer and stage s+2 is in flight to registers;
+    // one barrier per stage
+    const int64_t nst = Kp / GBK;
+    gload(0);
+    lstore(0);
+    if (nst > 1) gload(GBK);
+    __syncthreads();
+    for (int64_t st = 0; st < nst; ++st) {
+        const int buf = int(st & 1);
+#pragma unroll
+        for (int kk = 0; kk < GBK; kk += 16) {
+            bf16x8 a[TI][2], b[TJ][2];   // [tile][plane]
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+#pragma unroll
+                for (int t = 0; t < TI; ++t)
+                    a[t][p] = *reinterpret_cast<const bf16x8 *>(&sA[buf][p][wm * 128 + t * 32 + fr][kk + fk]);
+#pragma unroll
+                for (int t = 0; t < TJ; ++t)
+                    b[t][p] = *reinterpret_cast<const bf16x8 *>(&sB[buf][p][wn * 64 + t * 32 + fr][kk + fk]);
+            }
+            // three products, each over the 8 independent accumulators
+#pragma unroll
+            for (int i = 0; i < TI; ++i)
+#pragma unroll
+                for (int j = 0; j < TJ; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][0], acc[i][j], 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < TI; ++i)
+#pragma unroll
+                for (int j = 0; j < TJ; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][1], acc[i][j], 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < TI; ++i)
+#pragma unroll
+                for (int j = 0; j < TJ; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][1], b[j][0], acc[i][j], 0, 0, 0);
+        }
+        if (st + 1 < nst) {
+            lstore(buf ^ 1);                          // stage st+1 (already in registers)
+            if (st + 2 < nst) gload((st + 2) * GBK);  // stage st+2 in flight during the next compute
+        }
+        __syncthreads();
+    }
+    // epilogue: accumulator q of lane l holds row 8(q/4) + 4(l/32) + q%4, column l%32 of its 32x32 tile
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) {
+            const int64_t c = c0 + wn * 64 + j * 32 + (lane & 31);
+            if (c >= 2 * R) continue;
+            const int64_t r = c < R ? c : c - R;
+            const int part = c < R ? 0 : 1;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int64_t m = m0 + wm * 128 + i * 32 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+                if (m >= N) continue;
+                double v = double(acc[i][j][q]);
+                if (Bsub) v = Bsub[2 * (r * ldb + m) + part] - v;
+                Y[2 * (r * ldy + m) + part] = v;
+            }
+        }
+}
+
+}  // namespace
+
+int64_t gemm_pad_rows(int64_t N) { return (N + GBM - 1) / GBM * GBM; }
+int64_t gemm_pad_k(int64_t N) { return (2 * N + GBK - 1) / GBK * GBK; }
+int64_t gemm_pad_cols(int64_t R) { return (2 * R + GBN - 1) / GBN * GBN; }
+
+// Split-BF16 copy of the FP64 matrix (A planes, hi then lo).
+void split_matrix(bie_op *op, hipStream_t s)
+{
+    const int64_t N = op->mesh.N, Mp = gemm_pad_rows(N), Kp = gemm_pad_k(N);
+    const size_t plane = size_t(Mp) * size_t(Kp);
+    BIE_HIP(hipMalloc(&op->Abf, 2 * plane * sizeof(__bf16)));
+    op->gemm_Mp = Mp;
+    op->gemm_Kp = Kp;
+    __bf16 *Ah = static_cast<__bf16 *>(op->Abf), *Al = Ah + plane;
+    const dim3 grid(unsigned(std::min<int64_t>((Kp / 2 + 255) / 256, 64)), unsigned(Mp));
+    hipLaunchKernelGGL(k_split_matrix, grid, dim3(256), 0, s, (const double2 *)op->Z64, N, op->pk.nT, Kp, Ah, Al);
+    BIE_HIP(hipGetLastError());
+    BIE_HIP(hipStreamSynchronize(s));
+}
+
+// Y = T X (or Bsub - T X) for R vectors with the split-BF16 matrix; complex128 vectors.
+void gemm_product(const bie_op *opc, const void *X, int64_t ldx, void *Y, int64_t ldy, const void *Bsub, int64_t ldb,
+                  int64_t R, hipStream_t s)
+{
+    bie_op *op = const_cast<bie_op *>(opc);
+    const int64_t N = op->mesh.N, Kp = op->gemm_Kp, Mp = op->gemm_Mp, NCp = gemm_pad_cols(R);
+    const size_t plane = size_t(NCp) * size_t(Kp);
+    if (op->bstage_cols < NCp) {
+        BIE_HIP(hipStreamSynchronize(s));
+        if (op->Bbf) (void)hipFree(op->Bbf);
+        op->Bbf = nullptr;
+        op->bstage_cols = 0;
+        BIE_HIP(hipMalloc(&op->Bbf, 2 * plane * sizeof(__bf16)));
+        op->bstage_cols = NCp;
+    }
+    __bf16 *Bh = static_cast<__bf16 *>(op->Bbf), *Bl = Bh + plane;
+    const __bf16 *Ah = static_cast<const __bf16 *>(op->Abf), *Al = Ah + size_t(Mp) * size_t(Kp);
+    hipLaunchKernelGGL(k_split_vectors, dim3(unsigned(std::min<int64_t>((Kp / 2 + 255) / 256, 64)), unsigned(NCp)),
+                       dim3(256), 0, s, (const double2 *)X, ldx, N, R, Kp, Bh, Bl);
+    prof_gemm_begin(s);
+    hipLaunchKernelGGL(k_gemm_split, dim3(unsigned(Mp / GBM), unsigned(NCp / GBN)), dim3(512), 0, s, Ah, Al, Bh, Bl,
+                       Kp, N, R, (double *)Y, ldy, (const double *)Bsub, ldb);
+    prof_gemm_end(s);
+    BIE_HIP(hipGetLastError());
+}
+
+}  // namespace bie

@@ -758,11 +758,11 @@ void free_workspace(bie_op *op)
 // refinement, its cycles end on the recursive estimate alone (no criterion on
 // the true residual of this system).
 static int solve_impl(const bie_op *opc, const void *Bv, void *Xv, int64_t R, const bie_solve_opts &o,
-                      bie_solve_stat *stats, hipStream_t s, bool mat64, bool inner)
+                      bie_solve_stat *stats, hipStream_t s, int mat, bool inner)
 {
     bie_op *op = const_cast<bie_op *>(opc);
     const int64_t N = op->mesh.N;
-    const bool fp64 = mat64;
+    const int fp64 = mat;   // matrix of the products (MAT64 / MAT32 / MATBF16)
     const int m = o.method == BIE_GMRES ? o.restart : 1;
     Workspace *w = get_ws(op, R, m);
     const double2 *B = static_cast<const double2 *>(Bv);
@@ -1127,8 +1127,9 @@ struct IRBuf {
 static int solve_mixed(const bie_op *op, const void *Bv, void *Xv, int64_t R, const bie_solve_opts &o,
                        bie_solve_stat *stats, hipStream_t s)
 {
-    if (!op->Z64 || !op->Z32) throw Error(BIE_EINVAL, "mixed precision needs both the FP64 and the FP32 matrix "
-                                                      "(storage BIE_C64 with keep_fp64)");
+    if (!op->Z64 || !(op->Z32 || op->Abf))
+        throw Error(BIE_EINVAL, "mixed precision needs the FP64 matrix and a low-precision copy "
+                                "(storage BIE_C64 with keep_fp64, or BIE_SPLIT_BF16)");
     if (o.method != BIE_GMRES) throw Error(BIE_EINVAL, "mixed precision uses GMRES");
     const int64_t N = op->mesh.N;
     const double2 *B = static_cast<const double2 *>(Bv);
@@ -1158,7 +1159,7 @@ static int solve_mixed(const bie_op *op, const void *Bv, void *Xv, int64_t R, co
     io.crit = BIE_SCC;
     std::vector<bie_solve_stat> ist(R);
     for (int outer = 0; outer < 100; ++outer) {
-        product(op, true, true, X, N, b.res, N, B, N, R, nullptr, 1, false, s);   // r = b - T64 x
+        product(op, MAT64, true, X, N, b.res, N, B, N, R, nullptr, 1, false, s);   // r = b - T64 x
         norms(b.res, rn);
         bool any = false;
         for (int64_t r = 0; r < R; ++r) {
@@ -1184,7 +1185,7 @@ static int solve_mixed(const bie_op *op, const void *Bv, void *Xv, int64_t R, co
             if (active[r]) budget = std::min<int64_t>(budget, o.max_mvp - hs[r].mvps);
         io.tol = itol;
         io.max_mvp = std::max<int64_t>(1, budget);
-        solve_impl(op, b.res, b.d, R, io, ist.data(), s, false, true);
+        solve_impl(op, b.res, b.d, R, io, ist.data(), s, op->Abf ? MATBF16 : MAT32, true);
         for (int64_t r = 0; r < R; ++r)
             if (active[r]) {
                 hs[r].iters += ist[r].iters;
@@ -1208,7 +1209,7 @@ int solve(const bie_op *op, const void *B, void *X, int64_t R, const bie_solve_o
 {
     if (o.precision == 1) return solve_mixed(op, B, X, R, o, stats, s);
     if (!op->Z64 && o.crit == BIE_RSCC) throw Error(BIE_EINVAL, "the random-sampling criterion needs the FP64 matrix");
-    return solve_impl(op, B, X, R, o, stats, s, op->Z64 != nullptr, false);
+    return solve_impl(op, B, X, R, o, stats, s, op->Z64 ? MAT64 : MAT32, false);
 }
 
 }  // namespace bie
