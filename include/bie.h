@@ -181,6 +181,67 @@ int bie_farfield(const bie_op *op, const void *X, int64_t R, const double *obs, 
  * rows a given check used. */
 int bie_rscc_rows(int64_t N, int64_t S, uint64_t seed, int64_t *out);
 
+/* ---------------------------------------------------------------------------
+ * Learned warm start.  Not part of the paper: a production form beside the
+ * plain solve.  A POD basis U (K modes) of solutions the method computed and a
+ * small network map the incidence to K coefficients: x0 = U c.  The network
+ * takes (d_x, d_y, d_z, s) with d the propagation direction and s = +1 / -1
+ * for theta-hat / phi-hat polarisation, has two tanh layers of `hidden` units
+ * and a linear output layer of 2K values (Re, Im of c divided by one global
+ * RMS scale), FP32, trained on the device with mean squared error and Adam
+ * (0.9, 0.999, 1e-8), learning rate cosine-decayed lr_max -> lr_min.
+ * Glorot-uniform initial weights (SplitMix64(seed), in layer order, row-major
+ * (out, in)) and per-epoch Fisher-Yates shuffles (SplitMix64(seed + 1 + epoch)).
+ * Parameter layout (float): W1 (hidden x 4), b1, W2 (hidden x hidden), b2,
+ * W3 (2K x hidden), b3.  Plain GMRES from zero stays the fallback and the
+ * judge of the prediction (see bie_ws_predict). */
+typedef struct bie_ws bie_ws;
+
+typedef struct {
+    int pod_rank;        /* K, default 256 */
+    int hidden;          /* default 512 */
+    int epochs;          /* default 3000 */
+    int batch;           /* default 256 */
+    double lr_max;       /* default 1e-3 */
+    double lr_min;       /* default 1e-5 */
+    uint64_t seed;       /* default 555 */
+    int oversample;      /* POD range finder: L = K + oversample columns, default 32 */
+    int power_iters;     /* POD range finder power iterations, default 2 */
+} bie_ws_opts;
+
+/* Train from S solutions.  feats host S x 4; X device S x N complex128 (the
+ * solutions, e.g. from bie_solve).  POD: randomised range finder with power
+ * iterations and CholeskyQR2 on the device; the small (K + oversample)-sized
+ * Cholesky and Hermitian eigenproblems on the host.  The returned object
+ * refers to `op` (which must outlive it). */
+int bie_ws_train(const bie_op *op, const double *feats, const void *X, int64_t S, const bie_ws_opts *opts,
+                 void *stream, bie_ws **out);
+
+/* Predict x0 = U c for R inputs (feats host R x 4) into X0 (device R x N
+ * complex128).  If B (device R x N) is given, a prediction is kept only where
+ * ||b - T x0|| < ||b|| and set to 0 otherwise; used[r] (host, may be NULL)
+ * tells which were kept. */
+int bie_ws_predict(bie_ws *ws, const double *feats, int64_t R, const void *B, void *X0, int32_t *used, void *stream);
+
+/* Sizes and training summary; sigma (host, K entries, may be NULL): POD singular values. */
+int bie_ws_info(const bie_ws *ws, int64_t *pod_rank, int64_t *hidden, int64_t *nparams, double *scale,
+                double *final_loss, double *sigma);
+/* Copy of the POD basis: U device K x N complex128 (mode k contiguous). */
+int bie_ws_basis(const bie_ws *ws, void *U, void *stream);
+/* Network parameters (host float array of nparams): read (set = 0) or write (set = 1). */
+int bie_ws_params(bie_ws *ws, float *host, int set);
+/* Mean squared error of the network on R inputs (host R x 4) against targets
+ * (host R x 2K) and its gradient (host float nparams, may be NULL), computed by
+ * the device forward and backward kernels. */
+int bie_ws_loss_grad(bie_ws *ws, const double *feats, const float *targets, int64_t R, double *loss, float *grad);
+/* Network outputs (host R x 2K) for R inputs. */
+int bie_ws_forward(bie_ws *ws, const double *feats, int64_t R, float *out);
+/* Untrained network with Glorot-uniform weights (no POD basis). */
+int bie_ws_create(const bie_op *op, int pod_rank, int hidden, uint64_t seed, bie_ws **out);
+int bie_ws_save(const bie_ws *ws, const char *path);
+int bie_ws_load(const bie_op *op, const char *path, bie_ws **out);
+void bie_ws_destroy(bie_ws *ws);
+
 /* Measurement support (not part of the method): with on != 0 every launch of
  * the dense product kernels (from bie_apply and inside bie_solve) is bracketed
  * by HIP events on the stream it runs on.  bie_prof_read waits for the

@@ -44,6 +44,12 @@ class SolveOpts(ctypes.Structure):
                 ("inner_tol", ctypes.c_double)]
 
 
+class WsOpts(ctypes.Structure):
+    _fields_ = [("pod_rank", ctypes.c_int), ("hidden", ctypes.c_int), ("epochs", ctypes.c_int),
+                ("batch", ctypes.c_int), ("lr_max", ctypes.c_double), ("lr_min", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("oversample", ctypes.c_int), ("power_iters", ctypes.c_int)]
+
+
 class SolveStat(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int64), ("mvps", ctypes.c_int64), ("relres_est", ctypes.c_double),
                 ("relres_true", ctypes.c_double), ("converged", ctypes.c_int), ("checks", ctypes.c_int)]
@@ -67,6 +73,17 @@ SYMBOLS = [
     ("bie_solve", ctypes.c_int, [_P, _P, _P, _I64, _P, _P, _P]),
     ("bie_farfield", ctypes.c_int, [_P, _P, _I64, _P, _I64, _P, _P]),
     ("bie_rscc_rows", ctypes.c_int, [_I64, _I64, ctypes.c_uint64, _P]),
+    ("bie_ws_train", ctypes.c_int, [_P, _P, _P, _I64, _P, _P, ctypes.POINTER(_P)]),
+    ("bie_ws_predict", ctypes.c_int, [_P, _P, _I64, _P, _P, _P, _P]),
+    ("bie_ws_info", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+    ("bie_ws_basis", ctypes.c_int, [_P, _P, _P]),
+    ("bie_ws_params", ctypes.c_int, [_P, _P, ctypes.c_int]),
+    ("bie_ws_loss_grad", ctypes.c_int, [_P, _P, _P, _I64, _P, _P]),
+    ("bie_ws_forward", ctypes.c_int, [_P, _P, _I64, _P]),
+    ("bie_ws_create", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(_P)]),
+    ("bie_ws_save", ctypes.c_int, [_P, ctypes.c_char_p]),
+    ("bie_ws_load", ctypes.c_int, [_P, ctypes.c_char_p, ctypes.POINTER(_P)]),
+    ("bie_ws_destroy", None, [_P]),
     ("bie_prof_enable", ctypes.c_int, [ctypes.c_int]),
     ("bie_prof_read", ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_double)]),
     ("bie_last_error", ctypes.c_char_p, []),
@@ -247,3 +264,107 @@ class Operator:
         F = self.farfield(X, obs).cpu().numpy()
         tang = F - np.sum(obs[None] * F, axis=2, keepdims=True) * obs[None]
         return self.k ** 2 / (4 * np.pi) * np.sum(np.abs(tang) ** 2, axis=2)
+
+
+def features(dirs, pol_flags):
+    """Network inputs (d_x, d_y, d_z, s): propagation direction and +1 (theta-hat) / -1 (phi-hat)."""
+    d = np.atleast_2d(np.asarray(dirs, np.float64))
+    f = np.asarray(pol_flags, np.float64).reshape(-1, 1)
+    return np.ascontiguousarray(np.concatenate([d, f], axis=1))
+
+
+class WarmStart:
+    """Learned warm start: POD basis + MLP (bie_ws_* in include/bie.h)."""
+
+    def __init__(self, op: Operator, handle):
+        self.op = op
+        self._h = handle
+        K = ctypes.c_int64(); H = ctypes.c_int64(); n = ctypes.c_int64()
+        sc = ctypes.c_double(); loss = ctypes.c_double()
+        _check(_lib.bie_ws_info(self._h, ctypes.byref(K), ctypes.byref(H), ctypes.byref(n), ctypes.byref(sc),
+                                ctypes.byref(loss), None))
+        self.K, self.H, self.nparams = K.value, H.value, n.value
+        self.scale, self.final_loss = sc.value, loss.value
+
+    @classmethod
+    def train(cls, op: Operator, feats, X: torch.Tensor, pod_rank=256, hidden=512, epochs=3000, batch=256,
+              lr_max=1e-3, lr_min=1e-5, seed=555, oversample=32, power_iters=2, stream=None):
+        f, pf = _host(feats, np.float64)
+        X2 = X.reshape(-1, op.N)
+        o = WsOpts(pod_rank, hidden, epochs, batch, lr_max, lr_min, seed, oversample, power_iters)
+        h = ctypes.c_void_p()
+        _check(_lib.bie_ws_train(op._h, pf, _dev(X2, torch.complex128), X2.shape[0], ctypes.byref(o),
+                                 _stream(stream), ctypes.byref(h)))
+        return cls(op, h)
+
+    @classmethod
+    def create(cls, op: Operator, pod_rank=256, hidden=512, seed=555):
+        h = ctypes.c_void_p()
+        _check(_lib.bie_ws_create(op._h, pod_rank, hidden, ctypes.c_uint64(seed), ctypes.byref(h)))
+        return cls(op, h)
+
+    @classmethod
+    def load(cls, op: Operator, path: str):
+        h = ctypes.c_void_p()
+        _check(_lib.bie_ws_load(op._h, path.encode(), ctypes.byref(h)))
+        return cls(op, h)
+
+    def save(self, path: str):
+        _check(_lib.bie_ws_save(self._h, path.encode()))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.bie_ws_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sigma(self) -> np.ndarray:
+        out = np.zeros(self.K)
+        _check(_lib.bie_ws_info(self._h, None, None, None, None, None, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def basis(self, stream=None) -> torch.Tensor:
+        U = torch.empty((self.K, self.op.N), dtype=torch.complex128, device="cuda")
+        _check(_lib.bie_ws_basis(self._h, _dev(U, torch.complex128), _stream(stream)))
+        return U
+
+    def params(self) -> np.ndarray:
+        p = np.zeros(self.nparams, np.float32)
+        _check(_lib.bie_ws_params(self._h, p.ctypes.data_as(ctypes.c_void_p), 0))
+        return p
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, np.float32)
+        _check(_lib.bie_ws_params(self._h, p.ctypes.data_as(ctypes.c_void_p), 1))
+
+    def loss_grad(self, feats, targets):
+        f, pf = _host(feats, np.float64)
+        t, pt = _host(targets, np.float32)
+        g = np.zeros(self.nparams, np.float32)
+        loss = ctypes.c_double()
+        _check(_lib.bie_ws_loss_grad(self._h, pf, pt, f.shape[0], ctypes.byref(loss),
+                                     g.ctypes.data_as(ctypes.c_void_p)))
+        return loss.value, g
+
+    def forward(self, feats) -> np.ndarray:
+        f, pf = _host(feats, np.float64)
+        out = np.zeros((f.shape[0], 2 * self.K), np.float32)
+        _check(_lib.bie_ws_forward(self._h, pf, f.shape[0], out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def predict(self, feats, B: torch.Tensor | None = None, stream=None):
+        """x0 (R x N complex128) and which predictions were kept (fallback to 0 when
+        ||b - T x0|| >= ||b||; all kept when B is None)."""
+        f, pf = _host(feats, np.float64)
+        R = f.shape[0]
+        X0 = torch.empty((R, self.op.N), dtype=torch.complex128, device="cuda")
+        used = np.zeros(R, np.int32)
+        pb = None if B is None else _dev(B.reshape(R, self.op.N), torch.complex128)
+        _check(_lib.bie_ws_predict(self._h, pf, R, pb, _dev(X0, torch.complex128),
+                                   used.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
+        return X0, used.astype(bool)

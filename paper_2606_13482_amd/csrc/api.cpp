@@ -223,6 +223,112 @@ int bie_farfield(const bie_op *op, const void *X, int64_t R, const double *obs, 
     });
 }
 
+int bie_ws_train(const bie_op *op, const double *feats, const void *X, int64_t S, const bie_ws_opts *opts,
+                 void *stream, bie_ws **out)
+{
+    return guarded([&]() -> int {
+        if (!op || !feats || !X || !out) return fail(BIE_EINVAL, "NULL argument");
+        *out = nullptr;
+        bie_ws_opts o{ 256, 512, 3000, 256, 1e-3, 1e-5, 555, 32, 2 };
+        if (opts) o = *opts;
+        if (S < 2 || o.pod_rank < 1 || o.pod_rank > S || o.hidden < 1 || o.hidden > 4096 || o.epochs < 0 ||
+            o.batch < 1 || o.oversample < 0 || o.power_iters < 0 || !(o.lr_max > 0.0) || !(o.lr_min >= 0.0))
+            return fail(BIE_EINVAL, "bad warm-start options");
+        for (int64_t i = 0; i < 4 * S; ++i)
+            if (!std::isfinite(feats[i])) return fail(BIE_ENUMERIC, "non-finite feature");
+        *out = bie::ws_train(op, feats, X, S, o, as_stream(stream));
+        return BIE_OK;
+    });
+}
+
+int bie_ws_predict(bie_ws *ws, const double *feats, int64_t R, const void *B, void *X0, int32_t *used, void *stream)
+{
+    return guarded([&]() -> int {
+        if (!ws || !feats || !X0) return fail(BIE_EINVAL, "NULL argument");
+        if (R < 1 || R > 65535) return fail(BIE_EINVAL, "R out of range");
+        bie::ws_predict(ws, feats, R, B, X0, used, as_stream(stream));
+        return BIE_OK;
+    });
+}
+
+int bie_ws_info(const bie_ws *ws, int64_t *K, int64_t *H, int64_t *np, double *scale, double *loss, double *sigma)
+{
+    if (!ws) return fail(BIE_EINVAL, "NULL warm start");
+    bie::ws_info(ws, K, H, np, scale, loss, sigma);
+    return BIE_OK;
+}
+
+int bie_ws_basis(const bie_ws *ws, void *U, void *stream)
+{
+    return guarded([&]() -> int {
+        if (!ws || !U) return fail(BIE_EINVAL, "NULL argument");
+        bie::ws_basis(ws, U, as_stream(stream));
+        return BIE_OK;
+    });
+}
+
+int bie_ws_params(bie_ws *ws, float *host, int set)
+{
+    return guarded([&]() -> int {
+        if (!ws || !host) return fail(BIE_EINVAL, "NULL argument");
+        bie::ws_params(ws, host, set != 0);
+        return BIE_OK;
+    });
+}
+
+int bie_ws_loss_grad(bie_ws *ws, const double *feats, const float *targets, int64_t R, double *loss, float *grad)
+{
+    return guarded([&]() -> int {
+        if (!ws || !feats || !targets || !loss) return fail(BIE_EINVAL, "NULL argument");
+        if (R < 1 || R > 65535) return fail(BIE_EINVAL, "R out of range");
+        *loss = bie::ws_loss_grad(ws, feats, targets, R, grad, nullptr);
+        return BIE_OK;
+    });
+}
+
+int bie_ws_forward(bie_ws *ws, const double *feats, int64_t R, float *out)
+{
+    return guarded([&]() -> int {
+        if (!ws || !feats || !out) return fail(BIE_EINVAL, "NULL argument");
+        if (R < 1 || R > 65535) return fail(BIE_EINVAL, "R out of range");
+        bie::ws_forward(ws, feats, R, out, nullptr);
+        return BIE_OK;
+    });
+}
+
+int bie_ws_create(const bie_op *op, int pod_rank, int hidden, uint64_t seed, bie_ws **out)
+{
+    return guarded([&]() -> int {
+        if (!op || !out) return fail(BIE_EINVAL, "NULL argument");
+        if (pod_rank < 1 || hidden < 1 || hidden > 4096) return fail(BIE_EINVAL, "bad sizes");
+        *out = bie::ws_create_untrained(op, pod_rank, hidden, seed);
+        return BIE_OK;
+    });
+}
+
+int bie_ws_save(const bie_ws *ws, const char *path)
+{
+    return guarded([&]() -> int {
+        if (!ws || !path) return fail(BIE_EINVAL, "NULL argument");
+        bie::ws_save(ws, path);
+        return BIE_OK;
+    });
+}
+
+int bie_ws_load(const bie_op *op, const char *path, bie_ws **out)
+{
+    return guarded([&]() -> int {
+        if (!op || !path || !out) return fail(BIE_EINVAL, "NULL argument");
+        *out = bie::ws_load(op, path);
+        return BIE_OK;
+    });
+}
+
+void bie_ws_destroy(bie_ws *ws)
+{
+    if (ws) bie::ws_destroy(ws);
+}
+
 int bie_prof_enable(int on)
 {
     return guarded([&]() -> int {

@@ -94,6 +94,8 @@ __host__ __device__ inline void tile_decode(int64_t b, int64_t nT, int64_t &I, i
 
 }  // namespace bie
 
+struct bie_ws;   // learned warm start (warmstart.hip)
+
 struct bie_op {
     int device = 0;
     double k = 0.0;
@@ -147,6 +149,21 @@ void prof_gemm_end(hipStream_t s);
 void split_matrix(bie_op *op, hipStream_t s);
 void gemm_product(const bie_op *op, const void *X, int64_t ldx, void *Y, int64_t ldy, const void *Bsub, int64_t ldb,
                   int64_t R, hipStream_t s);
+
+// warmstart.hip
+bie_ws *ws_train(const bie_op *op, const double *feats, const void *X, int64_t S, const bie_ws_opts &o,
+                 hipStream_t s);
+void ws_predict(bie_ws *w, const double *feats, int64_t R, const void *B, void *X0, int *used, hipStream_t s);
+double ws_loss_grad(bie_ws *w, const double *feats, const float *targets, int64_t R, float *grad_host,
+                    hipStream_t s);
+void ws_forward(bie_ws *w, const double *feats, int64_t R, float *out_host, hipStream_t s);
+bie_ws *ws_create_untrained(const bie_op *op, int K, int H, uint64_t seed);
+void ws_params(bie_ws *w, float *host, bool set);
+void ws_basis(const bie_ws *w, void *U, hipStream_t s);
+void ws_save(const bie_ws *w, const char *path);
+bie_ws *ws_load(const bie_op *op, const char *path);
+void ws_destroy(bie_ws *w);
+void ws_info(const bie_ws *w, int64_t *K, int64_t *H, int64_t *nparams, double *scale, double *loss, double *sigma);
 
 // krylov.hip
 int solve(const bie_op *op, const void *B, void *X, int64_t R, const bie_solve_opts &o,
