@@ -207,21 +207,27 @@ typedef struct {
     uint64_t seed;       /* default 555 */
     int oversample;      /* POD range finder: L = K + oversample columns, default 32 */
     int power_iters;     /* POD range finder power iterations, default 2 */
+    int pol_model;       /* 0: inputs (d, s), 2K outputs; 1: linear in the polarisation:
+                            input d, outputs f_x, f_y, f_z (3 x 2K) and the coefficients
+                            for polarisation e are sum_c e_c f_c (smooth on the whole
+                            sphere, unlike the theta/phi frame); default 0 */
 } bie_ws_opts;
 
-/* Train from S solutions.  feats host S x 4; X device S x N complex128 (the
- * solutions, e.g. from bie_solve).  POD: randomised range finder with power
+/* Train from S solutions.  feats host S x 4; pols host S x 3 real unit
+ * polarisations (needed for pol_model 1, else may be NULL); X device S x N
+ * complex128 (the solutions, e.g. from bie_solve).  POD: randomised range finder with power
  * iterations and CholeskyQR2 on the device; the small (K + oversample)-sized
  * Cholesky and Hermitian eigenproblems on the host.  The returned object
  * refers to `op` (which must outlive it). */
-int bie_ws_train(const bie_op *op, const double *feats, const void *X, int64_t S, const bie_ws_opts *opts,
-                 void *stream, bie_ws **out);
+int bie_ws_train(const bie_op *op, const double *feats, const double *pols, const void *X, int64_t S,
+                 const bie_ws_opts *opts, void *stream, bie_ws **out);
 
-/* Predict x0 = U c for R inputs (feats host R x 4) into X0 (device R x N
- * complex128).  If B (device R x N) is given, a prediction is kept only where
+/* Predict x0 = U c for R inputs (feats host R x 4; pols host R x 3 for
+ * pol_model 1, else may be NULL) into X0 (device R x N complex128).  If B (device R x N) is given, a prediction is kept only where
  * ||b - T x0|| < ||b|| and set to 0 otherwise; used[r] (host, may be NULL)
  * tells which were kept. */
-int bie_ws_predict(bie_ws *ws, const double *feats, int64_t R, const void *B, void *X0, int32_t *used, void *stream);
+int bie_ws_predict(bie_ws *ws, const double *feats, const double *pols, int64_t R, const void *B, void *X0,
+                   int32_t *used, void *stream);
 
 /* Sizes and training summary; sigma (host, K entries, may be NULL): POD singular values. */
 int bie_ws_info(const bie_ws *ws, int64_t *pod_rank, int64_t *hidden, int64_t *nparams, double *scale,

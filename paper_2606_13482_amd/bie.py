@@ -47,7 +47,8 @@ class SolveOpts(ctypes.Structure):
 class WsOpts(ctypes.Structure):
     _fields_ = [("pod_rank", ctypes.c_int), ("hidden", ctypes.c_int), ("epochs", ctypes.c_int),
                 ("batch", ctypes.c_int), ("lr_max", ctypes.c_double), ("lr_min", ctypes.c_double),
-                ("seed", ctypes.c_uint64), ("oversample", ctypes.c_int), ("power_iters", ctypes.c_int)]
+                ("seed", ctypes.c_uint64), ("oversample", ctypes.c_int), ("power_iters", ctypes.c_int),
+                ("pol_model", ctypes.c_int)]
 
 
 class SolveStat(ctypes.Structure):
@@ -73,8 +74,8 @@ SYMBOLS = [
     ("bie_solve", ctypes.c_int, [_P, _P, _P, _I64, _P, _P, _P]),
     ("bie_farfield", ctypes.c_int, [_P, _P, _I64, _P, _I64, _P, _P]),
     ("bie_rscc_rows", ctypes.c_int, [_I64, _I64, ctypes.c_uint64, _P]),
-    ("bie_ws_train", ctypes.c_int, [_P, _P, _P, _I64, _P, _P, ctypes.POINTER(_P)]),
-    ("bie_ws_predict", ctypes.c_int, [_P, _P, _I64, _P, _P, _P, _P]),
+    ("bie_ws_train", ctypes.c_int, [_P, _P, _P, _P, _I64, _P, _P, ctypes.POINTER(_P)]),
+    ("bie_ws_predict", ctypes.c_int, [_P, _P, _P, _I64, _P, _P, _P, _P]),
     ("bie_ws_info", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     ("bie_ws_basis", ctypes.c_int, [_P, _P, _P]),
     ("bie_ws_params", ctypes.c_int, [_P, _P, ctypes.c_int]),
@@ -288,14 +289,20 @@ class WarmStart:
 
     @classmethod
     def train(cls, op: Operator, feats, X: torch.Tensor, pod_rank=256, hidden=512, epochs=3000, batch=256,
-              lr_max=1e-3, lr_min=1e-5, seed=555, oversample=32, power_iters=2, stream=None):
+              lr_max=1e-3, lr_min=1e-5, seed=555, oversample=32, power_iters=2, pols=None, pol_model=0,
+              stream=None):
         f, pf = _host(feats, np.float64)
+        pp = None
+        if pols is not None:
+            e, pp = _host(pols, np.float64)
         X2 = X.reshape(-1, op.N)
-        o = WsOpts(pod_rank, hidden, epochs, batch, lr_max, lr_min, seed, oversample, power_iters)
+        o = WsOpts(pod_rank, hidden, epochs, batch, lr_max, lr_min, seed, oversample, power_iters, pol_model)
         h = ctypes.c_void_p()
-        _check(_lib.bie_ws_train(op._h, pf, _dev(X2, torch.complex128), X2.shape[0], ctypes.byref(o),
+        _check(_lib.bie_ws_train(op._h, pf, pp, _dev(X2, torch.complex128), X2.shape[0], ctypes.byref(o),
                                  _stream(stream), ctypes.byref(h)))
-        return cls(op, h)
+        ws = cls(op, h)
+        ws.pol_model = pol_model
+        return ws
 
     @classmethod
     def create(cls, op: Operator, pod_rank=256, hidden=512, seed=555):
@@ -357,14 +364,17 @@ class WarmStart:
         _check(_lib.bie_ws_forward(self._h, pf, f.shape[0], out.ctypes.data_as(ctypes.c_void_p)))
         return out
 
-    def predict(self, feats, B: torch.Tensor | None = None, stream=None):
+    def predict(self, feats, B: torch.Tensor | None = None, pols=None, stream=None):
         """x0 (R x N complex128) and which predictions were kept (fallback to 0 when
         ||b - T x0|| >= ||b||; all kept when B is None)."""
         f, pf = _host(feats, np.float64)
+        pp = None
+        if pols is not None:
+            e, pp = _host(pols, np.float64)
         R = f.shape[0]
         X0 = torch.empty((R, self.op.N), dtype=torch.complex128, device="cuda")
         used = np.zeros(R, np.int32)
         pb = None if B is None else _dev(B.reshape(R, self.op.N), torch.complex128)
-        _check(_lib.bie_ws_predict(self._h, pf, R, pb, _dev(X0, torch.complex128),
+        _check(_lib.bie_ws_predict(self._h, pf, pp, R, pb, _dev(X0, torch.complex128),
                                    used.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
         return X0, used.astype(bool)

@@ -223,30 +223,32 @@ int bie_farfield(const bie_op *op, const void *X, int64_t R, const double *obs, 
     });
 }
 
-int bie_ws_train(const bie_op *op, const double *feats, const void *X, int64_t S, const bie_ws_opts *opts,
-                 void *stream, bie_ws **out)
+int bie_ws_train(const bie_op *op, const double *feats, const double *pols, const void *X, int64_t S,
+                 const bie_ws_opts *opts, void *stream, bie_ws **out)
 {
     return guarded([&]() -> int {
         if (!op || !feats || !X || !out) return fail(BIE_EINVAL, "NULL argument");
         *out = nullptr;
-        bie_ws_opts o{ 256, 512, 3000, 256, 1e-3, 1e-5, 555, 32, 2 };
+        bie_ws_opts o{ 256, 512, 3000, 256, 1e-3, 1e-5, 555, 32, 2, 0 };
         if (opts) o = *opts;
         if (S < 2 || o.pod_rank < 1 || o.pod_rank > S || o.hidden < 1 || o.hidden > 4096 || o.epochs < 0 ||
-            o.batch < 1 || o.oversample < 0 || o.power_iters < 0 || !(o.lr_max > 0.0) || !(o.lr_min >= 0.0))
+            o.batch < 1 || o.oversample < 0 || o.power_iters < 0 || !(o.lr_max > 0.0) || !(o.lr_min >= 0.0) ||
+            (o.pol_model != 0 && o.pol_model != 1) || (o.pol_model == 1 && !pols))
             return fail(BIE_EINVAL, "bad warm-start options");
         for (int64_t i = 0; i < 4 * S; ++i)
             if (!std::isfinite(feats[i])) return fail(BIE_ENUMERIC, "non-finite feature");
-        *out = bie::ws_train(op, feats, X, S, o, as_stream(stream));
+        *out = bie::ws_train(op, feats, pols, X, S, o, as_stream(stream));
         return BIE_OK;
     });
 }
 
-int bie_ws_predict(bie_ws *ws, const double *feats, int64_t R, const void *B, void *X0, int32_t *used, void *stream)
+int bie_ws_predict(bie_ws *ws, const double *feats, const double *pols, int64_t R, const void *B, void *X0,
+                   int32_t *used, void *stream)
 {
     return guarded([&]() -> int {
         if (!ws || !feats || !X0) return fail(BIE_EINVAL, "NULL argument");
         if (R < 1 || R > 65535) return fail(BIE_EINVAL, "R out of range");
-        bie::ws_predict(ws, feats, R, B, X0, used, as_stream(stream));
+        bie::ws_predict(ws, feats, pols, R, B, X0, used, as_stream(stream));
         return BIE_OK;
     });
 }

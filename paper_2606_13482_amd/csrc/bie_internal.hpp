@@ -151,9 +151,10 @@ void gemm_product(const bie_op *op, const void *X, int64_t ldx, void *Y, int64_t
                   int64_t R, hipStream_t s);
 
 // warmstart.hip
-bie_ws *ws_train(const bie_op *op, const double *feats, const void *X, int64_t S, const bie_ws_opts &o,
-                 hipStream_t s);
-void ws_predict(bie_ws *w, const double *feats, int64_t R, const void *B, void *X0, int *used, hipStream_t s);
+bie_ws *ws_train(const bie_op *op, const double *feats, const double *pols, const void *X, int64_t S,
+                 const bie_ws_opts &o, hipStream_t s);
+void ws_predict(bie_ws *w, const double *feats, const double *pols, int64_t R, const void *B, void *X0, int *used,
+                hipStream_t s);
 double ws_loss_grad(bie_ws *w, const double *feats, const float *targets, int64_t R, float *grad_host,
                     hipStream_t s);
 void ws_forward(bie_ws *w, const double *feats, int64_t R, float *out_host, hipStream_t s);

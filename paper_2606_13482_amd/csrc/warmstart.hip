@@ -226,6 +226,27 @@ __global__ void k_adam(int n, float *__restrict__ w, const float *__restrict__ g
     w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
+// Linear-in-polarisation model: the network gives three coefficient sets
+// f_c (c = x, y, z; each 2K reals: Re then Im) and the coefficients for
+// polarisation e are y = sum_c e_c f_c.
+__global__ void k_pol_combine(int B, int K2, const float *__restrict__ net, const float *__restrict__ E,
+                              float *__restrict__ y)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= B * K2) return;
+    const int b = i / K2, k = i % K2;
+    const float *f = net + int64_t(b) * 3 * K2;
+    y[i] = E[b * 3] * f[k] + E[b * 3 + 1] * f[K2 + k] + E[b * 3 + 2] * f[2 * K2 + k];
+}
+__global__ void k_pol_combine_back(int B, int K2, const float *__restrict__ dy, const float *__restrict__ E,
+                                   float *__restrict__ dnet)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= B * 3 * K2) return;
+    const int b = i / (3 * K2), r = i % (3 * K2), c = r / K2, k = r % K2;
+    dnet[i] = E[b * 3 + c] * dy[b * K2 + k];
+}
+
 // coefficients from the network output: c[r][k] = scale (out[r][k] + j out[r][K + k])
 __global__ void k_out_to_coef(int R, int K, const float *__restrict__ out, double scale, double2 *__restrict__ c)
 {
@@ -246,14 +267,16 @@ __global__ void k_targets(int S, int K, const double2 *__restrict__ C, double in
     t[int64_t(s) * 2 * K + K + k] = float(c.y * inv);
 }
 
-// batch gather: in[r] = F[perm[b0 + r]], tgt[r] = T[perm[b0 + r]]
+// batch gather: in[r] = F[perm[b0 + r]], tgt[r] = T[perm[b0 + r]], pol[r] = E[perm[b0 + r]]
 __global__ void k_gather(int B, int O, const int64_t *__restrict__ perm, int64_t b0, const float *__restrict__ F,
-                         const float *__restrict__ Tg, float *__restrict__ in, float *__restrict__ tgt)
+                         const float *__restrict__ Tg, const float *__restrict__ E, float *__restrict__ in,
+                         float *__restrict__ tgt, float *__restrict__ pol)
 {
     const int r = blockIdx.x;
     const int64_t i = perm[b0 + r];
     for (int c = threadIdx.x; c < O; c += blockDim.x) tgt[int64_t(r) * O + c] = Tg[i * O + c];
     if (threadIdx.x < 4) in[r * 4 + threadIdx.x] = F[i * 4 + threadIdx.x];
+    if (E && threadIdx.x < 3) pol[r * 3 + threadIdx.x] = E[i * 3 + threadIdx.x];
 }
 
 // squared norms of R complex vectors (one block per vector, fixed reduction tree)
@@ -400,7 +423,8 @@ void jacobi_eig(std::vector<cd> A, int L, std::vector<double> &w, std::vector<cd
 // ----------------------------------------------------------------------------- warm-start object
 struct bie_ws {
     const bie_op *op = nullptr;
-    int K = 0, H = 0, O = 0;
+    int K = 0, H = 0, O = 0;            // O: network outputs (2K, or 6K for the linear-in-polarisation model)
+    int pmodel = 0;                     // 0: inputs (d, s); 1: inputs d, outputs linear in the polarisation
     double scale = 1.0, final_loss = NAN;
     std::vector<double> sigma;          // POD singular values (descending)
     double2 *U = nullptr;               // K x N
@@ -411,13 +435,13 @@ struct bie_ws {
     float *grad = nullptr, *am = nullptr, *av = nullptr;
     int cap_batch = 0;
     float *in = nullptr, *z1 = nullptr, *a1 = nullptr, *z2 = nullptr, *a2 = nullptr, *y = nullptr, *dy = nullptr,
-          *d2 = nullptr, *d1 = nullptr, *tgt = nullptr;
+          *d2 = nullptr, *d1 = nullptr, *tgt = nullptr, *pol = nullptr, *yc = nullptr, *dyc = nullptr;
     double *lpart = nullptr;
     ~bie_ws()
     {
         for (void *p : { (void *)U, (void *)params, (void *)grad, (void *)am, (void *)av, (void *)in, (void *)z1,
                          (void *)a1, (void *)z2, (void *)a2, (void *)y, (void *)dy, (void *)d2, (void *)d1, (void *)tgt,
-                         (void *)lpart })
+                         (void *)lpart, (void *)pol, (void *)yc, (void *)dyc })
             if (p) (void)hipFree(p);
     }
 };
@@ -450,7 +474,8 @@ void ws_alloc_params(bie_ws *w)
 void ws_batch_scratch(bie_ws *w, int B)
 {
     if (w->cap_batch >= B) return;
-    for (float **p : { &w->in, &w->z1, &w->a1, &w->z2, &w->a2, &w->y, &w->dy, &w->d2, &w->d1, &w->tgt })
+    for (float **p : { &w->in, &w->z1, &w->a1, &w->z2, &w->a2, &w->y, &w->dy, &w->d2, &w->d1, &w->tgt, &w->pol,
+                       &w->yc, &w->dyc })
         if (*p) { (void)hipFree(*p); *p = nullptr; }
     if (w->lpart) { (void)hipFree(w->lpart); w->lpart = nullptr; }
     const size_t H = w->H, O = w->O;
@@ -464,6 +489,9 @@ void ws_batch_scratch(bie_ws *w, int B)
     w->d2 = dmalloc<float>(size_t(B) * H);
     w->d1 = dmalloc<float>(size_t(B) * H);
     w->tgt = dmalloc<float>(size_t(B) * O);
+    w->pol = dmalloc<float>(size_t(B) * 3);
+    w->yc = dmalloc<float>(size_t(B) * 2 * w->K);
+    w->dyc = dmalloc<float>(size_t(B) * 2 * w->K);
     w->lpart = dmalloc<double>(64);
     w->cap_batch = B;
 }
@@ -483,13 +511,25 @@ void mlp_forward(bie_ws *w, int B, hipStream_t s)
     BIE_HIP(hipGetLastError());
 }
 
-// loss partials (w->lpart[0..nb)) and gradient of the mean squared error into w->grad
-int mlp_backward(bie_ws *w, int B, hipStream_t s)
+// loss partials (w->lpart[0..nb)) and gradient of the mean squared error into
+// w->grad.  combine: the loss is on y = sum_c e_c f_c against 2K targets
+// (linear-in-polarisation model); otherwise on the raw outputs.
+int mlp_backward(bie_ws *w, int B, hipStream_t s, bool combine = false)
 {
     const int H = w->H, O = w->O;
     float *P = w->params, *G = w->grad;
     const int nb = 32;
-    hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, s, B * O, w->y, w->tgt, w->dy, 1.f / float(B * O), w->lpart);
+    if (combine) {
+        const int K2 = 2 * w->K;
+        hipLaunchKernelGGL(k_pol_combine, dim3((B * K2 + 255) / 256), dim3(256), 0, s, B, K2, w->y, w->pol, w->yc);
+        hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, s, B * K2, w->yc, w->tgt, w->dyc, 1.f / float(B * K2),
+                           w->lpart);
+        hipLaunchKernelGGL(k_pol_combine_back, dim3((B * O + 255) / 256), dim3(256), 0, s, B, K2, w->dyc, w->pol,
+                           w->dy);
+    } else {
+        hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, s, B * O, w->y, w->tgt, w->dy, 1.f / float(B * O),
+                           w->lpart);
+    }
     // layer 3
     sgemm<true, false>(O, H, B, w->dy, O, w->a2, H, G + w->off[4], H, false, s);   // dW3 = dy^T a2
     hipLaunchKernelGGL(k_colsum, dim3((O + 255) / 256), dim3(256), 0, s, B, O, w->dy, G + w->off[5]);
@@ -600,20 +640,22 @@ static void pod_basis(bie_ws *w, const double2 *X, int64_t S, int oversample, in
     cleanup();
 }
 
-bie_ws *ws_train(const bie_op *op, const double *feats, const void *Xv, int64_t S, const bie_ws_opts &o,
-                 hipStream_t s)
+bie_ws *ws_train(const bie_op *op, const double *feats, const double *pols, const void *Xv, int64_t S,
+                 const bie_ws_opts &o, hipStream_t s)
 {
     const int64_t N = op->mesh.N;
     auto w = std::make_unique<bie_ws>();
     w->op = op;
     w->K = o.pod_rank;
     w->H = o.hidden;
-    w->O = 2 * o.pod_rank;
+    w->pmodel = o.pol_model;
+    w->O = (o.pol_model == 1 ? 6 : 2) * o.pod_rank;
+    if (o.pol_model == 1 && !pols) throw Error(BIE_EINVAL, "the linear-in-polarisation model needs the polarisations");
     const double2 *X = static_cast<const double2 *>(Xv);
     pod_basis(w.get(), X, S, o.oversample, o.power_iters, o.seed, s);
     // targets: C = U^H X (K x S), one global RMS scale
     double2 *C = dmalloc<double2>(size_t(w->K) * S);
-    float *T = dmalloc<float>(size_t(S) * w->O);
+    float *T = dmalloc<float>(size_t(S) * 2 * w->K);
     std::vector<cd> ch(size_t(w->K) * S);
     inner(w->K, S, N, w->U, X, C, s);
     BIE_HIP(hipMemcpy(ch.data(), C, ch.size() * sizeof(cd), hipMemcpyDeviceToHost));
@@ -623,6 +665,7 @@ bie_ws *ws_train(const bie_op *op, const double *feats, const void *Xv, int64_t 
     if (!(w->scale > 0.0)) w->scale = 1.0;
     hipLaunchKernelGGL(k_targets, dim3(unsigned((S * w->K + 255) / 256)), dim3(256), 0, s, int(S), w->K, C,
                        1.0 / w->scale, T);
+    const int TW = 2 * w->K;   // target width
     BIE_HIP(hipGetLastError());
     ws_alloc_params(w.get());
     glorot(w.get(), o.seed);
@@ -633,8 +676,17 @@ bie_ws *ws_train(const bie_op *op, const double *feats, const void *Xv, int64_t 
     // features as FP32 on the device
     std::vector<float> fh(size_t(S) * 4);
     for (size_t i = 0; i < fh.size(); ++i) fh[i] = float(feats[i]);
+    if (w->pmodel == 1)
+        for (int64_t i = 0; i < S; ++i) fh[i * 4 + 3] = 0.f;   // input is the direction alone
     float *F = dmalloc<float>(fh.size());
     BIE_HIP(hipMemcpy(F, fh.data(), fh.size() * sizeof(float), hipMemcpyHostToDevice));
+    float *E = nullptr;
+    if (w->pmodel == 1) {
+        std::vector<float> eh(size_t(S) * 3);
+        for (size_t i = 0; i < eh.size(); ++i) eh[i] = float(pols[i]);
+        E = dmalloc<float>(eh.size());
+        BIE_HIP(hipMemcpy(E, eh.data(), eh.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
     const int64_t nbatch = (S + Bsz - 1) / Bsz;
     const int64_t total = int64_t(o.epochs) * nbatch;
     int64_t step = 0;
@@ -653,9 +705,10 @@ bie_ws *ws_train(const bie_op *op, const double *feats, const void *Xv, int64_t 
         for (int64_t bi = 0; bi < nbatch; ++bi) {
             const int64_t b0 = bi * Bsz;
             const int B = int(std::min<int64_t>(Bsz, S - b0));
-            hipLaunchKernelGGL(k_gather, dim3(unsigned(B)), dim3(256), 0, s, B, w->O, dperm, b0, F, T, w->in, w->tgt);
+            hipLaunchKernelGGL(k_gather, dim3(unsigned(B)), dim3(256), 0, s, B, TW, dperm, b0, F, T, E, w->in,
+                               w->tgt, w->pol);
             mlp_forward(w.get(), B, s);
-            const int nb = mlp_backward(w.get(), B, s);
+            const int nb = mlp_backward(w.get(), B, s, w->pmodel == 1);
             ++step;
             const double lr = o.lr_min + 0.5 * (o.lr_max - o.lr_min) *
                                              (1.0 + std::cos(PI * double(step - 1) / double(std::max<int64_t>(1, total - 1))));
@@ -668,7 +721,7 @@ bie_ws *ws_train(const bie_op *op, const double *feats, const void *Xv, int64_t 
                 BIE_HIP(hipStreamSynchronize(s));
                 double a = 0.0;
                 for (int q = 0; q < nb; ++q) a += lp[q];
-                eloss += a / double(B * w->O) * B;
+                eloss += a / double(B * TW) * B;
             }
         }
         if (ep == o.epochs - 1) last = eloss / double(S);
@@ -681,6 +734,7 @@ bie_ws *ws_train(const bie_op *op, const double *feats, const void *Xv, int64_t 
     (void)hipFree(C);
     (void)hipFree(T);
     (void)hipFree(F);
+    if (E) (void)hipFree(E);
     return w.release();
 }
 
@@ -690,17 +744,31 @@ static void ws_eval(bie_ws *w, const double *feats, int64_t R, hipStream_t s)
     ws_batch_scratch(w, int(R));
     std::vector<float> fh(size_t(R) * 4);
     for (size_t i = 0; i < fh.size(); ++i) fh[i] = float(feats[i]);
+    if (w->pmodel == 1)
+        for (int64_t i = 0; i < R; ++i) fh[i * 4 + 3] = 0.f;
     BIE_HIP(hipMemcpyAsync(w->in, fh.data(), fh.size() * sizeof(float), hipMemcpyHostToDevice, s));
     mlp_forward(w, int(R), s);
 }
 
-void ws_predict(bie_ws *w, const double *feats, int64_t R, const void *B, void *X0, int *used, hipStream_t s)
+void ws_predict(bie_ws *w, const double *feats, const double *pols, int64_t R, const void *B, void *X0, int *used,
+                hipStream_t s)
 {
     const int64_t N = w->op->mesh.N;
     if (!w->U) throw Error(BIE_EINVAL, "warm start has no POD basis (untrained)");
+    if (w->pmodel == 1 && !pols) throw Error(BIE_EINVAL, "the linear-in-polarisation model needs the polarisations");
     ws_eval(w, feats, R, s);
+    const float *out = w->y;
+    if (w->pmodel == 1) {
+        std::vector<float> eh(size_t(R) * 3);
+        for (size_t i = 0; i < eh.size(); ++i) eh[i] = float(pols[i]);
+        BIE_HIP(hipMemcpyAsync(w->pol, eh.data(), eh.size() * sizeof(float), hipMemcpyHostToDevice, s));
+        const int K2 = 2 * w->K;
+        hipLaunchKernelGGL(k_pol_combine, dim3(unsigned((R * K2 + 255) / 256)), dim3(256), 0, s, int(R), K2, w->y,
+                           w->pol, w->yc);
+        out = w->yc;
+    }
     double2 *c = dmalloc<double2>(size_t(R) * w->K);
-    hipLaunchKernelGGL(k_out_to_coef, dim3(unsigned((R * w->K + 255) / 256)), dim3(256), 0, s, int(R), w->K, w->y,
+    hipLaunchKernelGGL(k_out_to_coef, dim3(unsigned((R * w->K + 255) / 256)), dim3(256), 0, s, int(R), w->K, out,
                        w->scale, c);
     lincomb(R, w->K, N, c, w->U, static_cast<double2 *>(X0), s);
     (void)hipStreamSynchronize(s);
@@ -799,8 +867,8 @@ void ws_save(const bie_ws *w, const char *path)
     std::vector<float> P(w->nparams);
     BIE_HIP(hipMemcpy(U.data(), w->U, U.size() * sizeof(double2), hipMemcpyDeviceToHost));
     BIE_HIP(hipMemcpy(P.data(), w->params, P.size() * sizeof(float), hipMemcpyDeviceToHost));
-    const char magic[8] = { 'B', 'I', 'E', 'W', 'S', '0', '0', '1' };
-    const int64_t hdr[4] = { N, w->K, w->H, int64_t(w->nparams) };
+    const char magic[8] = { 'B', 'I', 'E', 'W', 'S', '0', '0', '2' };
+    const int64_t hdr[5] = { N, w->K, w->H, int64_t(w->nparams), w->pmodel };
     bool ok = std::fwrite(magic, 1, 8, f) == 8 && std::fwrite(hdr, sizeof(hdr), 1, f) == 1 &&
               std::fwrite(&w->scale, sizeof(double), 1, f) == 1 &&
               std::fwrite(w->sigma.data(), sizeof(double), w->sigma.size(), f) == w->sigma.size() &&
@@ -815,9 +883,9 @@ bie_ws *ws_load(const bie_op *op, const char *path)
     FILE *f = std::fopen(path, "rb");
     if (!f) throw Error(BIE_EINVAL, std::string("cannot open ") + path);
     char magic[8];
-    int64_t hdr[4];
+    int64_t hdr[5];
     double scale;
-    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "BIEWS001", 8) == 0 &&
+    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "BIEWS002", 8) == 0 &&
               std::fread(hdr, sizeof(hdr), 1, f) == 1 && std::fread(&scale, sizeof(double), 1, f) == 1;
     if (!ok || hdr[0] != op->mesh.N || hdr[1] < 1 || hdr[2] < 1) {
         std::fclose(f);
@@ -827,7 +895,8 @@ bie_ws *ws_load(const bie_op *op, const char *path)
     w->op = op;
     w->K = int(hdr[1]);
     w->H = int(hdr[2]);
-    w->O = 2 * w->K;
+    w->pmodel = int(hdr[4]);
+    w->O = (w->pmodel == 1 ? 6 : 2) * w->K;
     w->scale = scale;
     ws_alloc_params(w.get());
     if (int64_t(w->nparams) != hdr[3]) {
