@@ -38,7 +38,7 @@ void destroy_op(bie_op *op)
     if (!op) return;
     bie::free_workspace(op);
     bie::packed_free(op);
-    void *ptrs[] = { op->Z64, op->Z32, op->Abf, op->Bbf, op->tri.cent, op->tri.loc, op->tri.vfree, op->tri.verts,
+    void *ptrs[] = { op->Z64, op->Z32, op->Abf, op->Bbf, op->gemm_part, op->tri.cent, op->tri.loc, op->tri.vfree, op->tri.verts,
                      op->tri.area, op->tri.sgn, op->tri.slot_m, op->tri.edges };
     for (void *p : ptrs)
         if (p) (void)hipFree(p);

@@ -109,6 +109,8 @@ struct bie_op {
     int64_t gemm_Mp = 0, gemm_Kp = 0;
     void *Bbf = nullptr;          // split-BF16 staging of the right-hand block, [NCp][Kp] x 2
     int64_t bstage_cols = 0;
+    void *gemm_part = nullptr;    // split-K partial tiles, FP32 [KS][Mp][NCp]
+    size_t gemm_part_elems = 0;
     bie::Workspace *ws = nullptr;
 };
 

@@ -1,25 +1,35 @@
 // Block product Y = T X for many right-hand sides on the matrix cores.
 //
-// The complex product is one real GEMM with re/im interleaved along K:
-//   A[m][2n] = Re T_mn, A[m][2n+1] = Im T_mn                      (M = N, K = 2N)
-//   B[2n][r] = Re x_rn, B[2n+1][r] = -Im x_rn    (column r      -> Re y_r)
-//   B[2n][R+r] = Im x_rn, B[2n+1][R+r] = Re x_rn (column R + r  -> Im y_r)
+// The complex product is one real GEMM with re/im interleaved along K and the
+// two output parts of each right-hand side in adjacent columns:
+//   A[m][2n] = Re T_mn, A[m][2n+1] = Im T_mn                        (M = N, K = 2N)
+//   B[2n][2r]   = Re x_rn, B[2n+1][2r]   = -Im x_rn   (column 2r   -> Re y_r)
+//   B[2n][2r+1] = Im x_rn, B[2n+1][2r+1] =  Re x_rn   (column 2r+1 -> Im y_r)
 // Both operands are split into BF16 pairs (hi = rne(v), lo = rne(v - hi)) and
 // C = Ah Bh + Ah Bl + Al Bh is accumulated in FP32 with
 // v_mfma_f32_32x32x16_bf16 (about 16 significant bits per product entry; the
 // dropped lo*lo term is below the FP32 accumulation error).
 //
-// Tiling: a block of 8 waves computes a 256 x 256 tile of C; wave (wm, wn)
-// owns rows 128 wm .. +128 and columns 64 wn .. +64 as 4 x 2 MFMA tiles of
-// 32 x 32 (12 fragment reads from LDS feed 24 MFMAs per 16-deep step).  K advances in stages of 32; both planes of the A and B stage sit
-// in LDS, double-buffered (128 KiB of the 160 KiB LDS), rows padded to 40
-// BF16 to spread banks.  While a stage is computed (24 MFMAs per wave over 4
-// independent accumulators at a time), the next stage goes from registers to
-// the other buffer and the one after it is loaded from memory into registers:
-// one barrier per stage, loads issued two stages ahead.
+// Tiling: a block of 8 waves computes a 256 x 256 tile of C over one slice of
+// K; wave (wm, wn) owns rows 128 wm .. +128 and columns 64 wn .. +64 as 4 x 2
+// MFMA tiles of 32 x 32 (12 fragment reads from LDS feed 24 MFMAs per 16-deep
+// step).  K advances in stages of 32; both planes of the A and B stage sit in
+// LDS, double-buffered (160 KiB), rows padded to 40 BF16 to spread banks.
+// While a stage is computed the next one goes from registers to the other
+// buffer and the one after it is loaded from memory into registers: one
+// barrier per stage, loads issued two stages ahead.
+//
+// Split K: when the output tiles alone cannot fill the 256 compute units (one
+// 160 KiB block per CU), K is cut into KS slices (grid z).  Every block writes
+// its FP32 tile to a partial buffer [KS][Mp][NCp] (lanes along columns: 128-byte
+// runs); a second kernel sums the slices in FP64, subtracts from B if asked,
+// and transposes through LDS so that the complex128 output is written in
+// contiguous runs along m.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
+#include <cstdlib>
 
 #include "bie_internal.hpp"
 
@@ -71,8 +81,8 @@ __global__ __launch_bounds__(256) void k_split_vectors(const double2 *__restrict
     for (int64_t n = int64_t(blockIdx.x) * 256 + threadIdx.x; 2 * n < Kp; n += int64_t(gridDim.x) * 256) {
         float a = 0.f, b = 0.f;
         if (n < N && c < 2 * R) {
-            const double2 x = X[(c < R ? c : c - R) * ldx + n];
-            if (c < R) { a = float(x.x); b = float(-x.y); }
+            const double2 x = X[(c >> 1) * ldx + n];
+            if (!(c & 1)) { a = float(x.x); b = float(-x.y); }
             else { a = float(x.y); b = float(x.x); }
         }
         __bf16 h0, l0, h1, l1;
@@ -85,11 +95,11 @@ __global__ __launch_bounds__(256) void k_split_vectors(const double2 *__restrict
     }
 }
 
-// C = Ah Bh + Ah Bl + Al Bh; epilogue: Y[r][m] = (C[m][r], C[m][R + r]), or B - that.
+// Partial C = Ah Bh + Ah Bl + Al Bh over the stages of slice blockIdx.z, into
+// P[z][Mp][NCp].
 __global__ __launch_bounds__(512) void k_gemm_split(const __bf16 *__restrict__ Ah, const __bf16 *__restrict__ Al,
                                                     const __bf16 *__restrict__ Bh, const __bf16 *__restrict__ Bl,
-                                                    int64_t Kp, int64_t N, int64_t R, double *__restrict__ Y,
-                                                    int64_t ldy, const double *__restrict__ Bsub, int64_t ldb)
+                                                    int64_t Kp, int64_t Mp, int64_t NCp, float *__restrict__ P)
 {
     __shared__ __attribute__((aligned(16))) __bf16 sA[2][2][GBM][PK];   // [buffer][plane][row][k]
     __shared__ __attribute__((aligned(16))) __bf16 sB[2][2][GBN][PK];   // [buffer][plane][col][k]
@@ -134,13 +144,13 @@ __global__ __launch_bounds__(512) void k_gemm_split(const __bf16 *__restrict__ A
     // pipeline: stage s is computed from LDS buffer s%2 while stage s+1 is
     // stored into the other buffer and stage s+2 is in flight to registers;
     // one barrier per stage
-    const int64_t nst = Kp / GBK;
-    gload(0);
+    const int64_t nall = Kp / GBK, sb = nall * blockIdx.z / gridDim.z, se = nall * (blockIdx.z + 1) / gridDim.z;
+    gload(sb * GBK);
     lstore(0);
-    if (nst > 1) gload(GBK);
+    if (se - sb > 1) gload((sb + 1) * GBK);
     __syncthreads();
-    for (int64_t st = 0; st < nst; ++st) {
-        const int buf = int(st & 1);
+    for (int64_t st = sb; st < se; ++st) {
+        const int buf = int((st - sb) & 1);
 #pragma unroll
         for (int kk = 0; kk < GBK; kk += 16) {
             bf16x8 a[TI][2], b[TJ][2];   // [tile][plane]
@@ -170,30 +180,70 @@ __global__ __launch_bounds__(512) void k_gemm_split(const __bf16 *__restrict__ A
                 for (int j = 0; j < TJ; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][1], b[j][0], acc[i][j], 0, 0, 0);
         }
-        if (st + 1 < nst) {
-            lstore(buf ^ 1);                          // stage st+1 (already in registers)
-            if (st + 2 < nst) gload((st + 2) * GBK);  // stage st+2 in flight during the next compute
+        if (st + 1 < se) {
+            lstore(buf ^ 1);                         // stage st+1 (already in registers)
+            if (st + 2 < se) gload((st + 2) * GBK);  // stage st+2 in flight during the next compute
         }
         __syncthreads();
     }
-    // epilogue: accumulator q of lane l holds row 8(q/4) + 4(l/32) + q%4, column l%32 of its 32x32 tile
+    // accumulator q of lane l holds row 8(q/4) + 4(l/32) + q%4, column l%32 of its 32x32 tile
+    float *Pz = P + int64_t(blockIdx.z) * Mp * NCp;
 #pragma unroll
     for (int i = 0; i < TI; ++i)
 #pragma unroll
         for (int j = 0; j < TJ; ++j) {
             const int64_t c = c0 + wn * 64 + j * 32 + (lane & 31);
-            if (c >= 2 * R) continue;
-            const int64_t r = c < R ? c : c - R;
-            const int part = c < R ? 0 : 1;
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
                 const int64_t m = m0 + wm * 128 + i * 32 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
-                if (m >= N) continue;
-                double v = double(acc[i][j][q]);
-                if (Bsub) v = Bsub[2 * (r * ldb + m) + part] - v;
-                Y[2 * (r * ldy + m) + part] = v;
+                Pz[m * NCp + c] = acc[i][j][q];
             }
         }
+}
+
+// Y[r][m] = sum_z (P[z][m][2r], P[z][m][2r+1]) (or Bsub - that) for a tile of
+// 64 rows x 32 right-hand sides; the slices are summed in FP64.
+__global__ __launch_bounds__(256) void k_gemm_reduce(const float *__restrict__ P, int KS, int64_t Mp, int64_t NCp,
+                                                     int64_t N, int64_t R, double2 *__restrict__ Y, int64_t ldy,
+                                                     const double2 *__restrict__ Bsub, int64_t ldb)
+{
+    __shared__ double sd[64][65];   // [column][row]
+    const int t = threadIdx.x;
+    const int64_t m0 = int64_t(blockIdx.x) * 64, cb = int64_t(blockIdx.y) * 64;
+    const int cl = t & 63;
+#pragma unroll 4
+    for (int it = 0; it < 16; ++it) {
+        const int ml = it * 4 + (t >> 6);
+        double v = 0.0;
+        for (int z = 0; z < KS; ++z) v += double(P[(int64_t(z) * Mp + m0 + ml) * NCp + cb + cl]);
+        sd[cl][ml] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < 8; ++it) {
+        const int idx = it * 256 + t, rl = idx >> 6, ml = idx & 63;
+        const int64_t r = cb / 2 + rl, m = m0 + ml;
+        if (r >= R || m >= N) continue;
+        double2 y = make_double2(sd[2 * rl][ml], sd[2 * rl + 1][ml]);
+        if (Bsub) {
+            const double2 b = Bsub[r * ldb + m];
+            y = make_double2(b.x - y.x, b.y - y.y);
+        }
+        Y[r * ldy + m] = y;
+    }
+}
+
+// Slices of K per launch: enough blocks for the 256 compute units, at least
+// 8 stages per slice; BIE_GEMM_SPLITK overrides (measurement).
+int gemm_splitk(int64_t blocks, int64_t nst)
+{
+    static const int env = [] {
+        const char *e = getenv("BIE_GEMM_SPLITK");
+        return e ? atoi(e) : 0;
+    }();
+    int64_t ks = env > 0 ? env : std::max<int64_t>(1, 256 / blocks);
+    ks = std::min<int64_t>(ks, std::max<int64_t>(1, nst / 8));
+    return int(std::max<int64_t>(1, std::min<int64_t>(ks, 64)));
 }
 
 }  // namespace
@@ -232,14 +282,28 @@ void gemm_product(const bie_op *opc, const void *X, int64_t ldx, void *Y, int64_
         BIE_HIP(hipMalloc(&op->Bbf, 2 * plane * sizeof(__bf16)));
         op->bstage_cols = NCp;
     }
+    const int64_t blocks = (Mp / GBM) * (NCp / GBN);
+    const int KS = gemm_splitk(blocks, Kp / GBK);
+    const size_t pelems = size_t(KS) * size_t(Mp) * size_t(NCp);
+    if (op->gemm_part_elems < pelems) {
+        BIE_HIP(hipStreamSynchronize(s));
+        if (op->gemm_part) (void)hipFree(op->gemm_part);
+        op->gemm_part = nullptr;
+        op->gemm_part_elems = 0;
+        BIE_HIP(hipMalloc(&op->gemm_part, pelems * sizeof(float)));
+        op->gemm_part_elems = pelems;
+    }
     __bf16 *Bh = static_cast<__bf16 *>(op->Bbf), *Bl = Bh + plane;
     const __bf16 *Ah = static_cast<const __bf16 *>(op->Abf), *Al = Ah + size_t(Mp) * size_t(Kp);
+    float *P = static_cast<float *>(op->gemm_part);
     hipLaunchKernelGGL(k_split_vectors, dim3(unsigned(std::min<int64_t>((Kp / 2 + 255) / 256, 64)), unsigned(NCp)),
                        dim3(256), 0, s, (const double2 *)X, ldx, N, R, Kp, Bh, Bl);
     prof_gemm_begin(s);
-    hipLaunchKernelGGL(k_gemm_split, dim3(unsigned(Mp / GBM), unsigned(NCp / GBN)), dim3(512), 0, s, Ah, Al, Bh, Bl,
-                       Kp, N, R, (double *)Y, ldy, (const double *)Bsub, ldb);
+    hipLaunchKernelGGL(k_gemm_split, dim3(unsigned(Mp / GBM), unsigned(NCp / GBN), unsigned(KS)), dim3(512), 0, s, Ah,
+                       Al, Bh, Bl, Kp, Mp, NCp, P);
     prof_gemm_end(s);
+    hipLaunchKernelGGL(k_gemm_reduce, dim3(unsigned(Mp / 64), unsigned(NCp / 64)), dim3(256), 0, s, P, KS, Mp, NCp,
+                       N, R, (double2 *)Y, ldy, (const double2 *)Bsub, ldb);
     BIE_HIP(hipGetLastError());
 }
 
