@@ -139,6 +139,8 @@ typedef struct {
                                FP32 matrix (storage BIE_C64 with keep_fp64) */
     double inner_tol;    /* precision 1: inner tolerance relative to the outer residual
                             (0: default 1e-3) */
+    int64_t slots;       /* precision 1: right-hand sides in flight (continuous batch:
+                            a converged one hands its slot to the next); 0: all R */
 } bie_solve_opts;
 
 typedef struct {

@@ -41,7 +41,7 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int), ("restart", ctypes.c_int), ("tol", ctypes.c_double),
                 ("max_mvp", ctypes.c_int64), ("crit", ctypes.c_int), ("rscc_rows", ctypes.c_int64),
                 ("rscc_seed", ctypes.c_uint64), ("use_x0", ctypes.c_int), ("precision", ctypes.c_int),
-                ("inner_tol", ctypes.c_double)]
+                ("inner_tol", ctypes.c_double), ("slots", ctypes.c_int64)]
 
 
 class WsOpts(ctypes.Structure):
@@ -159,12 +159,13 @@ class Solve:
     rscc_seed: int = 1234
     precision: str = "plain"      # "plain" or "mixed" (FP32 inner GMRES + FP64 refinement)
     inner_tol: float = 0.0
+    slots: int = 0                # mixed: right-hand sides in flight (continuous batch); 0 = all
 
     def c(self, use_x0: bool) -> SolveOpts:
         return SolveOpts({"gmres": BIE_GMRES, "cgnr": BIE_CGNR}[self.method], self.restart, self.tol,
                          self.max_mvp, {"scc": BIE_SCC, "rscc": BIE_RSCC}[self.crit], self.rscc_rows,
                          self.rscc_seed, int(use_x0), {"plain": 0, "mixed": 1}[self.precision],
-                         self.inner_tol)
+                         self.inner_tol, self.slots)
 
 
 class Operator:

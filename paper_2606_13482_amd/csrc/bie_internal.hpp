@@ -149,8 +149,8 @@ void prof_gemm_begin(hipStream_t s);
 void prof_gemm_end(hipStream_t s);
 // gemm.hip
 void split_matrix(bie_op *op, hipStream_t s);
-void gemm_product(const bie_op *op, const void *X, int64_t ldx, void *Y, int64_t ldy, const void *Bsub, int64_t ldb,
-                  int64_t R, hipStream_t s);
+void gemm_product(const bie_op *op, const void *X, int64_t ldx, bool xf32, void *Y, int64_t ldy, const void *Bsub,
+                  int64_t ldb, int64_t R, const int *cols, hipStream_t s);
 
 // warmstart.hip
 bie_ws *ws_train(const bie_op *op, const double *feats, const double *pols, const void *X, int64_t S,

@@ -443,7 +443,7 @@ void product(const bie_op *opc, int mat, bool vec64, const void *X, int64_t ldx,
     if (mat == MATBF16) {
         if (!op->Abf) throw Error(BIE_EINVAL, "no split-BF16 matrix stored");
         if (!vec64 || conj) throw Error(BIE_EINVAL, "the block product takes complex128 vectors, no conjugate");
-        gemm_product(op, X, ldx, Y, ldy, B, ldb, R, s);
+        gemm_product(op, X, ldx, false, Y, ldy, B, ldb, R, nullptr, s);
         return;
     }
     const bool mat64 = mat == MAT64;

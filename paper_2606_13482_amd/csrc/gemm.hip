@@ -72,16 +72,19 @@ __global__ __launch_bounds__(256) void k_split_matrix(const double2 *__restrict_
     }
 }
 
-// B planes [NCp][Kp] from R complex vectors (vector r at X + r*ldx).
-__global__ __launch_bounds__(256) void k_split_vectors(const double2 *__restrict__ X, int64_t ldx, int64_t N,
-                                                       int64_t R, int64_t Kp, __bf16 *__restrict__ Bh,
+// B planes [NCp][Kp] from R complex vectors (complex128 or complex64 XT):
+// GEMM column pair r reads the vector at X + v*ldx, v = cols ? cols[r] : r.
+template <typename XT>
+__global__ __launch_bounds__(256) void k_split_vectors(const XT *__restrict__ X, int64_t ldx, const int *__restrict__ cols,
+                                                       int64_t N, int64_t R, int64_t Kp, __bf16 *__restrict__ Bh,
                                                        __bf16 *__restrict__ Bl)
 {
     const int64_t c = blockIdx.y;
+    const int64_t v = c < 2 * R ? (cols ? int64_t(cols[c >> 1]) : (c >> 1)) : 0;
     for (int64_t n = int64_t(blockIdx.x) * 256 + threadIdx.x; 2 * n < Kp; n += int64_t(gridDim.x) * 256) {
         float a = 0.f, b = 0.f;
         if (n < N && c < 2 * R) {
-            const double2 x = X[(c >> 1) * ldx + n];
+            const XT x = X[v * ldx + n];
             if (!(c & 1)) { a = float(x.x); b = float(-x.y); }
             else { a = float(x.y); b = float(x.x); }
         }
@@ -201,10 +204,12 @@ __global__ __launch_bounds__(512) void k_gemm_split(const __bf16 *__restrict__ A
         }
 }
 
-// Y[r][m] = sum_z (P[z][m][2r], P[z][m][2r+1]) (or Bsub - that) for a tile of
-// 64 rows x 32 right-hand sides; the slices are summed in FP64.
+// Y[v][m] = sum_z (P[z][m][2r], P[z][m][2r+1]) (or Bsub[v][m] - that), v = cols ?
+// cols[r] : r, for a tile of 64 rows x 32 right-hand sides; the slices are
+// summed in FP64.
 __global__ __launch_bounds__(256) void k_gemm_reduce(const float *__restrict__ P, int KS, int64_t Mp, int64_t NCp,
-                                                     int64_t N, int64_t R, double2 *__restrict__ Y, int64_t ldy,
+                                                     int64_t N, int64_t R, const int *__restrict__ cols,
+                                                     double2 *__restrict__ Y, int64_t ldy,
                                                      const double2 *__restrict__ Bsub, int64_t ldb)
 {
     __shared__ double sd[64][65];   // [column][row]
@@ -224,12 +229,13 @@ __global__ __launch_bounds__(256) void k_gemm_reduce(const float *__restrict__ P
         const int idx = it * 256 + t, rl = idx >> 6, ml = idx & 63;
         const int64_t r = cb / 2 + rl, m = m0 + ml;
         if (r >= R || m >= N) continue;
+        const int64_t v = cols ? int64_t(cols[r]) : r;
         double2 y = make_double2(sd[2 * rl][ml], sd[2 * rl + 1][ml]);
         if (Bsub) {
-            const double2 b = Bsub[r * ldb + m];
+            const double2 b = Bsub[v * ldb + m];
             y = make_double2(b.x - y.x, b.y - y.y);
         }
-        Y[r * ldy + m] = y;
+        Y[v * ldy + m] = y;
     }
 }
 
@@ -267,9 +273,11 @@ void split_matrix(bie_op *op, hipStream_t s)
     BIE_HIP(hipStreamSynchronize(s));
 }
 
-// Y = T X (or Bsub - T X) for R vectors with the split-BF16 matrix; complex128 vectors.
-void gemm_product(const bie_op *opc, const void *X, int64_t ldx, void *Y, int64_t ldy, const void *Bsub, int64_t ldb,
-                  int64_t R, hipStream_t s)
+// Y = T X (or Bsub - T X) for R vectors with the split-BF16 matrix; X
+// complex128 or complex64 (xf32), Y and Bsub complex128; cols (device, R
+// entries, or null for 0..R-1) names the vectors taking part.
+void gemm_product(const bie_op *opc, const void *X, int64_t ldx, bool xf32, void *Y, int64_t ldy, const void *Bsub,
+                  int64_t ldb, int64_t R, const int *cols, hipStream_t s)
 {
     bie_op *op = const_cast<bie_op *>(opc);
     const int64_t N = op->mesh.N, Kp = op->gemm_Kp, Mp = op->gemm_Mp, NCp = gemm_pad_cols(R);
@@ -296,14 +304,19 @@ void gemm_product(const bie_op *opc, const void *X, int64_t ldx, void *Y, int64_
     __bf16 *Bh = static_cast<__bf16 *>(op->Bbf), *Bl = Bh + plane;
     const __bf16 *Ah = static_cast<const __bf16 *>(op->Abf), *Al = Ah + size_t(Mp) * size_t(Kp);
     float *P = static_cast<float *>(op->gemm_part);
-    hipLaunchKernelGGL(k_split_vectors, dim3(unsigned(std::min<int64_t>((Kp / 2 + 255) / 256, 64)), unsigned(NCp)),
-                       dim3(256), 0, s, (const double2 *)X, ldx, N, R, Kp, Bh, Bl);
+    const dim3 sgrid(unsigned(std::min<int64_t>((Kp / 2 + 255) / 256, 64)), unsigned(NCp));
+    if (xf32)
+        hipLaunchKernelGGL(k_split_vectors<float2>, sgrid, dim3(256), 0, s, (const float2 *)X, ldx, cols, N, R, Kp, Bh,
+                           Bl);
+    else
+        hipLaunchKernelGGL(k_split_vectors<double2>, sgrid, dim3(256), 0, s, (const double2 *)X, ldx, cols, N, R, Kp,
+                           Bh, Bl);
     prof_gemm_begin(s);
     hipLaunchKernelGGL(k_gemm_split, dim3(unsigned(Mp / GBM), unsigned(NCp / GBN), unsigned(KS)), dim3(512), 0, s, Ah,
                        Al, Bh, Bl, Kp, Mp, NCp, P);
     prof_gemm_end(s);
     hipLaunchKernelGGL(k_gemm_reduce, dim3(unsigned(Mp / 64), unsigned(NCp / 64)), dim3(256), 0, s, P, KS, Mp, NCp,
-                       N, R, (double2 *)Y, ldy, (const double2 *)Bsub, ldb);
+                       N, R, cols, (double2 *)Y, ldy, (const double2 *)Bsub, ldb);
     BIE_HIP(hipGetLastError());
 }
 

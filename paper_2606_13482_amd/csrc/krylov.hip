@@ -28,9 +28,16 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <vector>
 
 #include "bie_internal.hpp"
+
+// No automatic fusion of multiplies and adds in this file: the rounding of
+// every result follows the source expression, so kernels instantiated with
+// different element counts per thread, or different column counts, give
+// bitwise identical columns.  Fused multiply-adds are written out as fma().
+#pragma clang fp contract(off)
 
 namespace bie {
 
@@ -62,11 +69,21 @@ struct ColStat {
 };
 static_assert(sizeof(ColStat) == 96, "ColStat layout");
 
-__device__ inline double2 cmul(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__device__ inline double2 cmul(double2 a, double2 b)
+{
+    return make_double2(fma(a.x, b.x, -(a.y * b.y)), fma(a.x, b.y, a.y * b.x));
+}
 __device__ inline double2 cmulc(double2 a, double2 b)   // conj(a) * b
 {
-    return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+    return make_double2(fma(a.x, b.x, a.y * b.y), fma(a.x, b.y, -(a.y * b.x)));
 }
+
+// Basis vectors are stored as complex128 or complex64 (VT); arithmetic is FP64.
+__device__ inline double2 ld2(const double2 &v) { return v; }
+__device__ inline double2 ld2(const float2 &v) { return make_double2(double(v.x), double(v.y)); }
+template <typename VT> __device__ inline VT st2(double2 v);
+template <> __device__ inline double2 st2<double2>(double2 v) { return v; }
+template <> __device__ inline float2 st2<float2>(double2 v) { return make_float2(float(v.x), float(v.y)); }
 
 __device__ inline double wsum(double v)
 {
@@ -113,24 +130,28 @@ __device__ inline void wave_sum8(double2 p[8])
     }
 }
 
-// Block partial of conj(V[k][e]) * w for k = 0..nk-1 (e = this thread's element),
-// written to red[k][wave]; wave-level sums use wave_sum8 over groups of 8 k.
-__device__ inline void block_dots(const double2 *__restrict__ V, int64_t N, int64_t e, bool in, double2 w, int nk,
-                                  double2 (*red)[4])
+// Chunk partials of conj(V[k][e]) * w[e] for k = 0..nk-1: element q of this
+// thread belongs to chunk q of the block; written to red[q][k][wave].  Wave
+// sums use wave_sum8 over groups of 8 k.
+template <typename VT, int EPT>
+__device__ inline void block_dots(const VT *__restrict__ V, int64_t N, const int64_t *e, const double2 *w, int nk,
+                                  double2 (*red)[MAXM + 1][4])
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int k0 = 0; k0 < nk; k0 += 8) {
-        double2 p[8];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int k = k0 + i;
-            p[i] = make_double2(0.0, 0.0);
-            if (in && k < nk) p[i] = cmulc(V[int64_t(k) * N + e], w);
+    for (int q = 0; q < EPT; ++q)
+        for (int k0 = 0; k0 < nk; k0 += 8) {
+            double2 p[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int k = k0 + i;
+                p[i] = make_double2(0.0, 0.0);
+                if (e[q] < N && k < nk) p[i] = cmulc(ld2(V[int64_t(k) * N + e[q]]), w[q]);
+            }
+            wave_sum8(p);
+            const int kk = k0 + ((lane >> 3) & 7);
+            if ((lane & 7) == 0 && kk < nk) red[q][kk][wave] = p[0];
         }
-        wave_sum8(p);
-        const int kk = k0 + ((lane >> 3) & 7);
-        if ((lane & 7) == 0 && kk < nk) red[kk][wave] = p[0];
-    }
 }
 
 // Last-block election: returns true in every thread of the block that
@@ -179,8 +200,10 @@ __device__ inline void chunk_dots(const double2 *__restrict__ V, int64_t N, int6
 // pass w' = w - V h1, a second pass is made only if ||w'||^2 < ||w||^2 / 2,
 // judged from ||w||^2 - ||h1||^2 (accurate whenever the test passes).  Every
 // block evaluates the test from the same sums in the same order, so all blocks
-// agree.  One element per thread; blocks write partial sums, the next launch
-// adds the partials of all blocks itself, in block order (no atomics).
+// agree.  Partial sums are kept per chunk of AB consecutive elements and the
+// next launch adds the partials of all chunks itself, in chunk order (no
+// atomics).  A thread handles EPT elements, one in each of EPT chunks of its
+// block; the chunk partials do not depend on EPT, so neither do the results.
 //   pass1:  P1 = partial V_{0..j}^H w (2-D grid: 8 basis vectors per block
 //           column), ||w||^2 partials
 //   pass2:  h1 = sum P1; w' = w - V h1; PN = partial ||w'||^2; if the test
@@ -191,7 +214,15 @@ __device__ inline void chunk_dots(const double2 *__restrict__ V, int64_t N, int6
 constexpr int AB = 256;   // elements (threads) per block in the Arnoldi kernels
 constexpr int KG = 8;     // basis vectors per block in the first pass
 
-__global__ __launch_bounds__(AB) void k_cgs_pass1(int64_t N, int m, int j, const double2 *__restrict__ Vall,
+// element q of thread t in block b (coalesced): (b EPT + q) AB + t
+template <int EPT>
+__device__ inline int64_t elem(int q)
+{
+    return (int64_t(blockIdx.x) * EPT + q) * AB + threadIdx.x;
+}
+
+template <typename VT, int EPT>
+__global__ __launch_bounds__(AB) void k_cgs_pass1(int64_t N, int m, int j, const VT *__restrict__ Vall,
                                                   const double2 *__restrict__ Wall, double2 *__restrict__ P1all,
                                                   double *__restrict__ PWall, const ColStat *__restrict__ st)
 {
@@ -199,34 +230,47 @@ __global__ __launch_bounds__(AB) void k_cgs_pass1(int64_t N, int m, int j, const
     if (st[r].done) return;
     const int k0 = blockIdx.y * KG;
     if (k0 > j) return;
-    const int nb = gridDim.x;
-    const int64_t e = int64_t(blockIdx.x) * AB + threadIdx.x;
-    const bool in = e < N;
-    const double2 *V = Vall + int64_t(r) * (m + 1) * N;
-    const double2 w = in ? Wall[int64_t(r) * N + e] : make_double2(0.0, 0.0);
+    const int nc = int((N + AB - 1) / AB);   // chunks of AB elements
+    const VT *V = Vall + int64_t(r) * (m + 1) * N;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    double2 p[8];
+    __shared__ double2 red[EPT][KG][AB / 64];
+    __shared__ double rn[EPT][AB / 64];
+    // all loads first (KG basis vectors x EPT elements), then one wave_sum8 per element
+    double2 w[EPT], vv[EPT][KG];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        p[i] = make_double2(0.0, 0.0);
-        if (in && k0 + i <= j) p[i] = cmulc(V[int64_t(k0 + i) * N + e], w);
+    for (int q = 0; q < EPT; ++q) {
+        const int64_t e = elem<EPT>(q);
+        w[q] = e < N ? Wall[int64_t(r) * N + e] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int i = 0; i < KG; ++i)
+            vv[q][i] = (e < N && k0 + i <= j) ? ld2(V[int64_t(k0 + i) * N + e]) : make_double2(0.0, 0.0);
     }
-    wave_sum8(p);
-    __shared__ double2 red[KG][AB / 64];
-    __shared__ double rn[AB / 64];
-    if ((lane & 7) == 0) red[lane >> 3][wave] = p[0];
-    if (blockIdx.y == 0) {
-        const double nn = wsum(w.x * w.x + w.y * w.y);
-        if (lane == 0) rn[wave] = nn;
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+        double2 p[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) p[i] = cmulc(vv[q][i], w[q]);
+        wave_sum8(p);
+        if ((lane & 7) == 0) red[q][lane >> 3][wave] = p[0];
+        if (blockIdx.y == 0) {
+            const double nn = wsum(w[q].x * w[q].x + w[q].y * w[q].y);
+            if (lane == 0) rn[q][wave] = nn;
+        }
     }
     __syncthreads();
-    double2 *P1 = P1all + (int64_t(r) * nb + blockIdx.x) * (m + 1);
-    if (threadIdx.x < KG && k0 + int(threadIdx.x) <= j) {
-        double2 a = red[threadIdx.x][0];
-        for (int q = 1; q < AB / 64; ++q) { a.x += red[threadIdx.x][q].x; a.y += red[threadIdx.x][q].y; }
-        P1[k0 + threadIdx.x] = a;
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+        const int c = int(blockIdx.x) * EPT + q;
+        if (c >= nc) break;
+        double2 *P1 = P1all + (int64_t(r) * nc + c) * (m + 1);
+        if (threadIdx.x < KG && k0 + int(threadIdx.x) <= j) {
+            double2 a = red[q][threadIdx.x][0];
+            for (int u = 1; u < AB / 64; ++u) { a.x += red[q][threadIdx.x][u].x; a.y += red[q][threadIdx.x][u].y; }
+            P1[k0 + threadIdx.x] = a;
+        }
+        if (blockIdx.y == 0 && threadIdx.x == 0)
+            PWall[int64_t(r) * nc + c] = rn[q][0] + rn[q][1] + rn[q][2] + rn[q][3];
     }
-    if (blockIdx.y == 0 && threadIdx.x == 0) PWall[int64_t(r) * nb + blockIdx.x] = rn[0] + rn[1] + rn[2] + rn[3];
 }
 
 // h[k] = sum over blocks of P[b][k], k <= kmax, into LDS (block order)
@@ -252,26 +296,36 @@ __device__ inline double sum_real_partials(const double *__restrict__ P, int nb)
     return wsum(a);
 }
 
-// w -= V_{0..j} h (h in LDS), loads batched 8 basis vectors at a time
-__device__ inline double2 cgs_update(const double2 *__restrict__ V, int64_t N, int64_t e, int j, double2 w,
-                                     const double2 *h)
+// w[q] -= V_{0..j} h for the EPT elements e[q] of this thread (h in LDS).
+// Loads are batched over 8 / EPT basis vectors and all EPT elements; every
+// element subtracts its terms in ascending k whatever EPT is.
+template <typename VT, int EPT>
+__device__ inline void cgs_update(const VT *__restrict__ V, int64_t N, const int64_t *e, int j, double2 *w,
+                                  const double2 *h)
 {
-    for (int k0 = 0; k0 <= j; k0 += 8) {
-        double2 vv[8];
+    constexpr int KB = 8 / EPT;
+    for (int k0 = 0; k0 <= j; k0 += KB) {
+        double2 vv[KB][EPT];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) vv[i] = k0 + i <= j ? V[int64_t(k0 + i) * N + e] : make_double2(0.0, 0.0);
+        for (int i = 0; i < KB; ++i)
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
+            for (int q = 0; q < EPT; ++q)
+                vv[i][q] = (k0 + i <= j && e[q] < N) ? ld2(V[int64_t(k0 + i) * N + e[q]]) : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int i = 0; i < KB; ++i) {
             if (k0 + i > j) break;
-            const double2 p = cmul(vv[i], h[k0 + i]);
-            w.x -= p.x;
-            w.y -= p.y;
+#pragma unroll
+            for (int q = 0; q < EPT; ++q) {
+                const double2 p = cmul(vv[i][q], h[k0 + i]);
+                w[q].x -= p.x;
+                w[q].y -= p.y;
+            }
         }
     }
-    return w;
 }
 
-__global__ __launch_bounds__(AB) void k_cgs_pass2(int64_t N, int m, int j, const double2 *__restrict__ Vall,
+template <typename VT, int EPT>
+__global__ __launch_bounds__(AB) void k_cgs_pass2(int64_t N, int m, int j, const VT *__restrict__ Vall,
                                                   double2 *__restrict__ Wall, const double2 *__restrict__ P1all,
                                                   const double *__restrict__ PWall, double2 *__restrict__ P2all,
                                                   double *__restrict__ PNall, double2 *__restrict__ Hall,
@@ -279,13 +333,13 @@ __global__ __launch_bounds__(AB) void k_cgs_pass2(int64_t N, int m, int j, const
 {
     const int r = blockIdx.y;
     if (st[r].done) return;
-    const int nb = gridDim.x;
+    const int nc = int((N + AB - 1) / AB);
     __shared__ double2 h[MAXM + 1];
     __shared__ int s_reorth;
     __shared__ double s_w2;
-    sum_partials(P1all + int64_t(r) * nb * (m + 1), nb, m + 1, j, h);
+    sum_partials(P1all + int64_t(r) * nc * (m + 1), nc, m + 1, j, h);
     if (threadIdx.x < 64) {
-        const double w2 = sum_real_partials(PWall + int64_t(r) * nb, nb);
+        const double w2 = sum_real_partials(PWall + int64_t(r) * nc, nc);
         if (threadIdx.x == 0) s_w2 = w2;
     }
     __syncthreads();
@@ -301,43 +355,59 @@ __global__ __launch_bounds__(AB) void k_cgs_pass2(int64_t N, int m, int j, const
         for (int k = threadIdx.x; k <= j; k += AB) Hall[(int64_t(r) * m + j) * (m + 1) + k] = h[k];
         if (threadIdx.x == 0) st[r].reorth = reorth;
     }
-    const int64_t e = int64_t(blockIdx.x) * AB + threadIdx.x;
-    const bool in = e < N;
-    const double2 *V = Vall + int64_t(r) * (m + 1) * N;
-    double2 w = make_double2(0.0, 0.0);
-    if (in) {
-        w = cgs_update(V, N, e, j, Wall[int64_t(r) * N + e], h);
-        Wall[int64_t(r) * N + e] = w;
+    const VT *V = Vall + int64_t(r) * (m + 1) * N;
+    int64_t e[EPT];
+    double2 w[EPT];
+    __shared__ double rn[EPT][AB / 64];
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+        e[q] = elem<EPT>(q);
+        w[q] = e[q] < N ? Wall[int64_t(r) * N + e[q]] : make_double2(0.0, 0.0);
     }
-    __shared__ double rn[AB / 64];
-    const double nn = wsum(w.x * w.x + w.y * w.y);
-    if ((threadIdx.x & 63) == 0) rn[threadIdx.x >> 6] = nn;
+    cgs_update<VT, EPT>(V, N, e, j, w, h);
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+        if (e[q] < N) Wall[int64_t(r) * N + e[q]] = w[q];
+        const double nn = wsum(w[q].x * w[q].x + w[q].y * w[q].y);
+        if ((threadIdx.x & 63) == 0) rn[q][threadIdx.x >> 6] = nn;
+    }
     if (reorth) {
-        __shared__ double2 red[MAXM + 1][AB / 64];
-        block_dots(V, N, e, in, w, j + 1, red);
+        __shared__ double2 red[EPT][MAXM + 1][AB / 64];
+        block_dots<VT, EPT>(V, N, e, w, j + 1, red);
         __syncthreads();
-        double2 *P2 = P2all + (int64_t(r) * nb + blockIdx.x) * (m + 1);
-        for (int k = threadIdx.x; k <= j; k += AB) {
-            double2 a = red[k][0];
-            for (int q = 1; q < AB / 64; ++q) { a.x += red[k][q].x; a.y += red[k][q].y; }
-            P2[k] = a;
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+            const int c = int(blockIdx.x) * EPT + q;
+            if (c >= nc) break;
+            double2 *P2 = P2all + (int64_t(r) * nc + c) * (m + 1);
+            for (int k = threadIdx.x; k <= j; k += AB) {
+                double2 a = red[q][k][0];
+                for (int u = 1; u < AB / 64; ++u) { a.x += red[q][k][u].x; a.y += red[q][k][u].y; }
+                P2[k] = a;
+            }
         }
     } else {
         __syncthreads();
     }
-    if (threadIdx.x == 0) PNall[int64_t(r) * nb + blockIdx.x] = rn[0] + rn[1] + rn[2] + rn[3];
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+            const int c = int(blockIdx.x) * EPT + q;
+            if (c < nc) PNall[int64_t(r) * nc + c] = rn[q][0] + rn[q][1] + rn[q][2] + rn[q][3];
+        }
 }
 
-__global__ __launch_bounds__(AB) void k_cgs_pass3(int64_t N, int m, int j, const double2 *__restrict__ Vall,
+template <typename VT, int EPT>
+__global__ __launch_bounds__(AB) void k_cgs_pass3(int64_t N, int m, int j, const VT *__restrict__ Vall,
                                                   double2 *__restrict__ Wall, const double2 *__restrict__ P2all,
                                                   double *__restrict__ PNall, double2 *__restrict__ Hall,
                                                   const ColStat *__restrict__ st)
 {
     const int r = blockIdx.y;
     if (st[r].done || !st[r].reorth) return;
-    const int nb = gridDim.x;
+    const int nc = int((N + AB - 1) / AB);
     __shared__ double2 h[MAXM + 1];
-    sum_partials(P2all + int64_t(r) * nb * (m + 1), nb, m + 1, j, h);
+    sum_partials(P2all + int64_t(r) * nc * (m + 1), nc, m + 1, j, h);
     __syncthreads();
     if (blockIdx.x == 0)
         for (int k = threadIdx.x; k <= j; k += AB) {
@@ -345,19 +415,33 @@ __global__ __launch_bounds__(AB) void k_cgs_pass3(int64_t N, int m, int j, const
             const double2 a = *hc;
             *hc = make_double2(a.x + h[k].x, a.y + h[k].y);
         }
-    const int64_t e = int64_t(blockIdx.x) * AB + threadIdx.x;
-    double nn = 0.0;
-    if (e < N) {
-        const double2 *V = Vall + int64_t(r) * (m + 1) * N;
-        const double2 w = cgs_update(V, N, e, j, Wall[int64_t(r) * N + e], h);
-        Wall[int64_t(r) * N + e] = w;
-        nn = w.x * w.x + w.y * w.y;
+    const VT *V = Vall + int64_t(r) * (m + 1) * N;
+    __shared__ double red[EPT][AB / 64];
+    int64_t e[EPT];
+    double2 w[EPT];
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+        e[q] = elem<EPT>(q);
+        w[q] = e[q] < N ? Wall[int64_t(r) * N + e[q]] : make_double2(0.0, 0.0);
     }
-    __shared__ double red[AB / 64];
-    nn = wsum(nn);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nn;
+    cgs_update<VT, EPT>(V, N, e, j, w, h);
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+        double nn = 0.0;
+        if (e[q] < N) {
+            Wall[int64_t(r) * N + e[q]] = w[q];
+            nn = w[q].x * w[q].x + w[q].y * w[q].y;
+        }
+        nn = wsum(nn);
+        if ((threadIdx.x & 63) == 0) red[q][threadIdx.x >> 6] = nn;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) PNall[int64_t(r) * nb + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+            const int c = int(blockIdx.x) * EPT + q;
+            if (c < nc) PNall[int64_t(r) * nc + c] = red[q][0] + red[q][1] + red[q][2] + red[q][3];
+        }
 }
 
 // Givens rotation [c s; -conj(s) c], c real, mapping (a, b) to (rho, 0).
@@ -372,7 +456,8 @@ __device__ inline void givens(double2 a, double2 b, double &c, double2 &s)
     s = make_double2((ph.x * b.x + ph.y * b.y) / t, (ph.y * b.x - ph.x * b.y) / t);   // (a/|a|) conj(b) / t
 }
 
-__global__ __launch_bounds__(AB) void k_cgs_finish(int64_t N, int m, int j, double tol, double2 *__restrict__ Vall,
+template <typename VT, int EPT>
+__global__ __launch_bounds__(AB) void k_cgs_finish(int64_t N, int m, int j, double tol, VT *__restrict__ Vall,
                                                    const double2 *__restrict__ Wall, const double *__restrict__ PNall,
                                                    const double *__restrict__ PWall, double2 *__restrict__ Hall,
                                                    double *__restrict__ csall, double2 *__restrict__ snall,
@@ -380,13 +465,13 @@ __global__ __launch_bounds__(AB) void k_cgs_finish(int64_t N, int m, int j, doub
 {
     const int r = blockIdx.y;
     if (st[r].done) return;
-    const int nb = gridDim.x;
+    const int nc = int((N + AB - 1) / AB);
     __shared__ double s_hn, s_w2;
     __shared__ double2 Hc[MAXM + 2], sn[MAXM];
     __shared__ double cs[MAXM];
     if (threadIdx.x < 64) {
-        const double a = sum_real_partials(PNall + int64_t(r) * nb, nb);
-        const double b = sum_real_partials(PWall + int64_t(r) * nb, nb);
+        const double a = sum_real_partials(PNall + int64_t(r) * nc, nc);
+        const double b = sum_real_partials(PWall + int64_t(r) * nc, nc);
         if (threadIdx.x == 0) { s_hn = sqrt(a); s_w2 = b; }
     }
     if (blockIdx.x == 0) {
@@ -398,11 +483,16 @@ __global__ __launch_bounds__(AB) void k_cgs_finish(int64_t N, int m, int j, doub
     }
     __syncthreads();
     const double hn = s_hn;
-    const int64_t e = int64_t(blockIdx.x) * AB + threadIdx.x;
-    if (e < N && hn > 0.0) {
+    if (hn > 0.0) {
         const double inv = 1.0 / hn;
-        const double2 w = Wall[int64_t(r) * N + e];
-        Vall[(int64_t(r) * (m + 1) + j + 1) * N + e] = make_double2(w.x * inv, w.y * inv);
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+            const int64_t e = elem<EPT>(q);
+            if (e < N) {
+                const double2 w = Wall[int64_t(r) * N + e];
+                Vall[(int64_t(r) * (m + 1) + j + 1) * N + e] = st2<VT>(make_double2(w.x * inv, w.y * inv));
+            }
+        }
     }
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
     ColStat &S = st[r];
@@ -473,7 +563,8 @@ __global__ __launch_bounds__(64) void k_lsq(int m, const double2 *__restrict__ H
 }
 
 // x += V_{0..jend-1} y
-__global__ __launch_bounds__(BT) void k_xupd(int64_t N, int m, const double2 *__restrict__ Vall,
+template <typename VT>
+__global__ __launch_bounds__(BT) void k_xupd(int64_t N, int m, const VT *__restrict__ Vall,
                                              const double2 *__restrict__ yall, double2 *__restrict__ X,
                                              const ColStat *__restrict__ st)
 {
@@ -483,11 +574,11 @@ __global__ __launch_bounds__(BT) void k_xupd(int64_t N, int m, const double2 *__
     __shared__ double2 sy[MAXM];
     if (threadIdx.x < je) sy[threadIdx.x] = yall[int64_t(r) * m + threadIdx.x];
     __syncthreads();
-    const double2 *V = Vall + int64_t(r) * (m + 1) * N;
+    const VT *V = Vall + int64_t(r) * (m + 1) * N;
     for (int64_t e = int64_t(blockIdx.x) * BT + threadIdx.x; e < N; e += int64_t(gridDim.x) * BT) {
         double2 x = X[int64_t(r) * N + e];
         for (int k = 0; k < je; ++k) {
-            const double2 p = cmul(V[int64_t(k) * N + e], sy[k]);
+            const double2 p = cmul(ld2(V[int64_t(k) * N + e]), sy[k]);
             x.x += p.x;
             x.y += p.y;
         }
@@ -523,18 +614,19 @@ __global__ __launch_bounds__(BT) void k_norm(int64_t N, const double2 *__restric
 }
 
 // Start a cycle from the residual: v0 = res/||res||, g = (||res||, 0, ...).
+template <typename VT>
 __global__ __launch_bounds__(BT) void k_restart(int64_t N, int m, const double2 *__restrict__ Res,
-                                                double2 *__restrict__ Vall, double2 *__restrict__ gall,
+                                                VT *__restrict__ Vall, double2 *__restrict__ gall,
                                                 ColStat *__restrict__ st, const int *__restrict__ mask)
 {
     const int r = blockIdx.y;
     if (!mask[r]) return;
     const double beta = st[r].rnorm;
     const double inv = 1.0 / beta;
-    double2 *v = Vall + int64_t(r) * (m + 1) * N;
+    VT *v = Vall + int64_t(r) * (m + 1) * N;
     for (int64_t e = int64_t(blockIdx.x) * BT + threadIdx.x; e < N; e += int64_t(gridDim.x) * BT) {
         const double2 w = Res[int64_t(r) * N + e];
-        v[e] = make_double2(w.x * inv, w.y * inv);
+        v[e] = st2<VT>(make_double2(w.x * inv, w.y * inv));
     }
     if (blockIdx.x == 0 && threadIdx.x <= m)
         gall[int64_t(r) * (m + 1) + threadIdx.x] = make_double2(threadIdx.x == 0 ? beta : 0.0, 0.0);
@@ -699,6 +791,31 @@ struct Workspace {
         for (void *p : all) (void)hipFree(p);
     }
 };
+
+// One Arnoldi step j for R columns after the product w = T v_j: CGS with
+// selective reorthogonalisation, normalisation and the Givens update.  One
+// element per thread: on 256 columns of 7680 unknowns this beat 2 and 4
+// elements per thread (fewer loads in flight across the chip), although those
+// add 2-4x fewer partial sums per block; the results are the same bitwise.
+template <typename VT, int EPT>
+static void arnoldi_launch(Workspace *w, VT *V, int64_t N, int m, int j, double tol, int64_t R, hipStream_t s)
+{
+    const unsigned nb = unsigned((N + AB * EPT - 1) / (AB * EPT));
+    const dim3 agrid(nb, unsigned(R));
+    const dim3 pgrid(nb, unsigned((m + 1 + KG - 1) / KG), unsigned(R));
+    hipLaunchKernelGGL((k_cgs_pass1<VT, EPT>), pgrid, dim3(AB), 0, s, N, m, j, V, w->W, w->P1, w->PW, w->st);
+    hipLaunchKernelGGL((k_cgs_pass2<VT, EPT>), agrid, dim3(AB), 0, s, N, m, j, V, w->W, w->P1, w->PW, w->P2, w->PN,
+                       w->H, w->st);
+    hipLaunchKernelGGL((k_cgs_pass3<VT, EPT>), agrid, dim3(AB), 0, s, N, m, j, V, w->W, w->P2, w->PN, w->H, w->st);
+    hipLaunchKernelGGL((k_cgs_finish<VT, EPT>), agrid, dim3(AB), 0, s, N, m, j, tol, V, w->W, w->PN, w->PW, w->H,
+                       w->cs, w->sn, w->g, w->st);
+    BIE_HIP(hipGetLastError());
+}
+template <typename VT>
+static void arnoldi_step(Workspace *w, VT *V, int64_t N, int m, int j, double tol, int64_t R, hipStream_t s)
+{
+    arnoldi_launch<VT, 1>(w, V, N, m, j, tol, R, s);
+}
 
 static constexpr int MAX_RSCC_ROWS = 4096;
 
@@ -923,28 +1040,19 @@ static int solve_impl(const bie_op *opc, const void *Bv, void *Xv, int64_t R, co
             }
             push_st();
             push_skip(need);
-            hipLaunchKernelGGL(k_restart, egrid, dim3(BT), 0, s, N, m, w->Res, w->V, w->g, w->st, (const int *)dskip);
+            hipLaunchKernelGGL(k_restart<double2>, egrid, dim3(BT), 0, s, N, m, w->Res, w->V, w->g, w->st, (const int *)dskip);
             BIE_HIP(hipGetLastError());
             int jmax = 0;
             for (int64_t r = 0; r < R; ++r)
                 if (active[r]) jmax = std::max(jmax, st[r].jcap);
-            const dim3 agrid(unsigned((N + AB - 1) / AB), unsigned(R));
-            const dim3 pgrid(unsigned((N + AB - 1) / AB), unsigned((m + 1 + KG - 1) / KG), unsigned(R));
             for (int j = 0; j < jmax; ++j) {
                 product(op, fp64, true, w->V + int64_t(j) * N, int64_t(m + 1) * N, w->W, N, nullptr, 0, R,
                         done_flags, done_stride, false, s);
-                hipLaunchKernelGGL(k_cgs_pass1, pgrid, dim3(AB), 0, s, N, m, j, w->V, w->W, w->P1, w->PW, w->st);
-                hipLaunchKernelGGL(k_cgs_pass2, agrid, dim3(AB), 0, s, N, m, j, w->V, w->W, w->P1, w->PW, w->P2,
-                                   w->PN, w->H, w->st);
-                hipLaunchKernelGGL(k_cgs_pass3, agrid, dim3(AB), 0, s, N, m, j, w->V, w->W, w->P2, w->PN, w->H,
-                                   w->st);
-                hipLaunchKernelGGL(k_cgs_finish, agrid, dim3(AB), 0, s, N, m, j, o.tol, w->V, w->W, w->PN, w->PW,
-                                   w->H, w->cs, w->sn, w->g, w->st);
-                BIE_HIP(hipGetLastError());
+                arnoldi_step<double2>(w, w->V, N, m, j, o.tol, R, s);
             }
             hipLaunchKernelGGL(k_lsq, dim3(unsigned(R)), dim3(64), size_t(m) * m * sizeof(double2), s, m, w->H, w->g,
                                w->y, w->st);
-            hipLaunchKernelGGL(k_xupd, egrid, dim3(BT), 0, s, N, m, w->V, w->y, X, w->st);
+            hipLaunchKernelGGL(k_xupd<double2>, egrid, dim3(BT), 0, s, N, m, w->V, w->y, X, w->st);
             BIE_HIP(hipGetLastError());
             pull_st();
             std::vector<int> cand(R, 0);
@@ -1108,91 +1216,259 @@ __global__ void k_colnorm_fin(int nb, const double *__restrict__ part, double *_
     if (threadIdx.x == 0) out[r] = sqrt(a);
 }
 
-struct IRBuf {
-    double2 *res = nullptr, *d = nullptr;
-    double *part = nullptr, *nrm = nullptr;
-    ~IRBuf()
+struct DevBufs {
+    std::vector<void *> all;
+    template <typename T>
+    T *get(size_t n)
     {
-        for (void *p : { (void *)res, (void *)d, (void *)part, (void *)nrm })
-            if (p) (void)hipFree(p);
+        void *p = nullptr;
+        BIE_HIP(hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T)));
+        all.push_back(p);
+        return static_cast<T *>(p);
+    }
+    ~DevBufs()
+    {
+        for (void *p : all) (void)hipFree(p);
     }
 };
 
+// phases of a slot of the refinement engine
+enum { SL_EMPTY = 0, SL_CHECK = 1, SL_FROM_B = 2, SL_NEW = 3, SL_CONT = 4 };
+constexpr int MAX_CHECKS = 100;   // outer refinement steps per right-hand side
+
 }  // namespace
 
-// Mixed precision with iterative refinement: the outer residual b - T x uses
-// the FP64 matrix and decides convergence (standard criterion in FP64); each
-// correction solves T_32 d = r with GMRES on the FP32-rounded matrix (FP64
-// vectors and accumulation) to a relative tolerance inner_tol; x += d.
-static int solve_mixed(const bie_op *op, const void *Bv, void *Xv, int64_t R, const bie_solve_opts &o,
-                       bie_solve_stat *stats, hipStream_t s)
+// Mixed precision with iterative refinement, as a continuous batch.
+//
+// Each right-hand side is refined as x <- x + d, where the outer residual
+// r = b - T x uses the FP64 matrix and decides convergence (standard criterion
+// in FP64) and the correction solves T_low d = r with GMRES(m) to a relative
+// tolerance inner_tol on the low-precision matrix: the split-BF16 block
+// product on the matrix cores (Krylov basis stored in complex64, FP64
+// arithmetic) or the FP32 packed matrix (FP64 vectors).
+//
+// W = slots right-hand sides are in flight (all R when slots = 0).  The host
+// loop alternates (1) FP64 checks of every slot whose correction has finished,
+// one product launch over those slots; a converged slot writes its solution
+// out and takes the next right-hand side; (2) one GMRES cycle (<= m
+// iterations) over every slot inside a correction, with one product launch per
+// iteration over exactly those slots.  A slot therefore never waits for the
+// slowest right-hand side of a block: throughput follows the mean number of
+// iterations, which is what a warm start reduces.
+template <typename VT>
+static int solve_stream(const bie_op *opc, const void *Bv, void *Xv, int64_t R, const bie_solve_opts &o,
+                        bie_solve_stat *stats, hipStream_t s, int low)
 {
-    if (!op->Z64 || !(op->Z32 || op->Abf))
-        throw Error(BIE_EINVAL, "mixed precision needs the FP64 matrix and a low-precision copy "
-                                "(storage BIE_C64 with keep_fp64, or BIE_SPLIT_BF16)");
+    bie_op *op = const_cast<bie_op *>(opc);
     if (o.method != BIE_GMRES) throw Error(BIE_EINVAL, "mixed precision uses GMRES");
     const int64_t N = op->mesh.N;
+    const int m = o.restart;
+    const int64_t W = o.slots > 0 ? std::min<int64_t>(o.slots, R) : R;
+    Workspace *w = get_ws(op, W, m);
     const double2 *B = static_cast<const double2 *>(Bv);
     double2 *X = static_cast<double2 *>(Xv);
-    IRBuf b;
+    VT *V = reinterpret_cast<VT *>(w->V);
+    const double itol = o.inner_tol > 0.0 ? o.inner_tol : 1e-3;
     const unsigned nb = unsigned((N + BE - 1) / BE);
-    BIE_HIP(hipMalloc(&b.res, size_t(R) * N * sizeof(double2)));
-    BIE_HIP(hipMalloc(&b.d, size_t(R) * N * sizeof(double2)));
-    BIE_HIP(hipMalloc(&b.part, size_t(R) * nb * sizeof(double)));
-    BIE_HIP(hipMalloc(&b.nrm, size_t(R) * sizeof(double)));
-    auto norms = [&](const double2 *v, std::vector<double> &out) {
-        hipLaunchKernelGGL(k_colnorm_part, dim3(nb, unsigned(R)), dim3(BT), 0, s, N, v, b.part);
-        hipLaunchKernelGGL(k_colnorm_fin, dim3(unsigned(R)), dim3(64), 0, s, int(nb), b.part, b.nrm);
+
+    DevBufs db;
+    double2 *Bs = db.get<double2>(size_t(W) * N);   // slot right-hand sides
+    double2 *Xs = db.get<double2>(size_t(W) * N);   // slot solutions
+    double2 *Rs = db.get<double2>(size_t(W) * N);   // outer residuals (right-hand sides of the corrections)
+    double2 *Ds = db.get<double2>(size_t(W) * N);   // corrections
+    double *part = db.get<double>(size_t(std::max(R, W)) * nb);
+    double *nrm = db.get<double>(size_t(std::max(R, W)));
+    int *dcols = db.get<int>(size_t(2 * W));
+    int *dskip = w->mask;
+
+    auto colnorms = [&](const double2 *v, int64_t cnt, std::vector<double> &out) {
+        hipLaunchKernelGGL(k_colnorm_part, dim3(nb, unsigned(cnt)), dim3(BT), 0, s, N, v, part);
+        hipLaunchKernelGGL(k_colnorm_fin, dim3(unsigned(cnt)), dim3(64), 0, s, int(nb), part, nrm);
         BIE_HIP(hipGetLastError());
-        out.resize(R);
-        BIE_HIP(hipMemcpyAsync(out.data(), b.nrm, R * sizeof(double), hipMemcpyDeviceToHost, s));
+        out.resize(cnt);
+        BIE_HIP(hipMemcpyAsync(out.data(), nrm, cnt * sizeof(double), hipMemcpyDeviceToHost, s));
         BIE_HIP(hipStreamSynchronize(s));
     };
-    std::vector<double> bn, rn;
-    norms(B, bn);
-    if (!o.use_x0) hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, s, R * N, X);
+    auto copy = [&](const double2 *a, double2 *b) { hipLaunchKernelGGL(k_copy, dim3(64), dim3(256), 0, s, N, a, b); };
+
+    std::vector<double> bn;
+    colnorms(B, R, bn);
     std::vector<bie_solve_stat> hs(R, bie_solve_stat{ 0, 0, NAN, NAN, 0, 0 });
-    std::vector<int> active(R, 1);
-    const double itol = o.inner_tol > 0.0 ? o.inner_tol : 1e-3;
-    bie_solve_opts io = o;
-    io.use_x0 = 0;
-    io.crit = BIE_SCC;
-    std::vector<bie_solve_stat> ist(R);
-    for (int outer = 0; outer < 100; ++outer) {
-        product(op, MAT64, true, X, N, b.res, N, B, N, R, nullptr, 1, false, s);   // r = b - T64 x
-        norms(b.res, rn);
-        bool any = false;
-        for (int64_t r = 0; r < R; ++r) {
-            if (!active[r]) continue;
-            hs[r].mvps += 1;
-            hs[r].checks += 1;
-            hs[r].relres_true = bn[r] > 0.0 ? rn[r] / bn[r] : 0.0;
-            if (bn[r] == 0.0 || hs[r].relres_true <= o.tol) {
-                active[r] = 0;
-                hs[r].converged = 1;
-            } else if (hs[r].mvps >= o.max_mvp) {
-                active[r] = 0;
-            } else {
-                any = true;
+    std::vector<int64_t> rhs(W, -1);
+    std::vector<int> phase(W, SL_EMPTY), skip(W, 1), colsh(2 * W, 0);
+    std::vector<double> rin(W, 0.0), rn;
+    std::vector<ColStat> st(W);
+    int64_t next = 0;
+
+    auto load = [&](int64_t sl) {
+        if (next >= R) {
+            rhs[sl] = -1;
+            phase[sl] = SL_EMPTY;
+            return;
+        }
+        const int64_t r = next++;
+        rhs[sl] = r;
+        copy(B + r * N, Bs + sl * N);
+        if (o.use_x0) {
+            copy(X + r * N, Xs + sl * N);
+            phase[sl] = SL_CHECK;
+        } else {
+            hipLaunchKernelGGL(k_zero, dim3(64), dim3(256), 0, s, N, Xs + sl * N);
+            phase[sl] = SL_FROM_B;
+        }
+    };
+    auto retire = [&](int64_t sl, bool converged) {
+        const int64_t r = rhs[sl];
+        hs[r].converged = converged;
+        copy(Xs + sl * N, X + r * N);
+        load(sl);
+    };
+    // product with the low-precision matrix for the slots listed in colsh[c0 ..
+    // c0 + n) (device copy at dcols + c0); packed FP32: skip array instead
+    // (Xp complex64 when xf32; the packed FP32 product takes complex128 only)
+    auto low_product = [&](const void *Xp, bool xf32, int64_t ldx, double2 *Y, const double2 *Bsub, int c0, int n,
+                           const int *pskip, int64_t sks) {
+        if (low == MATBF16) gemm_product(op, Xp, ldx, xf32, Y, N, Bsub, N, n, dcols + c0, s);
+        else product(op, MAT32, true, Xp, ldx, Y, N, Bsub, N, W, pskip, sks, false, s);
+    };
+    auto push_st = [&]() { BIE_HIP(hipMemcpyAsync(w->st, st.data(), W * sizeof(ColStat), hipMemcpyHostToDevice, s)); };
+    auto pull_st = [&]() {
+        BIE_HIP(hipMemcpyAsync(st.data(), w->st, W * sizeof(ColStat), hipMemcpyDeviceToHost, s));
+        BIE_HIP(hipStreamSynchronize(s));
+    };
+    const int *done_flags = &w->st[0].done;
+    const int64_t done_stride = sizeof(ColStat) / sizeof(int);
+    const int field_rnorm = offsetof(ColStat, rnorm) / sizeof(double);
+    const dim3 vgrid(w->nblk, unsigned(W));
+    const dim3 egrid(unsigned(std::min<int64_t>((N + BT - 1) / BT, 1024)), unsigned(W));
+
+    for (int64_t sl = 0; sl < W; ++sl) load(sl);
+    while (true) {
+        // (1) settle: zero right-hand sides, starts from b, FP64 checks.  Each
+        // pass retires (consuming a right-hand side) or advances every slot it
+        // looks at, so the loop ends.
+        while (true) {
+            bool changed = false;
+            for (int64_t sl = 0; sl < W; ++sl) {
+                if (phase[sl] != SL_FROM_B) continue;
+                const int64_t r = rhs[sl];
+                changed = true;
+                if (bn[r] == 0.0) {
+                    hs[r].relres_est = hs[r].relres_true = 0.0;
+                    retire(sl, true);
+                    continue;
+                }
+                copy(Bs + sl * N, Rs + sl * N);
+                rin[sl] = bn[r];
+                hs[r].relres_true = 1.0;
+                phase[sl] = SL_NEW;
+            }
+            bool anychk = false;
+            for (int64_t sl = 0; sl < W; ++sl) {
+                skip[sl] = phase[sl] == SL_CHECK ? 0 : 1;
+                anychk = anychk || !skip[sl];
+            }
+            if (!anychk) {
+                if (changed) continue;
+                break;
+            }
+            BIE_HIP(hipMemcpyAsync(dskip, skip.data(), W * sizeof(int), hipMemcpyHostToDevice, s));
+            product(op, MAT64, true, Xs, N, Rs, N, Bs, N, W, dskip, 1, false, s);   // r = b - T64 x
+            colnorms(Rs, W, rn);
+            for (int64_t sl = 0; sl < W; ++sl) {
+                if (skip[sl]) continue;
+                const int64_t r = rhs[sl];
+                hs[r].mvps += 1;
+                hs[r].checks += 1;
+                const double rel = bn[r] > 0.0 ? rn[sl] / bn[r] : 0.0;
+                hs[r].relres_true = rel;
+                if (bn[r] == 0.0 || rel <= o.tol) retire(sl, true);
+                else if (hs[r].mvps >= o.max_mvp || hs[r].checks >= MAX_CHECKS) retire(sl, false);
+                else {
+                    rin[sl] = rn[sl];
+                    phase[sl] = SL_NEW;
+                }
             }
         }
-        if (!any) break;
-        for (int64_t r = 0; r < R; ++r)
-            if (!active[r]) hipLaunchKernelGGL(k_zero, dim3(64), dim3(256), 0, s, N, b.res + r * N);
-        // correction on the FP32 matrix: tolerance relative to ||r|| (inner mode)
-        int64_t budget = o.max_mvp;
-        for (int64_t r = 0; r < R; ++r)
-            if (active[r]) budget = std::min<int64_t>(budget, o.max_mvp - hs[r].mvps);
-        io.tol = itol;
-        io.max_mvp = std::max<int64_t>(1, budget);
-        solve_impl(op, b.res, b.d, R, io, ist.data(), s, op->Abf ? MATBF16 : MAT32, true);
-        for (int64_t r = 0; r < R; ++r)
-            if (active[r]) {
-                hs[r].iters += ist[r].iters;
-                hs[r].mvps += ist[r].mvps;
-                hs[r].relres_est = ist[r].relres_est * (bn[r] > 0.0 ? rn[r] / bn[r] : 0.0);
+        // (2) one GMRES cycle over the slots inside a correction
+        int nin = 0, ncont = 0;
+        for (int64_t sl = 0; sl < W; ++sl)
+            if (phase[sl] == SL_NEW || phase[sl] == SL_CONT) colsh[nin++] = int(sl);
+        if (nin == 0) break;   // every slot empty: all right-hand sides retired
+        for (int64_t sl = 0; sl < W; ++sl)
+            if (phase[sl] == SL_CONT) colsh[W + ncont++] = int(sl);
+        BIE_HIP(hipMemcpyAsync(dcols, colsh.data(), 2 * W * sizeof(int), hipMemcpyHostToDevice, s));
+        for (int64_t sl = 0; sl < W; ++sl) {
+            const bool in = phase[sl] == SL_NEW || phase[sl] == SL_CONT;
+            st[sl] = ColStat{};
+            st[sl].bnorm = rin[sl];
+            st[sl].rnorm = rin[sl];
+            st[sl].active = in;
+            st[sl].done = in ? 0 : 1;
+            st[sl].jcap = in ? int(std::min<int64_t>(m, std::max<int64_t>(1, o.max_mvp - hs[rhs[sl]].mvps))) : 0;
+            skip[sl] = phase[sl] == SL_CONT ? 0 : 1;
+            if (phase[sl] == SL_NEW) {
+                hipLaunchKernelGGL(k_zero, dim3(64), dim3(256), 0, s, N, Ds + sl * N);
+                copy(Rs + sl * N, w->Res + sl * N);
             }
-        hipLaunchKernelGGL(k_axpy_cols, dim3(2048), dim3(256), 0, s, R * N, b.d, X);
+        }
+        push_st();
+        if (ncont > 0) {   // inner residual r - T_low d of the continuing corrections
+            BIE_HIP(hipMemcpyAsync(dskip, skip.data(), W * sizeof(int), hipMemcpyHostToDevice, s));
+            low_product(Ds, false, N, w->Res, Rs, int(W), ncont, dskip, 1);
+            std::vector<int> need(W);
+            for (int64_t sl = 0; sl < W; ++sl) need[sl] = 1 - skip[sl];
+            BIE_HIP(hipMemcpyAsync(dskip, need.data(), W * sizeof(int), hipMemcpyHostToDevice, s));
+            hipLaunchKernelGGL(k_norm, vgrid, dim3(BT), 0, s, N, w->Res, N, w->dpart, w->counters, w->st,
+                               field_rnorm, (const int *)dskip);
+            BIE_HIP(hipGetLastError());
+            pull_st();
+            bool exact = false;
+            for (int64_t sl = 0; sl < W; ++sl)
+                if (phase[sl] == SL_CONT) {
+                    hs[rhs[sl]].mvps += 1;
+                    if (st[sl].rnorm == 0.0) {   // correction solves the system exactly: skip the cycle
+                        st[sl].done = 1;
+                        st[sl].active = 0;
+                        exact = true;
+                    }
+                }
+            if (exact) push_st();
+        }
+        std::vector<int> act(W);
+        int jmax = 0;
+        for (int64_t sl = 0; sl < W; ++sl) {
+            act[sl] = st[sl].active;
+            if (act[sl]) jmax = std::max(jmax, st[sl].jcap);
+        }
+        BIE_HIP(hipMemcpyAsync(dskip, act.data(), W * sizeof(int), hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_restart<VT>, egrid, dim3(BT), 0, s, N, m, w->Res, V, w->g, w->st, (const int *)dskip);
+        BIE_HIP(hipGetLastError());
+        for (int j = 0; j < jmax; ++j) {
+            low_product(V + int64_t(j) * N, sizeof(VT) == 8, int64_t(m + 1) * N, w->W, nullptr, 0, nin, done_flags,
+                        done_stride);
+            arnoldi_step<VT>(w, V, N, m, j, itol, W, s);
+        }
+        hipLaunchKernelGGL(k_lsq, dim3(unsigned(W)), dim3(64), size_t(m) * m * sizeof(double2), s, m, w->H, w->g,
+                           w->y, w->st);
+        hipLaunchKernelGGL(k_xupd<VT>, egrid, dim3(BT), 0, s, N, m, V, w->y, Ds, w->st);
+        BIE_HIP(hipGetLastError());
+        pull_st();
+        for (int64_t sl = 0; sl < W; ++sl) {
+            if (phase[sl] != SL_NEW && phase[sl] != SL_CONT) continue;
+            const int64_t r = rhs[sl];
+            if (act[sl]) {
+                hs[r].iters += st[sl].jend;
+                hs[r].mvps += st[sl].jend;
+                hs[r].relres_est = st[sl].est * rin[sl] / bn[r];
+            }
+            if (!act[sl] || st[sl].est <= itol || st[sl].brk || hs[r].mvps >= o.max_mvp) {
+                hipLaunchKernelGGL(k_axpy_cols, dim3(64), dim3(256), 0, s, N, Ds + sl * N, Xs + sl * N);
+                phase[sl] = SL_CHECK;
+            } else {
+                phase[sl] = SL_CONT;
+            }
+        }
         BIE_HIP(hipGetLastError());
     }
     BIE_HIP(hipStreamSynchronize(s));
@@ -1207,7 +1483,13 @@ static int solve_mixed(const bie_op *op, const void *Bv, void *Xv, int64_t R, co
 int solve(const bie_op *op, const void *B, void *X, int64_t R, const bie_solve_opts &o, bie_solve_stat *stats,
           hipStream_t s)
 {
-    if (o.precision == 1) return solve_mixed(op, B, X, R, o, stats, s);
+    if (o.precision == 1) {
+        if (!op->Z64 || !(op->Z32 || op->Abf))
+            throw Error(BIE_EINVAL, "mixed precision needs the FP64 matrix and a low-precision copy "
+                                    "(storage BIE_C64 with keep_fp64, or BIE_SPLIT_BF16)");
+        if (op->Abf) return solve_stream<float2>(op, B, X, R, o, stats, s, MATBF16);
+        return solve_stream<double2>(op, B, X, R, o, stats, s, MAT32);
+    }
     if (!op->Z64 && o.crit == BIE_RSCC) throw Error(BIE_EINVAL, "the random-sampling criterion needs the FP64 matrix");
     return solve_impl(op, B, X, R, o, stats, s, op->Z64 ? MAT64 : MAT32, false);
 }

@@ -179,10 +179,15 @@ def test_rscc_criterion(bie):
     assert krylov.scc(Zo, b, x) < 5e-6
 
 
-def test_multi_rhs_equals_single(bie):
+@pytest.mark.parametrize("nrhs", [5, 20])
+def test_multi_rhs_equals_single(bie, nrhs):
+    """Columns solved together equal their single solves bitwise."""
     V, T, rwg, Zo = case(2, 2.0)
     op = bie.Operator(V, T, 2.0)
     inc = np.array([[0, 0, 1.0], [0.3, 0.1, 0.9], [1.0, 0, 0], [0, -1.0, 0], [0.5, 0.5, 0.5]])
+    if nrhs > len(inc):
+        from paper_2606_13482_amd.inputs import random_directions
+        inc = np.concatenate([inc, random_directions(nrhs - len(inc), 12)])
     d, e = planewave_set(inc, "theta")
     B = op.rhs(d, e)
     X, st = op.solve(B, bie.Solve(restart=30, tol=1e-8))
@@ -303,3 +308,60 @@ def test_mixed_refinement_split_bf16_block(bie):
     _say("  block mixed: max residual", res.max(), "outer checks", max(s["checks"] for s in st))
     assert all(s["converged"] for s in st)
     assert res.max() <= 1e-6 * (1 + 1e-6)
+
+
+@pytest.mark.parametrize("storage", ["split_bf16", "c64"])
+def test_continuous_batch_bitwise(bie, storage):
+    """The refinement engine keeps a fixed number of right-hand sides in flight and
+    hands the slot of a converged one to the next.  Every column is computed on its
+    own (block product columns, Arnoldi, FP64 residual), so each solution is bitwise
+    the same whatever the number of slots, including one right-hand side alone."""
+    V, T, rwg, Zo = case(3, 6.0)
+    op = bie.Operator(V, T, 6.0, storage=storage, keep_fp64=(storage == "c64"))
+    from paper_2606_13482_amd.inputs import random_directions
+    inc = random_directions(19, 8)
+    d, e = planewave_set(inc, "phi")
+    B = op.rhs(d, e)
+    base = bie.Solve(restart=20, tol=1e-6, precision="mixed", inner_tol=1e-2)
+    X0, st0 = op.solve(B, base)
+    for slots in (3, 4, 17, 64):
+        Xs, sts = op.solve(B, bie.Solve(**{**base.__dict__, "slots": slots}))
+        assert torch.equal(Xs, X0), slots
+        assert [s["iters"] for s in sts] == [s["iters"] for s in st0]
+    X1, st1 = op.solve(B[5:6], base)
+    assert torch.equal(X1[0], X0[5])
+    Bn = B.cpu().numpy(); Xn = X0.cpu().numpy()
+    res = np.linalg.norm(Bn - Xn @ Zo.T, axis=1) / np.linalg.norm(Bn, axis=1)
+    _say(f"  {storage}: max residual {res.max():.2e}, iterations {[s['iters'] for s in st0]}")
+    assert all(s["converged"] for s in st0)
+    assert res.max() <= 1e-6 * (1 + 1e-6)
+    for r in range(len(st0)):
+        assert abs(res[r] - st0[r]["relres_true"]) <= 1e-9
+
+
+def test_continuous_batch_warm_and_zero_rhs(bie):
+    """Initial guesses of mixed quality (exact, perturbed, zero) and a zero right-hand
+    side in one continuous batch with fewer slots than right-hand sides."""
+    V, T, rwg, Zo = case(3, 6.0)
+    op = bie.Operator(V, T, 6.0, storage="split_bf16")
+    from paper_2606_13482_amd.inputs import random_directions
+    inc = random_directions(6, 9)
+    d, e = planewave_set(inc, "theta")
+    B = op.rhs(d, e)
+    B[2] = 0
+    Bn = B.cpu().numpy()
+    xs = np.array([krylov.lu_solve(Zo, b) if np.any(b) else np.zeros_like(b) for b in Bn])
+    x0 = xs.copy()
+    x0[1] *= 1.0 + 1e-3
+    x0[3] = 0
+    x0[4] = complex_gaussian(op.N, 4)
+    X, st = op.solve(B, bie.Solve(restart=20, tol=1e-6, precision="mixed", inner_tol=1e-2, slots=2),
+                     x0=torch.from_numpy(x0).cuda())
+    Xn = X.cpu().numpy()
+    assert all(s["converged"] for s in st)
+    assert np.all(Xn[2] == 0) and st[2]["iters"] == 0
+    assert st[0]["iters"] == 0 and st[0]["checks"] == 1       # exact guess: one FP64 check
+    res = np.linalg.norm(Bn - Xn @ Zo.T, axis=1) / np.maximum(np.linalg.norm(Bn, axis=1), 1e-300)
+    res[2] = 0.0
+    assert res.max() <= 1e-6 * (1 + 1e-6)
+    assert st[1]["iters"] < st[3]["iters"]                     # a near guess saves iterations
