@@ -1,25 +1,32 @@
 """Benchmark: plane-wave EFIE solves per second on one MI355X.
 
-Workload (default): PEC sphere of radius 1 m, 5120-triangle icosphere
-(7680 RWG unknowns), k = 10 rad/m, one x-polarised plane wave arriving from
-+z, complex FP64 matrix, unpreconditioned GMRES(50) to a relative residual of
-1e-6 under the standard criterion.  One step is the whole path: mesh -> RWG
-table and pair list -> FP64 fill (regular + singular pairs) -> excitation ->
-GMRES with the criterion on the true residual.  value = solves per second of
-such steps (1 right-hand side per step).
+Headline (value): batched mixed precision + learned warm start on the PEC
+sphere of radius 1 m, 5120-triangle icosphere (7680 RWG unknowns), k = 10
+rad/m.  One step serves a batch of 512 held-out plane waves (256 directions
+uniform on the sphere x theta/phi polarisation) with the operator and the
+warm start resident: RHS assembly, warm-start inference (POD basis + MLP, with
+the zero fallback), and GMRES(50) with split-BF16 block products on the matrix
+cores and FP64 iterative refinement, as a continuous batch of 256 slots, to a
+true FP64 relative residual of 1e-6 for every right-hand side.
+value = right-hand sides per second over the timed steps.
 
-Also reported: the solve alone with the matrix resident, the FP32 fill, the
-dense-product kernel against the HBM roofline (HIP events around every launch
-in the timed region), and the CPU oracle on a bounded sample.
+Beside it, on the same GPU:
+  - plain FP64 GMRES(50) from zero on a sample of the same right-hand sides
+    (matrix resident) -> speedup of the headline over the plain method;
+  - the same batch without the warm start (mixed precision + batching alone);
+  - the plain FP64 whole-path step of one x-polarised plane wave from +z
+    (mesh -> fill -> RHS -> GMRES), with the packed FP64 product against the
+    HBM roofline (roofline_gemv);
+  - training of the warm start (snapshot solves, POD, MLP epochs), timed once;
+  - the CPU oracle on a bounded sample (cpu_baseline).
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--c5]
 """
 from __future__ import annotations
 
 import argparse
 import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -29,7 +36,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0       # MI355X HBM3E
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
+BF16_PEAK_TFLOPS = 2500.0    # MI355X dense BF16 MFMA
 METRIC = "GMRES solves/s to 1e-6 residual: batched mixed+learned vs plain FP64; GEMV GB/s"
 
 
@@ -43,20 +51,29 @@ def parse():
     ap.add_argument("--k", type=float, default=10.0)
     ap.add_argument("--restart", type=int, default=50)
     ap.add_argument("--tol", type=float, default=1e-6)
-    ap.add_argument("--no-mixed", dest="mixed", action="store_false", help="skip the mixed-precision leg")
-    ap.add_argument("--inner-tol", type=float, default=1e-3)
-    return ap.parse_args()
+    ap.add_argument("--inner-tol", type=float, default=1e-2)
+    ap.add_argument("--slots", type=int, default=256)
+    ap.add_argument("--train-dirs", type=int, default=512)
+    ap.add_argument("--test-dirs", type=int, default=256)
+    ap.add_argument("--epochs", type=int, default=1500)
+    ap.add_argument("--plain-sample", type=int, default=8)
+    ap.add_argument("--c5", action="store_true",
+                    help="full learned warm-start configuration: 2048 training / 512 test directions, 3000 epochs")
+    a = ap.parse_args()
+    if a.c5:
+        a.train_dirs, a.test_dirs, a.epochs = 2048, 512, 3000
+    return a
 
 
-def product_source_hash() -> str:
-    with open(os.path.join(ROOT, "paper_2606_13482_amd", "csrc", "blas.hip"), "rb") as f:
+def source_hash(name: str) -> str:
+    with open(os.path.join(ROOT, "paper_2606_13482_amd", "csrc", name), "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel_hash: str, N: int):
-    """HBM bytes per launch of the product kernel from the committed counter summary,
-    or None if absent or taken on a different version of the kernel source."""
-    path = os.path.join(ROOT, "profiles", "gemv_c128_n7680_counters.txt")
+def traffic_from_profiles(fname: str, kernel_src: str, N: int):
+    """HBM bytes per launch of a kernel from a committed counter summary, or None
+    if absent or taken on a different version of the kernel source."""
+    path = os.path.join(ROOT, "profiles", fname)
     if not os.path.exists(path):
         return None
     kv = {}
@@ -64,7 +81,7 @@ def traffic_from_profiles(kernel_hash: str, N: int):
         if "=" in line and not line.lstrip().startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_sha256_16") != kernel_hash or int(kv.get("N", -1)) != N:
+    if kv.get("kernel_source_sha256_16") != source_hash(kernel_src) or int(kv.get("N", -1)) != N:
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
@@ -72,10 +89,210 @@ def traffic_from_profiles(kernel_hash: str, N: int):
         return None
 
 
-def cpu_baseline(level: int, k: float, restart: int, mvps_gpu: float):
-    """The oracle (C fill with OpenMP + numpy GMRES) on a bounded sample of the workload:
-    the full FP64 fill and one GMRES(restart) cycle; the solve is extrapolated
-    to the number of products the GPU run needed."""
+def planewave_batch(bie, inc):
+    from paper_2606_13482_amd.inputs import planewave_set
+    d_t, e_t = planewave_set(inc, "theta")
+    d_p, e_p = planewave_set(inc, "phi")
+    dirs = np.concatenate([d_t, d_p])
+    pols = np.concatenate([e_t, e_p])
+    flags = np.concatenate([np.ones(len(inc)), -np.ones(len(inc))])
+    return dirs, pols, bie.features(dirs, flags)
+
+
+def plain_leg(args, bie, torch, V, T, k):
+    """Plain FP64 whole path for one x-polarised plane wave from +z."""
+    from paper_2606_13482_amd.inputs import planewave_set
+    d, e = planewave_set(np.array([[0.0, 0.0, 1.0]]), "theta")
+    opts = bie.Solve(restart=args.restart, tol=args.tol, max_mvp=20000)
+
+    def step():
+        op = bie.Operator(V, T, k)
+        B = op.rhs(d, e)
+        X, st = op.solve(B, opts)
+        return op, B, X, st
+
+    for _ in range(args.warmup):
+        step()[0].close()
+    torch.cuda.synchronize()
+    bie.prof_read(0)
+    bie.prof_enable(True)
+    t0 = time.perf_counter()
+    stats = []
+    for i in range(args.steps):
+        op, B, X, st = step()
+        stats.append(st[0])
+        if i != args.steps - 1:
+            op.close()
+    torch.cuda.synchronize()
+    t_steps = time.perf_counter() - t0
+    launches, gemv_ms = bie.prof_read(0)
+    bie.prof_enable(False)
+    N = op.N
+    relres = float(torch.linalg.vector_norm(B - op.apply(X)) / torch.linalg.vector_norm(B))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    op.solve(B, opts)
+    torch.cuda.synchronize()
+    t_solve = time.perf_counter() - t0
+    op.close()
+    t0 = time.perf_counter()
+    bie.Operator(V, T, k).close()
+    torch.cuda.synchronize()
+    t_fill64 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    bie.Operator(V, T, k, storage="c64").close()
+    torch.cuda.synchronize()
+    t_fill32 = time.perf_counter() - t0
+
+    avg_ms = gemv_ms / max(1, launches)
+    # Z = Z^T: a product reads each of the N(N+1)/2 distinct complex128 entries
+    # once, plus x read and y written
+    alg_bytes = N * (N + 1) // 2 * 16 + 2 * N * 16
+    achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic_from_profiles("gemv_c128_n7680_counters.txt", "blas.hip", N),
+            "kernel": "packed symmetric complex128 product (k_sym_tiles + k_sym_reduce)",
+            "alg_bytes_per_launch": alg_bytes, "avg_launch_us": round(avg_ms * 1e3, 2), "launches": launches}
+    ms_step = 1e3 * t_steps / args.steps
+    out = {"workload": f"PEC sphere, {T.shape[0]} triangles ({N} RWG), k={k:g}, 1 plane wave (x-pol, from +z), "
+                       f"FP64 fill + GMRES({args.restart}) to {args.tol:g} (SCC)",
+           "solves_per_s": round(1e3 / ms_step, 4), "ms_per_step": round(ms_step, 3),
+           "iters": int(stats[-1]["iters"]), "mvps": int(stats[-1]["mvps"]), "relres_true_fp64": relres,
+           "converged": bool(stats[-1]["converged"]), "solve_only_s": round(t_solve, 4),
+           "fill_fp64_s": round(t_fill64, 4), "fill_fp32_s": round(t_fill32, 4),
+           "gemv_share_of_step": round(gemv_ms / (t_steps * 1e3), 3)}
+    return out, roof
+
+
+def headline_leg(args, bie, torch, V, T, k):
+    from paper_2606_13482_amd.inputs import random_directions
+    sync = torch.cuda.synchronize
+    res = {}
+    t0 = time.perf_counter()
+    op = bie.Operator(V, T, k, storage="split_bf16")
+    sync()
+    res["setup_fill_split_s"] = round(time.perf_counter() - t0, 4)
+    N = op.N
+    mopts = bie.Solve(restart=args.restart, tol=args.tol, max_mvp=20000, precision="mixed",
+                      inner_tol=args.inner_tol, slots=args.slots)
+    popts = bie.Solve(restart=args.restart, tol=args.tol, max_mvp=20000)
+
+    # training: solutions the method computes, then POD + MLP on the GPU
+    dtr, ptr, ftr = planewave_batch(bie, random_directions(args.train_dirs, 5))
+    t0 = time.perf_counter()
+    Btr = op.rhs(dtr, ptr)
+    Xtr, sttr = op.solve(Btr, mopts)
+    sync()
+    t_snap = time.perf_counter() - t0
+    K = min(256, Xtr.shape[0])
+    t0 = time.perf_counter()
+    ws = bie.WarmStart.train(op, ftr, Xtr, pod_rank=K, hidden=512, epochs=args.epochs, batch=256,
+                             pols=ptr, pol_model=1)
+    sync()
+    t_train = time.perf_counter() - t0
+    res["training"] = {"snapshots": int(Xtr.shape[0]), "snapshot_solve_s": round(t_snap, 3),
+                       "snapshots_converged": float(np.mean([s["converged"] for s in sttr])),
+                       "pod_rank": K, "hidden": 512, "epochs": args.epochs, "train_s": round(t_train, 3),
+                       "final_loss": ws.final_loss, "model": "linear in the polarisation (inputs d; 3 x 2K outputs)"}
+    del Xtr, Btr
+
+    dte, pte, fte = planewave_batch(bie, random_directions(args.test_dirs, 55))
+    R = dte.shape[0]
+
+    def step():
+        B = op.rhs(dte, pte)
+        X0, used = ws.predict(fte, B, pols=pte)
+        X, st = op.solve(B, mopts, x0=X0)
+        return B, X, X0, used, st
+
+    for _ in range(args.warmup):
+        step()
+    sync()
+    bie.prof_read(0)
+    bie.prof_read(1)
+    bie.prof_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        B, X, X0, used, st = step()
+    sync()
+    t_steps = time.perf_counter() - t0
+    g_launch, g_ms, g_cols = bie.prof_read(1, columns=True)
+    p_launch, p_ms = bie.prof_read(0)
+    bie.prof_enable(False)
+    ms_step = 1e3 * t_steps / args.steps
+    conv = np.array([s["converged"] for s in st], bool)
+    relres = np.array([s["relres_true"] for s in st])
+    iters_w = np.array([s["iters"] for s in st])
+    r0 = (torch.linalg.vector_norm(B - op.apply(X0), dim=1) / torch.linalg.vector_norm(B, dim=1)).cpu().numpy()
+    # independent FP64 residual of the returned solutions
+    rchk = (torch.linalg.vector_norm(B - op.apply(X), dim=1) / torch.linalg.vector_norm(B, dim=1)).cpu().numpy()
+
+    # the same batch without the warm start
+    sync()
+    t0 = time.perf_counter()
+    Xz, stz = op.solve(B, mopts)
+    sync()
+    t_zero = time.perf_counter() - t0
+    iters_z = np.array([s["iters"] for s in stz])
+
+    # plain FP64 GMRES from zero on a sample of the batch, one right-hand side at a time
+    ns = min(args.plain_sample, R)
+    idx = np.linspace(0, R - 1, ns).round().astype(int)
+    Xp, itp = [], []
+    sync()
+    t0 = time.perf_counter()
+    for i in idx:
+        x, s = op.solve(B[i:i + 1], popts)
+        Xp.append(x)
+        itp.append((s[0]["iters"], s[0]["mvps"]))
+    sync()
+    t_plain = (time.perf_counter() - t0) / ns
+    Xp = torch.cat(Xp)
+    # a tight FP64 solution of the sample for the forward errors
+    Xt, _ = op.solve(B[idx], bie.Solve(restart=args.restart, tol=1e-10, max_mvp=40000))
+    nt = torch.linalg.vector_norm(Xt, dim=1)
+    fwd = lambda Y: float((torch.linalg.vector_norm(Y - Xt, dim=1) / nt).max())
+
+    value = R / (ms_step * 1e-3)
+    plain_rate = 1.0 / t_plain
+    res.update({
+        "rhs_per_step": R,
+        "solves_per_s": round(value, 3),
+        "converged": float(conv.mean()),
+        "relres_true_fp64_max": float(relres.max()),
+        "relres_recomputed_fp64_max": float(rchk.max()),
+        "iters_mean": float(iters_w.mean()), "iters_max": int(iters_w.max()),
+        "warm_start": {"kept": float(used.mean()), "initial_relres_median": float(np.median(r0)),
+                       "initial_relres_max": float(r0.max())},
+        "no_warm_start": {"solves_per_s": round(R / t_zero, 3), "iters_mean": float(iters_z.mean()),
+                          "iters_max": int(iters_z.max())},
+        "plain_fp64_sample": {"rhs": int(ns), "solves_per_s": round(plain_rate, 4),
+                              "iters_mean": float(np.mean([a for a, _ in itp]))},
+        "speedup_vs_plain_fp64": round(value / plain_rate, 2),
+        "speedup_no_warm_start_vs_plain_fp64": round((R / t_zero) / plain_rate, 2),
+        "forward_error_vs_tight_fp64": {"plain_fp64": fwd(Xp), "mixed_learned": fwd(X[idx]),
+                                        "mixed_zero": fwd(Xz[idx]), "reference": "FP64 GMRES to 1e-10 on the sample"},
+        "packed_fp64_share_of_step": round(p_ms / (t_steps * 1e3), 3),
+    })
+    avg = g_ms / max(1, g_launch)
+    alg_flops = 8.0 * N * N * g_cols / max(1, g_launch)   # per launch: complex product, 8 real flops per entry and column
+    achieved = alg_flops / (avg * 1e-3) / 1e12
+    roof = {"bound": "mfma", "achieved": round(achieved, 1), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / BF16_PEAK_TFLOPS, 4), "traffic": None,
+            "kernel": "split-BF16 complex block product (k_gemm_split, v_mfma_f32_32x32x16_bf16)",
+            "alg_flops_per_launch": alg_flops, "issued_tflops": round(3 * achieved, 1),
+            "avg_columns_per_launch": round(g_cols / max(1, g_launch), 1),
+            "avg_launch_us": round(avg * 1e3, 2), "launches": g_launch,
+            "gemm_share_of_step": round(g_ms / (t_steps * 1e3), 3)}
+    op.close()
+    return res, roof, ms_step, float(np.mean([b for _, b in itp])), int(ns)
+
+
+def cpu_baseline(level: int, k: float, restart: int, plain_mvps: float):
+    """The oracle (C fill with OpenMP + numpy GMRES) on a bounded sample: the full
+    FP64 fill and one GMRES(restart) cycle; a solve with the matrix resident is
+    extrapolated to the mean number of products plain FP64 GMRES needed on the GPU."""
     from oracle import cfill, efie, krylov
     from oracle.mesh import rwg_table
     from paper_2606_13482_amd.inputs import icosphere, planewave_set
@@ -90,156 +307,59 @@ def cpu_baseline(level: int, k: float, restart: int, mvps_gpu: float):
     _, st = krylov.gmres(Z, b, m=restart, tol=1e-30, max_mvp=restart)
     t_cycle = time.perf_counter() - t0
     t_mvp = t_cycle / max(1, st.mvps)
-    t_step = t_fill + mvps_gpu * t_mvp
+    t_solve = plain_mvps * t_mvp
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": 1.0 / t_step, "unit": "solves/s", "cores": threads, "kind": "oracle",
-            "sample": (f"full oracle FP64 fill of the {rwg['N']}-unknown matrix ({t_fill:.2f} s) + one "
-                       f"GMRES({restart}) cycle ({t_mvp * 1e3:.1f} ms per iteration); solve extrapolated "
-                       f"to the GPU run's {mvps_gpu:.0f} products")}
+    return {"value": round(1.0 / t_solve, 4), "unit": "solves/s", "cores": threads, "kind": "oracle",
+            "sample": (f"full oracle FP64 fill of the {rwg['N']}-unknown matrix ({t_fill:.2f} s) and one "
+                       f"GMRES({restart}) cycle ({t_mvp * 1e3:.1f} ms per iteration); a matrix-resident solve "
+                       f"extrapolated to the {plain_mvps:.0f} products plain FP64 GMRES took on the GPU sample"),
+            "fill_s": round(t_fill, 3)}
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     import torch
     from paper_2606_13482_amd import bie
-    from paper_2606_13482_amd.inputs import icosphere, planewave_set
+    from paper_2606_13482_amd.inputs import icosphere
 
+    torch.cuda.set_device(torch.device("cuda:0"))
     V, T = icosphere(args.level)
     k = args.k
-    d, e = planewave_set(np.array([[0.0, 0.0, 1.0]]), "theta")
-    opts = bie.Solve(restart=args.restart, tol=args.tol, max_mvp=20000)
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-
-    def step():
-        op = bie.Operator(V, T, k)
-        B = op.rhs(d, e)
-        X, st = op.solve(B, opts)
-        return op, B, X, st
-
-    for _ in range(args.warmup):
-        op, B, X, st = step()
-        op.close()
-    torch.cuda.synchronize()
-
-    bie.prof_read()
-    bie.prof_enable(True)
-    t0 = time.perf_counter()
-    stats = []
-    for _ in range(args.steps):
-        op, B, X, st = step()
-        stats.append(st[0])
-        if _ != args.steps - 1:
-            op.close()
-    torch.cuda.synchronize()
-    t_steps = time.perf_counter() - t0
-    launches, gemv_ms = bie.prof_read()
-    bie.prof_enable(False)
-    ms_per_step = 1e3 * t_steps / args.steps
-    N = op.N
-
-    # correctness of the last step: the true FP64 residual with the GPU matrix
-    R = B - op.apply(X)
-    relres = float(torch.linalg.vector_norm(R) / torch.linalg.vector_norm(B))
-
-    # solve alone with the matrix resident
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    X2, st2 = op.solve(B, opts)
-    torch.cuda.synchronize()
-    t_solve = time.perf_counter() - t0
-    # fill alone (FP64 and FP32)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    op64 = bie.Operator(V, T, k)
-    torch.cuda.synchronize()
-    t_fill64 = time.perf_counter() - t0
-    op64.close()
-    t0 = time.perf_counter()
-    op32 = bie.Operator(V, T, k, storage="c64")
-    torch.cuda.synchronize()
-    t_fill32 = time.perf_counter() - t0
-    op32.close()
-    op.close()
-
-    # mixed precision with iterative refinement on the same workload: FP64 fill,
-    # FP32 rounding, inner GMRES on the FP32 matrix, FP64 outer residual
-    mixed = None
-    if args.mixed:
-        mopts = bie.Solve(restart=args.restart, tol=args.tol, max_mvp=20000, precision="mixed",
-                          inner_tol=args.inner_tol)
-
-        def mstep():
-            opm = bie.Operator(V, T, k, storage="c64", keep_fp64=True)
-            Bm = opm.rhs(d, e)
-            Xm, stm = opm.solve(Bm, mopts)
-            return opm, Bm, Xm, stm
-        opm, Bm, Xm, stm = mstep()
-        opm.close()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            opm, Bm, Xm, stm = mstep()
-            if _ != args.steps - 1:
-                opm.close()
-        torch.cuda.synchronize()
-        tm = (time.perf_counter() - t0) / args.steps
-        Rm = Bm - opm.apply(Xm)    # FP64 matrix
-        t0 = time.perf_counter()
-        Xm2, stm2 = opm.solve(Bm, mopts)
-        torch.cuda.synchronize()
-        tms = time.perf_counter() - t0
-        mixed = {"solves_per_s": round(1.0 / tm, 4), "ms_per_step": round(tm * 1e3, 3),
-                 "solves_per_s_matrix_resident": round(1.0 / tms, 3), "iters": int(stm[0]["iters"]),
-                 "mvps": int(stm[0]["mvps"]), "outer_checks": int(stm[0]["checks"]),
-                 "relres_true_fp64": float(torch.linalg.vector_norm(Rm) / torch.linalg.vector_norm(Bm)),
-                 "rel_diff_vs_plain": float(torch.linalg.vector_norm(Xm - X) / torch.linalg.vector_norm(X)),
-                 "inner_tol": args.inner_tol, "speedup_vs_plain": round(ms_per_step / (tm * 1e3), 3)}
-        opm.close()
-
-    gemv_avg_ms = gemv_ms / max(1, launches)
-    # the matrix is symmetric: a product reads each of the N(N+1)/2 distinct
-    # entries once (complex128), plus x read and y written
-    alg_bytes = N * (N + 1) // 2 * 16 + 2 * N * 16
-    achieved = alg_bytes / (gemv_avg_ms * 1e-3) / 1e9
-    khash = product_source_hash()
-    traffic = traffic_from_profiles(khash, N)
-
-    mvps = float(np.mean([s["mvps"] for s in stats]))
+    plain, roof_gemv = plain_leg(args, bie, torch, V, T, k)
+    head, roof, ms_step, plain_mvps, ns = headline_leg(args, bie, torch, V, T, k)
+    N = 3 * T.shape[0] // 2
     out = {
         "metric": METRIC,
-        "value": round(1e3 / ms_per_step, 4),
+        "value": head["solves_per_s"],
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
+        "ms_per_step": round(ms_step, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c128",
+        "dtype": "split-bf16 products (f32 accumulate) + f64 refinement",
         "data": "synthetic",
-        "config": {"workload": f"PEC sphere r=1 m, icosphere {T.shape[0]} triangles ({N} RWG), k={k:g}, "
-                               f"1 plane wave (x-pol, from +z), FP64 fill + GMRES({args.restart}) to "
-                               f"{args.tol:g} (SCC)", "N": N, "k": k, "restart": args.restart,
-                   "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "packed symmetric complex128 product (tile pass + reduce)",
-                     "alg_bytes_per_launch": alg_bytes, "avg_launch_us": round(gemv_avg_ms * 1e3, 2),
-                     "launches": launches},
-        "solve": {"iters": int(stats[-1]["iters"]), "mvps": int(stats[-1]["mvps"]),
-                  "relres_true_fp64": relres, "converged": bool(stats[-1]["converged"]),
-                  "solve_only_s": round(t_solve, 4), "solves_per_s_matrix_resident": round(1.0 / t_solve, 3),
-                  "fill_fp64_s": round(t_fill64, 4), "fill_fp32_s": round(t_fill32, 4),
-                  "gemv_share_of_step": round(gemv_ms / (t_steps * 1e3), 3)},
-        "mixed_fp32_ir": mixed,
+        "config": {"workload": (f"PEC sphere r=1 m, icosphere {T.shape[0]} triangles ({N} RWG), k={k:g}; batches of "
+                                f"{2 * args.test_dirs} held-out plane waves ({args.test_dirs} directions x theta/phi), "
+                                f"operator and warm start resident; learned warm start (POD {min(256, 2 * args.train_dirs)}, "
+                                f"MLP 4-512-512, trained on {2 * args.train_dirs} solves); GMRES({args.restart}) on "
+                                f"split-BF16 MFMA products with FP64 refinement to {args.tol:g} (FP64 SCC), "
+                                f"continuous batch of {args.slots} slots"),
+                   "N": N, "k": k, "restart": args.restart, "inner_tol": args.inner_tol, "slots": args.slots,
+                   "rhs_per_step": 2 * args.test_dirs, "train_directions": args.train_dirs,
+                   "test_directions": args.test_dirs, "parallelism": "single GPU"},
+        "roofline": roof,
+        "roofline_gemv": roof_gemv,
+        "headline": head,
+        "plain_fp64_step": plain,
     }
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(args.level, k, args.restart, mvps)
+        out["cpu_baseline"] = cpu_baseline(args.level, k, args.restart, plain_mvps)
     print(json.dumps(out), flush=True)
 
 

@@ -254,10 +254,12 @@ void bie_ws_destroy(bie_ws *ws);
  * the dense product kernels (from bie_apply and inside bie_solve) is bracketed
  * by HIP events on the stream it runs on.  bie_prof_read waits for the
  * recorded events of `kernel` (0: packed symmetric product, 1: split-BF16
- * block product) and returns the number of launches and their summed
- * duration in ms since the previous read, then clears that record. */
+ * block product) and returns the number of launches, their summed duration in
+ * ms and (columns, may be NULL) the summed number of right-hand sides of those
+ * launches (the packed product counts every column of its grid, skipped ones
+ * included) since the previous read, then clears that record. */
 int bie_prof_enable(int on);
-int bie_prof_read(int kernel, int64_t *launches, double *total_ms);
+int bie_prof_read(int kernel, int64_t *launches, double *total_ms, int64_t *columns);
 
 const char *bie_last_error(void);
 

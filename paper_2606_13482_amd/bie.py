@@ -86,7 +86,8 @@ SYMBOLS = [
     ("bie_ws_load", ctypes.c_int, [_P, ctypes.c_char_p, ctypes.POINTER(_P)]),
     ("bie_ws_destroy", None, [_P]),
     ("bie_prof_enable", ctypes.c_int, [ctypes.c_int]),
-    ("bie_prof_read", ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_double)]),
+    ("bie_prof_read", ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(_I64)]),
     ("bie_last_error", ctypes.c_char_p, []),
 ]
 
@@ -140,12 +141,13 @@ def prof_enable(on: bool = True):
     _check(_lib.bie_prof_enable(int(on)))
 
 
-def prof_read(kernel: int = 0):
-    """(launches, total_ms) of a dense product kernel since the last read
-    (0: packed symmetric product, 1: split-BF16 block product)."""
-    n = ctypes.c_int64(); ms = ctypes.c_double()
-    _check(_lib.bie_prof_read(int(kernel), ctypes.byref(n), ctypes.byref(ms)))
-    return n.value, ms.value
+def prof_read(kernel: int = 0, columns: bool = False):
+    """(launches, total_ms[, columns]) of a dense product kernel since the last read
+    (0: packed symmetric product, 1: split-BF16 block product); columns = summed
+    right-hand sides of those launches."""
+    n = ctypes.c_int64(); ms = ctypes.c_double(); c = ctypes.c_int64()
+    _check(_lib.bie_prof_read(int(kernel), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(c)))
+    return (n.value, ms.value, c.value) if columns else (n.value, ms.value)
 
 
 @dataclass

@@ -340,11 +340,11 @@ int bie_prof_enable(int on)
     });
 }
 
-int bie_prof_read(int kernel, int64_t *launches, double *total_ms)
+int bie_prof_read(int kernel, int64_t *launches, double *total_ms, int64_t *columns)
 {
     return guarded([&]() -> int {
         if (!launches || !total_ms) return fail(BIE_EINVAL, "NULL argument");
-        bie::prof_read(kernel, launches, total_ms);
+        bie::prof_read(kernel, launches, total_ms, columns);
         return BIE_OK;
     });
 }

@@ -144,8 +144,8 @@ void convert_c128_to_c64(const void *src, void *dst, int64_t n, hipStream_t s);
 void convert_c64_to_c128(const void *src, void *dst, int64_t n, hipStream_t s);
 bool has_nonfinite(const void *x, int64_t n_doubles, hipStream_t s);
 void prof_enable(bool enable);
-void prof_read(int kernel, int64_t *launches, double *total_ms);
-void prof_gemm_begin(hipStream_t s);
+void prof_read(int kernel, int64_t *launches, double *total_ms, int64_t *columns);
+void prof_gemm_begin(hipStream_t s, int64_t ncols);
 void prof_gemm_end(hipStream_t s);
 // gemm.hip
 void split_matrix(bie_op *op, hipStream_t s);

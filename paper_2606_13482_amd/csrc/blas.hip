@@ -36,13 +36,15 @@ bool on = false;
 struct Rec {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
     size_t used = 0;
+    int64_t cols = 0;   // right-hand sides over the recorded launches
 };
 Rec rec[2];
 
-void begin(int k, hipStream_t s)
+void begin(int k, hipStream_t s, int64_t ncols)
 {
     if (!on) return;
     Rec &r = rec[k];
+    r.cols += ncols;
     if (r.used == r.ev.size()) {
         hipEvent_t a, b;
         BIE_HIP(hipEventCreate(&a));
@@ -61,10 +63,10 @@ void end(int k, hipStream_t s)
 }  // namespace prof
 
 void prof_enable(bool enable) { prof::on = enable; }
-void prof_gemm_begin(hipStream_t s) { prof::begin(1, s); }
+void prof_gemm_begin(hipStream_t s, int64_t ncols) { prof::begin(1, s, ncols); }
 void prof_gemm_end(hipStream_t s) { prof::end(1, s); }
 
-void prof_read(int kernel, int64_t *launches, double *total_ms)
+void prof_read(int kernel, int64_t *launches, double *total_ms, int64_t *columns)
 {
     if (kernel < 0 || kernel > 1) throw Error(BIE_EINVAL, "unknown kernel record");
     prof::Rec &r = prof::rec[kernel];
@@ -77,7 +79,9 @@ void prof_read(int kernel, int64_t *launches, double *total_ms)
     }
     *launches = int64_t(r.used);
     *total_ms = t;
+    if (columns) *columns = r.cols;
     r.used = 0;
+    r.cols = 0;
 }
 
 namespace {
@@ -370,7 +374,7 @@ void launch_product(const bie_op *op, const void *Z, const void *X, int64_t ldx,
 {
     const Packed &pk = op->pk;
     const dim3 grid(unsigned(pk.nunits), unsigned(R));
-    prof::begin(0, s);
+    prof::begin(0, s, R);
     if (sym_prefetch())
         hipLaunchKernelGGL((k_sym_tiles<M, T, CONJ, true>), grid, dim3(256), 0, s, (const M *)Z, pk.N, pk.nT,
                            pk.units, pk.unit_ptr, pk.seg, pk.nslots, (const T *)X, ldx, (T *)pk.part, skip, sks);

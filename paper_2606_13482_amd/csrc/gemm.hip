@@ -311,7 +311,7 @@ void gemm_product(const bie_op *opc, const void *X, int64_t ldx, bool xf32, void
     else
         hipLaunchKernelGGL(k_split_vectors<double2>, sgrid, dim3(256), 0, s, (const double2 *)X, ldx, cols, N, R, Kp,
                            Bh, Bl);
-    prof_gemm_begin(s);
+    prof_gemm_begin(s, R);
     hipLaunchKernelGGL(k_gemm_split, dim3(unsigned(Mp / GBM), unsigned(NCp / GBN), unsigned(KS)), dim3(512), 0, s, Ah,
                        Al, Bh, Bl, Kp, Mp, NCp, P);
     prof_gemm_end(s);
