@@ -51,7 +51,7 @@ def parse():
     ap.add_argument("--k", type=float, default=10.0)
     ap.add_argument("--restart", type=int, default=50)
     ap.add_argument("--tol", type=float, default=1e-6)
-    ap.add_argument("--inner-tol", type=float, default=1e-2)
+    ap.add_argument("--inner-tol", type=float, default=1e-1)
     ap.add_argument("--slots", type=int, default=256)
     ap.add_argument("--train-dirs", type=int, default=512)
     ap.add_argument("--test-dirs", type=int, default=256)
@@ -59,6 +59,9 @@ def parse():
     ap.add_argument("--plain-sample", type=int, default=8)
     ap.add_argument("--c5", action="store_true",
                     help="full learned warm-start configuration: 2048 training / 512 test directions, 3000 epochs")
+    ap.add_argument("--counters", action="store_true",
+                    help="only launch the dense product kernels a few times at the bench sizes, and a 1 GiB "
+                         "device copy as calibration, for hardware-counter runs")
     a = ap.parse_args()
     if a.c5:
         a.train_dirs, a.test_dirs, a.epochs = 2048, 512, 3000
@@ -289,6 +292,30 @@ def headline_leg(args, bie, torch, V, T, k):
     return res, roof, ms_step, float(np.mean([b for _, b in itp])), int(ns)
 
 
+def counters_probe(args, bie, torch):
+    """Kernels for the HBM traffic counters: 5 launches of the packed FP64 product
+    (one column), 5 of the split-BF16 block product (256 columns) on the bench
+    operator, and 3 plain copies of 1 GiB (FETCH_SIZE / WRITE_SIZE calibration)."""
+    from paper_2606_13482_amd.inputs import icosphere, complex_gaussian
+    V, T = icosphere(args.level)
+    op = bie.Operator(V, T, args.k, storage="split_bf16")
+    x = torch.from_numpy(complex_gaussian(op.N, 7)).cuda().reshape(1, -1)
+    Xb = torch.from_numpy(complex_gaussian(op.N, 7, cols=256)).cuda()
+    for _ in range(5):
+        op.apply(x)
+    for _ in range(5):
+        op.apply(Xb, block=True)
+    a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"counters_probe": {"N": op.N, "packed_fp64_launches": 5, "block_launches": 5,
+                                         "block_columns": 256, "copy_bytes": a.numel() * 4, "copies": 3}}),
+          flush=True)
+    op.close()
+
+
 def cpu_baseline(level: int, k: float, restart: int, plain_mvps: float):
     """The oracle (C fill with OpenMP + numpy GMRES) on a bounded sample: the full
     FP64 fill and one GMRES(restart) cycle; a solve with the matrix resident is
@@ -326,6 +353,9 @@ def main():
     from paper_2606_13482_amd.inputs import icosphere
 
     torch.cuda.set_device(torch.device("cuda:0"))
+    if args.counters:
+        counters_probe(args, bie, torch)
+        return
     V, T = icosphere(args.level)
     k = args.k
     plain, roof_gemv = plain_leg(args, bie, torch, V, T, k)

@@ -114,9 +114,13 @@ int bie_rhs_planewave(const bie_op *op, const double *dirs, const double *pols, 
  *   X, Y  device R x N, complex128 (vec = BIE_C128) or complex64 (vec = BIE_C64);
  *         vec = BIE_SPLIT_BF16: complex128 vectors through the split-BF16 block
  *         product on the matrix cores (storage BIE_SPLIT_BF16, conj = 0);
+ *         vec = BIE_APPLY_F64_BLOCK: complex128 vectors through the FP64 block
+ *         product on the matrix cores (FP64 matrix stored, conj = 0; a dense
+ *         FP64 copy of 16 N^2 bytes is made on first use and kept);
  *         X and Y must not overlap.  Complex128 vectors use the FP64 matrix when
  *         stored (else the FP32 matrix with FP64 accumulation); complex64 vectors
  *         use the FP32 matrix with FP32 accumulation. */
+#define BIE_APPLY_F64_BLOCK 3
 int bie_apply(const bie_op *op, const void *X, void *Y, int64_t R, int vec, int conj,
               void *stream);
 

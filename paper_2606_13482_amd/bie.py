@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libbie.so")
 BIE_OK, BIE_NOT_CONVERGED = 0, 1
 BIE_EINVAL, BIE_EMESH, BIE_ENOMEM, BIE_EDEVICE, BIE_ENUMERIC = -1, -2, -3, -4, -5
 BIE_C128, BIE_C64, BIE_SPLIT_BF16 = 0, 1, 2
+BIE_APPLY_F64_BLOCK = 3
 BIE_GMRES, BIE_CGNR = 0, 1
 BIE_SCC, BIE_RSCC = 0, 1
 
@@ -224,12 +225,18 @@ class Operator:
         return B
 
     def apply(self, X: torch.Tensor, conj: bool = False, out: torch.Tensor | None = None, stream=None,
-              block: bool = False):
-        """Y = T X (or T^H X); block=True: complex128 vectors through the split-BF16
-        block product on the matrix cores (storage "split_bf16")."""
+              block: bool | str = False):
+        """Y = T X (or T^H X).  block=True or "bf16": complex128 vectors through the
+        split-BF16 block product on the matrix cores (storage "split_bf16");
+        block="fp64": the FP64 block product on the matrix cores."""
         X2 = X.reshape(-1, self.N)
         Y = torch.empty_like(X2) if out is None else out
-        code = BIE_SPLIT_BF16 if block else (BIE_C128 if X2.dtype == torch.complex128 else BIE_C64)
+        if block == "fp64":
+            code = BIE_APPLY_F64_BLOCK
+        elif block:
+            code = BIE_SPLIT_BF16
+        else:
+            code = BIE_C128 if X2.dtype == torch.complex128 else BIE_C64
         _check(_lib.bie_apply(self._h, _dev(X2, X2.dtype), _dev(Y, X2.dtype, X2.shape), X2.shape[0], code,
                               int(conj), _stream(stream)))
         return Y.reshape(X.shape)

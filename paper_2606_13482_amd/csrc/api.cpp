@@ -38,7 +38,7 @@ void destroy_op(bie_op *op)
     if (!op) return;
     bie::free_workspace(op);
     bie::packed_free(op);
-    void *ptrs[] = { op->Z64, op->Z32, op->Abf, op->Bbf, op->gemm_part, op->tri.cent, op->tri.loc, op->tri.vfree, op->tri.verts,
+    void *ptrs[] = { op->Z64, op->Z32, op->Abf, op->Bbf, op->gemm_part, op->A64, op->d64_part, op->tri.cent, op->tri.loc, op->tri.vfree, op->tri.verts,
                      op->tri.area, op->tri.sgn, op->tri.slot_m, op->tri.edges };
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -178,6 +178,10 @@ int bie_apply(const bie_op *op, const void *X, void *Y, int64_t R, int vec, int 
             if (!op->Abf) return fail(BIE_EINVAL, "no split-BF16 matrix stored");
             if (conj) return fail(BIE_EINVAL, "the block product has no conjugate form");
             bie::product(op, bie::MATBF16, true, X, N, Y, N, nullptr, 0, R, nullptr, 1, false, s);
+        } else if (vec == BIE_APPLY_F64_BLOCK) {
+            if (!op->Z64) return fail(BIE_EINVAL, "the FP64 block product needs the FP64 matrix");
+            if (conj) return fail(BIE_EINVAL, "the block product has no conjugate form");
+            bie::gemm64_product(op, X, N, Y, N, nullptr, 0, R, nullptr, s);
         } else {
             return fail(BIE_EINVAL, "unknown vector dtype");
         }

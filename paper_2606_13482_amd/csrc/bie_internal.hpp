@@ -111,6 +111,10 @@ struct bie_op {
     int64_t bstage_cols = 0;
     void *gemm_part = nullptr;    // split-K partial tiles, FP32 [KS][Mp][NCp]
     size_t gemm_part_elems = 0;
+    void *A64 = nullptr;          // dense FP64 copy [d64_Mp][d64_Kp] (re/im interleaved) for the FP64 block product
+    int64_t d64_Mp = 0, d64_Kp = 0;
+    void *d64_part = nullptr;     // its split-K partial tiles, FP64
+    size_t d64_part_elems = 0;
     bie::Workspace *ws = nullptr;
 };
 
@@ -145,12 +149,15 @@ void convert_c64_to_c128(const void *src, void *dst, int64_t n, hipStream_t s);
 bool has_nonfinite(const void *x, int64_t n_doubles, hipStream_t s);
 void prof_enable(bool enable);
 void prof_read(int kernel, int64_t *launches, double *total_ms, int64_t *columns);
-void prof_gemm_begin(hipStream_t s, int64_t ncols);
-void prof_gemm_end(hipStream_t s);
+void prof_begin(int kernel, hipStream_t s, int64_t ncols);
+void prof_end(int kernel, hipStream_t s);
 // gemm.hip
 void split_matrix(bie_op *op, hipStream_t s);
 void gemm_product(const bie_op *op, const void *X, int64_t ldx, bool xf32, void *Y, int64_t ldy, const void *Bsub,
                   int64_t ldb, int64_t R, const int *cols, hipStream_t s);
+void dense64_setup(bie_op *op, hipStream_t s);
+void gemm64_product(const bie_op *op, const void *X, int64_t ldx, void *Y, int64_t ldy, const void *Bsub,
+                    int64_t ldb, int64_t R, const int *cols, hipStream_t s);
 
 // warmstart.hip
 bie_ws *ws_train(const bie_op *op, const double *feats, const double *pols, const void *X, int64_t S,

@@ -30,7 +30,8 @@
 namespace bie {
 
 // Optional timing of the dense product kernels: events recorded on the launch
-// stream around every launch (record 0: packed product, 1: block GEMM).
+// stream around every launch (record 0: packed FP64/FP32 product, 1: split-BF16
+// block product, 2: FP64 block product).
 namespace prof {
 bool on = false;
 struct Rec {
@@ -38,7 +39,7 @@ struct Rec {
     size_t used = 0;
     int64_t cols = 0;   // right-hand sides over the recorded launches
 };
-Rec rec[2];
+Rec rec[3];
 
 void begin(int k, hipStream_t s, int64_t ncols)
 {
@@ -63,12 +64,12 @@ void end(int k, hipStream_t s)
 }  // namespace prof
 
 void prof_enable(bool enable) { prof::on = enable; }
-void prof_gemm_begin(hipStream_t s, int64_t ncols) { prof::begin(1, s, ncols); }
-void prof_gemm_end(hipStream_t s) { prof::end(1, s); }
+void prof_begin(int kernel, hipStream_t s, int64_t ncols) { prof::begin(kernel, s, ncols); }
+void prof_end(int kernel, hipStream_t s) { prof::end(kernel, s); }
 
 void prof_read(int kernel, int64_t *launches, double *total_ms, int64_t *columns)
 {
-    if (kernel < 0 || kernel > 1) throw Error(BIE_EINVAL, "unknown kernel record");
+    if (kernel < 0 || kernel > 2) throw Error(BIE_EINVAL, "unknown kernel record");
     prof::Rec &r = prof::rec[kernel];
     double t = 0.0;
     for (size_t i = 0; i < r.used; ++i) {

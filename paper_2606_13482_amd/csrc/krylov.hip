@@ -1241,8 +1241,8 @@ constexpr int MAX_CHECKS = 100;   // outer refinement steps per right-hand side
 // Mixed precision with iterative refinement, as a continuous batch.
 //
 // Each right-hand side is refined as x <- x + d, where the outer residual
-// r = b - T x uses the FP64 matrix and decides convergence (standard criterion
-// in FP64) and the correction solves T_low d = r with GMRES(m) to a relative
+// r = b - T x uses the FP64 matrix (FP64 block product on the matrix cores over
+// the slots being checked) and decides convergence (standard criterion in FP64) and the correction solves T_low d = r with GMRES(m) to a relative
 // tolerance inner_tol on the low-precision matrix: the split-BF16 block
 // product on the matrix cores (Krylov basis stored in complex64, FP64
 // arithmetic) or the FP32 packed matrix (FP64 vectors).
@@ -1278,7 +1278,7 @@ static int solve_stream(const bie_op *opc, const void *Bv, void *Xv, int64_t R, 
     double2 *Ds = db.get<double2>(size_t(W) * N);   // corrections
     double *part = db.get<double>(size_t(std::max(R, W)) * nb);
     double *nrm = db.get<double>(size_t(std::max(R, W)));
-    int *dcols = db.get<int>(size_t(2 * W));
+    int *dcols = db.get<int>(size_t(3 * W));   // [0, W): cycle list, [W, 2W): continuing, [2W, 3W): checks
     int *dskip = w->mask;
 
     auto colnorms = [&](const double2 *v, int64_t cnt, std::vector<double> &out) {
@@ -1295,7 +1295,7 @@ static int solve_stream(const bie_op *opc, const void *Bv, void *Xv, int64_t R, 
     colnorms(B, R, bn);
     std::vector<bie_solve_stat> hs(R, bie_solve_stat{ 0, 0, NAN, NAN, 0, 0 });
     std::vector<int64_t> rhs(W, -1);
-    std::vector<int> phase(W, SL_EMPTY), skip(W, 1), colsh(2 * W, 0);
+    std::vector<int> phase(W, SL_EMPTY), skip(W, 1), colsh(2 * W, 0), chk;
     std::vector<double> rin(W, 0.0), rn;
     std::vector<ColStat> st(W);
     int64_t next = 0;
@@ -1363,17 +1363,18 @@ static int solve_stream(const bie_op *opc, const void *Bv, void *Xv, int64_t R, 
                 hs[r].relres_true = 1.0;
                 phase[sl] = SL_NEW;
             }
-            bool anychk = false;
+            chk.clear();
             for (int64_t sl = 0; sl < W; ++sl) {
                 skip[sl] = phase[sl] == SL_CHECK ? 0 : 1;
-                anychk = anychk || !skip[sl];
+                if (!skip[sl]) chk.push_back(int(sl));
             }
-            if (!anychk) {
+            if (chk.empty()) {
                 if (changed) continue;
                 break;
             }
-            BIE_HIP(hipMemcpyAsync(dskip, skip.data(), W * sizeof(int), hipMemcpyHostToDevice, s));
-            product(op, MAT64, true, Xs, N, Rs, N, Bs, N, W, dskip, 1, false, s);   // r = b - T64 x
+            // r = b - T64 x for the slots to check, one FP64 block product on the matrix cores
+            BIE_HIP(hipMemcpyAsync(dcols + 2 * W, chk.data(), chk.size() * sizeof(int), hipMemcpyHostToDevice, s));
+            gemm64_product(op, Xs, N, Rs, N, Bs, N, int64_t(chk.size()), dcols + 2 * W, s);
             colnorms(Rs, W, rn);
             for (int64_t sl = 0; sl < W; ++sl) {
                 if (skip[sl]) continue;

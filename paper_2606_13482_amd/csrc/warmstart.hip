@@ -782,7 +782,8 @@ void ws_predict(bie_ws *w, const double *feats, const double *pols, int64_t R, c
     double2 *res = dmalloc<double2>(size_t(R) * N);
     double *nr = dmalloc<double>(size_t(2 * R));
     const bool m64 = w->op->Z64 != nullptr;
-    product(w->op, m64 ? MAT64 : MAT32, true, X0, N, res, N, B, N, R, nullptr, 1, false, s);
+    if (m64 && R >= 8) gemm64_product(w->op, X0, N, res, N, B, N, R, nullptr, s);   // many columns: matrix cores
+    else product(w->op, m64 ? MAT64 : MAT32, true, X0, N, res, N, B, N, R, nullptr, 1, false, s);
     hipLaunchKernelGGL(k_sqnorm, dim3(unsigned(R)), dim3(256), 0, s, N, res, nr);
     hipLaunchKernelGGL(k_sqnorm, dim3(unsigned(R)), dim3(256), 0, s, N, static_cast<const double2 *>(B), nr + R);
     std::vector<double> h(size_t(2 * R));

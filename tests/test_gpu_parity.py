@@ -294,6 +294,24 @@ def test_block_product_split_bf16(bie, R):
     assert np.linalg.norm(Y64[0] - Yo[0]) / np.linalg.norm(Yo[0]) < 1e-10
 
 
+@pytest.mark.parametrize("R", [1, 3, 65, 130])
+def test_block_product_fp64(bie, R):
+    """FP64 block product on the matrix cores (dense FP64 copy, v_mfma_f64_16x16x4f64)
+    against the oracle matrix: FP64 rounding only, so 1e-13 relative to ||T x||;
+    and against the packed FP64 product of the same operator."""
+    V, T, rwg, Zo = case(3, 6.0)
+    op = bie.Operator(V, T, 6.0)
+    x = complex_gaussian(op.N, 23, cols=R)
+    X = torch.from_numpy(x).cuda()
+    Y = op.apply(X, block="fp64").cpu().numpy()
+    Yo = x @ Zo.T
+    err = np.linalg.norm(Y - Yo, axis=1) / np.linalg.norm(Yo, axis=1)
+    Yp = op.apply(X).cpu().numpy()
+    errp = np.linalg.norm(Y - Yp, axis=1) / np.linalg.norm(Yp, axis=1)
+    _say(f"  FP64 block product R={R}: max rel err {err.max():.2e} (vs packed {errp.max():.2e})")
+    assert err.max() < 1e-13 and errp.max() < 1e-13
+
+
 def test_mixed_refinement_split_bf16_block(bie):
     """Block GMRES (simultaneous columns) on the split-BF16 matrix with FP64 refinement."""
     V, T, rwg, Zo = case(3, 6.0)
