@@ -52,6 +52,7 @@ def parse():
     ap.add_argument("--restart", type=int, default=50)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--inner-tol", type=float, default=1e-1)
+    ap.add_argument("--inner-terms", type=int, default=3, choices=[2, 3])
     ap.add_argument("--slots", type=int, default=256)
     ap.add_argument("--train-dirs", type=int, default=512)
     ap.add_argument("--test-dirs", type=int, default=256)
@@ -178,7 +179,7 @@ def headline_leg(args, bie, torch, V, T, k):
     res["setup_fill_split_s"] = round(time.perf_counter() - t0, 4)
     N = op.N
     mopts = bie.Solve(restart=args.restart, tol=args.tol, max_mvp=20000, precision="mixed",
-                      inner_tol=args.inner_tol, slots=args.slots)
+                      inner_tol=args.inner_tol, slots=args.slots, inner_terms=args.inner_terms)
     popts = bie.Solve(restart=args.restart, tol=args.tol, max_mvp=20000)
 
     # training: solutions the method computes, then POD + MLP on the GPU
@@ -205,9 +206,9 @@ def headline_leg(args, bie, torch, V, T, k):
 
     def step():
         B = op.rhs(dte, pte)
-        X0, used = ws.predict(fte, B, pols=pte)
-        X, st = op.solve(B, mopts, x0=X0)
-        return B, X, X0, used, st
+        X0, _ = ws.predict(fte, None, pols=pte)
+        X, st = op.solve(B, mopts, x0=X0, x0_fallback=True)   # the fallback uses the solver's first FP64 residual
+        return B, X, X0, np.array([s["x0_kept"] for s in st], bool), st
 
     for _ in range(args.warmup):
         step()
@@ -293,9 +294,10 @@ def headline_leg(args, bie, torch, V, T, k):
 
 
 def counters_probe(args, bie, torch):
-    """Kernels for the HBM traffic counters: 5 launches of the packed FP64 product
-    (one column), 5 of the split-BF16 block product (256 columns) on the bench
-    operator, and 3 plain copies of 1 GiB (FETCH_SIZE / WRITE_SIZE calibration)."""
+    """Kernels for the HBM traffic counters: 5 launches each of the packed FP64
+    product (one column), the split-BF16 block product and the FP64 block product
+    (256 columns) on the bench operator, and 3 plain copies of 1 GiB
+    (FETCH_SIZE / WRITE_SIZE calibration)."""
     from paper_2606_13482_amd.inputs import icosphere, complex_gaussian
     V, T = icosphere(args.level)
     op = bie.Operator(V, T, args.k, storage="split_bf16")
@@ -305,6 +307,8 @@ def counters_probe(args, bie, torch):
         op.apply(x)
     for _ in range(5):
         op.apply(Xb, block=True)
+    for _ in range(5):
+        op.apply(Xb, block="fp64")
     a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     for _ in range(3):
@@ -381,6 +385,7 @@ def main():
                                 f"split-BF16 MFMA products with FP64 refinement to {args.tol:g} (FP64 SCC), "
                                 f"continuous batch of {args.slots} slots"),
                    "N": N, "k": k, "restart": args.restart, "inner_tol": args.inner_tol, "slots": args.slots,
+                   "inner_terms": args.inner_terms,
                    "rhs_per_step": 2 * args.test_dirs, "train_directions": args.train_dirs,
                    "test_directions": args.test_dirs, "parallelism": "single GPU"},
         "roofline": roof,

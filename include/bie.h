@@ -135,7 +135,9 @@ typedef struct {
     int crit;            /* bie_crit; default BIE_SCC */
     int64_t rscc_rows;   /* S, default 512 (min(S, N) used) */
     uint64_t rscc_seed;  /* default 1234 */
-    int use_x0;          /* 1: X holds the initial guess on entry */
+    int use_x0;          /* 1: X holds the initial guess on entry; 2: the same with
+                            fallback: a guess with ||b - T x0|| >= ||b|| (first FP64
+                            residual) is replaced by zero */
     int precision;       /* 0: products with the stored matrix (FP64 if stored);
                             1: mixed precision with iterative refinement: outer FP64
                                residual and criterion (SCC), inner GMRES on the
@@ -145,6 +147,11 @@ typedef struct {
                             (0: default 1e-3) */
     int64_t slots;       /* precision 1: right-hand sides in flight (continuous batch:
                             a converged one hands its slot to the next); 0: all R */
+    int inner_terms;     /* precision 1, split-BF16: terms of the inner block product,
+                            3 (hi/lo matrix x hi/lo vector, lo x lo dropped) or 2
+                            (hi/lo matrix x BF16 vector; the inner tolerance is then
+                            raised to at least 1e-2, the rounding of the vectors
+                            bounding what the inner solve can attain); 0: default 3 */
 } bie_solve_opts;
 
 typedef struct {
@@ -154,6 +161,7 @@ typedef struct {
     double relres_true;   /* last criterion value on the true residual */
     int converged;        /* criterion met */
     int checks;           /* criterion evaluations */
+    int x0_kept;          /* 1 if an initial guess was given and kept (use_x0 = 2 may drop it) */
 } bie_solve_stat;
 
 /* Solve T x = b for R right-hand sides to the selected criterion.

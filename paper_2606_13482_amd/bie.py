@@ -42,7 +42,7 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int), ("restart", ctypes.c_int), ("tol", ctypes.c_double),
                 ("max_mvp", ctypes.c_int64), ("crit", ctypes.c_int), ("rscc_rows", ctypes.c_int64),
                 ("rscc_seed", ctypes.c_uint64), ("use_x0", ctypes.c_int), ("precision", ctypes.c_int),
-                ("inner_tol", ctypes.c_double), ("slots", ctypes.c_int64)]
+                ("inner_tol", ctypes.c_double), ("slots", ctypes.c_int64), ("inner_terms", ctypes.c_int)]
 
 
 class WsOpts(ctypes.Structure):
@@ -54,7 +54,8 @@ class WsOpts(ctypes.Structure):
 
 class SolveStat(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int64), ("mvps", ctypes.c_int64), ("relres_est", ctypes.c_double),
-                ("relres_true", ctypes.c_double), ("converged", ctypes.c_int), ("checks", ctypes.c_int)]
+                ("relres_true", ctypes.c_double), ("converged", ctypes.c_int), ("checks", ctypes.c_int),
+                ("x0_kept", ctypes.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -163,12 +164,13 @@ class Solve:
     precision: str = "plain"      # "plain" or "mixed" (FP32 inner GMRES + FP64 refinement)
     inner_tol: float = 0.0
     slots: int = 0                # mixed: right-hand sides in flight (continuous batch); 0 = all
+    inner_terms: int = 0          # mixed, split-BF16: 3 or 2 terms of the inner block product; 0 = 3
 
-    def c(self, use_x0: bool) -> SolveOpts:
+    def c(self, use_x0: int) -> SolveOpts:
         return SolveOpts({"gmres": BIE_GMRES, "cgnr": BIE_CGNR}[self.method], self.restart, self.tol,
                          self.max_mvp, {"scc": BIE_SCC, "rscc": BIE_RSCC}[self.crit], self.rscc_rows,
                          self.rscc_seed, int(use_x0), {"plain": 0, "mixed": 1}[self.precision],
-                         self.inner_tol, self.slots)
+                         self.inner_tol, self.slots, self.inner_terms)
 
 
 class Operator:
@@ -242,7 +244,9 @@ class Operator:
         return Y.reshape(X.shape)
 
     def solve(self, B: torch.Tensor, opts: Solve | None = None, x0: torch.Tensor | None = None,
-              stream=None, out: torch.Tensor | None = None):
+              stream=None, out: torch.Tensor | None = None, x0_fallback: bool = False):
+        """Solve T X = B; x0: initial guesses (x0_fallback: a guess no better than
+        zero, ||b - T x0|| >= ||b||, is replaced by zero inside the solve)."""
         opts = opts or Solve()
         B2 = B.reshape(-1, self.N)
         R = B2.shape[0]
@@ -255,7 +259,7 @@ class Operator:
         if x0 is not None and out is not None:
             X.copy_(x0.reshape(-1, self.N))
         st = (SolveStat * R)()
-        co = opts.c(x0 is not None)
+        co = opts.c(0 if x0 is None else (2 if x0_fallback else 1))
         rc = _lib.bie_solve(self._h, _dev(B2, torch.complex128), _dev(X, torch.complex128, B2.shape), R,
                             ctypes.byref(co), st, _stream(stream))
         _check(rc, allow_nc=True)

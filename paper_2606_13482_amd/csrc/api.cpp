@@ -196,7 +196,7 @@ int bie_solve(const bie_op *op, const void *B, void *X, int64_t R, const bie_sol
         if (!op || !B || !X) return fail(BIE_EINVAL, "NULL argument");
         if (R < 0 || R > 4096) return fail(BIE_EINVAL, "R out of range (0..4096)");
         if (R == 0) return BIE_OK;
-        bie_solve_opts o{ BIE_GMRES, 30, 1e-6, 10000, BIE_SCC, 512, 1234, 0, 0, 0.0, 0 };
+        bie_solve_opts o{ BIE_GMRES, 30, 1e-6, 10000, BIE_SCC, 512, 1234, 0, 0, 0.0, 0, 0 };
         if (opts) o = *opts;
         if (o.method != BIE_GMRES && o.method != BIE_CGNR) return fail(BIE_EINVAL, "unknown method");
         if (o.crit != BIE_SCC && o.crit != BIE_RSCC) return fail(BIE_EINVAL, "unknown criterion");
@@ -207,6 +207,9 @@ int bie_solve(const bie_op *op, const void *B, void *X, int64_t R, const bie_sol
         if (o.precision != 0 && o.precision != 1) return fail(BIE_EINVAL, "precision must be 0 or 1");
         if (!(o.inner_tol >= 0.0 && o.inner_tol < 1.0)) return fail(BIE_EINVAL, "inner_tol must be in [0, 1)");
         if (o.slots < 0) return fail(BIE_EINVAL, "slots must be >= 0");
+        if (o.use_x0 < 0 || o.use_x0 > 2) return fail(BIE_EINVAL, "use_x0 must be 0, 1 or 2");
+        if (o.inner_terms != 0 && o.inner_terms != 2 && o.inner_terms != 3)
+            return fail(BIE_EINVAL, "inner_terms must be 0, 2 or 3");
         const int64_t N = op->mesh.N;
         hipStream_t s = as_stream(stream);
         if (bie::has_nonfinite(B, 2 * R * N, s)) return fail(BIE_ENUMERIC, "non-finite right-hand side");

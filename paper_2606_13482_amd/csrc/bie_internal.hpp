@@ -154,7 +154,7 @@ void prof_end(int kernel, hipStream_t s);
 // gemm.hip
 void split_matrix(bie_op *op, hipStream_t s);
 void gemm_product(const bie_op *op, const void *X, int64_t ldx, bool xf32, void *Y, int64_t ldy, const void *Bsub,
-                  int64_t ldb, int64_t R, const int *cols, hipStream_t s);
+                  int64_t ldb, int64_t R, const int *cols, hipStream_t s, int terms = 3);
 void dense64_setup(bie_op *op, hipStream_t s);
 void gemm64_product(const bie_op *op, const void *X, int64_t ldx, void *Y, int64_t ldy, const void *Bsub,
                     int64_t ldb, int64_t R, const int *cols, hipStream_t s);

@@ -92,7 +92,7 @@ __global__ __launch_bounds__(256) void k_split_matrix(const double2 *__restrict_
 template <typename XT>
 __global__ __launch_bounds__(256) void k_split_vectors(const XT *__restrict__ X, int64_t ldx, const int *__restrict__ cols,
                                                        int64_t N, int64_t R, int64_t Kp, __bf16 *__restrict__ Bh,
-                                                       __bf16 *__restrict__ Bl)
+                                                       __bf16 *__restrict__ Bl, bool lo)
 {
     const int64_t c = blockIdx.y;
     const int64_t v = c < 2 * R ? (cols ? int64_t(cols[c >> 1]) : (c >> 1)) : 0;
@@ -108,13 +108,19 @@ __global__ __launch_bounds__(256) void k_split_vectors(const XT *__restrict__ X,
         split_bf16(b, h1, l1);
         Bh[c * Kp + 2 * n] = h0;
         Bh[c * Kp + 2 * n + 1] = h1;
-        Bl[c * Kp + 2 * n] = l0;
-        Bl[c * Kp + 2 * n + 1] = l1;
+        if (lo) {
+            Bl[c * Kp + 2 * n] = l0;
+            Bl[c * Kp + 2 * n + 1] = l1;
+        }
     }
 }
 
-// Partial C = Ah Bh + Ah Bl + Al Bh over the stages of one K slice, into
-// P[z][Mp][NCp].
+// Partial C = Ah Bh + Al Bh (+ Ah Bl when TERMS == 3) over the stages of one K
+// slice, into P[z][Mp][NCp].  TERMS == 2 keeps the matrix split (about 16
+// significant bits) and rounds the vectors to BF16 (2^-9 relative): the form
+// for the inner corrections of iterative refinement, whose tolerance is far
+// above that rounding; the B lo plane is then neither loaded nor stored.
+template <int TERMS>
 __global__ __launch_bounds__(512) void k_gemm_split(const __bf16 *__restrict__ Ah, const __bf16 *__restrict__ Al,
                                                     const __bf16 *__restrict__ Bh, const __bf16 *__restrict__ Bl,
                                                     int64_t Kp, int64_t Mp, int64_t NCp, float *__restrict__ P)
@@ -138,7 +144,8 @@ __global__ __launch_bounds__(512) void k_gemm_split(const __bf16 *__restrict__ A
             for (int q = 0; q < 2; ++q) {
                 const int c = tid + 512 * q;
                 ra[p][q] = *reinterpret_cast<const u32x4 *>((p ? Al : Ah) + (m0 + c / CPR) * Kp + k0 + (c % CPR) * 8);
-                rb[p][q] = *reinterpret_cast<const u32x4 *>((p ? Bl : Bh) + (c0 + c / CPR) * Kp + k0 + (c % CPR) * 8);
+                if (TERMS == 3 || p == 0)
+                    rb[p][q] = *reinterpret_cast<const u32x4 *>((p ? Bl : Bh) + (c0 + c / CPR) * Kp + k0 + (c % CPR) * 8);
             }
     };
     auto lstore = [&](int buf) {
@@ -148,7 +155,7 @@ __global__ __launch_bounds__(512) void k_gemm_split(const __bf16 *__restrict__ A
             for (int q = 0; q < 2; ++q) {
                 const int c = tid + 512 * q;
                 *reinterpret_cast<u32x4 *>(&sA[buf][p][c / CPR][(c % CPR) * 8]) = ra[p][q];
-                *reinterpret_cast<u32x4 *>(&sB[buf][p][c / CPR][(c % CPR) * 8]) = rb[p][q];
+                if (TERMS == 3 || p == 0) *reinterpret_cast<u32x4 *>(&sB[buf][p][c / CPR][(c % CPR) * 8]) = rb[p][q];
             }
     };
 
@@ -179,21 +186,23 @@ __global__ __launch_bounds__(512) void k_gemm_split(const __bf16 *__restrict__ A
 #pragma unroll
                 for (int t = 0; t < TI; ++t)
                     a[t][p] = *reinterpret_cast<const bf16x8 *>(&sA[buf][p][wm * 128 + t * 32 + fr][kk + fk]);
+                if (TERMS == 3 || p == 0)
 #pragma unroll
-                for (int t = 0; t < TJ; ++t)
-                    b[t][p] = *reinterpret_cast<const bf16x8 *>(&sB[buf][p][wn * 64 + t * 32 + fr][kk + fk]);
+                    for (int t = 0; t < TJ; ++t)
+                        b[t][p] = *reinterpret_cast<const bf16x8 *>(&sB[buf][p][wn * 64 + t * 32 + fr][kk + fk]);
             }
-            // three products, each over the 8 independent accumulators
+            // the products, each over the 8 independent accumulators
 #pragma unroll
             for (int i = 0; i < TI; ++i)
 #pragma unroll
                 for (int j = 0; j < TJ; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][0], acc[i][j], 0, 0, 0);
+            if (TERMS == 3)
 #pragma unroll
-            for (int i = 0; i < TI; ++i)
+                for (int i = 0; i < TI; ++i)
 #pragma unroll
-                for (int j = 0; j < TJ; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][1], acc[i][j], 0, 0, 0);
+                    for (int j = 0; j < TJ; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][1], acc[i][j], 0, 0, 0);
 #pragma unroll
             for (int i = 0; i < TI; ++i)
 #pragma unroll
@@ -425,8 +434,9 @@ void split_matrix(bie_op *op, hipStream_t s)
 // complex128 or complex64 (xf32), Y and Bsub complex128; cols (device, R
 // entries, or null for 0..R-1) names the vectors taking part.
 void gemm_product(const bie_op *opc, const void *X, int64_t ldx, bool xf32, void *Y, int64_t ldy, const void *Bsub,
-                  int64_t ldb, int64_t R, const int *cols, hipStream_t s)
+                  int64_t ldb, int64_t R, const int *cols, hipStream_t s, int terms)
 {
+    if (terms != 2 && terms != 3) throw Error(BIE_EINVAL, "the split-BF16 product has 2 or 3 terms");
     bie_op *op = const_cast<bie_op *>(opc);
     const int64_t N = op->mesh.N, Kp = op->gemm_Kp, Mp = op->gemm_Mp, NCp = gemm_pad_cols(R);
     const size_t plane = size_t(NCp) * size_t(Kp);
@@ -455,13 +465,16 @@ void gemm_product(const bie_op *opc, const void *X, int64_t ldx, bool xf32, void
     const dim3 sgrid(unsigned(std::min<int64_t>((Kp / 2 + 255) / 256, 64)), unsigned(NCp));
     if (xf32)
         hipLaunchKernelGGL(k_split_vectors<float2>, sgrid, dim3(256), 0, s, (const float2 *)X, ldx, cols, N, R, Kp, Bh,
-                           Bl);
+                           Bl, terms == 3);
     else
         hipLaunchKernelGGL(k_split_vectors<double2>, sgrid, dim3(256), 0, s, (const double2 *)X, ldx, cols, N, R, Kp,
-                           Bh, Bl);
+                           Bh, Bl, terms == 3);
     prof_begin(1, s, R);
-    hipLaunchKernelGGL(k_gemm_split, dim3(unsigned(Mp / GBM), unsigned(NCp / GBN), unsigned(KS)), dim3(512), 0, s, Ah,
-                       Al, Bh, Bl, Kp, Mp, NCp, P);
+    const dim3 ggrid(unsigned(Mp / GBM), unsigned(NCp / GBN), unsigned(KS));
+    if (terms == 3)
+        hipLaunchKernelGGL(k_gemm_split<3>, ggrid, dim3(512), 0, s, Ah, Al, Bh, Bl, Kp, Mp, NCp, P);
+    else
+        hipLaunchKernelGGL(k_gemm_split<2>, ggrid, dim3(512), 0, s, Ah, Al, Bh, Bl, Kp, Mp, NCp, P);
     prof_end(1, s);
     hipLaunchKernelGGL(k_gemm_reduce<float>, dim3(unsigned(Mp / 64), unsigned(NCp / 64)), dim3(256), 0, s, P, KS, Mp,
                        NCp, N, R, cols, (double2 *)Y, ldy, (const double2 *)Bsub, ldb);

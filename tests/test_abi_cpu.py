@@ -69,3 +69,32 @@ def test_null_arguments():
     assert bie._lib.bie_apply(None, None, None, 1, 0, 0, None) == bie.BIE_EINVAL
     assert bie._lib.bie_solve(None, None, None, 1, None, None, None) == bie.BIE_EINVAL
     assert bie._lib.bie_rscc_rows(10, 0, 1, None) == bie.BIE_EINVAL
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Every option/statistics struct of include/bie.h has the same size and field
+    offsets in the ctypes binding (a small C program compiled against the header
+    prints them)."""
+    import shutil
+    import subprocess
+    from paper_2606_13482_amd import bie
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    structs = {"bie_fill_opts": bie.FillOpts, "bie_solve_opts": bie.SolveOpts, "bie_solve_stat": bie.SolveStat,
+               "bie_ws_opts": bie.WsOpts}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "bie.h"', 'int main(void) {']
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ['return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)

@@ -312,18 +312,22 @@ def test_block_product_fp64(bie, R):
     assert err.max() < 1e-13 and errp.max() < 1e-13
 
 
-def test_mixed_refinement_split_bf16_block(bie):
-    """Block GMRES (simultaneous columns) on the split-BF16 matrix with FP64 refinement."""
+@pytest.mark.parametrize("terms", [3, 2])
+def test_mixed_refinement_split_bf16_block(bie, terms):
+    """Block GMRES (simultaneous columns) on the split-BF16 matrix with FP64 refinement
+    (inner products with 3 terms, or 2: BF16-rounded vectors)."""
     V, T, rwg, Zo = case(3, 6.0)
     op = bie.Operator(V, T, 6.0, storage="split_bf16")
     from paper_2606_13482_amd.inputs import random_directions
     inc = random_directions(24, 3)
     d, e = planewave_set(inc, "theta")
     B = op.rhs(d, e)
-    X, st = op.solve(B, bie.Solve(restart=30, tol=1e-6, precision="mixed", inner_tol=1e-3))
+    itol = 1e-3 if terms == 3 else 1e-1
+    X, st = op.solve(B, bie.Solve(restart=30, tol=1e-6, precision="mixed", inner_tol=itol, inner_terms=terms))
     Bn = B.cpu().numpy(); Xn = X.cpu().numpy()
     res = np.linalg.norm(Bn - Xn @ Zo.T, axis=1) / np.linalg.norm(Bn, axis=1)
-    _say("  block mixed: max residual", res.max(), "outer checks", max(s["checks"] for s in st))
+    _say(f"  block mixed ({terms} terms): max residual", res.max(), "outer checks", max(s["checks"] for s in st),
+         "iterations", sum(s["iters"] for s in st))
     assert all(s["converged"] for s in st)
     assert res.max() <= 1e-6 * (1 + 1e-6)
 
@@ -383,3 +387,27 @@ def test_continuous_batch_warm_and_zero_rhs(bie):
     res[2] = 0.0
     assert res.max() <= 1e-6 * (1 + 1e-6)
     assert st[1]["iters"] < st[3]["iters"]                     # a near guess saves iterations
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_initial_guess_fallback(bie, mixed):
+    """use_x0 = 2: a guess no better than zero (||b - T x0|| >= ||b||) is replaced by
+    zero from the solver's first residual; a good guess is kept.  The dropped guess
+    gives the same iterations as a solve from zero."""
+    V, T, rwg, Zo = case(3, 6.0)
+    op = bie.Operator(V, T, 6.0, storage="split_bf16" if mixed else "c128")
+    from paper_2606_13482_amd.inputs import random_directions
+    d, e = planewave_set(random_directions(3, 21), "theta")
+    B = op.rhs(d, e)
+    Bn = B.cpu().numpy()
+    x0 = np.array([krylov.lu_solve(Zo, b) for b in Bn]) * (1.0 + 1e-4)
+    x0[1] = 30.0 * complex_gaussian(op.N, 5)      # far worse than zero
+    opts = bie.Solve(restart=20, tol=1e-6, precision="mixed" if mixed else "plain", inner_tol=1e-2)
+    X, st = op.solve(B, opts, x0=torch.from_numpy(x0).cuda(), x0_fallback=True)
+    Xz, stz = op.solve(B[1:2], opts)
+    assert [s["x0_kept"] for s in st] == [1, 0, 1]
+    assert all(s["converged"] for s in st)
+    assert st[1]["iters"] == stz[0]["iters"]
+    assert st[0]["iters"] < stz[0]["iters"] and st[2]["iters"] < stz[0]["iters"]
+    res = np.linalg.norm(Bn - X.cpu().numpy() @ Zo.T, axis=1) / np.linalg.norm(Bn, axis=1)
+    assert res.max() <= 1e-6 * (1 + 1e-6)
