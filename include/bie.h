@@ -182,6 +182,32 @@ typedef struct {
 int bie_solve(const bie_op *op, const void *B, void *X, int64_t R, const bie_solve_opts *opts,
               bie_solve_stat *stats, void *stream);
 
+/* Batched solves: the right-hand sides of nops operators of different sizes
+ * (meshes, wavenumbers) solved together with GMRES(m) on the stored matrices
+ * (all FP64 or all FP32) to the standard criterion (method BIE_GMRES,
+ * precision 0, crit BIE_SCC; other options as in bie_solve, use_x0 0/1/2).
+ * Every right-hand side keeps its own Krylov basis, Hessenberg matrix and
+ * criterion; the products of all operators share one grouped launch per
+ * iteration and each restart cycle is replayed as one captured HIP graph.
+ * Work runs on a library stream ordered after `stream`; the call returns
+ * when the solutions are written.
+ *   ops    host array of nops operators (one device)
+ *   B, X   host arrays of nops device pointers: R[p] x N_p complex128 each
+ *          (X in: initial guesses if use_x0; out: solutions)
+ *   R      host array of nops right-hand-side counts (0 allowed)
+ *   stats  host, sum(R) entries in operator order.
+ * Returns BIE_NOT_CONVERGED if any right-hand side missed the criterion. */
+int bie_batch_solve(const bie_op *const *ops, int64_t nops, const void *const *B, void *const *X,
+                    const int64_t *R, const bie_solve_opts *opts, bie_solve_stat *stats, void *stream);
+
+/* Batched solves, for measurement and tests: tiles per work unit of the
+ * grouped product (0: chosen per batch shape by timing candidates 2/4/8/16 on
+ * the batch, the default; the choices are kept for the process and appended to
+ * the file named by BIE_AUTOTUNE_CACHE if set) and graph replay (1: default). */
+int bie_batch_config(int unit_tiles, int use_graph);
+/* Tiles per unit chosen for this batch shape so far (0: none). */
+int bie_batch_tuned(const bie_op *const *ops, int64_t nops, const int64_t *R);
+
 /* Radiation vector F(r) = int j(y) exp(jk r . y) dS of the solutions X for M
  * unit directions (Sec. II, scattered field from the radiation potentials);
  * the far field is E_s ~ -jk exp(-jkr)/(4 pi r) (I - r r) . F and the bistatic

@@ -75,6 +75,9 @@ SYMBOLS = [
     ("bie_apply", ctypes.c_int, [_P, _P, _P, _I64, ctypes.c_int, ctypes.c_int, _P]),
     ("bie_solve", ctypes.c_int, [_P, _P, _P, _I64, _P, _P, _P]),
     ("bie_farfield", ctypes.c_int, [_P, _P, _I64, _P, _I64, _P, _P]),
+    ("bie_batch_solve", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P]),
+    ("bie_batch_config", ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
+    ("bie_batch_tuned", ctypes.c_int, [_P, _I64, _P]),
     ("bie_rscc_rows", ctypes.c_int, [_I64, _I64, ctypes.c_uint64, _P]),
     ("bie_ws_train", ctypes.c_int, [_P, _P, _P, _P, _I64, _P, _P, ctypes.POINTER(_P)]),
     ("bie_ws_predict", ctypes.c_int, [_P, _P, _P, _I64, _P, _P, _P, _P]),
@@ -279,6 +282,45 @@ class Operator:
         F = self.farfield(X, obs).cpu().numpy()
         tang = F - np.sum(obs[None] * F, axis=2, keepdims=True) * obs[None]
         return self.k ** 2 / (4 * np.pi) * np.sum(np.abs(tang) ** 2, axis=2)
+
+
+def batch_solve(ops, Bs, opts: Solve | None = None, x0s=None, x0_fallback: bool = False, stream=None):
+    """Solve T_p X_p = B_p for several operators at once (bie_batch_solve):
+    grouped products, one captured graph per restart cycle.  Returns the list of
+    solutions and the list of per-operator statistics lists."""
+    opts = opts or Solve()
+    P = len(ops)
+    Bs = [b.reshape(-1, op.N) for b, op in zip(Bs, ops)]
+    R = np.array([b.shape[0] for b in Bs], np.int64)
+    if x0s is not None:
+        Xs = [x.reshape(-1, op.N).clone() for x, op in zip(x0s, ops)]
+    else:
+        Xs = [torch.empty_like(b) for b in Bs]
+    oph = (ctypes.c_void_p * P)(*[op._h.value for op in ops])
+    bp = (ctypes.c_void_p * P)(*[_dev(b, torch.complex128).value for b in Bs])
+    xp = (ctypes.c_void_p * P)(*[_dev(x, torch.complex128, b.shape).value for x, b in zip(Xs, Bs)])
+    st = (SolveStat * int(max(1, R.sum())))()
+    use = 0 if x0s is None else (2 if x0_fallback else 1)
+    co = opts.c(use)
+    rc = _lib.bie_batch_solve(oph, P, bp, xp, R.ctypes.data_as(ctypes.c_void_p), ctypes.byref(co), st,
+                              _stream(stream))
+    _check(rc, allow_nc=True)
+    out, k = [], 0
+    for r in R:
+        out.append([st[k + i].as_dict() for i in range(int(r))])
+        k += int(r)
+    return Xs, out
+
+
+def batch_config(unit_tiles: int = 0, graph: bool = True):
+    """Tiles per unit of the grouped product (0: autotune) and graph replay of batched solves."""
+    _check(_lib.bie_batch_config(int(unit_tiles), int(graph)))
+
+
+def batch_tuned(ops, R) -> int:
+    oph = (ctypes.c_void_p * len(ops))(*[op._h.value for op in ops])
+    Rv = np.ascontiguousarray(R, np.int64)
+    return int(_lib.bie_batch_tuned(oph, len(ops), Rv.ctypes.data_as(ctypes.c_void_p)))
 
 
 def features(dirs, pol_flags):

@@ -220,6 +220,57 @@ int bie_solve(const bie_op *op, const void *B, void *X, int64_t R, const bie_sol
     });
 }
 
+int bie_batch_solve(const bie_op *const *ops, int64_t nops, const void *const *B, void *const *X,
+                    const int64_t *R, const bie_solve_opts *opts, bie_solve_stat *stats, void *stream)
+{
+    return guarded([&]() -> int {
+        if (!ops || !B || !X || !R) return fail(BIE_EINVAL, "NULL argument");
+        if (nops < 1 || nops > 4096) return fail(BIE_EINVAL, "nops out of range (1..4096)");
+        bie_solve_opts o{ BIE_GMRES, 30, 1e-6, 10000, BIE_SCC, 512, 1234, 0, 0, 0.0, 0, 0 };
+        if (opts) o = *opts;
+        if (o.method != BIE_GMRES || o.precision != 0 || o.crit != BIE_SCC)
+            return fail(BIE_EINVAL, "batched solves take GMRES, precision 0 and the standard criterion");
+        if (o.restart < 1 || o.restart > 64) return fail(BIE_EINVAL, "restart must be 1..64");
+        if (!(o.tol > 0.0)) return fail(BIE_EINVAL, "tol must be > 0");
+        if (o.max_mvp < 1) return fail(BIE_EINVAL, "max_mvp must be >= 1");
+        if (o.use_x0 < 0 || o.use_x0 > 2) return fail(BIE_EINVAL, "use_x0 must be 0, 1 or 2");
+        hipStream_t s = as_stream(stream);
+        int64_t total = 0;
+        for (int64_t p = 0; p < nops; ++p) {
+            if (!ops[p]) return fail(BIE_EINVAL, "NULL operator");
+            if (R[p] < 0 || R[p] > 4096) return fail(BIE_EINVAL, "R out of range (0..4096)");
+            if (R[p] > 0 && (!B[p] || !X[p])) return fail(BIE_EINVAL, "NULL vector pointer");
+            total += R[p];
+            const int64_t n2 = 2 * R[p] * ops[p]->mesh.N;
+            if (R[p] > 0 && bie::has_nonfinite(B[p], n2, s)) return fail(BIE_ENUMERIC, "non-finite right-hand side");
+            if (R[p] > 0 && o.use_x0 && bie::has_nonfinite(X[p], n2, s))
+                return fail(BIE_ENUMERIC, "non-finite initial guess");
+        }
+        if (total == 0) return BIE_OK;
+        if (total > 65535) return fail(BIE_EINVAL, "at most 65535 right-hand sides per batch");
+        const int rc = bie::solve_batch(ops, nops, B, X, R, o, stats, s);
+        if (rc == BIE_NOT_CONVERGED) g_err = "not converged within max_mvp";
+        return rc;
+    });
+}
+
+int bie_batch_config(int unit_tiles, int use_graph)
+{
+    return guarded([&]() -> int {
+        if (unit_tiles < 0 || unit_tiles > 64) return fail(BIE_EINVAL, "unit_tiles must be 0..64");
+        bie::batch_config(unit_tiles, use_graph != 0);
+        return BIE_OK;
+    });
+}
+
+int bie_batch_tuned(const bie_op *const *ops, int64_t nops, const int64_t *R)
+{
+    return guarded([&]() -> int {
+        if (!ops || !R || nops < 1) return fail(BIE_EINVAL, "bad arguments");
+        return bie::batch_unit_chosen(ops, nops, R);
+    });
+}
+
 int bie_farfield(const bie_op *op, const void *X, int64_t R, const double *obs, int64_t M, void *F, void *stream)
 {
     return guarded([&]() -> int {

@@ -76,6 +76,21 @@ struct Packed {
     int64_t part_R = 0;
     size_t part_elem = 0;          // bytes per complex element of the partials buffer
 };
+// One problem of a grouped (several-operator) packed product.
+struct GProb {
+    const void *Z;                 // packed matrix tiles (FP64 or FP32)
+    int64_t N, nT, nslots;
+    const int32_t *units, *unit_ptr;
+    const int64_t *seg;
+};
+// Columns of a grouped product (device tables indexed by column).
+struct GCols {
+    const int32_t *prob;   // problem of column c
+    const int64_t *xoff;   // offset of its input vector (complex elements)
+    const int64_t *yoff;   // offset of its output vector (and of the subtrahend)
+    const int64_t *poff;   // offset of its partial vectors (64-entry vectors)
+    int64_t xstep;         // input at xoff + xstep * N (basis vector xstep of a Krylov basis)
+};
 __host__ __device__ inline int64_t tile_of(int64_t I, int64_t J, int64_t nT)
 {
     return I * nT - I * (I - 1) / 2 + (J - I);
@@ -129,7 +144,16 @@ void farfield(const bie_op *op, const void *X, int64_t R, const double *obs, int
               hipStream_t s);
 
 // blas.hip: products with the packed symmetric matrix.
-void packed_setup(bie_op *op);        // unit table (host -> device)
+void packed_setup(bie_op *op);
+// work units of U tiles along each tile row, and the partial-vector slots
+void build_units(int64_t nT, int U, std::vector<int32_t> &units, std::vector<int32_t> &uptr,
+                 std::vector<int64_t> &seg);
+// Grouped packed product y_c = T_p(c) x_c (or b_c - that) for the columns of
+// several problems: one tile launch over (column, unit) items and one reduce
+// launch over (column, row block) items.  mat64: FP64 tiles, else FP32.
+void grouped_product(bool mat64, const GProb *probs, const GCols &gc, const int32_t *items, int64_t nitems,
+                     const int32_t *ritems, int64_t nritems, const void *X, void *part, void *Y, const void *B,
+                     const int *skip, int64_t sks, hipStream_t s);        // unit table (host -> device)
 void packed_free(bie_op *op);
 // Y = T X, T^H X (conj) or B - T X (B != NULL) for R vectors with the FP64
 // (mat64) or FP32 matrix; vectors complex128 (vec64, FP64 accumulation) or
@@ -149,6 +173,7 @@ void convert_c64_to_c128(const void *src, void *dst, int64_t n, hipStream_t s);
 bool has_nonfinite(const void *x, int64_t n_doubles, hipStream_t s);
 void prof_enable(bool enable);
 void prof_read(int kernel, int64_t *launches, double *total_ms, int64_t *columns);
+bool prof_active();
 void prof_begin(int kernel, hipStream_t s, int64_t ncols);
 void prof_end(int kernel, hipStream_t s);
 // gemm.hip
@@ -176,6 +201,10 @@ void ws_destroy(bie_ws *w);
 void ws_info(const bie_ws *w, int64_t *K, int64_t *H, int64_t *nparams, double *scale, double *loss, double *sigma);
 
 // krylov.hip
+int solve_batch(const bie_op *const *ops, int64_t P, const void *const *B, void *const *X, const int64_t *R,
+                const bie_solve_opts &o, bie_solve_stat *stats, hipStream_t s);
+void batch_config(int unit, int graph);
+int batch_unit_chosen(const bie_op *const *ops, int64_t P, const int64_t *R);
 int solve(const bie_op *op, const void *B, void *X, int64_t R, const bie_solve_opts &o,
           bie_solve_stat *stats, hipStream_t s);
 void free_workspace(bie_op *op);

@@ -64,6 +64,7 @@ void end(int k, hipStream_t s)
 }  // namespace prof
 
 void prof_enable(bool enable) { prof::on = enable; }
+bool prof_active() { return prof::on; }
 void prof_begin(int kernel, hipStream_t s, int64_t ncols) { prof::begin(kernel, s, ncols); }
 void prof_end(int kernel, hipStream_t s) { prof::end(kernel, s); }
 
@@ -161,28 +162,21 @@ __device__ inline void wave_sum8(T pr[8], T pi[8])
     }
 }
 
-// Tile pass.  Writes 64-entry partial vectors (complex T) into the slots of the
-// row block they belong to (see k_sym_reduce).
+// Tile pass of one work unit: tiles (I, J0 .. J1-1) of row block I, the
+// unit being the uo-th of its row.  Writes 64-entry partial vectors (complex
+// T) into the slots of the row block they belong to (see reduce_rows).
 // M: matrix storage type, T: vector and accumulation type (T >= M).
 template <typename M, typename T, bool CONJ, bool PREFETCH>
-__global__ __launch_bounds__(256) void k_sym_tiles(const M *__restrict__ Zp, int64_t N, int64_t nT,
-                                                   const int32_t *__restrict__ units,
-                                                   const int32_t *__restrict__ unit_ptr,
-                                                   const int64_t *__restrict__ seg, int64_t nslots,
-                                                   const T *__restrict__ X, int64_t ldx, T *__restrict__ part,
-                                                   const int *__restrict__ skip, int64_t sks)
+__device__ inline void tile_pass(const M *__restrict__ Zp, int64_t N, int64_t nT, int32_t I, int32_t J0, int32_t J1,
+                                 int64_t uo, const int64_t *__restrict__ seg,
+                                 const typename Cx<T>::type *__restrict__ x, typename Cx<T>::type *__restrict__ pv)
 {
     using V2 = typename Cx<T>::type;
     using MV = typename Cx<M>::type;
-    const int64_t u = blockIdx.x, v = blockIdx.y;
-    if (skip && skip[v * sks]) return;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: x rows in scalar registers
-    const int32_t I = units[3 * u], J0 = units[3 * u + 1], J1 = units[3 * u + 2];
-    const V2 *x = reinterpret_cast<const V2 *>(X) + v * ldx;
     // partials of row block K live in slots seg[K]..: first the column sums of
     // tiles (0..K-1, K), then the row sums of the units of tile row K
-    V2 *pv = reinterpret_cast<V2 *>(part) + v * nslots * TB;
     const MV *Z = reinterpret_cast<const MV *>(Zp);
 
     // x of this wave's 16 rows (the same for every lane)
@@ -254,9 +248,44 @@ __global__ __launch_bounds__(256) void k_sym_tiles(const M *__restrict__ Zp, int
 #pragma unroll
         for (int i = 0; i < 8; ++i) { pr[i] = rar[8 * g + i]; pi[i] = rai[8 * g + i]; }
         wave_sum8(pr, pi);
-        if ((lane & 7) == 0)
-            pv[(seg[I] + I + (u - unit_ptr[I])) * TB + wave * 16 + 8 * g + (lane >> 3)] = V2{ pr[0], pi[0] };
+        if ((lane & 7) == 0) pv[(seg[I] + I + uo) * TB + wave * 16 + 8 * g + (lane >> 3)] = V2{ pr[0], pi[0] };
     }
+}
+
+// Tile pass over the units of one problem: block (unit u, vector v).
+template <typename M, typename T, bool CONJ, bool PREFETCH>
+__global__ __launch_bounds__(256) void k_sym_tiles(const M *__restrict__ Zp, int64_t N, int64_t nT,
+                                                   const int32_t *__restrict__ units,
+                                                   const int32_t *__restrict__ unit_ptr,
+                                                   const int64_t *__restrict__ seg, int64_t nslots,
+                                                   const T *__restrict__ X, int64_t ldx, T *__restrict__ part,
+                                                   const int *__restrict__ skip, int64_t sks)
+{
+    using V2 = typename Cx<T>::type;
+    const int64_t u = blockIdx.x, v = blockIdx.y;
+    if (skip && skip[v * sks]) return;
+    const int32_t I = units[3 * u], J0 = units[3 * u + 1], J1 = units[3 * u + 2];
+    tile_pass<M, T, CONJ, PREFETCH>(Zp, N, nT, I, J0, J1, u - unit_ptr[I], seg,
+                                    reinterpret_cast<const V2 *>(X) + v * ldx,
+                                    reinterpret_cast<V2 *>(part) + v * nslots * TB);
+}
+
+// Grouped tile pass over several problems: block b is the work item
+// (column c, unit u of the problem of c).
+template <typename M, typename T, bool PREFETCH>
+__global__ __launch_bounds__(256) void k_sym_tiles_g(const GProb *__restrict__ probs, GCols gc,
+                                                     const int32_t *__restrict__ items, const T *__restrict__ X,
+                                                     T *__restrict__ part, const int *__restrict__ skip, int64_t sks)
+{
+    using V2 = typename Cx<T>::type;
+    const int64_t b = blockIdx.x;
+    const int32_t c = items[2 * b], u = items[2 * b + 1];
+    if (skip && skip[int64_t(c) * sks]) return;
+    const GProb P = probs[gc.prob[c]];
+    const int32_t I = P.units[3 * u], J0 = P.units[3 * u + 1], J1 = P.units[3 * u + 2];
+    tile_pass<M, T, false, PREFETCH>(static_cast<const M *>(P.Z), P.N, P.nT, I, J0, J1, u - P.unit_ptr[I], P.seg,
+                                     reinterpret_cast<const V2 *>(X) + gc.xoff[c] + gc.xstep * P.N,
+                                     reinterpret_cast<V2 *>(part) + gc.poff[c] * TB);
 }
 
 // y_I = sum of the partial vectors of row block I (column sums of tiles
@@ -264,16 +293,13 @@ __global__ __launch_bounds__(256) void k_sym_tiles(const M *__restrict__ Zp, int
 // Eight waves split the vectors (every eighth one) and their sums are added in
 // wave order (deterministic).
 template <typename T, bool SUB>
-__global__ __launch_bounds__(512) void k_sym_reduce(int64_t N, const int64_t *__restrict__ seg, int64_t nslots,
-                                                    const T *__restrict__ part, T *__restrict__ Y, int64_t ldy,
-                                                    const T *__restrict__ B, int64_t ldb,
-                                                    const int *__restrict__ skip, int64_t sks)
+__device__ inline void reduce_rows(int64_t N, const int64_t *__restrict__ seg, int64_t I,
+                                   const typename Cx<T>::type *__restrict__ pv, typename Cx<T>::type *__restrict__ y,
+                                   const typename Cx<T>::type *__restrict__ b)
 {
     using V2 = typename Cx<T>::type;
-    const int64_t I = blockIdx.x, v = blockIdx.y;
-    if (skip && skip[v * sks]) return;
     const int r = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const V2 *pv = reinterpret_cast<const V2 *>(part) + (v * nslots + seg[I]) * TB;
+    pv += seg[I] * TB;
     const int64_t K = seg[I + 1] - seg[I];
     V2 a = { 0, 0 };
 #pragma unroll 4
@@ -287,10 +313,39 @@ __global__ __launch_bounds__(512) void k_sym_reduce(int64_t N, const int64_t *__
     for (int q = 1; q < 8; ++q) a += red[q][r];
     const int64_t m = I * TB + r;
     if (m < N) {
-        V2 *y = reinterpret_cast<V2 *>(Y) + v * ldy;
-        if (SUB) y[m] = reinterpret_cast<const V2 *>(B)[v * ldb + m] - a;
+        if (SUB) y[m] = b[m] - a;
         else y[m] = a;
     }
+}
+
+template <typename T, bool SUB>
+__global__ __launch_bounds__(512) void k_sym_reduce(int64_t N, const int64_t *__restrict__ seg, int64_t nslots,
+                                                    const T *__restrict__ part, T *__restrict__ Y, int64_t ldy,
+                                                    const T *__restrict__ B, int64_t ldb,
+                                                    const int *__restrict__ skip, int64_t sks)
+{
+    using V2 = typename Cx<T>::type;
+    const int64_t I = blockIdx.x, v = blockIdx.y;
+    if (skip && skip[v * sks]) return;
+    reduce_rows<T, SUB>(N, seg, I, reinterpret_cast<const V2 *>(part) + v * nslots * TB,
+                        reinterpret_cast<V2 *>(Y) + v * ldy, SUB ? reinterpret_cast<const V2 *>(B) + v * ldb : nullptr);
+}
+
+// Grouped reduce: block b is the item (column c, row block I).
+template <typename T, bool SUB>
+__global__ __launch_bounds__(512) void k_sym_reduce_g(const GProb *__restrict__ probs, GCols gc,
+                                                      const int32_t *__restrict__ items, const T *__restrict__ part,
+                                                      T *__restrict__ Y, const T *__restrict__ B,
+                                                      const int *__restrict__ skip, int64_t sks)
+{
+    using V2 = typename Cx<T>::type;
+    const int64_t b = blockIdx.x;
+    const int32_t c = items[2 * b], I = items[2 * b + 1];
+    if (skip && skip[int64_t(c) * sks]) return;
+    const GProb P = probs[gc.prob[c]];
+    reduce_rows<T, SUB>(P.N, P.seg, I, reinterpret_cast<const V2 *>(part) + gc.poff[c] * TB,
+                        reinterpret_cast<V2 *>(Y) + gc.yoff[c],
+                        SUB ? reinterpret_cast<const V2 *>(B) + gc.yoff[c] : nullptr);
 }
 
 template <typename T>
@@ -390,26 +445,34 @@ void launch_product(const bie_op *op, const void *Z, const void *X, int64_t ldx,
 
 }  // namespace
 
+void build_units(int64_t nT, int U, std::vector<int32_t> &units, std::vector<int32_t> &uptr,
+                 std::vector<int64_t> &seg)
+{
+    units.clear();
+    uptr.assign(nT + 1, 0);
+    for (int64_t I = 0; I < nT; ++I) {
+        uptr[I] = int32_t(units.size() / 3);
+        for (int64_t J0 = I; J0 < nT; J0 += U) {
+            units.push_back(int32_t(I));
+            units.push_back(int32_t(J0));
+            units.push_back(int32_t(std::min<int64_t>(nT, J0 + U)));
+        }
+    }
+    uptr[nT] = int32_t(units.size() / 3);
+    seg.assign(nT + 1, 0);
+    for (int64_t I = 0; I < nT; ++I) seg[I + 1] = seg[I] + I + (uptr[I + 1] - uptr[I]);
+}
+
 void packed_setup(bie_op *op)
 {
     Packed &pk = op->pk;
     pk.N = op->mesh.N;
     pk.nT = (pk.N + TB - 1) / TB;
     pk.ntiles = pk.nT * (pk.nT + 1) / 2;
-    std::vector<int32_t> units, uptr(pk.nT + 1, 0);
-    for (int64_t I = 0; I < pk.nT; ++I) {
-        uptr[I] = int32_t(units.size() / 3);
-        const int ut = unit_tiles();
-        for (int64_t J0 = I; J0 < pk.nT; J0 += ut) {
-            units.push_back(int32_t(I));
-            units.push_back(int32_t(J0));
-            units.push_back(int32_t(std::min<int64_t>(pk.nT, J0 + ut)));
-        }
-    }
-    uptr[pk.nT] = int32_t(units.size() / 3);
+    std::vector<int32_t> units, uptr;
+    std::vector<int64_t> seg;
+    build_units(pk.nT, unit_tiles(), units, uptr, seg);
     pk.nunits = int64_t(units.size() / 3);
-    std::vector<int64_t> seg(pk.nT + 1, 0);
-    for (int64_t I = 0; I < pk.nT; ++I) seg[I + 1] = seg[I] + I + (uptr[I + 1] - uptr[I]);
     pk.nslots = seg[pk.nT];
     BIE_HIP(hipMalloc(&pk.seg, seg.size() * sizeof(int64_t)));
     BIE_HIP(hipMemcpy(pk.seg, seg.data(), seg.size() * sizeof(int64_t), hipMemcpyHostToDevice));
@@ -467,6 +530,30 @@ void product(const bie_op *opc, int mat, bool vec64, const void *X, int64_t ldx,
     if (mat64) dispatch<double, double>(op, Z, X, ldx, Y, ldy, B, ldb, R, skip, sks, conj, s);
     else if (vec64) dispatch<float, double>(op, Z, X, ldx, Y, ldy, B, ldb, R, skip, sks, conj, s);
     else dispatch<float, float>(op, Z, X, ldx, Y, ldy, B, ldb, R, skip, sks, conj, s);
+}
+
+void grouped_product(bool mat64, const GProb *probs, const GCols &gc, const int32_t *items, int64_t nitems,
+                     const int32_t *ritems, int64_t nritems, const void *X, void *part, void *Y, const void *B,
+                     const int *skip, int64_t sks, hipStream_t s)
+{
+    if (nitems == 0) return;
+    const bool pf = sym_prefetch() != 0;
+    if (mat64) {
+        if (pf) hipLaunchKernelGGL((k_sym_tiles_g<double, double, true>), dim3(unsigned(nitems)), dim3(256), 0, s, probs,
+                                   gc, items, (const double *)X, (double *)part, skip, sks);
+        else hipLaunchKernelGGL((k_sym_tiles_g<double, double, false>), dim3(unsigned(nitems)), dim3(256), 0, s,
+                                probs, gc, items, (const double *)X, (double *)part, skip, sks);
+    } else {
+        if (pf) hipLaunchKernelGGL((k_sym_tiles_g<float, double, true>), dim3(unsigned(nitems)), dim3(256), 0, s, probs,
+                                   gc, items, (const double *)X, (double *)part, skip, sks);
+        else hipLaunchKernelGGL((k_sym_tiles_g<float, double, false>), dim3(unsigned(nitems)), dim3(256), 0, s, probs,
+                                gc, items, (const double *)X, (double *)part, skip, sks);
+    }
+    if (B) hipLaunchKernelGGL((k_sym_reduce_g<double, true>), dim3(unsigned(nritems)), dim3(512), 0, s, probs, gc,
+                              ritems, (const double *)part, (double *)Y, (const double *)B, skip, sks);
+    else hipLaunchKernelGGL((k_sym_reduce_g<double, false>), dim3(unsigned(nritems)), dim3(512), 0, s, probs, gc,
+                            ritems, (const double *)part, (double *)Y, nullptr, skip, sks);
+    BIE_HIP(hipGetLastError());
 }
 
 void unpack_c128(const bie_op *op, bool from64, void *dst, hipStream_t s)

@@ -29,6 +29,11 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "bie_internal.hpp"
@@ -68,6 +73,23 @@ struct ColStat {
     int pad;
 };
 static_assert(sizeof(ColStat) == 96, "ColStat layout");
+
+// Where the vectors of column r live.  One problem (uniform): length N, basis
+// at r (m+1) N, vectors at r N, chunk partials at r nc(N).  Several problems
+// of different sizes (batched solves): per-column tables of length and
+// offsets, so that one launch serves columns of every problem.
+struct Cols {
+    const int64_t *n = nullptr;      // length of column r (null: N)
+    const int64_t *voff = nullptr;   // offset of its Krylov basis (elements)
+    const int64_t *woff = nullptr;   // offset of its vectors (W, residual, solution)
+    const int64_t *poff = nullptr;   // offset of its chunk partial sums
+    int64_t N = 0;
+    int m = 0;
+    __device__ int64_t len(int r) const { return n ? n[r] : N; }
+    __device__ int64_t vo(int r) const { return voff ? voff[r] : int64_t(r) * (m + 1) * N; }
+    __device__ int64_t wo(int r) const { return woff ? woff[r] : int64_t(r) * N; }
+    __device__ int64_t po(int r) const;
+};
 
 __device__ inline double2 cmul(double2 a, double2 b)
 {
@@ -214,6 +236,8 @@ __device__ inline void chunk_dots(const double2 *__restrict__ V, int64_t N, int6
 constexpr int AB = 256;   // elements (threads) per block in the Arnoldi kernels
 constexpr int KG = 8;     // basis vectors per block in the first pass
 
+__device__ inline int64_t Cols::po(int r) const { return poff ? poff[r] : int64_t(r) * ((N + AB - 1) / AB); }
+
 // element q of thread t in block b (coalesced): (b EPT + q) AB + t
 template <int EPT>
 __device__ inline int64_t elem(int q)
@@ -222,7 +246,7 @@ __device__ inline int64_t elem(int q)
 }
 
 template <typename VT, int EPT>
-__global__ __launch_bounds__(AB) void k_cgs_pass1(int64_t N, int m, int j, const VT *__restrict__ Vall,
+__global__ __launch_bounds__(AB) void k_cgs_pass1(Cols cl, int m, int j, const VT *__restrict__ Vall,
                                                   const double2 *__restrict__ Wall, double2 *__restrict__ P1all,
                                                   double *__restrict__ PWall, const ColStat *__restrict__ st)
 {
@@ -230,8 +254,13 @@ __global__ __launch_bounds__(AB) void k_cgs_pass1(int64_t N, int m, int j, const
     if (st[r].done) return;
     const int k0 = blockIdx.y * KG;
     if (k0 > j) return;
+    const int64_t N = cl.len(r);
+    if (int64_t(blockIdx.x) * EPT * AB >= N) return;   // beyond this column
     const int nc = int((N + AB - 1) / AB);   // chunks of AB elements
-    const VT *V = Vall + int64_t(r) * (m + 1) * N;
+    const VT *V = Vall + cl.vo(r);
+    Wall += cl.wo(r);
+    P1all += cl.po(r) * (m + 1);
+    PWall += cl.po(r);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     __shared__ double2 red[EPT][KG][AB / 64];
     __shared__ double rn[EPT][AB / 64];
@@ -240,7 +269,7 @@ __global__ __launch_bounds__(AB) void k_cgs_pass1(int64_t N, int m, int j, const
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
         const int64_t e = elem<EPT>(q);
-        w[q] = e < N ? Wall[int64_t(r) * N + e] : make_double2(0.0, 0.0);
+        w[q] = e < N ? Wall[e] : make_double2(0.0, 0.0);
 #pragma unroll
         for (int i = 0; i < KG; ++i)
             vv[q][i] = (e < N && k0 + i <= j) ? ld2(V[int64_t(k0 + i) * N + e]) : make_double2(0.0, 0.0);
@@ -262,14 +291,13 @@ __global__ __launch_bounds__(AB) void k_cgs_pass1(int64_t N, int m, int j, const
     for (int q = 0; q < EPT; ++q) {
         const int c = int(blockIdx.x) * EPT + q;
         if (c >= nc) break;
-        double2 *P1 = P1all + (int64_t(r) * nc + c) * (m + 1);
+        double2 *P1 = P1all + int64_t(c) * (m + 1);
         if (threadIdx.x < KG && k0 + int(threadIdx.x) <= j) {
             double2 a = red[q][threadIdx.x][0];
             for (int u = 1; u < AB / 64; ++u) { a.x += red[q][threadIdx.x][u].x; a.y += red[q][threadIdx.x][u].y; }
             P1[k0 + threadIdx.x] = a;
         }
-        if (blockIdx.y == 0 && threadIdx.x == 0)
-            PWall[int64_t(r) * nc + c] = rn[q][0] + rn[q][1] + rn[q][2] + rn[q][3];
+        if (blockIdx.y == 0 && threadIdx.x == 0) PWall[c] = rn[q][0] + rn[q][1] + rn[q][2] + rn[q][3];
     }
 }
 
@@ -325,7 +353,7 @@ __device__ inline void cgs_update(const VT *__restrict__ V, int64_t N, const int
 }
 
 template <typename VT, int EPT>
-__global__ __launch_bounds__(AB) void k_cgs_pass2(int64_t N, int m, int j, const VT *__restrict__ Vall,
+__global__ __launch_bounds__(AB) void k_cgs_pass2(Cols cl, int m, int j, const VT *__restrict__ Vall,
                                                   double2 *__restrict__ Wall, const double2 *__restrict__ P1all,
                                                   const double *__restrict__ PWall, double2 *__restrict__ P2all,
                                                   double *__restrict__ PNall, double2 *__restrict__ Hall,
@@ -333,13 +361,20 @@ __global__ __launch_bounds__(AB) void k_cgs_pass2(int64_t N, int m, int j, const
 {
     const int r = blockIdx.y;
     if (st[r].done) return;
+    const int64_t N = cl.len(r);
+    if (int64_t(blockIdx.x) * EPT * AB >= N) return;   // beyond this column
     const int nc = int((N + AB - 1) / AB);
+    Wall += cl.wo(r);
+    P1all += cl.po(r) * (m + 1);
+    P2all += cl.po(r) * (m + 1);
+    PWall += cl.po(r);
+    PNall += cl.po(r);
     __shared__ double2 h[MAXM + 1];
     __shared__ int s_reorth;
     __shared__ double s_w2;
-    sum_partials(P1all + int64_t(r) * nc * (m + 1), nc, m + 1, j, h);
+    sum_partials(P1all, nc, m + 1, j, h);
     if (threadIdx.x < 64) {
-        const double w2 = sum_real_partials(PWall + int64_t(r) * nc, nc);
+        const double w2 = sum_real_partials(PWall, nc);
         if (threadIdx.x == 0) s_w2 = w2;
     }
     __syncthreads();
@@ -355,19 +390,19 @@ __global__ __launch_bounds__(AB) void k_cgs_pass2(int64_t N, int m, int j, const
         for (int k = threadIdx.x; k <= j; k += AB) Hall[(int64_t(r) * m + j) * (m + 1) + k] = h[k];
         if (threadIdx.x == 0) st[r].reorth = reorth;
     }
-    const VT *V = Vall + int64_t(r) * (m + 1) * N;
+    const VT *V = Vall + cl.vo(r);
     int64_t e[EPT];
     double2 w[EPT];
     __shared__ double rn[EPT][AB / 64];
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
         e[q] = elem<EPT>(q);
-        w[q] = e[q] < N ? Wall[int64_t(r) * N + e[q]] : make_double2(0.0, 0.0);
+        w[q] = e[q] < N ? Wall[e[q]] : make_double2(0.0, 0.0);
     }
     cgs_update<VT, EPT>(V, N, e, j, w, h);
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
-        if (e[q] < N) Wall[int64_t(r) * N + e[q]] = w[q];
+        if (e[q] < N) Wall[e[q]] = w[q];
         const double nn = wsum(w[q].x * w[q].x + w[q].y * w[q].y);
         if ((threadIdx.x & 63) == 0) rn[q][threadIdx.x >> 6] = nn;
     }
@@ -379,7 +414,7 @@ __global__ __launch_bounds__(AB) void k_cgs_pass2(int64_t N, int m, int j, const
         for (int q = 0; q < EPT; ++q) {
             const int c = int(blockIdx.x) * EPT + q;
             if (c >= nc) break;
-            double2 *P2 = P2all + (int64_t(r) * nc + c) * (m + 1);
+            double2 *P2 = P2all + int64_t(c) * (m + 1);
             for (int k = threadIdx.x; k <= j; k += AB) {
                 double2 a = red[q][k][0];
                 for (int u = 1; u < AB / 64; ++u) { a.x += red[q][k][u].x; a.y += red[q][k][u].y; }
@@ -393,21 +428,26 @@ __global__ __launch_bounds__(AB) void k_cgs_pass2(int64_t N, int m, int j, const
 #pragma unroll
         for (int q = 0; q < EPT; ++q) {
             const int c = int(blockIdx.x) * EPT + q;
-            if (c < nc) PNall[int64_t(r) * nc + c] = rn[q][0] + rn[q][1] + rn[q][2] + rn[q][3];
+            if (c < nc) PNall[c] = rn[q][0] + rn[q][1] + rn[q][2] + rn[q][3];
         }
 }
 
 template <typename VT, int EPT>
-__global__ __launch_bounds__(AB) void k_cgs_pass3(int64_t N, int m, int j, const VT *__restrict__ Vall,
+__global__ __launch_bounds__(AB) void k_cgs_pass3(Cols cl, int m, int j, const VT *__restrict__ Vall,
                                                   double2 *__restrict__ Wall, const double2 *__restrict__ P2all,
                                                   double *__restrict__ PNall, double2 *__restrict__ Hall,
                                                   const ColStat *__restrict__ st)
 {
     const int r = blockIdx.y;
     if (st[r].done || !st[r].reorth) return;
+    const int64_t N = cl.len(r);
+    if (int64_t(blockIdx.x) * EPT * AB >= N) return;   // beyond this column
     const int nc = int((N + AB - 1) / AB);
+    Wall += cl.wo(r);
+    P2all += cl.po(r) * (m + 1);
+    PNall += cl.po(r);
     __shared__ double2 h[MAXM + 1];
-    sum_partials(P2all + int64_t(r) * nc * (m + 1), nc, m + 1, j, h);
+    sum_partials(P2all, nc, m + 1, j, h);
     __syncthreads();
     if (blockIdx.x == 0)
         for (int k = threadIdx.x; k <= j; k += AB) {
@@ -415,21 +455,21 @@ __global__ __launch_bounds__(AB) void k_cgs_pass3(int64_t N, int m, int j, const
             const double2 a = *hc;
             *hc = make_double2(a.x + h[k].x, a.y + h[k].y);
         }
-    const VT *V = Vall + int64_t(r) * (m + 1) * N;
+    const VT *V = Vall + cl.vo(r);
     __shared__ double red[EPT][AB / 64];
     int64_t e[EPT];
     double2 w[EPT];
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
         e[q] = elem<EPT>(q);
-        w[q] = e[q] < N ? Wall[int64_t(r) * N + e[q]] : make_double2(0.0, 0.0);
+        w[q] = e[q] < N ? Wall[e[q]] : make_double2(0.0, 0.0);
     }
     cgs_update<VT, EPT>(V, N, e, j, w, h);
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
         double nn = 0.0;
         if (e[q] < N) {
-            Wall[int64_t(r) * N + e[q]] = w[q];
+            Wall[e[q]] = w[q];
             nn = w[q].x * w[q].x + w[q].y * w[q].y;
         }
         nn = wsum(nn);
@@ -440,7 +480,7 @@ __global__ __launch_bounds__(AB) void k_cgs_pass3(int64_t N, int m, int j, const
 #pragma unroll
         for (int q = 0; q < EPT; ++q) {
             const int c = int(blockIdx.x) * EPT + q;
-            if (c < nc) PNall[int64_t(r) * nc + c] = red[q][0] + red[q][1] + red[q][2] + red[q][3];
+            if (c < nc) PNall[c] = red[q][0] + red[q][1] + red[q][2] + red[q][3];
         }
 }
 
@@ -457,7 +497,7 @@ __device__ inline void givens(double2 a, double2 b, double &c, double2 &s)
 }
 
 template <typename VT, int EPT>
-__global__ __launch_bounds__(AB) void k_cgs_finish(int64_t N, int m, int j, double tol, VT *__restrict__ Vall,
+__global__ __launch_bounds__(AB) void k_cgs_finish(Cols cl, int m, int j, double tol, VT *__restrict__ Vall,
                                                    const double2 *__restrict__ Wall, const double *__restrict__ PNall,
                                                    const double *__restrict__ PWall, double2 *__restrict__ Hall,
                                                    double *__restrict__ csall, double2 *__restrict__ snall,
@@ -465,13 +505,18 @@ __global__ __launch_bounds__(AB) void k_cgs_finish(int64_t N, int m, int j, doub
 {
     const int r = blockIdx.y;
     if (st[r].done) return;
+    const int64_t N = cl.len(r);
+    if (int64_t(blockIdx.x) * EPT * AB >= N) return;   // beyond this column (block 0 never is)
     const int nc = int((N + AB - 1) / AB);
+    Wall += cl.wo(r);
+    PNall += cl.po(r);
+    PWall += cl.po(r);
     __shared__ double s_hn, s_w2;
     __shared__ double2 Hc[MAXM + 2], sn[MAXM];
     __shared__ double cs[MAXM];
     if (threadIdx.x < 64) {
-        const double a = sum_real_partials(PNall + int64_t(r) * nc, nc);
-        const double b = sum_real_partials(PWall + int64_t(r) * nc, nc);
+        const double a = sum_real_partials(PNall, nc);
+        const double b = sum_real_partials(PWall, nc);
         if (threadIdx.x == 0) { s_hn = sqrt(a); s_w2 = b; }
     }
     if (blockIdx.x == 0) {
@@ -489,8 +534,8 @@ __global__ __launch_bounds__(AB) void k_cgs_finish(int64_t N, int m, int j, doub
         for (int q = 0; q < EPT; ++q) {
             const int64_t e = elem<EPT>(q);
             if (e < N) {
-                const double2 w = Wall[int64_t(r) * N + e];
-                Vall[(int64_t(r) * (m + 1) + j + 1) * N + e] = st2<VT>(make_double2(w.x * inv, w.y * inv));
+                const double2 w = Wall[e];
+                Vall[cl.vo(r) + int64_t(j + 1) * N + e] = st2<VT>(make_double2(w.x * inv, w.y * inv));
             }
         }
     }
@@ -564,37 +609,40 @@ __global__ __launch_bounds__(64) void k_lsq(int m, const double2 *__restrict__ H
 
 // x += V_{0..jend-1} y
 template <typename VT>
-__global__ __launch_bounds__(BT) void k_xupd(int64_t N, int m, const VT *__restrict__ Vall,
+__global__ __launch_bounds__(BT) void k_xupd(Cols cl, int m, const VT *__restrict__ Vall,
                                              const double2 *__restrict__ yall, double2 *__restrict__ X,
                                              const ColStat *__restrict__ st)
 {
     const int r = blockIdx.y;
     if (!st[r].active) return;
+    const int64_t N = cl.len(r);
+    X += cl.wo(r);
     const int je = st[r].jend;
     __shared__ double2 sy[MAXM];
     if (threadIdx.x < je) sy[threadIdx.x] = yall[int64_t(r) * m + threadIdx.x];
     __syncthreads();
-    const VT *V = Vall + int64_t(r) * (m + 1) * N;
+    const VT *V = Vall + cl.vo(r);
     for (int64_t e = int64_t(blockIdx.x) * BT + threadIdx.x; e < N; e += int64_t(gridDim.x) * BT) {
-        double2 x = X[int64_t(r) * N + e];
+        double2 x = X[e];
         for (int k = 0; k < je; ++k) {
             const double2 p = cmul(ld2(V[int64_t(k) * N + e]), sy[k]);
             x.x += p.x;
             x.y += p.y;
         }
-        X[int64_t(r) * N + e] = x;
+        X[e] = x;
     }
 }
 
 // ||v||^2 per column with last-block finish; writes sqrt into the field at `off`.
-__global__ __launch_bounds__(BT) void k_norm(int64_t N, const double2 *__restrict__ Vb, int64_t ld,
-                                             double *__restrict__ part, unsigned *__restrict__ counters,
-                                             ColStat *__restrict__ st, int field, const int *__restrict__ mask)
+__global__ __launch_bounds__(BT) void k_norm(Cols cl, const double2 *__restrict__ Vb, double *__restrict__ part,
+                                             unsigned *__restrict__ counters, ColStat *__restrict__ st, int field,
+                                             const int *__restrict__ mask)
 {
     const int r = blockIdx.y;
     if (mask && !mask[r]) return;
     const unsigned nblk = gridDim.x;
-    const double2 *v = Vb + int64_t(r) * ld;
+    const int64_t N = cl.len(r);
+    const double2 *v = Vb + cl.wo(r);
     double nn = 0.0;
     for (int t = threadIdx.x; t < BE; t += BT) {
         const int64_t e = int64_t(blockIdx.x) * BE + t;
@@ -615,7 +663,7 @@ __global__ __launch_bounds__(BT) void k_norm(int64_t N, const double2 *__restric
 
 // Start a cycle from the residual: v0 = res/||res||, g = (||res||, 0, ...).
 template <typename VT>
-__global__ __launch_bounds__(BT) void k_restart(int64_t N, int m, const double2 *__restrict__ Res,
+__global__ __launch_bounds__(BT) void k_restart(Cols cl, int m, const double2 *__restrict__ Res,
                                                 VT *__restrict__ Vall, double2 *__restrict__ gall,
                                                 ColStat *__restrict__ st, const int *__restrict__ mask)
 {
@@ -623,9 +671,11 @@ __global__ __launch_bounds__(BT) void k_restart(int64_t N, int m, const double2 
     if (!mask[r]) return;
     const double beta = st[r].rnorm;
     const double inv = 1.0 / beta;
-    VT *v = Vall + int64_t(r) * (m + 1) * N;
+    const int64_t N = cl.len(r);
+    VT *v = Vall + cl.vo(r);
+    Res += cl.wo(r);
     for (int64_t e = int64_t(blockIdx.x) * BT + threadIdx.x; e < N; e += int64_t(gridDim.x) * BT) {
-        const double2 w = Res[int64_t(r) * N + e];
+        const double2 w = Res[e];
         v[e] = st2<VT>(make_double2(w.x * inv, w.y * inv));
     }
     if (blockIdx.x == 0 && threadIdx.x <= m)
@@ -797,24 +847,36 @@ struct Workspace {
 // element per thread: on 256 columns of 7680 unknowns this beat 2 and 4
 // elements per thread (fewer loads in flight across the chip), although those
 // add 2-4x fewer partial sums per block; the results are the same bitwise.
+// Nmax: the longest column (grid size; shorter columns leave their extra
+// blocks at once).
 template <typename VT, int EPT>
-static void arnoldi_launch(Workspace *w, VT *V, int64_t N, int m, int j, double tol, int64_t R, hipStream_t s)
+static void arnoldi_launch(Workspace *w, const Cols &cl, int64_t Nmax, VT *V, int m, int j, double tol, int64_t R,
+                           hipStream_t s)
 {
-    const unsigned nb = unsigned((N + AB * EPT - 1) / (AB * EPT));
+    const unsigned nb = unsigned((Nmax + AB * EPT - 1) / (AB * EPT));
     const dim3 agrid(nb, unsigned(R));
     const dim3 pgrid(nb, unsigned((m + 1 + KG - 1) / KG), unsigned(R));
-    hipLaunchKernelGGL((k_cgs_pass1<VT, EPT>), pgrid, dim3(AB), 0, s, N, m, j, V, w->W, w->P1, w->PW, w->st);
-    hipLaunchKernelGGL((k_cgs_pass2<VT, EPT>), agrid, dim3(AB), 0, s, N, m, j, V, w->W, w->P1, w->PW, w->P2, w->PN,
+    hipLaunchKernelGGL((k_cgs_pass1<VT, EPT>), pgrid, dim3(AB), 0, s, cl, m, j, V, w->W, w->P1, w->PW, w->st);
+    hipLaunchKernelGGL((k_cgs_pass2<VT, EPT>), agrid, dim3(AB), 0, s, cl, m, j, V, w->W, w->P1, w->PW, w->P2, w->PN,
                        w->H, w->st);
-    hipLaunchKernelGGL((k_cgs_pass3<VT, EPT>), agrid, dim3(AB), 0, s, N, m, j, V, w->W, w->P2, w->PN, w->H, w->st);
-    hipLaunchKernelGGL((k_cgs_finish<VT, EPT>), agrid, dim3(AB), 0, s, N, m, j, tol, V, w->W, w->PN, w->PW, w->H,
+    hipLaunchKernelGGL((k_cgs_pass3<VT, EPT>), agrid, dim3(AB), 0, s, cl, m, j, V, w->W, w->P2, w->PN, w->H, w->st);
+    hipLaunchKernelGGL((k_cgs_finish<VT, EPT>), agrid, dim3(AB), 0, s, cl, m, j, tol, V, w->W, w->PN, w->PW, w->H,
                        w->cs, w->sn, w->g, w->st);
     BIE_HIP(hipGetLastError());
 }
 template <typename VT>
-static void arnoldi_step(Workspace *w, VT *V, int64_t N, int m, int j, double tol, int64_t R, hipStream_t s)
+static void arnoldi_step(Workspace *w, const Cols &cl, int64_t Nmax, VT *V, int m, int j, double tol, int64_t R,
+                         hipStream_t s)
 {
-    arnoldi_launch<VT, 1>(w, V, N, m, j, tol, R, s);
+    arnoldi_launch<VT, 1>(w, cl, Nmax, V, m, j, tol, R, s);
+}
+
+static Cols uniform_cols(int64_t N, int m)
+{
+    Cols c;
+    c.N = N;
+    c.m = m;
+    return c;
 }
 
 static constexpr int MAX_RSCC_ROWS = 4096;
@@ -882,6 +944,7 @@ static int solve_impl(const bie_op *opc, const void *Bv, void *Xv, int64_t R, co
     const int fp64 = mat;   // matrix of the products (MAT64 / MAT32 / MATBF16)
     const int m = o.method == BIE_GMRES ? o.restart : 1;
     Workspace *w = get_ws(op, R, m);
+    const Cols ucols = uniform_cols(N, m);
     const double2 *B = static_cast<const double2 *>(Bv);
     double2 *X = static_cast<double2 *>(Xv);
     std::vector<bie_solve_stat> hs(R);
@@ -913,7 +976,7 @@ static int solve_impl(const bie_op *opc, const void *Bv, void *Xv, int64_t R, co
         st[r].active = 1;
     }
     push_st();
-    hipLaunchKernelGGL(k_norm, vgrid, dim3(BT), 0, s, N, B, N, w->dpart, w->counters, w->st, field_bnorm,
+    hipLaunchKernelGGL(k_norm, vgrid, dim3(BT), 0, s, ucols, B, w->dpart, w->counters, w->st, field_bnorm,
                        (const int *)nullptr);
     BIE_HIP(hipGetLastError());
     if (!o.use_x0) hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, s, R * N, X);
@@ -937,7 +1000,7 @@ static int solve_impl(const bie_op *opc, const void *Bv, void *Xv, int64_t R, co
         product(op, fp64, true, X, N, w->Res, N, B, N, R, dskip, 1, false, s);
         // k_norm mask: need
         push_skip(need);
-        hipLaunchKernelGGL(k_norm, vgrid, dim3(BT), 0, s, N, w->Res, N, w->dpart, w->counters, w->st, field_rnorm,
+        hipLaunchKernelGGL(k_norm, vgrid, dim3(BT), 0, s, ucols, w->Res, w->dpart, w->counters, w->st, field_rnorm,
                            (const int *)dskip);
         BIE_HIP(hipGetLastError());
         for (int64_t r = 0; r < R; ++r)
@@ -1014,7 +1077,7 @@ static int solve_impl(const bie_op *opc, const void *Bv, void *Xv, int64_t R, co
                 }
             if (any) {
                 push_skip(back);
-                hipLaunchKernelGGL(k_norm, vgrid, dim3(BT), 0, s, N, w->Res, N, w->dpart, w->counters, w->st,
+                hipLaunchKernelGGL(k_norm, vgrid, dim3(BT), 0, s, ucols, w->Res, w->dpart, w->counters, w->st,
                                    field_rnorm, (const int *)dskip);
             }
         }
@@ -1024,7 +1087,7 @@ static int solve_impl(const bie_op *opc, const void *Bv, void *Xv, int64_t R, co
                 hipLaunchKernelGGL(k_copy, dim3(64), dim3(256), 0, s, N, B + r * N, w->Res + r * N);
         for (int64_t r = 0; r < R; ++r) need[r] = active[r];
         push_skip(need);
-        hipLaunchKernelGGL(k_norm, vgrid, dim3(BT), 0, s, N, w->Res, N, w->dpart, w->counters, w->st, field_rnorm,
+        hipLaunchKernelGGL(k_norm, vgrid, dim3(BT), 0, s, ucols, w->Res, w->dpart, w->counters, w->st, field_rnorm,
                            (const int *)dskip);
     }
     pull_st();
@@ -1058,7 +1121,7 @@ static int solve_impl(const bie_op *opc, const void *Bv, void *Xv, int64_t R, co
             }
             push_st();
             push_skip(need);
-            hipLaunchKernelGGL(k_restart<double2>, egrid, dim3(BT), 0, s, N, m, w->Res, w->V, w->g, w->st, (const int *)dskip);
+            hipLaunchKernelGGL(k_restart<double2>, egrid, dim3(BT), 0, s, ucols, m, w->Res, w->V, w->g, w->st, (const int *)dskip);
             BIE_HIP(hipGetLastError());
             int jmax = 0;
             for (int64_t r = 0; r < R; ++r)
@@ -1066,11 +1129,11 @@ static int solve_impl(const bie_op *opc, const void *Bv, void *Xv, int64_t R, co
             for (int j = 0; j < jmax; ++j) {
                 product(op, fp64, true, w->V + int64_t(j) * N, int64_t(m + 1) * N, w->W, N, nullptr, 0, R,
                         done_flags, done_stride, false, s);
-                arnoldi_step<double2>(w, w->V, N, m, j, o.tol, R, s);
+                arnoldi_step<double2>(w, ucols, N, w->V, m, j, o.tol, R, s);
             }
             hipLaunchKernelGGL(k_lsq, dim3(unsigned(R)), dim3(64), size_t(m) * m * sizeof(double2), s, m, w->H, w->g,
                                w->y, w->st);
-            hipLaunchKernelGGL(k_xupd<double2>, egrid, dim3(BT), 0, s, N, m, w->V, w->y, X, w->st);
+            hipLaunchKernelGGL(k_xupd<double2>, egrid, dim3(BT), 0, s, ucols, m, w->V, w->y, X, w->st);
             BIE_HIP(hipGetLastError());
             pull_st();
             std::vector<int> cand(R, 0);
@@ -1283,6 +1346,7 @@ static int solve_stream(const bie_op *opc, const void *Bv, void *Xv, int64_t R, 
     const int m = o.restart;
     const int64_t W = o.slots > 0 ? std::min<int64_t>(o.slots, R) : R;
     Workspace *w = get_ws(op, W, m);
+    const Cols ucols = uniform_cols(N, m);
     const double2 *B = static_cast<const double2 *>(Bv);
     double2 *X = static_cast<double2 *>(Xv);
     VT *V = reinterpret_cast<VT *>(w->V);
@@ -1447,7 +1511,7 @@ static int solve_stream(const bie_op *opc, const void *Bv, void *Xv, int64_t R, 
             std::vector<int> need(W);
             for (int64_t sl = 0; sl < W; ++sl) need[sl] = 1 - skip[sl];
             BIE_HIP(hipMemcpyAsync(dskip, need.data(), W * sizeof(int), hipMemcpyHostToDevice, s));
-            hipLaunchKernelGGL(k_norm, vgrid, dim3(BT), 0, s, N, w->Res, N, w->dpart, w->counters, w->st,
+            hipLaunchKernelGGL(k_norm, vgrid, dim3(BT), 0, s, ucols, w->Res, w->dpart, w->counters, w->st,
                                field_rnorm, (const int *)dskip);
             BIE_HIP(hipGetLastError());
             pull_st();
@@ -1470,16 +1534,16 @@ static int solve_stream(const bie_op *opc, const void *Bv, void *Xv, int64_t R, 
             if (act[sl]) jmax = std::max(jmax, st[sl].jcap);
         }
         BIE_HIP(hipMemcpyAsync(dskip, act.data(), W * sizeof(int), hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(k_restart<VT>, egrid, dim3(BT), 0, s, N, m, w->Res, V, w->g, w->st, (const int *)dskip);
+        hipLaunchKernelGGL(k_restart<VT>, egrid, dim3(BT), 0, s, ucols, m, w->Res, V, w->g, w->st, (const int *)dskip);
         BIE_HIP(hipGetLastError());
         for (int j = 0; j < jmax; ++j) {
             low_product(V + int64_t(j) * N, sizeof(VT) == 8, int64_t(m + 1) * N, w->W, nullptr, 0, nin, done_flags,
                         done_stride);
-            arnoldi_step<VT>(w, V, N, m, j, itol, W, s);
+            arnoldi_step<VT>(w, ucols, N, V, m, j, itol, W, s);
         }
         hipLaunchKernelGGL(k_lsq, dim3(unsigned(W)), dim3(64), size_t(m) * m * sizeof(double2), s, m, w->H, w->g,
                            w->y, w->st);
-        hipLaunchKernelGGL(k_xupd<VT>, egrid, dim3(BT), 0, s, N, m, V, w->y, Ds, w->st);
+        hipLaunchKernelGGL(k_xupd<VT>, egrid, dim3(BT), 0, s, ucols, m, V, w->y, Ds, w->st);
         BIE_HIP(hipGetLastError());
         pull_st();
         for (int64_t sl = 0; sl < W; ++sl) {
@@ -1506,6 +1570,473 @@ static int solve_stream(const bie_op *opc, const void *Bv, void *Xv, int64_t R, 
         if (stats) stats[r] = hs[r];
     }
     return status;
+}
+
+
+// ----------------------------------------------------------------------------- batched solves
+// GMRES(m) for the right-hand sides of several operators of different sizes at
+// once.  Every column keeps its own Krylov basis, Hessenberg matrix and
+// criterion, as in one solve; the columns of all operators share each launch:
+// the product is one grouped tile launch over (column, tile unit) items and one
+// grouped reduce over (column, row block) items, and the Arnoldi kernels read a
+// column table (length and offsets).  The m iterations of a cycle are captured
+// once in a HIP graph and replayed every cycle; columns whose cycle has ended
+// skip on the device.  The number of tiles per work unit is chosen per batch by
+// timing candidates on the batch itself (autotuner, cached per batch shape).
+
+namespace {
+
+struct BatchConfig {
+    int unit = 0;      // tiles per work unit; 0: autotune
+    int graph = 1;     // replay the cycles as a HIP graph
+};
+BatchConfig g_batch;
+
+// Device layout of a grouped product for one choice of tiles per unit.
+struct GLayout {
+    int U = 0;
+    DevBufs db;
+    GProb *probs = nullptr;
+    int32_t *items = nullptr, *ritems = nullptr;
+    int64_t nitems = 0, nritems = 0;
+    int64_t *gpoff = nullptr;   // partial-vector offset per column
+    double2 *gpart = nullptr;   // partial vectors of all columns
+};
+
+std::unique_ptr<GLayout> make_layout(const bie_op *const *ops, int64_t P, const int64_t *R, int U, bool mat64)
+{
+    auto L = std::make_unique<GLayout>();
+    L->U = U;
+    std::vector<GProb> probs(P);
+    std::vector<int64_t> nslots(P);
+    std::vector<std::vector<int32_t>> unitsv(P);
+    for (int64_t p = 0; p < P; ++p) {
+        const int64_t nT = ops[p]->pk.nT;
+        std::vector<int32_t> units, uptr;
+        std::vector<int64_t> seg;
+        build_units(nT, U, units, uptr, seg);
+        int32_t *du = L->db.get<int32_t>(units.size());
+        int32_t *dp = L->db.get<int32_t>(uptr.size());
+        int64_t *ds = L->db.get<int64_t>(seg.size());
+        BIE_HIP(hipMemcpy(du, units.data(), units.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        BIE_HIP(hipMemcpy(dp, uptr.data(), uptr.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        BIE_HIP(hipMemcpy(ds, seg.data(), seg.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+        probs[p] = GProb{ mat64 ? ops[p]->Z64 : ops[p]->Z32, ops[p]->mesh.N, nT, seg[nT], du, dp, ds };
+        nslots[p] = seg[nT];
+        unitsv[p] = std::move(units);
+    }
+    std::vector<int32_t> items, ritems;
+    std::vector<int64_t> gpoff;
+    int64_t c = 0, off = 0;
+    for (int64_t p = 0; p < P; ++p)
+        for (int64_t r = 0; r < R[p]; ++r, ++c) {
+            gpoff.push_back(off);
+            off += nslots[p];
+            for (int64_t u = 0; u < int64_t(unitsv[p].size() / 3); ++u) {
+                items.push_back(int32_t(c));
+                items.push_back(int32_t(u));
+            }
+            for (int64_t I = 0; I < probs[p].nT; ++I) {
+                ritems.push_back(int32_t(c));
+                ritems.push_back(int32_t(I));
+            }
+        }
+    if (items.size() / 2 > 0x7fffffff || ritems.size() / 2 > 0x7fffffff)
+        throw Error(BIE_EINVAL, "batch too large for one grouped launch");
+    L->nitems = int64_t(items.size() / 2);
+    L->nritems = int64_t(ritems.size() / 2);
+    L->probs = L->db.get<GProb>(P);
+    L->items = L->db.get<int32_t>(items.size());
+    L->ritems = L->db.get<int32_t>(ritems.size());
+    L->gpoff = L->db.get<int64_t>(gpoff.size());
+    L->gpart = L->db.get<double2>(size_t(off) * TB);
+    BIE_HIP(hipMemcpy(L->probs, probs.data(), P * sizeof(GProb), hipMemcpyHostToDevice));
+    BIE_HIP(hipMemcpy(L->items, items.data(), items.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    BIE_HIP(hipMemcpy(L->ritems, ritems.data(), ritems.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    BIE_HIP(hipMemcpy(L->gpoff, gpoff.data(), gpoff.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    return L;
+}
+
+// Autotuner cache: batch shape -> tiles per unit (in memory; also appended to
+// the file named by BIE_AUTOTUNE_CACHE and read from it on first use).
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune;
+bool g_tune_loaded = false;
+
+std::string batch_key(const bie_op *const *ops, int64_t P, const int64_t *R, bool mat64)
+{
+    std::string k = mat64 ? "f64" : "f32";
+    for (int64_t p = 0; p < P; ++p) k += ":" + std::to_string(ops[p]->mesh.N) + "x" + std::to_string(R[p]);
+    return k;
+}
+
+void tune_cache_load()
+{
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *path = getenv("BIE_AUTOTUNE_CACHE");
+    if (!path) return;
+    std::ifstream f(path);
+    std::string key;
+    int U;
+    while (f >> key >> U)
+        if (U >= 1 && U <= 64) g_tune[key] = U;
+}
+
+void tune_cache_store(const std::string &key, int U)
+{
+    g_tune[key] = U;
+    if (const char *path = getenv("BIE_AUTOTUNE_CACHE")) {
+        std::ofstream f(path, std::ios::app);
+        f << key << " " << U << "\n";
+    }
+}
+
+}  // namespace
+
+int solve_batch(const bie_op *const *ops, int64_t P, const void *const *Bp, void *const *Xp, const int64_t *Rp,
+                const bie_solve_opts &o, bie_solve_stat *stats, hipStream_t user)
+{
+    if (o.method != BIE_GMRES || o.precision != 0 || o.crit != BIE_SCC)
+        throw Error(BIE_EINVAL, "batched solves take GMRES, the stored matrices and the standard criterion");
+    const bool mat64 = ops[0]->Z64 != nullptr;
+    for (int64_t p = 0; p < P; ++p) {
+        if ((ops[p]->Z64 != nullptr) != mat64 || (!mat64 && !ops[p]->Z32))
+            throw Error(BIE_EINVAL, "all operators of a batch need the same stored matrix (FP64 or FP32)");
+        if (ops[p]->device != ops[0]->device) throw Error(BIE_EINVAL, "all operators of a batch on one device");
+    }
+    const int m = o.restart;
+    // column tables
+    std::vector<int32_t> prob;
+    std::vector<int64_t> cn, voff, woff, aoff;
+    int64_t nv = 0, nw = 0, na = 0, Nmax = 0;
+    for (int64_t p = 0; p < P; ++p) {
+        const int64_t N = ops[p]->mesh.N;
+        Nmax = std::max(Nmax, N);
+        for (int64_t r = 0; r < Rp[p]; ++r) {
+            prob.push_back(int32_t(p));
+            cn.push_back(N);
+            voff.push_back(nv);
+            woff.push_back(nw);
+            aoff.push_back(na);
+            nv += (m + 1) * N;
+            nw += N;
+            na += (N + AB - 1) / AB;
+        }
+    }
+    const int64_t C = int64_t(prob.size());
+    if (C == 0) return BIE_OK;
+
+    // own stream (graph capture is not possible on the null stream), ordered
+    // after the caller's stream
+    hipStream_t s;
+    BIE_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    struct StreamGuard {
+        hipStream_t s;
+        ~StreamGuard() { (void)hipStreamDestroy(s); }
+    } sguard{ s };
+    {
+        hipEvent_t ev;
+        BIE_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        BIE_HIP(hipEventRecord(ev, user));
+        BIE_HIP(hipStreamWaitEvent(s, ev, 0));
+        BIE_HIP(hipStreamSynchronize(s));
+        (void)hipEventDestroy(ev);
+    }
+
+    DevBufs db;
+    Workspace ws;
+    Workspace *w = &ws;
+    w->N = Nmax;
+    w->R = C;
+    w->m = m;
+    w->nblk = unsigned((Nmax + BE - 1) / BE);
+    w->V = w->alloc<double2>(size_t(nv));
+    w->W = w->alloc<double2>(size_t(nw));
+    w->Res = w->alloc<double2>(size_t(nw));
+    w->H = w->alloc<double2>(size_t(C) * m * (m + 1));
+    w->sn = w->alloc<double2>(size_t(C) * m);
+    w->cs = w->alloc<double>(size_t(C) * m);
+    w->g = w->alloc<double2>(size_t(C) * (m + 1));
+    w->y = w->alloc<double2>(size_t(C) * m);
+    w->P1 = w->alloc<double2>(size_t(na) * (m + 1));
+    w->P2 = w->alloc<double2>(size_t(na) * (m + 1));
+    w->PN = w->alloc<double>(size_t(na));
+    w->PW = w->alloc<double>(size_t(na));
+    w->dpart = w->alloc<double>(size_t(C) * w->nblk);
+    w->counters = w->alloc<unsigned>(size_t(C));
+    BIE_HIP(hipMemsetAsync(w->counters, 0, size_t(C) * sizeof(unsigned), s));
+    w->st = w->alloc<ColStat>(size_t(C));
+    w->mask = w->alloc<int>(size_t(C));
+    double2 *Xw = db.get<double2>(size_t(nw)), *Bw = db.get<double2>(size_t(nw));
+    int32_t *dprob = db.get<int32_t>(C);
+    int64_t *dcn = db.get<int64_t>(C), *dvo = db.get<int64_t>(C), *dwo = db.get<int64_t>(C),
+            *dao = db.get<int64_t>(C);
+    BIE_HIP(hipMemcpyAsync(dprob, prob.data(), C * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    BIE_HIP(hipMemcpyAsync(dcn, cn.data(), C * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    BIE_HIP(hipMemcpyAsync(dvo, voff.data(), C * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    BIE_HIP(hipMemcpyAsync(dwo, woff.data(), C * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    BIE_HIP(hipMemcpyAsync(dao, aoff.data(), C * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    Cols cl;
+    cl.n = dcn;
+    cl.voff = dvo;
+    cl.woff = dwo;
+    cl.poff = dao;
+    cl.N = Nmax;
+    cl.m = m;
+    // right-hand sides and initial guesses into the column buffers
+    for (int64_t p = 0; p < P; ++p) {
+        const int64_t c0 = std::find(prob.begin(), prob.end(), int32_t(p)) - prob.begin();
+        if (Rp[p] == 0) continue;
+        const size_t bytes = size_t(Rp[p]) * ops[p]->mesh.N * sizeof(double2);
+        BIE_HIP(hipMemcpyAsync(Bw + woff[c0], Bp[p], bytes, hipMemcpyDeviceToDevice, s));
+        if (o.use_x0) BIE_HIP(hipMemcpyAsync(Xw + woff[c0], Xp[p], bytes, hipMemcpyDeviceToDevice, s));
+    }
+    if (!o.use_x0) hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, s, nw, Xw);
+
+    // grouped product layout: tiles per unit from the autotuner
+    std::unique_ptr<GLayout> L;
+    const std::string key = batch_key(ops, P, Rp, mat64);
+    int U = g_batch.unit;
+    if (U <= 0) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_cache_load();
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) U = it->second;
+    }
+    auto layout_cols = [&](const GLayout &gl, const int64_t *xoff, int64_t xstep) {
+        return GCols{ dprob, xoff, dwo, gl.gpoff, xstep };
+    };
+    if (U <= 0) {
+        // time each candidate: 1 warm-up + 3 products of the right-hand sides
+        hipEvent_t e0, e1;
+        BIE_HIP(hipEventCreate(&e0));
+        BIE_HIP(hipEventCreate(&e1));
+        float best = 0.f;
+        for (int cand : { 2, 4, 8, 16 }) {
+            auto Lc = make_layout(ops, P, Rp, cand, mat64);
+            const GCols gc = layout_cols(*Lc, dwo, 0);
+            grouped_product(mat64, Lc->probs, gc, Lc->items, Lc->nitems, Lc->ritems, Lc->nritems, Bw, Lc->gpart,
+                            w->W, nullptr, nullptr, 1, s);
+            BIE_HIP(hipEventRecord(e0, s));
+            for (int rep = 0; rep < 3; ++rep)
+                grouped_product(mat64, Lc->probs, gc, Lc->items, Lc->nitems, Lc->ritems, Lc->nritems, Bw, Lc->gpart,
+                                w->W, nullptr, nullptr, 1, s);
+            BIE_HIP(hipEventRecord(e1, s));
+            BIE_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            BIE_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (!L || ms < best) {
+                best = ms;
+                L = std::move(Lc);
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_cache_store(key, L->U);
+    } else {
+        L = make_layout(ops, P, Rp, U, mat64);
+    }
+    const GCols gres = layout_cols(*L, dwo, 0);
+    auto full_residual = [&](const int *skipdev) {   // Res = B - T X for the columns not skipped
+        grouped_product(mat64, L->probs, gres, L->items, L->nitems, L->ritems, L->nritems, Xw, L->gpart, w->Res, Bw,
+                        skipdev, 1, s);
+    };
+
+    std::vector<bie_solve_stat> hs(C, bie_solve_stat{ 0, 0, NAN, NAN, 0, 0, o.use_x0 ? 1 : 0 });
+    std::vector<ColStat> st(C);
+    std::vector<int> active(C, 1), need(C), skip(C);
+    auto push_st = [&]() { BIE_HIP(hipMemcpyAsync(w->st, st.data(), C * sizeof(ColStat), hipMemcpyHostToDevice, s)); };
+    auto pull_st = [&]() {
+        BIE_HIP(hipMemcpyAsync(st.data(), w->st, C * sizeof(ColStat), hipMemcpyDeviceToHost, s));
+        BIE_HIP(hipStreamSynchronize(s));
+    };
+    auto push_mask = [&](const std::vector<int> &v) {
+        BIE_HIP(hipMemcpyAsync(w->mask, v.data(), C * sizeof(int), hipMemcpyHostToDevice, s));
+    };
+    const dim3 vgrid(w->nblk, unsigned(C));
+    const dim3 egrid(unsigned(std::min<int64_t>((Nmax + BT - 1) / BT, 1024)), unsigned(C));
+    const int field_rnorm = offsetof(ColStat, rnorm) / sizeof(double);
+    const int field_bnorm = offsetof(ColStat, bnorm) / sizeof(double);
+    auto norms = [&](const double2 *v, const std::vector<int> &msk, int field) {
+        push_mask(msk);
+        hipLaunchKernelGGL(k_norm, vgrid, dim3(BT), 0, s, cl, v, w->dpart, w->counters, w->st, field,
+                           (const int *)w->mask);
+        BIE_HIP(hipGetLastError());
+    };
+    for (int64_t c = 0; c < C; ++c) {
+        st[c] = ColStat{};
+        st[c].active = 1;
+    }
+    push_st();
+    norms(Bw, active, field_bnorm);
+    pull_st();
+    for (int64_t c = 0; c < C; ++c)
+        if (st[c].bnorm == 0.0) {
+            active[c] = 0;
+            hs[c].converged = 1;
+            hs[c].relres_est = hs[c].relres_true = 0.0;
+            hipLaunchKernelGGL(k_zero, dim3(64), dim3(256), 0, s, cn[c], Xw + woff[c]);
+        }
+    // skip array for the residual product: 1 = skip
+    auto residual_of = [&](const std::vector<int> &nd) {
+        for (int64_t c = 0; c < C; ++c) skip[c] = nd[c] ? 0 : 1;
+        push_mask(skip);
+        full_residual(w->mask);
+        norms(w->Res, nd, field_rnorm);
+        for (int64_t c = 0; c < C; ++c)
+            if (nd[c]) hs[c].mvps += 1;
+    };
+    for (int64_t c = 0; c < C; ++c) need[c] = active[c];
+    if (o.use_x0) {
+        residual_of(need);
+        if (o.use_x0 == 2) {
+            pull_st();
+            std::vector<int> back(C, 0);
+            bool any = false;
+            for (int64_t c = 0; c < C; ++c)
+                if (active[c] && !(st[c].rnorm < st[c].bnorm)) {
+                    back[c] = 1;
+                    any = true;
+                    hs[c].x0_kept = 0;
+                    hipLaunchKernelGGL(k_zero, dim3(64), dim3(256), 0, s, cn[c], Xw + woff[c]);
+                    hipLaunchKernelGGL(k_copy, dim3(64), dim3(256), 0, s, cn[c], Bw + woff[c], w->Res + woff[c]);
+                }
+            if (any) norms(w->Res, back, field_rnorm);
+        }
+    } else {
+        BIE_HIP(hipMemcpyAsync(w->Res, Bw, size_t(nw) * sizeof(double2), hipMemcpyDeviceToDevice, s));
+        norms(w->Res, need, field_rnorm);
+    }
+    pull_st();
+    if (o.use_x0)
+        for (int64_t c = 0; c < C; ++c)
+            if (active[c] && st[c].rnorm / st[c].bnorm <= o.tol) {
+                active[c] = 0;
+                hs[c].converged = 1;
+                hs[c].checks += 1;
+                hs[c].relres_est = hs[c].relres_true = st[c].rnorm / st[c].bnorm;
+            }
+
+    // the m iterations of a cycle, captured once, replayed per cycle
+    const int *done_flags = &w->st[0].done;
+    const int64_t done_stride = sizeof(ColStat) / sizeof(int);
+    auto cycle_body = [&]() {
+        for (int j = 0; j < m; ++j) {
+            const GCols gv = layout_cols(*L, dvo, j);
+            grouped_product(mat64, L->probs, gv, L->items, L->nitems, L->ritems, L->nritems, w->V, L->gpart, w->W,
+                            nullptr, done_flags, done_stride, s);
+            arnoldi_step<double2>(w, cl, Nmax, w->V, m, j, o.tol, C, s);
+        }
+    };
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    struct GraphGuard {
+        hipGraph_t &g;
+        hipGraphExec_t &e;
+        ~GraphGuard()
+        {
+            if (e) (void)hipGraphExecDestroy(e);
+            if (g) (void)hipGraphDestroy(g);
+        }
+    } gguard{ graph, gexec };
+    const bool use_graph = g_batch.graph != 0;
+    const bool prof_was = prof_active();
+    if (use_graph) {
+        prof_enable(false);   // no event records inside the captured graph
+        BIE_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        cycle_body();
+        BIE_HIP(hipStreamEndCapture(s, &graph));
+        BIE_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+        prof_enable(prof_was);
+    }
+
+    while (true) {
+        bool any = false;
+        for (int64_t c = 0; c < C; ++c) {
+            if (active[c] && hs[c].mvps >= o.max_mvp) active[c] = 0;
+            any = any || active[c];
+        }
+        if (!any) break;
+        for (int64_t c = 0; c < C; ++c) {
+            ColStat &q = st[c];
+            q.done = active[c] ? 0 : 1;
+            q.active = active[c];
+            q.jend = 0;
+            q.brk = 0;
+            q.jcap = int(std::min<int64_t>(m, std::max<int64_t>(1, o.max_mvp - hs[c].mvps)));
+            need[c] = active[c];
+        }
+        push_st();
+        push_mask(need);
+        hipLaunchKernelGGL(k_restart<double2>, egrid, dim3(BT), 0, s, cl, m, w->Res, w->V, w->g, w->st,
+                           (const int *)w->mask);
+        BIE_HIP(hipGetLastError());
+        if (use_graph) BIE_HIP(hipGraphLaunch(gexec, s));
+        else cycle_body();
+        hipLaunchKernelGGL(k_lsq, dim3(unsigned(C)), dim3(64), size_t(m) * m * sizeof(double2), s, m, w->H, w->g,
+                           w->y, w->st);
+        hipLaunchKernelGGL(k_xupd<double2>, egrid, dim3(BT), 0, s, cl, m, w->V, w->y, Xw, w->st);
+        BIE_HIP(hipGetLastError());
+        pull_st();
+        std::vector<int> nd(C, 0);
+        bool anyr = false;
+        for (int64_t c = 0; c < C; ++c) {
+            if (!active[c]) continue;
+            hs[c].iters += st[c].jend;
+            hs[c].mvps += st[c].jend;
+            hs[c].relres_est = st[c].est;
+            if (hs[c].mvps < o.max_mvp || st[c].est <= o.tol || st[c].brk) {
+                nd[c] = 1;   // true residual: the criterion, or the restart
+                anyr = true;
+            }
+        }
+        if (anyr) residual_of(nd);
+        pull_st();
+        for (int64_t c = 0; c < C; ++c) {
+            if (!active[c] || !nd[c]) continue;
+            const bool cand = st[c].est <= o.tol || st[c].brk;
+            if (cand) {
+                hs[c].checks += 1;
+                hs[c].relres_true = st[c].rnorm / st[c].bnorm;
+                if (hs[c].relres_true <= o.tol) {
+                    active[c] = 0;
+                    hs[c].converged = 1;
+                }
+            }
+            if (active[c] && st[c].rnorm == 0.0) {
+                active[c] = 0;
+                hs[c].converged = 1;
+                hs[c].relres_true = 0.0;
+            }
+        }
+    }
+    // solutions out
+    for (int64_t p = 0, c0 = 0; p < P; c0 += Rp[p], ++p)
+        if (Rp[p] > 0)
+            BIE_HIP(hipMemcpyAsync(Xp[p], Xw + woff[c0], size_t(Rp[p]) * ops[p]->mesh.N * sizeof(double2),
+                                   hipMemcpyDeviceToDevice, s));
+    BIE_HIP(hipStreamSynchronize(s));
+    int status = BIE_OK;
+    for (int64_t c = 0; c < C; ++c) {
+        if (!hs[c].converged) status = BIE_NOT_CONVERGED;
+        if (stats) stats[c] = hs[c];
+    }
+    return status;
+}
+
+void batch_config(int unit, int graph)
+{
+    g_batch.unit = unit;
+    g_batch.graph = graph;
+}
+
+int batch_unit_chosen(const bie_op *const *ops, int64_t P, const int64_t *R)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(batch_key(ops, P, R, ops[0]->Z64 != nullptr));
+    return it == g_tune.end() ? 0 : it->second;
 }
 
 int solve(const bie_op *op, const void *B, void *X, int64_t R, const bie_solve_opts &o, bie_solve_stat *stats,

@@ -26,3 +26,13 @@ def ico():
             cache[level] = rwg_table(V, T)
         return cache[level]
     return get
+
+
+@pytest.fixture(scope="session")
+def bie():
+    """The library binding; GPU tests skip without a device."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_13482_amd import bie as b
+    return b

@@ -1,0 +1,114 @@
+"""Batched solves over several operators of different sizes (bie_batch_solve)
+against single solves and the oracle matrices."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import cfill, krylov
+from oracle.mesh import rwg_table
+from paper_2606_13482_amd.inputs import complex_gaussian, cube_sphere, mean_edge_length, planewave_set, random_directions
+
+pytestmark = pytest.mark.gpu
+
+# (cube-sphere resolution, family, axes): N = 18 n^2 = 162 .. 648
+SHAPES = [(3, "sphere", (1.0, 1.0, 1.0)), (5, "ellipsoid", (1.0, 1.7, 2.4)), (4, "rounded_cube", (1.0, 1.0, 1.0)),
+          (6, "ellipsoid", (1.0, 2.6, 1.3))]
+RHS = [1, 3, 2, 5]
+_CACHE = {}
+
+
+def _problems():
+    if "p" not in _CACHE:
+        out = []
+        for i, (n, fam, axes) in enumerate(SHAPES):
+            V, T = cube_sphere(n, fam, axes=axes)
+            k = 2 * np.pi / (10 * mean_edge_length(V, T))
+            rwg = rwg_table(V, T)
+            d, e = planewave_set(random_directions(RHS[i], 40 + i), "theta")
+            out.append(dict(V=V, T=T, k=k, Zo=cfill.fill(rwg, k), d=d, e=e))
+        _CACHE["p"] = out
+    return _CACHE["p"]
+
+
+def _ops(bie, storage):
+    ops, Bs = [], []
+    for pr in _problems():
+        op = bie.Operator(pr["V"], pr["T"], pr["k"], storage=storage)
+        ops.append(op)
+        Bs.append(op.rhs(pr["d"], pr["e"]))
+    return ops, Bs
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_batch_equals_single_bitwise(bie, graph):
+    """With the tiles per unit of the single-operator product (8), every column of
+    the batch equals its single solve bitwise, with or without graph replay."""
+    ops, Bs = _ops(bie, "c128")
+    opts = bie.Solve(restart=20, tol=1e-8)
+    bie.batch_config(8, graph)
+    try:
+        Xs, sts = bie.batch_solve(ops, Bs, opts)
+    finally:
+        bie.batch_config(0, True)
+    for p, op in enumerate(ops):
+        X1, st1 = op.solve(Bs[p], opts)
+        assert [s["iters"] for s in sts[p]] == [s["iters"] for s in st1], p
+        assert torch.equal(Xs[p], X1), p
+        Zo = _problems()[p]["Zo"]
+        Bn, Xn = Bs[p].cpu().numpy(), Xs[p].cpu().numpy()
+        res = np.linalg.norm(Bn - Xn @ Zo.T, axis=1) / np.linalg.norm(Bn, axis=1)
+        assert all(s["converged"] for s in sts[p]) and res.max() <= 1e-8 * (1 + 1e-6), (p, res)
+
+
+def test_batch_fp32_autotuned(bie):
+    """FP32 matrices (the uneven-batch configuration), tiles per unit from the
+    autotuner: converged on the FP32 operator; against the FP64 oracle matrix the
+    residual is within the FP32 rounding of the matrix times the conditioning."""
+    ops, Bs = _ops(bie, "c64")
+    opts = bie.Solve(restart=30, tol=1e-6)
+    bie.batch_config(0, True)
+    Xs, sts = bie.batch_solve(ops, Bs, opts)
+    U = bie.batch_tuned(ops, [b.shape[0] for b in Bs])
+    print(f"\n  autotuned tiles per unit: {U}")
+    assert U in (2, 4, 8, 16)
+    for p in range(len(ops)):
+        assert all(s["converged"] for s in sts[p])
+        assert max(s["relres_true"] for s in sts[p]) <= 1e-6 * (1 + 1e-6)
+        Zo = _problems()[p]["Zo"]
+        Bn, Xn = Bs[p].cpu().numpy(), Xs[p].cpu().numpy()
+        res = np.linalg.norm(Bn - Xn @ Zo.T, axis=1) / np.linalg.norm(Bn, axis=1)
+        assert res.max() < 1e-4, (p, res)
+        # a second call reuses the tuned choice
+    Xs2, _ = bie.batch_solve(ops, Bs, opts)
+    assert all(torch.equal(a, b) for a, b in zip(Xs, Xs2))
+
+
+def test_batch_guesses_and_edges(bie):
+    """Initial guesses with fallback, a zero right-hand side and an operator with no
+    right-hand sides in one batch."""
+    ops, Bs = _ops(bie, "c128")
+    Bs[1] = Bs[1].clone()
+    Bs[1][1] = 0
+    Bs[2] = Bs[2][:0]
+    x0s = []
+    for p, op in enumerate(ops):
+        Zo = _problems()[p]["Zo"]
+        Bn = Bs[p].cpu().numpy()
+        x = np.zeros((Bn.shape[0], op.N), np.complex128)
+        for i, b in enumerate(Bn):
+            if np.any(b):
+                x[i] = krylov.lu_solve(Zo, b)
+        if p == 3:
+            x[0] = 50 * complex_gaussian(op.N, 9)   # far worse than zero: dropped
+        x0s.append(torch.from_numpy(x).cuda())
+    bie.batch_config(8, True)
+    try:
+        Xs, sts = bie.batch_solve(ops, Bs, bie.Solve(restart=20, tol=1e-6), x0s=x0s, x0_fallback=True)
+    finally:
+        bie.batch_config(0, True)
+    assert len(sts[2]) == 0 and Xs[2].shape[0] == 0
+    assert sts[1][1]["converged"] and sts[1][1]["iters"] == 0 and torch.count_nonzero(Xs[1][1]) == 0
+    assert sts[3][0]["x0_kept"] == 0 and sts[3][0]["converged"]
+    assert sts[0][0]["x0_kept"] == 1 and sts[0][0]["iters"] == 0
+    for p in (0, 1, 3):
+        assert all(s["converged"] for s in sts[p])

@@ -22,14 +22,6 @@ def _say(*a):
     sys.stdout.flush()
 
 
-@pytest.fixture(scope="module")
-def bie():
-    if not torch.cuda.is_available():
-        pytest.skip("no GPU")
-    from paper_2606_13482_amd import bie as b
-    return b
-
-
 CASES = {}
 
 

@@ -20,14 +20,6 @@ def _say(*a):
 
 
 @pytest.fixture(scope="module")
-def bie():
-    if not torch.cuda.is_available():
-        pytest.skip("no GPU")
-    from paper_2606_13482_amd import bie as b
-    return b
-
-
-@pytest.fixture(scope="module")
 def small(bie):
     V, T = icosphere(2)
     return bie.Operator(V, T, 2.0)
