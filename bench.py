@@ -60,6 +60,8 @@ def parse():
     ap.add_argument("--plain-sample", type=int, default=8)
     ap.add_argument("--c5", action="store_true",
                     help="full learned warm-start configuration: 2048 training / 512 test directions, 3000 epochs")
+    ap.add_argument("--no-batch", dest="batch", action="store_false",
+                    help="skip the uneven batch of 64 surfaces (batched solves over many operators)")
     ap.add_argument("--counters", action="store_true",
                     help="only launch the dense product kernels a few times at the bench sizes, and a 1 GiB "
                          "device copy as calibration, for hardware-counter runs")
@@ -293,6 +295,54 @@ def headline_leg(args, bie, torch, V, T, k):
     return res, roof, ms_step, float(np.mean([b for _, b in itp])), int(ns)
 
 
+def uneven_batch_leg(args, bie, torch):
+    """64 closed surfaces (spheres, ellipsoids, rounded cubes; 648..5832 unknowns,
+    10 edges per wavelength), 1..32 plane waves each, FP32 matrices: the batched
+    solve (grouped products, graph-replayed cycles, autotuned work units) against
+    the same operators solved one after another."""
+    from paper_2606_13482_amd.inputs import uneven_batch
+    sync = torch.cuda.synchronize
+    probs = uneven_batch()
+    sync()
+    t0 = time.perf_counter()
+    ops = [bie.Operator(p["V"], p["T"], p["k"], storage="c64") for p in probs]
+    Bs = [op.rhs(p["dirs"], p["pols"]) for op, p in zip(ops, probs)]
+    sync()
+    t_fill = time.perf_counter() - t0
+    Ns = [op.N for op in ops]
+    Rs = [b.shape[0] for b in Bs]
+    opts = bie.Solve(restart=50, tol=args.tol)
+    bie.batch_config(0, True)
+    t0 = time.perf_counter()
+    bie.batch_solve(ops, Bs, opts)          # first call: autotuner
+    sync()
+    t_first = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    Xs, sts = bie.batch_solve(ops, Bs, opts)
+    sync()
+    t_batch = time.perf_counter() - t0
+    its = np.array([s["iters"] for st in sts for s in st])
+    conv = np.array([s["converged"] for st in sts for s in st], bool)
+    t0 = time.perf_counter()
+    for op, B in zip(ops, Bs):
+        op.solve(B, opts)
+    sync()
+    t_seq = time.perf_counter() - t0
+    nrhs = int(sum(Rs))
+    out = {"workload": (f"{len(ops)} surfaces, N {min(Ns)}..{max(Ns)}, {nrhs} plane waves, FP32 matrices, "
+                        f"GMRES(50) to {args.tol:g} (SCC), max 10000 products per right-hand side"),
+           "solves_per_s": round(int(conv.sum()) / t_batch, 2), "batch_s": round(t_batch, 3),
+           "first_call_s_with_autotune": round(t_first, 3), "fill_s": round(t_fill, 3),
+           "tiles_per_unit": bie.batch_tuned(ops, Rs), "converged": float(conv.mean()),
+           "iters_mean": float(its.mean()), "iters_max": int(its.max()),
+           "relres_max_converged": float(max(s["relres_true"] for st in sts for s in st if s["converged"])),
+           "sequential_s": round(t_seq, 3), "speedup_vs_sequential": round(t_seq / t_batch, 3),
+           "packed_fp32_bytes_per_product": int(sum(4 * n * (n + 1) for n in Ns))}
+    for op in ops:
+        op.close()
+    return out
+
+
 def counters_probe(args, bie, torch):
     """Kernels for the HBM traffic counters: 5 launches each of the packed FP64
     product (one column), the split-BF16 block product and the FP64 block product
@@ -393,6 +443,8 @@ def main():
         "headline": head,
         "plain_fp64_step": plain,
     }
+    if args.batch:
+        out["uneven_batch"] = uneven_batch_leg(args, bie, torch)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.level, k, args.restart, plain_mvps)
     print(json.dumps(out), flush=True)

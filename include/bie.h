@@ -201,9 +201,11 @@ int bie_batch_solve(const bie_op *const *ops, int64_t nops, const void *const *B
                     const int64_t *R, const bie_solve_opts *opts, bie_solve_stat *stats, void *stream);
 
 /* Batched solves, for measurement and tests: tiles per work unit of the
- * grouped product (0: chosen per batch shape by timing candidates 2/4/8/16 on
- * the batch, the default; the choices are kept for the process and appended to
- * the file named by BIE_AUTOTUNE_CACHE if set) and graph replay (1: default). */
+ * grouped product (0, the default: tiles per unit in {4, 8, 16} and columns per
+ * work item in {4, 8, 32} chosen per batch shape by timing the candidates on
+ * the batch; the choices are kept for the process and appended to the file
+ * named by BIE_AUTOTUNE_CACHE if set; > 0: that many tiles per unit, 8 columns
+ * per item) and graph replay (1: default). */
 int bie_batch_config(int unit_tiles, int use_graph);
 /* Tiles per unit chosen for this batch shape so far (0: none). */
 int bie_batch_tuned(const bie_op *const *ops, int64_t nops, const int64_t *R);

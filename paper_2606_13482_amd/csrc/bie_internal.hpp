@@ -82,6 +82,7 @@ struct GProb {
     int64_t N, nT, nslots;
     const int32_t *units, *unit_ptr;
     const int64_t *seg;
+    int32_t c0, c1;                // its columns: c0 .. c1-1
 };
 // Columns of a grouped product (device tables indexed by column).
 struct GCols {
@@ -149,9 +150,10 @@ void packed_setup(bie_op *op);
 void build_units(int64_t nT, int U, std::vector<int32_t> &units, std::vector<int32_t> &uptr,
                  std::vector<int64_t> &seg);
 // Grouped packed product y_c = T_p(c) x_c (or b_c - that) for the columns of
-// several problems: one tile launch over (column, unit) items and one reduce
-// launch over (column, row block) items.  mat64: FP64 tiles, else FP32.
-void grouped_product(bool mat64, const GProb *probs, const GCols &gc, const int32_t *items, int64_t nitems,
+// several problems: one tile launch over (problem, unit, group of G columns)
+// items, each going through its columns, and one reduce launch over (column,
+// row block) items.  mat64: FP64 tiles, else FP32.
+void grouped_product(bool mat64, const GProb *probs, const GCols &gc, const int32_t *items, int64_t nitems, int G,
                      const int32_t *ritems, int64_t nritems, const void *X, void *part, void *Y, const void *B,
                      const int *skip, int64_t sks, hipStream_t s);        // unit table (host -> device)
 void packed_free(bie_op *op);

@@ -165,8 +165,10 @@ __device__ inline void wave_sum8(T pr[8], T pi[8])
 // Tile pass of one work unit: tiles (I, J0 .. J1-1) of row block I, the
 // unit being the uo-th of its row.  Writes 64-entry partial vectors (complex
 // T) into the slots of the row block they belong to (see reduce_rows).
-// M: matrix storage type, T: vector and accumulation type (T >= M).
-template <typename M, typename T, bool CONJ, bool PREFETCH>
+// M: matrix storage type, T: vector and accumulation type (T >= M).  NT:
+// non-temporal tile loads (one vector streams the matrix once; several
+// vectors re-read the unit's tiles from the caches).
+template <typename M, typename T, bool CONJ, bool PREFETCH, bool NT = true>
 __device__ inline void tile_pass(const M *__restrict__ Zp, int64_t N, int64_t nT, int32_t I, int32_t J0, int32_t J1,
                                  int64_t uo, const int64_t *__restrict__ seg,
                                  const typename Cx<T>::type *__restrict__ x, typename Cx<T>::type *__restrict__ pv)
@@ -198,7 +200,7 @@ __device__ inline void tile_pass(const M *__restrict__ Zp, int64_t N, int64_t nT
     if (PREFETCH) {
         const MV *tile = Z + tile_of(I, J0, nT) * TB * TB + (wave * 16) * TB + lane;
 #pragma unroll
-        for (int i = 0; i < 16; ++i) t[i] = __builtin_nontemporal_load(tile + i * TB);
+        for (int i = 0; i < 16; ++i) t[i] = NT ? __builtin_nontemporal_load(tile + i * TB) : tile[i * TB];
     }
     for (int32_t J = J0; J < J1; ++J) {
         const int64_t n = int64_t(J) * TB + lane;
@@ -211,12 +213,12 @@ __device__ inline void tile_pass(const M *__restrict__ Zp, int64_t N, int64_t nT
             if (J + 1 < J1) {   // next tile's loads go out before this tile's arithmetic
                 const MV *tile = Z + tile_of(I, J + 1, nT) * TB * TB + (wave * 16) * TB + lane;
 #pragma unroll
-                for (int i = 0; i < 16; ++i) t[i] = __builtin_nontemporal_load(tile + i * TB);
+                for (int i = 0; i < 16; ++i) t[i] = NT ? __builtin_nontemporal_load(tile + i * TB) : tile[i * TB];
             }
         } else {
             const MV *tile = Z + tile_of(I, J, nT) * TB * TB + (wave * 16) * TB + lane;
 #pragma unroll
-            for (int i = 0; i < 16; ++i) cur[i] = __builtin_nontemporal_load(tile + i * TB);
+            for (int i = 0; i < 16; ++i) cur[i] = NT ? __builtin_nontemporal_load(tile + i * TB) : tile[i * TB];
         }
         T car = 0, cai = 0;
 #pragma unroll
@@ -270,22 +272,28 @@ __global__ __launch_bounds__(256) void k_sym_tiles(const M *__restrict__ Zp, int
                                     reinterpret_cast<V2 *>(part) + v * nslots * TB);
 }
 
-// Grouped tile pass over several problems: block b is the work item
-// (column c, unit u of the problem of c).
+// Grouped tile pass over several problems: block b is the work item (problem
+// p, unit u, column group g) and goes through columns c0 + gG .. of p in turn,
+// skipping finished ones; the unit's tiles come from memory for the first
+// column and from the caches for the others.  Items are ordered longest first.
 template <typename M, typename T, bool PREFETCH>
 __global__ __launch_bounds__(256) void k_sym_tiles_g(const GProb *__restrict__ probs, GCols gc,
-                                                     const int32_t *__restrict__ items, const T *__restrict__ X,
+                                                     const int32_t *__restrict__ items, int G, const T *__restrict__ X,
                                                      T *__restrict__ part, const int *__restrict__ skip, int64_t sks)
 {
     using V2 = typename Cx<T>::type;
     const int64_t b = blockIdx.x;
-    const int32_t c = items[2 * b], u = items[2 * b + 1];
-    if (skip && skip[int64_t(c) * sks]) return;
-    const GProb P = probs[gc.prob[c]];
+    const int32_t p = items[3 * b], u = items[3 * b + 1], g = items[3 * b + 2];
+    const GProb P = probs[p];
     const int32_t I = P.units[3 * u], J0 = P.units[3 * u + 1], J1 = P.units[3 * u + 2];
-    tile_pass<M, T, false, PREFETCH>(static_cast<const M *>(P.Z), P.N, P.nT, I, J0, J1, u - P.unit_ptr[I], P.seg,
-                                     reinterpret_cast<const V2 *>(X) + gc.xoff[c] + gc.xstep * P.N,
-                                     reinterpret_cast<V2 *>(part) + gc.poff[c] * TB);
+    const int32_t cb = P.c0 + g * G, ce = min(P.c1, cb + G);
+    for (int32_t c = cb; c < ce; ++c) {
+        if (skip && skip[int64_t(c) * sks]) continue;   // uniform over the block
+        tile_pass<M, T, false, PREFETCH, false>(static_cast<const M *>(P.Z), P.N, P.nT, I, J0, J1,
+                                                u - P.unit_ptr[I], P.seg,
+                                                reinterpret_cast<const V2 *>(X) + gc.xoff[c] + gc.xstep * P.N,
+                                                reinterpret_cast<V2 *>(part) + gc.poff[c] * TB);
+    }
 }
 
 // y_I = sum of the partial vectors of row block I (column sums of tiles
@@ -532,7 +540,7 @@ void product(const bie_op *opc, int mat, bool vec64, const void *X, int64_t ldx,
     else dispatch<float, float>(op, Z, X, ldx, Y, ldy, B, ldb, R, skip, sks, conj, s);
 }
 
-void grouped_product(bool mat64, const GProb *probs, const GCols &gc, const int32_t *items, int64_t nitems,
+void grouped_product(bool mat64, const GProb *probs, const GCols &gc, const int32_t *items, int64_t nitems, int G,
                      const int32_t *ritems, int64_t nritems, const void *X, void *part, void *Y, const void *B,
                      const int *skip, int64_t sks, hipStream_t s)
 {
@@ -540,14 +548,14 @@ void grouped_product(bool mat64, const GProb *probs, const GCols &gc, const int3
     const bool pf = sym_prefetch() != 0;
     if (mat64) {
         if (pf) hipLaunchKernelGGL((k_sym_tiles_g<double, double, true>), dim3(unsigned(nitems)), dim3(256), 0, s, probs,
-                                   gc, items, (const double *)X, (double *)part, skip, sks);
+                                   gc, items, G, (const double *)X, (double *)part, skip, sks);
         else hipLaunchKernelGGL((k_sym_tiles_g<double, double, false>), dim3(unsigned(nitems)), dim3(256), 0, s,
-                                probs, gc, items, (const double *)X, (double *)part, skip, sks);
+                                probs, gc, items, G, (const double *)X, (double *)part, skip, sks);
     } else {
         if (pf) hipLaunchKernelGGL((k_sym_tiles_g<float, double, true>), dim3(unsigned(nitems)), dim3(256), 0, s, probs,
-                                   gc, items, (const double *)X, (double *)part, skip, sks);
+                                   gc, items, G, (const double *)X, (double *)part, skip, sks);
         else hipLaunchKernelGGL((k_sym_tiles_g<float, double, false>), dim3(unsigned(nitems)), dim3(256), 0, s, probs,
-                                gc, items, (const double *)X, (double *)part, skip, sks);
+                                gc, items, G, (const double *)X, (double *)part, skip, sks);
     }
     if (B) hipLaunchKernelGGL((k_sym_reduce_g<double, true>), dim3(unsigned(nritems)), dim3(512), 0, s, probs, gc,
                               ritems, (const double *)part, (double *)Y, (const double *)B, skip, sks);

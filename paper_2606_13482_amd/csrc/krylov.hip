@@ -1577,12 +1577,15 @@ static int solve_stream(const bie_op *opc, const void *Bv, void *Xv, int64_t R, 
 // GMRES(m) for the right-hand sides of several operators of different sizes at
 // once.  Every column keeps its own Krylov basis, Hessenberg matrix and
 // criterion, as in one solve; the columns of all operators share each launch:
-// the product is one grouped tile launch over (column, tile unit) items and one
-// grouped reduce over (column, row block) items, and the Arnoldi kernels read a
-// column table (length and offsets).  The m iterations of a cycle are captured
-// once in a HIP graph and replayed every cycle; columns whose cycle has ended
-// skip on the device.  The number of tiles per work unit is chosen per batch by
-// timing candidates on the batch itself (autotuner, cached per batch shape).
+// the product is one grouped tile launch over (operator, tile unit, column
+// group) items, longest first, and one grouped reduce over (column, row block)
+// items, and the Arnoldi kernels read a column table (length and offsets).
+// A tile item goes through the columns of its group with the unit's tiles
+// kept in the caches, so each matrix is read from memory about once per group.
+// The m iterations of a cycle are captured once in a HIP graph and replayed
+// every cycle; columns whose cycle has ended skip on the device.  Tiles per
+// unit and columns per group are chosen per batch by timing candidates on the
+// batch itself (autotuner, cached per batch shape).
 
 namespace {
 
@@ -1592,9 +1595,10 @@ struct BatchConfig {
 };
 BatchConfig g_batch;
 
-// Device layout of a grouped product for one choice of tiles per unit.
+// Device layout of a grouped product for one choice of tiles per unit (U) and
+// columns per work item (G).
 struct GLayout {
-    int U = 0;
+    int U = 0, G = 0;
     DevBufs db;
     GProb *probs = nullptr;
     int32_t *items = nullptr, *ritems = nullptr;
@@ -1603,10 +1607,11 @@ struct GLayout {
     double2 *gpart = nullptr;   // partial vectors of all columns
 };
 
-std::unique_ptr<GLayout> make_layout(const bie_op *const *ops, int64_t P, const int64_t *R, int U, bool mat64)
+std::unique_ptr<GLayout> make_layout(const bie_op *const *ops, int64_t P, const int64_t *R, int U, int G, bool mat64)
 {
     auto L = std::make_unique<GLayout>();
     L->U = U;
+    L->G = G;
     std::vector<GProb> probs(P);
     std::vector<int64_t> nslots(P);
     std::vector<std::vector<int32_t>> unitsv(P);
@@ -1621,29 +1626,47 @@ std::unique_ptr<GLayout> make_layout(const bie_op *const *ops, int64_t P, const 
         BIE_HIP(hipMemcpy(du, units.data(), units.size() * sizeof(int32_t), hipMemcpyHostToDevice));
         BIE_HIP(hipMemcpy(dp, uptr.data(), uptr.size() * sizeof(int32_t), hipMemcpyHostToDevice));
         BIE_HIP(hipMemcpy(ds, seg.data(), seg.size() * sizeof(int64_t), hipMemcpyHostToDevice));
-        probs[p] = GProb{ mat64 ? ops[p]->Z64 : ops[p]->Z32, ops[p]->mesh.N, nT, seg[nT], du, dp, ds };
+        probs[p] = GProb{ mat64 ? ops[p]->Z64 : ops[p]->Z32, ops[p]->mesh.N, nT, seg[nT], du, dp, ds, 0, 0 };
         nslots[p] = seg[nT];
         unitsv[p] = std::move(units);
     }
+    // tile items (p, u, g), longest first (work = columns x tiles)
+    struct Item {
+        int64_t work;
+        int32_t p, u, g;
+    };
+    std::vector<Item> tl;
+    for (int64_t p = 0; p < P; ++p)
+        for (int64_t u = 0; u < int64_t(unitsv[p].size() / 3); ++u) {
+            const int64_t nt = unitsv[p][3 * u + 2] - unitsv[p][3 * u + 1];
+            for (int64_t g = 0; g * G < R[p]; ++g)
+                tl.push_back(Item{ nt * std::min<int64_t>(G, R[p] - g * G), int32_t(p), int32_t(u), int32_t(g) });
+        }
+    std::stable_sort(tl.begin(), tl.end(), [](const Item &a, const Item &b) { return a.work > b.work; });
     std::vector<int32_t> items, ritems;
+    items.reserve(3 * tl.size());
+    for (const Item &it : tl) {
+        items.push_back(it.p);
+        items.push_back(it.u);
+        items.push_back(it.g);
+    }
     std::vector<int64_t> gpoff;
     int64_t c = 0, off = 0;
-    for (int64_t p = 0; p < P; ++p)
+    for (int64_t p = 0; p < P; ++p) {
+        probs[p].c0 = int32_t(c);
         for (int64_t r = 0; r < R[p]; ++r, ++c) {
             gpoff.push_back(off);
             off += nslots[p];
-            for (int64_t u = 0; u < int64_t(unitsv[p].size() / 3); ++u) {
-                items.push_back(int32_t(c));
-                items.push_back(int32_t(u));
-            }
             for (int64_t I = 0; I < probs[p].nT; ++I) {
                 ritems.push_back(int32_t(c));
                 ritems.push_back(int32_t(I));
             }
         }
-    if (items.size() / 2 > 0x7fffffff || ritems.size() / 2 > 0x7fffffff)
+        probs[p].c1 = int32_t(c);
+    }
+    if (items.size() / 3 > 0x7fffffff || ritems.size() / 2 > 0x7fffffff)
         throw Error(BIE_EINVAL, "batch too large for one grouped launch");
-    L->nitems = int64_t(items.size() / 2);
+    L->nitems = int64_t(items.size() / 3);
     L->nritems = int64_t(ritems.size() / 2);
     L->probs = L->db.get<GProb>(P);
     L->items = L->db.get<int32_t>(items.size());
@@ -1660,7 +1683,7 @@ std::unique_ptr<GLayout> make_layout(const bie_op *const *ops, int64_t P, const 
 // Autotuner cache: batch shape -> tiles per unit (in memory; also appended to
 // the file named by BIE_AUTOTUNE_CACHE and read from it on first use).
 std::mutex g_tune_mu;
-std::map<std::string, int> g_tune;
+std::map<std::string, std::pair<int, int>> g_tune;   // (U, G)
 bool g_tune_loaded = false;
 
 std::string batch_key(const bie_op *const *ops, int64_t P, const int64_t *R, bool mat64)
@@ -1678,17 +1701,17 @@ void tune_cache_load()
     if (!path) return;
     std::ifstream f(path);
     std::string key;
-    int U;
-    while (f >> key >> U)
-        if (U >= 1 && U <= 64) g_tune[key] = U;
+    int U, G;
+    while (f >> key >> U >> G)
+        if (U >= 1 && U <= 64 && G >= 1 && G <= 4096) g_tune[key] = { U, G };
 }
 
-void tune_cache_store(const std::string &key, int U)
+void tune_cache_store(const std::string &key, int U, int G)
 {
-    g_tune[key] = U;
+    g_tune[key] = { U, G };
     if (const char *path = getenv("BIE_AUTOTUNE_CACHE")) {
         std::ofstream f(path, std::ios::app);
-        f << key << " " << U << "\n";
+        f << key << " " << U << " " << G << "\n";
     }
 }
 
@@ -1794,15 +1817,18 @@ int solve_batch(const bie_op *const *ops, int64_t P, const void *const *Bp, void
     }
     if (!o.use_x0) hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, s, nw, Xw);
 
-    // grouped product layout: tiles per unit from the autotuner
+    // grouped product layout: tiles per unit and columns per item from the autotuner
     std::unique_ptr<GLayout> L;
     const std::string key = batch_key(ops, P, Rp, mat64);
-    int U = g_batch.unit;
+    int U = g_batch.unit, G = 8;
     if (U <= 0) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         tune_cache_load();
         auto it = g_tune.find(key);
-        if (it != g_tune.end()) U = it->second;
+        if (it != g_tune.end()) {
+            U = it->second.first;
+            G = it->second.second;
+        }
     }
     auto layout_cols = [&](const GLayout &gl, const int64_t *xoff, int64_t xstep) {
         return GCols{ dprob, xoff, dwo, gl.gpoff, xstep };
@@ -1813,34 +1839,36 @@ int solve_batch(const bie_op *const *ops, int64_t P, const void *const *Bp, void
         BIE_HIP(hipEventCreate(&e0));
         BIE_HIP(hipEventCreate(&e1));
         float best = 0.f;
-        for (int cand : { 2, 4, 8, 16 }) {
-            auto Lc = make_layout(ops, P, Rp, cand, mat64);
-            const GCols gc = layout_cols(*Lc, dwo, 0);
-            grouped_product(mat64, Lc->probs, gc, Lc->items, Lc->nitems, Lc->ritems, Lc->nritems, Bw, Lc->gpart,
-                            w->W, nullptr, nullptr, 1, s);
-            BIE_HIP(hipEventRecord(e0, s));
-            for (int rep = 0; rep < 3; ++rep)
-                grouped_product(mat64, Lc->probs, gc, Lc->items, Lc->nitems, Lc->ritems, Lc->nritems, Bw, Lc->gpart,
-                                w->W, nullptr, nullptr, 1, s);
-            BIE_HIP(hipEventRecord(e1, s));
-            BIE_HIP(hipEventSynchronize(e1));
-            float ms = 0.f;
-            BIE_HIP(hipEventElapsedTime(&ms, e0, e1));
-            if (!L || ms < best) {
-                best = ms;
-                L = std::move(Lc);
+        for (int cu : { 4, 8, 16 })
+            for (int cg : { 4, 8, 32 }) {
+                auto Lc = make_layout(ops, P, Rp, cu, cg, mat64);
+                const GCols gc = layout_cols(*Lc, dwo, 0);
+                auto run = [&]() {
+                    grouped_product(mat64, Lc->probs, gc, Lc->items, Lc->nitems, Lc->G, Lc->ritems, Lc->nritems, Bw,
+                                    Lc->gpart, w->W, nullptr, nullptr, 1, s);
+                };
+                run();
+                BIE_HIP(hipEventRecord(e0, s));
+                for (int rep = 0; rep < 3; ++rep) run();
+                BIE_HIP(hipEventRecord(e1, s));
+                BIE_HIP(hipEventSynchronize(e1));
+                float ms = 0.f;
+                BIE_HIP(hipEventElapsedTime(&ms, e0, e1));
+                if (!L || ms < best) {
+                    best = ms;
+                    L = std::move(Lc);
+                }
             }
-        }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        tune_cache_store(key, L->U);
+        tune_cache_store(key, L->U, L->G);
     } else {
-        L = make_layout(ops, P, Rp, U, mat64);
+        L = make_layout(ops, P, Rp, U, G, mat64);
     }
     const GCols gres = layout_cols(*L, dwo, 0);
     auto full_residual = [&](const int *skipdev) {   // Res = B - T X for the columns not skipped
-        grouped_product(mat64, L->probs, gres, L->items, L->nitems, L->ritems, L->nritems, Xw, L->gpart, w->Res, Bw,
+        grouped_product(mat64, L->probs, gres, L->items, L->nitems, L->G, L->ritems, L->nritems, Xw, L->gpart, w->Res, Bw,
                         skipdev, 1, s);
     };
 
@@ -1925,7 +1953,7 @@ int solve_batch(const bie_op *const *ops, int64_t P, const void *const *Bp, void
     auto cycle_body = [&]() {
         for (int j = 0; j < m; ++j) {
             const GCols gv = layout_cols(*L, dvo, j);
-            grouped_product(mat64, L->probs, gv, L->items, L->nitems, L->ritems, L->nritems, w->V, L->gpart, w->W,
+            grouped_product(mat64, L->probs, gv, L->items, L->nitems, L->G, L->ritems, L->nritems, w->V, L->gpart, w->W,
                             nullptr, done_flags, done_stride, s);
             arnoldi_step<double2>(w, cl, Nmax, w->V, m, j, o.tol, C, s);
         }
@@ -2036,7 +2064,7 @@ int batch_unit_chosen(const bie_op *const *ops, int64_t P, const int64_t *R)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(batch_key(ops, P, R, ops[0]->Z64 != nullptr));
-    return it == g_tune.end() ? 0 : it->second;
+    return it == g_tune.end() ? 0 : it->second.first;
 }
 
 int solve(const bie_op *op, const void *B, void *X, int64_t R, const bie_solve_opts &o, bie_solve_stat *stats,

@@ -70,7 +70,7 @@ def test_batch_fp32_autotuned(bie):
     Xs, sts = bie.batch_solve(ops, Bs, opts)
     U = bie.batch_tuned(ops, [b.shape[0] for b in Bs])
     print(f"\n  autotuned tiles per unit: {U}")
-    assert U in (2, 4, 8, 16)
+    assert U in (4, 8, 16)
     for p in range(len(ops)):
         assert all(s["converged"] for s in sts[p])
         assert max(s["relres_true"] for s in sts[p]) <= 1e-6 * (1 + 1e-6)
