@@ -280,12 +280,17 @@ int bie_ws_basis(const bie_ws *ws, void *U, void *stream);
 int bie_ws_params(bie_ws *ws, float *host, int set);
 /* Mean squared error of the network on R inputs (host R x 4) against targets
  * (host R x 2K) and its gradient (host float nparams, may be NULL), computed by
- * the device forward and backward kernels. */
-int bie_ws_loss_grad(bie_ws *ws, const double *feats, const float *targets, int64_t R, double *loss, float *grad);
-/* Network outputs (host R x 2K) for R inputs. */
+ * the device forward and backward kernels.  pol_model 1: the error is that of
+ * the combination sum_c e_c f_c with the polarisations pols (host R x 3);
+ * pols may be NULL for pol_model 0. */
+int bie_ws_loss_grad(bie_ws *ws, const double *feats, const double *pols, const float *targets, int64_t R,
+                     double *loss, float *grad);
+/* Raw network outputs (host R x O, O = 2K, or 6K for pol_model 1) for R inputs
+ * (pol_model 1 ignores the fourth input). */
 int bie_ws_forward(bie_ws *ws, const double *feats, int64_t R, float *out);
-/* Untrained network with Glorot-uniform weights (no POD basis). */
-int bie_ws_create(const bie_op *op, int pod_rank, int hidden, uint64_t seed, bie_ws **out);
+/* Untrained network with Glorot-uniform weights (no POD basis); pol_model as in
+ * bie_ws_opts. */
+int bie_ws_create(const bie_op *op, int pod_rank, int hidden, uint64_t seed, int pol_model, bie_ws **out);
 int bie_ws_save(const bie_ws *ws, const char *path);
 int bie_ws_load(const bie_op *op, const char *path, bie_ws **out);
 void bie_ws_destroy(bie_ws *ws);

@@ -16,6 +16,11 @@ solve.  Definitions written out plainly:
     index on [0, i] as the high 64 bits of z (i + 1).
   * Adam (Kingma & Ba 2015) with beta = (0.9, 0.999), eps = 1e-8 and a cosine
     learning rate from lr_max to lr_min over all steps.
+  * Linear-in-polarisation model (pol_model 1): a solution is linear in the
+    polarisation vector e, so the network takes f = (d_x, d_y, d_z, 0) and gives
+    three coefficient sets f_x, f_y, f_z (6K outputs); the coefficients for e
+    are y = e_x f_x + e_y f_y + e_z f_z and the loss is the mean squared error of
+    y against the 2K targets.
 """
 from __future__ import annotations
 
@@ -32,23 +37,23 @@ def pod(X: np.ndarray, K: int):
     return U[:, :K].T.copy(), s
 
 
-def layout(K: int, H: int):
-    O = 2 * K
+def layout(K: int, H: int, pol_model: int = 0):
+    O = (6 if pol_model == 1 else 2) * K
     sizes = [H * 4, H, H * H, H, O * H, O]
     offs = np.concatenate([[0], np.cumsum(sizes)])
     return offs, O
 
 
-def unpack(p: np.ndarray, K: int, H: int):
-    offs, O = layout(K, H)
+def unpack(p: np.ndarray, K: int, H: int, pol_model: int = 0):
+    offs, O = layout(K, H, pol_model)
     W1 = p[offs[0]:offs[1]].reshape(H, 4); b1 = p[offs[1]:offs[2]]
     W2 = p[offs[2]:offs[3]].reshape(H, H); b2 = p[offs[3]:offs[4]]
     W3 = p[offs[4]:offs[5]].reshape(O, H); b3 = p[offs[5]:offs[6]]
     return W1, b1, W2, b2, W3, b3
 
 
-def glorot(K: int, H: int, seed: int) -> np.ndarray:
-    offs, O = layout(K, H)
+def glorot(K: int, H: int, seed: int, pol_model: int = 0) -> np.ndarray:
+    offs, O = layout(K, H, pol_model)
     p = np.zeros(offs[-1])
     g = SplitMix64(seed)
 
@@ -63,28 +68,51 @@ def glorot(K: int, H: int, seed: int) -> np.ndarray:
     return p
 
 
-def forward(p, K, H, F):
-    W1, b1, W2, b2, W3, b3 = unpack(p, K, H)
+def forward(p, K, H, F, pol_model: int = 0):
+    W1, b1, W2, b2, W3, b3 = unpack(p, K, H, pol_model)
     a1 = np.tanh(F @ W1.T + b1)
     a2 = np.tanh(a1 @ W2.T + b2)
     return a2 @ W3.T + b3, (a1, a2)
 
 
-def loss_grad(p, K, H, F, T):
-    """Mean squared error and its gradient (same layout as p)."""
-    W1, b1, W2, b2, W3, b3 = unpack(p, K, H)
-    y, (a1, a2) = forward(p, K, H, F)
-    B, O = y.shape
-    d = y - T
-    loss = float(np.mean(d * d))
-    dy = 2.0 * d / (B * O)
+def _backprop(p, K, H, F, dy, a1, a2, pol_model=0):
+    """Gradient of the loss with respect to p from dL/d(outputs) = dy."""
+    W1, b1, W2, b2, W3, b3 = unpack(p, K, H, pol_model)
     gW3 = dy.T @ a2; gb3 = dy.sum(0)
     da2 = (dy @ W3) * (1.0 - a2 * a2)
     gW2 = da2.T @ a1; gb2 = da2.sum(0)
     da1 = (da2 @ W2) * (1.0 - a1 * a1)
     gW1 = da1.T @ F; gb1 = da1.sum(0)
-    g = np.concatenate([gW1.ravel(), gb1, gW2.ravel(), gb2, gW3.ravel(), gb3])
-    return loss, g
+    return np.concatenate([gW1.ravel(), gb1, gW2.ravel(), gb2, gW3.ravel(), gb3])
+
+
+def loss_grad(p, K, H, F, T):
+    """Mean squared error and its gradient (same layout as p)."""
+    y, (a1, a2) = forward(p, K, H, F)
+    B, O = y.shape
+    d = y - T
+    loss = float(np.mean(d * d))
+    return loss, _backprop(p, K, H, F, 2.0 * d / (B * O), a1, a2)
+
+
+def combine(raw, E, K):
+    """Coefficients of the linear-in-polarisation model: sum_c E[:, c] f_c."""
+    return sum(E[:, c:c + 1] * raw[:, 2 * K * c:2 * K * (c + 1)] for c in range(3))
+
+
+def loss_grad_pol(p, K, H, D, E, T):
+    """Linear-in-polarisation model: inputs D (directions, B x 3), polarisations E
+    (B x 3), targets T (B x 2K); mean squared error of the combination and its
+    gradient."""
+    F = np.concatenate([D, np.zeros((D.shape[0], 1))], axis=1)
+    raw, (a1, a2) = forward(p, K, H, F, 1)
+    y = combine(raw, E, K)
+    B = y.shape[0]
+    d = y - T
+    loss = float(np.mean(d * d))
+    dyc = 2.0 * d / (B * 2 * K)
+    draw = np.concatenate([E[:, c:c + 1] * dyc for c in range(3)], axis=1)
+    return loss, _backprop(p, K, H, F, draw, a1, a2, 1)
 
 
 def shuffle(S: int, seed: int, epoch: int) -> np.ndarray:

@@ -84,9 +84,10 @@ SYMBOLS = [
     ("bie_ws_info", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     ("bie_ws_basis", ctypes.c_int, [_P, _P, _P]),
     ("bie_ws_params", ctypes.c_int, [_P, _P, ctypes.c_int]),
-    ("bie_ws_loss_grad", ctypes.c_int, [_P, _P, _P, _I64, _P, _P]),
+    ("bie_ws_loss_grad", ctypes.c_int, [_P, _P, _P, _P, _I64, _P, _P]),
     ("bie_ws_forward", ctypes.c_int, [_P, _P, _I64, _P]),
-    ("bie_ws_create", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(_P)]),
+    ("bie_ws_create", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_int,
+                                     ctypes.POINTER(_P)]),
     ("bie_ws_save", ctypes.c_int, [_P, ctypes.c_char_p]),
     ("bie_ws_load", ctypes.c_int, [_P, ctypes.c_char_p, ctypes.POINTER(_P)]),
     ("bie_ws_destroy", None, [_P]),
@@ -361,9 +362,9 @@ class WarmStart:
         return ws
 
     @classmethod
-    def create(cls, op: Operator, pod_rank=256, hidden=512, seed=555):
+    def create(cls, op: Operator, pod_rank=256, hidden=512, seed=555, pol_model=0):
         h = ctypes.c_void_p()
-        _check(_lib.bie_ws_create(op._h, pod_rank, hidden, ctypes.c_uint64(seed), ctypes.byref(h)))
+        _check(_lib.bie_ws_create(op._h, pod_rank, hidden, ctypes.c_uint64(seed), pol_model, ctypes.byref(h)))
         return cls(op, h)
 
     @classmethod
@@ -405,18 +406,27 @@ class WarmStart:
         p = np.ascontiguousarray(p, np.float32)
         _check(_lib.bie_ws_params(self._h, p.ctypes.data_as(ctypes.c_void_p), 1))
 
-    def loss_grad(self, feats, targets):
+    def loss_grad(self, feats, targets, pols=None):
         f, pf = _host(feats, np.float64)
         t, pt = _host(targets, np.float32)
+        pp = None
+        if pols is not None:
+            e, pp = _host(pols, np.float64)
         g = np.zeros(self.nparams, np.float32)
         loss = ctypes.c_double()
-        _check(_lib.bie_ws_loss_grad(self._h, pf, pt, f.shape[0], ctypes.byref(loss),
+        _check(_lib.bie_ws_loss_grad(self._h, pf, pp, pt, f.shape[0], ctypes.byref(loss),
                                      g.ctypes.data_as(ctypes.c_void_p)))
         return loss.value, g
 
+    @property
+    def outputs(self) -> int:
+        """Network outputs: 2K, or 6K for the linear-in-polarisation model."""
+        H = self.H
+        return (self.nparams - 6 * H - H * H) // (H + 1)
+
     def forward(self, feats) -> np.ndarray:
         f, pf = _host(feats, np.float64)
-        out = np.zeros((f.shape[0], 2 * self.K), np.float32)
+        out = np.zeros((f.shape[0], self.outputs), np.float32)
         _check(_lib.bie_ws_forward(self._h, pf, f.shape[0], out.ctypes.data_as(ctypes.c_void_p)))
         return out
 

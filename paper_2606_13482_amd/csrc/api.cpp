@@ -337,12 +337,13 @@ int bie_ws_params(bie_ws *ws, float *host, int set)
     });
 }
 
-int bie_ws_loss_grad(bie_ws *ws, const double *feats, const float *targets, int64_t R, double *loss, float *grad)
+int bie_ws_loss_grad(bie_ws *ws, const double *feats, const double *pols, const float *targets, int64_t R,
+                     double *loss, float *grad)
 {
     return guarded([&]() -> int {
         if (!ws || !feats || !targets || !loss) return fail(BIE_EINVAL, "NULL argument");
         if (R < 1 || R > 65535) return fail(BIE_EINVAL, "R out of range");
-        *loss = bie::ws_loss_grad(ws, feats, targets, R, grad, nullptr);
+        *loss = bie::ws_loss_grad(ws, feats, pols, targets, R, grad, nullptr);
         return BIE_OK;
     });
 }
@@ -357,12 +358,13 @@ int bie_ws_forward(bie_ws *ws, const double *feats, int64_t R, float *out)
     });
 }
 
-int bie_ws_create(const bie_op *op, int pod_rank, int hidden, uint64_t seed, bie_ws **out)
+int bie_ws_create(const bie_op *op, int pod_rank, int hidden, uint64_t seed, int pol_model, bie_ws **out)
 {
     return guarded([&]() -> int {
         if (!op || !out) return fail(BIE_EINVAL, "NULL argument");
         if (pod_rank < 1 || hidden < 1 || hidden > 4096) return fail(BIE_EINVAL, "bad sizes");
-        *out = bie::ws_create_untrained(op, pod_rank, hidden, seed);
+        if (pol_model != 0 && pol_model != 1) return fail(BIE_EINVAL, "pol_model must be 0 or 1");
+        *out = bie::ws_create_untrained(op, pod_rank, hidden, seed, pol_model);
         return BIE_OK;
     });
 }

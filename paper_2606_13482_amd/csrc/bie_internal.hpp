@@ -191,10 +191,10 @@ bie_ws *ws_train(const bie_op *op, const double *feats, const double *pols, cons
                  const bie_ws_opts &o, hipStream_t s);
 void ws_predict(bie_ws *w, const double *feats, const double *pols, int64_t R, const void *B, void *X0, int *used,
                 hipStream_t s);
-double ws_loss_grad(bie_ws *w, const double *feats, const float *targets, int64_t R, float *grad_host,
-                    hipStream_t s);
+double ws_loss_grad(bie_ws *w, const double *feats, const double *pols, const float *targets, int64_t R,
+                    float *grad_host, hipStream_t s);
 void ws_forward(bie_ws *w, const double *feats, int64_t R, float *out_host, hipStream_t s);
-bie_ws *ws_create_untrained(const bie_op *op, int K, int H, uint64_t seed);
+bie_ws *ws_create_untrained(const bie_op *op, int K, int H, uint64_t seed, int pol_model);
 void ws_params(bie_ws *w, float *host, bool set);
 void ws_basis(const bie_ws *w, void *U, hipStream_t s);
 void ws_save(const bie_ws *w, const char *path);

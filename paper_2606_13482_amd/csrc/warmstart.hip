@@ -799,19 +799,29 @@ void ws_predict(bie_ws *w, const double *feats, const double *pols, int64_t R, c
     BIE_HIP(hipStreamSynchronize(s));
 }
 
-// Loss and gradient of the MSE for given inputs (R x 4) and targets (R x 2K), host buffers.
-double ws_loss_grad(bie_ws *w, const double *feats, const float *targets, int64_t R, float *grad_host, hipStream_t s)
+// Loss and gradient of the MSE for given inputs (R x 4; R x 3 polarisations
+// for the linear-in-polarisation model) and targets (R x 2K), host buffers.
+double ws_loss_grad(bie_ws *w, const double *feats, const double *pols, const float *targets, int64_t R,
+                    float *grad_host, hipStream_t s)
 {
+    if (w->pmodel == 1 && !pols) throw Error(BIE_EINVAL, "the linear-in-polarisation model needs the polarisations");
     ws_eval(w, feats, R, s);
-    BIE_HIP(hipMemcpyAsync(w->tgt, targets, size_t(R) * w->O * sizeof(float), hipMemcpyHostToDevice, s));
-    const int nb = mlp_backward(w, int(R), s);
+    const int TW = 2 * w->K;
+    BIE_HIP(hipMemcpyAsync(w->tgt, targets, size_t(R) * TW * sizeof(float), hipMemcpyHostToDevice, s));
+    std::vector<float> eh;
+    if (w->pmodel == 1) {
+        eh.resize(size_t(R) * 3);
+        for (size_t i = 0; i < eh.size(); ++i) eh[i] = float(pols[i]);
+        BIE_HIP(hipMemcpyAsync(w->pol, eh.data(), eh.size() * sizeof(float), hipMemcpyHostToDevice, s));
+    }
+    const int nb = mlp_backward(w, int(R), s, w->pmodel == 1);
     std::vector<double> lp(nb);
     BIE_HIP(hipMemcpyAsync(lp.data(), w->lpart, nb * sizeof(double), hipMemcpyDeviceToHost, s));
     if (grad_host) BIE_HIP(hipMemcpyAsync(grad_host, w->grad, w->nparams * sizeof(float), hipMemcpyDeviceToHost, s));
     BIE_HIP(hipStreamSynchronize(s));
     double a = 0.0;
     for (double v : lp) a += v;
-    return a / double(R * w->O);
+    return a / double(R * TW);
 }
 
 void ws_forward(bie_ws *w, const double *feats, int64_t R, float *out_host, hipStream_t s)
@@ -834,13 +844,14 @@ void ws_info(const bie_ws *w, int64_t *K, int64_t *H, int64_t *nparams, double *
         for (size_t i = 0; i < w->sigma.size(); ++i) sigma[i] = w->sigma[i];
 }
 
-bie_ws *ws_create_untrained(const bie_op *op, int K, int H, uint64_t seed)
+bie_ws *ws_create_untrained(const bie_op *op, int K, int H, uint64_t seed, int pol_model)
 {
     auto w = std::make_unique<bie_ws>();
     w->op = op;
     w->K = K;
     w->H = H;
-    w->O = 2 * K;
+    w->pmodel = pol_model;
+    w->O = (pol_model == 1 ? 6 : 2) * K;
     ws_alloc_params(w.get());
     glorot(w.get(), seed);
     return w.release();

@@ -59,6 +59,30 @@ def test_forward_and_gradient_parity(bie, small):
     assert np.linalg.norm(g - go) <= 1e-5 * np.linalg.norm(go)
 
 
+def test_linear_polarisation_model_parity(bie, small):
+    """Linear-in-polarisation network: initial weights bitwise (6K outputs), raw
+    outputs and the loss/gradient of the combination sum_c e_c f_c against the
+    oracle."""
+    K, H = 12, 48
+    ws = bie.WarmStart.create(small, K, H, 31, pol_model=1)
+    assert ws.outputs == 6 * K
+    assert np.array_equal(ws.params(), learn.glorot(K, H, 31, pol_model=1).astype(np.float32))
+    rng = np.random.default_rng(5)
+    p = (learn.glorot(K, H, 31, pol_model=1) + 0.02 * rng.standard_normal(ws.nparams)).astype(np.float32)
+    ws.set_params(p)
+    dirs, pols, F = _feats(bie, random_directions(16, 6))
+    Tt = rng.standard_normal((F.shape[0], 2 * K)).astype(np.float32)
+    F0 = np.concatenate([dirs, np.zeros((dirs.shape[0], 1))], axis=1)
+    y = ws.forward(F)
+    yo, _ = learn.forward(p.astype(np.float64), K, H, F0, 1)
+    assert np.max(np.abs(y - yo)) <= 1e-5 * np.max(np.abs(yo))
+    loss, g = ws.loss_grad(F, Tt, pols=pols)
+    lo, go = learn.loss_grad_pol(p.astype(np.float64), K, H, dirs, pols, Tt.astype(np.float64))
+    _say("  linear model: loss gpu/oracle", loss, lo, "grad rel err", np.linalg.norm(g - go) / np.linalg.norm(go))
+    assert abs(loss - lo) <= 1e-5 * lo
+    assert np.linalg.norm(g - go) <= 1e-5 * np.linalg.norm(go)
+
+
 def test_pod_basis_against_svd(bie, small):
     """GPU randomised POD: orthonormal, singular values and projection error equal to
     the exact SVD of the same snapshots (Eckart-Young optimum)."""

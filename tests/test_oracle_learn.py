@@ -62,3 +62,33 @@ def test_training_fits_a_smooth_map():
     l0 = learn.loss_grad(p0, K, H, F, T)[0]
     p = learn.train(p0, K, H, F, T, epochs=150, batch=16, lr_max=1e-2, lr_min=1e-4, seed=5)
     assert learn.loss_grad(p, K, H, F, T)[0] < 0.05 * l0
+
+
+def test_linear_polarisation_gradient_and_combination():
+    """Linear-in-polarisation model: the gradient equals central differences, and
+    the combination is linear in e (a theta/phi pair at one direction reproduces
+    any other real polarisation in their span)."""
+    K, H = 3, 6
+    rng = np.random.default_rng(7)
+    p = learn.glorot(K, H, 123, pol_model=1) + 0.05 * rng.standard_normal(learn.layout(K, H, 1)[0][-1])
+    D = rng.standard_normal((5, 3)); D /= np.linalg.norm(D, axis=1, keepdims=True)
+    E = rng.standard_normal((5, 3)); E -= (E * D).sum(1, keepdims=True) * D; E /= np.linalg.norm(E, axis=1, keepdims=True)
+    T = rng.standard_normal((5, 2 * K))
+    loss, g = learn.loss_grad_pol(p, K, H, D, E, T)
+    h = 1e-6
+    idx = rng.choice(len(p), 40, replace=False)
+    for i in idx:
+        q = p.copy(); q[i] += h; lp, _ = learn.loss_grad_pol(q, K, H, D, E, T)
+        q[i] -= 2 * h; lm, _ = learn.loss_grad_pol(q, K, H, D, E, T)
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-7 * max(1.0, abs(fd)), (i, fd, g[i])
+    # linearity in e: y(a e1 + b e2) = a y(e1) + b y(e2)
+    F = np.concatenate([D, np.zeros((5, 1))], axis=1)
+    raw, _ = learn.forward(p, K, H, F, 1)
+    e1, e2 = E, np.cross(D, E)
+    a, b = 0.6, -0.8
+    assert np.allclose(learn.combine(raw, a * e1 + b * e2, K), a * learn.combine(raw, e1, K) + b * learn.combine(raw, e2, K),
+                       atol=1e-14)
+    # the output layer has 6K rows; the first layers are those of the base model
+    assert learn.layout(K, H, 1)[1] == 6 * K
+    assert np.array_equal(learn.glorot(K, H, 9, 1)[:learn.layout(K, H)[0][4]], learn.glorot(K, H, 9)[:learn.layout(K, H)[0][4]])
