@@ -60,6 +60,9 @@ def parse():
     ap.add_argument("--plain-sample", type=int, default=8)
     ap.add_argument("--c5", action="store_true",
                     help="full learned warm-start configuration: 2048 training / 512 test directions, 3000 epochs")
+    ap.add_argument("--c3", action="store_true",
+                    help="large-sphere workload instead: 30720 unknowns, k=20, the 512 plane waves of a 16x16 "
+                         "(theta, phi) grid x theta/phi, split-BF16 block GMRES with FP64 refinement")
     ap.add_argument("--no-batch", dest="batch", action="store_false",
                     help="skip the uneven batch of 64 surfaces (batched solves over many operators)")
     ap.add_argument("--counters", action="store_true",
@@ -285,7 +288,9 @@ def headline_leg(args, bie, torch, V, T, k):
     alg_flops = 8.0 * N * N * g_cols / max(1, g_launch)   # per launch: complex product, 8 real flops per entry and column
     achieved = alg_flops / (avg * 1e-3) / 1e12
     roof = {"bound": "mfma", "achieved": round(achieved, 1), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / BF16_PEAK_TFLOPS, 4), "traffic": None,
+            "frac": round(achieved / BF16_PEAK_TFLOPS, 4),
+            "traffic": traffic_from_profiles("gemm_split_bf16_n7680_r256_counters.txt", "gemm.hip", N),
+            "traffic_note": "HBM bytes per launch at 256 columns (counters), null if the kernel changed since",
             "kernel": "split-BF16 complex block product (k_gemm_split, v_mfma_f32_32x32x16_bf16)",
             "alg_flops_per_launch": alg_flops, "issued_tflops": round(3 * achieved, 1),
             "avg_columns_per_launch": round(g_cols / max(1, g_launch), 1),
@@ -293,6 +298,86 @@ def headline_leg(args, bie, torch, V, T, k):
             "gemm_share_of_step": round(g_ms / (t_steps * 1e3), 3)}
     op.close()
     return res, roof, ms_step, float(np.mean([b for _, b in itp])), int(ns)
+
+
+def c3_run(args, bie, torch):
+    """Large sphere: 20480-triangle icosphere (30720 RWG), k = 20, 512 plane waves
+    (16 x 16 (theta, phi) grid x theta/phi) per step, operator resident; GMRES(30)
+    with split-BF16 block products and FP64 refinement as a continuous batch of 256
+    slots to FP64 SCC 1e-6; plain FP64 GMRES(30) on a sample of the same waves."""
+    from paper_2606_13482_amd.inputs import grid_planewaves, icosphere
+    sync = torch.cuda.synchronize
+    V, T = icosphere(5)
+    k = 20.0
+    t0 = time.perf_counter()
+    op = bie.Operator(V, T, k, storage="split_bf16")
+    sync()
+    t_fill = time.perf_counter() - t0
+    N = op.N
+    dirs, pols = grid_planewaves(16, 16)
+    R = dirs.shape[0]
+    mopts = bie.Solve(restart=30, tol=args.tol, max_mvp=20000, precision="mixed", inner_tol=args.inner_tol,
+                      slots=args.slots, inner_terms=args.inner_terms)
+
+    def step():
+        B = op.rhs(dirs, pols)
+        X, st = op.solve(B, mopts)
+        return B, X, st
+
+    for _ in range(args.warmup):
+        step()
+    sync()
+    bie.prof_read(1)
+    bie.prof_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        B, X, st = step()
+    sync()
+    t_steps = time.perf_counter() - t0
+    g_launch, g_ms, g_cols = bie.prof_read(1, columns=True)
+    bie.prof_enable(False)
+    ms_step = 1e3 * t_steps / args.steps
+    its = np.array([s["iters"] for s in st])
+    conv = np.array([s["converged"] for s in st], bool)
+    ns = 2
+    idx = np.linspace(0, R - 1, ns).round().astype(int)
+    popts = bie.Solve(restart=30, tol=args.tol, max_mvp=20000)
+    sync()
+    t0 = time.perf_counter()
+    itp = []
+    for i in idx:
+        _, s = op.solve(B[i:i + 1], popts)
+        itp.append(s[0]["iters"])
+    sync()
+    t_plain = (time.perf_counter() - t0) / ns
+    avg = g_ms / max(1, g_launch)
+    alg = 8.0 * N * N * g_cols / max(1, g_launch)
+    ach = alg / (avg * 1e-3) / 1e12
+    value = R / (ms_step * 1e-3)
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "split-bf16 products (f32 accumulate) + f64 refinement", "data": "synthetic",
+        "config": {"workload": (f"PEC sphere r=1 m, icosphere {T.shape[0]} triangles ({N} RWG), k={k:g}; {R} plane "
+                                f"waves (16x16 theta/phi grid x theta/phi) per step, operator resident; GMRES(30) "
+                                f"on split-BF16 MFMA products with FP64 refinement to {args.tol:g} (FP64 SCC), "
+                                f"continuous batch of {args.slots} slots"),
+                   "N": N, "k": k, "restart": 30, "inner_tol": args.inner_tol, "slots": args.slots,
+                   "rhs_per_step": R, "parallelism": "single GPU"},
+        "roofline": {"bound": "mfma", "achieved": round(ach, 1), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(ach / BF16_PEAK_TFLOPS, 4), "traffic": None,
+                     "kernel": "split-BF16 complex block product (k_gemm_split)", "alg_flops_per_launch": alg,
+                     "issued_tflops": round(3 * ach, 1), "avg_columns_per_launch": round(g_cols / max(1, g_launch), 1),
+                     "avg_launch_us": round(avg * 1e3, 2), "launches": g_launch,
+                     "gemm_share_of_step": round(g_ms / (t_steps * 1e3), 3)},
+        "c3": {"fill_and_split_s": round(t_fill, 3), "converged": float(conv.mean()),
+               "relres_true_fp64_max": float(max(s["relres_true"] for s in st)), "iters_mean": float(its.mean()),
+               "iters_max": int(its.max()), "plain_fp64_sample": {"rhs": ns, "solves_per_s": round(1.0 / t_plain, 4),
+                                                                  "iters": itp},
+               "speedup_vs_plain_fp64": round(value * t_plain, 2)},
+    }
+    op.close()
+    return out
 
 
 def uneven_batch_leg(args, bie, torch):
@@ -409,6 +494,9 @@ def main():
     torch.cuda.set_device(torch.device("cuda:0"))
     if args.counters:
         counters_probe(args, bie, torch)
+        return
+    if args.c3:
+        print(json.dumps(c3_run(args, bie, torch)), flush=True)
         return
     V, T = icosphere(args.level)
     k = args.k
