@@ -10,17 +10,28 @@
 // v_mfma_f32_32x32x16_bf16 (about 16 significant bits per product entry; the
 // dropped lo*lo term is below the FP32 accumulation error).
 //
-// Tiling: a block of 8 waves computes a 256 x 256 tile of C over one slice of
-// K; wave (wm, wn) owns rows 128 wm .. +128 and columns 64 wn .. +64 as 4 x 2
-// MFMA tiles of 32 x 32 (12 fragment reads from LDS feed 24 MFMAs per 16-deep
-// step).  K advances in stages of 32; both planes of the A and B stage sit in
-// LDS, double-buffered (160 KiB), rows padded to 40 BF16 to spread banks.
-// While a stage is computed the next one goes from registers to the other
-// buffer and the one after it is loaded from memory into registers: one
-// barrier per stage, loads issued two stages ahead.
+// Operand layout.  Every BF16 plane (A rows m, B columns c, both along K) is
+// stored as 1 KiB tiles of 32 rows x 16 K values, one MFMA K step: tile
+// (strip s = row / 32, stage t = k / 16) starts at element (s Kp/16 + t) 512,
+// and inside it the 16-byte chunk h = (k / 8) mod 2 of row r sits in slot
+// 2r + (h ^ ((r / 8) & 1)).  A tile is one contiguous run in HBM, so one LDS
+// DMA instruction of one wave (global_load_lds_dwordx4: lane i's 16 bytes land
+// at LDS base + 16 i) moves it into LDS unchanged, and the fragment read of a
+// 32x32x16 MFMA (lane l: row l % 32, chunk l / 32) touches 16 distinct
+// 16-byte bank groups in every 16 lanes: no bank conflicts.
+//
+// Tiling: a block computes a 256 x 256 tile of C over one slice of K, with 8
+// waves of 128 x 64 (4 x 2 MFMA tiles: 12 fragment reads feed 24 MFMAs per K
+// stage) or, selectable for measurement, 8 waves of 64 x 128 or 4 of 128 x 128.
+// K stages of 16 (both planes of the A and B stage: 32 KiB) rotate through
+// NS = 4 LDS buffers.  Step i: each wave waits for its own DMA of stage i+1,
+// one barrier, the DMA of stage i+NS goes into the buffer of stage i (whose
+// fragments are already in registers), stage i+1 is read into the second
+// register set, and the MFMAs of stage i run from the first.  The DMA is
+// three stages ahead of its use and the fragment reads one stage ahead.
 //
 // Split K: when the output tiles alone cannot fill the 256 compute units (one
-// 160 KiB block per CU), K is cut into KS slices (grid z).  Every block writes
+// 128 KiB block per CU), K is cut into KS slices (grid z).  Every block writes
 // its FP32 tile to a partial buffer [KS][Mp][NCp] (lanes along columns: 128-byte
 // runs); a second kernel sums the slices in FP64, subtracts from B if asked,
 // and transposes through LDS so that the complex128 output is written in
@@ -39,10 +50,8 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int GBM = 256, GBN = 256, GBK = 32, PK = GBK + 8;
-constexpr int TI = 4, TJ = 2;   // 32x32 MFMA tiles per wave (128 rows x 64 columns)
+constexpr int GBM = 256, GBN = 256, GBK = 16;   // block tile rows, columns; K stage
 
 // XCD-aware tile order: workgroups are dealt to the 8 XCDs round robin by
 // linear id p, so logical tile L = (p % 8) Q + p / 8 (Q = P / 8) gives each XCD
@@ -65,12 +74,32 @@ __device__ inline void split_bf16(float v, __bf16 &hi, __bf16 &lo)
     lo = (__bf16)(v - (float)hi);
 }
 
-// A planes [Mp][Kp] from the packed symmetric FP64 tiles (zero padding).
-__global__ __launch_bounds__(256) void k_split_matrix(const double2 *__restrict__ Zp, int64_t N, int64_t nT,
-                                                      int64_t Kp, __bf16 *__restrict__ Ah, __bf16 *__restrict__ Al)
+// Tile and slot of the 16-byte chunk h of row r (r < 32) in the tiled layout.
+__device__ inline int tile_slot(int r, int h) { return 2 * r + (h ^ ((r >> 3) & 1)); }
+
+// One wave per tile writes its 64 slots: lane l -> row l / 2 of the strip and
+// the chunk stored in slot l.
+__device__ inline void slot_owner(int lane, int &r, int &h)
 {
-    const int64_t m = blockIdx.y;
-    for (int64_t n = int64_t(blockIdx.x) * 256 + threadIdx.x; 2 * n < Kp; n += int64_t(gridDim.x) * 256) {
+    r = lane >> 1;
+    h = (lane & 1) ^ ((r >> 3) & 1);
+}
+
+// A planes (tiled, [Mp / 32][Kp / 16] tiles) from the packed symmetric FP64
+// matrix (zero padding); one wave per tile, 4 tiles per block.
+__global__ __launch_bounds__(256) void k_split_matrix(const double2 *__restrict__ Zp, int64_t N, int64_t nT,
+                                                      int64_t Mp, int64_t Kp, __bf16 *__restrict__ Ah,
+                                                      __bf16 *__restrict__ Al)
+{
+    const int64_t nst = Kp / GBK, tile = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    if (tile >= (Mp / 32) * nst) return;
+    int r, h;
+    slot_owner(threadIdx.x & 63, r, h);
+    const int64_t m = (tile / nst) * 32 + r, n0 = (tile % nst) * 8 + h * 4;   // 4 complex entries n0 .. n0+3
+    bf16x8 hi, lo;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int64_t n = n0 + e;
         double2 z = make_double2(0.0, 0.0);
         if (m < N && n < N) {
             const int64_t I = m / TB, J = n / TB;
@@ -80,25 +109,37 @@ __global__ __launch_bounds__(256) void k_split_matrix(const double2 *__restrict_
         __bf16 h0, l0, h1, l1;
         split_bf16(float(z.x), h0, l0);
         split_bf16(float(z.y), h1, l1);
-        Ah[m * Kp + 2 * n] = h0;
-        Ah[m * Kp + 2 * n + 1] = h1;
-        Al[m * Kp + 2 * n] = l0;
-        Al[m * Kp + 2 * n + 1] = l1;
+        hi[2 * e] = h0;
+        hi[2 * e + 1] = h1;
+        lo[2 * e] = l0;
+        lo[2 * e + 1] = l1;
     }
+    const int64_t off = tile * 512 + (threadIdx.x & 63) * 8;
+    *reinterpret_cast<bf16x8 *>(Ah + off) = hi;
+    *reinterpret_cast<bf16x8 *>(Al + off) = lo;
 }
 
-// B planes [NCp][Kp] from R complex vectors (complex128 or complex64 XT):
-// GEMM column pair r reads the vector at X + v*ldx, v = cols ? cols[r] : r.
+// B planes (tiled, [NCp / 32][Kp / 16] tiles) from R complex vectors
+// (complex128 or complex64 XT): GEMM column pair r reads the vector at X + v*ldx,
+// v = cols ? cols[r] : r.  One wave per tile.
 template <typename XT>
 __global__ __launch_bounds__(256) void k_split_vectors(const XT *__restrict__ X, int64_t ldx, const int *__restrict__ cols,
-                                                       int64_t N, int64_t R, int64_t Kp, __bf16 *__restrict__ Bh,
-                                                       __bf16 *__restrict__ Bl, bool lo)
+                                                       int64_t N, int64_t R, int64_t NCp, int64_t Kp,
+                                                       __bf16 *__restrict__ Bh, __bf16 *__restrict__ Bl, bool lo)
 {
-    const int64_t c = blockIdx.y;
-    const int64_t v = c < 2 * R ? (cols ? int64_t(cols[c >> 1]) : (c >> 1)) : 0;
-    for (int64_t n = int64_t(blockIdx.x) * 256 + threadIdx.x; 2 * n < Kp; n += int64_t(gridDim.x) * 256) {
+    const int64_t nst = Kp / GBK, tile = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    if (tile >= (NCp / 32) * nst) return;
+    int r, h;
+    slot_owner(threadIdx.x & 63, r, h);
+    const int64_t c = (tile / nst) * 32 + r, n0 = (tile % nst) * 8 + h * 4;
+    const bool live = c < 2 * R;
+    const int64_t v = live ? (cols ? int64_t(cols[c >> 1]) : (c >> 1)) : 0;
+    bf16x8 hi, lw;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int64_t n = n0 + e;
         float a = 0.f, b = 0.f;
-        if (n < N && c < 2 * R) {
+        if (live && n < N) {
             const XT x = X[v * ldx + n];
             if (!(c & 1)) { a = float(x.x); b = float(-x.y); }
             else { a = float(x.y); b = float(x.x); }
@@ -106,126 +147,184 @@ __global__ __launch_bounds__(256) void k_split_vectors(const XT *__restrict__ X,
         __bf16 h0, l0, h1, l1;
         split_bf16(a, h0, l0);
         split_bf16(b, h1, l1);
-        Bh[c * Kp + 2 * n] = h0;
-        Bh[c * Kp + 2 * n + 1] = h1;
-        if (lo) {
-            Bl[c * Kp + 2 * n] = l0;
-            Bl[c * Kp + 2 * n + 1] = l1;
-        }
+        hi[2 * e] = h0;
+        hi[2 * e + 1] = h1;
+        lw[2 * e] = l0;
+        lw[2 * e + 1] = l1;
     }
+    const int64_t off = tile * 512 + (threadIdx.x & 63) * 8;
+    *reinterpret_cast<bf16x8 *>(Bh + off) = hi;
+    if (lo) *reinterpret_cast<bf16x8 *>(Bl + off) = lw;
+}
+
+// vmcnt(N) and lgkmcnt(0) in one wait (expcnt not waited on)
+template <int N> __device__ inline void wait_vm_lds()
+{
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt(0x070 | (N & 15) | ((N >> 4) << 14));
+}
+
+// Workgroup barrier without a memory fence: the LDS DMA completions it must
+// order are waited for explicitly (wait_vm_lds) by every wave before it.  The
+// empty asm statements keep the compiler from moving memory accesses across.
+__device__ inline void block_barrier()
+{
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+// 16 bytes per lane from global memory into LDS at l + 16 * lane (l uniform).
+__device__ inline void lds_dma16(const void *g, void *l)
+{
+    __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void *)l, 16, 0, 0);
 }
 
 // Partial C = Ah Bh + Al Bh (+ Ah Bl when TERMS == 3) over the stages of one K
 // slice, into P[z][Mp][NCp].  TERMS == 2 keeps the matrix split (about 16
 // significant bits) and rounds the vectors to BF16 (2^-9 relative): the form
 // for the inner corrections of iterative refinement, whose tolerance is far
-// above that rounding; the B lo plane is then neither loaded nor stored.
-template <int TERMS>
-__global__ __launch_bounds__(512) void k_gemm_split(const __bf16 *__restrict__ Ah, const __bf16 *__restrict__ Al,
-                                                    const __bf16 *__restrict__ Bh, const __bf16 *__restrict__ Bl,
-                                                    int64_t Kp, int64_t Mp, int64_t NCp, float *__restrict__ P)
+// above that rounding; the B lo plane is then not loaded.
+template <int TERMS, int WM, int WN, int NS>
+__global__ __launch_bounds__(64 * (GBM / WM) * (GBN / WN)) void k_gemm_split(
+    const __bf16 *__restrict__ Ah, const __bf16 *__restrict__ Al, const __bf16 *__restrict__ Bh,
+    const __bf16 *__restrict__ Bl, int64_t Kp, int64_t Mp, int64_t NCp, float *__restrict__ P)
 {
-    __shared__ __attribute__((aligned(16))) __bf16 sA[2][2][GBM][PK];   // [buffer][plane][row][k]
-    __shared__ __attribute__((aligned(16))) __bf16 sB[2][2][GBN][PK];   // [buffer][plane][col][k]
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 2, wn = wave & 3;   // wave tile: rows 128 wm .. +128, columns 64 wn .. +64
+    constexpr int TIw = WM / 32, TJw = WN / 32, NWN = GBN / WN, W = (GBM / WM) * (GBN / WN);
+    constexpr int SA = GBM / 32, SB = GBN / 32;                  // tiles of A and of B per plane and stage
+    constexpr int LOADS = 2 * SA + (TERMS == 3 ? 2 : 1) * SB;   // DMA instructions per stage
+    static_assert(LOADS % W == 0 && NS >= 3, "stage loads are shared evenly by the waves");
+    constexpr int LPW = LOADS / W;
+    constexpr int STAGE = (2 * SA + 2 * SB) * 512;              // BF16 per stage buffer
+    __shared__ __attribute__((aligned(1024))) __bf16 lds[NS][STAGE];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wm = wave / NWN, wn = wave % NWN;
     unsigned bx, by, bz;
     xcd_tile(bx, by, bz);
     const int64_t m0 = int64_t(bx) * GBM, c0 = int64_t(by) * GBN;
+    const int64_t nst = Kp / GBK;
 
-    // global -> register staging (16-byte chunks): per plane, A 256 x 32 and
-    // B 256 x 32 = 1024 chunks each (2 per thread)
-    constexpr int CPR = GBK / 8;   // chunks per row
-    u32x4 ra[2][2], rb[2][2];
-    auto gload = [&](int64_t k0) {
+    // the DMA instructions of this wave: tile q of the stage, its source (stage
+    // 0) and its place in the stage buffer
+    const __bf16 *src[LPW];
+    int dst[LPW];
 #pragma unroll
-        for (int p = 0; p < 2; ++p)
+    for (int q = 0; q < LPW; ++q) {
+        const int i = wave + W * q;
+        if (i < 2 * SA) {
+            const int p = i / SA, t = i % SA;
+            src[q] = (p ? Al : Ah) + (m0 / 32 + t) * nst * 512;
+            dst[q] = (p * SA + t) * 512;
+        } else {
+            const int j = i - 2 * SA, p = j / SB, t = j % SB;
+            src[q] = (p ? Bl : Bh) + (c0 / 32 + t) * nst * 512;
+            dst[q] = (2 * SA + p * SB + t) * 512;
+        }
+    }
+    const int64_t sb = nst * bz / gridDim.z, n = nst * (bz + 1) / gridDim.z - sb;
+    auto issue = [&](int64_t st, int buf) {
 #pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const int c = tid + 512 * q;
-                ra[p][q] = *reinterpret_cast<const u32x4 *>((p ? Al : Ah) + (m0 + c / CPR) * Kp + k0 + (c % CPR) * 8);
-                if (TERMS == 3 || p == 0)
-                    rb[p][q] = *reinterpret_cast<const u32x4 *>((p ? Bl : Bh) + (c0 + c / CPR) * Kp + k0 + (c % CPR) * 8);
-            }
-    };
-    auto lstore = [&](int buf) {
-#pragma unroll
-        for (int p = 0; p < 2; ++p)
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const int c = tid + 512 * q;
-                *reinterpret_cast<u32x4 *>(&sA[buf][p][c / CPR][(c % CPR) * 8]) = ra[p][q];
-                if (TERMS == 3 || p == 0) *reinterpret_cast<u32x4 *>(&sB[buf][p][c / CPR][(c % CPR) * 8]) = rb[p][q];
-            }
+        for (int q = 0; q < LPW; ++q) lds_dma16(src[q] + (sb + st) * 512 + lane * 8, &lds[buf][dst[q]]);
     };
 
-    f32x16 acc[TI][TJ];
+    f32x16 acc[TIw][TJw];
 #pragma unroll
-    for (int i = 0; i < TI; ++i)
+    for (int i = 0; i < TIw; ++i)
 #pragma unroll
-        for (int j = 0; j < TJ; ++j)
+        for (int j = 0; j < TJw; ++j)
 #pragma unroll
             for (int q = 0; q < 16; ++q) acc[i][j][q] = 0.f;
 
-    const int fr = lane & 31, fk = (lane >> 5) * 8;
-    // pipeline: stage s is computed from LDS buffer s%2 while stage s+1 is
-    // stored into the other buffer and stage s+2 is in flight to registers;
-    // one barrier per stage
-    const int64_t nall = Kp / GBK, sb = nall * bz / gridDim.z, se = nall * (bz + 1) / gridDim.z;
-    gload(sb * GBK);
-    lstore(0);
-    if (se - sb > 1) gload((sb + 1) * GBK);
-    __syncthreads();
-    for (int64_t st = sb; st < se; ++st) {
-        const int buf = int((st - sb) & 1);
+    const int fr = lane & 31, foff = tile_slot(fr, lane >> 5) * 8;
+    const int aoff = (wm * WM / 32) * 512 + foff, boff = (2 * SA + wn * WN / 32) * 512 + foff;
+    bf16x8 xa[TIw][2], xb[TJw][2], ya[TIw][2], yb[TJw][2];   // [tile][plane], two register sets
+    auto fetch = [&](int buf, bf16x8 (&fa)[TIw][2], bf16x8 (&fb)[TJw][2]) {
+        const __bf16 *L = &lds[buf][0];
 #pragma unroll
-        for (int kk = 0; kk < GBK; kk += 16) {
-            bf16x8 a[TI][2], b[TJ][2];   // [tile][plane]
+        for (int p = 0; p < 2; ++p) {
 #pragma unroll
-            for (int p = 0; p < 2; ++p) {
+            for (int t = 0; t < TIw; ++t) fa[t][p] = *reinterpret_cast<const bf16x8 *>(L + aoff + (p * SA + t) * 512);
+            if (TERMS == 3 || p == 0)
 #pragma unroll
-                for (int t = 0; t < TI; ++t)
-                    a[t][p] = *reinterpret_cast<const bf16x8 *>(&sA[buf][p][wm * 128 + t * 32 + fr][kk + fk]);
-                if (TERMS == 3 || p == 0)
-#pragma unroll
-                    for (int t = 0; t < TJ; ++t)
-                        b[t][p] = *reinterpret_cast<const bf16x8 *>(&sB[buf][p][wn * 64 + t * 32 + fr][kk + fk]);
-            }
-            // the products, each over the 8 independent accumulators
-#pragma unroll
-            for (int i = 0; i < TI; ++i)
-#pragma unroll
-                for (int j = 0; j < TJ; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][0], acc[i][j], 0, 0, 0);
-            if (TERMS == 3)
-#pragma unroll
-                for (int i = 0; i < TI; ++i)
-#pragma unroll
-                    for (int j = 0; j < TJ; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][1], acc[i][j], 0, 0, 0);
-#pragma unroll
-            for (int i = 0; i < TI; ++i)
-#pragma unroll
-                for (int j = 0; j < TJ; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][1], b[j][0], acc[i][j], 0, 0, 0);
+                for (int t = 0; t < TJw; ++t)
+                    fb[t][p] = *reinterpret_cast<const bf16x8 *>(L + boff + (p * SB + t) * 512);
         }
-        if (st + 1 < se) {
-            lstore(buf ^ 1);                         // stage st+1 (already in registers)
-            if (st + 2 < se) gload((st + 2) * GBK);  // stage st+2 in flight during the next compute
-        }
-        __syncthreads();
+    };
+    // the products, each over the independent accumulators
+    auto mfma = [&](const bf16x8 (&fa)[TIw][2], const bf16x8 (&fb)[TJw][2]) {
+#pragma unroll
+        for (int i = 0; i < TIw; ++i)
+#pragma unroll
+            for (int j = 0; j < TJw; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i][0], fb[j][0], acc[i][j], 0, 0, 0);
+        if (TERMS == 3)
+#pragma unroll
+            for (int i = 0; i < TIw; ++i)
+#pragma unroll
+                for (int j = 0; j < TJw; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i][0], fb[j][1], acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < TIw; ++i)
+#pragma unroll
+            for (int j = 0; j < TJw; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i][1], fb[j][0], acc[i][j], 0, 0, 0);
+    };
+    // step i while stage i + NS exists: stages i+1 .. i+NS-1 are in flight;
+    // wait for i+1 (its NS-2 successors may stay outstanding)
+    auto steady = [&](int64_t i, const bf16x8 (&fa)[TIw][2], const bf16x8 (&fb)[TJw][2], bf16x8 (&ga)[TIw][2],
+                      bf16x8 (&gb)[TJw][2]) {
+        __builtin_amdgcn_sched_barrier(0);
+        wait_vm_lds<(NS - 2) * LPW>();
+        block_barrier();
+        issue(i + NS, int(i % NS));
+        fetch(int((i + 1) % NS), ga, gb);
+        __builtin_amdgcn_sched_barrier(0);
+        mfma(fa, fb);
+    };
+    // the last steps: wait for everything in flight
+    auto tail = [&](int64_t i, const bf16x8 (&fa)[TIw][2], const bf16x8 (&fb)[TJw][2], bf16x8 (&ga)[TIw][2],
+                    bf16x8 (&gb)[TJw][2]) {
+        __builtin_amdgcn_sched_barrier(0);
+        wait_vm_lds<0>();
+        block_barrier();
+        if (i + NS < n) issue(i + NS, int(i % NS));
+        if (i + 1 < n) fetch(int((i + 1) % NS), ga, gb);
+        __builtin_amdgcn_sched_barrier(0);
+        mfma(fa, fb);
+    };
+
+    if (n >= NS) {
+#pragma unroll
+        for (int d = 0; d < NS; ++d) issue(d, d);
+        wait_vm_lds<(NS - 1) * LPW>();
+    } else {
+        for (int64_t d = 0; d < n; ++d) issue(d, int(d));
+        wait_vm_lds<0>();
     }
+    block_barrier();
+    if (n > 0) fetch(0, xa, xb);
+    int64_t i = 0;
+    for (; i + 1 + NS < n; i += 2) {   // two steps per trip: the register sets swap roles
+        steady(i, xa, xb, ya, yb);
+        steady(i + 1, ya, yb, xa, xb);
+    }
+    for (; i < n; i += 2) {
+        tail(i, xa, xb, ya, yb);
+        if (i + 1 < n) tail(i + 1, ya, yb, xa, xb);
+    }
+
     // accumulator q of lane l holds row 8(q/4) + 4(l/32) + q%4, column l%32 of its 32x32 tile
     float *Pz = P + int64_t(bz) * Mp * NCp;
 #pragma unroll
-    for (int i = 0; i < TI; ++i)
+    for (int i2 = 0; i2 < TIw; ++i2)
 #pragma unroll
-        for (int j = 0; j < TJ; ++j) {
-            const int64_t c = c0 + wn * 64 + j * 32 + (lane & 31);
+        for (int j = 0; j < TJw; ++j) {
+            const int64_t c = c0 + wn * WN + j * 32 + (lane & 31);
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
-                const int64_t m = m0 + wm * 128 + i * 32 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
-                Pz[m * NCp + c] = acc[i][j][q];
+                const int64_t m = m0 + wm * WM + i2 * 32 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+                Pz[m * NCp + c] = acc[i2][j][q];
             }
         }
 }
@@ -409,13 +508,40 @@ int gemm_splitk(int64_t blocks, int64_t nst)
     return int(std::max<int64_t>(1, std::min<int64_t>(ks, 64)));
 }
 
+template <int WM, int WN, int NS>
+void launch_split(int terms, dim3 grid, hipStream_t s, const __bf16 *Ah, const __bf16 *Al, const __bf16 *Bh,
+                  const __bf16 *Bl, int64_t Kp, int64_t Mp, int64_t NCp, float *P)
+{
+    constexpr int NT = 64 * (GBM / WM) * (GBN / WN);
+    if (terms == 3)
+        hipLaunchKernelGGL((k_gemm_split<3, WM, WN, NS>), grid, dim3(NT), 0, s, Ah, Al, Bh, Bl, Kp, Mp, NCp, P);
+    else
+        hipLaunchKernelGGL((k_gemm_split<2, WM, WN, NS>), grid, dim3(NT), 0, s, Ah, Al, Bh, Bl, Kp, Mp, NCp, P);
+}
+
+typedef void (*SplitLaunch)(int, dim3, hipStream_t, const __bf16 *, const __bf16 *, const __bf16 *, const __bf16 *,
+                            int64_t, int64_t, int64_t, float *);
+// wave tiles of the 256 x 256 block: 128 x 64 (default), 64 x 128, 128 x 128
+// (accumulators in AGPRs); BIE_GEMM_CFG = 0, 1, 2 selects one (measurement)
+const SplitLaunch kSplitLaunch[] = { launch_split<128, 64, 4>, launch_split<64, 128, 4>, launch_split<128, 128, 4> };
+
+SplitLaunch split_launch()
+{
+    static const int idx = [] {
+        const char *e = getenv("BIE_GEMM_CFG");
+        const int v = e ? atoi(e) : 0;
+        return v >= 0 && v < int(sizeof(kSplitLaunch) / sizeof(kSplitLaunch[0])) ? v : 0;
+    }();
+    return kSplitLaunch[idx];
+}
+
 }  // namespace
 
 int64_t gemm_pad_rows(int64_t N) { return (N + GBM - 1) / GBM * GBM; }
 int64_t gemm_pad_k(int64_t N) { return (2 * N + GBK - 1) / GBK * GBK; }
 int64_t gemm_pad_cols(int64_t R) { return (2 * R + GBN - 1) / GBN * GBN; }
 
-// Split-BF16 copy of the FP64 matrix (A planes, hi then lo).
+// Split-BF16 copy of the FP64 matrix (A planes, hi then lo, tiled).
 void split_matrix(bie_op *op, hipStream_t s)
 {
     const int64_t N = op->mesh.N, Mp = gemm_pad_rows(N), Kp = gemm_pad_k(N);
@@ -424,8 +550,9 @@ void split_matrix(bie_op *op, hipStream_t s)
     op->gemm_Mp = Mp;
     op->gemm_Kp = Kp;
     __bf16 *Ah = static_cast<__bf16 *>(op->Abf), *Al = Ah + plane;
-    const dim3 grid(unsigned(std::min<int64_t>((Kp / 2 + 255) / 256, 64)), unsigned(Mp));
-    hipLaunchKernelGGL(k_split_matrix, grid, dim3(256), 0, s, (const double2 *)op->Z64, N, op->pk.nT, Kp, Ah, Al);
+    const int64_t tiles = (Mp / 32) * (Kp / GBK);
+    hipLaunchKernelGGL(k_split_matrix, dim3(unsigned((tiles + 3) / 4)), dim3(256), 0, s, (const double2 *)op->Z64, N,
+                       op->pk.nT, Mp, Kp, Ah, Al);
     BIE_HIP(hipGetLastError());
     BIE_HIP(hipStreamSynchronize(s));
 }
@@ -462,25 +589,22 @@ void gemm_product(const bie_op *opc, const void *X, int64_t ldx, bool xf32, void
     __bf16 *Bh = static_cast<__bf16 *>(op->Bbf), *Bl = Bh + plane;
     const __bf16 *Ah = static_cast<const __bf16 *>(op->Abf), *Al = Ah + size_t(Mp) * size_t(Kp);
     float *P = static_cast<float *>(op->gemm_part);
-    const dim3 sgrid(unsigned(std::min<int64_t>((Kp / 2 + 255) / 256, 64)), unsigned(NCp));
+    const int64_t btiles = (NCp / 32) * (Kp / GBK);
+    const dim3 sgrid(unsigned((btiles + 3) / 4));
     if (xf32)
-        hipLaunchKernelGGL(k_split_vectors<float2>, sgrid, dim3(256), 0, s, (const float2 *)X, ldx, cols, N, R, Kp, Bh,
-                           Bl, terms == 3);
+        hipLaunchKernelGGL(k_split_vectors<float2>, sgrid, dim3(256), 0, s, (const float2 *)X, ldx, cols, N, R, NCp,
+                           Kp, Bh, Bl, terms == 3);
     else
-        hipLaunchKernelGGL(k_split_vectors<double2>, sgrid, dim3(256), 0, s, (const double2 *)X, ldx, cols, N, R, Kp,
-                           Bh, Bl, terms == 3);
+        hipLaunchKernelGGL(k_split_vectors<double2>, sgrid, dim3(256), 0, s, (const double2 *)X, ldx, cols, N, R, NCp,
+                           Kp, Bh, Bl, terms == 3);
     prof_begin(1, s, R);
-    const dim3 ggrid(unsigned(Mp / GBM), unsigned(NCp / GBN), unsigned(KS));
-    if (terms == 3)
-        hipLaunchKernelGGL(k_gemm_split<3>, ggrid, dim3(512), 0, s, Ah, Al, Bh, Bl, Kp, Mp, NCp, P);
-    else
-        hipLaunchKernelGGL(k_gemm_split<2>, ggrid, dim3(512), 0, s, Ah, Al, Bh, Bl, Kp, Mp, NCp, P);
+    split_launch()(terms, dim3(unsigned(Mp / GBM), unsigned(NCp / GBN), unsigned(KS)), s, Ah, Al, Bh, Bl, Kp, Mp,
+                   NCp, P);
     prof_end(1, s);
     hipLaunchKernelGGL(k_gemm_reduce<float>, dim3(unsigned(Mp / 64), unsigned(NCp / 64)), dim3(256), 0, s, P, KS, Mp,
                        NCp, N, R, cols, (double2 *)Y, ldy, (const double2 *)Bsub, ldb);
     BIE_HIP(hipGetLastError());
 }
-
 
 // Dense FP64 copy of the packed matrix for the FP64 block product.
 void dense64_setup(bie_op *op, hipStream_t s)
