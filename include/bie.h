@@ -205,7 +205,9 @@ int bie_batch_solve(const bie_op *const *ops, int64_t nops, const void *const *B
  * work item in {4, 8, 32} chosen per batch shape by timing the candidates on
  * the batch; the choices are kept for the process and appended to the file
  * named by BIE_AUTOTUNE_CACHE if set; > 0: that many tiles per unit, 8 columns
- * per item) and graph replay (1: default). */
+ * per item; -1: each operator's own single-product units, 8 columns per item,
+ * which makes every column bitwise equal to its single solve) and graph replay
+ * (1: default).  BIE_EINVAL outside -1..64. */
 int bie_batch_config(int unit_tiles, int use_graph);
 /* Tiles per unit chosen for this batch shape so far (0: none). */
 int bie_batch_tuned(const bie_op *const *ops, int64_t nops, const int64_t *R);
@@ -298,8 +300,10 @@ void bie_ws_destroy(bie_ws *ws);
 /* Measurement support (not part of the method): with on != 0 every launch of
  * the dense product kernels (from bie_apply and inside bie_solve) is bracketed
  * by HIP events on the stream it runs on.  bie_prof_read waits for the
- * recorded events of `kernel` (0: packed symmetric product, 1: split-BF16
- * block product) and returns the number of launches, their summed duration in
+ * recorded events of `kernel` (0: tile pass of the packed symmetric product,
+ * 1: split-BF16 block product, 2: FP64 block product, 3: reduction of the
+ * packed product's partial sums; BIE_EINVAL otherwise) and returns the number
+ * of launches, their summed duration in
  * ms and (columns, may be NULL) the summed number of right-hand sides of those
  * launches (the packed product counts every column of its grid, skipped ones
  * included) since the previous read, then clears that record. */

@@ -314,7 +314,8 @@ def batch_solve(ops, Bs, opts: Solve | None = None, x0s=None, x0_fallback: bool 
 
 
 def batch_config(unit_tiles: int = 0, graph: bool = True):
-    """Tiles per unit of the grouped product (0: autotune) and graph replay of batched solves."""
+    """Tiles per unit of the grouped product (0: autotune; -1: each operator's own
+    single-product units, bitwise equal to single solves) and graph replay of batched solves."""
     _check(_lib.bie_batch_config(int(unit_tiles), int(graph)))
 
 

@@ -257,7 +257,7 @@ int bie_batch_solve(const bie_op *const *ops, int64_t nops, const void *const *B
 int bie_batch_config(int unit_tiles, int use_graph)
 {
     return guarded([&]() -> int {
-        if (unit_tiles < 0 || unit_tiles > 64) return fail(BIE_EINVAL, "unit_tiles must be 0..64");
+        if (unit_tiles < -1 || unit_tiles > 64) return fail(BIE_EINVAL, "unit_tiles must be -1..64");
         bie::batch_config(unit_tiles, use_graph != 0);
         return BIE_OK;
     });

@@ -70,6 +70,10 @@ struct Packed {
     int64_t N = 0, nT = 0, ntiles = 0, nunits = 0;
     int32_t *units = nullptr;      // device, nunits x 3: (I, J0, J1) = tiles J0..J1-1 of tile row I
     int32_t *unit_ptr = nullptr;   // device, nT + 1: units of tile row I are unit_ptr[I] .. unit_ptr[I+1]-1
+    int32_t *run_ptr = nullptr;    // device, nruns + 1: block b of the tile pass takes units run_ptr[b] ..
+    int64_t nruns = 0;
+    std::vector<int32_t> h_units, h_unit_ptr;   // host copies of the unit tables
+    std::vector<int64_t> h_seg;
     int64_t *seg = nullptr;        // device, nT + 1: partial vectors of row block I occupy slots seg[I]..seg[I+1]-1
     int64_t nslots = 0;            // partial vectors per product vector (= seg[nT])
     void *part = nullptr;          // device partial sums of the product, sized for part_R vectors

@@ -30,8 +30,9 @@
 namespace bie {
 
 // Optional timing of the dense product kernels: events recorded on the launch
-// stream around every launch (record 0: packed FP64/FP32 product, 1: split-BF16
-// block product, 2: FP64 block product).
+// stream around every launch (record 0: tile pass of the packed FP64/FP32
+// product, 1: split-BF16 block product, 2: FP64 block product, 3: reduction of
+// the packed product's partial sums).
 namespace prof {
 bool on = false;
 struct Rec {
@@ -39,7 +40,7 @@ struct Rec {
     size_t used = 0;
     int64_t cols = 0;   // right-hand sides over the recorded launches
 };
-Rec rec[3];
+Rec rec[4];
 
 void begin(int k, hipStream_t s, int64_t ncols)
 {
@@ -70,7 +71,7 @@ void prof_end(int kernel, hipStream_t s) { prof::end(kernel, s); }
 
 void prof_read(int kernel, int64_t *launches, double *total_ms, int64_t *columns)
 {
-    if (kernel < 0 || kernel > 2) throw Error(BIE_EINVAL, "unknown kernel record");
+    if (kernel < 0 || kernel > 3) throw Error(BIE_EINVAL, "unknown kernel record");
     prof::Rec &r = prof::rec[kernel];
     double t = 0.0;
     for (size_t i = 0; i < r.used; ++i) {
@@ -88,13 +89,15 @@ void prof_read(int kernel, int64_t *launches, double *total_ms, int64_t *columns
 
 namespace {
 
-// tiles per work unit of the tile pass (BIE_SYM_UNIT overrides)
+// Work of the single-operator tile pass: 0 (default) = balanced runs, one per
+// block; BIE_SYM_UNIT = 1..64 selects units of that many tiles, one per block
+// (measurement).
 int unit_tiles()
 {
     static int v = [] {
         const char *e = getenv("BIE_SYM_UNIT");
-        const int u = e ? atoi(e) : 8;
-        return u >= 1 && u <= 64 ? u : 8;
+        const int u = e ? atoi(e) : 0;
+        return u >= 1 && u <= 64 ? u : 0;
     }();
     return v;
 }
@@ -196,26 +199,37 @@ __device__ inline void tile_pass(const M *__restrict__ Zp, int64_t N, int64_t nT
     for (int i = 0; i < 16; ++i) { rar[i] = 0; rai[i] = 0; }
     __shared__ V2 red[2][4][TB];
 
+    // x_J of lane's column, loaded with the tile it multiplies (a load issued
+    // just before its use would expose its latency once per tile)
+    auto xcol = [&](int32_t J) {
+        const int64_t n = int64_t(J) * TB + lane;
+        V2 v = { 0, 0 };
+        if (n < N) v = x[n];
+        return v;
+    };
     MV t[16];
+    V2 xt = { 0, 0 };
     if (PREFETCH) {
         const MV *tile = Z + tile_of(I, J0, nT) * TB * TB + (wave * 16) * TB + lane;
 #pragma unroll
         for (int i = 0; i < 16; ++i) t[i] = NT ? __builtin_nontemporal_load(tile + i * TB) : tile[i * TB];
+        xt = xcol(J0);
     }
     for (int32_t J = J0; J < J1; ++J) {
-        const int64_t n = int64_t(J) * TB + lane;
-        V2 xj = { 0, 0 };
-        if (n < N) xj = x[n];
+        V2 xj;
         MV cur[16];
         if (PREFETCH) {
 #pragma unroll
             for (int i = 0; i < 16; ++i) cur[i] = t[i];
+            xj = xt;
             if (J + 1 < J1) {   // next tile's loads go out before this tile's arithmetic
                 const MV *tile = Z + tile_of(I, J + 1, nT) * TB * TB + (wave * 16) * TB + lane;
 #pragma unroll
                 for (int i = 0; i < 16; ++i) t[i] = NT ? __builtin_nontemporal_load(tile + i * TB) : tile[i * TB];
+                xt = xcol(J + 1);
             }
         } else {
+            xj = xcol(J);
             const MV *tile = Z + tile_of(I, J, nT) * TB * TB + (wave * 16) * TB + lane;
 #pragma unroll
             for (int i = 0; i < 16; ++i) cur[i] = NT ? __builtin_nontemporal_load(tile + i * TB) : tile[i * TB];
@@ -254,22 +268,29 @@ __device__ inline void tile_pass(const M *__restrict__ Zp, int64_t N, int64_t nT
     }
 }
 
-// Tile pass over the units of one problem: block (unit u, vector v).
-template <typename M, typename T, bool CONJ, bool PREFETCH>
+// Tile pass over the units of one problem: block (run b, vector v) takes the
+// units run_ptr[b] .. run_ptr[b+1]-1 in turn (a barrier between units: the
+// LDS buffers of the column sums restart at parity 0).
+template <typename M, typename T, bool CONJ, bool PREFETCH, bool NT>
 __global__ __launch_bounds__(256) void k_sym_tiles(const M *__restrict__ Zp, int64_t N, int64_t nT,
                                                    const int32_t *__restrict__ units,
                                                    const int32_t *__restrict__ unit_ptr,
+                                                   const int32_t *__restrict__ run_ptr,
                                                    const int64_t *__restrict__ seg, int64_t nslots,
                                                    const T *__restrict__ X, int64_t ldx, T *__restrict__ part,
                                                    const int *__restrict__ skip, int64_t sks)
 {
     using V2 = typename Cx<T>::type;
-    const int64_t u = blockIdx.x, v = blockIdx.y;
+    const int64_t v = blockIdx.y;
     if (skip && skip[v * sks]) return;
-    const int32_t I = units[3 * u], J0 = units[3 * u + 1], J1 = units[3 * u + 2];
-    tile_pass<M, T, CONJ, PREFETCH>(Zp, N, nT, I, J0, J1, u - unit_ptr[I], seg,
-                                    reinterpret_cast<const V2 *>(X) + v * ldx,
-                                    reinterpret_cast<V2 *>(part) + v * nslots * TB);
+    const int32_t u0 = run_ptr[blockIdx.x], u1 = run_ptr[blockIdx.x + 1];
+    for (int32_t u = u0; u < u1; ++u) {
+        if (u > u0) __syncthreads();
+        const int32_t I = units[3 * u], J0 = units[3 * u + 1], J1 = units[3 * u + 2];
+        tile_pass<M, T, CONJ, PREFETCH, NT>(Zp, N, nT, I, J0, J1, u - unit_ptr[I], seg,
+                                        reinterpret_cast<const V2 *>(X) + v * ldx,
+                                        reinterpret_cast<V2 *>(part) + v * nslots * TB);
+    }
 }
 
 // Grouped tile pass over several problems: block b is the work item (problem
@@ -437,38 +458,85 @@ void launch_product(const bie_op *op, const void *Z, const void *X, int64_t ldx,
                     int64_t ldb, int64_t R, const int *skip, int64_t sks, hipStream_t s)
 {
     const Packed &pk = op->pk;
-    const dim3 grid(unsigned(pk.nunits), unsigned(R));
+    const dim3 grid(unsigned(pk.nruns), unsigned(R));
     prof::begin(0, s, R);
+    // non-temporal tile loads for the FP64 matrix, cached loads for the FP32
+    // one (measured: 92 vs 144 us, 52 vs 47 us at N = 7680)
+    constexpr bool NT = sizeof(M) == 8;
     if (sym_prefetch())
-        hipLaunchKernelGGL((k_sym_tiles<M, T, CONJ, true>), grid, dim3(256), 0, s, (const M *)Z, pk.N, pk.nT,
-                           pk.units, pk.unit_ptr, pk.seg, pk.nslots, (const T *)X, ldx, (T *)pk.part, skip, sks);
+        hipLaunchKernelGGL((k_sym_tiles<M, T, CONJ, true, NT>), grid, dim3(256), 0, s, (const M *)Z, pk.N, pk.nT,
+                           pk.units, pk.unit_ptr, pk.run_ptr, pk.seg, pk.nslots, (const T *)X, ldx, (T *)pk.part,
+                           skip, sks);
     else
-        hipLaunchKernelGGL((k_sym_tiles<M, T, CONJ, false>), grid, dim3(256), 0, s, (const M *)Z, pk.N, pk.nT,
-                           pk.units, pk.unit_ptr, pk.seg, pk.nslots, (const T *)X, ldx, (T *)pk.part, skip, sks);
+        hipLaunchKernelGGL((k_sym_tiles<M, T, CONJ, false, NT>), grid, dim3(256), 0, s, (const M *)Z, pk.N, pk.nT,
+                           pk.units, pk.unit_ptr, pk.run_ptr, pk.seg, pk.nslots, (const T *)X, ldx, (T *)pk.part,
+                           skip, sks);
+    prof::end(0, s);
+    prof::begin(3, s, R);
     hipLaunchKernelGGL((k_sym_reduce<T, SUB>), dim3(unsigned(pk.nT), unsigned(R)), dim3(512), 0, s, pk.N, pk.seg,
                        pk.nslots, (const T *)pk.part, (T *)Y, ldy, (const T *)B, ldb, skip, sks);
     BIE_HIP(hipGetLastError());
-    prof::end(0, s);
+    prof::end(3, s);
 }
 
 }  // namespace
+
+// Row pointers and partial-slot segments of a unit table sorted by tile row:
+// row block I owns the column sums of tiles (J < I, I), then one row-sum slot
+// per unit of tile row I.
+static void unit_rows(int64_t nT, const std::vector<int32_t> &units, std::vector<int32_t> &uptr,
+                      std::vector<int64_t> &seg)
+{
+    const int64_t nu = int64_t(units.size() / 3);
+    uptr.assign(nT + 1, int32_t(nu));
+    for (int64_t u = nu - 1; u >= 0; --u) uptr[units[3 * u]] = int32_t(u);
+    for (int64_t I = nT - 1; I >= 0; --I) uptr[I] = std::min(uptr[I], uptr[I + 1]);
+    seg.assign(nT + 1, 0);
+    for (int64_t I = 0; I < nT; ++I) seg[I + 1] = seg[I] + I + (uptr[I + 1] - uptr[I]);
+}
 
 void build_units(int64_t nT, int U, std::vector<int32_t> &units, std::vector<int32_t> &uptr,
                  std::vector<int64_t> &seg)
 {
     units.clear();
-    uptr.assign(nT + 1, 0);
-    for (int64_t I = 0; I < nT; ++I) {
-        uptr[I] = int32_t(units.size() / 3);
+    for (int64_t I = 0; I < nT; ++I)
         for (int64_t J0 = I; J0 < nT; J0 += U) {
             units.push_back(int32_t(I));
             units.push_back(int32_t(J0));
             units.push_back(int32_t(std::min<int64_t>(nT, J0 + U)));
         }
+    unit_rows(nT, units, uptr, seg);
+}
+
+// Balanced runs: the T = nT (nT + 1) / 2 stored tiles in row-major order
+// (I, J >= I) are cut into nb runs [T b / nb, T (b+1) / nb) of equal length
+// to within one tile, and each run into units at the ends of tile rows; run b
+// is units rptr[b] .. rptr[b+1]-1.  With nb = 512 (two 4-wave blocks on each of
+// the 256 CUs) every block of a single-vector product has the same work and
+// all are resident at once: no tail of short blocks.
+void build_runs(int64_t nT, int64_t nb, std::vector<int32_t> &units, std::vector<int32_t> &uptr,
+                std::vector<int64_t> &seg, std::vector<int32_t> &rptr)
+{
+    const int64_t T = nT * (nT + 1) / 2;
+    nb = std::max<int64_t>(1, std::min(nb, T));
+    units.clear();
+    rptr.assign(nb + 1, 0);
+    int64_t I = 0, J = 0, t = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+        rptr[b] = int32_t(units.size() / 3);
+        const int64_t t1 = T * (b + 1) / nb;
+        while (t < t1) {
+            const int64_t take = std::min(nT - J, t1 - t);
+            units.push_back(int32_t(I));
+            units.push_back(int32_t(J));
+            units.push_back(int32_t(J + take));
+            t += take;
+            J += take;
+            if (J == nT) J = ++I;
+        }
     }
-    uptr[nT] = int32_t(units.size() / 3);
-    seg.assign(nT + 1, 0);
-    for (int64_t I = 0; I < nT; ++I) seg[I + 1] = seg[I] + I + (uptr[I + 1] - uptr[I]);
+    rptr[nb] = int32_t(units.size() / 3);
+    unit_rows(nT, units, uptr, seg);
 }
 
 void packed_setup(bie_op *op)
@@ -477,17 +545,29 @@ void packed_setup(bie_op *op)
     pk.N = op->mesh.N;
     pk.nT = (pk.N + TB - 1) / TB;
     pk.ntiles = pk.nT * (pk.nT + 1) / 2;
-    std::vector<int32_t> units, uptr;
+    std::vector<int32_t> units, uptr, rptr;
     std::vector<int64_t> seg;
-    build_units(pk.nT, unit_tiles(), units, uptr, seg);
+    if (unit_tiles() > 0) {
+        build_units(pk.nT, unit_tiles(), units, uptr, seg);
+        rptr.resize(units.size() / 3 + 1);
+        for (size_t b = 0; b < rptr.size(); ++b) rptr[b] = int32_t(b);
+    } else {
+        build_runs(pk.nT, 512, units, uptr, seg, rptr);
+    }
     pk.nunits = int64_t(units.size() / 3);
+    pk.nruns = int64_t(rptr.size()) - 1;
     pk.nslots = seg[pk.nT];
     BIE_HIP(hipMalloc(&pk.seg, seg.size() * sizeof(int64_t)));
     BIE_HIP(hipMemcpy(pk.seg, seg.data(), seg.size() * sizeof(int64_t), hipMemcpyHostToDevice));
     BIE_HIP(hipMalloc(&pk.units, units.size() * sizeof(int32_t)));
     BIE_HIP(hipMalloc(&pk.unit_ptr, uptr.size() * sizeof(int32_t)));
+    BIE_HIP(hipMalloc(&pk.run_ptr, rptr.size() * sizeof(int32_t)));
     BIE_HIP(hipMemcpy(pk.units, units.data(), units.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     BIE_HIP(hipMemcpy(pk.unit_ptr, uptr.data(), uptr.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    BIE_HIP(hipMemcpy(pk.run_ptr, rptr.data(), rptr.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    pk.h_units = std::move(units);
+    pk.h_unit_ptr = std::move(uptr);
+    pk.h_seg = std::move(seg);
 }
 
 void packed_free(bie_op *op)
@@ -495,6 +575,8 @@ void packed_free(bie_op *op)
     Packed &pk = op->pk;
     if (pk.units) (void)hipFree(pk.units);
     if (pk.unit_ptr) (void)hipFree(pk.unit_ptr);
+    if (pk.run_ptr) (void)hipFree(pk.run_ptr);
+    pk.run_ptr = nullptr;
     if (pk.seg) (void)hipFree(pk.seg);
     pk.seg = nullptr;
     if (pk.part) (void)hipFree(pk.part);

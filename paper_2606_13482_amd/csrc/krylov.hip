@@ -1619,7 +1619,13 @@ std::unique_ptr<GLayout> make_layout(const bie_op *const *ops, int64_t P, const 
         const int64_t nT = ops[p]->pk.nT;
         std::vector<int32_t> units, uptr;
         std::vector<int64_t> seg;
-        build_units(nT, U, units, uptr, seg);
+        if (U < 0) {   // the operator's own single-product units
+            units = ops[p]->pk.h_units;
+            uptr = ops[p]->pk.h_unit_ptr;
+            seg = ops[p]->pk.h_seg;
+        } else {
+            build_units(nT, U, units, uptr, seg);
+        }
         int32_t *du = L->db.get<int32_t>(units.size());
         int32_t *dp = L->db.get<int32_t>(uptr.size());
         int64_t *ds = L->db.get<int64_t>(seg.size());
@@ -1821,7 +1827,7 @@ int solve_batch(const bie_op *const *ops, int64_t P, const void *const *Bp, void
     std::unique_ptr<GLayout> L;
     const std::string key = batch_key(ops, P, Rp, mat64);
     int U = g_batch.unit, G = 8;
-    if (U <= 0) {
+    if (U == 0) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         tune_cache_load();
         auto it = g_tune.find(key);
@@ -1833,7 +1839,7 @@ int solve_batch(const bie_op *const *ops, int64_t P, const void *const *Bp, void
     auto layout_cols = [&](const GLayout &gl, const int64_t *xoff, int64_t xstep) {
         return GCols{ dprob, xoff, dwo, gl.gpoff, xstep };
     };
-    if (U <= 0) {
+    if (U == 0) {
         // time each candidate: 1 warm-up + 3 products of the right-hand sides
         hipEvent_t e0, e1;
         BIE_HIP(hipEventCreate(&e0));

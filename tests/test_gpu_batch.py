@@ -41,11 +41,12 @@ def _ops(bie, storage):
 
 @pytest.mark.parametrize("graph", [True, False])
 def test_batch_equals_single_bitwise(bie, graph):
-    """With the tiles per unit of the single-operator product (8), every column of
-    the batch equals its single solve bitwise, with or without graph replay."""
+    """With the units of the single-operator product (batch_config(-1)), every
+    column of the batch equals its single solve bitwise, with or without graph
+    replay."""
     ops, Bs = _ops(bie, "c128")
     opts = bie.Solve(restart=20, tol=1e-8)
-    bie.batch_config(8, graph)
+    bie.batch_config(-1, graph)
     try:
         Xs, sts = bie.batch_solve(ops, Bs, opts)
     finally:
