@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--inner-tol", type=float, default=1e-1)
     ap.add_argument("--inner-terms", type=int, default=3, choices=[2, 3])
+    ap.add_argument("--basis", default="f16", choices=["f16", "c64"],
+                    help="storage of the inner Krylov basis (FP16 pairs or complex64)")
     ap.add_argument("--slots", type=int, default=256)
     ap.add_argument("--train-dirs", type=int, default=512)
     ap.add_argument("--test-dirs", type=int, default=256)
@@ -190,7 +192,7 @@ def headline_leg(args, bie, torch, V, T, k):
     res["setup_fill_split_s"] = round(time.perf_counter() - t0, 4)
     N = op.N
     mopts = bie.Solve(restart=args.restart, tol=args.tol, max_mvp=20000, precision="mixed",
-                      inner_tol=args.inner_tol, slots=args.slots, inner_terms=args.inner_terms)
+                      inner_tol=args.inner_tol, slots=args.slots, inner_terms=args.inner_terms, basis=args.basis)
     popts = bie.Solve(restart=args.restart, tol=args.tol, max_mvp=20000)
 
     # training: solutions the method computes, then POD + MLP on the GPU
@@ -323,7 +325,7 @@ def c3_run(args, bie, torch):
     dirs, pols = grid_planewaves(16, 16)
     R = dirs.shape[0]
     mopts = bie.Solve(restart=30, tol=args.tol, max_mvp=20000, precision="mixed", inner_tol=args.inner_tol,
-                      slots=args.slots, inner_terms=args.inner_terms)
+                      slots=args.slots, inner_terms=args.inner_terms, basis=args.basis)
 
     def step():
         B = op.rhs(dirs, pols)
@@ -527,9 +529,10 @@ def main():
                                 f"operator and warm start resident; learned warm start (POD {min(256, 2 * args.train_dirs)}, "
                                 f"MLP 4-512-512, trained on {2 * args.train_dirs} solves); GMRES({args.restart}) on "
                                 f"split-BF16 MFMA products with FP64 refinement to {args.tol:g} (FP64 SCC), "
+                                f"{'FP16' if args.basis == 'f16' else 'complex64'} inner Krylov basis, "
                                 f"continuous batch of {args.slots} slots"),
                    "N": N, "k": k, "restart": args.restart, "inner_tol": args.inner_tol, "slots": args.slots,
-                   "inner_terms": args.inner_terms,
+                   "inner_terms": args.inner_terms, "basis": args.basis,
                    "rhs_per_step": 2 * args.test_dirs, "train_directions": args.train_dirs,
                    "test_directions": args.test_dirs, "parallelism": "single GPU"},
         "roofline": roof,

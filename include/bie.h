@@ -152,6 +152,11 @@ typedef struct {
                             (hi/lo matrix x BF16 vector; the inner tolerance is then
                             raised to at least 1e-2, the rounding of the vectors
                             bounding what the inner solve can attain); 0: default 3 */
+    int basis;           /* precision 1, split-BF16: storage of the inner Krylov basis,
+                            0 complex64 (default) or 1 FP16 pairs (half the traffic of
+                            the Arnoldi kernels; the 3-term split of an FP16 vector into
+                            BF16 hi/lo is exact).  BIE_EINVAL for 1 with another
+                            precision or storage */
 } bie_solve_opts;
 
 typedef struct {

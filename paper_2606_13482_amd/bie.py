@@ -42,7 +42,8 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int), ("restart", ctypes.c_int), ("tol", ctypes.c_double),
                 ("max_mvp", ctypes.c_int64), ("crit", ctypes.c_int), ("rscc_rows", ctypes.c_int64),
                 ("rscc_seed", ctypes.c_uint64), ("use_x0", ctypes.c_int), ("precision", ctypes.c_int),
-                ("inner_tol", ctypes.c_double), ("slots", ctypes.c_int64), ("inner_terms", ctypes.c_int)]
+                ("inner_tol", ctypes.c_double), ("slots", ctypes.c_int64), ("inner_terms", ctypes.c_int),
+                ("basis", ctypes.c_int)]
 
 
 class WsOpts(ctypes.Structure):
@@ -169,12 +170,13 @@ class Solve:
     inner_tol: float = 0.0
     slots: int = 0                # mixed: right-hand sides in flight (continuous batch); 0 = all
     inner_terms: int = 0          # mixed, split-BF16: 3 or 2 terms of the inner block product; 0 = 3
+    basis: str = "c64"            # mixed, split-BF16: inner Krylov basis "c64" or "f16" (FP16 pairs)
 
     def c(self, use_x0: int) -> SolveOpts:
         return SolveOpts({"gmres": BIE_GMRES, "cgnr": BIE_CGNR}[self.method], self.restart, self.tol,
                          self.max_mvp, {"scc": BIE_SCC, "rscc": BIE_RSCC}[self.crit], self.rscc_rows,
                          self.rscc_seed, int(use_x0), {"plain": 0, "mixed": 1}[self.precision],
-                         self.inner_tol, self.slots, self.inner_terms)
+                         self.inner_tol, self.slots, self.inner_terms, {"c64": 0, "f16": 1}[self.basis])
 
 
 class Operator:

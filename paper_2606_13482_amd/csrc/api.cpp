@@ -210,6 +210,9 @@ int bie_solve(const bie_op *op, const void *B, void *X, int64_t R, const bie_sol
         if (o.use_x0 < 0 || o.use_x0 > 2) return fail(BIE_EINVAL, "use_x0 must be 0, 1 or 2");
         if (o.inner_terms != 0 && o.inner_terms != 2 && o.inner_terms != 3)
             return fail(BIE_EINVAL, "inner_terms must be 0, 2 or 3");
+        if (o.basis != 0 && o.basis != 1) return fail(BIE_EINVAL, "basis must be 0 or 1");
+        if (o.basis == 1 && (o.precision != 1 || !op->Abf))
+            return fail(BIE_EINVAL, "the FP16 basis is for mixed precision with split-BF16 storage");
         const int64_t N = op->mesh.N;
         hipStream_t s = as_stream(stream);
         if (bie::has_nonfinite(B, 2 * R * N, s)) return fail(BIE_ENUMERIC, "non-finite right-hand side");
@@ -228,7 +231,7 @@ int bie_batch_solve(const bie_op *const *ops, int64_t nops, const void *const *B
         if (nops < 1 || nops > 4096) return fail(BIE_EINVAL, "nops out of range (1..4096)");
         bie_solve_opts o{ BIE_GMRES, 30, 1e-6, 10000, BIE_SCC, 512, 1234, 0, 0, 0.0, 0, 0 };
         if (opts) o = *opts;
-        if (o.method != BIE_GMRES || o.precision != 0 || o.crit != BIE_SCC)
+        if (o.method != BIE_GMRES || o.precision != 0 || o.crit != BIE_SCC || o.basis != 0)
             return fail(BIE_EINVAL, "batched solves take GMRES, precision 0 and the standard criterion");
         if (o.restart < 1 || o.restart > 64) return fail(BIE_EINVAL, "restart must be 1..64");
         if (!(o.tol > 0.0)) return fail(BIE_EINVAL, "tol must be > 0");

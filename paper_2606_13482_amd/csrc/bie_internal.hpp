@@ -184,7 +184,13 @@ void prof_begin(int kernel, hipStream_t s, int64_t ncols);
 void prof_end(int kernel, hipStream_t s);
 // gemm.hip
 void split_matrix(bie_op *op, hipStream_t s);
-void gemm_product(const bie_op *op, const void *X, int64_t ldx, bool xf32, void *Y, int64_t ldy, const void *Bsub,
+// vector element types of the block product's right-hand block
+enum { VEC_C128 = 0, VEC_C64 = 1, VEC_F16 = 2 };
+// complex value as two FP16 (storage of the FP16 Krylov basis)
+struct c32h {
+    _Float16 x, y;
+};
+void gemm_product(const bie_op *op, const void *X, int64_t ldx, int vtype, void *Y, int64_t ldy, const void *Bsub,
                   int64_t ldb, int64_t R, const int *cols, hipStream_t s, int terms = 3);
 void dense64_setup(bie_op *op, hipStream_t s);
 void gemm64_product(const bie_op *op, const void *X, int64_t ldx, void *Y, int64_t ldy, const void *Bsub,

@@ -89,15 +89,16 @@ void prof_read(int kernel, int64_t *launches, double *total_ms, int64_t *columns
 
 namespace {
 
-// Work of the single-operator tile pass: 0 (default) = balanced runs, one per
-// block; BIE_SYM_UNIT = 1..64 selects units of that many tiles, one per block
-// (measurement).
+// Work of the single-operator tile pass: units of 8 tiles, one per block
+// (default); BIE_SYM_UNIT = 1..64 selects another unit length, 0 balanced runs
+// (measurement: at N = 7680 both take the same time, and on the small
+// matrices of the uneven batch the runs were slower).
 int unit_tiles()
 {
     static int v = [] {
         const char *e = getenv("BIE_SYM_UNIT");
-        const int u = e ? atoi(e) : 0;
-        return u >= 1 && u <= 64 ? u : 0;
+        const int u = e ? atoi(e) : 8;
+        return u >= 0 && u <= 64 ? u : 8;
     }();
     return v;
 }
@@ -172,7 +173,7 @@ __device__ inline void wave_sum8(T pr[8], T pi[8])
 // non-temporal tile loads (one vector streams the matrix once; several
 // vectors re-read the unit's tiles from the caches).
 template <typename M, typename T, bool CONJ, bool PREFETCH, bool NT = true>
-__device__ inline void tile_pass(const M *__restrict__ Zp, int64_t N, int64_t nT, int32_t I, int32_t J0, int32_t J1,
+__device__ __forceinline__ void tile_pass(const M *__restrict__ Zp, int64_t N, int64_t nT, int32_t I, int32_t J0, int32_t J1,
                                  int64_t uo, const int64_t *__restrict__ seg,
                                  const typename Cx<T>::type *__restrict__ x, typename Cx<T>::type *__restrict__ pv)
 {
@@ -270,9 +271,10 @@ __device__ inline void tile_pass(const M *__restrict__ Zp, int64_t N, int64_t nT
 
 // Tile pass over the units of one problem: block (run b, vector v) takes the
 // units run_ptr[b] .. run_ptr[b+1]-1 in turn (a barrier between units: the
-// LDS buffers of the column sums restart at parity 0).
+// LDS buffers of the column sums restart at parity 0).  At most 256 VGPRs:
+// two blocks per CU.
 template <typename M, typename T, bool CONJ, bool PREFETCH, bool NT>
-__global__ __launch_bounds__(256) void k_sym_tiles(const M *__restrict__ Zp, int64_t N, int64_t nT,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_sym_tiles(const M *__restrict__ Zp, int64_t N, int64_t nT,
                                                    const int32_t *__restrict__ units,
                                                    const int32_t *__restrict__ unit_ptr,
                                                    const int32_t *__restrict__ run_ptr,
@@ -513,7 +515,9 @@ void build_units(int64_t nT, int U, std::vector<int32_t> &units, std::vector<int
 // to within one tile, and each run into units at the ends of tile rows; run b
 // is units rptr[b] .. rptr[b+1]-1.  With nb = 512 (two 4-wave blocks on each of
 // the 256 CUs) every block of a single-vector product has the same work and
-// all are resident at once: no tail of short blocks.
+// all are resident at once; small matrices take fewer runs (at least 8 tiles
+// each: a run's fixed cost is loading x and writing its row sums).  Selected
+// with BIE_SYM_UNIT=0.
 void build_runs(int64_t nT, int64_t nb, std::vector<int32_t> &units, std::vector<int32_t> &uptr,
                 std::vector<int64_t> &seg, std::vector<int32_t> &rptr)
 {
@@ -551,8 +555,8 @@ void packed_setup(bie_op *op)
         build_units(pk.nT, unit_tiles(), units, uptr, seg);
         rptr.resize(units.size() / 3 + 1);
         for (size_t b = 0; b < rptr.size(); ++b) rptr[b] = int32_t(b);
-    } else {
-        build_runs(pk.nT, 512, units, uptr, seg, rptr);
+    } else {   // 512 runs, or fewer for small matrices: at least 8 tiles per run
+        build_runs(pk.nT, std::max<int64_t>(1, std::min<int64_t>(512, pk.ntiles / 8)), units, uptr, seg, rptr);
     }
     pk.nunits = int64_t(units.size() / 3);
     pk.nruns = int64_t(rptr.size()) - 1;
@@ -601,7 +605,7 @@ void product(const bie_op *opc, int mat, bool vec64, const void *X, int64_t ldx,
     if (mat == MATBF16) {
         if (!op->Abf) throw Error(BIE_EINVAL, "no split-BF16 matrix stored");
         if (!vec64 || conj) throw Error(BIE_EINVAL, "the block product takes complex128 vectors, no conjugate");
-        gemm_product(op, X, ldx, false, Y, ldy, B, ldb, R, nullptr, s);
+        gemm_product(op, X, ldx, VEC_C128, Y, ldy, B, ldb, R, nullptr, s);
         return;
     }
     const bool mat64 = mat == MAT64;

@@ -120,7 +120,7 @@ __global__ __launch_bounds__(256) void k_split_matrix(const double2 *__restrict_
 }
 
 // B planes (tiled, [NCp / 32][Kp / 16] tiles) from R complex vectors
-// (complex128 or complex64 XT): GEMM column pair r reads the vector at X + v*ldx,
+// (complex128, complex64 or FP16 pairs XT): GEMM column pair r reads the vector at X + v*ldx,
 // v = cols ? cols[r] : r.  One wave per tile.
 template <typename XT>
 __global__ __launch_bounds__(256) void k_split_vectors(const XT *__restrict__ X, int64_t ldx, const int *__restrict__ cols,
@@ -558,9 +558,9 @@ void split_matrix(bie_op *op, hipStream_t s)
 }
 
 // Y = T X (or Bsub - T X) for R vectors with the split-BF16 matrix; X
-// complex128 or complex64 (xf32), Y and Bsub complex128; cols (device, R
-// entries, or null for 0..R-1) names the vectors taking part.
-void gemm_product(const bie_op *opc, const void *X, int64_t ldx, bool xf32, void *Y, int64_t ldy, const void *Bsub,
+// complex128, complex64 or FP16 pairs (vtype), Y and Bsub complex128; cols
+// (device, R entries, or null for 0..R-1) names the vectors taking part.
+void gemm_product(const bie_op *opc, const void *X, int64_t ldx, int vtype, void *Y, int64_t ldy, const void *Bsub,
                   int64_t ldb, int64_t R, const int *cols, hipStream_t s, int terms)
 {
     if (terms != 2 && terms != 3) throw Error(BIE_EINVAL, "the split-BF16 product has 2 or 3 terms");
@@ -591,7 +591,10 @@ void gemm_product(const bie_op *opc, const void *X, int64_t ldx, bool xf32, void
     float *P = static_cast<float *>(op->gemm_part);
     const int64_t btiles = (NCp / 32) * (Kp / GBK);
     const dim3 sgrid(unsigned((btiles + 3) / 4));
-    if (xf32)
+    if (vtype == VEC_F16)
+        hipLaunchKernelGGL(k_split_vectors<c32h>, sgrid, dim3(256), 0, s, (const c32h *)X, ldx, cols, N, R, NCp, Kp,
+                           Bh, Bl, terms == 3);
+    else if (vtype == VEC_C64)
         hipLaunchKernelGGL(k_split_vectors<float2>, sgrid, dim3(256), 0, s, (const float2 *)X, ldx, cols, N, R, NCp,
                            Kp, Bh, Bl, terms == 3);
     else

@@ -324,19 +324,48 @@ def test_mixed_refinement_split_bf16_block(bie, terms):
     assert res.max() <= 1e-6 * (1 + 1e-6)
 
 
-@pytest.mark.parametrize("storage", ["split_bf16", "c64"])
-def test_continuous_batch_bitwise(bie, storage):
+def test_fp16_basis_refinement(bie):
+    """FP16 storage of the inner Krylov basis (split-BF16 products, FP64
+    refinement): converged to 1e-6 against the oracle matrix, with about the
+    iterations of the complex64 basis; the option is refused where it does not
+    apply."""
+    V, T, rwg, Zo = case(3, 6.0)
+    op = bie.Operator(V, T, 6.0, storage="split_bf16")
+    from paper_2606_13482_amd.inputs import random_directions
+    inc = random_directions(16, 21)
+    d, e = planewave_set(inc, "theta")
+    B = op.rhs(d, e)
+    Bn = B.cpu().numpy()
+    out = {}
+    for basis in ("c64", "f16"):
+        X, st = op.solve(B, bie.Solve(restart=30, tol=1e-6, precision="mixed", inner_tol=0.1, basis=basis))
+        res = np.linalg.norm(Bn - X.cpu().numpy() @ Zo.T, axis=1) / np.linalg.norm(Bn, axis=1)
+        assert all(s["converged"] for s in st), basis
+        assert res.max() <= 1e-6 * (1 + 1e-6), (basis, res.max())
+        out[basis] = sum(s["iters"] for s in st)
+        _say(f"  {basis} basis: max residual {res.max():.2e}, iterations {out[basis]}")
+    assert out["f16"] <= 1.25 * out["c64"]
+    with pytest.raises(bie.BieError):
+        op.solve(B[:1], bie.Solve(basis="f16"))   # plain precision
+    op64 = bie.Operator(V, T, 6.0, storage="c64", keep_fp64=True)
+    with pytest.raises(bie.BieError):
+        op64.solve(B[:1], bie.Solve(precision="mixed", basis="f16"))   # FP32 storage
+
+
+@pytest.mark.parametrize("storage,basis", [("split_bf16", "c64"), ("c64", "c64"), ("split_bf16", "f16")])
+def test_continuous_batch_bitwise(bie, storage, basis):
     """The refinement engine keeps a fixed number of right-hand sides in flight and
     hands the slot of a converged one to the next.  Every column is computed on its
     own (block product columns, Arnoldi, FP64 residual), so each solution is bitwise
-    the same whatever the number of slots, including one right-hand side alone."""
+    the same whatever the number of slots, including one right-hand side alone
+    (complex64 or FP16 inner Krylov basis)."""
     V, T, rwg, Zo = case(3, 6.0)
     op = bie.Operator(V, T, 6.0, storage=storage, keep_fp64=(storage == "c64"))
     from paper_2606_13482_amd.inputs import random_directions
     inc = random_directions(19, 8)
     d, e = planewave_set(inc, "phi")
     B = op.rhs(d, e)
-    base = bie.Solve(restart=20, tol=1e-6, precision="mixed", inner_tol=1e-2)
+    base = bie.Solve(restart=20, tol=1e-6, precision="mixed", inner_tol=1e-2, basis=basis)
     X0, st0 = op.solve(B, base)
     for slots in (3, 4, 17, 64):
         Xs, sts = op.solve(B, bie.Solve(**{**base.__dict__, "slots": slots}))
@@ -346,7 +375,7 @@ def test_continuous_batch_bitwise(bie, storage):
     assert torch.equal(X1[0], X0[5])
     Bn = B.cpu().numpy(); Xn = X0.cpu().numpy()
     res = np.linalg.norm(Bn - Xn @ Zo.T, axis=1) / np.linalg.norm(Bn, axis=1)
-    _say(f"  {storage}: max residual {res.max():.2e}, iterations {[s['iters'] for s in st0]}")
+    _say(f"  {storage} ({basis} basis): max residual {res.max():.2e}, iterations {[s['iters'] for s in st0]}")
     assert all(s["converged"] for s in st0)
     assert res.max() <= 1e-6 * (1 + 1e-6)
     for r in range(len(st0)):
