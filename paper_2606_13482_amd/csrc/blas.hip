@@ -295,6 +295,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     }
 }
 
+// a value known to be the same in every lane, moved to scalar registers
+__device__ inline int64_t uniform64(int64_t v)
+{
+    const uint64_t u = uint64_t(v);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(u)), hi = __builtin_amdgcn_readfirstlane(uint32_t(u >> 32));
+    return int64_t((uint64_t(hi) << 32) | lo);
+}
+
 // Grouped tile pass over several problems: block b is the work item (problem
 // p, unit u, column group g) and goes through columns c0 + gG .. of p in turn,
 // skipping finished ones; the unit's tiles come from memory for the first
@@ -308,14 +316,20 @@ __global__ __launch_bounds__(256) void k_sym_tiles_g(const GProb *__restrict__ p
     const int64_t b = blockIdx.x;
     const int32_t p = items[3 * b], u = items[3 * b + 1], g = items[3 * b + 2];
     const GProb P = probs[p];
-    const int32_t I = P.units[3 * u], J0 = P.units[3 * u + 1], J1 = P.units[3 * u + 2];
+    // values read through the tables' pointers are the same in every lane:
+    // made scalar so that the tile pass keeps its row indices and x of the
+    // tile rows in scalar registers, as in the single-operator pass
+    const int32_t I = __builtin_amdgcn_readfirstlane(P.units[3 * u]);
+    const int32_t J0 = __builtin_amdgcn_readfirstlane(P.units[3 * u + 1]);
+    const int32_t J1 = __builtin_amdgcn_readfirstlane(P.units[3 * u + 2]);
+    const int32_t uo = __builtin_amdgcn_readfirstlane(u - P.unit_ptr[I]);
     const int32_t cb = P.c0 + g * G, ce = min(P.c1, cb + G);
     for (int32_t c = cb; c < ce; ++c) {
         if (skip && skip[int64_t(c) * sks]) continue;   // uniform over the block
-        tile_pass<M, T, false, PREFETCH, false>(static_cast<const M *>(P.Z), P.N, P.nT, I, J0, J1,
-                                                u - P.unit_ptr[I], P.seg,
-                                                reinterpret_cast<const V2 *>(X) + gc.xoff[c] + gc.xstep * P.N,
-                                                reinterpret_cast<V2 *>(part) + gc.poff[c] * TB);
+        const int64_t xo = uniform64(gc.xoff[c] + gc.xstep * P.N), po = uniform64(gc.poff[c] * TB);
+        tile_pass<M, T, false, PREFETCH, false>(static_cast<const M *>(P.Z), P.N, P.nT, I, J0, J1, uo, P.seg,
+                                                reinterpret_cast<const V2 *>(X) + xo,
+                                                reinterpret_cast<V2 *>(part) + po);
     }
 }
 
