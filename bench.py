@@ -67,6 +67,8 @@ def parse():
                          "(theta, phi) grid x theta/phi, split-BF16 block GMRES with FP64 refinement")
     ap.add_argument("--no-batch", dest="batch", action="store_false",
                     help="skip the uneven batch of 64 surfaces (batched solves over many operators)")
+    ap.add_argument("--no-star", dest="star", action="store_false",
+                    help="skip the star-split operator leg (low-frequency mixed precision, product times)")
     ap.add_argument("--counters", action="store_true",
                     help="only launch the dense product kernels a few times at the bench sizes, and a 1 GiB "
                          "device copy as calibration, for hardware-counter runs")
@@ -388,6 +390,59 @@ def c3_run(args, bie, torch):
     return out
 
 
+def star_leg(args, bie, torch, V, T):
+    """Star-split operator (Sec. VI-A: T = jk T_A + Sigma V Sigma^T / (jk)) against
+    the assembled one on the bench sphere: (1) mixed precision with FP32 storage at
+    low frequency (k = 0.1), 16 plane waves to FP64 SCC 1e-6; (2) the FP64 product
+    time of both forms at the bench wavenumber."""
+    from paper_2606_13482_amd.inputs import random_directions, planewave_set
+    sync = torch.cuda.synchronize
+    d, e = planewave_set(random_directions(8, 66), "theta")
+    d2, e2 = planewave_set(random_directions(8, 66), "phi")
+    dirs, pols = np.concatenate([d, d2]), np.concatenate([e, e2])
+    out = {"workload": f"PEC sphere, {T.shape[0]} triangles, k = 0.1 (low frequency), {dirs.shape[0]} plane waves, "
+                       f"FP32 storage, GMRES({args.restart}) inner solves (tolerance 1e-3) with FP64 refinement "
+                       f"to {args.tol:g}"}
+    opts = bie.Solve(restart=args.restart, tol=args.tol, precision="mixed", inner_tol=1e-3, max_mvp=20000)
+    for star in (False, True):
+        op = bie.Operator(V, T, 0.1, storage="c64", keep_fp64=True, star=star)
+        B = op.rhs(dirs, pols)
+        op.solve(B[:1], opts)
+        sync()
+        t0 = time.perf_counter()
+        X, st = op.solve(B, opts)
+        sync()
+        t = time.perf_counter() - t0
+        out["star" if star else "assembled"] = {
+            "solves_per_s": round(B.shape[0] / t, 2), "iters_mean": float(np.mean([s["iters"] for s in st])),
+            "converged": float(np.mean([s["converged"] for s in st])),
+            "relres_true_fp64_max": float(max(s["relres_true"] for s in st))}
+        op.close()
+    out["speedup_star_vs_assembled"] = round(out["star"]["solves_per_s"] / out["assembled"]["solves_per_s"], 2)
+    # FP64 product times at the bench wavenumber
+    from paper_2606_13482_amd.inputs import complex_gaussian
+    prod = {}
+    for star in (False, True):
+        op = bie.Operator(V, T, args.k, star=star)
+        x = torch.from_numpy(complex_gaussian(op.N, 7)).cuda().reshape(1, -1)
+        y = op.apply(x)
+        sync()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(20):
+            op.apply(x, out=y)
+        ev1.record()
+        sync()
+        us = ev0.elapsed_time(ev1) / 20 * 1e3
+        N, F = op.N, T.shape[0]
+        nbytes = N * (N + 1) // 2 * 16 + (F * (F + 1) // 2 * 16 if star else 0)
+        prod["star" if star else "assembled"] = {"us_per_product": round(us, 1), "packed_bytes": nbytes,
+                                                  "GB_per_s": round(nbytes / us / 1e3, 1)}
+        op.close()
+    out["fp64_product"] = prod
+    return out
+
+
 def uneven_batch_leg(args, bie, torch):
     """64 closed surfaces (spheres, ellipsoids, rounded cubes; 648..5832 unknowns,
     10 edges per wavelength), 1..32 plane waves each, FP32 matrices: the batched
@@ -540,6 +595,8 @@ def main():
         "headline": head,
         "plain_fp64_step": plain,
     }
+    if args.star:
+        out["star_split"] = star_leg(args, bie, torch, V, T)
     if args.batch:
         out["uneven_batch"] = uneven_batch_leg(args, bie, torch)
     if not args.no_cpu:

@@ -68,6 +68,17 @@ typedef struct {
                              (or sharing a vertex) get singularity subtraction; default 2.0 */
     int keep_fp64;        /* with storage BIE_C64: also keep the FP64 matrix (for FP64
                              residuals / iterative refinement); default 0 */
+    int star;             /* 1: star-split form (Sec. VI-A, star factorisation): the
+                             operator stores T_A' = jk T_A (packed N x N) and
+                             V' = V / (jk) (packed F x F, V the piecewise-constant single
+                             layer with basis 1/A) and every product is
+                             T x = T_A' x + Sigma V' Sigma^T x, Sigma the sparse star matrix
+                             (+-1 for the triangles of each RWG).  The scalar part then
+                             vanishes exactly on solenoidal (loop) currents whatever the
+                             storage precision.  Not with BIE_SPLIT_BF16; solves with the
+                             standard criterion only (RSCC needs assembled rows); no
+                             warm start, batched solve or bie_op_matrix (BIE_EINVAL).
+                             Default 0 */
 } bie_fill_opts;
 
 /* Operator: mesh + wavenumber -> dense impedance matrix T on the current device.

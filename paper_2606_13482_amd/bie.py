@@ -35,7 +35,8 @@ class BieError(RuntimeError):
 
 
 class FillOpts(ctypes.Structure):
-    _fields_ = [("storage", ctypes.c_int), ("near_factor", ctypes.c_double), ("keep_fp64", ctypes.c_int)]
+    _fields_ = [("storage", ctypes.c_int), ("near_factor", ctypes.c_double), ("keep_fp64", ctypes.c_int),
+                ("star", ctypes.c_int)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -183,17 +184,20 @@ class Operator:
     """Dense EFIE operator T of a closed PEC surface at wavenumber k (Sec. II)."""
 
     def __init__(self, V, T, k: float, storage: str = "c128", near_factor: float = 2.0,
-                 keep_fp64: bool = False, stream=None):
+                 keep_fp64: bool = False, star: bool = False, stream=None):
+        """star: store the star-split form T_A' = jk T_A and V' = V/(jk) (Sec. VI-A);
+        products are T_A' x + Sigma V' Sigma^T x."""
         V, pv = _host(V, np.float64)
         T, pt = _host(T, np.int32)
         opts = FillOpts({"c128": BIE_C128, "c64": BIE_C64, "split_bf16": BIE_SPLIT_BF16}[storage], near_factor,
-                        int(keep_fp64))
+                        int(keep_fp64), int(star))
         h = ctypes.c_void_p()
         _check(_lib.bie_op_create(pv, V.shape[0], pt, T.shape[0], float(k), ctypes.byref(opts),
                                   _stream(stream), ctypes.byref(h)))
         self._h = h
         self.k = float(k)
         self.storage = storage
+        self.star = bool(star)
         self.N = int(_lib.bie_op_n(h))
 
     def close(self):

@@ -37,9 +37,11 @@ void destroy_op(bie_op *op)
 {
     if (!op) return;
     bie::free_workspace(op);
-    bie::packed_free(op);
-    void *ptrs[] = { op->Z64, op->Z32, op->Abf, op->Bbf, op->gemm_part, op->A64, op->d64_part, op->tri.cent, op->tri.loc, op->tri.vfree, op->tri.verts,
-                     op->tri.area, op->tri.sgn, op->tri.slot_m, op->tri.edges };
+    bie::packed_free(op->pk);
+    bie::packed_free(op->pkv);
+    void *ptrs[] = { op->Z64, op->Z32, op->V64, op->V32, op->star_buf, op->Abf, op->Bbf, op->gemm_part, op->A64,
+                     op->d64_part, op->tri.cent, op->tri.loc, op->tri.vfree, op->tri.verts, op->tri.area, op->tri.sgn,
+                     op->tri.slot_m, op->tri.edges };
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete op;
@@ -58,10 +60,12 @@ int bie_op_create(const double *verts, int64_t nv, const int32_t *tris, int64_t 
         *out = nullptr;
         if (!verts || !tris) return fail(BIE_EINVAL, "NULL mesh array");
         if (!(k > 0.0) || !std::isfinite(k)) return fail(BIE_EINVAL, "wavenumber must be positive and finite");
-        bie_fill_opts o{ BIE_C128, 2.0, 0 };
+        bie_fill_opts o{ BIE_C128, 2.0, 0, 0 };
         if (opts) o = *opts;
         if (o.storage != BIE_C128 && o.storage != BIE_C64 && o.storage != BIE_SPLIT_BF16)
             return fail(BIE_EINVAL, "unknown storage");
+        if (o.star != 0 && o.star != 1) return fail(BIE_EINVAL, "star must be 0 or 1");
+        if (o.star && o.storage == BIE_SPLIT_BF16) return fail(BIE_EINVAL, "the star-split form has no split-BF16 copy");
         if (!(o.near_factor >= 0.0)) return fail(BIE_EINVAL, "near_factor must be >= 0");
         bie::Mesh mesh = bie::build_mesh(verts, nv, tris, nt, o.near_factor);   // host only: EMESH first
         bie_op *op = new bie_op();
@@ -70,16 +74,19 @@ int bie_op_create(const double *verts, int64_t nv, const int32_t *tris, int64_t 
             BIE_HIP(hipGetDevice(&op->device));
             op->k = k;
             op->storage = o.storage;
-            const int64_t N = op->mesh.N;
+            op->star = o.star;
             hipStream_t s = as_stream(stream);
             bie::upload_triangles(op, s);
-            bie::packed_setup(op);
-            (void)N;
+            bie::packed_setup(op->pk, op->mesh.N);
+            if (op->star) bie::packed_setup(op->pkv, op->mesh.F);
             const size_t tile_elems = size_t(op->pk.ntiles) * bie::TB * bie::TB;
+            const size_t vtile_elems = op->star ? size_t(op->pkv.ntiles) * bie::TB * bie::TB : 0;
             const bool want64 = o.storage == BIE_C128 || o.storage == BIE_SPLIT_BF16 || o.keep_fp64;
             const bool want32 = o.storage == BIE_C64;
             if (want64) BIE_HIP(hipMalloc(&op->Z64, tile_elems * 16));
             if (want32) BIE_HIP(hipMalloc(&op->Z32, tile_elems * 8));
+            if (want64 && op->star) BIE_HIP(hipMalloc(&op->V64, vtile_elems * 16));
+            if (want32 && op->star) BIE_HIP(hipMalloc(&op->V32, vtile_elems * 8));
             if (o.storage == BIE_C128) {
                 bie::fill_matrix(op, true, true, false, s);
             } else if (o.storage == BIE_SPLIT_BF16) {
@@ -89,6 +96,7 @@ int bie_op_create(const double *verts, int64_t nv, const int32_t *tris, int64_t 
                 // FP64 fill; the FP32 matrix is its rounding (the best FP32 representation)
                 bie::fill_matrix(op, true, true, false, s);
                 bie::convert_c128_to_c64(op->Z64, op->Z32, int64_t(tile_elems), s);
+                if (op->star) bie::convert_c128_to_c64(op->V64, op->V32, int64_t(vtile_elems), s);
                 BIE_HIP(hipStreamSynchronize(s));
             } else {
                 bie::fill_matrix(op, false, false, true, s);          // FP32 regular, FP64 singular
@@ -125,6 +133,7 @@ int bie_op_matrix(const bie_op *op, void *dst, int dtype, void *stream)
 {
     return guarded([&]() -> int {
         if (!op || !dst) return fail(BIE_EINVAL, "NULL argument");
+        if (op->star) return fail(BIE_EINVAL, "a star-split operator holds no assembled matrix");
         hipStream_t s = as_stream(stream);
         if (dtype == BIE_C128) {
             bie::unpack_c128(op, op->Z64 != nullptr, dst, s);
@@ -180,6 +189,7 @@ int bie_apply(const bie_op *op, const void *X, void *Y, int64_t R, int vec, int 
             bie::product(op, bie::MATBF16, true, X, N, Y, N, nullptr, 0, R, nullptr, 1, false, s);
         } else if (vec == BIE_APPLY_F64_BLOCK) {
             if (!op->Z64) return fail(BIE_EINVAL, "the FP64 block product needs the FP64 matrix");
+            if (op->star) return fail(BIE_EINVAL, "no FP64 block product for a star-split operator");
             if (conj) return fail(BIE_EINVAL, "the block product has no conjugate form");
             bie::gemm64_product(op, X, N, Y, N, nullptr, 0, R, nullptr, s);
         } else {
@@ -211,6 +221,8 @@ int bie_solve(const bie_op *op, const void *B, void *X, int64_t R, const bie_sol
         if (o.inner_terms != 0 && o.inner_terms != 2 && o.inner_terms != 3)
             return fail(BIE_EINVAL, "inner_terms must be 0, 2 or 3");
         if (o.basis != 0 && o.basis != 1) return fail(BIE_EINVAL, "basis must be 0 or 1");
+        if (op->star && o.crit == BIE_RSCC)
+            return fail(BIE_EINVAL, "the random-sampling criterion needs assembled rows (not a star-split operator)");
         if (o.basis == 1 && (o.precision != 1 || !op->Abf))
             return fail(BIE_EINVAL, "the FP16 basis is for mixed precision with split-BF16 storage");
         const int64_t N = op->mesh.N;
@@ -241,6 +253,7 @@ int bie_batch_solve(const bie_op *const *ops, int64_t nops, const void *const *B
         int64_t total = 0;
         for (int64_t p = 0; p < nops; ++p) {
             if (!ops[p]) return fail(BIE_EINVAL, "NULL operator");
+            if (ops[p]->star) return fail(BIE_EINVAL, "batched solves take assembled operators");
             if (R[p] < 0 || R[p] > 4096) return fail(BIE_EINVAL, "R out of range (0..4096)");
             if (R[p] > 0 && (!B[p] || !X[p])) return fail(BIE_EINVAL, "NULL vector pointer");
             total += R[p];
@@ -290,6 +303,7 @@ int bie_ws_train(const bie_op *op, const double *feats, const double *pols, cons
 {
     return guarded([&]() -> int {
         if (!op || !feats || !X || !out) return fail(BIE_EINVAL, "NULL argument");
+        if (op->star) return fail(BIE_EINVAL, "the warm start takes an assembled operator");
         *out = nullptr;
         bie_ws_opts o{ 256, 512, 3000, 256, 1e-3, 1e-5, 555, 32, 2, 0 };
         if (opts) o = *opts;
@@ -365,6 +379,7 @@ int bie_ws_create(const bie_op *op, int pod_rank, int hidden, uint64_t seed, int
 {
     return guarded([&]() -> int {
         if (!op || !out) return fail(BIE_EINVAL, "NULL argument");
+        if (op->star) return fail(BIE_EINVAL, "the warm start takes an assembled operator");
         if (pod_rank < 1 || hidden < 1 || hidden > 4096) return fail(BIE_EINVAL, "bad sizes");
         if (pol_model != 0 && pol_model != 1) return fail(BIE_EINVAL, "pol_model must be 0 or 1");
         *out = bie::ws_create_untrained(op, pod_rank, hidden, seed, pol_model);
@@ -385,6 +400,7 @@ int bie_ws_load(const bie_op *op, const char *path, bie_ws **out)
 {
     return guarded([&]() -> int {
         if (!op || !path || !out) return fail(BIE_EINVAL, "NULL argument");
+        if (op->star) return fail(BIE_EINVAL, "the warm start takes an assembled operator");
         *out = bie::ws_load(op, path);
         return BIE_OK;
     });

@@ -122,9 +122,14 @@ struct bie_op {
     int storage = BIE_C128;
     bie::Mesh mesh;
     bie::TriDev tri;
-    void *Z64 = nullptr;   // packed symmetric tiles, complex128 (storage C128 or keep_fp64)
-    void *Z32 = nullptr;   // packed symmetric tiles, complex64 (storage C64)
+    void *Z64 = nullptr;   // packed symmetric tiles, complex128 (storage C128 or keep_fp64); star: T_A' = jk T_A
+    void *Z32 = nullptr;   // packed symmetric tiles, complex64 (storage C64); star: T_A'
     bie::Packed pk;
+    int star = 0;          // star-split operator: T = T_A' + Sigma V' Sigma^T
+    void *V64 = nullptr, *V32 = nullptr;   // star: V' = V / (jk), packed F x F tiles (complex128 / complex64)
+    bie::Packed pkv;       // tables of the F x F tiles
+    void *star_buf = nullptr;   // star product scratch: u and w, star_R x F each (complex128 sized)
+    int64_t star_R = 0;
     void *Abf = nullptr;          // split-BF16 matrix for the block product: hi plane, lo plane, [Mp][Kp]
     int64_t gemm_Mp = 0, gemm_Kp = 0;
     void *Bbf = nullptr;          // split-BF16 staging of the right-hand block, [NCp][Kp] x 2
@@ -149,7 +154,7 @@ void farfield(const bie_op *op, const void *X, int64_t R, const double *obs, int
               hipStream_t s);
 
 // blas.hip: products with the packed symmetric matrix.
-void packed_setup(bie_op *op);
+void packed_setup(Packed &pk, int64_t n);   // tables of the packed n x n tiles
 // work units of U tiles along each tile row, and the partial-vector slots
 void build_units(int64_t nT, int U, std::vector<int32_t> &units, std::vector<int32_t> &uptr,
                  std::vector<int64_t> &seg);
@@ -160,7 +165,7 @@ void build_units(int64_t nT, int U, std::vector<int32_t> &units, std::vector<int
 void grouped_product(bool mat64, const GProb *probs, const GCols &gc, const int32_t *items, int64_t nitems, int G,
                      const int32_t *ritems, int64_t nritems, const void *X, void *part, void *Y, const void *B,
                      const int *skip, int64_t sks, hipStream_t s);        // unit table (host -> device)
-void packed_free(bie_op *op);
+void packed_free(Packed &pk);
 // Y = T X, T^H X (conj) or B - T X (B != NULL) for R vectors with the FP64
 // (mat64) or FP32 matrix; vectors complex128 (vec64, FP64 accumulation) or
 // complex64 (FP32 matrix only).

@@ -469,11 +469,54 @@ int sym_prefetch()
     return v;
 }
 
+// Star-split product (Sec. VI-A): T x = T_A' x + Sigma V' Sigma^T x.
+// u = Sigma^T x: u_p = sum over the three edges m of triangle p of s x_m.
+template <typename T>
+__global__ __launch_bounds__(256) void k_star_gather(int64_t F, const int32_t *__restrict__ slot_m,
+                                                     const int8_t *__restrict__ sgn, const T *__restrict__ X,
+                                                     int64_t ldx, T *__restrict__ U, const int *__restrict__ skip,
+                                                     int64_t sks)
+{
+    using V2 = typename Cx<T>::type;
+    const int64_t v = blockIdx.y;
+    if (skip && skip[v * sks]) return;
+    const V2 *x = reinterpret_cast<const V2 *>(X) + v * ldx;
+    V2 *u = reinterpret_cast<V2 *>(U) + v * F;
+    for (int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x; p < F; p += int64_t(gridDim.x) * 256) {
+        V2 a = { 0, 0 };
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+            const V2 xm = x[slot_m[3 * p + e]];
+            if (sgn[3 * p + e] > 0) a += xm;
+            else a -= xm;
+        }
+        u[p] = a;
+    }
+}
+
+// y_m += w_{c+(m)} - w_{c-(m)} (SUB: -=), w = V' u
+template <typename T, bool SUB>
+__global__ __launch_bounds__(256) void k_star_scatter(int64_t N, int64_t F, const int4 *__restrict__ rwg4,
+                                                      const T *__restrict__ W, T *__restrict__ Y, int64_t ldy,
+                                                      const int *__restrict__ skip, int64_t sks)
+{
+    using V2 = typename Cx<T>::type;
+    const int64_t v = blockIdx.y;
+    if (skip && skip[v * sks]) return;
+    const V2 *w = reinterpret_cast<const V2 *>(W) + v * F;
+    V2 *y = reinterpret_cast<V2 *>(Y) + v * ldy;
+    for (int64_t m = int64_t(blockIdx.x) * 256 + threadIdx.x; m < N; m += int64_t(gridDim.x) * 256) {
+        const int4 e = rwg4[m];
+        const V2 d = w[e.x] - w[e.y];
+        if (SUB) y[m] -= d;
+        else y[m] += d;
+    }
+}
+
 template <typename M, typename T, bool CONJ, bool SUB>
-void launch_product(const bie_op *op, const void *Z, const void *X, int64_t ldx, void *Y, int64_t ldy, const void *B,
+void launch_product(const Packed &pk, const void *Z, const void *X, int64_t ldx, void *Y, int64_t ldy, const void *B,
                     int64_t ldb, int64_t R, const int *skip, int64_t sks, hipStream_t s)
 {
-    const Packed &pk = op->pk;
     const dim3 grid(unsigned(pk.nruns), unsigned(R));
     prof::begin(0, s, R);
     // non-temporal tile loads for the FP64 matrix, cached loads for the FP32
@@ -557,10 +600,9 @@ void build_runs(int64_t nT, int64_t nb, std::vector<int32_t> &units, std::vector
     unit_rows(nT, units, uptr, seg);
 }
 
-void packed_setup(bie_op *op)
+void packed_setup(Packed &pk, int64_t n)
 {
-    Packed &pk = op->pk;
-    pk.N = op->mesh.N;
+    pk.N = n;
     pk.nT = (pk.N + TB - 1) / TB;
     pk.ntiles = pk.nT * (pk.nT + 1) / 2;
     std::vector<int32_t> units, uptr, rptr;
@@ -588,9 +630,8 @@ void packed_setup(bie_op *op)
     pk.h_seg = std::move(seg);
 }
 
-void packed_free(bie_op *op)
+void packed_free(Packed &pk)
 {
-    Packed &pk = op->pk;
     if (pk.units) (void)hipFree(pk.units);
     if (pk.unit_ptr) (void)hipFree(pk.unit_ptr);
     if (pk.run_ptr) (void)hipFree(pk.run_ptr);
@@ -604,12 +645,53 @@ void packed_free(bie_op *op)
 }
 
 template <typename M, typename T>
-void dispatch(const bie_op *op, const void *Z, const void *X, int64_t ldx, void *Y, int64_t ldy, const void *B,
+void dispatch(const Packed &pk, const void *Z, const void *X, int64_t ldx, void *Y, int64_t ldy, const void *B,
               int64_t ldb, int64_t R, const int *skip, int64_t sks, bool conj, hipStream_t s)
 {
-    if (B) launch_product<M, T, false, true>(op, Z, X, ldx, Y, ldy, B, ldb, R, skip, sks, s);
-    else if (conj) launch_product<M, T, true, false>(op, Z, X, ldx, Y, ldy, nullptr, 0, R, skip, sks, s);
-    else launch_product<M, T, false, false>(op, Z, X, ldx, Y, ldy, nullptr, 0, R, skip, sks, s);
+    if (B) launch_product<M, T, false, true>(pk, Z, X, ldx, Y, ldy, B, ldb, R, skip, sks, s);
+    else if (conj) launch_product<M, T, true, false>(pk, Z, X, ldx, Y, ldy, nullptr, 0, R, skip, sks, s);
+    else launch_product<M, T, false, false>(pk, Z, X, ldx, Y, ldy, nullptr, 0, R, skip, sks, s);
+}
+
+// partial-sum buffer of a packed product for R vectors (sized for complex128)
+static void ensure_part(Packed &pk, int64_t R, hipStream_t s)
+{
+    if (pk.part_R >= R) return;
+    BIE_HIP(hipStreamSynchronize(s));
+    if (pk.part) (void)hipFree(pk.part);
+    pk.part = nullptr;
+    pk.part_R = 0;
+    BIE_HIP(hipMalloc(&pk.part, size_t(R) * size_t(pk.nslots) * TB * 16));
+    pk.part_R = R;
+}
+
+// T x (conj: conj(T) x; B: B - T x) for the star-split operator: u = Sigma^T x,
+// w = V' u, y = T_A' x (or B - T_A' x), y += Sigma w (or -=).
+template <typename M, typename T>
+static void star_product(bie_op *op, const void *Za, const void *Vm, const void *X, int64_t ldx, void *Y,
+                         int64_t ldy, const void *B, int64_t ldb, int64_t R, const int *skip, int64_t sks, bool conj,
+                         hipStream_t s)
+{
+    const int64_t N = op->mesh.N, F = op->mesh.F;
+    if (op->star_R < R) {
+        BIE_HIP(hipStreamSynchronize(s));
+        if (op->star_buf) (void)hipFree(op->star_buf);
+        op->star_buf = nullptr;
+        op->star_R = 0;
+        BIE_HIP(hipMalloc(&op->star_buf, 2 * size_t(R) * size_t(F) * 16));
+        op->star_R = R;
+    }
+    T *U = static_cast<T *>(op->star_buf), *W = U + 2 * R * F;
+    const unsigned gx = unsigned(std::min<int64_t>((std::max(N, F) + 255) / 256, 1024));
+    hipLaunchKernelGGL(k_star_gather<T>, dim3(gx, unsigned(R)), dim3(256), 0, s, F, op->tri.slot_m, op->tri.sgn,
+                       (const T *)X, ldx, U, skip, sks);
+    dispatch<M, T>(op->pkv, Vm, U, F, W, F, nullptr, 0, R, skip, sks, conj, s);
+    dispatch<M, T>(op->pk, Za, X, ldx, Y, ldy, B, ldb, R, skip, sks, conj, s);
+    if (B) hipLaunchKernelGGL((k_star_scatter<T, true>), dim3(gx, unsigned(R)), dim3(256), 0, s, N, F,
+                              (const int4 *)op->tri.edges, W, (T *)Y, ldy, skip, sks);
+    else hipLaunchKernelGGL((k_star_scatter<T, false>), dim3(gx, unsigned(R)), dim3(256), 0, s, N, F,
+                            (const int4 *)op->tri.edges, W, (T *)Y, ldy, skip, sks);
+    BIE_HIP(hipGetLastError());
 }
 
 void product(const bie_op *opc, int mat, bool vec64, const void *X, int64_t ldx, void *Y, int64_t ldy,
@@ -623,21 +705,21 @@ void product(const bie_op *opc, int mat, bool vec64, const void *X, int64_t ldx,
         return;
     }
     const bool mat64 = mat == MAT64;
-    Packed &pk = op->pk;
     const void *Z = mat64 ? op->Z64 : op->Z32;
     if (!Z) throw Error(BIE_EINVAL, "matrix not stored in the requested precision");
     if (mat64 && !vec64) throw Error(BIE_EINVAL, "complex64 vectors need the FP32 matrix");
-    if (pk.part_R < R) {   // partial sums, sized for complex128
-        BIE_HIP(hipStreamSynchronize(s));
-        if (pk.part) (void)hipFree(pk.part);
-        pk.part = nullptr;
-        pk.part_R = 0;
-        BIE_HIP(hipMalloc(&pk.part, size_t(R) * size_t(pk.nslots) * TB * 16));
-        pk.part_R = R;
+    ensure_part(op->pk, R, s);
+    if (op->star) {
+        const void *Vm = mat64 ? op->V64 : op->V32;
+        ensure_part(op->pkv, R, s);
+        if (mat64) star_product<double, double>(op, Z, Vm, X, ldx, Y, ldy, B, ldb, R, skip, sks, conj, s);
+        else if (vec64) star_product<float, double>(op, Z, Vm, X, ldx, Y, ldy, B, ldb, R, skip, sks, conj, s);
+        else star_product<float, float>(op, Z, Vm, X, ldx, Y, ldy, B, ldb, R, skip, sks, conj, s);
+        return;
     }
-    if (mat64) dispatch<double, double>(op, Z, X, ldx, Y, ldy, B, ldb, R, skip, sks, conj, s);
-    else if (vec64) dispatch<float, double>(op, Z, X, ldx, Y, ldy, B, ldb, R, skip, sks, conj, s);
-    else dispatch<float, float>(op, Z, X, ldx, Y, ldy, B, ldb, R, skip, sks, conj, s);
+    if (mat64) dispatch<double, double>(op->pk, Z, X, ldx, Y, ldy, B, ldb, R, skip, sks, conj, s);
+    else if (vec64) dispatch<float, double>(op->pk, Z, X, ldx, Y, ldy, B, ldb, R, skip, sks, conj, s);
+    else dispatch<float, float>(op->pk, Z, X, ldx, Y, ldy, B, ldb, R, skip, sks, conj, s);
 }
 
 void grouped_product(bool mat64, const GProb *probs, const GCols &gc, const int32_t *items, int64_t nitems, int G,

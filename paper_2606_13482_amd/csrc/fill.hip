@@ -9,6 +9,14 @@
 // with area-relative weights (the areas cancel against 1/(A_p A_q)).  The
 // minus signs of eq:efie and eq:matTPhi cancel.
 //
+// Star-split form (Sec. VI-A, star factorisation of the scalar potential):
+// with div f_m = +-1/A on c_m^+- the scalar term of T is Sigma V Sigma^T,
+// Sigma_mp = s (the sign of triangle p in RWG m) and V_pq = J0 / (jk) the
+// piecewise-constant single layer (basis 1/A) scaled by 1/(jk).  In that form
+// the local blocks keep only the vector part s_a s_b (jk/4) J_ab (assembled
+// into T_A' = jk T_A exactly as T), and J0 / (jk) of every pair p <= q is
+// written to its own tile array and assembled into packed F x F tiles of V'.
+//
 // Pipeline (three launches, no atomics, bitwise symmetric result):
 //   1. k_pairs_regular: one thread per ordered triangle pair p <= q of a 16x16
 //      triangle tile staged in LDS; 49 kernel evaluations; writes the 3x3
@@ -92,13 +100,13 @@ __device__ inline double rsqrt_t<double>(double x) { return 1.0 / sqrt(x); }
 template <>
 __device__ inline float rsqrt_t<float>(float x) { return rsqrtf(x); }
 
-template <typename R>
+template <typename R, bool SPLIT>
 __global__ __launch_bounds__(256) void k_pairs_regular(int64_t F, int64_t nT, int64_t ntiles,
                                                        const double *__restrict__ cent,
                                                        const double *__restrict__ loc,
                                                        const double *__restrict__ vfree,
                                                        const int8_t *__restrict__ sgn, double k,
-                                                       R *__restrict__ LB)
+                                                       R *__restrict__ LB, R *__restrict__ VS)
 {
     __shared__ TriLDS<R> sp[TT], sq[TT];
     __shared__ double scp[TT][3], scq[TT][3];
@@ -208,11 +216,15 @@ __global__ __launch_bounds__(256) void k_pairs_regular(int64_t F, int64_t nT, in
             jr += vv * s0r;
             ji += vv * s0i;
             const R ss = R(sgn[p * 3 + aa] * sgn[q * 3 + bb]);
-            const R lr = ss * (-k4 * ji + ik * s0i);
-            const R li = ss * (k4 * jr - ik * s0r);
+            const R lr = SPLIT ? ss * (-k4 * ji) : ss * (-k4 * ji + ik * s0i);
+            const R li = SPLIT ? ss * (k4 * jr) : ss * (k4 * jr - ik * s0r);
             out[((aa * 3 + bb) * 256 + tid) * 2 + 0] = lr;
             out[((aa * 3 + bb) * 256 + tid) * 2 + 1] = li;
         }
+    }
+    if (SPLIT) {   // V'_pq = J0 / (jk)
+        VS[(tile * 256 + tid) * 2 + 0] = ik * s0i;
+        VS[(tile * 256 + tid) * 2 + 1] = -ik * s0r;
     }
 }
 
@@ -264,7 +276,7 @@ __device__ void static_potentials(const double x[3], const double A[3], const do
     for (int d = 0; d < 3; ++d) K1[d] = kp[d] - h * n[d] * k0;
 }
 
-template <typename R>
+template <typename R, bool SPLIT>
 __global__ __launch_bounds__(128) void k_pairs_singular(int64_t npairs, int64_t nT,
                                                         const int32_t *__restrict__ pairs,
                                                         const double *__restrict__ cent,
@@ -273,7 +285,7 @@ __global__ __launch_bounds__(128) void k_pairs_singular(int64_t npairs, int64_t 
                                                         const double *__restrict__ verts,
                                                         const double *__restrict__ area,
                                                         const int8_t *__restrict__ sgn, double k,
-                                                        R *__restrict__ LB)
+                                                        R *__restrict__ LB, R *__restrict__ VS)
 {
     const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (idx >= npairs) return;
@@ -379,9 +391,14 @@ __global__ __launch_bounds__(128) void k_pairs_singular(int64_t npairs, int64_t 
         for (int b = 0; b < 3; ++b) {
             const double Jr = Jr_[a][b], Ji = Ji_[a][b];
             const double ss = double(sgn[p * 3 + a] * sgn[q * 3 + b]);
-            out[((a * 3 + b) * 256 + tid) * 2 + 0] = R(ss * (-k4 * Ji + ik * j0i));
-            out[((a * 3 + b) * 256 + tid) * 2 + 1] = R(ss * (k4 * Jr - ik * j0r));
+            out[((a * 3 + b) * 256 + tid) * 2 + 0] = R(SPLIT ? ss * (-k4 * Ji) : ss * (-k4 * Ji + ik * j0i));
+            out[((a * 3 + b) * 256 + tid) * 2 + 1] = R(SPLIT ? ss * (k4 * Jr) : ss * (k4 * Jr - ik * j0r));
         }
+    if (SPLIT) {
+        const int64_t t = tile_index(I, J, nT);
+        VS[(t * 256 + tid) * 2 + 0] = R(ik * j0i);
+        VS[(t * 256 + tid) * 2 + 1] = R(-ik * j0r);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -427,6 +444,31 @@ __global__ __launch_bounds__(256) void k_assemble(int64_t N, int64_t nT, int64_t
         }
         if (Z64) Z64[base + e] = make_double2(double(zr), double(zi));
         if (Z32) Z32[base + e] = make_float2(float(zr), float(zi));
+    }
+}
+
+// V' into packed F x F tiles (TB x TB, I <= J) from the per-pair values of the
+// triangle tiles (p <= q; the other half by symmetry).
+template <typename R>
+__global__ __launch_bounds__(256) void k_assemble_v(int64_t F, int64_t nT, int64_t nTv, const R *__restrict__ VS,
+                                                    double2 *__restrict__ V64, float2 *__restrict__ V32)
+{
+    int64_t I, J;
+    tile_decode(blockIdx.x, nTv, I, J);
+    const int64_t base = int64_t(blockIdx.x) * TB * TB;
+#pragma unroll 4
+    for (int q = 0; q < TB * TB / 256; ++q) {
+        const int e = threadIdx.x + 256 * q;
+        int64_t a = I * TB + e / TB, b = J * TB + e % TB;
+        R vr = 0, vi = 0;
+        if (a < F && b < F) {
+            if (a > b) { const int64_t t = a; a = b; b = t; }
+            const R *src = VS + (tile_index(a / TT, b / TT, nT) * 256 + (a % TT) * TT + (b % TT)) * 2;
+            vr = src[0];
+            vi = src[1];
+        }
+        if (V64) V64[base + e] = make_double2(double(vr), double(vi));
+        if (V32) V32[base + e] = make_float2(float(vr), float(vi));
     }
 }
 
@@ -581,52 +623,61 @@ void upload_triangles(bie_op *op, hipStream_t s)
     (void)s;
 }
 
+template <typename R, bool SPLIT>
+static void fill_launch(bie_op *op, int64_t nT, int64_t ntiles, const int32_t *pairs, int64_t npairs, void *LB,
+                        void *VS, bool want64, bool want32, hipStream_t s)
+{
+    const Mesh &M = op->mesh;
+    const TriDev &D = op->tri;
+    hipLaunchKernelGGL((k_pairs_regular<R, SPLIT>), dim3(unsigned(ntiles)), dim3(256), 0, s, M.F, nT, ntiles, D.cent,
+                       D.loc, D.vfree, D.sgn, op->k, (R *)LB, (R *)VS);
+    if (npairs)
+        hipLaunchKernelGGL((k_pairs_singular<R, SPLIT>), dim3(unsigned((npairs + 127) / 128)), dim3(128), 0, s, npairs,
+                           nT, pairs, D.cent, D.loc, D.vfree, D.verts, D.area, D.sgn, op->k, (R *)LB, (R *)VS);
+    hipLaunchKernelGGL(k_assemble<R>, dim3(unsigned(op->pk.ntiles)), dim3(256), 0, s, M.N, nT, op->pk.nT,
+                       (const int4 *)D.edges, (const R *)LB, want64 ? (double2 *)op->Z64 : nullptr,
+                       want32 ? (float2 *)op->Z32 : nullptr);
+    if (SPLIT)
+        hipLaunchKernelGGL(k_assemble_v<R>, dim3(unsigned(op->pkv.ntiles)), dim3(256), 0, s, M.F, nT, op->pkv.nT,
+                           (const R *)VS, want64 ? (double2 *)op->V64 : nullptr, want32 ? (float2 *)op->V32 : nullptr);
+}
+
+// The matrix (or, for a star-split operator, T_A' and V') into the packed
+// arrays the operator holds.
 void fill_matrix(bie_op *op, bool fp64_regular, bool want64, bool want32, hipStream_t s)
 {
     const Mesh &M = op->mesh;
-    const int64_t F = M.F, N = M.N;
+    const int64_t F = M.F;
     const int64_t nT = (F + TT - 1) / TT;
     const int64_t ntiles = nT * (nT + 1) / 2;
     const size_t elem = fp64_regular ? sizeof(double) : sizeof(float);
-    void *LB = nullptr;
-    BIE_HIP(hipMalloc(&LB, size_t(ntiles) * 9 * 256 * 2 * elem));
+    void *LB = nullptr, *VS = nullptr;
     int32_t *pairs = nullptr;
     const int64_t npairs = int64_t(M.near.size() / 2);
     try {
+        BIE_HIP(hipMalloc(&LB, size_t(ntiles) * 9 * 256 * 2 * elem));
+        if (op->star) BIE_HIP(hipMalloc(&VS, size_t(ntiles) * 256 * 2 * elem));
         if (npairs) {
             BIE_HIP(hipMalloc(&pairs, M.near.size() * sizeof(int32_t)));
             BIE_HIP(hipMemcpyAsync(pairs, M.near.data(), M.near.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
         }
-        const TriDev &D = op->tri;
         if (fp64_regular) {
-            hipLaunchKernelGGL(k_pairs_regular<double>, dim3(unsigned(ntiles)), dim3(256), 0, s, F, nT, ntiles,
-                               D.cent, D.loc, D.vfree, D.sgn, op->k, (double *)LB);
-            if (npairs)
-                hipLaunchKernelGGL(k_pairs_singular<double>, dim3(unsigned((npairs + 127) / 128)), dim3(128), 0, s,
-                                   npairs, nT, pairs, D.cent, D.loc, D.vfree, D.verts, D.area, D.sgn, op->k,
-                                   (double *)LB);
-            hipLaunchKernelGGL(k_assemble<double>, dim3(unsigned(op->pk.ntiles)), dim3(256), 0, s, N, nT, op->pk.nT,
-                               (const int4 *)D.edges, (const double *)LB,
-                               want64 ? (double2 *)op->Z64 : nullptr, want32 ? (float2 *)op->Z32 : nullptr);
+            if (op->star) fill_launch<double, true>(op, nT, ntiles, pairs, npairs, LB, VS, want64, want32, s);
+            else fill_launch<double, false>(op, nT, ntiles, pairs, npairs, LB, VS, want64, want32, s);
         } else {
-            hipLaunchKernelGGL(k_pairs_regular<float>, dim3(unsigned(ntiles)), dim3(256), 0, s, F, nT, ntiles,
-                               D.cent, D.loc, D.vfree, D.sgn, op->k, (float *)LB);
-            if (npairs)
-                hipLaunchKernelGGL(k_pairs_singular<float>, dim3(unsigned((npairs + 127) / 128)), dim3(128), 0, s,
-                                   npairs, nT, pairs, D.cent, D.loc, D.vfree, D.verts, D.area, D.sgn, op->k,
-                                   (float *)LB);
-            hipLaunchKernelGGL(k_assemble<float>, dim3(unsigned(op->pk.ntiles)), dim3(256), 0, s, N, nT, op->pk.nT,
-                               (const int4 *)D.edges, (const float *)LB,
-                               want64 ? (double2 *)op->Z64 : nullptr, want32 ? (float2 *)op->Z32 : nullptr);
+            if (op->star) fill_launch<float, true>(op, nT, ntiles, pairs, npairs, LB, VS, want64, want32, s);
+            else fill_launch<float, false>(op, nT, ntiles, pairs, npairs, LB, VS, want64, want32, s);
         }
         BIE_HIP(hipGetLastError());
         BIE_HIP(hipStreamSynchronize(s));
     } catch (...) {
-        hipFree(LB);
+        if (LB) hipFree(LB);
+        if (VS) hipFree(VS);
         if (pairs) hipFree(pairs);
         throw;
     }
     hipFree(LB);
+    if (VS) hipFree(VS);
     if (pairs) hipFree(pairs);
 }
 

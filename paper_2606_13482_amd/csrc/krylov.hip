@@ -1522,9 +1522,15 @@ static int solve_stream(const bie_op *opc, const void *Bv, void *Xv, int64_t R, 
                 if (changed) continue;
                 break;
             }
-            // r = b - T64 x for the slots to check, one FP64 block product on the matrix cores
-            BIE_HIP(hipMemcpyAsync(dcols + 2 * W, chk.data(), chk.size() * sizeof(int), hipMemcpyHostToDevice, s));
-            gemm64_product(op, Xs, N, Rs, N, Bs, N, int64_t(chk.size()), dcols + 2 * W, s);
+            // r = b - T64 x for the slots to check: one FP64 block product on the
+            // matrix cores, or the packed FP64 product of a star-split operator
+            if (op->star) {
+                BIE_HIP(hipMemcpyAsync(dskip, skip.data(), W * sizeof(int), hipMemcpyHostToDevice, s));
+                product(op, MAT64, true, Xs, N, Rs, N, Bs, N, W, dskip, 1, false, s);
+            } else {
+                BIE_HIP(hipMemcpyAsync(dcols + 2 * W, chk.data(), chk.size() * sizeof(int), hipMemcpyHostToDevice, s));
+                gemm64_product(op, Xs, N, Rs, N, Bs, N, int64_t(chk.size()), dcols + 2 * W, s);
+            }
             colnorms(Rs, W, rn);
             for (int64_t sl = 0; sl < W; ++sl) {
                 if (skip[sl]) continue;
