@@ -136,14 +136,14 @@ int bie_apply(const bie_op *op, const void *X, void *Y, int64_t R, int vec, int 
               void *stream);
 
 typedef enum { BIE_GMRES = 0, BIE_CGNR = 1 } bie_method;
-typedef enum { BIE_SCC = 0, BIE_RSCC = 1 } bie_crit;
+typedef enum { BIE_SCC = 0, BIE_RSCC = 1, BIE_CCC = 2 } bie_crit;
 
 typedef struct {
     int method;          /* bie_method; default BIE_GMRES */
     int restart;         /* GMRES restart length m (1..64); default 30 */
     double tol;          /* relative to ||b||_2; default 1e-6 */
     int64_t max_mvp;     /* cap on products per right-hand side; default 10000 */
-    int crit;            /* bie_crit; default BIE_SCC */
+    int crit;            /* bie_crit; default BIE_SCC (precision 1: BIE_SCC only) */
     int64_t rscc_rows;   /* S, default 512 (min(S, N) used) */
     uint64_t rscc_seed;  /* default 1234 */
     int use_x0;          /* 1: X holds the initial guess on entry; 2: the same with
@@ -185,7 +185,11 @@ typedef struct {
  *   SCC:  ||b - T x||_2 / ||b||_2 <= tol;
  *   RSCC: sqrt((N/S) sum_{i in S} |b_i - (T x)_i|^2) / ||b||_2 <= tol over S
  *         rows drawn by Floyd's algorithm from SplitMix64 seeded with
- *         rscc_seed + (number of earlier checks of that right-hand side).
+ *         rscc_seed + (number of earlier checks of that right-hand side);
+ *   CCC:  combined: the RSCC value gates each check, and a right-hand side whose
+ *         RSCC value is <= tol is accepted only if the SCC holds as well (its
+ *         full residual then also restarts the method when it does not).
+ *   RSCC and CCC need the FP64 matrix (assembled operator) and precision 0.
  * GMRES(m): Arnoldi with classical Gram-Schmidt and selective
  * reorthogonalisation (a second pass when the first removes more than half of
  * ||w||^2), FP64 Givens rotations; a cycle ends when the estimate <= tol or j = m, then the

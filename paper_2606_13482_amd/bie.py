@@ -22,7 +22,7 @@ BIE_EINVAL, BIE_EMESH, BIE_ENOMEM, BIE_EDEVICE, BIE_ENUMERIC = -1, -2, -3, -4, -
 BIE_C128, BIE_C64, BIE_SPLIT_BF16 = 0, 1, 2
 BIE_APPLY_F64_BLOCK = 3
 BIE_GMRES, BIE_CGNR = 0, 1
-BIE_SCC, BIE_RSCC = 0, 1
+BIE_SCC, BIE_RSCC, BIE_CCC = 0, 1, 2
 
 _ERRNAMES = {BIE_EINVAL: "EINVAL", BIE_EMESH: "EMESH", BIE_ENOMEM: "ENOMEM",
              BIE_EDEVICE: "EDEVICE", BIE_ENUMERIC: "ENUMERIC"}
@@ -164,7 +164,7 @@ class Solve:
     restart: int = 30
     tol: float = 1e-6
     max_mvp: int = 10000
-    crit: str = "scc"
+    crit: str = "scc"             # "scc", "rscc" or "ccc" (RSCC gates, SCC confirms)
     rscc_rows: int = 512
     rscc_seed: int = 1234
     precision: str = "plain"      # "plain" or "mixed" (FP32 inner GMRES + FP64 refinement)
@@ -175,7 +175,7 @@ class Solve:
 
     def c(self, use_x0: int) -> SolveOpts:
         return SolveOpts({"gmres": BIE_GMRES, "cgnr": BIE_CGNR}[self.method], self.restart, self.tol,
-                         self.max_mvp, {"scc": BIE_SCC, "rscc": BIE_RSCC}[self.crit], self.rscc_rows,
+                         self.max_mvp, {"scc": BIE_SCC, "rscc": BIE_RSCC, "ccc": BIE_CCC}[self.crit], self.rscc_rows,
                          self.rscc_seed, int(use_x0), {"plain": 0, "mixed": 1}[self.precision],
                          self.inner_tol, self.slots, self.inner_terms, {"c64": 0, "f16": 1}[self.basis])
 

@@ -209,7 +209,9 @@ int bie_solve(const bie_op *op, const void *B, void *X, int64_t R, const bie_sol
         bie_solve_opts o{ BIE_GMRES, 30, 1e-6, 10000, BIE_SCC, 512, 1234, 0, 0, 0.0, 0, 0 };
         if (opts) o = *opts;
         if (o.method != BIE_GMRES && o.method != BIE_CGNR) return fail(BIE_EINVAL, "unknown method");
-        if (o.crit != BIE_SCC && o.crit != BIE_RSCC) return fail(BIE_EINVAL, "unknown criterion");
+        if (o.crit != BIE_SCC && o.crit != BIE_RSCC && o.crit != BIE_CCC) return fail(BIE_EINVAL, "unknown criterion");
+        if (o.precision == 1 && o.crit != BIE_SCC)
+            return fail(BIE_EINVAL, "mixed precision decides convergence by the standard criterion");
         if (o.method == BIE_GMRES && (o.restart < 1 || o.restart > 64)) return fail(BIE_EINVAL, "restart must be 1..64");
         if (!(o.tol > 0.0)) return fail(BIE_EINVAL, "tol must be > 0");
         if (o.max_mvp < 1) return fail(BIE_EINVAL, "max_mvp must be >= 1");
@@ -221,7 +223,7 @@ int bie_solve(const bie_op *op, const void *B, void *X, int64_t R, const bie_sol
         if (o.inner_terms != 0 && o.inner_terms != 2 && o.inner_terms != 3)
             return fail(BIE_EINVAL, "inner_terms must be 0, 2 or 3");
         if (o.basis != 0 && o.basis != 1) return fail(BIE_EINVAL, "basis must be 0 or 1");
-        if (op->star && o.crit == BIE_RSCC)
+        if (op->star && o.crit != BIE_SCC)
             return fail(BIE_EINVAL, "the random-sampling criterion needs assembled rows (not a star-split operator)");
         if (o.basis == 1 && (o.precision != 1 || !op->Abf))
             return fail(BIE_EINVAL, "the FP16 basis is for mixed precision with split-BF16 storage");

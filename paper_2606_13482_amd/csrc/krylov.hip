@@ -1070,11 +1070,13 @@ static int solve_impl(const bie_op *opc, const void *Bv, void *Xv, int64_t R, co
         for (int64_t r = 0; r < R; ++r)
             if (need[r]) hs[r].mvps += 1;
     };
+    // have_res[r]: the criterion left the full residual of the current x in Res
+    std::vector<int> have_res(R, 0);
     auto criterion = [&](const std::vector<int> &cand, std::vector<int> &met) {
         // returns per-column criterion value in hs[r].relres_true; met[r] set
         std::vector<int> need(R, 0);
         bool any = false;
-        for (int64_t r = 0; r < R; ++r) { met[r] = 0; if (cand[r]) { need[r] = 1; any = true; } }
+        for (int64_t r = 0; r < R; ++r) { met[r] = 0; have_res[r] = 0; if (cand[r]) { need[r] = 1; any = true; } }
         if (!any) return;
         if (inner) {   // estimate only
             for (int64_t r = 0; r < R; ++r)
@@ -1093,6 +1095,7 @@ static int solve_impl(const bie_op *opc, const void *Bv, void *Xv, int64_t R, co
                     hs[r].relres_true = v;
                     hs[r].checks += 1;
                     met[r] = v <= o.tol;
+                    have_res[r] = 1;
                 }
         } else {
             const int64_t S = std::min<int64_t>(std::min<int64_t>(o.rscc_rows, N), MAX_RSCC_ROWS);
@@ -1120,6 +1123,25 @@ static int solve_impl(const bie_op *opc, const void *Bv, void *Xv, int64_t R, co
                     hs[r].mvps += (S + N - 1) / N;   // S/N of a product, rounded up
                     met[r] = v <= o.tol;
                 }
+            if (o.crit == BIE_CCC) {
+                // combined: a sampled estimate at or below the tolerance is
+                // confirmed by the standard criterion on the full residual
+                std::vector<int> conf(R, 0);
+                bool anyc = false;
+                for (int64_t r = 0; r < R; ++r)
+                    if (need[r] && met[r]) { conf[r] = 1; anyc = true; }
+                if (anyc) {
+                    full_residual(conf);
+                    pull_st();
+                    for (int64_t r = 0; r < R; ++r)
+                        if (conf[r]) {
+                            const double v = st[r].rnorm / st[r].bnorm;
+                            hs[r].relres_true = v;
+                            met[r] = v <= o.tol;
+                            have_res[r] = 1;
+                        }
+                }
+            }
         }
     };
 
@@ -1218,7 +1240,7 @@ static int solve_impl(const bie_op *opc, const void *Bv, void *Xv, int64_t R, co
             std::vector<int> nd(R, 0);
             bool anyr = false;
             for (int64_t r = 0; r < R; ++r)
-                if (active[r] && hs[r].mvps < o.max_mvp && !(o.crit == BIE_SCC && !inner && cand[r])) {
+                if (active[r] && hs[r].mvps < o.max_mvp && !(!inner && cand[r] && have_res[r])) {
                     nd[r] = 1;
                     anyr = true;
                 }
@@ -1303,7 +1325,11 @@ static int solve_impl(const bie_op *opc, const void *Bv, void *Xv, int64_t R, co
                 else active[r] = 0;
             }
             if (anyr) {
-                if (o.crit != BIE_SCC) full_residual(again);
+                std::vector<int> fr(R, 0);
+                bool anyf = false;
+                for (int64_t r = 0; r < R; ++r)
+                    if (again[r] && !have_res[r]) { fr[r] = 1; anyf = true; }
+                if (anyf) full_residual(fr);
                 pull_st();
                 cg_restart(again);
             }
@@ -2155,7 +2181,7 @@ int solve(const bie_op *op, const void *B, void *X, int64_t R, const bie_solve_o
         if (op->Abf) return solve_stream<float2>(op, B, X, R, o, stats, s, MATBF16);
         return solve_stream<double2>(op, B, X, R, o, stats, s, MAT32);
     }
-    if (!op->Z64 && o.crit == BIE_RSCC) throw Error(BIE_EINVAL, "the random-sampling criterion needs the FP64 matrix");
+    if (!op->Z64 && o.crit != BIE_SCC) throw Error(BIE_EINVAL, "the random-sampling criterion needs the FP64 matrix");
     return solve_impl(op, B, X, R, o, stats, s, op->Z64 ? MAT64 : MAT32, false);
 }
 

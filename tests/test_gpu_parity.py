@@ -171,6 +171,27 @@ def test_rscc_criterion(bie):
     assert krylov.scc(Zo, b, x) < 5e-6
 
 
+def test_ccc_criterion(bie):
+    """Combined criterion (RSCC gates, SCC confirms): converged columns report the
+    SCC of their solution against the oracle matrix; with every row sampled it
+    takes the SCC's iterations."""
+    V, T, rwg, Zo = case(2, 2.0)
+    op = bie.Operator(V, T, 2.0)
+    d, e = planewave_set(np.array([[0.3, 0.1, 0.9], [0.0, 0.0, 1.0], [1.0, 0.2, -0.3]]), "phi")
+    B = op.rhs(d, e)
+    X, st = op.solve(B, bie.Solve(restart=30, tol=1e-6, crit="ccc", rscc_rows=48, rscc_seed=3))
+    Xn, Bn = X.cpu().numpy(), B.cpu().numpy()
+    for r in range(B.shape[0]):
+        want = krylov.scc(Zo, Bn[r], Xn[r])
+        assert st[r]["converged"] and abs(st[r]["relres_true"] - want) <= 1e-9 * want and want <= 1e-6
+    Xs, sts = op.solve(B, bie.Solve(restart=30, tol=1e-6))
+    Xa, sta = op.solve(B, bie.Solve(restart=30, tol=1e-6, crit="ccc", rscc_rows=op.N))
+    assert [s["iters"] for s in sta] == [s["iters"] for s in sts]
+    assert torch.equal(Xa, Xs)
+    with pytest.raises(bie.BieError):
+        op.solve(B[:1], bie.Solve(crit="ccc", precision="mixed"))
+
+
 @pytest.mark.parametrize("nrhs", [5, 20])
 def test_multi_rhs_equals_single(bie, nrhs):
     """Columns solved together equal their single solves bitwise."""

@@ -113,6 +113,20 @@ def test_gmres_rscc_criterion(ico):
     assert krylov.scc(Z, b, x) < 3e-6
 
 
+def test_gmres_ccc_criterion(ico):
+    """Combined criterion: with every row sampled (S = N) the RSCC equals the SCC,
+    so CCC takes the SCC's iterations and solution; with a small sample the
+    reported value is the SCC of the returned x and meets the tolerance."""
+    rwg, Z, b = _c1_like(ico, 2)
+    n = b.shape[0]
+    xs, ss = krylov.gmres(Z, b, m=30, tol=1e-6, crit="scc")
+    xc, sc = krylov.gmres(Z, b, m=30, tol=1e-6, crit="ccc", rscc_rows=n)
+    assert sc.converged and sc.iters == ss.iters and np.allclose(xc, xs, rtol=0, atol=1e-14)
+    xc, sc = krylov.gmres(Z, b, m=30, tol=1e-6, crit="ccc", rscc_rows=24, rscc_seed=5)
+    assert sc.converged
+    assert sc.relres_true == krylov.scc(Z, b, xc) and sc.relres_true <= 1e-6
+
+
 def test_reciprocity(ico):
     """e_s . F(r; d, e_i) = e_i . F(-d; -r, e_s) since Z = Z^T (far field of Sec. II)."""
     rwg, Z, _ = _c1_like(ico, 2)
