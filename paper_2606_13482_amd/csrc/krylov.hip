@@ -1702,6 +1702,7 @@ struct GLayout {
     int64_t nitems = 0, nritems = 0;
     int64_t *gpoff = nullptr;   // partial-vector offset per column
     double2 *gpart = nullptr;   // partial vectors of all columns
+    std::vector<int32_t> h_items, h_ritems, h_c0, h_c1;   // host copies: items, reduce items, columns of each problem
 };
 
 std::unique_ptr<GLayout> make_layout(const bie_op *const *ops, int64_t P, const int64_t *R, int U, int G, bool mat64)
@@ -1780,6 +1781,12 @@ std::unique_ptr<GLayout> make_layout(const bie_op *const *ops, int64_t P, const 
     BIE_HIP(hipMemcpy(L->items, items.data(), items.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     BIE_HIP(hipMemcpy(L->ritems, ritems.data(), ritems.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     BIE_HIP(hipMemcpy(L->gpoff, gpoff.data(), gpoff.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    L->h_items = std::move(items);
+    L->h_ritems = std::move(ritems);
+    for (int64_t p = 0; p < P; ++p) {
+        L->h_c0.push_back(probs[p].c0);
+        L->h_c1.push_back(probs[p].c1);
+    }
     return L;
 }
 
@@ -1970,8 +1977,38 @@ int solve_batch(const bie_op *const *ops, int64_t P, const void *const *Bp, void
         L = make_layout(ops, P, Rp, U, G, mat64);
     }
     const GCols gres = layout_cols(*L, dwo, 0);
+    // Live work: the tile items with at least one live column and the reduce
+    // items of live columns, rebuilt (and the cycle graph captured again) when
+    // the live columns have dropped by a quarter since the last build, so that
+    // late cycles launch only the work of the slow columns.  Order and
+    // arithmetic per column are unchanged (results are bitwise the same).
+    int32_t *litems = db.get<int32_t>(std::max<size_t>(1, L->h_items.size()));
+    int32_t *lritems = db.get<int32_t>(std::max<size_t>(1, L->h_ritems.size()));
+    int64_t nlitems = 0, nlritems = 0, live_built = -1;
+    auto build_live = [&](const std::vector<int> &live) {
+        std::vector<int32_t> it, rit;
+        for (size_t i = 0; 3 * i < L->h_items.size(); ++i) {
+            const int32_t p = L->h_items[3 * i], g = L->h_items[3 * i + 2];
+            const int32_t cb = L->h_c0[p] + g * L->G, ce = std::min(L->h_c1[p], cb + L->G);
+            bool any = false;
+            for (int32_t c = cb; c < ce && !any; ++c) any = live[c] != 0;
+            if (any) it.insert(it.end(), { p, L->h_items[3 * i + 1], g });
+        }
+        for (size_t i = 0; 2 * i < L->h_ritems.size(); ++i)
+            if (live[L->h_ritems[2 * i]]) rit.insert(rit.end(), { L->h_ritems[2 * i], L->h_ritems[2 * i + 1] });
+        nlitems = int64_t(it.size() / 3);
+        nlritems = int64_t(rit.size() / 2);
+        if (!it.empty()) BIE_HIP(hipMemcpyAsync(litems, it.data(), it.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        if (!rit.empty())
+            BIE_HIP(hipMemcpyAsync(lritems, rit.data(), rit.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        BIE_HIP(hipStreamSynchronize(s));
+        live_built = 0;
+        for (int v : live) live_built += v != 0;
+    };
+    std::vector<int> all_live(C, 1);
+    build_live(all_live);
     auto full_residual = [&](const int *skipdev) {   // Res = B - T X for the columns not skipped
-        grouped_product(mat64, L->probs, gres, L->items, L->nitems, L->G, L->ritems, L->nritems, Xw, L->gpart, w->Res, Bw,
+        grouped_product(mat64, L->probs, gres, litems, nlitems, L->G, lritems, nlritems, Xw, L->gpart, w->Res, Bw,
                         skipdev, 1, s);
     };
 
@@ -2056,7 +2093,7 @@ int solve_batch(const bie_op *const *ops, int64_t P, const void *const *Bp, void
     auto cycle_body = [&]() {
         for (int j = 0; j < m; ++j) {
             const GCols gv = layout_cols(*L, dvo, j);
-            grouped_product(mat64, L->probs, gv, L->items, L->nitems, L->G, L->ritems, L->nritems, w->V, L->gpart, w->W,
+            grouped_product(mat64, L->probs, gv, litems, nlitems, L->G, lritems, nlritems, w->V, L->gpart, w->W,
                             nullptr, done_flags, done_stride, s);
             arnoldi_step<double2>(w, cl, Nmax, w->V, m, j, o.tol, C, s);
         }
@@ -2074,14 +2111,19 @@ int solve_batch(const bie_op *const *ops, int64_t P, const void *const *Bp, void
     } gguard{ graph, gexec };
     const bool use_graph = g_batch.graph != 0;
     const bool prof_was = prof_active();
-    if (use_graph) {
+    auto capture = [&]() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        gexec = nullptr;
+        graph = nullptr;
         prof_enable(false);   // no event records inside the captured graph
         BIE_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         cycle_body();
         BIE_HIP(hipStreamEndCapture(s, &graph));
         BIE_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
         prof_enable(prof_was);
-    }
+    };
+    if (use_graph) capture();
 
     while (true) {
         bool any = false;
@@ -2090,6 +2132,12 @@ int solve_batch(const bie_op *const *ops, int64_t P, const void *const *Bp, void
             any = any || active[c];
         }
         if (!any) break;
+        int64_t nlive = 0;
+        for (int64_t c = 0; c < C; ++c) nlive += active[c] != 0;
+        if (4 * nlive <= 3 * live_built) {
+            build_live(active);
+            if (use_graph) capture();
+        }
         for (int64_t c = 0; c < C; ++c) {
             ColStat &q = st[c];
             q.done = active[c] ? 0 : 1;
