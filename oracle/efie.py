@@ -155,12 +155,14 @@ def fill(rwg: dict, k: float, rule=None, near_factor: float = 2.0, singular: boo
     return (Z, A, P) if parts else Z
 
 
-def fill_rows(rwg: dict, k: float, rows, rule=None, near_factor: float = 2.0):
-    """Rows Z[rows, :] computed from the triangle pairs of those rows only."""
+def fill_rows(rwg: dict, k: float, rows, rule=None, near_factor: float = 2.0, flags=None):
+    """Rows Z[rows, :] computed from the triangle pairs of those rows only
+    (flags: the flagged-pair matrix of mesh.flagged_pairs, if already at hand)."""
     rows = np.asarray(rows, dtype=np.int64)
     G = Geometry(rwg, rule)
     N = rwg["N"]
-    flags = flagged_pairs(rwg, near_factor)
+    if flags is None:
+        flags = flagged_pairs(rwg, near_factor)
     tris = np.unique(np.concatenate([rwg["tp"][rows], rwg["tm"][rows]]))
     out = np.zeros((rows.size, N), np.complex128)
     for c0 in range(0, tris.size, 16):

@@ -1,0 +1,117 @@
+"""Parity at the workloads' full sizes, in the launch configurations the bench
+times: the 7680-unknown sphere at k = 10 and the 30720-unknown sphere at k = 20,
+on sampled outputs the oracle computes one by one (matrix rows from the triangle
+pairs of those rows only), and the headline solve against the oracle's full
+matrix (7680 unknowns)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import cfill, efie
+from oracle.mesh import flagged_pairs, rwg_table
+from paper_2606_13482_amd.inputs import complex_gaussian, icosphere, planewave_set, random_directions
+
+pytestmark = pytest.mark.gpu
+
+_MESH = {}
+
+
+def _mesh(level):
+    """Mesh, RWG table and flagged triangle pairs (the near rule of the fill)."""
+    if level not in _MESH:
+        V, T = icosphere(level)
+        rwg = rwg_table(V, T)
+        _MESH[level] = (V, T, rwg, flagged_pairs(rwg, 2.0))
+    return _MESH[level]
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _maxrel(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+@pytest.mark.parametrize("level,k,nrows", [(4, 10.0, 6), (5, 20.0, 3)])
+def test_full_size_sampled_rows(bie, level, k, nrows):
+    """FP64 and FP32 fills, the packed FP64 product (one vector) and the split-BF16
+    and FP64 block products (256 columns, the bench's launch shape) at full size,
+    compared on sampled rows with the oracle's rows."""
+    V, T, rwg, flags = _mesh(level)
+    N = rwg["N"]
+    rng = np.random.default_rng(1000 + level)
+    rows = np.unique(np.concatenate([[0, N - 1], rng.choice(N, nrows - 2, replace=False)]))
+    Ro = efie.fill_rows(rwg, k, rows, flags=flags)    # (S, N)
+    op = bie.Operator(V, T, k, storage="split_bf16")
+    # fill: T e_i is column i = row i (T = T^T)
+    E = np.zeros((rows.size, N), np.complex128)
+    E[np.arange(rows.size), rows] = 1.0
+    cols = op.apply(torch.from_numpy(E).cuda()).cpu().numpy()
+    e_fill = _maxrel(cols, Ro)
+    # packed FP64 product of one vector (the GEMV kernel)
+    x = complex_gaussian(N, 7)
+    y = op.apply(torch.from_numpy(x).cuda().reshape(1, -1)).cpu().numpy()[0]
+    e_gemv = _maxrel(y[rows], Ro @ x)
+    # block products, 256 columns
+    X = complex_gaussian(N, 11, cols=256)
+    ref = X @ Ro.T                                                            # (256, S)
+    Xd = torch.from_numpy(X).cuda()
+    e_bf16 = _maxrel(op.apply(Xd, block=True).cpu().numpy()[:, rows], ref)
+    e_f64 = _maxrel(op.apply(Xd, block="fp64").cpu().numpy()[:, rows], ref)
+    op.close()
+    op32 = bie.Operator(V, T, k, storage="c64")
+    e_fill32 = _maxrel(op32.apply(torch.from_numpy(E.astype(np.complex64)).cuda()).cpu().numpy(), Ro)
+    op32.close()
+    _say(f"  N={N} rows {rows.tolist()}: fill FP64 {e_fill:.1e}, FP32 {e_fill32:.1e}; packed product {e_gemv:.1e}; "
+         f"block split-BF16 {e_bf16:.1e}, FP64 {e_f64:.1e}")
+    assert e_fill <= 1e-12 and e_gemv <= 1e-12 and e_f64 <= 1e-12
+    assert e_fill32 <= 1e-6
+    assert e_bf16 <= 3e-5
+
+
+def test_full_size_headline_solve(bie):
+    """The headline form (split-BF16 block products, FP16 inner basis, FP64
+    refinement, continuous batch) on 16 plane waves at 7680 unknowns: every
+    solution meets SCC 1e-6 against the oracle's full matrix, and the residual the
+    solver reports is that SCC."""
+    V, T, rwg, _ = _mesh(4)
+    op = bie.Operator(V, T, 10.0, storage="split_bf16")
+    d, e = planewave_set(random_directions(8, 77), "theta")
+    d2, e2 = planewave_set(random_directions(8, 78), "phi")
+    B = op.rhs(np.concatenate([d, d2]), np.concatenate([e, e2]))
+    X, st = op.solve(B, bie.Solve(restart=50, tol=1e-6, precision="mixed", inner_tol=0.1, slots=256, basis="f16"))
+    op.close()
+    Zo = cfill.fill(rwg, 10.0)
+    Bn, Xn = B.cpu().numpy(), X.cpu().numpy()
+    res = np.linalg.norm(Bn - Xn @ Zo.T, axis=1) / np.linalg.norm(Bn, axis=1)
+    rep = np.array([s["relres_true"] for s in st])
+    _say(f"  headline form, 7680 unknowns: max residual {res.max():.3e}, reported {rep.max():.3e}, "
+         f"iterations {int(np.mean([s['iters'] for s in st]))} mean")
+    assert all(s["converged"] for s in st)
+    assert res.max() <= 1e-6 * (1 + 1e-6)
+    assert np.max(np.abs(rep - res) / res) <= 1e-7
+
+
+def test_full_size_large_sphere_solve(bie):
+    """The large-sphere form (30720 unknowns, k = 20, GMRES(30), split-BF16
+    products with FP64 refinement) on 4 plane waves: converged to 1e-6, and the
+    FP64 residual it is judged by agrees on sampled rows with the oracle's rows."""
+    V, T, rwg, flags = _mesh(5)
+    N = rwg["N"]
+    op = bie.Operator(V, T, 20.0, storage="split_bf16")
+    d, e = planewave_set(random_directions(4, 79), "theta")
+    B = op.rhs(d, e)
+    X, st = op.solve(B, bie.Solve(restart=30, tol=1e-6, precision="mixed", inner_tol=0.1, slots=256, basis="f16"))
+    assert all(s["converged"] for s in st) and max(s["relres_true"] for s in st) <= 1e-6
+    Rg = (B - op.apply(X)).cpu().numpy()                      # FP64 residual on the GPU
+    rows = np.array([3, N // 2, N - 2])
+    Ro = efie.fill_rows(rwg, 20.0, rows, flags=flags)
+    Bn, Xn = B.cpu().numpy(), X.cpu().numpy()
+    ro = Bn[:, rows] - Xn @ Ro.T
+    scale = np.linalg.norm(Bn, axis=1)[:, None]
+    err = float(np.max(np.abs(Rg[:, rows] - ro) / scale))
+    _say(f"  large sphere: reported residuals {[round(s['relres_true'], 9) for s in st]}, "
+         f"sampled-row residual difference {err:.1e} of |b|")
+    assert err <= 1e-12
+    op.close()
