@@ -140,3 +140,115 @@ def test_reciprocity(ico):
     f1 = efie.radiation_vector(rwg, k, x1, r[None])[0] @ es
     f2 = efie.radiation_vector(rwg, k, x2, -d[None])[0] @ ei
     assert abs(f1 - f2) / abs(f1) < 1e-12
+
+
+def _planewaves(rwg, k, count, seed):
+    from paper_2606_13482_amd.inputs import random_directions
+    d, e = planewave_set(random_directions(count, seed), "theta")
+    return efie.rhs(rwg, k, d, e)
+
+
+def test_block_gmres_block_one_is_gmres(ico):
+    """With one right-hand side per block the method is GMRES(m) itself: the same
+    iteration counts and iterates as the scalar oracle (pinned to LU)."""
+    rwg = ico(2)
+    Z = cfill.fill(rwg, 2.0)
+    B = _planewaves(rwg, 2.0, 3, 31)
+    X, st = krylov.block_gmres(Z, B, m=20, tol=1e-8, block=1)
+    for i in range(3):
+        x, s = krylov.gmres(Z, B[i], m=20, tol=1e-8)
+        assert st[i].converged and s.converged
+        assert st[i].iters == s.iters
+        assert np.linalg.norm(X[i] - x) / np.linalg.norm(x) < 1e-10
+
+
+def test_block_gmres_minimal_residual_brute_force(ico):
+    """One cycle of j block steps gives, for every column, the minimiser of
+    ||b_i - Z x|| over the block Krylov space span{B, ZB, ..., Z^{j-1} B}: checked
+    against least squares over that space built explicitly (N = 120, 4 columns,
+    j = 3).  A dropped Hessenberg block, a wrong least-squares right side or a
+    wrong scaling moves the result off the minimiser."""
+    rwg = ico(1)
+    Z = cfill.fill(rwg, 2.0)
+    B = _planewaves(rwg, 2.0, 4, 32)
+    j = 3
+    X, st = krylov.block_gmres(Z, B, m=j, tol=1e-30, block=4, max_mvp=j)
+    K = [B.T]
+    for _ in range(j - 1):
+        K.append(Z @ K[-1])
+    K, _ = np.linalg.qr(np.concatenate(K, axis=1))                 # N x jq
+    ZK = Z @ K
+    for i in range(4):
+        c = np.linalg.lstsq(ZK, B[i], rcond=None)[0]
+        xb = K @ c
+        assert np.linalg.norm(X[i] - xb) / np.linalg.norm(xb) < 1e-9
+        # the cycle's estimate is the true residual of the minimiser
+        rt = np.linalg.norm(B[i] - Z @ X[i]) / np.linalg.norm(B[i])
+        assert abs(st[i].relres_est - rt) <= 1e-9 * rt
+        assert abs(st[i].relres_true - rt) <= 1e-12 * rt
+    # and a larger block space never does worse than each column's own space
+    for i in range(4):
+        xs, _ = krylov.gmres(Z, B[i], m=j, tol=1e-30, max_mvp=j)
+        assert np.linalg.norm(B[i] - Z @ X[i]) <= np.linalg.norm(B[i] - Z @ xs) * (1 + 1e-12)
+
+
+def test_block_gmres_full_space_equals_lu(ico):
+    """When the block Krylov space reaches the whole space (j q >= N) the method
+    solves exactly: equals LU (N = 120, 4 columns)."""
+    rwg = ico(1)
+    Z = cfill.fill(rwg, 2.0)
+    B = _planewaves(rwg, 2.0, 4, 33)
+    X, st = krylov.block_gmres(Z, B, m=40, tol=1e-12, block=4)
+    Xl = np.linalg.solve(Z, B.T).T
+    assert all(s.converged for s in st)
+    assert np.max(np.linalg.norm(X - Xl, axis=1) / np.linalg.norm(Xl, axis=1)) < 1e-9
+    assert max(s.iters for s in st) <= 30
+
+
+def test_block_gmres_dependent_columns(ico):
+    """Dependent right-hand sides (a repeat and a sum) are deflated from the
+    initial block: the block keeps 2 directions and every solution is still the
+    linear image of the independent ones."""
+    rwg = ico(2)
+    Z = cfill.fill(rwg, 2.0)
+    b = _planewaves(rwg, 2.0, 2, 34)
+    B = np.stack([b[0], b[1], b[0], 2.0 * b[0] - 1j * b[1]])
+    X, st = krylov.block_gmres(Z, B, m=30, tol=1e-9, block=4)
+    assert all(s.converged for s in st)
+    Xl = np.linalg.solve(Z, B.T).T
+    assert np.max(np.linalg.norm(X - Xl, axis=1) / np.linalg.norm(Xl, axis=1)) < 1e-6
+    assert np.linalg.norm(X[2] - X[0]) <= 1e-8 * np.linalg.norm(X[0])
+
+
+def test_block_gmres_breakdown_on_invariant_space():
+    """A matrix with three distinct eigenvalues: the block Krylov space of two
+    right-hand sides stops growing after three steps (partial breakdown), and the
+    solution is then exact."""
+    rng = np.random.default_rng(3)
+    N = 60
+    Q, _ = np.linalg.qr(rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N)))
+    lam = np.repeat([1.0, 2.0 + 1.0j, -0.5 + 0.3j], N // 3)
+    Z = (Q * lam) @ np.linalg.inv(Q)
+    B = rng.standard_normal((2, N)) + 1j * rng.standard_normal((2, N))
+    X, st = krylov.block_gmres(Z, B, m=30, tol=1e-11, block=2)
+    assert all(s.converged for s in st)
+    assert max(s.iters for s in st) <= 3
+    assert np.max(np.linalg.norm(B - X @ Z.T, axis=1) / np.linalg.norm(B, axis=1)) < 1e-11
+
+
+def test_block_gmres_restarts_and_zero_rhs(ico):
+    """Restarted block GMRES reaches the standard criterion for every column,
+    with fewer block steps per right-hand side than GMRES(m) per column; a zero
+    right-hand side gives x = 0 at once."""
+    rwg = ico(2)
+    Z = cfill.fill(rwg, 2.0)
+    B = _planewaves(rwg, 2.0, 8, 35)
+    B[3] = 0.0
+    X, st = krylov.block_gmres(Z, B, m=10, tol=1e-8, block=4)
+    res = np.linalg.norm(B - X @ Z.T, axis=1)
+    nb = np.linalg.norm(B, axis=1)
+    assert all(s.converged for s in st)
+    assert np.all(res <= 1e-8 * nb * (1 + 1e-9))
+    assert st[3].iters == 0 and np.all(X[3] == 0)
+    its = [krylov.gmres(Z, B[i], m=10, tol=1e-8)[1].iters for i in range(8) if i != 3]
+    assert np.mean([st[i].iters for i in range(8) if i != 3]) < np.mean(its)
