@@ -135,7 +135,7 @@ int bie_rhs_planewave(const bie_op *op, const double *dirs, const double *pols, 
 int bie_apply(const bie_op *op, const void *X, void *Y, int64_t R, int vec, int conj,
               void *stream);
 
-typedef enum { BIE_GMRES = 0, BIE_CGNR = 1 } bie_method;
+typedef enum { BIE_GMRES = 0, BIE_CGNR = 1, BIE_BGMRES = 2 } bie_method;
 typedef enum { BIE_SCC = 0, BIE_RSCC = 1, BIE_CCC = 2 } bie_crit;
 
 typedef struct {
@@ -168,6 +168,8 @@ typedef struct {
                             the Arnoldi kernels; the 3-term split of an FP16 vector into
                             BF16 hi/lo is exact).  BIE_EINVAL for 1 with another
                             precision or storage */
+    int block;           /* BIE_BGMRES: right-hand sides per block Krylov space
+                            (1..32); 0: 32 */
 } bie_solve_opts;
 
 typedef struct {
@@ -190,6 +192,24 @@ typedef struct {
  *         RSCC value is <= tol is accepted only if the SCC holds as well (its
  *         full residual then also restarts the method when it does not).
  *   RSCC and CCC need the FP64 matrix (assembled operator) and precision 0.
+ * Block GMRES (BIE_BGMRES; the paper names GMRES only, block GMRES is a
+ * reading for many right-hand sides): consecutive groups of at most `block`
+ * right-hand sides that have not converged share one block Krylov space
+ * span{R0, T R0, ..., T^{j-1} R0} per restart cycle, and every column takes the
+ * element of it that minimises its own residual.  R0 holds the residuals scaled
+ * to unit norm, orthonormalised with rank revealing (directions below 1e-6 of
+ * the largest are left out); block Gram-Schmidt with a second pass when a
+ * column loses more than half its norm squared, Cholesky QR of the new block,
+ * block Householder QR of the block Hessenberg matrix.  A cycle ends when every
+ * column's estimate meets its target, after `restart` block steps, or on a
+ * partial breakdown (a new direction at or below 1e-6 of the largest column of
+ * T V_j).  Then every column is checked on its FP64 residual (SCC), converged
+ * ones leave and the rest are regrouped.  Precision 0: FP64 basis and FP64
+ * block products, target tol ||b||; precision 1 (split-BF16 storage):
+ * complex64 basis and split-BF16 products, one cycle per refinement step to
+ * inner_tol relative to the FP64 residual.  SCC only; slots > 0 solves the
+ * right-hand sides in consecutive chunks of that many.  Counts: one iteration
+ * and one product per block step for every column of the block.
  * GMRES(m): Arnoldi with classical Gram-Schmidt and selective
  * reorthogonalisation (a second pass when the first removes more than half of
  * ||w||^2), FP64 Givens rotations; a cycle ends when the estimate <= tol or j = m, then the

@@ -21,7 +21,7 @@ BIE_OK, BIE_NOT_CONVERGED = 0, 1
 BIE_EINVAL, BIE_EMESH, BIE_ENOMEM, BIE_EDEVICE, BIE_ENUMERIC = -1, -2, -3, -4, -5
 BIE_C128, BIE_C64, BIE_SPLIT_BF16 = 0, 1, 2
 BIE_APPLY_F64_BLOCK = 3
-BIE_GMRES, BIE_CGNR = 0, 1
+BIE_GMRES, BIE_CGNR, BIE_BGMRES = 0, 1, 2
 BIE_SCC, BIE_RSCC, BIE_CCC = 0, 1, 2
 
 _ERRNAMES = {BIE_EINVAL: "EINVAL", BIE_EMESH: "EMESH", BIE_ENOMEM: "ENOMEM",
@@ -44,7 +44,7 @@ class SolveOpts(ctypes.Structure):
                 ("max_mvp", ctypes.c_int64), ("crit", ctypes.c_int), ("rscc_rows", ctypes.c_int64),
                 ("rscc_seed", ctypes.c_uint64), ("use_x0", ctypes.c_int), ("precision", ctypes.c_int),
                 ("inner_tol", ctypes.c_double), ("slots", ctypes.c_int64), ("inner_terms", ctypes.c_int),
-                ("basis", ctypes.c_int)]
+                ("basis", ctypes.c_int), ("block", ctypes.c_int)]
 
 
 class WsOpts(ctypes.Structure):
@@ -172,12 +172,14 @@ class Solve:
     slots: int = 0                # mixed: right-hand sides in flight (continuous batch); 0 = all
     inner_terms: int = 0          # mixed, split-BF16: 3 or 2 terms of the inner block product; 0 = 3
     basis: str = "c64"            # mixed, split-BF16: inner Krylov basis "c64" or "f16" (FP16 pairs)
+    block: int = 0                # method "bgmres": right-hand sides per block Krylov space (1..32); 0 = 32
 
     def c(self, use_x0: int) -> SolveOpts:
-        return SolveOpts({"gmres": BIE_GMRES, "cgnr": BIE_CGNR}[self.method], self.restart, self.tol,
+        return SolveOpts({"gmres": BIE_GMRES, "cgnr": BIE_CGNR, "bgmres": BIE_BGMRES}[self.method], self.restart, self.tol,
                          self.max_mvp, {"scc": BIE_SCC, "rscc": BIE_RSCC, "ccc": BIE_CCC}[self.crit], self.rscc_rows,
                          self.rscc_seed, int(use_x0), {"plain": 0, "mixed": 1}[self.precision],
-                         self.inner_tol, self.slots, self.inner_terms, {"c64": 0, "f16": 1}[self.basis])
+                         self.inner_tol, self.slots, self.inner_terms, {"c64": 0, "f16": 1}[self.basis],
+                         self.block)
 
 
 class Operator:

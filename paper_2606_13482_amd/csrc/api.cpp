@@ -206,13 +206,24 @@ int bie_solve(const bie_op *op, const void *B, void *X, int64_t R, const bie_sol
         if (!op || !B || !X) return fail(BIE_EINVAL, "NULL argument");
         if (R < 0 || R > 4096) return fail(BIE_EINVAL, "R out of range (0..4096)");
         if (R == 0) return BIE_OK;
-        bie_solve_opts o{ BIE_GMRES, 30, 1e-6, 10000, BIE_SCC, 512, 1234, 0, 0, 0.0, 0, 0 };
+        bie_solve_opts o{ BIE_GMRES, 30, 1e-6, 10000, BIE_SCC, 512, 1234, 0, 0, 0.0, 0, 0, 0, 0 };
         if (opts) o = *opts;
-        if (o.method != BIE_GMRES && o.method != BIE_CGNR) return fail(BIE_EINVAL, "unknown method");
+        if (o.method != BIE_GMRES && o.method != BIE_CGNR && o.method != BIE_BGMRES)
+            return fail(BIE_EINVAL, "unknown method");
         if (o.crit != BIE_SCC && o.crit != BIE_RSCC && o.crit != BIE_CCC) return fail(BIE_EINVAL, "unknown criterion");
         if (o.precision == 1 && o.crit != BIE_SCC)
             return fail(BIE_EINVAL, "mixed precision decides convergence by the standard criterion");
-        if (o.method == BIE_GMRES && (o.restart < 1 || o.restart > 64)) return fail(BIE_EINVAL, "restart must be 1..64");
+        if ((o.method == BIE_GMRES || o.method == BIE_BGMRES) && (o.restart < 1 || o.restart > 64))
+            return fail(BIE_EINVAL, "restart must be 1..64");
+        if (o.method == BIE_BGMRES) {
+            if (o.block < 0 || o.block > 32) return fail(BIE_EINVAL, "block must be 0..32");
+            if (o.crit != BIE_SCC) return fail(BIE_EINVAL, "block GMRES decides convergence by the standard criterion");
+            if (op->star) return fail(BIE_EINVAL, "block GMRES needs an assembled operator");
+            if (o.basis != 0) return fail(BIE_EINVAL, "block GMRES keeps a complex64 or FP64 basis");
+            if (o.precision == 1 && !op->Abf)
+                return fail(BIE_EINVAL, "mixed-precision block GMRES needs split-BF16 storage");
+            if (!op->Z64) return fail(BIE_EINVAL, "block GMRES needs the FP64 matrix");
+        }
         if (!(o.tol > 0.0)) return fail(BIE_EINVAL, "tol must be > 0");
         if (o.max_mvp < 1) return fail(BIE_EINVAL, "max_mvp must be >= 1");
         if (o.rscc_rows < 1) return fail(BIE_EINVAL, "rscc_rows must be >= 1");
@@ -231,7 +242,8 @@ int bie_solve(const bie_op *op, const void *B, void *X, int64_t R, const bie_sol
         hipStream_t s = as_stream(stream);
         if (bie::has_nonfinite(B, 2 * R * N, s)) return fail(BIE_ENUMERIC, "non-finite right-hand side");
         if (o.use_x0 && bie::has_nonfinite(X, 2 * R * N, s)) return fail(BIE_ENUMERIC, "non-finite initial guess");
-        const int rc = bie::solve(op, B, X, R, o, stats, s);
+        const int rc = o.method == BIE_BGMRES ? bie::solve_block(op, B, X, R, o, stats, s)
+                                              : bie::solve(op, B, X, R, o, stats, s);
         if (rc == BIE_NOT_CONVERGED) g_err = "not converged within max_mvp";
         return rc;
     });
@@ -243,7 +255,7 @@ int bie_batch_solve(const bie_op *const *ops, int64_t nops, const void *const *B
     return guarded([&]() -> int {
         if (!ops || !B || !X || !R) return fail(BIE_EINVAL, "NULL argument");
         if (nops < 1 || nops > 4096) return fail(BIE_EINVAL, "nops out of range (1..4096)");
-        bie_solve_opts o{ BIE_GMRES, 30, 1e-6, 10000, BIE_SCC, 512, 1234, 0, 0, 0.0, 0, 0 };
+        bie_solve_opts o{ BIE_GMRES, 30, 1e-6, 10000, BIE_SCC, 512, 1234, 0, 0, 0.0, 0, 0, 0, 0 };
         if (opts) o = *opts;
         if (o.method != BIE_GMRES || o.precision != 0 || o.crit != BIE_SCC || o.basis != 0)
             return fail(BIE_EINVAL, "batched solves take GMRES, precision 0 and the standard criterion");

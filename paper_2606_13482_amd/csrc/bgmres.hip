@@ -1,0 +1,1014 @@
+// Restarted block GMRES over groups of right-hand sides: every group of at most
+// `block` right-hand sides shares one block Krylov space, and each of its
+// columns takes the element of that space that minimises its own residual
+// (block GMRES: Vital 1990; Saad, Iterative Methods for Sparse Linear Systems,
+// Sec. 6.12).  The paper's acronym list names GMRES only; block GMRES is the
+// reading used for its many-right-hand-side runs.
+//
+// One restart cycle of a group of q columns:
+//   R0 (scaled to unit columns) = V_0 S     rank-revealing: pivoted Cholesky of
+//                                           the Gram matrix, directions below
+//                                           delta are left out (width r <= q)
+//   j = 0, 1, ...:
+//     W = T V_j                             one block product over the active
+//                                           columns of every group
+//     C = V^H W, G = W^H W; W -= V C        block classical Gram-Schmidt with the
+//                                           Gram matrix of W in the same pass;
+//                                           a second pass when a column lost more
+//                                           than half of its norm squared
+//     W^H W = R^H R (Cholesky), V_{j+1} = W R^{-1}
+//     Hbar(:, j) = [C; R]; block Householder update of its QR factorisation and
+//     of E_1 S; per-column residual estimate from the last r rows
+//   the cycle ends when every column meets its target, on a partial breakdown
+//   (a Cholesky pivot at or below delta times the largest column norm of T V_j)
+//   or after m steps; then Y = argmin ||E_1 S - Hbar Y|| and X += V Y.
+//
+// Everything after the product runs on the device, with one host
+// synchronisation per step (the estimates decide which groups go on).
+// Precision 0: FP64 basis, FP64 block products on the matrix cores, target
+// tol ||b||.  Precision 1 (iterative refinement): complex64 basis, split-BF16
+// block products, one cycle per refinement step to inner_tol relative to the
+// FP64 residual, FP64 residuals and criterion outside.
+#include "bie_internal.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <vector>
+
+namespace bie {
+namespace {
+
+constexpr int BMAX = 32;    // right-hand sides per group, at most
+constexpr int DT = 64;      // basis vectors per tile of the dot kernel
+constexpr int DS = 32;      // rows per LDS stage of the dot kernel
+constexpr double DELTA = 1e-6;
+
+__device__ inline double2 to_d2(double2 v) { return v; }
+__device__ inline double2 to_d2(float2 v) { return make_double2(double(v.x), double(v.y)); }
+template <typename T>
+__device__ inline T from_d2(double2 v);
+template <>
+__device__ inline double2 from_d2<double2>(double2 v) { return v; }
+template <>
+__device__ inline float2 from_d2<float2>(double2 v) { return make_float2(float(v.x), float(v.y)); }
+
+__device__ inline double2 cmul(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__device__ inline double2 cmulc(double2 a, double2 b)   // conj(a) * b
+{
+    return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ inline double2 cscale(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
+
+// Dot item: dst[(k0 + v) * ld + b] = sum_n conj(A_{k0+v}[n]) B_b[n] for v < kc, b < nb.
+// Basis vector k is at A + ((k / ar) * astride + k % ar) * N (blocks of ar
+// vectors, astride vectors apart); column b of B at Bm + b * N.
+struct DItem {
+    const void *A;
+    int64_t astride;
+    const double2 *Bm;
+    double2 *dst;
+    const int *flag;   // item runs only if *flag != 0 (null: always)
+    int ar, k0, kc, nb, ld, pad;
+};
+
+// Combination item: out_b[n] = beta out_b[n] + alpha sum_k A_k[n] C[k * ldc + b]
+// for k < K, b < nb; output column b at out + (ocol ? ocol[b] : b) * N.
+struct CItem {
+    const void *A;
+    int64_t astride;
+    const double2 *C;
+    void *out;
+    const int *ocol;
+    const int *flag;
+    double alpha, beta;
+    int ar, K, ldc, nb;
+};
+
+// Partial dots over a chunk of L rows; part[((item * nchunks + chunk) * DT + v) * BMAX + b].
+// Thread (v = t % 64, wave w): basis vector v of the tile against columns w, w + 4, ...
+template <typename AT, int NQ>
+__global__ __launch_bounds__(256) void k_bdots(const DItem *__restrict__ items, int64_t N, int nchunks, int64_t L,
+                                               double2 *__restrict__ part)
+{
+    const DItem it = items[blockIdx.y];
+    if (it.flag && *it.flag == 0) return;
+    const int t = threadIdx.x, v = t & 63, w = t >> 6;
+    const int64_t n0 = int64_t(blockIdx.x) * L, n1 = min(N, n0 + L);
+    __shared__ double2 As[DS][DT + 1];
+    __shared__ double2 Bs[BMAX][DS + 1];
+    __shared__ int64_t Aoff[DT];
+    if (t < DT) {
+        const int k = it.k0 + t;
+        Aoff[t] = t < it.kc ? (int64_t(k / it.ar) * it.astride + k % it.ar) * N : 0;
+    }
+    double2 acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] = make_double2(0.0, 0.0);
+    const AT *A = static_cast<const AT *>(it.A);
+    for (int64_t ns = n0; ns < n1; ns += DS) {
+        __syncthreads();
+        for (int e = t; e < DT * DS; e += 256) {
+            const int vv = e / DS, rr = e % DS;
+            const int64_t n = ns + rr;
+            As[rr][vv] = (vv < it.kc && n < n1) ? to_d2(A[Aoff[vv] + n]) : make_double2(0.0, 0.0);
+        }
+        for (int e = t; e < 4 * NQ * DS; e += 256) {
+            const int b = e / DS, rr = e % DS;
+            const int64_t n = ns + rr;
+            Bs[b][rr] = (b < it.nb && n < n1) ? it.Bm[int64_t(b) * N + n] : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int rr = 0; rr < DS; ++rr) {
+            const double2 av = As[rr][v];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const double2 bv = Bs[w + 4 * q][rr];
+                acc[q].x = fma(av.x, bv.x, fma(av.y, bv.y, acc[q].x));
+                acc[q].y = fma(av.x, bv.y, fma(-av.y, bv.x, acc[q].y));
+            }
+        }
+    }
+    if (v < it.kc) {
+        double2 *o = part + ((int64_t(blockIdx.y) * nchunks + blockIdx.x) * DT + v) * BMAX;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            if (w + 4 * q < it.nb) o[w + 4 * q] = acc[q];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bdots_fin(const DItem *__restrict__ items, int nchunks,
+                                                   const double2 *__restrict__ part)
+{
+    const DItem it = items[blockIdx.x];
+    if (it.flag && *it.flag == 0) return;
+    for (int e = threadIdx.x; e < it.kc * it.nb; e += 256) {
+        const int v = e / it.nb, b = e % it.nb;
+        double2 s = make_double2(0.0, 0.0);
+        for (int c = 0; c < nchunks; ++c) s = cadd(s, part[((int64_t(blockIdx.x) * nchunks + c) * DT + v) * BMAX + b]);
+        it.dst[int64_t(it.k0 + v) * it.ld + b] = s;
+    }
+}
+
+template <typename AT, typename OT, int NB>
+__global__ __launch_bounds__(256) void k_bcomb(const CItem *__restrict__ items, int64_t N)
+{
+    const CItem it = items[blockIdx.y];
+    if (it.flag && *it.flag == 0) return;
+    const int t = threadIdx.x;
+    const int64_t n = int64_t(blockIdx.x) * 256 + t;
+    __shared__ double2 Cs[64][NB];
+    __shared__ int64_t Aoff[64];
+    double2 acc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[b] = make_double2(0.0, 0.0);
+    const AT *A = static_cast<const AT *>(it.A);
+    for (int k0 = 0; k0 < it.K; k0 += 64) {
+        const int kc = min(64, it.K - k0);
+        __syncthreads();
+        for (int e = t; e < 64 * NB; e += 256) {
+            const int kk = e / NB, b = e % NB;
+            Cs[kk][b] = (kk < kc && b < it.nb) ? it.C[int64_t(k0 + kk) * it.ldc + b] : make_double2(0.0, 0.0);
+        }
+        if (t < 64) {
+            const int k = k0 + t;
+            Aoff[t] = t < kc ? (int64_t(k / it.ar) * it.astride + k % it.ar) * N : 0;
+        }
+        __syncthreads();
+        if (n < N) {
+            for (int kk = 0; kk < kc; ++kk) {
+                const double2 av = to_d2(A[Aoff[kk] + n]);
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    const double2 c = Cs[kk][b];
+                    acc[b].x = fma(av.x, c.x, fma(-av.y, c.y, acc[b].x));
+                    acc[b].y = fma(av.x, c.y, fma(av.y, c.x, acc[b].y));
+                }
+            }
+        }
+    }
+    if (n >= N) return;
+    OT *out = static_cast<OT *>(it.out);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        if (b < it.nb) {
+            const int64_t o = int64_t(it.ocol ? it.ocol[b] : b) * N + n;
+            double2 y = cscale(it.alpha, acc[b]);
+            if (it.beta != 0.0) y = cadd(y, cscale(it.beta, to_d2(out[o])));
+            out[o] = from_d2<OT>(y);
+        }
+    }
+}
+
+// dst[i * N + n] = src[cols[i] * N + n]
+__global__ __launch_bounds__(256) void k_bgather(int64_t N, const double2 *__restrict__ src, const int *__restrict__ cols,
+                                                 double2 *__restrict__ dst)
+{
+    const int i = blockIdx.y;
+    const double2 *a = src + int64_t(cols[i]) * N;
+    double2 *b = dst + int64_t(i) * N;
+    for (int64_t n = int64_t(blockIdx.x) * 256 + threadIdx.x; n < N; n += int64_t(gridDim.x) * 256) b[n] = a[n];
+}
+
+// squared norms of columns cols[i] of src, partial over row chunks, then summed
+// in a fixed order
+__global__ __launch_bounds__(256) void k_bnorm_part(int64_t N, const double2 *__restrict__ src,
+                                                    const int *__restrict__ cols, double *__restrict__ part)
+{
+    const int i = blockIdx.y;
+    const double2 *a = src + int64_t(cols[i]) * N;
+    double s = 0.0;
+    for (int64_t n = int64_t(blockIdx.x) * 256 + threadIdx.x; n < N; n += int64_t(gridDim.x) * 256)
+        s = fma(a[n].x, a[n].x, fma(a[n].y, a[n].y, s));
+    __shared__ double red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[int64_t(i) * gridDim.x + blockIdx.x] = red[0];
+}
+__global__ void k_bnorm_fin(int nparts, int count, const double *__restrict__ part, double *__restrict__ out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    double s = 0.0;
+    for (int c = 0; c < nparts; ++c) s += part[int64_t(i) * nparts + c];
+    out[i] = std::sqrt(s);
+}
+
+// Device state of one group (fixed regions sized for r, q <= BMAX and m steps).
+struct GDev {
+    double2 *C1, *C2;   // projection coefficients of the two passes, ((m+1) r) x r
+    double2 *G1, *G2;   // Gram matrices of W in the two passes, r x r
+    double2 *Rt;        // block column j at Rt + j * (m+1) r r: rows 0 .. (j+2) r of Hbar, reduced in place
+    double2 *U;         // Householder vectors of block column j: 2r x r at U + j * 2 r r
+    double2 *T;         // triangular factor of those reflectors (Q = I - U T U^H): r x r at T + j r r
+    double2 *Tinv;      // R^{-1} of the current step, r x r
+    double2 *Gv;        // E_1 S with the reflectors applied, ((m+1) r) x q
+    double2 *Y;         // least-squares solution times the column scales, (m r) x q
+    double *est;        // per-column residual estimate (scaled units)
+    double *scale;      // per-column residual norm at the start of the cycle
+    int *flag;          // [0] second Gram-Schmidt pass needed, [1] partial breakdown
+    int r, q, steps, pad;
+};
+
+// Gram after the update (G - C^H C) decides whether a second pass runs.
+__global__ __launch_bounds__(64) void k_bflag(GDev *__restrict__ gd, const int *__restrict__ gids, int j)
+{
+    GDev g = gd[gids[blockIdx.x]];
+    const int r = g.r, K = (j + 1) * r, a = threadIdx.x;
+    __shared__ int need;
+    if (a == 0) need = 0;
+    __syncthreads();
+    if (a < r) {
+        double s = g.G1[a * r + a].x;
+        const double g0 = s;
+        for (int k = 0; k < K; ++k) {
+            const double2 c = g.C1[int64_t(k) * r + a];
+            s -= c.x * c.x + c.y * c.y;
+        }
+        if (s < 0.5 * g0) atomicOr(&need, 1);
+    }
+    __syncthreads();
+    if (a == 0) {
+        g.flag[0] = need;
+        g.flag[1] = 0;
+    }
+}
+
+// Assemble Hbar(:, j) = [C1 + C2; R] with R^H R = G'' (Cholesky of the Gram
+// after the passes), and R^{-1} for the next basis block.  A pivot at or below
+// delta^2 times the largest squared column norm of T V_j marks a partial
+// breakdown; that direction gets a zero row in R.
+__global__ __launch_bounds__(256) void k_bchol(GDev *__restrict__ gd, const int *__restrict__ gids, int j, int m,
+                                               double delta)
+{
+    GDev g = gd[gids[blockIdx.x]];
+    const int r = g.r, K = (j + 1) * r, t = threadIdx.x;
+    const bool two = g.flag[0] != 0;
+    __shared__ double2 Gs[BMAX][BMAX + 1];
+    __shared__ double2 L[BMAX][BMAX + 1];
+    __shared__ double2 Ti[BMAX][BMAX + 1];
+    __shared__ double gmax;
+    __shared__ int brk;
+    double2 *H = g.Rt + int64_t(j) * (m + 1) * r * r;   // ((m+1) r) x r, row-major
+    // H rows 0 .. K: the projection coefficients
+    for (int e = t; e < K * r; e += 256) {
+        double2 c = g.C1[e];
+        if (two) c = cadd(c, g.C2[e]);
+        H[e] = c;
+    }
+    // G'' = Gp - Cp^H Cp of the last pass
+    const double2 *Gp = two ? g.G2 : g.G1;
+    const double2 *Cp = two ? g.C2 : g.C1;
+    for (int e = t; e < r * r; e += 256) {
+        const int a = e / r, b = e % r;
+        double2 s = Gp[e];
+        for (int k = 0; k < K; ++k) s = csub(s, cmulc(Cp[int64_t(k) * r + a], Cp[int64_t(k) * r + b]));
+        Gs[a][b] = s;
+    }
+    if (t == 0) {
+        double mx = 0.0;
+        for (int a = 0; a < r; ++a) mx = fmax(mx, g.G1[a * r + a].x);
+        gmax = mx;
+        brk = 0;
+    }
+    for (int e = t; e < BMAX * (BMAX + 1); e += 256) {
+        (&L[0][0])[e] = make_double2(0.0, 0.0);
+        (&Ti[0][0])[e] = make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    // Cholesky, column by column (L lower, G'' = L L^H)
+    for (int k = 0; k < r; ++k) {
+        if (t == 0) {
+            double p = Gs[k][k].x;
+            for (int l = 0; l < k; ++l) p -= L[k][l].x * L[k][l].x + L[k][l].y * L[k][l].y;
+            if (!(p > delta * delta * gmax)) {
+                brk = 1;
+                L[k][k] = make_double2(0.0, 0.0);
+            } else {
+                L[k][k] = make_double2(std::sqrt(p), 0.0);
+            }
+        }
+        __syncthreads();
+        const double d = L[k][k].x;
+        if (t > k && t < r) {
+            double2 s = Gs[t][k];
+            for (int l = 0; l < k; ++l) s = csub(s, cmul(L[t][l], make_double2(L[k][l].x, -L[k][l].y)));
+            L[t][k] = d > 0.0 ? cscale(1.0 / d, s) : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+    }
+    // R = L^H into rows K .. K + r of H; Ti = R^{-1} (upper), zero for broken pivots
+    for (int e = t; e < r * r; e += 256) {
+        const int a = e / r, b = e % r;
+        const double2 v = b >= a ? make_double2(L[b][a].x, -L[b][a].y) : make_double2(0.0, 0.0);
+        H[int64_t(K + a) * r + b] = v;
+    }
+    // columns of R^{-1}: R Ti(:, b) = e_b, back substitution per column (thread b)
+    if (t < r) {
+        const int b = t;
+        for (int a = b; a >= 0; --a) {
+            const double raa = L[a][a].x;
+            double2 s = a == b ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0);
+            for (int c = a + 1; c <= b; ++c) s = csub(s, cmul(make_double2(L[c][a].x, -L[c][a].y), Ti[c][b]));
+            Ti[a][b] = raa > 0.0 ? cscale(1.0 / raa, s) : make_double2(0.0, 0.0);
+        }
+    }
+    __syncthreads();
+    for (int e = t; e < r * r; e += 256) g.Tinv[e] = Ti[e / r][e % r];
+    if (t == 0) g.flag[1] = brk;
+}
+
+// Apply Q^H = I - U T^H U^H (U: 2r x r, T: r x r upper) to X (2r x nc) in LDS.
+// All 256 threads take part; W1, W2 are r x nc scratch.
+__device__ void wy_apply(double2 (*X)[BMAX + 1], double2 (*Us)[BMAX + 1], double2 (*Ts)[BMAX + 1],
+                         double2 (*W1)[BMAX + 1], double2 (*W2)[BMAX + 1], int r, int nc)
+{
+    const int t = threadIdx.x;
+    for (int e = t; e < r * nc; e += 256) {   // W1 = U^H X
+        const int a = e / nc, c = e % nc;
+        double2 s = make_double2(0.0, 0.0);
+        for (int i = a; i < 2 * r; ++i) s = cadd(s, cmulc(Us[i][a], X[i][c]));
+        W1[a][c] = s;
+    }
+    __syncthreads();
+    for (int e = t; e < r * nc; e += 256) {   // W2 = T^H W1
+        const int a = e / nc, c = e % nc;
+        double2 s = make_double2(0.0, 0.0);
+        for (int b = 0; b <= a; ++b) s = cadd(s, cmulc(Ts[b][a], W1[b][c]));
+        W2[a][c] = s;
+    }
+    __syncthreads();
+    for (int e = t; e < 2 * r * nc; e += 256) {   // X -= U W2
+        const int i = e / nc, c = e % nc;
+        double2 s = X[i][c];
+        const int amax = min(i, r - 1);
+        for (int a = 0; a <= amax; ++a) s = csub(s, cmul(Us[i][a], W2[a][c]));
+        X[i][c] = s;
+    }
+    __syncthreads();
+}
+
+// One step of the QR factorisation of Hbar: the reflectors of block columns
+// 0 .. j-1 applied to the new block column, new reflectors for its rows
+// jr .. jr + 2r, the same applied to E_1 S, and the residual estimates.
+__global__ __launch_bounds__(256) void k_bls_step(GDev *__restrict__ gd, const int *__restrict__ gids, int j, int m)
+{
+    GDev g = gd[gids[blockIdx.x]];
+    const int r = g.r, q = g.q, t = threadIdx.x;
+    __shared__ double2 X[2 * BMAX][BMAX + 1];
+    __shared__ double2 Us[2 * BMAX][BMAX + 1];
+    __shared__ double2 Ts[BMAX][BMAX + 1];
+    __shared__ double2 W1[BMAX][BMAX + 1];
+    __shared__ double2 W2[BMAX][BMAX + 1];
+    __shared__ double2 alpha_s;
+    __shared__ double beta_s;
+    double2 *H = g.Rt + int64_t(j) * (m + 1) * r * r;
+    for (int i = 0; i < j; ++i) {
+        const double2 *Ui = g.U + int64_t(i) * 2 * r * r, *Ti = g.T + int64_t(i) * r * r;
+        for (int e = t; e < 2 * r * r; e += 256) {
+            X[e / r][e % r] = H[int64_t(i) * r * r + e];
+            Us[e / r][e % r] = Ui[e];
+        }
+        for (int e = t; e < r * r; e += 256) Ts[e / r][e % r] = Ti[e];
+        __syncthreads();
+        wy_apply(X, Us, Ts, W1, W2, r, r);
+        for (int e = t; e < 2 * r * r; e += 256) H[int64_t(i) * r * r + e] = X[e / r][e % r];
+        __syncthreads();
+    }
+    // Householder QR of rows jr .. jr + 2r
+    for (int e = t; e < 2 * r * r; e += 256) {
+        X[e / r][e % r] = H[int64_t(j) * r * r + e];
+        Us[e / r][e % r] = make_double2(0.0, 0.0);
+    }
+    for (int e = t; e < r * r; e += 256) Ts[e / r][e % r] = make_double2(0.0, 0.0);
+    __syncthreads();
+    for (int k = 0; k < r; ++k) {
+        if (t < 64) {   // one wave: the reflector of column k
+            double s = 0.0;
+            for (int i = k + t; i < 2 * r; i += 64) s += X[i][k].x * X[i][k].x + X[i][k].y * X[i][k].y;
+            for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+            const double nx = std::sqrt(s);
+            const double2 x0 = X[k][k];
+            const double ax0 = std::sqrt(x0.x * x0.x + x0.y * x0.y);
+            const double2 ph = ax0 > 0.0 ? make_double2(x0.x / ax0, x0.y / ax0) : make_double2(1.0, 0.0);
+            const double2 al = make_double2(-ph.x * nx, -ph.y * nx);
+            // v = x - alpha e_1; |v|^2 = |x|^2 - 2 Re(conj(alpha) x0) + |alpha|^2 = 2 nx (nx + |x0|)
+            const double vv = 2.0 * nx * (nx + ax0);
+            for (int i = k + t; i < 2 * r; i += 64) Us[i][k] = i == k ? csub(X[k][k], al) : X[i][k];
+            if (t == 0) {
+                alpha_s = al;
+                beta_s = vv > 0.0 ? 2.0 / vv : 0.0;
+                Ts[k][k] = make_double2(vv > 0.0 ? 2.0 / vv : 0.0, 0.0);
+            }
+        }
+        __syncthreads();
+        const double beta = beta_s;
+        // apply to columns k+1 .. r-1: x -= beta v (v^H x), one column per thread group of 8
+        for (int c = k + 1 + (t >> 3); c < r; c += 32) {
+            const int l = t & 7;
+            double2 s = make_double2(0.0, 0.0);
+            for (int i = k + l; i < 2 * r; i += 8) s = cadd(s, cmulc(Us[i][k], X[i][c]));
+            for (int o = 4; o > 0; o >>= 1) {
+                s.x += __shfl_xor(s.x, o, 8);
+                s.y += __shfl_xor(s.y, o, 8);
+            }
+            for (int i = k + l; i < 2 * r; i += 8) X[i][c] = csub(X[i][c], cscale(beta, cmul(Us[i][k], s)));
+        }
+        __syncthreads();
+        if (t == 0) X[k][k] = alpha_s;
+        for (int i = k + 1 + t; i < 2 * r; i += 256) X[i][k] = make_double2(0.0, 0.0);
+        __syncthreads();
+    }
+    // T of the new reflectors: T(0:k, k) = -beta_k T(0:k, 0:k) (U(:, 0:k)^H u_k)
+    for (int e = t; e < r * r; e += 256) {   // W1 = U^H U (upper part used)
+        const int a = e / r, b = e % r;
+        double2 s = make_double2(0.0, 0.0);
+        if (a < b)
+            for (int i = b; i < 2 * r; ++i) s = cadd(s, cmulc(Us[i][a], Us[i][b]));
+        W1[a][b] = s;
+    }
+    __syncthreads();
+    for (int k = 1; k < r; ++k) {
+        if (t < k) {
+            double2 s = make_double2(0.0, 0.0);
+            for (int l = t; l < k; ++l) s = cadd(s, cmul(Ts[t][l], W1[l][k]));
+            W2[t][0] = cscale(-Ts[k][k].x, s);
+        }
+        __syncthreads();
+        if (t < k) Ts[t][k] = W2[t][0];
+        __syncthreads();
+    }
+    double2 *Uj = g.U + int64_t(j) * 2 * r * r, *Tj = g.T + int64_t(j) * r * r;
+    for (int e = t; e < 2 * r * r; e += 256) {
+        H[int64_t(j) * r * r + e] = X[e / r][e % r];
+        Uj[e] = Us[e / r][e % r];
+    }
+    for (int e = t; e < r * r; e += 256) Tj[e] = Ts[e / r][e % r];
+    __syncthreads();
+    // E_1 S rows jr .. jr + 2r, q columns
+    for (int e = t; e < 2 * r * q; e += 256) X[e / q][e % q] = g.Gv[int64_t(j) * r * q + e];
+    __syncthreads();
+    wy_apply(X, Us, Ts, W1, W2, r, q);
+    for (int e = t; e < 2 * r * q; e += 256) g.Gv[int64_t(j) * r * q + e] = X[e / q][e % q];
+    if (t < q) {
+        double s = 0.0;
+        for (int i = r; i < 2 * r; ++i) s += X[i][t].x * X[i][t].x + X[i][t].y * X[i][t].y;
+        g.est[t] = std::sqrt(s);
+    }
+}
+
+// Y = R^{-1} Gv(0 : J r, :) by block back substitution (R upper triangular,
+// block column b of R at Rt + b (m+1) r r), scaled by the column norms.
+__global__ __launch_bounds__(256) void k_bls_solve(GDev *__restrict__ gd, const int *__restrict__ gids, int m)
+{
+    GDev g = gd[gids[blockIdx.x]];
+    const int r = g.r, q = g.q, J = g.steps, t = threadIdx.x;
+    const int64_t bs = int64_t(m + 1) * r * r;
+    __shared__ double2 S[BMAX][BMAX + 1];
+    auto Rel = [&](int row, int col) { return g.Rt[(col / r) * bs + int64_t(row) * r + col % r]; };
+    for (int I = J - 1; I >= 0; --I) {
+        for (int e = t; e < r * q; e += 256) {
+            const int a = e / q, c = e % q, row = I * r + a;
+            double2 s = g.Gv[int64_t(row) * q + c];
+            for (int sg = (I + 1) * r; sg < J * r; ++sg) s = csub(s, cmul(Rel(row, sg), g.Y[int64_t(sg) * q + c]));
+            S[a][c] = s;
+        }
+        __syncthreads();
+        if (t < q) {
+            for (int a = r - 1; a >= 0; --a) {
+                const int row = I * r + a;
+                double2 s = S[a][t];
+                for (int b = a + 1; b < r; ++b) s = csub(s, cmul(Rel(row, I * r + b), S[b][t]));
+                const double2 d = Rel(row, row);
+                const double dd = d.x * d.x + d.y * d.y;
+                S[a][t] = dd > 0.0 ? make_double2((s.x * d.x + s.y * d.y) / dd, (s.y * d.x - s.x * d.y) / dd)
+                                   : make_double2(0.0, 0.0);
+            }
+        }
+        __syncthreads();
+        for (int e = t; e < r * q; e += 256) g.Y[int64_t(I * r + e / q) * q + e % q] = S[e / q][e % q];
+        __syncthreads();
+    }
+    for (int e = t; e < J * r * q; e += 256) g.Y[e] = cscale(g.scale[e % q], g.Y[e]);
+}
+
+__global__ void k_bzero(int64_t n, double2 *__restrict__ a)
+{
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256)
+        a[i] = make_double2(0.0, 0.0);
+}
+
+using cd = std::complex<double>;
+
+// Device allocations released at scope exit.
+struct Bufs {
+    std::vector<void *> all;
+    template <typename T>
+    T *get(size_t n)
+    {
+        void *p = nullptr;
+        BIE_HIP(hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T)));
+        all.push_back(p);
+        return static_cast<T *>(p);
+    }
+    ~Bufs()
+    {
+        for (void *p : all) (void)hipFree(p);
+    }
+};
+
+// Small per-launch tables: staged in pinned host memory and copied to a device
+// mirror on the stream.  Space is reused only after a stream synchronisation,
+// when every copy and every kernel reading the tables has finished.
+struct Arena {
+    char *h = nullptr, *d = nullptr;
+    size_t cap = 0, used = 0;
+    explicit Arena(size_t n) : cap(n)
+    {
+        BIE_HIP(hipHostMalloc(reinterpret_cast<void **>(&h), n));
+        BIE_HIP(hipMalloc(reinterpret_cast<void **>(&d), n));
+    }
+    ~Arena()
+    {
+        if (h) (void)hipHostFree(h);
+        if (d) (void)hipFree(d);
+    }
+    size_t stage(const void *src, size_t bytes)
+    {
+        const size_t off = (used + 255) & ~size_t(255);
+        if (off + bytes > cap) throw Error(BIE_ENOMEM, "block GMRES: table space exhausted");
+        std::memcpy(h + off, src, bytes);
+        used = off + bytes;
+        return off;
+    }
+    template <typename T>
+    T *put(const std::vector<T> &v, hipStream_t s)
+    {
+        const size_t off = stage(v.data(), v.size() * sizeof(T));
+        BIE_HIP(hipMemcpyAsync(d + off, h + off, v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+        return reinterpret_cast<T *>(d + off);
+    }
+    template <typename T>
+    void copy_to(T *dst, const T *src, size_t count, hipStream_t s)
+    {
+        const size_t off = stage(src, count * sizeof(T));
+        BIE_HIP(hipMemcpyAsync(dst, h + off, count * sizeof(T), hipMemcpyHostToDevice, s));
+    }
+    void reset() { used = 0; }
+};
+
+struct HGroup {
+    std::vector<int> rhs;          // chunk-local right-hand sides of the columns
+    std::vector<double> scale, target;
+    int q = 0, r = 0, c0 = 0, qoff = 0, cap = 0, steps = 0;
+    bool active = false;
+};
+
+int pick_nb(int n) { return n <= 4 ? 4 : n <= 8 ? 8 : n <= 16 ? 16 : 32; }
+
+template <typename AT>
+void launch_dots(const std::vector<DItem> &items, Arena &ar, int64_t N, double2 *part, int nbmax, hipStream_t s)
+{
+    if (items.empty()) return;
+    const int64_t ni = int64_t(items.size());
+    const int64_t nch = std::max<int64_t>(1, std::min<int64_t>((1024 + ni - 1) / ni, (N + 127) / 128));
+    const int64_t L = ((N + nch - 1) / nch + DS - 1) / DS * DS;
+    const int nchunks = int((N + L - 1) / L);
+    const DItem *d = ar.put(items, s);
+    const dim3 grid{ unsigned(nchunks), unsigned(ni) };
+    const int nq = (nbmax + 3) / 4;
+    if (nq <= 1) hipLaunchKernelGGL((k_bdots<AT, 1>), grid, dim3(256), 0, s, d, N, nchunks, L, part);
+    else if (nq <= 2) hipLaunchKernelGGL((k_bdots<AT, 2>), grid, dim3(256), 0, s, d, N, nchunks, L, part);
+    else if (nq <= 4) hipLaunchKernelGGL((k_bdots<AT, 4>), grid, dim3(256), 0, s, d, N, nchunks, L, part);
+    else hipLaunchKernelGGL((k_bdots<AT, 8>), grid, dim3(256), 0, s, d, N, nchunks, L, part);
+    hipLaunchKernelGGL(k_bdots_fin, dim3(unsigned(ni)), dim3(256), 0, s, d, nchunks, (const double2 *)part);
+    BIE_HIP(hipGetLastError());
+}
+
+template <typename AT, typename OT>
+void launch_comb(const std::vector<CItem> &items, Arena &ar, int64_t N, int nbmax, hipStream_t s)
+{
+    if (items.empty()) return;
+    const CItem *d = ar.put(items, s);
+    const dim3 grid(unsigned((N + 255) / 256), unsigned(items.size()));
+    switch (pick_nb(nbmax)) {
+    case 4: hipLaunchKernelGGL((k_bcomb<AT, OT, 4>), grid, dim3(256), 0, s, d, N); break;
+    case 8: hipLaunchKernelGGL((k_bcomb<AT, OT, 8>), grid, dim3(256), 0, s, d, N); break;
+    case 16: hipLaunchKernelGGL((k_bcomb<AT, OT, 16>), grid, dim3(256), 0, s, d, N); break;
+    default: hipLaunchKernelGGL((k_bcomb<AT, OT, 32>), grid, dim3(256), 0, s, d, N); break;
+    }
+    BIE_HIP(hipGetLastError());
+}
+
+// Rank-revealing orthonormalisation of the unit-scaled residual block from its
+// Gram matrix G (q x q, row-major): pivoted Cholesky P^T Gs P = L L^H stopped at
+// pivots <= delta^2.  Returns r; T0 (q x r) maps the unscaled residual columns
+// to V_0, S (r x q) gives the scaled residuals as V_0 S.
+int rank_revealing(const std::vector<cd> &G, int q, const std::vector<double> &scale, std::vector<cd> &T0,
+                   std::vector<cd> &S)
+{
+    std::vector<cd> A(size_t(q) * q), L(size_t(q) * q, cd(0.0));
+    for (int a = 0; a < q; ++a)
+        for (int b = 0; b < q; ++b) A[a * q + b] = G[a * q + b] / (scale[a] * scale[b]);
+    std::vector<int> perm(q);
+    for (int i = 0; i < q; ++i) perm[i] = i;
+    int r = 0;
+    for (int k = 0; k < q; ++k) {
+        int p = k;
+        for (int i = k + 1; i < q; ++i)
+            if (A[i * q + i].real() > A[p * q + p].real()) p = i;
+        if (!(A[p * q + p].real() > DELTA * DELTA)) break;
+        if (p != k) {
+            for (int i = 0; i < q; ++i) std::swap(A[k * q + i], A[p * q + i]);
+            for (int i = 0; i < q; ++i) std::swap(A[i * q + k], A[i * q + p]);
+            for (int i = 0; i < k; ++i) std::swap(L[k * q + i], L[p * q + i]);
+            std::swap(perm[k], perm[p]);
+        }
+        const double d = std::sqrt(A[k * q + k].real());
+        L[k * q + k] = d;
+        for (int i = k + 1; i < q; ++i) L[i * q + k] = A[i * q + k] / d;
+        for (int i = k + 1; i < q; ++i)
+            for (int l = k + 1; l < q; ++l) A[i * q + l] -= L[i * q + k] * std::conj(L[l * q + k]);
+        r = k + 1;
+    }
+    // Li = L11^{-1} (lower), V_0 = R0s(:, perm[0..r)) Li^H
+    std::vector<cd> Li(size_t(r) * r, cd(0.0));
+    for (int c = 0; c < r; ++c) {
+        Li[c * r + c] = 1.0 / L[c * q + c];
+        for (int i = c + 1; i < r; ++i) {
+            cd s = 0.0;
+            for (int l = c; l < i; ++l) s += L[i * q + l] * Li[l * r + c];
+            Li[i * r + c] = -s / L[i * q + i];
+        }
+    }
+    T0.assign(size_t(q) * r, cd(0.0));
+    for (int i = 0; i < r; ++i)
+        for (int c = 0; c < r; ++c) T0[perm[i] * r + c] = std::conj(Li[c * r + i]) / scale[perm[i]];
+    S.assign(size_t(r) * q, cd(0.0));
+    for (int i = 0; i < q; ++i)
+        for (int a = 0; a < std::min(r, i + 1); ++a) S[a * q + perm[i]] = std::conj(L[i * q + a]);
+    return r;
+}
+
+template <typename VT>
+int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_solve_opts &o, bie_solve_stat *hs,
+                hipStream_t s)
+{
+    const int64_t N = op->mesh.N;
+    const int m = o.restart;
+    const int p = o.block > 0 ? o.block : 32;
+    const bool mixed = o.precision == 1;
+    const int terms = o.inner_terms ? o.inner_terms : 3;
+    const double itol = std::max(o.inner_tol > 0.0 ? o.inner_tol : 1e-3, terms == 2 ? 1e-2 : 0.0);
+    const int64_t Gmax = (R + p - 1) / p;
+
+    Bufs db;
+    double2 *Rres = db.get<double2>(size_t(R) * N);
+    double2 *Wb = db.get<double2>(size_t(R) * N);
+    VT *V = db.get<VT>(size_t(m + 1) * R * N);
+    const int64_t tiles = ((m + 1) * p + DT - 1) / DT + 1;
+    double2 *part = db.get<double2>(size_t(Gmax * tiles + 1024) * DT * BMAX);
+    const int nparts = int(std::min<int64_t>(64, (N + 255) / 256));
+    double *npart = db.get<double>(size_t(R) * nparts);
+    double *nrm = db.get<double>(size_t(R));
+    // group regions
+    const size_t p2 = size_t(p) * p;
+    const size_t per = 2 * (m + 1) * p2 + 2 * p2 + size_t(m) * (m + 1) * p2 + 2 * size_t(m) * p2 + size_t(m) * p2 + p2 +
+                       (m + 1) * p2 + size_t(m) * p2;
+    double2 *greg = db.get<double2>(per * Gmax);
+    double *gest = db.get<double>(size_t(Gmax) * BMAX);
+    double *gscale = db.get<double>(size_t(Gmax) * BMAX);
+    int *gflag = db.get<int>(size_t(Gmax) * 2);
+    GDev *gd = db.get<GDev>(size_t(Gmax));
+    std::vector<GDev> hg(Gmax);
+    for (int64_t g = 0; g < Gmax; ++g) {
+        double2 *b = greg + per * g;
+        GDev &d = hg[g];
+        d.C1 = b; b += (m + 1) * p2;
+        d.C2 = b; b += (m + 1) * p2;
+        d.G1 = b; b += p2;
+        d.G2 = b; b += p2;
+        d.Rt = b; b += size_t(m) * (m + 1) * p2;
+        d.U = b; b += 2 * size_t(m) * p2;
+        d.T = b; b += size_t(m) * p2;
+        d.Tinv = b; b += p2;
+        d.Gv = b; b += (m + 1) * p2;
+        d.Y = b;
+        d.est = gest + g * BMAX;
+        d.scale = gscale + g * BMAX;
+        d.flag = gflag + 2 * g;
+    }
+    Arena ar(size_t(8) << 20);
+    auto sync = [&]() {
+        BIE_HIP(hipStreamSynchronize(s));
+        ar.reset();
+    };
+    auto norms = [&](const double2 *src, const std::vector<int> &cols, std::vector<double> &out) {
+        const int *dc = ar.put(cols, s);
+        hipLaunchKernelGGL(k_bnorm_part, dim3(unsigned(nparts), unsigned(cols.size())), dim3(256), 0, s, N, src, dc,
+                           npart);
+        hipLaunchKernelGGL(k_bnorm_fin, dim3(unsigned((cols.size() + 63) / 64)), dim3(64), 0, s, nparts,
+                           int(cols.size()), (const double *)npart, nrm);
+        BIE_HIP(hipGetLastError());
+        out.resize(cols.size());
+        BIE_HIP(hipMemcpyAsync(out.data(), nrm, cols.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        sync();
+    };
+
+    std::vector<int> all(R);
+    for (int64_t i = 0; i < R; ++i) all[i] = int(i);
+    std::vector<double> bn;
+    norms(B, all, bn);
+    for (int64_t i = 0; i < R; ++i) hs[i] = bie_solve_stat{ 0, 0, NAN, NAN, 0, 0, o.use_x0 ? 1 : 0 };
+    if (!o.use_x0) BIE_HIP(hipMemsetAsync(X, 0, size_t(R) * N * sizeof(double2), s));
+    std::vector<int> live;
+    for (int64_t i = 0; i < R; ++i) {
+        if (bn[i] == 0.0) {
+            BIE_HIP(hipMemsetAsync(X + i * N, 0, N * sizeof(double2), s));
+            hs[i].converged = 1;
+            hs[i].relres_est = hs[i].relres_true = 0.0;
+        } else {
+            live.push_back(int(i));
+        }
+    }
+    bool first = true;
+    std::vector<double> rn;
+    std::vector<HGroup> grp;
+    while (!live.empty()) {
+        // (1) FP64 residuals and the standard criterion
+        if (first && !o.use_x0) {
+            BIE_HIP(hipMemcpyAsync(Rres, B, size_t(R) * N * sizeof(double2), hipMemcpyDeviceToDevice, s));
+        } else {
+            const int *dl = ar.put(live, s);
+            gemm64_product(op, X, N, Rres, N, B, N, int64_t(live.size()), dl, s);
+        }
+        norms(Rres, live, rn);
+        std::vector<int> keep;
+        std::vector<double> krn;
+        for (size_t a = 0; a < live.size(); ++a) {
+            const int i = live[a];
+            bie_solve_stat &st = hs[i];
+            if (!(first && !o.use_x0)) st.mvps += 1;
+            st.checks += 1;
+            double rel = rn[a] / bn[i];
+            if (first && o.use_x0 == 2 && !(rel < 1.0)) {   // a guess no better than zero is replaced by zero
+                st.x0_kept = 0;
+                BIE_HIP(hipMemsetAsync(X + int64_t(i) * N, 0, N * sizeof(double2), s));
+                BIE_HIP(hipMemcpyAsync(Rres + int64_t(i) * N, B + int64_t(i) * N, N * sizeof(double2),
+                                       hipMemcpyDeviceToDevice, s));
+                rn[a] = bn[i];
+                rel = 1.0;
+            }
+            st.relres_true = rel;
+            if (rel <= o.tol) st.converged = 1;
+            else if (st.mvps < o.max_mvp) {
+                keep.push_back(i);
+                krn.push_back(rn[a]);
+            }
+        }
+        first = false;
+        live = keep;
+        if (live.empty()) break;
+        // (2) groups of consecutive live right-hand sides; their residuals
+        // gathered into Wb, Gram matrices, rank-revealing start blocks
+        grp.clear();
+        for (size_t g0 = 0; g0 < live.size(); g0 += p) {
+            HGroup h;
+            h.q = int(std::min<size_t>(p, live.size() - g0));
+            h.qoff = int(g0);
+            h.rhs.assign(live.begin() + g0, live.begin() + g0 + h.q);
+            grp.push_back(h);
+        }
+        const int ng = int(grp.size());
+        {
+            const int *dl = ar.put(live, s);
+            hipLaunchKernelGGL(k_bgather, dim3(unsigned(std::min<int64_t>((N + 255) / 256, 64)), unsigned(live.size())),
+                               dim3(256), 0, s, N, (const double2 *)Rres, dl, Wb);
+            std::vector<DItem> it;
+            for (int g = 0; g < ng; ++g) {
+                const HGroup &h = grp[g];
+                it.push_back(DItem{ Wb + int64_t(h.qoff) * N, 0, Wb + int64_t(h.qoff) * N, hg[g].G1, nullptr, h.q, 0,
+                                    h.q, h.q, h.q, 0 });
+            }
+            launch_dots<double2>(it, ar, N, part, p, s);
+        }
+        std::vector<std::vector<cd>> hG(ng);
+        for (int g = 0; g < ng; ++g) {
+            hG[g].resize(size_t(grp[g].q) * grp[g].q);
+            BIE_HIP(hipMemcpyAsync(hG[g].data(), hg[g].G1, hG[g].size() * sizeof(double2), hipMemcpyDeviceToHost, s));
+        }
+        sync();
+        int Wc = 0;
+        std::vector<std::vector<cd>> T0(ng), S(ng);
+        for (int g = 0; g < ng; ++g) {
+            HGroup &h = grp[g];
+            h.scale.resize(h.q);
+            for (int a = 0; a < h.q; ++a) h.scale[a] = std::sqrt(std::max(hG[g][a * h.q + a].real(), 0.0));
+            h.r = rank_revealing(hG[g], h.q, h.scale, T0[g], S[g]);
+            h.c0 = Wc;
+            Wc += h.r;
+            h.target.resize(h.q);
+            int64_t used = 0;
+            for (int a = 0; a < h.q; ++a) {
+                h.target[a] = mixed ? itol : o.tol * bn[h.rhs[a]] / h.scale[a];
+                used = std::max<int64_t>(used, hs[h.rhs[a]].mvps);
+            }
+            h.cap = int(std::min<int64_t>(m, std::max<int64_t>(1, o.max_mvp - used)));
+            h.steps = 0;
+            h.active = true;
+            hg[g].r = h.r;
+            hg[g].q = h.q;
+            hg[g].steps = 0;
+        }
+        ar.copy_to(gd, hg.data(), size_t(ng), s);
+        {
+            std::vector<CItem> it;
+            for (int g = 0; g < ng; ++g) {
+                const HGroup &h = grp[g];
+                std::vector<double2> t0(T0[g].size());
+                for (size_t e = 0; e < t0.size(); ++e) t0[e] = make_double2(T0[g][e].real(), T0[g][e].imag());
+                const double2 *dT = ar.put(t0, s);
+                it.push_back(CItem{ Wb + int64_t(h.qoff) * N, 0, dT, V + int64_t(h.c0) * N, nullptr, nullptr, 1.0, 0.0,
+                                    h.q, h.q, h.r, h.r });
+                // E_1 S into Gv (rows 0 .. r), zeros below; column scales
+                hipLaunchKernelGGL(k_bzero, dim3(64), dim3(256), 0, s, int64_t(m + 1) * h.r * h.q, hg[g].Gv);
+                std::vector<double2> sv(S[g].size());
+                for (size_t e = 0; e < sv.size(); ++e) sv[e] = make_double2(S[g][e].real(), S[g][e].imag());
+                ar.copy_to(hg[g].Gv, sv.data(), sv.size(), s);
+                ar.copy_to(hg[g].scale, h.scale.data(), size_t(h.q), s);
+            }
+            launch_comb<double2, VT>(it, ar, N, p, s);
+        }
+        // (3) block Arnoldi steps; every active group advances together
+        for (int j = 0; j < m; ++j) {
+            std::vector<int> act, cols;
+            for (int g = 0; g < ng; ++g)
+                if (grp[g].active) {
+                    act.push_back(g);
+                    for (int a = 0; a < grp[g].r; ++a) cols.push_back(grp[g].c0 + a);
+                }
+            if (act.empty()) break;
+            const int na = int(act.size());
+            const int *dg = ar.put(act, s);
+            const int *dc = ar.put(cols, s);
+            const VT *Vj = V + int64_t(j) * Wc * N;
+            if (mixed) gemm_product(op, Vj, N, VEC_C64, Wb, N, nullptr, 0, int64_t(cols.size()), dc, s, terms);
+            else gemm64_product(op, Vj, N, Wb, N, nullptr, 0, int64_t(cols.size()), dc, s);
+            for (int pass = 0; pass < 2; ++pass) {
+                std::vector<DItem> dv, dw;   // basis dots (VT) and Gram matrices (FP64)
+                std::vector<CItem> ci;
+                for (int g : act) {
+                    const HGroup &h = grp[g];
+                    const int K = (j + 1) * h.r;
+                    const int *fl = pass ? hg[g].flag : nullptr;
+                    double2 *Cd = pass ? hg[g].C2 : hg[g].C1;
+                    double2 *Gd = pass ? hg[g].G2 : hg[g].G1;
+                    for (int k0 = 0; k0 < K; k0 += DT)
+                        dv.push_back(DItem{ V + int64_t(h.c0) * N, Wc, Wb + int64_t(h.c0) * N, Cd, fl, h.r, k0,
+                                            std::min(DT, K - k0), h.r, h.r, 0 });
+                    dw.push_back(DItem{ Wb + int64_t(h.c0) * N, 0, Wb + int64_t(h.c0) * N, Gd, fl, h.r, 0, h.r, h.r,
+                                        h.r, 0 });
+                    ci.push_back(CItem{ V + int64_t(h.c0) * N, Wc, Cd, Wb + int64_t(h.c0) * N, nullptr, fl, -1.0, 1.0,
+                                        h.r, K, h.r, h.r });
+                }
+                launch_dots<VT>(dv, ar, N, part, p, s);
+                launch_dots<double2>(dw, ar, N, part, p, s);
+                launch_comb<VT, double2>(ci, ar, N, p, s);
+                if (pass == 0) {
+                    hipLaunchKernelGGL(k_bflag, dim3(unsigned(na)), dim3(64), 0, s, gd, dg, j);
+                    BIE_HIP(hipGetLastError());
+                }
+            }
+            hipLaunchKernelGGL(k_bchol, dim3(unsigned(na)), dim3(256), 0, s, gd, dg, j, m, DELTA);
+            hipLaunchKernelGGL(k_bls_step, dim3(unsigned(na)), dim3(256), 0, s, gd, dg, j, m);
+            BIE_HIP(hipGetLastError());
+            {
+                std::vector<CItem> it;
+                for (int g : act) {
+                    const HGroup &h = grp[g];
+                    it.push_back(CItem{ Wb + int64_t(h.c0) * N, 0, hg[g].Tinv, V + (int64_t(j + 1) * Wc + h.c0) * N,
+                                        nullptr, nullptr, 1.0, 0.0, h.r, h.r, h.r, h.r });
+                }
+                launch_comb<double2, VT>(it, ar, N, p, s);
+            }
+            std::vector<double> est(size_t(ng) * BMAX);
+            std::vector<int> fl(size_t(ng) * 2);
+            BIE_HIP(hipMemcpyAsync(est.data(), gest, est.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+            BIE_HIP(hipMemcpyAsync(fl.data(), gflag, fl.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+            sync();
+            std::vector<int> ended;
+            for (int g : act) {
+                HGroup &h = grp[g];
+                h.steps = j + 1;
+                bool met = true;
+                for (int a = 0; a < h.q; ++a) {
+                    const double e = est[size_t(g) * BMAX + a];
+                    bie_solve_stat &st = hs[h.rhs[a]];
+                    st.iters += 1;
+                    st.mvps += 1;
+                    st.relres_est = e * h.scale[a] / bn[h.rhs[a]];
+                    if (!(e <= h.target[a])) met = false;
+                }
+                if (met || fl[2 * g + 1] || h.steps >= h.cap) {
+                    h.active = false;
+                    hg[g].steps = h.steps;
+                    ended.push_back(g);
+                }
+            }
+            if (!ended.empty()) {
+                ar.copy_to(gd, hg.data(), size_t(ng), s);
+                const int *de = ar.put(ended, s);
+                hipLaunchKernelGGL(k_bls_solve, dim3(unsigned(ended.size())), dim3(256), 0, s, gd, de, m);
+                BIE_HIP(hipGetLastError());
+                std::vector<CItem> it;
+                for (int g : ended) {
+                    const HGroup &h = grp[g];
+                    const int *oc = ar.put(h.rhs, s);
+                    it.push_back(CItem{ V + int64_t(h.c0) * N, Wc, hg[g].Y, X, oc, nullptr, 1.0, 1.0, h.r,
+                                        h.steps * h.r, h.q, h.q });
+                }
+                launch_comb<VT, double2>(it, ar, N, p, s);
+            }
+        }
+    }
+    sync();
+    int status = BIE_OK;
+    for (int64_t i = 0; i < R; ++i)
+        if (!hs[i].converged) status = BIE_NOT_CONVERGED;
+    return status;
+}
+
+}  // namespace
+
+// Block GMRES for R right-hand sides, in consecutive chunks of `slots` (all R
+// when 0), each chunk solved to the end before the next.
+int solve_block(const bie_op *opc, const void *Bv, void *Xv, int64_t R, const bie_solve_opts &o,
+                bie_solve_stat *stats, hipStream_t s)
+{
+    bie_op *op = const_cast<bie_op *>(opc);
+    const int64_t N = op->mesh.N;
+    const int64_t W = o.slots > 0 ? std::min<int64_t>(o.slots, R) : R;
+    const double2 *B = static_cast<const double2 *>(Bv);
+    double2 *X = static_cast<double2 *>(Xv);
+    std::vector<bie_solve_stat> hs(R);
+    int status = BIE_OK;
+    for (int64_t c0 = 0; c0 < R; c0 += W) {
+        const int64_t n = std::min(W, R - c0);
+        const int rc = o.precision == 1 ? solve_chunk<float2>(op, B + c0 * N, X + c0 * N, n, o, hs.data() + c0, s)
+                                        : solve_chunk<double2>(op, B + c0 * N, X + c0 * N, n, o, hs.data() + c0, s);
+        if (rc != BIE_OK) status = rc;
+    }
+    if (stats)
+        for (int64_t i = 0; i < R; ++i) stats[i] = hs[i];
+    return status;
+}
+
+}  // namespace bie

@@ -225,5 +225,8 @@ int batch_unit_chosen(const bie_op *const *ops, int64_t P, const int64_t *R);
 int solve(const bie_op *op, const void *B, void *X, int64_t R, const bie_solve_opts &o,
           bie_solve_stat *stats, hipStream_t s);
 void free_workspace(bie_op *op);
+// bgmres.hip
+int solve_block(const bie_op *op, const void *B, void *X, int64_t R, const bie_solve_opts &o,
+                bie_solve_stat *stats, hipStream_t s);
 
 }  // namespace bie
