@@ -35,6 +35,7 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <memory>
 #include <vector>
 
 namespace bie {
@@ -89,14 +90,16 @@ struct CItem {
 };
 
 // Partial dots over a chunk of L rows; part[((item * nchunks + chunk) * DT + v) * BMAX + b].
-// Thread (v = t % 64, wave w): basis vector v of the tile against columns w, w + 4, ...
+// Thread (v = t % 32, wave-half h = t / 32): basis vectors v and v + 32 of the
+// tile against columns h, h + 8, h + 16, h + 24 (those below 4 NQ).
 template <typename AT, int NQ>
 __global__ __launch_bounds__(256) void k_bdots(const DItem *__restrict__ items, int64_t N, int nchunks, int64_t L,
                                                double2 *__restrict__ part)
 {
+    constexpr int NC = (NQ + 1) / 2;   // columns per thread: 4 NQ columns over 8 thread groups
     const DItem it = items[blockIdx.y];
     if (it.flag && *it.flag == 0) return;
-    const int t = threadIdx.x, v = t & 63, w = t >> 6;
+    const int t = threadIdx.x, v = t & 31, h = t >> 5;
     const int64_t n0 = int64_t(blockIdx.x) * L, n1 = min(N, n0 + L);
     __shared__ double2 As[DS][DT + 1];
     __shared__ double2 Bs[BMAX][DS + 1];
@@ -105,9 +108,9 @@ __global__ __launch_bounds__(256) void k_bdots(const DItem *__restrict__ items, 
         const int k = it.k0 + t;
         Aoff[t] = t < it.kc ? (int64_t(k / it.ar) * it.astride + k % it.ar) * N : 0;
     }
-    double2 acc[NQ];
+    double2 acc0[NC], acc1[NC];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) acc[q] = make_double2(0.0, 0.0);
+    for (int q = 0; q < NC; ++q) acc0[q] = acc1[q] = make_double2(0.0, 0.0);
     const AT *A = static_cast<const AT *>(it.A);
     for (int64_t ns = n0; ns < n1; ns += DS) {
         __syncthreads();
@@ -116,90 +119,120 @@ __global__ __launch_bounds__(256) void k_bdots(const DItem *__restrict__ items, 
             const int64_t n = ns + rr;
             As[rr][vv] = (vv < it.kc && n < n1) ? to_d2(A[Aoff[vv] + n]) : make_double2(0.0, 0.0);
         }
-        for (int e = t; e < 4 * NQ * DS; e += 256) {
+        for (int e = t; e < 8 * NC * DS; e += 256) {
             const int b = e / DS, rr = e % DS;
             const int64_t n = ns + rr;
             Bs[b][rr] = (b < it.nb && n < n1) ? it.Bm[int64_t(b) * N + n] : make_double2(0.0, 0.0);
         }
         __syncthreads();
-#pragma unroll 4
+#pragma unroll 2
         for (int rr = 0; rr < DS; ++rr) {
-            const double2 av = As[rr][v];
+            const double2 a0 = As[rr][v], a1 = As[rr][v + 32];
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                const double2 bv = Bs[w + 4 * q][rr];
-                acc[q].x = fma(av.x, bv.x, fma(av.y, bv.y, acc[q].x));
-                acc[q].y = fma(av.x, bv.y, fma(-av.y, bv.x, acc[q].y));
+            for (int q = 0; q < NC; ++q) {
+                const double2 bv = Bs[h + 8 * q][rr];
+                acc0[q].x = fma(a0.x, bv.x, fma(a0.y, bv.y, acc0[q].x));
+                acc0[q].y = fma(a0.x, bv.y, fma(-a0.y, bv.x, acc0[q].y));
+                acc1[q].x = fma(a1.x, bv.x, fma(a1.y, bv.y, acc1[q].x));
+                acc1[q].y = fma(a1.x, bv.y, fma(-a1.y, bv.x, acc1[q].y));
             }
         }
     }
-    if (v < it.kc) {
-        double2 *o = part + ((int64_t(blockIdx.y) * nchunks + blockIdx.x) * DT + v) * BMAX;
+    double2 *o = part + (int64_t(blockIdx.y) * nchunks + blockIdx.x) * DT * BMAX;
 #pragma unroll
-        for (int q = 0; q < NQ; ++q)
-            if (w + 4 * q < it.nb) o[w + 4 * q] = acc[q];
+    for (int q = 0; q < NC; ++q) {
+        const int b = h + 8 * q;
+        if (b < it.nb) {
+            if (v < it.kc) o[v * BMAX + b] = acc0[q];
+            if (v + 32 < it.kc) o[(v + 32) * BMAX + b] = acc1[q];
+        }
     }
 }
 
+// Sums the chunk partials in a fixed order: 4 lanes per output, chunks c = lane
+// mod 4, then a 4-lane reduction.
 __global__ __launch_bounds__(256) void k_bdots_fin(const DItem *__restrict__ items, int nchunks,
                                                    const double2 *__restrict__ part)
 {
     const DItem it = items[blockIdx.x];
     if (it.flag && *it.flag == 0) return;
-    for (int e = threadIdx.x; e < it.kc * it.nb; e += 256) {
-        const int v = e / it.nb, b = e % it.nb;
-        double2 s = make_double2(0.0, 0.0);
-        for (int c = 0; c < nchunks; ++c) s = cadd(s, part[((int64_t(blockIdx.x) * nchunks + c) * DT + v) * BMAX + b]);
-        it.dst[int64_t(it.k0 + v) * it.ld + b] = s;
+    const int e = blockIdx.y * 64 + (threadIdx.x >> 2), l = threadIdx.x & 3;
+    const bool live = e < it.kc * it.nb;
+    const int v = live ? e / it.nb : 0, b = live ? e % it.nb : 0;
+    double2 sv = make_double2(0.0, 0.0);
+    if (live)
+        for (int c = l; c < nchunks; c += 4) sv = cadd(sv, part[((int64_t(blockIdx.x) * nchunks + c) * DT + v) * BMAX + b]);
+    for (int o = 1; o < 4; o <<= 1) {
+        sv.x += __shfl_xor(sv.x, o, 4);
+        sv.y += __shfl_xor(sv.y, o, 4);
     }
+    if (live && l == 0) it.dst[int64_t(it.k0 + v) * it.ld + b] = sv;
 }
 
+// 64 rows per block; thread (rows v, v + 32 with v = t % 32, h = t / 32)
+// accumulates columns h, h + 8, ...; 32 basis vectors and their coefficient
+// rows staged in LDS per round.
 template <typename AT, typename OT, int NB>
 __global__ __launch_bounds__(256) void k_bcomb(const CItem *__restrict__ items, int64_t N)
 {
+    constexpr int NC = (NB + 7) / 8;
     const CItem it = items[blockIdx.y];
     if (it.flag && *it.flag == 0) return;
-    const int t = threadIdx.x;
-    const int64_t n = int64_t(blockIdx.x) * 256 + t;
-    __shared__ double2 Cs[64][NB];
-    __shared__ int64_t Aoff[64];
-    double2 acc[NB];
+    const int t = threadIdx.x, v = t & 31, h = t >> 5;
+    const int64_t n0 = int64_t(blockIdx.x) * 64;
+    __shared__ double2 As[32][65];
+    __shared__ double2 Cs[32][8 * NC];
+    __shared__ int64_t Aoff[32];
+    double2 acc0[NC], acc1[NC];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) acc[b] = make_double2(0.0, 0.0);
+    for (int q = 0; q < NC; ++q) acc0[q] = acc1[q] = make_double2(0.0, 0.0);
     const AT *A = static_cast<const AT *>(it.A);
-    for (int k0 = 0; k0 < it.K; k0 += 64) {
-        const int kc = min(64, it.K - k0);
+    for (int k0 = 0; k0 < it.K; k0 += 32) {
+        const int kc = min(32, it.K - k0);
         __syncthreads();
-        for (int e = t; e < 64 * NB; e += 256) {
-            const int kk = e / NB, b = e % NB;
-            Cs[kk][b] = (kk < kc && b < it.nb) ? it.C[int64_t(k0 + kk) * it.ldc + b] : make_double2(0.0, 0.0);
-        }
-        if (t < 64) {
+        if (t < 32) {
             const int k = k0 + t;
             Aoff[t] = t < kc ? (int64_t(k / it.ar) * it.astride + k % it.ar) * N : 0;
         }
+        for (int e = t; e < 32 * 8 * NC; e += 256) {
+            const int kk = e / (8 * NC), b = e % (8 * NC);
+            Cs[kk][b] = (kk < kc && b < it.nb) ? it.C[int64_t(k0 + kk) * it.ldc + b] : make_double2(0.0, 0.0);
+        }
         __syncthreads();
-        if (n < N) {
-            for (int kk = 0; kk < kc; ++kk) {
-                const double2 av = to_d2(A[Aoff[kk] + n]);
+        for (int e = t; e < 32 * 64; e += 256) {
+            const int kk = e >> 6, rr = e & 63;
+            const int64_t nn = n0 + rr;
+            As[kk][rr] = (kk < kc && nn < N) ? to_d2(A[Aoff[kk] + nn]) : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int kk = 0; kk < kc; ++kk) {
+            const double2 a0 = As[kk][v], a1 = As[kk][v + 32];
 #pragma unroll
-                for (int b = 0; b < NB; ++b) {
-                    const double2 c = Cs[kk][b];
-                    acc[b].x = fma(av.x, c.x, fma(-av.y, c.y, acc[b].x));
-                    acc[b].y = fma(av.x, c.y, fma(av.y, c.x, acc[b].y));
-                }
+            for (int q = 0; q < NC; ++q) {
+                const double2 c = Cs[kk][h + 8 * q];
+                acc0[q].x = fma(a0.x, c.x, fma(-a0.y, c.y, acc0[q].x));
+                acc0[q].y = fma(a0.x, c.y, fma(a0.y, c.x, acc0[q].y));
+                acc1[q].x = fma(a1.x, c.x, fma(-a1.y, c.y, acc1[q].x));
+                acc1[q].y = fma(a1.x, c.y, fma(a1.y, c.x, acc1[q].y));
             }
         }
     }
-    if (n >= N) return;
     OT *out = static_cast<OT *>(it.out);
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
+    for (int q = 0; q < NC; ++q) {
+        const int b = h + 8 * q;
         if (b < it.nb) {
-            const int64_t o = int64_t(it.ocol ? it.ocol[b] : b) * N + n;
-            double2 y = cscale(it.alpha, acc[b]);
-            if (it.beta != 0.0) y = cadd(y, cscale(it.beta, to_d2(out[o])));
-            out[o] = from_d2<OT>(y);
+            const int64_t col = int64_t(it.ocol ? it.ocol[b] : b) * N;
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int64_t n = n0 + v + 32 * u;
+                if (n < N) {
+                    double2 y = cscale(it.alpha, u ? acc1[q] : acc0[q]);
+                    if (it.beta != 0.0) y = cadd(y, cscale(it.beta, to_d2(out[col + n])));
+                    out[col + n] = from_d2<OT>(y);
+                }
+            }
         }
     }
 }
@@ -244,8 +277,9 @@ __global__ void k_bnorm_fin(int nparts, int count, const double *__restrict__ pa
 
 // Device state of one group (fixed regions sized for r, q <= BMAX and m steps).
 struct GDev {
-    double2 *C1, *C2;   // projection coefficients of the two passes, ((m+1) r) x r
-    double2 *G1, *G2;   // Gram matrices of W in the two passes, r x r
+    double2 *C2;        // projection coefficients of the second pass, ((m+1) r) x r (the first
+                        // pass writes its own into Hbar)
+    double2 *G1, *G2;   // Gram matrices of T V_j before the passes and of W after the last one, r x r
     double2 *Rt;        // block column j at Rt + j * (m+1) r r: rows 0 .. (j+2) r of Hbar, reduced in place
     double2 *U;         // Householder vectors of block column j: 2r x r at U + j * 2 r r
     double2 *T;         // triangular factor of those reflectors (Q = I - U T U^H): r x r at T + j r r
@@ -254,38 +288,26 @@ struct GDev {
     double2 *Y;         // least-squares solution times the column scales, (m r) x q
     double *est;        // per-column residual estimate (scaled units)
     double *scale;      // per-column residual norm at the start of the cycle
-    int *flag;          // [0] second Gram-Schmidt pass needed, [1] partial breakdown
-    int r, q, steps, pad;
+    int *flag;          // [0] second Gram-Schmidt pass needed, [2 + (j & 1)] partial breakdown at step j
+    int r, q;
 };
 
-// Gram after the update (G - C^H C) decides whether a second pass runs.
-__global__ __launch_bounds__(64) void k_bflag(GDev *__restrict__ gd, const int *__restrict__ gids, int j)
+// The Gram matrix after the first update (G2) against the one before (G1)
+// decides whether a second pass runs: any column that kept less than half of
+// its norm squared.
+__global__ __launch_bounds__(64) void k_bflag(GDev *__restrict__ gd, const int *__restrict__ gids)
 {
     GDev g = gd[gids[blockIdx.x]];
-    const int r = g.r, K = (j + 1) * r, a = threadIdx.x;
-    __shared__ int need;
-    if (a == 0) need = 0;
-    __syncthreads();
-    if (a < r) {
-        double s = g.G1[a * r + a].x;
-        const double g0 = s;
-        for (int k = 0; k < K; ++k) {
-            const double2 c = g.C1[int64_t(k) * r + a];
-            s -= c.x * c.x + c.y * c.y;
-        }
-        if (s < 0.5 * g0) atomicOr(&need, 1);
-    }
-    __syncthreads();
-    if (a == 0) {
-        g.flag[0] = need;
-        g.flag[1] = 0;
-    }
+    const int r = g.r, a = threadIdx.x;
+    const bool lost = a < r && g.G2[a * r + a].x < 0.5 * g.G1[a * r + a].x;
+    const unsigned long long any = __ballot(lost);
+    if (a == 0) g.flag[0] = any != 0ull;
 }
 
-// Assemble Hbar(:, j) = [C1 + C2; R] with R^H R = G'' (Cholesky of the Gram
-// after the passes), and R^{-1} for the next basis block.  A pivot at or below
-// delta^2 times the largest squared column norm of T V_j marks a partial
-// breakdown; that direction gets a zero row in R.
+// Complete Hbar(:, j) = [C1 + C2; R] (C1 already in place) with R^H R = G2 (Cholesky of the Gram
+// matrix of W after the last pass), and R^{-1} for the next basis block.  A
+// pivot at or below delta^2 times the largest squared column norm of T V_j
+// marks a partial breakdown; that direction gets a zero row in R.
 __global__ __launch_bounds__(256) void k_bchol(GDev *__restrict__ gd, const int *__restrict__ gids, int j, int m,
                                                double delta)
 {
@@ -298,21 +320,8 @@ __global__ __launch_bounds__(256) void k_bchol(GDev *__restrict__ gd, const int 
     __shared__ double gmax;
     __shared__ int brk;
     double2 *H = g.Rt + int64_t(j) * (m + 1) * r * r;   // ((m+1) r) x r, row-major
-    // H rows 0 .. K: the projection coefficients
-    for (int e = t; e < K * r; e += 256) {
-        double2 c = g.C1[e];
-        if (two) c = cadd(c, g.C2[e]);
-        H[e] = c;
-    }
-    // G'' = Gp - Cp^H Cp of the last pass
-    const double2 *Gp = two ? g.G2 : g.G1;
-    const double2 *Cp = two ? g.C2 : g.C1;
-    for (int e = t; e < r * r; e += 256) {
-        const int a = e / r, b = e % r;
-        double2 s = Gp[e];
-        for (int k = 0; k < K; ++k) s = csub(s, cmulc(Cp[int64_t(k) * r + a], Cp[int64_t(k) * r + b]));
-        Gs[a][b] = s;
-    }
+    if (two)   // the first pass wrote its coefficients into H directly
+        for (int e = t; e < K * r; e += 256) H[e] = cadd(H[e], g.C2[e]);
     if (t == 0) {
         double mx = 0.0;
         for (int a = 0; a < r; ++a) mx = fmax(mx, g.G1[a * r + a].x);
@@ -323,8 +332,9 @@ __global__ __launch_bounds__(256) void k_bchol(GDev *__restrict__ gd, const int 
         (&L[0][0])[e] = make_double2(0.0, 0.0);
         (&Ti[0][0])[e] = make_double2(0.0, 0.0);
     }
+    for (int e = t; e < r * r; e += 256) Gs[e / r][e % r] = g.G2[e];
     __syncthreads();
-    // Cholesky, column by column (L lower, G'' = L L^H)
+    // Cholesky, column by column (L lower, G2 = L L^H)
     for (int k = 0; k < r; ++k) {
         if (t == 0) {
             double p = Gs[k][k].x;
@@ -339,9 +349,9 @@ __global__ __launch_bounds__(256) void k_bchol(GDev *__restrict__ gd, const int 
         __syncthreads();
         const double d = L[k][k].x;
         if (t > k && t < r) {
-            double2 s = Gs[t][k];
-            for (int l = 0; l < k; ++l) s = csub(s, cmul(L[t][l], make_double2(L[k][l].x, -L[k][l].y)));
-            L[t][k] = d > 0.0 ? cscale(1.0 / d, s) : make_double2(0.0, 0.0);
+            double2 sv = Gs[t][k];
+            for (int l = 0; l < k; ++l) sv = csub(sv, cmul(L[t][l], make_double2(L[k][l].x, -L[k][l].y)));
+            L[t][k] = d > 0.0 ? cscale(1.0 / d, sv) : make_double2(0.0, 0.0);
         }
         __syncthreads();
     }
@@ -356,50 +366,78 @@ __global__ __launch_bounds__(256) void k_bchol(GDev *__restrict__ gd, const int 
         const int b = t;
         for (int a = b; a >= 0; --a) {
             const double raa = L[a][a].x;
-            double2 s = a == b ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0);
-            for (int c = a + 1; c <= b; ++c) s = csub(s, cmul(make_double2(L[c][a].x, -L[c][a].y), Ti[c][b]));
-            Ti[a][b] = raa > 0.0 ? cscale(1.0 / raa, s) : make_double2(0.0, 0.0);
+            double2 sv = a == b ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0);
+            for (int c = a + 1; c <= b; ++c) sv = csub(sv, cmul(make_double2(L[c][a].x, -L[c][a].y), Ti[c][b]));
+            Ti[a][b] = raa > 0.0 ? cscale(1.0 / raa, sv) : make_double2(0.0, 0.0);
         }
     }
     __syncthreads();
     for (int e = t; e < r * r; e += 256) g.Tinv[e] = Ti[e / r][e % r];
-    if (t == 0) g.flag[1] = brk;
+    if (t == 0) g.flag[2 + (j & 1)] = brk;
 }
 
 // Apply Q^H = I - U T^H U^H (U: 2r x r, T: r x r upper) to X (2r x nc) in LDS.
 // All 256 threads take part; W1, W2 are r x nc scratch.
-__device__ void wy_apply(double2 (*X)[BMAX + 1], double2 (*Us)[BMAX + 1], double2 (*Ts)[BMAX + 1],
-                         double2 (*W1)[BMAX + 1], double2 (*W2)[BMAX + 1], int r, int nc)
+template <int XC>
+__device__ void wy_apply(double2 (*X)[XC], double2 (*Us)[BMAX + 1], double2 (*Ts)[BMAX + 1], double2 (*W1)[XC],
+                         double2 (*W2)[XC], int r, int nc)
 {
     const int t = threadIdx.x;
     for (int e = t; e < r * nc; e += 256) {   // W1 = U^H X
         const int a = e / nc, c = e % nc;
-        double2 s = make_double2(0.0, 0.0);
-        for (int i = a; i < 2 * r; ++i) s = cadd(s, cmulc(Us[i][a], X[i][c]));
-        W1[a][c] = s;
+        double2 sv = make_double2(0.0, 0.0);
+        for (int i = a; i < 2 * r; ++i) sv = cadd(sv, cmulc(Us[i][a], X[i][c]));
+        W1[a][c] = sv;
     }
     __syncthreads();
     for (int e = t; e < r * nc; e += 256) {   // W2 = T^H W1
         const int a = e / nc, c = e % nc;
-        double2 s = make_double2(0.0, 0.0);
-        for (int b = 0; b <= a; ++b) s = cadd(s, cmulc(Ts[b][a], W1[b][c]));
-        W2[a][c] = s;
+        double2 sv = make_double2(0.0, 0.0);
+        for (int b = 0; b <= a; ++b) sv = cadd(sv, cmulc(Ts[b][a], W1[b][c]));
+        W2[a][c] = sv;
     }
     __syncthreads();
     for (int e = t; e < 2 * r * nc; e += 256) {   // X -= U W2
         const int i = e / nc, c = e % nc;
-        double2 s = X[i][c];
+        double2 sv = X[i][c];
         const int amax = min(i, r - 1);
-        for (int a = 0; a <= amax; ++a) s = csub(s, cmul(Us[i][a], W2[a][c]));
-        X[i][c] = s;
+        for (int a = 0; a <= amax; ++a) sv = csub(sv, cmul(Us[i][a], W2[a][c]));
+        X[i][c] = sv;
     }
     __syncthreads();
 }
 
-// One step of the QR factorisation of Hbar: the reflectors of block columns
-// 0 .. j-1 applied to the new block column, new reflectors for its rows
-// jr .. jr + 2r, the same applied to E_1 S, and the residual estimates.
-__global__ __launch_bounds__(256) void k_bls_step(GDev *__restrict__ gd, const int *__restrict__ gids, int j, int m)
+constexpr int CS = 8;   // columns of the new block column per workgroup of k_bls_apply
+
+// The reflectors of block columns 0 .. j-1 applied, in order, to the new block
+// column of Hbar; the columns are independent, CS of them per workgroup.
+__global__ __launch_bounds__(256) void k_bls_apply(GDev *__restrict__ gd, const int *__restrict__ gids, int j, int m)
+{
+    GDev g = gd[gids[blockIdx.x]];
+    const int r = g.r, c0 = blockIdx.y * CS, nc = min(CS, r - c0), t = threadIdx.x;
+    if (nc <= 0 || j == 0) return;
+    __shared__ double2 X[2 * BMAX][CS + 1];
+    __shared__ double2 Us[2 * BMAX][BMAX + 1];
+    __shared__ double2 Ts[BMAX][BMAX + 1];
+    __shared__ double2 W1[BMAX][CS + 1];
+    __shared__ double2 W2[BMAX][CS + 1];
+    double2 *H = g.Rt + int64_t(j) * (m + 1) * r * r;
+    for (int i = 0; i < j; ++i) {
+        const double2 *Ui = g.U + int64_t(i) * 2 * r * r, *Ti = g.T + int64_t(i) * r * r;
+        for (int e = t; e < 2 * r * nc; e += 256) X[e / nc][e % nc] = H[int64_t(i * r + e / nc) * r + c0 + e % nc];
+        for (int e = t; e < 2 * r * r; e += 256) Us[e / r][e % r] = Ui[e];
+        for (int e = t; e < r * r; e += 256) Ts[e / r][e % r] = Ti[e];
+        __syncthreads();
+        wy_apply<CS + 1>(X, Us, Ts, W1, W2, r, nc);
+        for (int e = t; e < 2 * r * nc; e += 256) H[int64_t(i * r + e / nc) * r + c0 + e % nc] = X[e / nc][e % nc];
+        __syncthreads();
+    }
+}
+
+// New reflectors for rows jr .. jr + 2r of the new block column of Hbar (the
+// earlier ones already applied), their triangular factor, the same applied to
+// E_1 S, and the residual estimates.  One workgroup per group.
+__global__ __launch_bounds__(256) void k_bls_qr(GDev *__restrict__ gd, const int *__restrict__ gids, int j, int m)
 {
     GDev g = gd[gids[blockIdx.x]];
     const int r = g.r, q = g.q, t = threadIdx.x;
@@ -411,18 +449,6 @@ __global__ __launch_bounds__(256) void k_bls_step(GDev *__restrict__ gd, const i
     __shared__ double2 alpha_s;
     __shared__ double beta_s;
     double2 *H = g.Rt + int64_t(j) * (m + 1) * r * r;
-    for (int i = 0; i < j; ++i) {
-        const double2 *Ui = g.U + int64_t(i) * 2 * r * r, *Ti = g.T + int64_t(i) * r * r;
-        for (int e = t; e < 2 * r * r; e += 256) {
-            X[e / r][e % r] = H[int64_t(i) * r * r + e];
-            Us[e / r][e % r] = Ui[e];
-        }
-        for (int e = t; e < r * r; e += 256) Ts[e / r][e % r] = Ti[e];
-        __syncthreads();
-        wy_apply(X, Us, Ts, W1, W2, r, r);
-        for (int e = t; e < 2 * r * r; e += 256) H[int64_t(i) * r * r + e] = X[e / r][e % r];
-        __syncthreads();
-    }
     // Householder QR of rows jr .. jr + 2r
     for (int e = t; e < 2 * r * r; e += 256) {
         X[e / r][e % r] = H[int64_t(j) * r * r + e];
@@ -496,7 +522,7 @@ __global__ __launch_bounds__(256) void k_bls_step(GDev *__restrict__ gd, const i
     // E_1 S rows jr .. jr + 2r, q columns
     for (int e = t; e < 2 * r * q; e += 256) X[e / q][e % q] = g.Gv[int64_t(j) * r * q + e];
     __syncthreads();
-    wy_apply(X, Us, Ts, W1, W2, r, q);
+    wy_apply<BMAX + 1>(X, Us, Ts, W1, W2, r, q);
     for (int e = t; e < 2 * r * q; e += 256) g.Gv[int64_t(j) * r * q + e] = X[e / q][e % q];
     if (t < q) {
         double s = 0.0;
@@ -505,39 +531,67 @@ __global__ __launch_bounds__(256) void k_bls_step(GDev *__restrict__ gd, const i
     }
 }
 
-// Y = R^{-1} Gv(0 : J r, :) by block back substitution (R upper triangular,
-// block column b of R at Rt + b (m+1) r r), scaled by the column norms.
-__global__ __launch_bounds__(256) void k_bls_solve(GDev *__restrict__ gd, const int *__restrict__ gids, int m)
+// Y = R^{-1} Gv(0 : J r, :) by right-looking block back substitution (R upper
+// triangular, block column b of R at Rt + b (m+1) r r), one block row I per
+// pair of launches from the last: k_bls_tri solves R_II Y_I = Gv_I, then
+// k_bls_upd takes R(0 : I r, I) Y_I off the rows above.  Gv is consumed.
+__global__ __launch_bounds__(256) void k_bls_tri(GDev *__restrict__ gd, const int *__restrict__ gids,
+                                                 const int *__restrict__ steps, int I, int m)
 {
-    GDev g = gd[gids[blockIdx.x]];
-    const int r = g.r, q = g.q, J = g.steps, t = threadIdx.x;
+    const int gid = gids[blockIdx.x];
+    GDev g = gd[gid];
+    const int r = g.r, q = g.q, t = threadIdx.x;
+    if (I >= steps[gid]) return;
     const int64_t bs = int64_t(m + 1) * r * r;
     __shared__ double2 S[BMAX][BMAX + 1];
-    auto Rel = [&](int row, int col) { return g.Rt[(col / r) * bs + int64_t(row) * r + col % r]; };
-    for (int I = J - 1; I >= 0; --I) {
-        for (int e = t; e < r * q; e += 256) {
-            const int a = e / q, c = e % q, row = I * r + a;
-            double2 s = g.Gv[int64_t(row) * q + c];
-            for (int sg = (I + 1) * r; sg < J * r; ++sg) s = csub(s, cmul(Rel(row, sg), g.Y[int64_t(sg) * q + c]));
-            S[a][c] = s;
+    __shared__ double2 D[BMAX][BMAX + 1];
+    const double2 *Rb = g.Rt + I * bs;
+    for (int e = t; e < r * r; e += 256) D[e / r][e % r] = Rb[int64_t(I * r + e / r) * r + e % r];
+    for (int e = t; e < r * q; e += 256) S[e / q][e % q] = g.Gv[int64_t(I * r + e / q) * q + e % q];
+    __syncthreads();
+    if (t < q) {
+        for (int a = r - 1; a >= 0; --a) {
+            double2 sv = S[a][t];
+            for (int b = a + 1; b < r; ++b) sv = csub(sv, cmul(D[a][b], S[b][t]));
+            const double2 d = D[a][a];
+            const double dd = d.x * d.x + d.y * d.y;
+            S[a][t] = dd > 0.0 ? make_double2((sv.x * d.x + sv.y * d.y) / dd, (sv.y * d.x - sv.x * d.y) / dd)
+                               : make_double2(0.0, 0.0);
         }
-        __syncthreads();
-        if (t < q) {
-            for (int a = r - 1; a >= 0; --a) {
-                const int row = I * r + a;
-                double2 s = S[a][t];
-                for (int b = a + 1; b < r; ++b) s = csub(s, cmul(Rel(row, I * r + b), S[b][t]));
-                const double2 d = Rel(row, row);
-                const double dd = d.x * d.x + d.y * d.y;
-                S[a][t] = dd > 0.0 ? make_double2((s.x * d.x + s.y * d.y) / dd, (s.y * d.x - s.x * d.y) / dd)
-                                   : make_double2(0.0, 0.0);
-            }
-        }
-        __syncthreads();
-        for (int e = t; e < r * q; e += 256) g.Y[int64_t(I * r + e / q) * q + e % q] = S[e / q][e % q];
-        __syncthreads();
     }
-    for (int e = t; e < J * r * q; e += 256) g.Y[e] = cscale(g.scale[e % q], g.Y[e]);
+    __syncthreads();
+    // Y holds the solution times the column scales
+    for (int e = t; e < r * q; e += 256) g.Y[int64_t(I * r + e / q) * q + e % q] = cscale(g.scale[e % q], S[e / q][e % q]);
+}
+
+// rows 64 blockIdx.y .. of block rows 0 .. I-1: Gv -= R(rows, I) Y_I / scale
+__global__ __launch_bounds__(256) void k_bls_upd(GDev *__restrict__ gd, const int *__restrict__ gids,
+                                                 const int *__restrict__ steps, int I, int m)
+{
+    const int gid = gids[blockIdx.x];
+    GDev g = gd[gid];
+    const int r = g.r, q = g.q, t = threadIdx.x;
+    if (I >= steps[gid]) return;
+    const int row0 = blockIdx.y * 64;
+    if (row0 >= I * r) return;
+    const int64_t bs = int64_t(m + 1) * r * r;
+    __shared__ double2 Ys[BMAX][BMAX + 1];
+    for (int e = t; e < r * q; e += 256) {
+        const int c = e % q;
+        const double sc = g.scale[c];
+        const double2 y = g.Y[int64_t(I * r + e / q) * q + c];
+        Ys[e / q][c] = sc > 0.0 ? cscale(1.0 / sc, y) : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    const double2 *Rb = g.Rt + I * bs;
+    for (int e = t; e < 64 * q; e += 256) {
+        const int row = row0 + e / q, c = e % q;
+        if (row >= I * r) continue;
+        double2 sv = g.Gv[int64_t(row) * q + c];
+        const double2 *Rr = Rb + int64_t(row) * r;
+        for (int b = 0; b < r; ++b) sv = csub(sv, cmul(Rr[b], Ys[b][c]));
+        g.Gv[int64_t(row) * q + c] = sv;
+    }
 }
 
 __global__ void k_bzero(int64_t n, double2 *__restrict__ a)
@@ -566,11 +620,12 @@ struct Bufs {
 };
 
 // Small per-launch tables: staged in pinned host memory and copied to a device
-// mirror on the stream.  Space is reused only after a stream synchronisation,
-// when every copy and every kernel reading the tables has finished.
+// mirror on the stream, all tables staged since the last copy in one transfer
+// (flush).  Space is reused only after a stream synchronisation, when every
+// copy and every kernel reading the tables has finished.
 struct Arena {
     char *h = nullptr, *d = nullptr;
-    size_t cap = 0, used = 0;
+    size_t cap = 0, used = 0, flushed = 0;
     explicit Arena(size_t n) : cap(n)
     {
         BIE_HIP(hipHostMalloc(reinterpret_cast<void **>(&h), n));
@@ -589,20 +644,28 @@ struct Arena {
         used = off + bytes;
         return off;
     }
+    // device address of a staged copy of v (valid after the next flush)
     template <typename T>
-    T *put(const std::vector<T> &v, hipStream_t s)
+    T *put(const std::vector<T> &v)
     {
-        const size_t off = stage(v.data(), v.size() * sizeof(T));
-        BIE_HIP(hipMemcpyAsync(d + off, h + off, v.size() * sizeof(T), hipMemcpyHostToDevice, s));
-        return reinterpret_cast<T *>(d + off);
+        return reinterpret_cast<T *>(d + stage(v.data(), v.size() * sizeof(T)));
     }
+    void flush(hipStream_t s)
+    {
+        if (used > flushed)
+            BIE_HIP(hipMemcpyAsync(d + flushed, h + flushed, used - flushed, hipMemcpyHostToDevice, s));
+        flushed = used;
+    }
+    // staged copy to another device buffer
     template <typename T>
     void copy_to(T *dst, const T *src, size_t count, hipStream_t s)
     {
+        flush(s);
         const size_t off = stage(src, count * sizeof(T));
         BIE_HIP(hipMemcpyAsync(dst, h + off, count * sizeof(T), hipMemcpyHostToDevice, s));
+        flushed = used;
     }
-    void reset() { used = 0; }
+    void reset() { used = flushed = 0; }
 };
 
 struct HGroup {
@@ -615,30 +678,28 @@ struct HGroup {
 int pick_nb(int n) { return n <= 4 ? 4 : n <= 8 ? 8 : n <= 16 ? 16 : 32; }
 
 template <typename AT>
-void launch_dots(const std::vector<DItem> &items, Arena &ar, int64_t N, double2 *part, int nbmax, hipStream_t s)
+void launch_dots(const DItem *d, size_t ni, int64_t N, double2 *part, int nbmax, hipStream_t s)
 {
-    if (items.empty()) return;
-    const int64_t ni = int64_t(items.size());
-    const int64_t nch = std::max<int64_t>(1, std::min<int64_t>((1024 + ni - 1) / ni, (N + 127) / 128));
+    if (ni == 0) return;
+    const int64_t nch = std::max<int64_t>(1, std::min<int64_t>((1024 + int64_t(ni) - 1) / int64_t(ni), (N + 127) / 128));
     const int64_t L = ((N + nch - 1) / nch + DS - 1) / DS * DS;
     const int nchunks = int((N + L - 1) / L);
-    const DItem *d = ar.put(items, s);
     const dim3 grid{ unsigned(nchunks), unsigned(ni) };
     const int nq = (nbmax + 3) / 4;
     if (nq <= 1) hipLaunchKernelGGL((k_bdots<AT, 1>), grid, dim3(256), 0, s, d, N, nchunks, L, part);
     else if (nq <= 2) hipLaunchKernelGGL((k_bdots<AT, 2>), grid, dim3(256), 0, s, d, N, nchunks, L, part);
     else if (nq <= 4) hipLaunchKernelGGL((k_bdots<AT, 4>), grid, dim3(256), 0, s, d, N, nchunks, L, part);
     else hipLaunchKernelGGL((k_bdots<AT, 8>), grid, dim3(256), 0, s, d, N, nchunks, L, part);
-    hipLaunchKernelGGL(k_bdots_fin, dim3(unsigned(ni)), dim3(256), 0, s, d, nchunks, (const double2 *)part);
+    hipLaunchKernelGGL(k_bdots_fin, dim3(unsigned(ni), unsigned((DT * BMAX) / 64)), dim3(256), 0, s, d, nchunks,
+                       (const double2 *)part);
     BIE_HIP(hipGetLastError());
 }
 
 template <typename AT, typename OT>
-void launch_comb(const std::vector<CItem> &items, Arena &ar, int64_t N, int nbmax, hipStream_t s)
+void launch_comb(const CItem *d, size_t ni, int64_t N, int nbmax, hipStream_t s)
 {
-    if (items.empty()) return;
-    const CItem *d = ar.put(items, s);
-    const dim3 grid(unsigned((N + 255) / 256), unsigned(items.size()));
+    if (ni == 0) return;
+    const dim3 grid(unsigned((N + 63) / 64), unsigned(ni));
     switch (pick_nb(nbmax)) {
     case 4: hipLaunchKernelGGL((k_bcomb<AT, OT, 4>), grid, dim3(256), 0, s, d, N); break;
     case 8: hipLaunchKernelGGL((k_bcomb<AT, OT, 8>), grid, dim3(256), 0, s, d, N); break;
@@ -698,6 +759,26 @@ int rank_revealing(const std::vector<cd> &G, int q, const std::vector<double> &s
     return r;
 }
 
+// Second stream, events and pinned buffers of one solve, released at scope exit.
+struct Aux {
+    hipStream_t s2 = nullptr;
+    hipEvent_t ev[5] = {};
+    std::vector<void *> pinned;
+    Aux()
+    {
+        BIE_HIP(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
+        for (auto &e : ev) BIE_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+    ~Aux()
+    {
+        if (s2) (void)hipStreamSynchronize(s2);
+        for (auto &e : ev)
+            if (e) (void)hipEventDestroy(e);
+        if (s2) (void)hipStreamDestroy(s2);
+        for (void *p : pinned) (void)hipHostFree(p);
+    }
+};
+
 template <typename VT>
 int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_solve_opts &o, bie_solve_stat *hs,
                 hipStream_t s)
@@ -715,24 +796,23 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
     double2 *Wb = db.get<double2>(size_t(R) * N);
     VT *V = db.get<VT>(size_t(m + 1) * R * N);
     const int64_t tiles = ((m + 1) * p + DT - 1) / DT + 1;
-    double2 *part = db.get<double2>(size_t(Gmax * tiles + 1024) * DT * BMAX);
+    double2 *part = db.get<double2>(size_t(Gmax * tiles + 2048) * DT * BMAX);
     const int nparts = int(std::min<int64_t>(64, (N + 255) / 256));
     double *npart = db.get<double>(size_t(R) * nparts);
     double *nrm = db.get<double>(size_t(R));
     // group regions
     const size_t p2 = size_t(p) * p;
-    const size_t per = 2 * (m + 1) * p2 + 2 * p2 + size_t(m) * (m + 1) * p2 + 2 * size_t(m) * p2 + size_t(m) * p2 + p2 +
+    const size_t per = (m + 1) * p2 + 2 * p2 + size_t(m) * (m + 1) * p2 + 2 * size_t(m) * p2 + size_t(m) * p2 + p2 +
                        (m + 1) * p2 + size_t(m) * p2;
     double2 *greg = db.get<double2>(per * Gmax);
     double *gest = db.get<double>(size_t(Gmax) * BMAX);
     double *gscale = db.get<double>(size_t(Gmax) * BMAX);
-    int *gflag = db.get<int>(size_t(Gmax) * 2);
+    int *gflag = db.get<int>(size_t(Gmax) * 4);
     GDev *gd = db.get<GDev>(size_t(Gmax));
     std::vector<GDev> hg(Gmax);
     for (int64_t g = 0; g < Gmax; ++g) {
         double2 *b = greg + per * g;
         GDev &d = hg[g];
-        d.C1 = b; b += (m + 1) * p2;
         d.C2 = b; b += (m + 1) * p2;
         d.G1 = b; b += p2;
         d.G2 = b; b += p2;
@@ -744,15 +824,33 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
         d.Y = b;
         d.est = gest + g * BMAX;
         d.scale = gscale + g * BMAX;
-        d.flag = gflag + 2 * g;
+        d.flag = gflag + 4 * g;
     }
     Arena ar(size_t(8) << 20);
+    std::unique_ptr<Arena> arena[2] = { std::make_unique<Arena>(size_t(8) << 20),
+                                        std::make_unique<Arena>(size_t(8) << 20) };
+    Aux aux;
+    hipStream_t s2 = aux.s2;
+    hipEvent_t ev_chol = aux.ev[0], ev_ls[2] = { aux.ev[1], aux.ev[2] }, ev_arena[2] = { aux.ev[3], aux.ev[4] };
+    BIE_HIP(hipEventRecord(ev_arena[0], s));
+    BIE_HIP(hipEventRecord(ev_arena[1], s));
+    double *hest[2];
+    int *hfl[2];
+    for (int i = 0; i < 2; ++i) {
+        BIE_HIP(hipHostMalloc(reinterpret_cast<void **>(&hest[i]), size_t(Gmax) * BMAX * sizeof(double)));
+        aux.pinned.push_back(hest[i]);
+        BIE_HIP(hipHostMalloc(reinterpret_cast<void **>(&hfl[i]), size_t(Gmax) * 4 * sizeof(int)));
+        aux.pinned.push_back(hfl[i]);
+    }
+    int *gsteps = db.get<int>(size_t(Gmax));
+    std::vector<int> hsteps(Gmax, 0);
     auto sync = [&]() {
         BIE_HIP(hipStreamSynchronize(s));
         ar.reset();
     };
     auto norms = [&](const double2 *src, const std::vector<int> &cols, std::vector<double> &out) {
-        const int *dc = ar.put(cols, s);
+        const int *dc = ar.put(cols);
+        ar.flush(s);
         hipLaunchKernelGGL(k_bnorm_part, dim3(unsigned(nparts), unsigned(cols.size())), dim3(256), 0, s, N, src, dc,
                            npart);
         hipLaunchKernelGGL(k_bnorm_fin, dim3(unsigned((cols.size() + 63) / 64)), dim3(64), 0, s, nparts,
@@ -787,7 +885,8 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
         if (first && !o.use_x0) {
             BIE_HIP(hipMemcpyAsync(Rres, B, size_t(R) * N * sizeof(double2), hipMemcpyDeviceToDevice, s));
         } else {
-            const int *dl = ar.put(live, s);
+            const int *dl = ar.put(live);
+            ar.flush(s);
             gemm64_product(op, X, N, Rres, N, B, N, int64_t(live.size()), dl, s);
         }
         norms(Rres, live, rn);
@@ -829,16 +928,18 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
         }
         const int ng = int(grp.size());
         {
-            const int *dl = ar.put(live, s);
-            hipLaunchKernelGGL(k_bgather, dim3(unsigned(std::min<int64_t>((N + 255) / 256, 64)), unsigned(live.size())),
-                               dim3(256), 0, s, N, (const double2 *)Rres, dl, Wb);
+            const int *dl = ar.put(live);
             std::vector<DItem> it;
             for (int g = 0; g < ng; ++g) {
                 const HGroup &h = grp[g];
                 it.push_back(DItem{ Wb + int64_t(h.qoff) * N, 0, Wb + int64_t(h.qoff) * N, hg[g].G1, nullptr, h.q, 0,
                                     h.q, h.q, h.q, 0 });
             }
-            launch_dots<double2>(it, ar, N, part, p, s);
+            const DItem *di = ar.put(it);
+            ar.flush(s);
+            hipLaunchKernelGGL(k_bgather, dim3(unsigned(std::min<int64_t>((N + 255) / 256, 64)), unsigned(live.size())),
+                               dim3(256), 0, s, N, (const double2 *)Rres, dl, Wb);
+            launch_dots<double2>(di, it.size(), N, part, p, s);
         }
         std::vector<std::vector<cd>> hG(ng);
         for (int g = 0; g < ng; ++g) {
@@ -866,7 +967,6 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
             h.active = true;
             hg[g].r = h.r;
             hg[g].q = h.q;
-            hg[g].steps = 0;
         }
         ar.copy_to(gd, hg.data(), size_t(ng), s);
         {
@@ -875,7 +975,7 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
                 const HGroup &h = grp[g];
                 std::vector<double2> t0(T0[g].size());
                 for (size_t e = 0; e < t0.size(); ++e) t0[e] = make_double2(T0[g][e].real(), T0[g][e].imag());
-                const double2 *dT = ar.put(t0, s);
+                const double2 *dT = ar.put(t0);
                 it.push_back(CItem{ Wb + int64_t(h.qoff) * N, 0, dT, V + int64_t(h.c0) * N, nullptr, nullptr, 1.0, 0.0,
                                     h.q, h.q, h.r, h.r });
                 // E_1 S into Gv (rows 0 .. r), zeros below; column scales
@@ -885,99 +985,138 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
                 ar.copy_to(hg[g].Gv, sv.data(), sv.size(), s);
                 ar.copy_to(hg[g].scale, h.scale.data(), size_t(h.q), s);
             }
-            launch_comb<double2, VT>(it, ar, N, p, s);
+            const CItem *ci = ar.put(it);
+            ar.flush(s);
+            launch_comb<double2, VT>(ci, it.size(), N, p, s);
         }
-        // (3) block Arnoldi steps; every active group advances together
-        for (int j = 0; j < m; ++j) {
+        // (3) block Arnoldi steps; every active group advances together.  The
+        // least-squares update of step j runs on the second stream beside the
+        // product and orthogonalisation of step j + 1; its estimates are read
+        // one step late, so a group that has met its targets runs at most one
+        // step more (discarded: its solution uses the steps up to the decision).
+        int prev = -1;
+        std::vector<int> prev_act;
+        for (int j = 0; j <= m; ++j) {
             std::vector<int> act, cols;
-            for (int g = 0; g < ng; ++g)
-                if (grp[g].active) {
-                    act.push_back(g);
-                    for (int a = 0; a < grp[g].r; ++a) cols.push_back(grp[g].c0 + a);
-                }
-            if (act.empty()) break;
-            const int na = int(act.size());
-            const int *dg = ar.put(act, s);
-            const int *dc = ar.put(cols, s);
-            const VT *Vj = V + int64_t(j) * Wc * N;
-            if (mixed) gemm_product(op, Vj, N, VEC_C64, Wb, N, nullptr, 0, int64_t(cols.size()), dc, s, terms);
-            else gemm64_product(op, Vj, N, Wb, N, nullptr, 0, int64_t(cols.size()), dc, s);
-            for (int pass = 0; pass < 2; ++pass) {
-                std::vector<DItem> dv, dw;   // basis dots (VT) and Gram matrices (FP64)
-                std::vector<CItem> ci;
+            if (j < m)
+                for (int g = 0; g < ng; ++g)
+                    if (grp[g].active && j < grp[g].cap) {
+                        act.push_back(g);
+                        for (int a = 0; a < grp[g].r; ++a) cols.push_back(grp[g].c0 + a);
+                    }
+            if (act.empty() && prev < 0) break;
+            Arena &A = *arena[j & 1];
+            BIE_HIP(hipEventSynchronize(ev_arena[j & 1]));
+            A.reset();
+            if (!act.empty()) {
+                const int na = int(act.size());
+                // tables of the step: pass 1 basis dots, Gram before and after,
+                // updates; pass 2 the same for flagged groups; basis scaling
+                std::vector<DItem> dv[2], dpre, dpost[2];
+                std::vector<CItem> ci[2], cs;
                 for (int g : act) {
                     const HGroup &h = grp[g];
                     const int K = (j + 1) * h.r;
-                    const int *fl = pass ? hg[g].flag : nullptr;
-                    double2 *Cd = pass ? hg[g].C2 : hg[g].C1;
-                    double2 *Gd = pass ? hg[g].G2 : hg[g].G1;
-                    for (int k0 = 0; k0 < K; k0 += DT)
-                        dv.push_back(DItem{ V + int64_t(h.c0) * N, Wc, Wb + int64_t(h.c0) * N, Cd, fl, h.r, k0,
-                                            std::min(DT, K - k0), h.r, h.r, 0 });
-                    dw.push_back(DItem{ Wb + int64_t(h.c0) * N, 0, Wb + int64_t(h.c0) * N, Gd, fl, h.r, 0, h.r, h.r,
-                                        h.r, 0 });
-                    ci.push_back(CItem{ V + int64_t(h.c0) * N, Wc, Cd, Wb + int64_t(h.c0) * N, nullptr, fl, -1.0, 1.0,
-                                        h.r, K, h.r, h.r });
+                    double2 *Wg = Wb + int64_t(h.c0) * N;
+                    for (int pass = 0; pass < 2; ++pass) {
+                        const int *fl = pass ? hg[g].flag : nullptr;
+                        // first-pass coefficients straight into column block j of Hbar
+                        double2 *Cd = pass ? hg[g].C2 : hg[g].Rt + int64_t(j) * (m + 1) * h.r * h.r;
+                        for (int k0 = 0; k0 < K; k0 += DT)
+                            dv[pass].push_back(DItem{ V + int64_t(h.c0) * N, Wc, Wg, Cd, fl, h.r, k0, std::min(DT, K - k0),
+                                                      h.r, h.r, 0 });
+                        dpost[pass].push_back(DItem{ Wg, 0, Wg, hg[g].G2, fl, h.r, 0, h.r, h.r, h.r, 0 });
+                        ci[pass].push_back(CItem{ V + int64_t(h.c0) * N, Wc, Cd, Wg, nullptr, fl, -1.0, 1.0, h.r, K, h.r,
+                                                  h.r });
+                    }
+                    dpre.push_back(DItem{ Wg, 0, Wg, hg[g].G1, nullptr, h.r, 0, h.r, h.r, h.r, 0 });
+                    cs.push_back(CItem{ Wg, 0, hg[g].Tinv, V + (int64_t(j + 1) * Wc + h.c0) * N, nullptr, nullptr, 1.0,
+                                        0.0, h.r, h.r, h.r, h.r });
                 }
-                launch_dots<VT>(dv, ar, N, part, p, s);
-                launch_dots<double2>(dw, ar, N, part, p, s);
-                launch_comb<VT, double2>(ci, ar, N, p, s);
-                if (pass == 0) {
-                    hipLaunchKernelGGL(k_bflag, dim3(unsigned(na)), dim3(64), 0, s, gd, dg, j);
-                    BIE_HIP(hipGetLastError());
-                }
-            }
-            hipLaunchKernelGGL(k_bchol, dim3(unsigned(na)), dim3(256), 0, s, gd, dg, j, m, DELTA);
-            hipLaunchKernelGGL(k_bls_step, dim3(unsigned(na)), dim3(256), 0, s, gd, dg, j, m);
-            BIE_HIP(hipGetLastError());
-            {
-                std::vector<CItem> it;
-                for (int g : act) {
-                    const HGroup &h = grp[g];
-                    it.push_back(CItem{ Wb + int64_t(h.c0) * N, 0, hg[g].Tinv, V + (int64_t(j + 1) * Wc + h.c0) * N,
-                                        nullptr, nullptr, 1.0, 0.0, h.r, h.r, h.r, h.r });
-                }
-                launch_comb<double2, VT>(it, ar, N, p, s);
-            }
-            std::vector<double> est(size_t(ng) * BMAX);
-            std::vector<int> fl(size_t(ng) * 2);
-            BIE_HIP(hipMemcpyAsync(est.data(), gest, est.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-            BIE_HIP(hipMemcpyAsync(fl.data(), gflag, fl.size() * sizeof(int), hipMemcpyDeviceToHost, s));
-            sync();
-            std::vector<int> ended;
-            for (int g : act) {
-                HGroup &h = grp[g];
-                h.steps = j + 1;
-                bool met = true;
-                for (int a = 0; a < h.q; ++a) {
-                    const double e = est[size_t(g) * BMAX + a];
-                    bie_solve_stat &st = hs[h.rhs[a]];
-                    st.iters += 1;
-                    st.mvps += 1;
-                    st.relres_est = e * h.scale[a] / bn[h.rhs[a]];
-                    if (!(e <= h.target[a])) met = false;
-                }
-                if (met || fl[2 * g + 1] || h.steps >= h.cap) {
-                    h.active = false;
-                    hg[g].steps = h.steps;
-                    ended.push_back(g);
-                }
-            }
-            if (!ended.empty()) {
-                ar.copy_to(gd, hg.data(), size_t(ng), s);
-                const int *de = ar.put(ended, s);
-                hipLaunchKernelGGL(k_bls_solve, dim3(unsigned(ended.size())), dim3(256), 0, s, gd, de, m);
+                const int *dg = A.put(act), *dc = A.put(cols);
+                const DItem *pv0 = A.put(dv[0]), *pv1 = A.put(dv[1]), *ppre = A.put(dpre), *pp0 = A.put(dpost[0]),
+                            *pp1 = A.put(dpost[1]);
+                const CItem *pc0 = A.put(ci[0]), *pc1 = A.put(ci[1]), *pcs = A.put(cs);
+                A.flush(s);
+                const VT *Vj = V + int64_t(j) * Wc * N;
+                if (mixed) gemm_product(op, Vj, N, VEC_C64, Wb, N, nullptr, 0, int64_t(cols.size()), dc, s, terms);
+                else gemm64_product(op, Vj, N, Wb, N, nullptr, 0, int64_t(cols.size()), dc, s);
+                launch_dots<VT>(pv0, dv[0].size(), N, part, p, s);
+                launch_dots<double2>(ppre, dpre.size(), N, part, p, s);
+                launch_comb<VT, double2>(pc0, ci[0].size(), N, p, s);
+                launch_dots<double2>(pp0, dpost[0].size(), N, part, p, s);
+                hipLaunchKernelGGL(k_bflag, dim3(unsigned(na)), dim3(64), 0, s, gd, dg);
+                launch_dots<VT>(pv1, dv[1].size(), N, part, p, s);
+                launch_comb<VT, double2>(pc1, ci[1].size(), N, p, s);
+                launch_dots<double2>(pp1, dpost[1].size(), N, part, p, s);
+                hipLaunchKernelGGL(k_bchol, dim3(unsigned(na)), dim3(256), 0, s, gd, dg, j, m, DELTA);
+                BIE_HIP(hipEventRecord(ev_chol, s));
+                launch_comb<double2, VT>(pcs, cs.size(), N, p, s);
+                BIE_HIP(hipStreamWaitEvent(s2, ev_chol, 0));
+                hipLaunchKernelGGL(k_bls_apply, dim3(unsigned(na), unsigned((p + CS - 1) / CS)), dim3(256), 0, s2, gd,
+                                   dg, j, m);
+                hipLaunchKernelGGL(k_bls_qr, dim3(unsigned(na)), dim3(256), 0, s2, gd, dg, j, m);
                 BIE_HIP(hipGetLastError());
-                std::vector<CItem> it;
-                for (int g : ended) {
-                    const HGroup &h = grp[g];
-                    const int *oc = ar.put(h.rhs, s);
-                    it.push_back(CItem{ V + int64_t(h.c0) * N, Wc, hg[g].Y, X, oc, nullptr, 1.0, 1.0, h.r,
-                                        h.steps * h.r, h.q, h.q });
-                }
-                launch_comb<VT, double2>(it, ar, N, p, s);
+                BIE_HIP(hipMemcpyAsync(hest[j & 1], gest, size_t(ng) * BMAX * sizeof(double), hipMemcpyDeviceToHost, s2));
+                BIE_HIP(hipMemcpyAsync(hfl[j & 1], gflag, size_t(ng) * 4 * sizeof(int), hipMemcpyDeviceToHost, s2));
+                BIE_HIP(hipEventRecord(ev_ls[j & 1], s2));
             }
+            if (prev >= 0) {
+                BIE_HIP(hipEventSynchronize(ev_ls[prev & 1]));
+                const double *est = hest[prev & 1];
+                const int *fl = hfl[prev & 1];
+                std::vector<int> ended;
+                for (int g : prev_act) {
+                    HGroup &h = grp[g];
+                    if (!h.active) continue;
+                    h.steps = prev + 1;
+                    bool met = true;
+                    for (int a = 0; a < h.q; ++a) {
+                        const double e = est[size_t(g) * BMAX + a];
+                        bie_solve_stat &st = hs[h.rhs[a]];
+                        st.iters += 1;
+                        st.mvps += 1;
+                        st.relres_est = e * h.scale[a] / bn[h.rhs[a]];
+                        if (!(e <= h.target[a])) met = false;
+                    }
+                    if (met || fl[4 * g + 2 + (prev & 1)] || h.steps >= h.cap) {
+                        h.active = false;
+                        hsteps[g] = h.steps;
+                        ended.push_back(g);
+                    }
+                }
+                if (!ended.empty()) {
+                    // Y = R^{-1} (E_1 S) and X += V Y for the groups that ended at step prev
+                    std::vector<CItem> it;
+                    std::vector<const int *> oc;
+                    const int *de = A.put(ended);
+                    for (int g : ended) oc.push_back(A.put(grp[g].rhs));
+                    for (size_t e = 0; e < ended.size(); ++e) {
+                        const HGroup &h = grp[ended[e]];
+                        it.push_back(CItem{ V + int64_t(h.c0) * N, Wc, hg[ended[e]].Y, X, oc[e], nullptr, 1.0, 1.0, h.r,
+                                            h.steps * h.r, h.q, h.q });
+                    }
+                    const CItem *pit = A.put(it);
+                    A.copy_to(gsteps, hsteps.data(), size_t(ng), s);
+                    BIE_HIP(hipStreamWaitEvent(s, ev_ls[prev & 1], 0));
+                    int jmax = 0;
+                    for (int g : ended) jmax = std::max(jmax, grp[g].steps);
+                    for (int I = jmax - 1; I >= 0; --I) {
+                        hipLaunchKernelGGL(k_bls_tri, dim3(unsigned(ended.size())), dim3(256), 0, s, gd, de, gsteps, I,
+                                           m);
+                        if (I > 0)
+                            hipLaunchKernelGGL(k_bls_upd, dim3(unsigned(ended.size()), unsigned((I * p + 63) / 64)),
+                                               dim3(256), 0, s, gd, de, gsteps, I, m);
+                    }
+                    BIE_HIP(hipGetLastError());
+                    launch_comb<VT, double2>(pit, it.size(), N, p, s);
+                }
+            }
+            BIE_HIP(hipEventRecord(ev_arena[j & 1], s));
+            prev = act.empty() ? -1 : j;
+            prev_act = act;
         }
+        BIE_HIP(hipStreamSynchronize(s2));
     }
     sync();
     int status = BIE_OK;
