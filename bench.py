@@ -5,9 +5,11 @@ sphere of radius 1 m, 5120-triangle icosphere (7680 RWG unknowns), k = 10
 rad/m.  One step serves a batch of 512 held-out plane waves (256 directions
 uniform on the sphere x theta/phi polarisation) with the operator and the
 warm start resident: RHS assembly, warm-start inference (POD basis + MLP, with
-the zero fallback), and GMRES(50) with split-BF16 block products on the matrix
-cores and FP64 iterative refinement, as a continuous batch of 256 slots, to a
-true FP64 relative residual of 1e-6 for every right-hand side.
+the zero fallback), and block GMRES(50) over groups of 32 right-hand sides (one
+shared block Krylov space per group) with split-BF16 block products on the
+matrix cores and FP64 iterative refinement, to a true FP64 relative residual of
+1e-6 for every right-hand side (--method gmres: column GMRES as a continuous
+batch of 256 slots instead).
 value = right-hand sides per second over the timed steps.
 
 Beside it, on the same GPU:
@@ -38,6 +40,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
 BF16_PEAK_TFLOPS = 2500.0    # MI355X dense BF16 MFMA
+FP64_VALU_PEAK_TFLOPS = 78.6  # 256 CUs x 4 SIMDs x 16 FP64 lanes x 2 flops (FMA) x 2.4 GHz
 METRIC = "GMRES solves/s to 1e-6 residual: batched mixed+learned vs plain FP64; GEMV GB/s"
 
 
@@ -56,6 +59,10 @@ def parse():
     ap.add_argument("--basis", default="f16", choices=["f16", "c64"],
                     help="storage of the inner Krylov basis (FP16 pairs or complex64)")
     ap.add_argument("--slots", type=int, default=256)
+    ap.add_argument("--method", default="bgmres", choices=["gmres", "bgmres"],
+                    help="inner solver of the mixed-precision forms: column GMRES as a continuous batch, or "
+                         "block GMRES over groups of --block right-hand sides")
+    ap.add_argument("--block", type=int, default=32)
     ap.add_argument("--train-dirs", type=int, default=512)
     ap.add_argument("--test-dirs", type=int, default=256)
     ap.add_argument("--epochs", type=int, default=1500)
@@ -100,6 +107,24 @@ def traffic_from_profiles(fname: str, kernel_src: str, N: int):
         return float(kv["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def solver_text(args, restart):
+    if args.method == "bgmres":
+        return f"block GMRES({restart}) over groups of {args.block} right-hand sides"
+    return (f"GMRES({restart}), {'FP16' if args.basis == 'f16' else 'complex64'} inner Krylov basis, continuous "
+            f"batch of {args.slots} slots")
+
+
+def mixed_opts(args, bie, restart):
+    """Options of the mixed-precision solves: column GMRES as a continuous batch
+    (FP16 or complex64 basis), or block GMRES (complex64 basis, all right-hand
+    sides at once)."""
+    if args.method == "bgmres":
+        return bie.Solve(method="bgmres", block=args.block, restart=restart, tol=args.tol, max_mvp=20000,
+                         precision="mixed", inner_tol=args.inner_tol, inner_terms=args.inner_terms)
+    return bie.Solve(restart=restart, tol=args.tol, max_mvp=20000, precision="mixed", inner_tol=args.inner_tol,
+                     slots=args.slots, inner_terms=args.inner_terms, basis=args.basis)
 
 
 def planewave_batch(bie, inc):
@@ -193,8 +218,7 @@ def headline_leg(args, bie, torch, V, T, k):
     sync()
     res["setup_fill_split_s"] = round(time.perf_counter() - t0, 4)
     N = op.N
-    mopts = bie.Solve(restart=args.restart, tol=args.tol, max_mvp=20000, precision="mixed",
-                      inner_tol=args.inner_tol, slots=args.slots, inner_terms=args.inner_terms, basis=args.basis)
+    mopts = mixed_opts(args, bie, args.restart)
     popts = bie.Solve(restart=args.restart, tol=args.tol, max_mvp=20000)
 
     # training: solutions the method computes, then POD + MLP on the GPU
@@ -228,8 +252,8 @@ def headline_leg(args, bie, torch, V, T, k):
     for _ in range(args.warmup):
         step()
     sync()
-    bie.prof_read(0)
-    bie.prof_read(1)
+    for k in (0, 1, 4, 5):
+        bie.prof_read(k)
     bie.prof_enable(True)
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -238,6 +262,7 @@ def headline_leg(args, bie, torch, V, T, k):
     t_steps = time.perf_counter() - t0
     g_launch, g_ms, g_cols = bie.prof_read(1, columns=True)
     p_launch, p_ms = bie.prof_read(0)
+    orth = {k: bie.prof_read(k, columns=True) for k in (4, 5)}
     bie.prof_enable(False)
     ms_step = 1e3 * t_steps / args.steps
     conv = np.array([s["converged"] for s in st], bool)
@@ -306,15 +331,36 @@ def headline_leg(args, bie, torch, V, T, k):
             "avg_columns_per_launch": round(g_cols / max(1, g_launch), 1),
             "avg_launch_us": round(avg * 1e3, 2), "launches": g_launch,
             "gemm_share_of_step": round(g_ms / (t_steps * 1e3), 3)}
+    # block GMRES orthogonalisation (first pass): dots V^H W and update W -= V C,
+    # FP64 arithmetic on the vector ALUs; 8 real flops per row for every basis
+    # vector x column pair
+    cands = [(g_ms, roof)]
+    names = {4: "block GMRES basis dots V^H W (k_bdots + k_bdots_fin)",
+             5: "block GMRES basis update W -= V C (k_bcomb)"}
+    for k, (n_l, ms, pairs) in orth.items():
+        if n_l == 0:
+            continue
+        avg_o = ms / n_l
+        alg_o = 8.0 * N * pairs / n_l
+        ach_o = alg_o / (avg_o * 1e-3) / 1e12
+        cands.append((ms, {"bound": "alu", "achieved": round(ach_o, 2), "peak": FP64_VALU_PEAK_TFLOPS,
+                           "unit": "TFLOP/s", "frac": round(ach_o / FP64_VALU_PEAK_TFLOPS, 4), "traffic": None,
+                           "traffic_note": "no counter summary for this kernel",
+                           "kernel": names[k], "alg_flops_per_launch": alg_o,
+                           "avg_launch_us": round(avg_o * 1e3, 2), "launches": n_l,
+                           "share_of_step": round(ms / (t_steps * 1e3), 3)}))
+    cands.sort(key=lambda c: -c[0])
+    res["kernel_rooflines"] = [c[1] for c in cands]
     op.close()
-    return res, roof, ms_step, float(np.mean([b for _, b in itp])), int(ns)
+    return res, cands[0][1], ms_step, float(np.mean([b for _, b in itp])), int(ns)
 
 
 def c3_run(args, bie, torch):
     """Large sphere: 20480-triangle icosphere (30720 RWG), k = 20, 512 plane waves
     (16 x 16 (theta, phi) grid x theta/phi) per step, operator resident; GMRES(30)
-    with split-BF16 block products and FP64 refinement as a continuous batch of 256
-    slots to FP64 SCC 1e-6; plain FP64 GMRES(30) on a sample of the same waves."""
+    with split-BF16 block products and FP64 refinement (block GMRES over groups of
+    --block right-hand sides, or column GMRES as a continuous batch of --slots) to
+    FP64 SCC 1e-6; plain FP64 GMRES(30) on a sample of the same waves."""
     from paper_2606_13482_amd.inputs import grid_planewaves, icosphere
     sync = torch.cuda.synchronize
     V, T = icosphere(5)
@@ -326,8 +372,7 @@ def c3_run(args, bie, torch):
     N = op.N
     dirs, pols = grid_planewaves(16, 16)
     R = dirs.shape[0]
-    mopts = bie.Solve(restart=30, tol=args.tol, max_mvp=20000, precision="mixed", inner_tol=args.inner_tol,
-                      slots=args.slots, inner_terms=args.inner_terms, basis=args.basis)
+    mopts = mixed_opts(args, bie, 30)
 
     def step():
         B = op.rhs(dirs, pols)
@@ -369,10 +414,12 @@ def c3_run(args, bie, torch):
         "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "split-bf16 products (f32 accumulate) + f64 refinement", "data": "synthetic",
         "config": {"workload": (f"PEC sphere r=1 m, icosphere {T.shape[0]} triangles ({N} RWG), k={k:g}; {R} plane "
-                                f"waves (16x16 theta/phi grid x theta/phi) per step, operator resident; GMRES(30) "
-                                f"on split-BF16 MFMA products with FP64 refinement to {args.tol:g} (FP64 SCC), "
-                                f"continuous batch of {args.slots} slots"),
-                   "N": N, "k": k, "restart": 30, "inner_tol": args.inner_tol, "slots": args.slots,
+                                f"waves (16x16 theta/phi grid x theta/phi) per step, operator resident; "
+                                f"{solver_text(args, 30)} on split-BF16 MFMA products with FP64 refinement to "
+                                f"{args.tol:g} (FP64 SCC)"),
+                   "N": N, "k": k, "restart": 30, "inner_tol": args.inner_tol, "method": args.method,
+                   "block": args.block if args.method == "bgmres" else None,
+                   "slots": args.slots if args.method == "gmres" else None,
                    "rhs_per_step": R, "parallelism": "single GPU"},
         "roofline": {"bound": "mfma", "achieved": round(ach, 1), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(ach / BF16_PEAK_TFLOPS, 4), "traffic": None,
@@ -582,12 +629,13 @@ def main():
         "config": {"workload": (f"PEC sphere r=1 m, icosphere {T.shape[0]} triangles ({N} RWG), k={k:g}; batches of "
                                 f"{2 * args.test_dirs} held-out plane waves ({args.test_dirs} directions x theta/phi), "
                                 f"operator and warm start resident; learned warm start (POD {min(256, 2 * args.train_dirs)}, "
-                                f"MLP 4-512-512, trained on {2 * args.train_dirs} solves); GMRES({args.restart}) on "
-                                f"split-BF16 MFMA products with FP64 refinement to {args.tol:g} (FP64 SCC), "
-                                f"{'FP16' if args.basis == 'f16' else 'complex64'} inner Krylov basis, "
-                                f"continuous batch of {args.slots} slots"),
-                   "N": N, "k": k, "restart": args.restart, "inner_tol": args.inner_tol, "slots": args.slots,
-                   "inner_terms": args.inner_terms, "basis": args.basis,
+                                f"MLP 4-512-512, trained on {2 * args.train_dirs} solves); "
+                                f"{solver_text(args, args.restart)} on split-BF16 MFMA products with FP64 refinement "
+                                f"to {args.tol:g} (FP64 SCC)"),
+                   "N": N, "k": k, "restart": args.restart, "inner_tol": args.inner_tol, "method": args.method,
+                   "block": args.block if args.method == "bgmres" else None,
+                   "slots": args.slots if args.method == "gmres" else None,
+                   "inner_terms": args.inner_terms, "basis": args.basis if args.method == "gmres" else "c64",
                    "rhs_per_step": 2 * args.test_dirs, "train_directions": args.train_dirs,
                    "test_directions": args.test_dirs, "parallelism": "single GPU"},
         "roofline": roof,

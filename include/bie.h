@@ -198,8 +198,9 @@ typedef struct {
  * span{R0, T R0, ..., T^{j-1} R0} per restart cycle, and every column takes the
  * element of it that minimises its own residual.  R0 holds the residuals scaled
  * to unit norm, orthonormalised with rank revealing (directions below 1e-6 of
- * the largest are left out); block Gram-Schmidt with a second pass when a
- * column loses more than half its norm squared, Cholesky QR of the new block,
+ * the largest are left out); block classical Gram-Schmidt (with the FP64
+ * basis a second pass when a column keeps less than half its norm squared; the
+ * complex64 basis of precision 1 takes one pass), Cholesky QR of the new block,
  * block Householder QR of the block Hessenberg matrix.  A cycle ends when every
  * column's estimate meets its target, after `restart` block steps, or on a
  * partial breakdown (a new direction at or below 1e-6 of the largest column of
@@ -342,11 +343,13 @@ void bie_ws_destroy(bie_ws *ws);
  * by HIP events on the stream it runs on.  bie_prof_read waits for the
  * recorded events of `kernel` (0: tile pass of the packed symmetric product,
  * 1: split-BF16 block product, 2: FP64 block product, 3: reduction of the
- * packed product's partial sums; BIE_EINVAL otherwise) and returns the number
- * of launches, their summed duration in
+ * packed product's partial sums, 4: block GMRES first-pass dots V^H W with
+ * their reduction, 5: block GMRES first-pass update W -= V C; BIE_EINVAL
+ * otherwise) and returns the number of launches, their summed duration in
  * ms and (columns, may be NULL) the summed number of right-hand sides of those
  * launches (the packed product counts every column of its grid, skipped ones
- * included) since the previous read, then clears that record. */
+ * included; records 4 and 5 count basis vector x column pairs, sum of K r over
+ * the groups) since the previous read, then clears that record. */
 int bie_prof_enable(int on);
 int bie_prof_read(int kernel, int64_t *launches, double *total_ms, int64_t *columns);
 

@@ -12,10 +12,10 @@
 //   j = 0, 1, ...:
 //     W = T V_j                             one block product over the active
 //                                           columns of every group
-//     C = V^H W, G = W^H W; W -= V C        block classical Gram-Schmidt with the
-//                                           Gram matrix of W in the same pass;
-//                                           a second pass when a column lost more
-//                                           than half of its norm squared
+//     C = V^H W; W -= V C; G = W^H W        block classical Gram-Schmidt; with
+//                                           the FP64 basis a second pass when a
+//                                           column kept less than half of its
+//                                           norm squared
 //     W^H W = R^H R (Cholesky), V_{j+1} = W R^{-1}
 //     Hbar(:, j) = [C; R]; block Householder update of its QR factorisation and
 //     of E_1 S; per-column residual estimate from the last r rows
@@ -42,8 +42,8 @@ namespace bie {
 namespace {
 
 constexpr int BMAX = 32;    // right-hand sides per group, at most
-constexpr int DT = 64;      // basis vectors per tile of the dot kernel
-constexpr int DS = 32;      // rows per LDS stage of the dot kernel
+constexpr int DT = 128;     // basis vectors per tile of the dot kernel
+constexpr int DS = 16;      // rows per LDS stage of the dot kernel
 constexpr double DELTA = 1e-6;
 
 __device__ inline double2 to_d2(double2 v) { return v; }
@@ -89,32 +89,36 @@ struct CItem {
     int ar, K, ldc, nb;
 };
 
-// Partial dots over a chunk of L rows; part[((item * nchunks + chunk) * DT + v) * BMAX + b].
-// Thread (v = t % 32, wave-half h = t / 32): basis vectors v and v + 32 of the
-// tile against columns h, h + 8, h + 16, h + 24 (those below 4 NQ).
-template <typename AT, int NQ>
+// Partial dots over a chunk of L rows, tiles of 32 U basis vectors;
+// part[((item * nchunks + chunk) * 32 U + v) * BMAX + b].  Thread (v = t % 32,
+// h = t / 32): basis vectors v + 32 u (u < U) of the tile against columns
+// h + 8 q (q < NC).
+template <typename AT, int NQ, int U>
 __global__ __launch_bounds__(256) void k_bdots(const DItem *__restrict__ items, int64_t N, int nchunks, int64_t L,
                                                double2 *__restrict__ part)
 {
     constexpr int NC = (NQ + 1) / 2;   // columns per thread: 4 NQ columns over 8 thread groups
+    constexpr int TU = 32 * U;         // basis vectors per tile
     const DItem it = items[blockIdx.y];
     if (it.flag && *it.flag == 0) return;
     const int t = threadIdx.x, v = t & 31, h = t >> 5;
     const int64_t n0 = int64_t(blockIdx.x) * L, n1 = min(N, n0 + L);
-    __shared__ double2 As[DS][DT + 1];
+    __shared__ double2 As[DS][TU + 1];
     __shared__ double2 Bs[BMAX][DS + 1];
-    __shared__ int64_t Aoff[DT];
-    if (t < DT) {
+    __shared__ int64_t Aoff[TU];
+    if (t < TU) {
         const int k = it.k0 + t;
         Aoff[t] = t < it.kc ? (int64_t(k / it.ar) * it.astride + k % it.ar) * N : 0;
     }
-    double2 acc0[NC], acc1[NC];
+    double2 acc[U][NC];
 #pragma unroll
-    for (int q = 0; q < NC; ++q) acc0[q] = acc1[q] = make_double2(0.0, 0.0);
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int q = 0; q < NC; ++q) acc[u][q] = make_double2(0.0, 0.0);
     const AT *A = static_cast<const AT *>(it.A);
     for (int64_t ns = n0; ns < n1; ns += DS) {
         __syncthreads();
-        for (int e = t; e < DT * DS; e += 256) {
+        for (int e = t; e < TU * DS; e += 256) {
             const int vv = e / DS, rr = e % DS;
             const int64_t n = ns + rr;
             As[rr][vv] = (vv < it.kc && n < n1) ? to_d2(A[Aoff[vv] + n]) : make_double2(0.0, 0.0);
@@ -127,31 +131,34 @@ __global__ __launch_bounds__(256) void k_bdots(const DItem *__restrict__ items, 
         __syncthreads();
 #pragma unroll 2
         for (int rr = 0; rr < DS; ++rr) {
-            const double2 a0 = As[rr][v], a1 = As[rr][v + 32];
+            double2 a[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) a[u] = As[rr][v + 32 * u];
 #pragma unroll
             for (int q = 0; q < NC; ++q) {
                 const double2 bv = Bs[h + 8 * q][rr];
-                acc0[q].x = fma(a0.x, bv.x, fma(a0.y, bv.y, acc0[q].x));
-                acc0[q].y = fma(a0.x, bv.y, fma(-a0.y, bv.x, acc0[q].y));
-                acc1[q].x = fma(a1.x, bv.x, fma(a1.y, bv.y, acc1[q].x));
-                acc1[q].y = fma(a1.x, bv.y, fma(-a1.y, bv.x, acc1[q].y));
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    acc[u][q].x = fma(a[u].x, bv.x, fma(a[u].y, bv.y, acc[u][q].x));
+                    acc[u][q].y = fma(a[u].x, bv.y, fma(-a[u].y, bv.x, acc[u][q].y));
+                }
             }
         }
     }
-    double2 *o = part + (int64_t(blockIdx.y) * nchunks + blockIdx.x) * DT * BMAX;
+    double2 *o = part + (int64_t(blockIdx.y) * nchunks + blockIdx.x) * TU * BMAX;
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
         const int b = h + 8 * q;
-        if (b < it.nb) {
-            if (v < it.kc) o[v * BMAX + b] = acc0[q];
-            if (v + 32 < it.kc) o[(v + 32) * BMAX + b] = acc1[q];
-        }
+        if (b < it.nb)
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (v + 32 * u < it.kc) o[(v + 32 * u) * BMAX + b] = acc[u][q];
     }
 }
 
 // Sums the chunk partials in a fixed order: 4 lanes per output, chunks c = lane
 // mod 4, then a 4-lane reduction.
-__global__ __launch_bounds__(256) void k_bdots_fin(const DItem *__restrict__ items, int nchunks,
+__global__ __launch_bounds__(256) void k_bdots_fin(const DItem *__restrict__ items, int nchunks, int tu,
                                                    const double2 *__restrict__ part)
 {
     const DItem it = items[blockIdx.x];
@@ -161,7 +168,7 @@ __global__ __launch_bounds__(256) void k_bdots_fin(const DItem *__restrict__ ite
     const int v = live ? e / it.nb : 0, b = live ? e % it.nb : 0;
     double2 sv = make_double2(0.0, 0.0);
     if (live)
-        for (int c = l; c < nchunks; c += 4) sv = cadd(sv, part[((int64_t(blockIdx.x) * nchunks + c) * DT + v) * BMAX + b]);
+        for (int c = l; c < nchunks; c += 4) sv = cadd(sv, part[((int64_t(blockIdx.x) * nchunks + c) * tu + v) * BMAX + b]);
     for (int o = 1; o < 4; o <<= 1) {
         sv.x += __shfl_xor(sv.x, o, 4);
         sv.y += __shfl_xor(sv.y, o, 4);
@@ -169,52 +176,57 @@ __global__ __launch_bounds__(256) void k_bdots_fin(const DItem *__restrict__ ite
     if (live && l == 0) it.dst[int64_t(it.k0 + v) * it.ld + b] = sv;
 }
 
-// 64 rows per block; thread (rows v, v + 32 with v = t % 32, h = t / 32)
-// accumulates columns h, h + 8, ...; 32 basis vectors and their coefficient
+// 128 rows per block; thread (rows v + 32 u, u < 4, with v = t % 32, h = t / 32)
+// accumulates columns h, h + 8, ...; 16 basis vectors and their coefficient
 // rows staged in LDS per round.
 template <typename AT, typename OT, int NB>
 __global__ __launch_bounds__(256) void k_bcomb(const CItem *__restrict__ items, int64_t N)
 {
-    constexpr int NC = (NB + 7) / 8;
+    constexpr int NC = (NB + 7) / 8, KS = 16, RT = 128;
     const CItem it = items[blockIdx.y];
     if (it.flag && *it.flag == 0) return;
     const int t = threadIdx.x, v = t & 31, h = t >> 5;
-    const int64_t n0 = int64_t(blockIdx.x) * 64;
-    __shared__ double2 As[32][65];
-    __shared__ double2 Cs[32][8 * NC];
-    __shared__ int64_t Aoff[32];
-    double2 acc0[NC], acc1[NC];
+    const int64_t n0 = int64_t(blockIdx.x) * RT;
+    __shared__ double2 As[KS][RT + 1];
+    __shared__ double2 Cs[KS][8 * NC];
+    __shared__ int64_t Aoff[KS];
+    double2 acc[4][NC];
 #pragma unroll
-    for (int q = 0; q < NC; ++q) acc0[q] = acc1[q] = make_double2(0.0, 0.0);
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int q = 0; q < NC; ++q) acc[u][q] = make_double2(0.0, 0.0);
     const AT *A = static_cast<const AT *>(it.A);
-    for (int k0 = 0; k0 < it.K; k0 += 32) {
-        const int kc = min(32, it.K - k0);
+    for (int k0 = 0; k0 < it.K; k0 += KS) {
+        const int kc = min(KS, it.K - k0);
         __syncthreads();
-        if (t < 32) {
+        if (t < KS) {
             const int k = k0 + t;
             Aoff[t] = t < kc ? (int64_t(k / it.ar) * it.astride + k % it.ar) * N : 0;
         }
-        for (int e = t; e < 32 * 8 * NC; e += 256) {
+        for (int e = t; e < KS * 8 * NC; e += 256) {
             const int kk = e / (8 * NC), b = e % (8 * NC);
             Cs[kk][b] = (kk < kc && b < it.nb) ? it.C[int64_t(k0 + kk) * it.ldc + b] : make_double2(0.0, 0.0);
         }
         __syncthreads();
-        for (int e = t; e < 32 * 64; e += 256) {
-            const int kk = e >> 6, rr = e & 63;
+        for (int e = t; e < KS * RT; e += 256) {
+            const int kk = e / RT, rr = e % RT;
             const int64_t nn = n0 + rr;
             As[kk][rr] = (kk < kc && nn < N) ? to_d2(A[Aoff[kk] + nn]) : make_double2(0.0, 0.0);
         }
         __syncthreads();
 #pragma unroll 2
         for (int kk = 0; kk < kc; ++kk) {
-            const double2 a0 = As[kk][v], a1 = As[kk][v + 32];
+            double2 a[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) a[u] = As[kk][v + 32 * u];
 #pragma unroll
             for (int q = 0; q < NC; ++q) {
                 const double2 c = Cs[kk][h + 8 * q];
-                acc0[q].x = fma(a0.x, c.x, fma(-a0.y, c.y, acc0[q].x));
-                acc0[q].y = fma(a0.x, c.y, fma(a0.y, c.x, acc0[q].y));
-                acc1[q].x = fma(a1.x, c.x, fma(-a1.y, c.y, acc1[q].x));
-                acc1[q].y = fma(a1.x, c.y, fma(a1.y, c.x, acc1[q].y));
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    acc[u][q].x = fma(a[u].x, c.x, fma(-a[u].y, c.y, acc[u][q].x));
+                    acc[u][q].y = fma(a[u].x, c.y, fma(a[u].y, c.x, acc[u][q].y));
+                }
             }
         }
     }
@@ -225,10 +237,10 @@ __global__ __launch_bounds__(256) void k_bcomb(const CItem *__restrict__ items, 
         if (b < it.nb) {
             const int64_t col = int64_t(it.ocol ? it.ocol[b] : b) * N;
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
+            for (int u = 0; u < 4; ++u) {
                 const int64_t n = n0 + v + 32 * u;
                 if (n < N) {
-                    double2 y = cscale(it.alpha, u ? acc1[q] : acc0[q]);
+                    double2 y = cscale(it.alpha, acc[u][q]);
                     if (it.beta != 0.0) y = cadd(y, cscale(it.beta, to_d2(out[col + n])));
                     out[col + n] = from_d2<OT>(y);
                 }
@@ -293,13 +305,13 @@ struct GDev {
 };
 
 // The Gram matrix after the first update (G2) against the one before (G1)
-// decides whether a second pass runs: any column that kept less than half of
-// its norm squared.
-__global__ __launch_bounds__(64) void k_bflag(GDev *__restrict__ gd, const int *__restrict__ gids)
+// decides whether a second pass runs: any column that kept less than `keep`
+// of its norm squared (0: never).
+__global__ __launch_bounds__(64) void k_bflag(GDev *__restrict__ gd, const int *__restrict__ gids, double keep)
 {
     GDev g = gd[gids[blockIdx.x]];
     const int r = g.r, a = threadIdx.x;
-    const bool lost = a < r && g.G2[a * r + a].x < 0.5 * g.G1[a * r + a].x;
+    const bool lost = a < r && g.G2[a * r + a].x < keep * g.G1[a * r + a].x;
     const unsigned long long any = __ballot(lost);
     if (a == 0) g.flag[0] = any != 0ull;
 }
@@ -677,7 +689,8 @@ struct HGroup {
 
 int pick_nb(int n) { return n <= 4 ? 4 : n <= 8 ? 8 : n <= 16 ? 16 : 32; }
 
-template <typename AT>
+// U = 4: tiles of 128 basis vectors (basis dots); U = 1: tiles of 32 (Gram matrices)
+template <typename AT, int U = 4>
 void launch_dots(const DItem *d, size_t ni, int64_t N, double2 *part, int nbmax, hipStream_t s)
 {
     if (ni == 0) return;
@@ -686,12 +699,12 @@ void launch_dots(const DItem *d, size_t ni, int64_t N, double2 *part, int nbmax,
     const int nchunks = int((N + L - 1) / L);
     const dim3 grid{ unsigned(nchunks), unsigned(ni) };
     const int nq = (nbmax + 3) / 4;
-    if (nq <= 1) hipLaunchKernelGGL((k_bdots<AT, 1>), grid, dim3(256), 0, s, d, N, nchunks, L, part);
-    else if (nq <= 2) hipLaunchKernelGGL((k_bdots<AT, 2>), grid, dim3(256), 0, s, d, N, nchunks, L, part);
-    else if (nq <= 4) hipLaunchKernelGGL((k_bdots<AT, 4>), grid, dim3(256), 0, s, d, N, nchunks, L, part);
-    else hipLaunchKernelGGL((k_bdots<AT, 8>), grid, dim3(256), 0, s, d, N, nchunks, L, part);
-    hipLaunchKernelGGL(k_bdots_fin, dim3(unsigned(ni), unsigned((DT * BMAX) / 64)), dim3(256), 0, s, d, nchunks,
-                       (const double2 *)part);
+    if (nq <= 1) hipLaunchKernelGGL((k_bdots<AT, 1, U>), grid, dim3(256), 0, s, d, N, nchunks, L, part);
+    else if (nq <= 2) hipLaunchKernelGGL((k_bdots<AT, 2, U>), grid, dim3(256), 0, s, d, N, nchunks, L, part);
+    else if (nq <= 4) hipLaunchKernelGGL((k_bdots<AT, 4, U>), grid, dim3(256), 0, s, d, N, nchunks, L, part);
+    else hipLaunchKernelGGL((k_bdots<AT, 8, U>), grid, dim3(256), 0, s, d, N, nchunks, L, part);
+    hipLaunchKernelGGL(k_bdots_fin, dim3(unsigned(ni), unsigned((32 * U * BMAX) / 64)), dim3(256), 0, s, d, nchunks,
+                       32 * U, (const double2 *)part);
     BIE_HIP(hipGetLastError());
 }
 
@@ -699,7 +712,7 @@ template <typename AT, typename OT>
 void launch_comb(const CItem *d, size_t ni, int64_t N, int nbmax, hipStream_t s)
 {
     if (ni == 0) return;
-    const dim3 grid(unsigned((N + 63) / 64), unsigned(ni));
+    const dim3 grid(unsigned((N + 127) / 128), unsigned(ni));
     switch (pick_nb(nbmax)) {
     case 4: hipLaunchKernelGGL((k_bcomb<AT, OT, 4>), grid, dim3(256), 0, s, d, N); break;
     case 8: hipLaunchKernelGGL((k_bcomb<AT, OT, 8>), grid, dim3(256), 0, s, d, N); break;
@@ -790,13 +803,18 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
     const int terms = o.inner_terms ? o.inner_terms : 3;
     const double itol = std::max(o.inner_tol > 0.0 ? o.inner_tol : 1e-3, terms == 2 ? 1e-2 : 0.0);
     const int64_t Gmax = (R + p - 1) / p;
+    // second Gram-Schmidt pass when a column keeps less than half its norm
+    // squared; none with the complex64 basis of the refinement's inner solves,
+    // whose storage already bounds orthogonality near 1e-7 against their
+    // tolerance of 1e-3 .. 1e-1
+    const double reorth = mixed ? 0.0 : 0.5;
 
     Bufs db;
     double2 *Rres = db.get<double2>(size_t(R) * N);
     double2 *Wb = db.get<double2>(size_t(R) * N);
     VT *V = db.get<VT>(size_t(m + 1) * R * N);
-    const int64_t tiles = ((m + 1) * p + DT - 1) / DT + 1;
-    double2 *part = db.get<double2>(size_t(Gmax * tiles + 2048) * DT * BMAX);
+    const int64_t tiles = ((m + 1) * p + DT - 1) / DT + 1;   // basis tiles per group, and its Gram item
+    double2 *part = db.get<double2>(size_t(Gmax * tiles + 1024) * DT * BMAX);
     const int nparts = int(std::min<int64_t>(64, (N + 255) / 256));
     double *npart = db.get<double>(size_t(R) * nparts);
     double *nrm = db.get<double>(size_t(R));
@@ -939,7 +957,7 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
             ar.flush(s);
             hipLaunchKernelGGL(k_bgather, dim3(unsigned(std::min<int64_t>((N + 255) / 256, 64)), unsigned(live.size())),
                                dim3(256), 0, s, N, (const double2 *)Rres, dl, Wb);
-            launch_dots<double2>(di, it.size(), N, part, p, s);
+            launch_dots<double2, 1>(di, it.size(), N, part, p, s);
         }
         std::vector<std::vector<cd>> hG(ng);
         for (int g = 0; g < ng; ++g) {
@@ -1041,14 +1059,22 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
                 const VT *Vj = V + int64_t(j) * Wc * N;
                 if (mixed) gemm_product(op, Vj, N, VEC_C64, Wb, N, nullptr, 0, int64_t(cols.size()), dc, s, terms);
                 else gemm64_product(op, Vj, N, Wb, N, nullptr, 0, int64_t(cols.size()), dc, s);
+                int64_t pairs = 0;   // basis vector x column pairs of the first pass
+                for (int g : act) pairs += int64_t(j + 1) * grp[g].r * grp[g].r;
+                prof_begin(4, s, pairs);
                 launch_dots<VT>(pv0, dv[0].size(), N, part, p, s);
-                launch_dots<double2>(ppre, dpre.size(), N, part, p, s);
+                prof_end(4, s);
+                launch_dots<double2, 1>(ppre, dpre.size(), N, part, p, s);
+                prof_begin(5, s, pairs);
                 launch_comb<VT, double2>(pc0, ci[0].size(), N, p, s);
-                launch_dots<double2>(pp0, dpost[0].size(), N, part, p, s);
-                hipLaunchKernelGGL(k_bflag, dim3(unsigned(na)), dim3(64), 0, s, gd, dg);
-                launch_dots<VT>(pv1, dv[1].size(), N, part, p, s);
-                launch_comb<VT, double2>(pc1, ci[1].size(), N, p, s);
-                launch_dots<double2>(pp1, dpost[1].size(), N, part, p, s);
+                prof_end(5, s);
+                launch_dots<double2, 1>(pp0, dpost[0].size(), N, part, p, s);
+                hipLaunchKernelGGL(k_bflag, dim3(unsigned(na)), dim3(64), 0, s, gd, dg, reorth);
+                if (reorth > 0.0) {
+                    launch_dots<VT>(pv1, dv[1].size(), N, part, p, s);
+                    launch_comb<VT, double2>(pc1, ci[1].size(), N, p, s);
+                    launch_dots<double2, 1>(pp1, dpost[1].size(), N, part, p, s);
+                }
                 hipLaunchKernelGGL(k_bchol, dim3(unsigned(na)), dim3(256), 0, s, gd, dg, j, m, DELTA);
                 BIE_HIP(hipEventRecord(ev_chol, s));
                 launch_comb<double2, VT>(pcs, cs.size(), N, p, s);

@@ -32,7 +32,8 @@ namespace bie {
 // Optional timing of the dense product kernels: events recorded on the launch
 // stream around every launch (record 0: tile pass of the packed FP64/FP32
 // product, 1: split-BF16 block product, 2: FP64 block product, 3: reduction of
-// the packed product's partial sums).
+// the packed product's partial sums, 4: block GMRES basis dots, 5: block GMRES
+// basis update).
 namespace prof {
 bool on = false;
 struct Rec {
@@ -40,7 +41,7 @@ struct Rec {
     size_t used = 0;
     int64_t cols = 0;   // right-hand sides over the recorded launches
 };
-Rec rec[4];
+Rec rec[6];
 
 void begin(int k, hipStream_t s, int64_t ncols)
 {
@@ -71,7 +72,7 @@ void prof_end(int kernel, hipStream_t s) { prof::end(kernel, s); }
 
 void prof_read(int kernel, int64_t *launches, double *total_ms, int64_t *columns)
 {
-    if (kernel < 0 || kernel > 3) throw Error(BIE_EINVAL, "unknown kernel record");
+    if (kernel < 0 || kernel > 5) throw Error(BIE_EINVAL, "unknown kernel record");
     prof::Rec &r = prof::rec[kernel];
     double t = 0.0;
     for (size_t i = 0; i < r.used; ++i) {
