@@ -249,6 +249,173 @@ __global__ __launch_bounds__(256) void k_bcomb(const CItem *__restrict__ items, 
     }
 }
 
+// FP32 matrix-core forms of the dots and the update for the complex64 basis of
+// the refinement's inner solves (FP32 products, FP32 accumulation; the inner
+// tolerance is 1e-3 .. 1e-1).  v_mfma_f32_32x32x2f32: A[i][k] in lane i + 32 k,
+// B[k][j] in lane j + 32 k, D value q of lane l at row 8 (q / 4) + 4 (l / 32) +
+// q % 4, column l % 32.  Complex products as four real ones.
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ inline f32x16 mfma32(float a, float b, f32x16 c) { return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0); }
+
+// Dots C = V^H W over a chunk of L rows, tiles of 128 basis vectors (one 32 x 32
+// output tile per wave) against up to 32 columns; partials as k_bdots with U = 4.
+__global__ __launch_bounds__(256) void k_bdots_mf(const DItem *__restrict__ items, int64_t N, int nchunks, int64_t L,
+                                                  double2 *__restrict__ part)
+{
+    constexpr int MS = 32;   // rows per LDS stage
+    const DItem it = items[blockIdx.y];
+    if (it.flag && *it.flag == 0) return;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int64_t n0 = int64_t(blockIdx.x) * L, n1 = min(N, n0 + L);
+    __shared__ float2 As[MS][128 + 1];
+    __shared__ float2 Bs[MS][32 + 1];
+    __shared__ int64_t Aoff[128];
+    if (t < 128) {
+        const int k = it.k0 + t;
+        Aoff[t] = t < it.kc ? (int64_t(k / it.ar) * it.astride + k % it.ar) * N : 0;
+    }
+    f32x16 cr, ci;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) cr[q] = ci[q] = 0.f;
+    const float2 *A = static_cast<const float2 *>(it.A);
+    // each thread stages 16 basis entries and 4 column entries per stage; the
+    // next stage is loaded into registers while the current one is multiplied
+    float2 ra[16];
+    double2 rb[4];
+    auto gload = [&](int64_t ns) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int e = t + 256 * u, vv = e / MS, rr = e % MS;
+            const int64_t n = ns + rr;
+            ra[u] = (vv < it.kc && n < n1) ? A[Aoff[vv] + n] : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = t + 256 * u, b = e / MS, rr = e % MS;
+            const int64_t n = ns + rr;
+            rb[u] = (b < it.nb && n < n1) ? it.Bm[int64_t(b) * N + n] : make_double2(0.0, 0.0);
+        }
+    };
+    __syncthreads();   // Aoff
+    if (n0 < n1) gload(n0);
+    for (int64_t ns = n0; ns < n1; ns += MS) {
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int e = t + 256 * u;
+            As[e % MS][e / MS] = ra[u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = t + 256 * u;
+            Bs[e % MS][e / MS] = make_float2(float(rb[u].x), float(rb[u].y));
+        }
+        __syncthreads();
+        if (ns + MS < n1) gload(ns + MS);
+#pragma unroll 4
+        for (int rr = 0; rr < MS; rr += 2) {
+            const float2 a = As[rr + (lane >> 5)][32 * w + (lane & 31)];
+            const float2 b = Bs[rr + (lane >> 5)][lane & 31];
+            cr = mfma32(a.x, b.x, cr);
+            cr = mfma32(a.y, b.y, cr);
+            ci = mfma32(a.x, b.y, ci);
+            ci = mfma32(-a.y, b.x, ci);
+        }
+    }
+    double2 *o = part + (int64_t(blockIdx.y) * nchunks + blockIdx.x) * 128 * BMAX;
+    const int col = lane & 31;
+    if (col < it.nb) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int v = 32 * w + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+            if (v < it.kc) o[v * BMAX + col] = make_double2(double(cr[q]), double(ci[q]));
+        }
+    }
+}
+
+// Update out_b = beta out_b + alpha (V C)_b on 128 rows per block (one 32 x 32
+// output tile per wave), 32 basis vectors per LDS stage.
+__global__ __launch_bounds__(256) void k_bcomb_mf(const CItem *__restrict__ items, int64_t N)
+{
+    constexpr int KS = 32;
+    const CItem it = items[blockIdx.y];
+    if (it.flag && *it.flag == 0) return;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int64_t n0 = int64_t(blockIdx.x) * 128;
+    __shared__ float2 As[KS][128 + 1];
+    __shared__ float2 Cs[KS][32 + 1];
+    __shared__ int64_t Aoff[KS];
+    f32x16 orr, oi;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) orr[q] = oi[q] = 0.f;
+    const float2 *A = static_cast<const float2 *>(it.A);
+    // 16 basis entries and 4 coefficients per thread and stage; the next stage
+    // is loaded into registers while the current one is multiplied
+    float2 ra[16];
+    double2 rc[4];
+    auto offs = [&](int k0) {
+        if (t < KS) {
+            const int k = k0 + t;
+            Aoff[t] = k < it.K ? (int64_t(k / it.ar) * it.astride + k % it.ar) * N : 0;
+        }
+    };
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int e = t + 256 * u, kk = e / 128, rr = e % 128;
+            const int64_t nn = n0 + rr;
+            ra[u] = (k0 + kk < it.K && nn < N) ? A[Aoff[kk] + nn] : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = t + 256 * u, kk = e / 32, b = e % 32;
+            rc[u] = (k0 + kk < it.K && b < it.nb) ? it.C[int64_t(k0 + kk) * it.ldc + b] : make_double2(0.0, 0.0);
+        }
+    };
+    offs(0);
+    __syncthreads();
+    gload(0);
+    for (int k0 = 0; k0 < it.K; k0 += KS) {
+        __syncthreads();   // previous stage's LDS reads and Aoff reads done
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int e = t + 256 * u;
+            As[e / 128][e % 128] = ra[u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = t + 256 * u;
+            Cs[e / 32][e % 32] = make_float2(float(rc[u].x), float(rc[u].y));
+        }
+        offs(k0 + KS);
+        __syncthreads();
+        if (k0 + KS < it.K) gload(k0 + KS);
+#pragma unroll 4
+        for (int kk = 0; kk < KS; kk += 2) {
+            const float2 a = As[kk + (lane >> 5)][32 * w + (lane & 31)];
+            const float2 c = Cs[kk + (lane >> 5)][lane & 31];
+            orr = mfma32(a.x, c.x, orr);
+            orr = mfma32(-a.y, c.y, orr);
+            oi = mfma32(a.x, c.y, oi);
+            oi = mfma32(a.y, c.x, oi);
+        }
+    }
+    const int col = lane & 31;
+    if (col >= it.nb) return;
+    double2 *out = static_cast<double2 *>(it.out);
+    const int64_t ob = int64_t(it.ocol ? it.ocol[col] : col) * N;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int64_t n = n0 + 32 * w + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+        if (n < N) {
+            double2 y = make_double2(it.alpha * double(orr[q]), it.alpha * double(oi[q]));
+            if (it.beta != 0.0) y = cadd(y, cscale(it.beta, out[ob + n]));
+            out[ob + n] = y;
+        }
+    }
+}
+
 // dst[i * N + n] = src[cols[i] * N + n]
 __global__ __launch_bounds__(256) void k_bgather(int64_t N, const double2 *__restrict__ src, const int *__restrict__ cols,
                                                  double2 *__restrict__ dst)
@@ -722,6 +889,40 @@ void launch_comb(const CItem *d, size_t ni, int64_t N, int nbmax, hipStream_t s)
     BIE_HIP(hipGetLastError());
 }
 
+void launch_dots_mf(const DItem *d, size_t ni, int64_t N, double2 *part, hipStream_t s)
+{
+    if (ni == 0) return;
+    const int64_t nch = std::max<int64_t>(1, std::min<int64_t>((1024 + int64_t(ni) - 1) / int64_t(ni), (N + 127) / 128));
+    const int64_t L = ((N + nch - 1) / nch + 31) / 32 * 32;
+    const int nchunks = int((N + L - 1) / L);
+    hipLaunchKernelGGL(k_bdots_mf, dim3(unsigned(nchunks), unsigned(ni)), dim3(256), 0, s, d, N, nchunks, L, part);
+    hipLaunchKernelGGL(k_bdots_fin, dim3(unsigned(ni), unsigned((128 * BMAX) / 64)), dim3(256), 0, s, d, nchunks, 128,
+                       (const double2 *)part);
+    BIE_HIP(hipGetLastError());
+}
+
+void launch_comb_mf(const CItem *d, size_t ni, int64_t N, hipStream_t s)
+{
+    if (ni == 0) return;
+    hipLaunchKernelGGL(k_bcomb_mf, dim3(unsigned((N + 127) / 128), unsigned(ni)), dim3(256), 0, s, d, N);
+    BIE_HIP(hipGetLastError());
+}
+
+// basis dots and updates: FP32 matrix cores for the complex64 basis, FP64 vector
+// ALUs for the FP64 basis
+template <typename VT>
+void basis_dots(const DItem *d, size_t ni, int64_t N, double2 *part, int nbmax, hipStream_t s)
+{
+    if constexpr (sizeof(VT) == 8) launch_dots_mf(d, ni, N, part, s);
+    else launch_dots<VT>(d, ni, N, part, nbmax, s);
+}
+template <typename VT>
+void basis_comb(const CItem *d, size_t ni, int64_t N, int nbmax, hipStream_t s)
+{
+    if constexpr (sizeof(VT) == 8) launch_comb_mf(d, ni, N, s);
+    else launch_comb<VT, double2>(d, ni, N, nbmax, s);
+}
+
 // Rank-revealing orthonormalisation of the unit-scaled residual block from its
 // Gram matrix G (q x q, row-major): pivoted Cholesky P^T Gs P = L L^H stopped at
 // pivots <= delta^2.  Returns r; T0 (q x r) maps the unscaled residual columns
@@ -1062,17 +1263,17 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
                 int64_t pairs = 0;   // basis vector x column pairs of the first pass
                 for (int g : act) pairs += int64_t(j + 1) * grp[g].r * grp[g].r;
                 prof_begin(4, s, pairs);
-                launch_dots<VT>(pv0, dv[0].size(), N, part, p, s);
+                basis_dots<VT>(pv0, dv[0].size(), N, part, p, s);
                 prof_end(4, s);
                 launch_dots<double2, 1>(ppre, dpre.size(), N, part, p, s);
                 prof_begin(5, s, pairs);
-                launch_comb<VT, double2>(pc0, ci[0].size(), N, p, s);
+                basis_comb<VT>(pc0, ci[0].size(), N, p, s);
                 prof_end(5, s);
                 launch_dots<double2, 1>(pp0, dpost[0].size(), N, part, p, s);
                 hipLaunchKernelGGL(k_bflag, dim3(unsigned(na)), dim3(64), 0, s, gd, dg, reorth);
                 if (reorth > 0.0) {
-                    launch_dots<VT>(pv1, dv[1].size(), N, part, p, s);
-                    launch_comb<VT, double2>(pc1, ci[1].size(), N, p, s);
+                    basis_dots<VT>(pv1, dv[1].size(), N, part, p, s);
+                    basis_comb<VT>(pc1, ci[1].size(), N, p, s);
                     launch_dots<double2, 1>(pp1, dpost[1].size(), N, part, p, s);
                 }
                 hipLaunchKernelGGL(k_bchol, dim3(unsigned(na)), dim3(256), 0, s, gd, dg, j, m, DELTA);
@@ -1135,7 +1336,7 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
                                                dim3(256), 0, s, gd, de, gsteps, I, m);
                     }
                     BIE_HIP(hipGetLastError());
-                    launch_comb<VT, double2>(pit, it.size(), N, p, s);
+                    basis_comb<VT>(pit, it.size(), N, p, s);
                 }
             }
             BIE_HIP(hipEventRecord(ev_arena[j & 1], s));
