@@ -56,7 +56,9 @@ def parse():
     ap.add_argument("--restart", type=int, default=50)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--inner-tol", type=float, default=1e-1)
-    ap.add_argument("--inner-terms", type=int, default=3, choices=[2, 3])
+    ap.add_argument("--inner-terms", type=int, default=None, choices=[2, 3],
+                    help="terms of the inner split-BF16 products: 3 (hi/lo matrix x hi/lo vectors) or 2 (hi/lo "
+                         "matrix x BF16 vectors); default 2 for block GMRES, 3 for column GMRES")
     ap.add_argument("--basis", default="f16", choices=["f16", "c64"],
                     help="storage of the inner Krylov basis (FP16 pairs or complex64)")
     ap.add_argument("--slots", type=int, default=256)
@@ -81,6 +83,8 @@ def parse():
                     help="only launch the dense product kernels a few times at the bench sizes, and a 1 GiB "
                          "device copy as calibration, for hardware-counter runs")
     a = ap.parse_args()
+    if a.inner_terms is None:
+        a.inner_terms = 2 if a.method == "bgmres" else 3
     if a.c5:
         a.train_dirs, a.test_dirs, a.epochs = 2048, 512, 3000
     return a
@@ -325,8 +329,8 @@ def headline_leg(args, bie, torch, V, T, k):
     achieved = alg_flops / (avg * 1e-3) / 1e12
     roof = {"bound": "mfma", "achieved": round(achieved, 1), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": round(achieved / BF16_PEAK_TFLOPS, 4),
-            "traffic": traffic_from_profiles("gemm_split_bf16_n7680_r256_counters.txt", "gemm.hip", N),
-            "traffic_note": "HBM bytes per launch at 256 columns (counters), null if the kernel changed since",
+            "traffic": traffic_from_profiles("gemm_split_bf16_n7680_r512_counters.txt", "gemm.hip", N),
+            "traffic_note": "HBM bytes per launch at 512 columns (counters), null if the kernel changed since",
             "kernel": "split-BF16 complex block product (k_gemm_split, v_mfma_f32_32x32x16_bf16)",
             "alg_flops_per_launch": alg_flops, "issued_tflops": round(3 * achieved, 1),
             "avg_columns_per_launch": round(g_cols / max(1, g_launch), 1),
@@ -542,13 +546,13 @@ def uneven_batch_leg(args, bie, torch):
 def counters_probe(args, bie, torch):
     """Kernels for the HBM traffic counters: 5 launches each of the packed FP64
     product (one column), the split-BF16 block product and the FP64 block product
-    (256 columns) on the bench operator, and 3 plain copies of 1 GiB
-    (FETCH_SIZE / WRITE_SIZE calibration)."""
+    (512 columns, the headline's 16 groups of 32) on the bench operator, and 3
+    plain copies of 1 GiB (FETCH_SIZE / WRITE_SIZE calibration)."""
     from paper_2606_13482_amd.inputs import icosphere, complex_gaussian
     V, T = icosphere(args.level)
     op = bie.Operator(V, T, args.k, storage="split_bf16")
     x = torch.from_numpy(complex_gaussian(op.N, 7)).cuda().reshape(1, -1)
-    Xb = torch.from_numpy(complex_gaussian(op.N, 7, cols=256)).cuda()
+    Xb = torch.from_numpy(complex_gaussian(op.N, 7, cols=512)).cuda()
     for _ in range(5):
         op.apply(x)
     for _ in range(5):
@@ -561,7 +565,7 @@ def counters_probe(args, bie, torch):
         b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"counters_probe": {"N": op.N, "packed_fp64_launches": 5, "block_launches": 5,
-                                         "block_columns": 256, "copy_bytes": a.numel() * 4, "copies": 3}}),
+                                         "block_columns": 512, "copy_bytes": a.numel() * 4, "copies": 3}}),
           flush=True)
     op.close()
 

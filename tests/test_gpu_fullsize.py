@@ -117,23 +117,25 @@ def test_full_size_large_sphere_solve(bie):
     op.close()
 
 
-def test_full_size_headline_block_solve(bie):
+@pytest.mark.parametrize("terms", [2, 3])
+def test_full_size_headline_block_solve(bie, terms):
     """The bench's default mixed form (block GMRES(50) over groups of 32 on
-    split-BF16 products, FP64 refinement) on 64 plane waves at 7680 unknowns:
-    every residual at most 1e-6 against the oracle's full matrix and equal to the
-    reported SCC."""
+    split-BF16 products, 2 terms by default, FP64 refinement) on 64 plane waves at
+    7680 unknowns: every residual at most 1e-6 against the oracle's full matrix and
+    equal to the reported SCC."""
     V, T, rwg, _ = _mesh(4)
     op = bie.Operator(V, T, 10.0, storage="split_bf16")
     d, e = planewave_set(random_directions(32, 80), "theta")
     d2, e2 = planewave_set(random_directions(32, 80), "phi")
     B = op.rhs(np.concatenate([d, d2]), np.concatenate([e, e2]))
-    X, st = op.solve(B, bie.Solve(method="bgmres", block=32, restart=50, tol=1e-6, precision="mixed", inner_tol=0.1))
+    X, st = op.solve(B, bie.Solve(method="bgmres", block=32, restart=50, tol=1e-6, precision="mixed", inner_tol=0.1,
+                                  inner_terms=terms))
     op.close()
     Zo = cfill.fill(rwg, 10.0)
     Bn, Xn = B.cpu().numpy(), X.cpu().numpy()
     res = np.linalg.norm(Bn - Xn @ Zo.T, axis=1) / np.linalg.norm(Bn, axis=1)
     rep = np.array([s["relres_true"] for s in st])
-    _say(f"  block form, 7680 unknowns: max residual {res.max():.3e}, reported {rep.max():.3e}, "
+    _say(f"  block form ({terms} terms), 7680 unknowns: max residual {res.max():.3e}, reported {rep.max():.3e}, "
          f"iterations {int(np.mean([s['iters'] for s in st]))} mean")
     assert all(s["converged"] for s in st)
     assert res.max() <= 1e-6 * (1 + 1e-6)
