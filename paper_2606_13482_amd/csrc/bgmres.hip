@@ -1050,7 +1050,7 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
                                         std::make_unique<Arena>(size_t(8) << 20) };
     Aux aux;
     hipStream_t s2 = aux.s2;
-    hipEvent_t ev_chol = aux.ev[0], ev_ls[2] = { aux.ev[1], aux.ev[2] }, ev_arena[2] = { aux.ev[3], aux.ev[4] };
+    hipEvent_t ev_prod = aux.ev[0], ev_ls[2] = { aux.ev[1], aux.ev[2] }, ev_arena[2] = { aux.ev[3], aux.ev[4] };
     BIE_HIP(hipEventRecord(ev_arena[0], s));
     BIE_HIP(hipEventRecord(ev_arena[1], s));
     double *hest[2];
@@ -1210,9 +1210,9 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
         }
         // (3) block Arnoldi steps; every active group advances together.  The
         // least-squares update of step j runs on the second stream beside the
-        // product and orthogonalisation of step j + 1; its estimates are read
-        // one step late, so a group that has met its targets runs at most one
-        // step more (discarded: its solution uses the steps up to the decision).
+        // orthogonalisation of step j + 1; its estimates are read one step late,
+        // so a group that has met its targets runs at most one step more
+        // (discarded: its solution uses the steps up to the decision).
         int prev = -1;
         std::vector<int> prev_act;
         for (int j = 0; j <= m; ++j) {
@@ -1227,6 +1227,31 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
             Arena &A = *arena[j & 1];
             BIE_HIP(hipEventSynchronize(ev_arena[j & 1]));
             A.reset();
+            // least-squares update of step prev on the second stream, queued after
+            // this step's product so that it shares the GPU with the smaller
+            // kernels of the step instead of with the product's workgroups
+            bool ls_queued = false;
+            auto launch_ls = [&]() {
+                if (prev < 0 || ls_queued) return;
+                ls_queued = true;
+                std::vector<int> lsg;
+                for (int g : prev_act)
+                    if (grp[g].active) lsg.push_back(g);
+                if (!lsg.empty()) {
+                    const int *dls = A.put(lsg);
+                    A.flush(s);
+                    BIE_HIP(hipEventRecord(ev_prod, s));
+                    BIE_HIP(hipStreamWaitEvent(s2, ev_prod, 0));
+                    hipLaunchKernelGGL(k_bls_apply, dim3(unsigned(lsg.size()), unsigned((p + CS - 1) / CS)), dim3(256), 0,
+                                       s2, gd, dls, prev, m);
+                    hipLaunchKernelGGL(k_bls_qr, dim3(unsigned(lsg.size())), dim3(256), 0, s2, gd, dls, prev, m);
+                    BIE_HIP(hipGetLastError());
+                }
+                BIE_HIP(hipMemcpyAsync(hest[prev & 1], gest, size_t(ng) * BMAX * sizeof(double), hipMemcpyDeviceToHost,
+                                       s2));
+                BIE_HIP(hipMemcpyAsync(hfl[prev & 1], gflag, size_t(ng) * 4 * sizeof(int), hipMemcpyDeviceToHost, s2));
+                BIE_HIP(hipEventRecord(ev_ls[prev & 1], s2));
+            };
             if (!act.empty()) {
                 const int na = int(act.size());
                 // tables of the step: pass 1 basis dots, Gram before and after,
@@ -1260,6 +1285,7 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
                 const VT *Vj = V + int64_t(j) * Wc * N;
                 if (mixed) gemm_product(op, Vj, N, VEC_C64, Wb, N, nullptr, 0, int64_t(cols.size()), dc, s, terms);
                 else gemm64_product(op, Vj, N, Wb, N, nullptr, 0, int64_t(cols.size()), dc, s);
+                launch_ls();
                 int64_t pairs = 0;   // basis vector x column pairs of the first pass
                 for (int g : act) pairs += int64_t(j + 1) * grp[g].r * grp[g].r;
                 prof_begin(4, s, pairs);
@@ -1277,17 +1303,9 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
                     launch_dots<double2, 1>(pp1, dpost[1].size(), N, part, p, s);
                 }
                 hipLaunchKernelGGL(k_bchol, dim3(unsigned(na)), dim3(256), 0, s, gd, dg, j, m, DELTA);
-                BIE_HIP(hipEventRecord(ev_chol, s));
                 launch_comb<double2, VT>(pcs, cs.size(), N, p, s);
-                BIE_HIP(hipStreamWaitEvent(s2, ev_chol, 0));
-                hipLaunchKernelGGL(k_bls_apply, dim3(unsigned(na), unsigned((p + CS - 1) / CS)), dim3(256), 0, s2, gd,
-                                   dg, j, m);
-                hipLaunchKernelGGL(k_bls_qr, dim3(unsigned(na)), dim3(256), 0, s2, gd, dg, j, m);
-                BIE_HIP(hipGetLastError());
-                BIE_HIP(hipMemcpyAsync(hest[j & 1], gest, size_t(ng) * BMAX * sizeof(double), hipMemcpyDeviceToHost, s2));
-                BIE_HIP(hipMemcpyAsync(hfl[j & 1], gflag, size_t(ng) * 4 * sizeof(int), hipMemcpyDeviceToHost, s2));
-                BIE_HIP(hipEventRecord(ev_ls[j & 1], s2));
             }
+            launch_ls();   // no step j: the update of step prev right away
             if (prev >= 0) {
                 BIE_HIP(hipEventSynchronize(ev_ls[prev & 1]));
                 const double *est = hest[prev & 1];
