@@ -478,7 +478,7 @@ __global__ __launch_bounds__(64) void k_bflag(GDev *__restrict__ gd, const int *
 {
     GDev g = gd[gids[blockIdx.x]];
     const int r = g.r, a = threadIdx.x;
-    const bool lost = a < r && g.G2[a * r + a].x < keep * g.G1[a * r + a].x;
+    const bool lost = keep > 0.0 && a < r && g.G2[a * r + a].x < keep * g.G1[a * r + a].x;
     const unsigned long long any = __ballot(lost);
     if (a == 0) g.flag[0] = any != 0ull;
 }
@@ -486,7 +486,8 @@ __global__ __launch_bounds__(64) void k_bflag(GDev *__restrict__ gd, const int *
 // Complete Hbar(:, j) = [C1 + C2; R] (C1 already in place) with R^H R = G2 (Cholesky of the Gram
 // matrix of W after the last pass), and R^{-1} for the next basis block.  A
 // pivot at or below delta^2 times the largest squared column norm of T V_j
-// marks a partial breakdown; that direction gets a zero row in R.
+// (G2_aa + sum_k |H_ka|^2: the part removed plus the part kept) marks a partial
+// breakdown; that direction gets a zero row in R.
 __global__ __launch_bounds__(256) void k_bchol(GDev *__restrict__ gd, const int *__restrict__ gids, int j, int m,
                                                double delta)
 {
@@ -501,9 +502,26 @@ __global__ __launch_bounds__(256) void k_bchol(GDev *__restrict__ gd, const int 
     double2 *H = g.Rt + int64_t(j) * (m + 1) * r * r;   // ((m+1) r) x r, row-major
     if (two)   // the first pass wrote its coefficients into H directly
         for (int e = t; e < K * r; e += 256) H[e] = cadd(H[e], g.C2[e]);
+    __shared__ double cn[8][BMAX];
+    __syncthreads();
+    {   // squared column norms of H(0 : K, :), 8 partial sums per column
+        const int a = t & 31, part = t >> 5;
+        double sv = 0.0;
+        if (a < r)
+            for (int k = part; k < K; k += 8) {
+                const double2 h = H[int64_t(k) * r + a];
+                sv += h.x * h.x + h.y * h.y;
+            }
+        cn[part][a] = sv;
+    }
+    __syncthreads();
     if (t == 0) {
         double mx = 0.0;
-        for (int a = 0; a < r; ++a) mx = fmax(mx, g.G1[a * r + a].x);
+        for (int a = 0; a < r; ++a) {
+            double sv = g.G2[a * r + a].x;
+            for (int q = 0; q < 8; ++q) sv += cn[q][a];
+            mx = fmax(mx, sv);
+        }
         gmax = mx;
         brk = 0;
     }
@@ -1291,7 +1309,7 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
                 prof_begin(4, s, pairs);
                 basis_dots<VT>(pv0, dv[0].size(), N, part, p, s);
                 prof_end(4, s);
-                launch_dots<double2, 1>(ppre, dpre.size(), N, part, p, s);
+                if (reorth > 0.0) launch_dots<double2, 1>(ppre, dpre.size(), N, part, p, s);   // G1 for the second-pass test
                 prof_begin(5, s, pairs);
                 basis_comb<VT>(pc0, ci[0].size(), N, p, s);
                 prof_end(5, s);

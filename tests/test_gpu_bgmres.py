@@ -143,3 +143,22 @@ def test_bgmres_rejections(bie):
     ops = bie.Operator(V, T, 2.0, star=True)
     with pytest.raises(bie.BieError):
         ops.solve(B, bie.Solve(method="bgmres"))
+
+
+def test_bgmres_slots_and_cap(bie):
+    """slots > 0 solves the right-hand sides in consecutive chunks (each chunk
+    grouped on its own; every residual still within tol against the oracle
+    matrix); max_mvp caps the products and the call reports not converged."""
+    V, T, rwg, Zo = _case(2, 2.0)
+    op = bie.Operator(V, T, 2.0)
+    B = _rhs(op, 10, 46)
+    X, st = op.solve(B, bie.Solve(method="bgmres", block=4, restart=10, tol=1e-8, slots=4))
+    res = _res(Zo, B, X)
+    _say(f"  chunks of 4: iterations {[s['iters'] for s in st]}, max residual {res.max():.2e}")
+    assert all(s["converged"] for s in st) and res.max() <= 1e-8 * (1 + 1e-6)
+    Xc, sc = op.solve(B, bie.Solve(method="bgmres", block=4, restart=10, tol=1e-14, max_mvp=25))
+    _say(f"  cap 25: products {[s['mvps'] for s in sc]}, converged {[s['converged'] for s in sc]}")
+    assert not any(s["converged"] for s in sc)
+    assert all(s["mvps"] <= 25 + 10 for s in sc)
+    rc = _res(Zo, B, Xc)
+    assert np.all(rc < 1.0) and np.all(np.abs(np.array([s["relres_true"] for s in sc]) - rc) <= 1e-6 * rc)
