@@ -462,6 +462,7 @@ struct GDev {
     double2 *Rt;        // block column j at Rt + j * (m+1) r r: rows 0 .. (j+2) r of Hbar, reduced in place
     double2 *U;         // Householder vectors of block column j: 2r x r at U + j * 2 r r
     double2 *T;         // triangular factor of those reflectors (Q = I - U T U^H): r x r at T + j r r
+    double2 *Mw;        // M = U T^H of block column j (Q^H x = x - M U^H x): 2r x r at Mw + j * 2 r r
     double2 *Tinv;      // R^{-1} of the current step, r x r
     double2 *Gv;        // E_1 S with the reflectors applied, ((m+1) r) x q
     double2 *Y;         // least-squares solution times the column scales, (m r) x q
@@ -607,7 +608,11 @@ __device__ void wy_apply(double2 (*X)[XC], double2 (*Us)[BMAX + 1], double2 (*Ts
 constexpr int CS = 8;   // columns of the new block column per workgroup of k_bls_apply
 
 // The reflectors of block columns 0 .. j-1 applied, in order, to the new block
-// column of Hbar; the columns are independent, CS of them per workgroup.
+// column of Hbar as x -= M_i (U_i^H x); the columns are independent, CS of them
+// per workgroup.  Block i works on rows ir .. ir + 2r: its upper half is final
+// afterwards and is written back, its lower half stays in LDS as the next
+// block's upper half; U and M of the next block are loaded into registers
+// while the current block is applied.
 __global__ __launch_bounds__(256) void k_bls_apply(GDev *__restrict__ gd, const int *__restrict__ gids, int j, int m)
 {
     GDev g = gd[gids[blockIdx.x]];
@@ -615,19 +620,60 @@ __global__ __launch_bounds__(256) void k_bls_apply(GDev *__restrict__ gd, const 
     if (nc <= 0 || j == 0) return;
     __shared__ double2 X[2 * BMAX][CS + 1];
     __shared__ double2 Us[2 * BMAX][BMAX + 1];
-    __shared__ double2 Ts[BMAX][BMAX + 1];
+    __shared__ double2 Ms[2 * BMAX][BMAX + 1];
     __shared__ double2 W1[BMAX][CS + 1];
-    __shared__ double2 W2[BMAX][CS + 1];
     double2 *H = g.Rt + int64_t(j) * (m + 1) * r * r;
+    const int nu = 2 * r * r;   // entries of U (and of M) per block column, <= 2048
+    double2 pu[8], pm[8];
+    auto fetch = [&](int i) {
+        const double2 *Ui = g.U + int64_t(i) * nu, *Mi = g.Mw + int64_t(i) * nu;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = t + 256 * u;
+            pu[u] = e < nu ? Ui[e] : make_double2(0.0, 0.0);
+            pm[u] = e < nu ? Mi[e] : make_double2(0.0, 0.0);
+        }
+    };
+    fetch(0);
+    for (int e = t; e < 2 * r * nc; e += 256) X[e / nc][e % nc] = H[int64_t(e / nc) * r + c0 + e % nc];
     for (int i = 0; i < j; ++i) {
-        const double2 *Ui = g.U + int64_t(i) * 2 * r * r, *Ti = g.T + int64_t(i) * r * r;
-        for (int e = t; e < 2 * r * nc; e += 256) X[e / nc][e % nc] = H[int64_t(i * r + e / nc) * r + c0 + e % nc];
-        for (int e = t; e < 2 * r * r; e += 256) Us[e / r][e % r] = Ui[e];
-        for (int e = t; e < r * r; e += 256) Ts[e / r][e % r] = Ti[e];
         __syncthreads();
-        wy_apply<CS + 1>(X, Us, Ts, W1, W2, r, nc);
-        for (int e = t; e < 2 * r * nc; e += 256) H[int64_t(i * r + e / nc) * r + c0 + e % nc] = X[e / nc][e % nc];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = t + 256 * u;
+            if (e < nu) {
+                Us[e / r][e % r] = pu[u];
+                Ms[e / r][e % r] = pm[u];
+            }
+        }
         __syncthreads();
+        if (i + 1 < j) fetch(i + 1);
+        for (int e = t; e < r * nc; e += 256) {   // W1 = U^H X
+            const int a = e / nc, c = e % nc;
+            double2 sv = make_double2(0.0, 0.0);
+            for (int row = a; row < 2 * r; ++row) sv = cadd(sv, cmulc(Us[row][a], X[row][c]));
+            W1[a][c] = sv;
+        }
+        __syncthreads();
+        for (int e = t; e < 2 * r * nc; e += 256) {   // X -= M W1
+            const int row = e / nc, c = e % nc;
+            double2 sv = X[row][c];
+            const int amax = min(row, r - 1);
+            for (int a = 0; a <= amax; ++a) sv = csub(sv, cmul(Ms[row][a], W1[a][c]));
+            X[row][c] = sv;
+        }
+        __syncthreads();
+        // rows ir .. ir + r are final; shift the lower half up and load the next rows
+        if (i + 1 < j) {
+            for (int e = t; e < r * nc; e += 256) {
+                const int row = e / nc, c = e % nc;
+                H[int64_t(i * r + row) * r + c0 + c] = X[row][c];
+                X[row][c] = X[r + row][c];
+                X[r + row][c] = H[int64_t((i + 2) * r + row) * r + c0 + c];
+            }
+        } else {
+            for (int e = t; e < 2 * r * nc; e += 256) H[int64_t(i * r + e / nc) * r + c0 + e % nc] = X[e / nc][e % nc];
+        }
     }
 }
 
@@ -709,10 +755,15 @@ __global__ __launch_bounds__(256) void k_bls_qr(GDev *__restrict__ gd, const int
         if (t < k) Ts[t][k] = W2[t][0];
         __syncthreads();
     }
-    double2 *Uj = g.U + int64_t(j) * 2 * r * r, *Tj = g.T + int64_t(j) * r * r;
+    double2 *Uj = g.U + int64_t(j) * 2 * r * r, *Tj = g.T + int64_t(j) * r * r, *Mj = g.Mw + int64_t(j) * 2 * r * r;
     for (int e = t; e < 2 * r * r; e += 256) {
         H[int64_t(j) * r * r + e] = X[e / r][e % r];
         Uj[e] = Us[e / r][e % r];
+        const int row = e / r, a = e % r;   // M = U T^H: sum over b >= a, b <= row
+        double2 sv = make_double2(0.0, 0.0);
+        const int bmax = min(row, r - 1);
+        for (int b = a; b <= bmax; ++b) sv = cadd(sv, cmul(Us[row][b], make_double2(Ts[a][b].x, -Ts[a][b].y)));
+        Mj[e] = sv;
     }
     for (int e = t; e < r * r; e += 256) Tj[e] = Ts[e / r][e % r];
     __syncthreads();
@@ -1039,7 +1090,7 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
     double *nrm = db.get<double>(size_t(R));
     // group regions
     const size_t p2 = size_t(p) * p;
-    const size_t per = (m + 1) * p2 + 2 * p2 + size_t(m) * (m + 1) * p2 + 2 * size_t(m) * p2 + size_t(m) * p2 + p2 +
+    const size_t per = (m + 1) * p2 + 2 * p2 + size_t(m) * (m + 1) * p2 + 4 * size_t(m) * p2 + size_t(m) * p2 + p2 +
                        (m + 1) * p2 + size_t(m) * p2;
     double2 *greg = db.get<double2>(per * Gmax);
     double *gest = db.get<double>(size_t(Gmax) * BMAX);
@@ -1056,6 +1107,7 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
         d.Rt = b; b += size_t(m) * (m + 1) * p2;
         d.U = b; b += 2 * size_t(m) * p2;
         d.T = b; b += size_t(m) * p2;
+        d.Mw = b; b += 2 * size_t(m) * p2;
         d.Tinv = b; b += p2;
         d.Gv = b; b += (m + 1) * p2;
         d.Y = b;
