@@ -507,24 +507,23 @@ __global__ __launch_bounds__(256) void k_bchol(GDev *__restrict__ gd, const int 
     __syncthreads();
     {   // squared column norms of H(0 : K, :), 8 partial sums per column
         const int a = t & 31, part = t >> 5;
-        double sv = 0.0;
-        if (a < r)
-            for (int k = part; k < K; k += 8) {
-                const double2 h = H[int64_t(k) * r + a];
-                sv += h.x * h.x + h.y * h.y;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        if (a < r) {
+            int k = part;
+            for (; k + 24 < K; k += 32) {
+                const double2 h0 = H[int64_t(k) * r + a], h1 = H[int64_t(k + 8) * r + a];
+                const double2 h2 = H[int64_t(k + 16) * r + a], h3 = H[int64_t(k + 24) * r + a];
+                s0 += h0.x * h0.x + h0.y * h0.y;
+                s1 += h1.x * h1.x + h1.y * h1.y;
+                s2 += h2.x * h2.x + h2.y * h2.y;
+                s3 += h3.x * h3.x + h3.y * h3.y;
             }
-        cn[part][a] = sv;
-    }
-    __syncthreads();
-    if (t == 0) {
-        double mx = 0.0;
-        for (int a = 0; a < r; ++a) {
-            double sv = g.G2[a * r + a].x;
-            for (int q = 0; q < 8; ++q) sv += cn[q][a];
-            mx = fmax(mx, sv);
+            for (; k < K; k += 8) {
+                const double2 h = H[int64_t(k) * r + a];
+                s0 += h.x * h.x + h.y * h.y;
+            }
         }
-        gmax = mx;
-        brk = 0;
+        cn[part][a] = (s0 + s1) + (s2 + s3);
     }
     for (int e = t; e < BMAX * (BMAX + 1); e += 256) {
         (&L[0][0])[e] = make_double2(0.0, 0.0);
@@ -532,11 +531,22 @@ __global__ __launch_bounds__(256) void k_bchol(GDev *__restrict__ gd, const int 
     }
     for (int e = t; e < r * r; e += 256) Gs[e / r][e % r] = g.G2[e];
     __syncthreads();
-    // Cholesky, column by column (L lower, G2 = L L^H)
+    if (t == 0) {
+        double mx = 0.0;
+        for (int a = 0; a < r; ++a) {
+            double sv = Gs[a][a].x;
+            for (int q = 0; q < 8; ++q) sv += cn[q][a];
+            mx = fmax(mx, sv);
+        }
+        gmax = mx;
+        brk = 0;
+    }
+    __syncthreads();
+    // right-looking Cholesky of the lower triangle of Gs (G2 = L L^H): pivot,
+    // column k, then the trailing update of the columns after k
     for (int k = 0; k < r; ++k) {
         if (t == 0) {
-            double p = Gs[k][k].x;
-            for (int l = 0; l < k; ++l) p -= L[k][l].x * L[k][l].x + L[k][l].y * L[k][l].y;
+            const double p = Gs[k][k].x;
             if (!(p > delta * delta * gmax)) {
                 brk = 1;
                 L[k][k] = make_double2(0.0, 0.0);
@@ -546,28 +556,41 @@ __global__ __launch_bounds__(256) void k_bchol(GDev *__restrict__ gd, const int 
         }
         __syncthreads();
         const double d = L[k][k].x;
-        if (t > k && t < r) {
-            double2 sv = Gs[t][k];
-            for (int l = 0; l < k; ++l) sv = csub(sv, cmul(L[t][l], make_double2(L[k][l].x, -L[k][l].y)));
-            L[t][k] = d > 0.0 ? cscale(1.0 / d, sv) : make_double2(0.0, 0.0);
+        if (t > k && t < r) L[t][k] = d > 0.0 ? cscale(1.0 / d, Gs[t][k]) : make_double2(0.0, 0.0);
+        __syncthreads();
+        for (int e = t; e < r * r; e += 256) {
+            const int i = e / r, l = e % r;
+            if (l > k && l <= i) Gs[i][l] = csub(Gs[i][l], cmul(L[i][k], make_double2(L[l][k].x, -L[l][k].y)));
         }
         __syncthreads();
     }
-    // R = L^H into rows K .. K + r of H; Ti = R^{-1} (upper), zero for broken pivots
+    // R = L^H into rows K .. K + r of H
     for (int e = t; e < r * r; e += 256) {
         const int a = e / r, b = e % r;
         const double2 v = b >= a ? make_double2(L[b][a].x, -L[b][a].y) : make_double2(0.0, 0.0);
         H[int64_t(K + a) * r + b] = v;
     }
-    // columns of R^{-1}: R Ti(:, b) = e_b, back substitution per column (thread b)
-    if (t < r) {
-        const int b = t;
-        for (int a = b; a >= 0; --a) {
-            const double raa = L[a][a].x;
-            double2 sv = a == b ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0);
-            for (int c = a + 1; c <= b; ++c) sv = csub(sv, cmul(make_double2(L[c][a].x, -L[c][a].y), Ti[c][b]));
-            Ti[a][b] = raa > 0.0 ? cscale(1.0 / raa, sv) : make_double2(0.0, 0.0);
+    // L^{-1} by forward substitution, row i at a time, 8 lanes per column c <= i
+    // (Gs is free now and holds it); R^{-1} = (L^{-1})^H; zero for broken pivots
+    for (int i = 0; i < r; ++i) {
+        const int c = t >> 3, part = t & 7;
+        double2 sv = make_double2(0.0, 0.0);
+        if (c <= i && c < r)
+            for (int l = c + part; l < i; l += 8) sv = cadd(sv, cmul(L[i][l], Gs[l][c]));
+        for (int o = 4; o > 0; o >>= 1) {
+            sv.x += __shfl_xor(sv.x, o, 8);
+            sv.y += __shfl_xor(sv.y, o, 8);
         }
+        if (part == 0 && c <= i && c < r) {
+            const double lii = L[i][i].x;
+            const double2 rhs = c == i ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0);
+            Gs[i][c] = lii > 0.0 ? cscale(1.0 / lii, csub(rhs, sv)) : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+    }
+    for (int e = t; e < r * r; e += 256) {
+        const int a = e / r, b = e % r;
+        Ti[a][b] = b >= a ? make_double2(Gs[b][a].x, -Gs[b][a].y) : make_double2(0.0, 0.0);
     }
     __syncthreads();
     for (int e = t; e < r * r; e += 256) g.Tinv[e] = Ti[e / r][e % r];
