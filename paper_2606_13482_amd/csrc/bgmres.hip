@@ -671,19 +671,33 @@ __global__ __launch_bounds__(256) void k_bls_apply(GDev *__restrict__ gd, const 
         }
         __syncthreads();
         if (i + 1 < j) fetch(i + 1);
-        for (int e = t; e < r * nc; e += 256) {   // W1 = U^H X
+        for (int e = t; e < r * nc; e += 256) {   // W1 = U^H X, four independent partial sums
             const int a = e / nc, c = e % nc;
-            double2 sv = make_double2(0.0, 0.0);
-            for (int row = a; row < 2 * r; ++row) sv = cadd(sv, cmulc(Us[row][a], X[row][c]));
-            W1[a][c] = sv;
+            double2 s0 = make_double2(0.0, 0.0), s1 = s0, s2 = s0, s3 = s0;
+            int row = a;
+            for (; row + 3 < 2 * r; row += 4) {
+                s0 = cadd(s0, cmulc(Us[row][a], X[row][c]));
+                s1 = cadd(s1, cmulc(Us[row + 1][a], X[row + 1][c]));
+                s2 = cadd(s2, cmulc(Us[row + 2][a], X[row + 2][c]));
+                s3 = cadd(s3, cmulc(Us[row + 3][a], X[row + 3][c]));
+            }
+            for (; row < 2 * r; ++row) s0 = cadd(s0, cmulc(Us[row][a], X[row][c]));
+            W1[a][c] = cadd(cadd(s0, s1), cadd(s2, s3));
         }
         __syncthreads();
-        for (int e = t; e < 2 * r * nc; e += 256) {   // X -= M W1
+        for (int e = t; e < 2 * r * nc; e += 256) {   // X -= M W1, four independent partial sums
             const int row = e / nc, c = e % nc;
-            double2 sv = X[row][c];
             const int amax = min(row, r - 1);
-            for (int a = 0; a <= amax; ++a) sv = csub(sv, cmul(Ms[row][a], W1[a][c]));
-            X[row][c] = sv;
+            double2 s0 = make_double2(0.0, 0.0), s1 = s0, s2 = s0, s3 = s0;
+            int a = 0;
+            for (; a + 3 <= amax; a += 4) {
+                s0 = cadd(s0, cmul(Ms[row][a], W1[a][c]));
+                s1 = cadd(s1, cmul(Ms[row][a + 1], W1[a + 1][c]));
+                s2 = cadd(s2, cmul(Ms[row][a + 2], W1[a + 2][c]));
+                s3 = cadd(s3, cmul(Ms[row][a + 3], W1[a + 3][c]));
+            }
+            for (; a <= amax; ++a) s0 = cadd(s0, cmul(Ms[row][a], W1[a][c]));
+            X[row][c] = csub(X[row][c], cadd(cadd(s0, s1), cadd(s2, s3)));
         }
         __syncthreads();
         // rows ir .. ir + r are final; shift the lower half up and load the next rows
