@@ -817,19 +817,40 @@ __global__ __launch_bounds__(256) void k_bls_qr(GDev *__restrict__ gd, const int
 }
 
 // Y = R^{-1} Gv(0 : J r, :) by right-looking block back substitution (R upper
-// triangular, block column b of R at Rt + b (m+1) r r), one block row I per
-// pair of launches from the last: k_bls_tri solves R_II Y_I = Gv_I, then
-// k_bls_upd takes R(0 : I r, I) Y_I off the rows above.  Gv is consumed.
-__global__ __launch_bounds__(256) void k_bls_tri(GDev *__restrict__ gd, const int *__restrict__ gids,
-                                                 const int *__restrict__ steps, int I, int m)
+// triangular, block column b of R at Rt + b (m+1) r r), one launch per block
+// row I from the last: workgroup b (block row b <= I) takes R(b, I+1) Y_{I+1}
+// off its rows of Gv, and the workgroup of block row I then solves
+// R_II Y_I = Gv_I.  Y holds the solution times the column scales; Gv is consumed.
+__global__ __launch_bounds__(256) void k_bls_back(GDev *__restrict__ gd, const int *__restrict__ gids,
+                                                  const int *__restrict__ steps, int I, int m)
 {
     const int gid = gids[blockIdx.x];
     GDev g = gd[gid];
-    const int r = g.r, q = g.q, t = threadIdx.x;
-    if (I >= steps[gid]) return;
+    const int r = g.r, q = g.q, t = threadIdx.x, b = blockIdx.y, J = steps[gid];
+    if (I >= J || b > I) return;
     const int64_t bs = int64_t(m + 1) * r * r;
+    __shared__ double2 Ys[BMAX][BMAX + 1];
     __shared__ double2 S[BMAX][BMAX + 1];
     __shared__ double2 D[BMAX][BMAX + 1];
+    if (I + 1 < J) {   // Y_{I+1} without the column scales
+        for (int e = t; e < r * q; e += 256) {
+            const int c = e % q;
+            const double sc = g.scale[c];
+            const double2 y = g.Y[int64_t((I + 1) * r + e / q) * q + c];
+            Ys[e / q][c] = sc > 0.0 ? cscale(1.0 / sc, y) : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+        const double2 *Rb = g.Rt + (I + 1) * bs;
+        for (int e = t; e < r * q; e += 256) {
+            const int row = b * r + e / q, c = e % q;
+            double2 sv = g.Gv[int64_t(row) * q + c];
+            const double2 *Rr = Rb + int64_t(row) * r;
+            for (int k = 0; k < r; ++k) sv = csub(sv, cmul(Rr[k], Ys[k][c]));
+            g.Gv[int64_t(row) * q + c] = sv;
+        }
+    }
+    if (b != I) return;
+    __syncthreads();
     const double2 *Rb = g.Rt + I * bs;
     for (int e = t; e < r * r; e += 256) D[e / r][e % r] = Rb[int64_t(I * r + e / r) * r + e % r];
     for (int e = t; e < r * q; e += 256) S[e / q][e % q] = g.Gv[int64_t(I * r + e / q) * q + e % q];
@@ -837,7 +858,7 @@ __global__ __launch_bounds__(256) void k_bls_tri(GDev *__restrict__ gd, const in
     if (t < q) {
         for (int a = r - 1; a >= 0; --a) {
             double2 sv = S[a][t];
-            for (int b = a + 1; b < r; ++b) sv = csub(sv, cmul(D[a][b], S[b][t]));
+            for (int c = a + 1; c < r; ++c) sv = csub(sv, cmul(D[a][c], S[c][t]));
             const double2 d = D[a][a];
             const double dd = d.x * d.x + d.y * d.y;
             S[a][t] = dd > 0.0 ? make_double2((sv.x * d.x + sv.y * d.y) / dd, (sv.y * d.x - sv.x * d.y) / dd)
@@ -845,38 +866,7 @@ __global__ __launch_bounds__(256) void k_bls_tri(GDev *__restrict__ gd, const in
         }
     }
     __syncthreads();
-    // Y holds the solution times the column scales
     for (int e = t; e < r * q; e += 256) g.Y[int64_t(I * r + e / q) * q + e % q] = cscale(g.scale[e % q], S[e / q][e % q]);
-}
-
-// rows 64 blockIdx.y .. of block rows 0 .. I-1: Gv -= R(rows, I) Y_I / scale
-__global__ __launch_bounds__(256) void k_bls_upd(GDev *__restrict__ gd, const int *__restrict__ gids,
-                                                 const int *__restrict__ steps, int I, int m)
-{
-    const int gid = gids[blockIdx.x];
-    GDev g = gd[gid];
-    const int r = g.r, q = g.q, t = threadIdx.x;
-    if (I >= steps[gid]) return;
-    const int row0 = blockIdx.y * 64;
-    if (row0 >= I * r) return;
-    const int64_t bs = int64_t(m + 1) * r * r;
-    __shared__ double2 Ys[BMAX][BMAX + 1];
-    for (int e = t; e < r * q; e += 256) {
-        const int c = e % q;
-        const double sc = g.scale[c];
-        const double2 y = g.Y[int64_t(I * r + e / q) * q + c];
-        Ys[e / q][c] = sc > 0.0 ? cscale(1.0 / sc, y) : make_double2(0.0, 0.0);
-    }
-    __syncthreads();
-    const double2 *Rb = g.Rt + I * bs;
-    for (int e = t; e < 64 * q; e += 256) {
-        const int row = row0 + e / q, c = e % q;
-        if (row >= I * r) continue;
-        double2 sv = g.Gv[int64_t(row) * q + c];
-        const double2 *Rr = Rb + int64_t(row) * r;
-        for (int b = 0; b < r; ++b) sv = csub(sv, cmul(Rr[b], Ys[b][c]));
-        g.Gv[int64_t(row) * q + c] = sv;
-    }
 }
 
 __global__ void k_bzero(int64_t n, double2 *__restrict__ a)
@@ -1453,13 +1443,9 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
                     BIE_HIP(hipStreamWaitEvent(s, ev_ls[prev & 1], 0));
                     int jmax = 0;
                     for (int g : ended) jmax = std::max(jmax, grp[g].steps);
-                    for (int I = jmax - 1; I >= 0; --I) {
-                        hipLaunchKernelGGL(k_bls_tri, dim3(unsigned(ended.size())), dim3(256), 0, s, gd, de, gsteps, I,
-                                           m);
-                        if (I > 0)
-                            hipLaunchKernelGGL(k_bls_upd, dim3(unsigned(ended.size()), unsigned((I * p + 63) / 64)),
-                                               dim3(256), 0, s, gd, de, gsteps, I, m);
-                    }
+                    for (int I = jmax - 1; I >= 0; --I)
+                        hipLaunchKernelGGL(k_bls_back, dim3(unsigned(ended.size()), unsigned(I + 1)), dim3(256), 0, s, gd,
+                                           de, gsteps, I, m);
                     BIE_HIP(hipGetLastError());
                     basis_comb<VT>(pit, it.size(), N, p, s);
                 }
