@@ -1069,22 +1069,26 @@ int rank_revealing(const std::vector<cd> &G, int q, const std::vector<double> &s
     return r;
 }
 
-// Second stream, events and pinned buffers of one solve, released at scope exit.
+// Second and third streams (least-squares updates; end-of-cycle solutions),
+// events and pinned buffers of one solve, released at scope exit.
 struct Aux {
-    hipStream_t s2 = nullptr;
-    hipEvent_t ev[5] = {};
+    hipStream_t s2 = nullptr, s3 = nullptr;
+    hipEvent_t ev[7] = {};
     std::vector<void *> pinned;
     Aux()
     {
         BIE_HIP(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
+        BIE_HIP(hipStreamCreateWithFlags(&s3, hipStreamNonBlocking));
         for (auto &e : ev) BIE_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     }
     ~Aux()
     {
         if (s2) (void)hipStreamSynchronize(s2);
+        if (s3) (void)hipStreamSynchronize(s3);
         for (auto &e : ev)
             if (e) (void)hipEventDestroy(e);
         if (s2) (void)hipStreamDestroy(s2);
+        if (s3) (void)hipStreamDestroy(s3);
         for (void *p : pinned) (void)hipHostFree(p);
     }
 };
@@ -1146,10 +1150,13 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
     std::unique_ptr<Arena> arena[2] = { std::make_unique<Arena>(size_t(8) << 20),
                                         std::make_unique<Arena>(size_t(8) << 20) };
     Aux aux;
-    hipStream_t s2 = aux.s2;
+    hipStream_t s2 = aux.s2, s3 = aux.s3;
     hipEvent_t ev_prod = aux.ev[0], ev_ls[2] = { aux.ev[1], aux.ev[2] }, ev_arena[2] = { aux.ev[3], aux.ev[4] };
+    hipEvent_t ev_s3[2] = { aux.ev[5], aux.ev[6] };
     BIE_HIP(hipEventRecord(ev_arena[0], s));
     BIE_HIP(hipEventRecord(ev_arena[1], s));
+    BIE_HIP(hipEventRecord(ev_s3[0], s3));
+    BIE_HIP(hipEventRecord(ev_s3[1], s3));
     double *hest[2];
     int *hfl[2];
     for (int i = 0; i < 2; ++i) {
@@ -1323,6 +1330,7 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
             if (act.empty() && prev < 0) break;
             Arena &A = *arena[j & 1];
             BIE_HIP(hipEventSynchronize(ev_arena[j & 1]));
+            BIE_HIP(hipEventSynchronize(ev_s3[j & 1]));
             A.reset();
             // least-squares update of step prev on the second stream, queued after
             // this step's product so that it shares the GPU with the smaller
@@ -1428,7 +1436,9 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
                     }
                 }
                 if (!ended.empty()) {
-                    // Y = R^{-1} (E_1 S) and X += V Y for the groups that ended at step prev
+                    // Y = R^{-1} (E_1 S) and X += V Y for the groups that ended at step prev,
+                    // on the third stream beside the next steps (after their tables and the
+                    // least-squares update of step prev)
                     std::vector<CItem> it;
                     std::vector<const int *> oc;
                     const int *de = A.put(ended);
@@ -1439,22 +1449,24 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
                                             h.steps * h.r, h.q, h.q });
                     }
                     const CItem *pit = A.put(it);
-                    A.copy_to(gsteps, hsteps.data(), size_t(ng), s);
-                    BIE_HIP(hipStreamWaitEvent(s, ev_ls[prev & 1], 0));
+                    A.copy_to(gsteps, hsteps.data(), size_t(ng), s3);   // also uploads the tables above
+                    BIE_HIP(hipStreamWaitEvent(s3, ev_ls[prev & 1], 0));
                     int jmax = 0;
                     for (int g : ended) jmax = std::max(jmax, grp[g].steps);
                     for (int I = jmax - 1; I >= 0; --I)
-                        hipLaunchKernelGGL(k_bls_back, dim3(unsigned(ended.size()), unsigned(I + 1)), dim3(256), 0, s, gd,
-                                           de, gsteps, I, m);
+                        hipLaunchKernelGGL(k_bls_back, dim3(unsigned(ended.size()), unsigned(I + 1)), dim3(256), 0, s3,
+                                           gd, de, gsteps, I, m);
                     BIE_HIP(hipGetLastError());
-                    basis_comb<VT>(pit, it.size(), N, p, s);
+                    basis_comb<VT>(pit, it.size(), N, p, s3);
                 }
+                BIE_HIP(hipEventRecord(ev_s3[j & 1], s3));
             }
             BIE_HIP(hipEventRecord(ev_arena[j & 1], s));
             prev = act.empty() ? -1 : j;
             prev_act = act;
         }
         BIE_HIP(hipStreamSynchronize(s2));
+        BIE_HIP(hipStreamSynchronize(s3));
     }
     sync();
     int status = BIE_OK;
