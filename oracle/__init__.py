@@ -20,4 +20,6 @@ Modules
   krylov      LU, restarted GMRES (MGS), CGNR, SCC and RSCC criteria
   sampling    SplitMix64 and Floyd's sampling for the random-sampling criterion
   mie         Mie series of a PEC sphere (check path)
+  calderon    barycentric refinement, BC functions, mixed Gram matrix and the
+              multiplicative Calderon preconditioner (Andriulli et al. 2008)
 """

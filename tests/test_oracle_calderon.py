@@ -1,0 +1,193 @@
+"""Pins of the oracle's Calderon preconditioner (barycentric refinement, BC
+functions, mixed Gram matrix, preconditioned operator) against what geometry,
+the divergence theorem, integration by parts and the Calderon identity fix,
+independently of how the oracle builds them."""
+import numpy as np
+import pytest
+
+from oracle import calderon, cfill, krylov
+from oracle.efie import rhs
+from oracle.mesh import vertex_loops
+from paper_2606_13482_amd.inputs import icosphere, planewave_set, random_directions
+
+_CACHE = {}
+
+
+def _built(level, k=2.0):
+    if (level, k) not in _CACHE:
+        V, T = icosphere(level)
+        _CACHE[(level, k)] = calderon.build(V, T, k)
+    return _CACHE[(level, k)]
+
+
+def _area(P):
+    return 0.5 * np.linalg.norm(np.cross(P[1] - P[0], P[2] - P[0]))
+
+
+@pytest.mark.parametrize("level", [1, 2])
+def test_barycentric_refinement(level):
+    """Six children per triangle, each of a sixth of its parent's area and inside
+    its plane; the refined mesh is closed and consistently oriented (its RWG
+    table exists), with V - E + F = 2 and 9 F edges."""
+    P = _built(level)
+    rwg, rwgb, Vb, Tb = P["rwg"], P["rwgb"], P["Vb"], P["Tb"]
+    F = rwg["F"]
+    assert Tb.shape == (6 * F, 3) and rwgb["N"] == 9 * F
+    assert Vb.shape[0] - rwgb["N"] + rwgb["F"] == 2
+    for t in range(6 * F):
+        T = P["parent"][t]
+        assert abs(_area(Vb[Tb[t]]) - rwg["area"][T] / 6) <= 1e-14
+        assert abs(np.dot(Vb[Tb[t]] - rwg["V"][rwg["T"][T, 0]], rwg["normal"][T])).max() <= 1e-14
+        assert np.dot(rwgb["normal"][t], rwg["normal"][T]) > 1 - 1e-12      # orientation kept
+
+
+def _b_at(P, m, t, x):
+    """BC function m on child t at points x, summed from its refined RWG terms."""
+    rwgb, C = P["rwgb"], P["C"]
+    val = np.zeros_like(x)
+    for e in np.nonzero(C[m])[0]:
+        if t in (rwgb["tp"][e], rwgb["tm"][e]):
+            val += C[m, e] * calderon._rwg_on(rwgb, e, t, x)
+    return val
+
+
+def test_bc_charge_and_fluxes():
+    """Divergence theorem on every child of the support, by evaluating b_m on the
+    child's edges: the net outflow is +A_t/A(hi) in the dual cell of the higher
+    vertex, -A_t/A(lo) in the lower one's; the flux through each half of the dual
+    edge is 1/2, through the halves of edge m 0, and b_m . nu is continuous
+    across every child edge."""
+    P = _built(1)
+    rwg, rwgb, Vb, Tb, corner = P["rwg"], P["rwgb"], P["Vb"], P["Tb"], P["corner"]
+    nv, E = rwg["V"].shape[0], rwg["N"]
+    Ac = np.zeros(nv)
+    for t in range(Tb.shape[0]):
+        Ac[corner[t]] += _area(Vb[Tb[t]])
+    g = np.array([0.5 - np.sqrt(3 / 20), 0.5, 0.5 + np.sqrt(3 / 20)])   # 3-point Gauss on [0, 1]
+    wg = np.array([5, 8, 5]) / 18
+
+    def flux(m, t, a, b):
+        """Outflow of b_m from child t through its edge a -> b (CCW order)."""
+        n = rwgb["normal"][t]
+        nu = np.cross(Vb[b] - Vb[a], n)        # outward, times the edge length
+        x = Vb[a][None, :] + g[:, None] * (Vb[b] - Vb[a])[None, :]
+        return float(np.sum(wg * (_b_at(P, m, t, x) @ nu)))
+
+    for m in range(0, rwg["N"], 7):
+        lo, hi = rwg["edges"][m]
+        support = sorted({int(t) for e in np.nonzero(P["C"][m])[0] for t in (rwgb["tp"][e], rwgb["tm"][e])})
+        assert set(corner[support]) == {lo, hi}
+        edge_flux = {}
+        halves = 0
+        for t in support:
+            tot = 0.0
+            for k in range(3):
+                a, b = int(Tb[t, k]), int(Tb[t, (k + 1) % 3])
+                f = flux(m, t, a, b)
+                edge_flux[(t, a, b)] = f
+                tot += f
+            want = _area(Vb[Tb[t]]) / Ac[hi] if corner[t] == hi else -_area(Vb[Tb[t]]) / Ac[lo]
+            assert abs(tot - want) <= 1e-13
+        for (t, a, b), f in edge_flux.items():
+            # normal continuity: the neighbour across a -> b sees the opposite flux
+            other = [key for key in edge_flux if key[1:] == (b, a)]
+            for key in other:
+                assert abs(f + edge_flux[key]) <= 1e-13
+            if not other:
+                assert abs(f) <= 1e-13          # support boundary: no flux leaves
+            mid = nv + m                                    # midpoint of edge m
+            gs = {nv + E + int(rwg["tp"][m]), nv + E + int(rwg["tm"][m])}
+            if corner[t] == hi and {a, b} == {hi, mid}:
+                assert abs(f) <= 1e-13          # half of edge m
+            if corner[t] == hi and mid in (a, b) and ({a, b} - {mid}) <= gs:
+                assert abs(f - 0.5) <= 1e-13    # half of the dual edge, out of the cell of hi
+                halves += 1
+        assert halves == 2
+
+
+def test_gram_against_vertex_loops():
+    """Vertex loops L_v = sum_n (L)_vn f_n = n x grad(lambda_v) turn G into
+    <b_m, grad lambda_v> = -<div b_m, lambda_v>, which needs only the cell
+    charges and the integrals of the hat functions over the children; G also
+    has a positive diagonal and a small condition number."""
+    P = _built(2)
+    rwg, G, Vb, Tb, corner, parent = P["rwg"], P["G"], P["Vb"], P["Tb"], P["corner"], P["parent"]
+    nv, F = rwg["V"].shape[0], rwg["F"]
+    E = rwg["N"]
+    Lp = vertex_loops(rwg)                                    # (nv, N)
+    lhs = G @ Lp.T                                            # (N, nv)
+    # hat function lambda_v at the refined vertices: vertex, edge midpoint, centroid
+    lam = np.zeros((Vb.shape[0], nv))
+    lam[np.arange(nv), np.arange(nv)] = 1.0
+    for i, (a, b) in enumerate(rwg["edges"]):
+        lam[nv + i, a] = lam[nv + i, b] = 0.5
+    for t in range(F):
+        lam[nv + E + t, rwg["T"][t]] = 1.0 / 3.0
+    Ac = np.zeros(nv)
+    I = np.zeros((nv, nv))                                    # I[c, v] = int over cell c of lambda_v
+    for t in range(Tb.shape[0]):
+        A = _area(Vb[Tb[t]])
+        Ac[corner[t]] += A
+        I[corner[t]] += A * lam[Tb[t]].mean(axis=0)
+    lo, hi = rwg["edges"][:, 0], rwg["edges"][:, 1]
+    rhs_ = -(I[hi] / Ac[hi][:, None] - I[lo] / Ac[lo][:, None])
+    assert np.max(np.abs(lhs - rhs_)) <= 1e-12 * np.max(np.abs(rhs_))
+    assert np.all(np.diag(G) > 0)
+    assert np.linalg.cond(G) < 5.0
+
+
+def test_calderon_identity_and_iterations():
+    """M Z discretises the square of the EFIE operator: its spectrum accumulates
+    at -1/4 (Calderon identity), its condition number is small and far below Z's,
+    M and T_BC are complex symmetric, and right-preconditioned GMRES reaches the
+    LU solution in fewer iterations than plain GMRES."""
+    P = _built(2)
+    rwg, M = P["rwg"], P["M"]
+    Z = cfill.fill(rwg, 2.0)
+    ev = np.linalg.eigvals(M @ Z)
+    assert np.mean(np.abs(ev + 0.25) < 0.1) >= 0.95
+    assert np.linalg.cond(M @ Z) < 3.0 < np.linalg.cond(Z) / 10
+    for A in (P["Tbc"], M):
+        assert np.max(np.abs(A - A.T)) <= 1e-13 * np.max(np.abs(A))
+    d, e = planewave_set(random_directions(1, 5), "theta")
+    b = rhs(rwg, 2.0, d, e)[0]
+    x, st = calderon.gmres_right(Z, M, b, m=30, tol=1e-8)
+    x0, s0 = krylov.gmres(Z, b, m=30, tol=1e-8)
+    xl = np.linalg.solve(Z, b)
+    assert st.converged and krylov.scc(Z, b, x) <= 1e-8
+    assert np.linalg.norm(x - xl) / np.linalg.norm(xl) <= 1e-6
+    assert st.iters * 4 <= s0.iters
+
+
+def test_refined_matrix_reproduces_rwg_matrix():
+    """Each RWG function of the mesh is exactly the combination of refined RWG
+    functions given by its fluxes through the refined edges (checked pointwise);
+    carried through the refined-mesh EFIE matrix, that combination gives back
+    the RWG matrix up to the quadrature difference of the two meshes (1.4 % in
+    Frobenius norm here), which pins the refined fill that T_BC is built from."""
+    P = _built(1)
+    rwg, rwgb, Vb, parent = P["rwg"], P["rwgb"], P["Vb"], P["parent"]
+    R = np.zeros((rwg["N"], rwgb["N"]))
+    for e in range(rwgb["N"]):
+        t = rwgb["tp"][e]
+        Tt = list(rwgb["T"][t])
+        k = [i for i in range(3) if {Tt[i], Tt[(i + 1) % 3]} == set(rwgb["edges"][e])][0]
+        p, q = Tt[k], Tt[(k + 1) % 3]
+        nu = np.cross(Vb[q] - Vb[p], rwgb["normal"][t])        # out of t, times the length
+        x = ((Vb[p] + Vb[q]) / 2)[None, :]
+        for n in range(rwg["N"]):
+            if parent[t] in (rwg["tp"][n], rwg["tm"][n]):
+                R[n, e] = float(calderon._rwg_on(rwg, n, parent[t], x)[0] @ nu)
+    rng = np.random.default_rng(3)
+    for t in range(0, rwgb["F"], 5):
+        w = rng.dirichlet(np.ones(3), size=4)
+        x = w @ Vb[rwgb["T"][t]]
+        for n in range(rwg["N"]):
+            if parent[t] not in (rwg["tp"][n], rwg["tm"][n]):
+                continue
+            got = sum(R[n, e] * calderon._rwg_on(rwgb, e, t, x) for e in np.nonzero(R[n])[0]
+                      if t in (rwgb["tp"][e], rwgb["tm"][e]))
+            assert np.max(np.abs(got - calderon._rwg_on(rwg, n, parent[t], x))) <= 1e-12
+    Z = cfill.fill(rwg, 2.0)
+    Zb = cfill.fill(rwgb, 2.0)
+    assert np.linalg.norm(R @ Zb @ R.T - Z) <= 0.025 * np.linalg.norm(Z)
