@@ -170,6 +170,13 @@ typedef struct {
                             precision or storage */
     int block;           /* BIE_BGMRES: right-hand sides per block Krylov space
                             (1..32); 0: 32 */
+    const struct bie_calderon *calderon;
+                         /* NULL, or a Calderon preconditioner built for this
+                            operator (bie_calderon_create): GMRES then runs on
+                            T M u = b with x = M u (right preconditioning, so the
+                            GMRES residual and the criteria stay those of T x = b).
+                            Method BIE_GMRES and precision 0 only (BIE_EINVAL
+                            otherwise, or if it was built for another operator) */
 } bie_solve_opts;
 
 typedef struct {
@@ -252,6 +259,39 @@ int bie_batch_solve(const bie_op *const *ops, int64_t nops, const void *const *B
 int bie_batch_config(int unit_tiles, int use_graph);
 /* Tiles per unit chosen for this batch shape so far (0: none). */
 int bie_batch_tuned(const bie_op *const *ops, int64_t nops, const int64_t *R);
+
+/* ---------------------------------------------------------------------------
+ * Multiplicative Calderon preconditioner (Andriulli et al., IEEE TAP 56(8),
+ * 2008), used by the paper in all of its simulations (Sec. VI-A, remark on the
+ * star-split operator; Sec. VII).  M = -G^{-1} T_BC G^{-T} with T_BC the EFIE
+ * matrix in the Buffa-Christiansen basis (built on the barycentric refinement
+ * of the mesh: charge spread uniformly over each dual cell, flux 1/2 through
+ * each half of the dual edge, none through the halves of the primal edge) and
+ * G_mn = <n x b_m, f_n> the mixed Gram matrix; M T discretises the square of the
+ * EFIE operator (spectrum accumulating at -1/4).  M is complex symmetric and
+ * kept in FP64 in the same packed tiles as T, so a preconditioned product is
+ * two packed products. */
+typedef struct bie_calderon bie_calderon;
+typedef struct {
+    int64_t N, Nb;             /* unknowns of the mesh and of its barycentric refinement (9 F) */
+    int64_t nnz_bc;            /* nonzeros of the BC coefficient map (N x Nb) */
+    int64_t nnz_gram;          /* nonzeros of G */
+    int64_t cg_iters[2];       /* CG iterations of the two Gram solves (all N columns at once) */
+    double cg_relres[2];       /* their final relative residuals, max over columns (<= 1e-13) */
+    double setup_ms;           /* wall time of bie_calderon_create */
+} bie_calderon_info;
+
+/* Builds M for an assembled operator (not star-split) with N <= 12288 (the
+ * refined mesh's FP64 matrix and its dense copy take 864 N^2 bytes while it is
+ * built, then are freed).  Fills the refined mesh on the device, forms T_BC in
+ * column chunks, solves with G by CG on the normal equations for all N columns
+ * and stores M (16 N^2 / 2 bytes).  The operator must outlive the
+ * preconditioner.  BIE_ENUMERIC if a Gram solve misses 1e-13. */
+int bie_calderon_create(const bie_op *op, void *stream, bie_calderon **out);
+/* Y = M X for R complex128 vectors (device, R x N each, vectors contiguous). */
+int bie_calderon_apply(const bie_calderon *pc, const void *X, void *Y, int64_t R, void *stream);
+int bie_calderon_get_info(const bie_calderon *pc, bie_calderon_info *info);
+void bie_calderon_destroy(bie_calderon *pc);
 
 /* Radiation vector F(r) = int j(y) exp(jk r . y) dS of the solutions X for M
  * unit directions (Sec. II, scattered field from the radiation potentials);

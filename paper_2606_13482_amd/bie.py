@@ -44,7 +44,13 @@ class SolveOpts(ctypes.Structure):
                 ("max_mvp", ctypes.c_int64), ("crit", ctypes.c_int), ("rscc_rows", ctypes.c_int64),
                 ("rscc_seed", ctypes.c_uint64), ("use_x0", ctypes.c_int), ("precision", ctypes.c_int),
                 ("inner_tol", ctypes.c_double), ("slots", ctypes.c_int64), ("inner_terms", ctypes.c_int),
-                ("basis", ctypes.c_int), ("block", ctypes.c_int)]
+                ("basis", ctypes.c_int), ("block", ctypes.c_int), ("calderon", ctypes.c_void_p)]
+
+
+class CalderonInfo(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int64), ("Nb", ctypes.c_int64), ("nnz_bc", ctypes.c_int64),
+                ("nnz_gram", ctypes.c_int64), ("cg_iters", ctypes.c_int64 * 2), ("cg_relres", ctypes.c_double * 2),
+                ("setup_ms", ctypes.c_double)]
 
 
 class WsOpts(ctypes.Structure):
@@ -96,6 +102,10 @@ SYMBOLS = [
     ("bie_prof_enable", ctypes.c_int, [ctypes.c_int]),
     ("bie_prof_read", ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(_I64)]),
+    ("bie_calderon_create", ctypes.c_int, [_P, _P, ctypes.POINTER(_P)]),
+    ("bie_calderon_apply", ctypes.c_int, [_P, _P, _P, _I64, _P]),
+    ("bie_calderon_get_info", ctypes.c_int, [_P, _P]),
+    ("bie_calderon_destroy", None, [_P]),
     ("bie_last_error", ctypes.c_char_p, []),
 ]
 
@@ -175,13 +185,14 @@ class Solve:
     inner_terms: int = 0          # mixed, split-BF16: 3 or 2 terms of the inner block product; 0 = 3
     basis: str = "c64"            # mixed, split-BF16: inner Krylov basis "c64" or "f16" (FP16 pairs)
     block: int = 0                # method "bgmres": right-hand sides per block Krylov space (1..32); 0 = 32
+    calderon: "Calderon | None" = None   # GMRES, precision "plain": right preconditioner built for the operator
 
     def c(self, use_x0: int) -> SolveOpts:
         return SolveOpts({"gmres": BIE_GMRES, "cgnr": BIE_CGNR, "bgmres": BIE_BGMRES}[self.method], self.restart, self.tol,
                          self.max_mvp, {"scc": BIE_SCC, "rscc": BIE_RSCC, "ccc": BIE_CCC}[self.crit], self.rscc_rows,
                          self.rscc_seed, int(use_x0), {"plain": 0, "mixed": 1}[self.precision],
                          self.inner_tol, self.slots, self.inner_terms, {"c64": 0, "f16": 1}[self.basis],
-                         self.block)
+                         self.block, None if self.calderon is None else self.calderon._h)
 
 
 class Operator:
@@ -293,6 +304,44 @@ class Operator:
         F = self.farfield(X, obs).cpu().numpy()
         tang = F - np.sum(obs[None] * F, axis=2, keepdims=True) * obs[None]
         return self.k ** 2 / (4 * np.pi) * np.sum(np.abs(tang) ** 2, axis=2)
+
+
+class Calderon:
+    """Multiplicative Calderon preconditioner M = -G^{-1} T_BC G^{-T} of an
+    operator (bie_calderon_create): pass it as Solve(calderon=...) to run GMRES
+    on T M u = b, x = M u."""
+
+    def __init__(self, op: Operator, stream=None):
+        h = ctypes.c_void_p()
+        _check(_lib.bie_calderon_create(op._h, _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self.op = op            # the operator must outlive the preconditioner
+        self.N = op.N
+
+    def apply(self, X: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """Y = M X for complex128 vectors (rows of X)."""
+        X2 = X.reshape(-1, self.N)
+        Y = torch.empty_like(X2) if out is None else out
+        _check(_lib.bie_calderon_apply(self._h, _dev(X2, torch.complex128), _dev(Y, torch.complex128, X2.shape),
+                                       X2.shape[0], _stream(stream)))
+        return Y.reshape(X.shape)
+
+    def info(self) -> dict:
+        i = CalderonInfo()
+        _check(_lib.bie_calderon_get_info(self._h, ctypes.byref(i)))
+        return dict(N=i.N, Nb=i.Nb, nnz_bc=i.nnz_bc, nnz_gram=i.nnz_gram, cg_iters=list(i.cg_iters),
+                    cg_relres=list(i.cg_relres), setup_ms=i.setup_ms)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.bie_calderon_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def batch_solve(ops, Bs, opts: Solve | None = None, x0s=None, x0_fallback: bool = False, stream=None):

@@ -206,7 +206,7 @@ int bie_solve(const bie_op *op, const void *B, void *X, int64_t R, const bie_sol
         if (!op || !B || !X) return fail(BIE_EINVAL, "NULL argument");
         if (R < 0 || R > 4096) return fail(BIE_EINVAL, "R out of range (0..4096)");
         if (R == 0) return BIE_OK;
-        bie_solve_opts o{ BIE_GMRES, 30, 1e-6, 10000, BIE_SCC, 512, 1234, 0, 0, 0.0, 0, 0, 0, 0 };
+        bie_solve_opts o{ BIE_GMRES, 30, 1e-6, 10000, BIE_SCC, 512, 1234, 0, 0, 0.0, 0, 0, 0, 0, nullptr };
         if (opts) o = *opts;
         if (o.method != BIE_GMRES && o.method != BIE_CGNR && o.method != BIE_BGMRES)
             return fail(BIE_EINVAL, "unknown method");
@@ -223,6 +223,12 @@ int bie_solve(const bie_op *op, const void *B, void *X, int64_t R, const bie_sol
             if (o.precision == 1 && !op->Abf)
                 return fail(BIE_EINVAL, "mixed-precision block GMRES needs split-BF16 storage");
             if (!op->Z64) return fail(BIE_EINVAL, "block GMRES needs the FP64 matrix");
+        }
+        if (o.calderon) {
+            if (o.method != BIE_GMRES || o.precision != 0)
+                return fail(BIE_EINVAL, "the Calderon preconditioner takes GMRES with precision 0");
+            if (bie::calderon_operator(o.calderon) != op)
+                return fail(BIE_EINVAL, "the Calderon preconditioner was built for another operator");
         }
         if (!(o.tol > 0.0)) return fail(BIE_EINVAL, "tol must be > 0");
         if (o.max_mvp < 1) return fail(BIE_EINVAL, "max_mvp must be >= 1");
@@ -249,16 +255,43 @@ int bie_solve(const bie_op *op, const void *B, void *X, int64_t R, const bie_sol
     });
 }
 
+int bie_calderon_create(const bie_op *op, void *stream, bie_calderon **out)
+{
+    return guarded([&]() -> int {
+        if (!op || !out) return fail(BIE_EINVAL, "NULL argument");
+        *out = nullptr;
+        *out = bie::calderon_create(op, as_stream(stream));
+        return BIE_OK;
+    });
+}
+
+int bie_calderon_apply(const bie_calderon *pc, const void *X, void *Y, int64_t R, void *stream)
+{
+    return guarded([&]() -> int {
+        if (!pc || !X || !Y) return fail(BIE_EINVAL, "NULL argument");
+        if (R < 0 || R > 4096) return fail(BIE_EINVAL, "R out of range (0..4096)");
+        if (R == 0) return BIE_OK;
+        if (X == Y) return fail(BIE_EINVAL, "X and Y must not alias");
+        bie_calderon_info info;
+        bie_calderon_get_info(pc, &info);
+        bie::calderon_apply(pc, X, info.N, Y, info.N, R, nullptr, 1, as_stream(stream));
+        return BIE_OK;
+    });
+}
+
+void bie_calderon_destroy(bie_calderon *pc) { bie::calderon_destroy(pc); }
+
 int bie_batch_solve(const bie_op *const *ops, int64_t nops, const void *const *B, void *const *X,
                     const int64_t *R, const bie_solve_opts *opts, bie_solve_stat *stats, void *stream)
 {
     return guarded([&]() -> int {
         if (!ops || !B || !X || !R) return fail(BIE_EINVAL, "NULL argument");
         if (nops < 1 || nops > 4096) return fail(BIE_EINVAL, "nops out of range (1..4096)");
-        bie_solve_opts o{ BIE_GMRES, 30, 1e-6, 10000, BIE_SCC, 512, 1234, 0, 0, 0.0, 0, 0, 0, 0 };
+        bie_solve_opts o{ BIE_GMRES, 30, 1e-6, 10000, BIE_SCC, 512, 1234, 0, 0, 0.0, 0, 0, 0, 0, nullptr };
         if (opts) o = *opts;
         if (o.method != BIE_GMRES || o.precision != 0 || o.crit != BIE_SCC || o.basis != 0)
             return fail(BIE_EINVAL, "batched solves take GMRES, precision 0 and the standard criterion");
+        if (o.calderon) return fail(BIE_EINVAL, "batched solves take no preconditioner");
         if (o.restart < 1 || o.restart > 64) return fail(BIE_EINVAL, "restart must be 1..64");
         if (!(o.tol > 0.0)) return fail(BIE_EINVAL, "tol must be > 0");
         if (o.max_mvp < 1) return fail(BIE_EINVAL, "max_mvp must be >= 1");

@@ -145,6 +145,18 @@ struct bie_op {
 
 namespace bie {
 
+// calderon.hip: the multiplicative Calderon preconditioner.
+bie_calderon *calderon_create(const bie_op *op, hipStream_t s);
+void calderon_destroy(bie_calderon *pc);
+const bie_op *calderon_operator(const bie_calderon *pc);
+// Y = M X (R complex128 vectors; columns with skip[c * sks] != 0 left untouched).
+void calderon_apply(const bie_calderon *pc, const void *X, int64_t ldx, void *Y, int64_t ldy, int64_t R,
+                    const int *skip, int64_t sks, hipStream_t s);
+// Two R x N complex128 blocks owned by the preconditioner (grown on demand).
+double2 *calderon_scratch(const bie_calderon *pc, int64_t R, hipStream_t s);
+void add_into(int64_t n, const void *a, void *x, hipStream_t s);   // x += a (n complex)
+void zero_into(int64_t n, void *x, hipStream_t s);
+
 // fill.hip
 void upload_triangles(bie_op *op, hipStream_t s);
 void fill_matrix(bie_op *op, bool fp64_regular, bool want64, bool want32, hipStream_t s);

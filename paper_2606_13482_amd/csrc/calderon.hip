@@ -1,0 +1,581 @@
+// Multiplicative Calderon preconditioner of the EFIE (Andriulli et al., IEEE TAP
+// 56(8), 2008), which the paper uses in all of its simulations (Sec. VI-A, remark
+// on the star-split operator; Sec. VII, setup of the results) without restating it.
+//
+// M = -G^{-1} T_BC G^{-T}, stored like T in packed symmetric FP64 tiles (M is
+// complex symmetric because T_BC is), so that one preconditioned product costs
+// two packed products.  Pieces:
+//   * barycentric refinement (host): each triangle cut into six by its centroid
+//     and edge midpoints; vertices = original, then the midpoint of RWG edge m at
+//     nv + m, then the centroid of triangle t at nv + N + t;
+//   * BC functions (host): b_m is the combination of refined RWG functions on
+//     the dual cells (refined triangles around a vertex) of the two ends of edge
+//     m with charge +1/A(hi) spread uniformly over the cell of the higher vertex
+//     and -1/A(lo) over the lower one's, flux 1/2 through each of the two refined
+//     edges from the midpoint of m to the centroids of c+ and c-, and no flux
+//     through the two halves of edge m.  Walking around a cell from the child
+//     next to one half of the dual edge, the flux through each radial edge is
+//     the previous one plus the child's share of the charge;
+//   * mixed Gram matrix G_mn = <n x b_m, f_n> (host, CSR): exact with the
+//     three-edge-midpoint rule on each refined triangle (quadratic integrand);
+//   * T_BC = C Z_b C^T (device): Z_b from the FP64 fill of the refined mesh,
+//     taken in column chunks through the FP64 matrix-core product and the sparse
+//     BC map C on both sides;
+//   * G^{-1} applied to all N columns at once by CG on the normal equations
+//     (G is well conditioned), twice with a transpose in between.
+#include <algorithm>
+#include <chrono>
+#include <memory>
+#include <unordered_map>
+
+#include "bie_internal.hpp"
+
+struct bie_calderon {
+    const bie_op *op = nullptr;   // operator it was built for (mesh and k)
+    bie_op *view = nullptr;       // N x N packed FP64 tiles of M, products through the packed kernels
+    void *tmp = nullptr;          // 2 x tmp_R x N complex128 for the preconditioned solve
+    int64_t tmp_R = 0;
+    bie_calderon_info info{};
+};
+
+namespace bie {
+namespace {
+
+constexpr int CT = 256;
+
+struct Csr {
+    std::vector<int64_t> ptr;
+    std::vector<int32_t> idx;
+    std::vector<double> val;
+};
+
+struct CsrDev {
+    int64_t rows = 0;
+    int64_t *ptr = nullptr;
+    int32_t *idx = nullptr;
+    double *val = nullptr;
+    void upload(const Csr &c)
+    {
+        rows = int64_t(c.ptr.size()) - 1;
+        BIE_HIP(hipMalloc(&ptr, c.ptr.size() * sizeof(int64_t)));
+        BIE_HIP(hipMalloc(&idx, std::max<size_t>(1, c.idx.size()) * sizeof(int32_t)));
+        BIE_HIP(hipMalloc(&val, std::max<size_t>(1, c.val.size()) * sizeof(double)));
+        BIE_HIP(hipMemcpy(ptr, c.ptr.data(), c.ptr.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+        BIE_HIP(hipMemcpy(idx, c.idx.data(), c.idx.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        BIE_HIP(hipMemcpy(val, c.val.data(), c.val.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+    ~CsrDev()
+    {
+        if (ptr) (void)hipFree(ptr);
+        if (idx) (void)hipFree(idx);
+        if (val) (void)hipFree(val);
+    }
+};
+
+// ----------------------------------------------------------------------------- kernels
+
+// Y[:, c] = A X[:, c] for a real CSR matrix A and complex columns (grid.y = columns).
+__global__ __launch_bounds__(CT) void k_csr_cols(int64_t rows, const int64_t *__restrict__ ptr,
+                                                 const int32_t *__restrict__ idx, const double *__restrict__ val,
+                                                 const double2 *__restrict__ X, int64_t ldx, double2 *__restrict__ Y,
+                                                 int64_t ldy)
+{
+    const int64_t i = int64_t(blockIdx.x) * CT + threadIdx.x;
+    if (i >= rows) return;
+    const double2 *x = X + int64_t(blockIdx.y) * ldx;
+    double re = 0.0, im = 0.0;
+    for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k) {
+        const double a = val[k];
+        const double2 v = x[idx[k]];
+        re += a * v.x;
+        im += a * v.y;
+    }
+    Y[int64_t(blockIdx.y) * ldy + i] = make_double2(re, im);
+}
+
+// Column c of Xc = row j0 + c of the CSR matrix, as a dense vector (Xc zeroed first).
+__global__ void k_rows_to_cols(const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
+                               const double *__restrict__ val, int64_t j0, double2 *__restrict__ Xc, int64_t ld)
+{
+    const int64_t c = blockIdx.x;
+    for (int64_t k = ptr[j0 + c] + threadIdx.x; k < ptr[j0 + c + 1]; k += blockDim.x)
+        Xc[c * ld + idx[k]] = make_double2(val[k], 0.0);
+}
+
+__global__ void k_fill0(int64_t n, double2 *__restrict__ a)
+{
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += int64_t(gridDim.x) * blockDim.x)
+        a[e] = make_double2(0.0, 0.0);
+}
+
+// out[c] = sum_i |X[c][i]|^2, one block per column.
+__global__ __launch_bounds__(CT) void k_colsq(int64_t n, const double2 *__restrict__ X, double *__restrict__ out)
+{
+    const double2 *x = X + int64_t(blockIdx.x) * n;
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += CT) s += x[i].x * x[i].x + x[i].y * x[i].y;
+    __shared__ double red[CT / 64];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < CT / 64; ++w) t += red[w];
+        out[blockIdx.x] = t;
+    }
+}
+
+// CGNR step, per column: alpha = zz / ww; X += alpha P; R -= alpha W.
+__global__ __launch_bounds__(CT) void k_cg_xr(int64_t n, const double *__restrict__ zz, const double *__restrict__ ww,
+                                              const double2 *__restrict__ P, const double2 *__restrict__ W,
+                                              double2 *__restrict__ X, double2 *__restrict__ Rr)
+{
+    const int64_t i = int64_t(blockIdx.x) * CT + threadIdx.x;
+    if (i >= n) return;
+    const int64_t c = blockIdx.y, e = c * n + i;
+    const double a = ww[c] > 0.0 ? zz[c] / ww[c] : 0.0;
+    const double2 p = P[e], w = W[e];
+    double2 x = X[e], r = Rr[e];
+    x.x += a * p.x;
+    x.y += a * p.y;
+    r.x -= a * w.x;
+    r.y -= a * w.y;
+    X[e] = x;
+    Rr[e] = r;
+}
+
+// CGNR direction, per column: beta = zn / zz; P = Z + beta P.
+__global__ __launch_bounds__(CT) void k_cg_p(int64_t n, const double *__restrict__ zn, const double *__restrict__ zz,
+                                             const double2 *__restrict__ Zv, double2 *__restrict__ P)
+{
+    const int64_t i = int64_t(blockIdx.x) * CT + threadIdx.x;
+    if (i >= n) return;
+    const int64_t c = blockIdx.y, e = c * n + i;
+    const double b = zz[c] > 0.0 ? zn[c] / zz[c] : 0.0;
+    const double2 z = Zv[e], p = P[e];
+    P[e] = make_double2(z.x + b * p.x, z.y + b * p.y);
+}
+
+// B = A^T for column-major n x n complex matrices (32 x 32 tiles through LDS).
+__global__ __launch_bounds__(256) void k_transpose(int64_t n, const double2 *__restrict__ A, double2 *__restrict__ B)
+{
+    __shared__ double2 t[32][33];
+    const int64_t c0 = int64_t(blockIdx.y) * 32, r0 = int64_t(blockIdx.x) * 32;
+    for (int k = threadIdx.y; k < 32; k += 8) {
+        const int64_t r = r0 + threadIdx.x, c = c0 + k;
+        if (r < n && c < n) t[k][threadIdx.x] = A[c * n + r];
+    }
+    __syncthreads();
+    for (int k = threadIdx.y; k < 32; k += 8) {
+        const int64_t r = c0 + threadIdx.x, c = r0 + k;   // B(r, c) = A(c, r)
+        if (r < n && c < n) B[c * n + r] = t[threadIdx.x][k];
+    }
+}
+
+// Packed symmetric tiles (I <= J, row-major tiles of TB x TB, row-major over the
+// upper triangle) of s (A + A^T)/2 for a dense column-major n x n matrix A.
+__global__ __launch_bounds__(256) void k_pack_sym(int64_t n, int64_t nT, const double2 *__restrict__ A, double s,
+                                                  double2 *__restrict__ Zp)
+{
+    const int64_t I = blockIdx.y, J = blockIdx.x;
+    if (J < I) return;
+    double2 *tile = Zp + (I * nT - I * (I - 1) / 2 + (J - I)) * int64_t(TB * TB);
+    for (int e = threadIdx.x; e < TB * TB; e += 256) {
+        const int64_t i = I * TB + e / TB, j = J * TB + e % TB;
+        double2 v = make_double2(0.0, 0.0);
+        if (i < n && j < n) {
+            const double2 a = A[j * n + i], b = A[i * n + j];
+            v = make_double2(0.5 * s * (a.x + b.x), 0.5 * s * (a.y + b.y));
+        }
+        tile[e] = v;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_add_cols(int64_t n, const double2 *__restrict__ a, double2 *__restrict__ x)
+{
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += int64_t(gridDim.x) * blockDim.x) {
+        const double2 v = a[e];
+        double2 y = x[e];
+        y.x += v.x;
+        y.y += v.y;
+        x[e] = y;
+    }
+}
+
+// ----------------------------------------------------------------------------- host geometry
+
+struct V3 {
+    double x, y, z;
+};
+inline V3 vsub(V3 a, V3 b) { return { a.x - b.x, a.y - b.y, a.z - b.z }; }
+inline V3 vmid(V3 a, V3 b) { return { 0.5 * (a.x + b.x), 0.5 * (a.y + b.y), 0.5 * (a.z + b.z) }; }
+inline V3 vcross(V3 a, V3 b) { return { a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x }; }
+inline double vdot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+inline V3 vscale(V3 a, double s) { return { a.x * s, a.y * s, a.z * s }; }
+
+// Barycentric refinement of a validated closed mesh.
+void refine(const Mesh &M, std::vector<double> &Vb, std::vector<int32_t> &Tb)
+{
+    const int64_t nv = M.nv, N = M.N, F = M.F;
+    Vb.assign(3 * (nv + N + F), 0.0);
+    std::copy(M.V.begin(), M.V.end(), Vb.begin());
+    for (int64_t m = 0; m < N; ++m)
+        for (int d = 0; d < 3; ++d)
+            Vb[3 * (nv + m) + d] = 0.5 * (M.V[3 * M.edges[4 * m] + d] + M.V[3 * M.edges[4 * m + 1] + d]);
+    for (int64_t t = 0; t < F; ++t)
+        for (int d = 0; d < 3; ++d)
+            Vb[3 * (nv + N + t) + d] =
+                (M.V[3 * M.T[3 * t] + d] + M.V[3 * M.T[3 * t + 1] + d] + M.V[3 * M.T[3 * t + 2] + d]) / 3.0;
+    Tb.assign(18 * F, 0);
+    for (int64_t t = 0; t < F; ++t) {
+        const int32_t g = int32_t(nv + N + t);
+        for (int k = 0; k < 3; ++k) {
+            const int32_t a = M.T[3 * t + k], b = M.T[3 * t + (k + 1) % 3];
+            const int32_t mab = int32_t(nv + M.slot_m[3 * t + (k + 2) % 3]);   // edge a-b is opposite vertex k+2
+            int32_t *c0 = &Tb[3 * (6 * t + 2 * k)];
+            c0[0] = a; c0[1] = mab; c0[2] = g;
+            c0[3] = mab; c0[4] = b; c0[5] = g;
+        }
+    }
+}
+
+// BC coefficients (CSR, N rows over the refined RWG functions) and the mixed Gram
+// matrix (CSR, N x N) and its transpose.
+void bc_and_gram(const Mesh &M, const Mesh &B, Csr &C, Csr &G, Csr &Gt)
+{
+    const int64_t nv = M.nv, N = M.N, nvb = B.nv;
+    std::unordered_map<uint64_t, int32_t> eid;
+    eid.reserve(size_t(B.N) * 2);
+    for (int64_t e = 0; e < B.N; ++e) eid[uint64_t(B.edges[4 * e]) * uint64_t(nvb) + uint64_t(B.edges[4 * e + 1])] = int32_t(e);
+    auto edge_of = [&](int32_t a, int32_t b) -> int32_t {
+        const auto it = eid.find(uint64_t(std::min(a, b)) * uint64_t(nvb) + uint64_t(std::max(a, b)));
+        if (it == eid.end()) throw Error(BIE_EMESH, "refined mesh lacks an expected edge");
+        return it->second;
+    };
+    auto sigma = [&](int32_t e, int32_t t) { return B.edges[4 * e + 2] == t ? 1.0 : -1.0; };
+    auto across = [&](int32_t e, int32_t t) { return B.edges[4 * e + 2] == t ? B.edges[4 * e + 3] : B.edges[4 * e + 2]; };
+    auto Vb = [&](int32_t v) { return V3{ B.V[3 * v], B.V[3 * v + 1], B.V[3 * v + 2] }; };
+    // the radial edge of child t (corner v) other than e
+    auto other_radial = [&](int32_t t, int32_t v, int32_t e) {
+        int32_t x[2], n = 0;
+        for (int k = 0; k < 3; ++k)
+            if (B.T[3 * t + k] != v) x[n++] = B.T[3 * t + k];
+        const int32_t e1 = edge_of(v, x[0]), e2 = edge_of(v, x[1]);
+        return e1 == e ? e2 : e1;
+    };
+
+    C.ptr.assign(1, 0);
+    std::vector<std::pair<int32_t, double>> row;
+    for (int64_t m = 0; m < N; ++m) {
+        row.clear();
+        const int32_t lo = M.edges[4 * m], hi = M.edges[4 * m + 1], cp = M.edges[4 * m + 2], cm = M.edges[4 * m + 3];
+        const int32_t mid = int32_t(nv + m);
+        const int32_t half_p = edge_of(mid, int32_t(nv + N + cp)), half_m = edge_of(mid, int32_t(nv + N + cm));
+        for (int side = 0; side < 2; ++side) {
+            const int32_t v = side == 0 ? hi : lo;
+            const double charge = side == 0 ? 1.0 : -1.0;
+            const int32_t e0 = edge_of(v, mid);
+            const int32_t t1 = B.edges[4 * e0 + 2] / 6 == cp ? B.edges[4 * e0 + 2] : B.edges[4 * e0 + 3];
+            std::vector<int32_t> ts, es;
+            int32_t t = t1, prev = e0;
+            while (true) {
+                ts.push_back(t);
+                const int32_t nx = other_radial(t, v, prev);
+                if (nx == e0) break;
+                es.push_back(nx);
+                t = across(nx, t);
+                prev = nx;
+                if (ts.size() > 256) throw Error(BIE_EMESH, "dual cell walk did not close");
+            }
+            double Ac = 0.0;
+            for (int32_t c : ts) Ac += B.area[c];
+            double phi = 0.0;   // flux through the half of edge m: none
+            for (size_t i = 0; i + 1 < ts.size(); ++i) {
+                const double out_dual = i == 0 ? 0.5 * charge : 0.0;
+                phi += charge * B.area[ts[i]] / Ac - out_dual;
+                row.emplace_back(es[i], phi * sigma(es[i], ts[i]));
+            }
+            if (side == 0) {
+                row.emplace_back(half_p, 0.5 * sigma(half_p, ts.front()));
+                row.emplace_back(half_m, 0.5 * sigma(half_m, ts.back()));
+            }
+        }
+        std::sort(row.begin(), row.end());
+        for (auto &p : row) {
+            C.idx.push_back(p.first);
+            C.val.push_back(p.second);
+        }
+        C.ptr.push_back(int64_t(C.idx.size()));
+    }
+
+    // G_mn = <n x b_m, f_n>
+    G.ptr.assign(1, 0);
+    std::vector<double> acc(N, 0.0);
+    std::vector<char> seen(N, 0);
+    std::vector<int32_t> touched;
+    for (int64_t m = 0; m < N; ++m) {
+        touched.clear();
+        for (int64_t k = C.ptr[m]; k < C.ptr[m + 1]; ++k) {
+            const int32_t e = C.idx[k];
+            const double ce = C.val[k];
+            for (int side = 0; side < 2; ++side) {
+                const int32_t t = B.edges[4 * e + 2 + side], T = t / 6;
+                const V3 a = { M.V[3 * M.T[3 * T]], M.V[3 * M.T[3 * T] + 1], M.V[3 * M.T[3 * T] + 2] };
+                const V3 b = { M.V[3 * M.T[3 * T + 1]], M.V[3 * M.T[3 * T + 1] + 1], M.V[3 * M.T[3 * T + 1] + 2] };
+                const V3 c = { M.V[3 * M.T[3 * T + 2]], M.V[3 * M.T[3 * T + 2] + 1], M.V[3 * M.T[3 * T + 2] + 2] };
+                V3 nrm = vcross(vsub(b, a), vsub(c, a));
+                nrm = vscale(nrm, 1.0 / std::sqrt(vdot(nrm, nrm)));
+                int32_t fb = -1;
+                for (int q = 0; q < 3; ++q)
+                    if (B.T[3 * t + q] != B.edges[4 * e] && B.T[3 * t + q] != B.edges[4 * e + 1]) fb = B.T[3 * t + q];
+                const V3 p0 = Vb(B.T[3 * t]), p1 = Vb(B.T[3 * t + 1]), p2 = Vb(B.T[3 * t + 2]);
+                const V3 xq[3] = { vmid(p0, p1), vmid(p1, p2), vmid(p2, p0) };
+                const double sb = sigma(e, t) / (2.0 * B.area[t]);
+                for (int sl = 0; sl < 3; ++sl) {
+                    const int32_t n = M.slot_m[3 * T + sl];
+                    const V3 vf = { M.V[3 * M.T[3 * T + sl]], M.V[3 * M.T[3 * T + sl] + 1], M.V[3 * M.T[3 * T + sl] + 2] };
+                    const double sf = double(M.slot_s[3 * T + sl]) / (2.0 * M.area[T]);
+                    double s = 0.0;
+                    for (int q = 0; q < 3; ++q) {
+                        const V3 rb = vcross(nrm, vscale(vsub(xq[q], Vb(fb)), sb));
+                        s += vdot(rb, vscale(vsub(xq[q], vf), sf));
+                    }
+                    if (!seen[n]) {
+                        seen[n] = 1;
+                        touched.push_back(n);
+                    }
+                    acc[n] += ce * B.area[t] / 3.0 * s;
+                }
+            }
+        }
+        std::sort(touched.begin(), touched.end());
+        for (int32_t n : touched) {
+            G.idx.push_back(n);
+            G.val.push_back(acc[n]);
+            acc[n] = 0.0;
+            seen[n] = 0;
+        }
+        G.ptr.push_back(int64_t(G.idx.size()));
+    }
+    // transpose
+    Gt.ptr.assign(N + 1, 0);
+    for (int32_t n : G.idx) Gt.ptr[n + 1] += 1;
+    for (int64_t i = 0; i < N; ++i) Gt.ptr[i + 1] += Gt.ptr[i];
+    Gt.idx.assign(G.idx.size(), 0);
+    Gt.val.assign(G.val.size(), 0.0);
+    std::vector<int64_t> fillp(Gt.ptr.begin(), Gt.ptr.end() - 1);
+    for (int64_t m = 0; m < N; ++m)
+        for (int64_t k = G.ptr[m]; k < G.ptr[m + 1]; ++k) {
+            const int64_t d = fillp[G.idx[k]]++;
+            Gt.idx[d] = int32_t(m);
+            Gt.val[d] = G.val[k];
+        }
+}
+
+// G X = B for the nc = n columns of B by CG on the normal equations G^T G X = G^T B;
+// R (input B, overwritten by the residual), X, P, W are n x n column-major.
+void gram_solve(const CsrDev &G, const CsrDev &Gt, int64_t n, double2 *Rr, double2 *X, double2 *P, double2 *W,
+                double *sc, hipStream_t s, int64_t &iters, double &relres)
+{
+    const int64_t nn = n * n;
+    double *zz = sc, *zn = sc + n, *ww = sc + 2 * n, *rr = sc + 3 * n, *bb = sc + 4 * n;
+    const dim3 cg(unsigned((n + CT - 1) / CT), unsigned(n));
+    hipLaunchKernelGGL(k_fill0, dim3(2048), dim3(256), 0, s, nn, X);
+    hipLaunchKernelGGL(k_colsq, dim3(unsigned(n)), dim3(CT), 0, s, n, Rr, bb);
+    hipLaunchKernelGGL(k_csr_cols, cg, dim3(CT), 0, s, n, Gt.ptr, Gt.idx, Gt.val, Rr, n, P, n);   // z = G^T r
+    hipLaunchKernelGGL(k_colsq, dim3(unsigned(n)), dim3(CT), 0, s, n, P, zz);
+    BIE_HIP(hipGetLastError());
+    std::vector<double> hb(n), hr(n);
+    BIE_HIP(hipMemcpyAsync(hb.data(), bb, n * sizeof(double), hipMemcpyDeviceToHost, s));
+    BIE_HIP(hipStreamSynchronize(s));
+    const double target = 1e-13;
+    const int64_t maxit = 2000;
+    relres = 1.0;
+    for (iters = 1; iters <= maxit; ++iters) {
+        hipLaunchKernelGGL(k_csr_cols, cg, dim3(CT), 0, s, n, G.ptr, G.idx, G.val, P, n, W, n);      // w = G p
+        hipLaunchKernelGGL(k_colsq, dim3(unsigned(n)), dim3(CT), 0, s, n, W, ww);
+        hipLaunchKernelGGL(k_cg_xr, cg, dim3(CT), 0, s, n, zz, ww, P, W, X, Rr);
+        hipLaunchKernelGGL(k_csr_cols, cg, dim3(CT), 0, s, n, Gt.ptr, Gt.idx, Gt.val, Rr, n, W, n);  // z = G^T r
+        hipLaunchKernelGGL(k_colsq, dim3(unsigned(n)), dim3(CT), 0, s, n, W, zn);
+        hipLaunchKernelGGL(k_cg_p, cg, dim3(CT), 0, s, n, zn, zz, W, P);
+        BIE_HIP(hipGetLastError());
+        std::swap(zz, zn);
+        if (iters % 8 == 0 || iters == maxit) {
+            hipLaunchKernelGGL(k_colsq, dim3(unsigned(n)), dim3(CT), 0, s, n, Rr, rr);
+            BIE_HIP(hipMemcpyAsync(hr.data(), rr, n * sizeof(double), hipMemcpyDeviceToHost, s));
+            BIE_HIP(hipStreamSynchronize(s));
+            relres = 0.0;
+            for (int64_t c = 0; c < n; ++c)
+                if (hb[c] > 0.0) relres = std::max(relres, std::sqrt(hr[c] / hb[c]));
+            if (relres <= target) break;
+        }
+    }
+    if (relres > target) throw Error(BIE_ENUMERIC, "Gram solve of the Calderon preconditioner did not converge");
+    iters = std::min(iters, maxit);
+}
+
+}  // namespace
+
+// Largest N for which the preconditioner is built (the refined mesh has 6 N
+// unknowns; its FP64 matrix and dense copy take 24 (6 N)^2 bytes of HBM).
+constexpr int64_t CALDERON_MAX_N = 12288;
+
+bie_calderon *calderon_create(const bie_op *op, hipStream_t s)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    const Mesh &M = op->mesh;
+    const int64_t N = M.N;
+    if (N > CALDERON_MAX_N) throw Error(BIE_EINVAL, "Calderon preconditioner: N above 12288 (refined dense matrix too large)");
+    if (op->star) throw Error(BIE_EINVAL, "Calderon preconditioner: needs an assembled operator");
+    std::vector<double> Vb;
+    std::vector<int32_t> Tb;
+    refine(M, Vb, Tb);
+    bie_op *opb = nullptr;
+    bie_fill_opts fo{};
+    fo.storage = BIE_C128;
+    fo.near_factor = 2.0;
+    int rc = bie_op_create(Vb.data(), int64_t(Vb.size() / 3), Tb.data(), int64_t(Tb.size() / 3), op->k, &fo, s, &opb);
+    if (rc != BIE_OK) throw Error(rc, std::string("Calderon preconditioner, refined mesh: ") + bie_last_error());
+    std::unique_ptr<bie_op, void (*)(bie_op *)> hold(opb, bie_op_destroy);
+    const int64_t Nb = opb->mesh.N;
+    if (Nb != 9 * M.F) throw Error(BIE_EMESH, "refined mesh has an unexpected edge count");
+
+    Csr C, G, Gt;
+    bc_and_gram(M, opb->mesh, C, G, Gt);
+    CsrDev dC, dG, dGt;
+    dC.upload(C);
+    dG.upload(G);
+    dGt.upload(Gt);
+
+    auto pc = std::make_unique<bie_calderon>();
+    pc->op = op;
+    pc->info.N = N;
+    pc->info.Nb = Nb;
+    pc->info.nnz_bc = int64_t(C.idx.size());
+    pc->info.nnz_gram = int64_t(G.idx.size());
+
+    // dense work: T_BC / residual, X, P, W (n x n each) and column scalars
+    const int64_t nn = N * N;
+    double2 *buf[4] = {};
+    double *scal = nullptr;
+    struct Free {
+        double2 **b;
+        double **sc;
+        ~Free()
+        {
+            for (int i = 0; i < 4; ++i)
+                if (b[i]) (void)hipFree(b[i]);
+            if (*sc) (void)hipFree(*sc);
+        }
+    } guard{ buf, &scal };
+    for (int i = 0; i < 4; ++i) BIE_HIP(hipMalloc(&buf[i], size_t(nn) * sizeof(double2)));
+    BIE_HIP(hipMalloc(&scal, size_t(5 * N) * sizeof(double)));
+
+    // T_BC in column chunks: Xc = C^T[:, chunk], Yc = Z_b Xc, T_BC[:, chunk] = C Yc
+    {
+        const int64_t ch = std::min<int64_t>(N, 512);
+        double2 *Xc = nullptr, *Yc = nullptr;
+        BIE_HIP(hipMalloc(&Xc, size_t(Nb * ch) * sizeof(double2)));
+        struct F2 {
+            double2 *p;
+            ~F2() { if (p) (void)hipFree(p); }
+        } fx{ Xc };
+        BIE_HIP(hipMalloc(&Yc, size_t(Nb * ch) * sizeof(double2)));
+        F2 fy{ Yc };
+        for (int64_t j0 = 0; j0 < N; j0 += ch) {
+            const int64_t nc = std::min(ch, N - j0);
+            hipLaunchKernelGGL(k_fill0, dim3(2048), dim3(256), 0, s, Nb * nc, Xc);
+            hipLaunchKernelGGL(k_rows_to_cols, dim3(unsigned(nc)), dim3(64), 0, s, dC.ptr, dC.idx, dC.val, j0, Xc, Nb);
+            BIE_HIP(hipGetLastError());
+            gemm64_product(opb, Xc, Nb, Yc, Nb, nullptr, 0, nc, nullptr, s);
+            hipLaunchKernelGGL(k_csr_cols, dim3(unsigned((N + CT - 1) / CT), unsigned(nc)), dim3(CT), 0, s, N, dC.ptr,
+                               dC.idx, dC.val, Yc, Nb, buf[0] + j0 * N, N);
+            BIE_HIP(hipGetLastError());
+        }
+        BIE_HIP(hipStreamSynchronize(s));
+    }
+    hold.reset();   // the refined operator is no longer needed
+
+    // A1 = G^{-1} T_BC (into buf1); M' = G^{-1} A1^T (into buf1 again, A1^T in buf0)
+    gram_solve(dG, dGt, N, buf[0], buf[1], buf[2], buf[3], scal, s, pc->info.cg_iters[0], pc->info.cg_relres[0]);
+    hipLaunchKernelGGL(k_transpose, dim3(unsigned((N + 31) / 32), unsigned((N + 31) / 32)), dim3(32, 8), 0, s, N,
+                       buf[1], buf[0]);
+    BIE_HIP(hipGetLastError());
+    gram_solve(dG, dGt, N, buf[0], buf[1], buf[2], buf[3], scal, s, pc->info.cg_iters[1], pc->info.cg_relres[1]);
+
+    // M = -(M' + M'^T)/2 in packed tiles
+    bie_op *v = new bie_op();
+    pc->view = v;
+    v->device = op->device;
+    v->k = op->k;
+    v->storage = BIE_C128;
+    v->mesh.N = N;
+    packed_setup(v->pk, N);
+    BIE_HIP(hipMalloc(&v->Z64, size_t(v->pk.ntiles) * TB * TB * sizeof(double2)));
+    hipLaunchKernelGGL(k_pack_sym, dim3(unsigned(v->pk.nT), unsigned(v->pk.nT)), dim3(256), 0, s, N, v->pk.nT,
+                       buf[1], -1.0, (double2 *)v->Z64);
+    BIE_HIP(hipGetLastError());
+    BIE_HIP(hipStreamSynchronize(s));
+    pc->info.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return pc.release();
+}
+
+void calderon_destroy(bie_calderon *pc)
+{
+    if (!pc) return;
+    if (pc->view) {
+        free_workspace(pc->view);
+        packed_free(pc->view->pk);
+        if (pc->view->Z64) (void)hipFree(pc->view->Z64);
+        delete pc->view;
+    }
+    if (pc->tmp) (void)hipFree(pc->tmp);
+    delete pc;
+}
+
+const bie_op *calderon_operator(const bie_calderon *pc) { return pc->op; }
+
+// Two R x N complex128 scratch blocks for the preconditioned solve.
+double2 *calderon_scratch(const bie_calderon *pcc, int64_t R, hipStream_t s)
+{
+    bie_calderon *pc = const_cast<bie_calderon *>(pcc);
+    if (pc->tmp_R < R) {
+        BIE_HIP(hipStreamSynchronize(s));
+        if (pc->tmp) (void)hipFree(pc->tmp);
+        pc->tmp = nullptr;
+        pc->tmp_R = 0;
+        BIE_HIP(hipMalloc(&pc->tmp, size_t(2 * R * pc->info.N) * sizeof(double2)));
+        pc->tmp_R = R;
+    }
+    return static_cast<double2 *>(pc->tmp);
+}
+
+void calderon_apply(const bie_calderon *pc, const void *X, int64_t ldx, void *Y, int64_t ldy, int64_t R,
+                    const int *skip, int64_t sks, hipStream_t s)
+{
+    product(pc->view, MAT64, true, X, ldx, Y, ldy, nullptr, 0, R, skip, sks, false, s);
+}
+
+// x += a for n complex entries.
+void add_into(int64_t n, const void *a, void *x, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_add_cols, dim3(unsigned(std::min<int64_t>((n + 255) / 256, 4096))), dim3(256), 0, s, n,
+                       (const double2 *)a, (double2 *)x);
+    BIE_HIP(hipGetLastError());
+}
+
+void zero_into(int64_t n, void *x, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill0, dim3(unsigned(std::min<int64_t>((n + 255) / 256, 4096))), dim3(256), 0, s, n,
+                       (double2 *)x);
+    BIE_HIP(hipGetLastError());
+}
+
+}  // namespace bie
+
+extern "C" int bie_calderon_get_info(const bie_calderon *pc, bie_calderon_info *info)
+{
+    if (!pc || !info) return BIE_EINVAL;
+    *info = pc->info;
+    return BIE_OK;
+}

@@ -1009,6 +1009,9 @@ static int solve_impl(const bie_op *opc, const void *Bv, void *Xv, int64_t R, co
     const int m = o.method == BIE_GMRES ? o.restart : 1;
     Workspace *w = get_ws(op, R, m);
     const Cols ucols = uniform_cols(N, m);
+    // Calderon preconditioner (GMRES only): two R x N scratch blocks
+    const bie_calderon *pcd = o.method == BIE_GMRES ? o.calderon : nullptr;
+    double2 *pcw = pcd ? calderon_scratch(pcd, R, s) : nullptr;
     const double2 *B = static_cast<const double2 *>(Bv);
     double2 *X = static_cast<double2 *>(Xv);
     std::vector<bie_solve_stat> hs(R);
@@ -1213,13 +1216,26 @@ static int solve_impl(const bie_op *opc, const void *Bv, void *Xv, int64_t R, co
             for (int64_t r = 0; r < R; ++r)
                 if (active[r]) jmax = std::max(jmax, st[r].jcap);
             for (int j = 0; j < jmax; ++j) {
-                product(op, fp64, true, w->V + int64_t(j) * N, int64_t(m + 1) * N, w->W, N, nullptr, 0, R,
-                        done_flags, done_stride, false, s);
+                const double2 *vj = w->V + int64_t(j) * N;
+                if (pcd) {   // right preconditioning: w = T (M v_j)
+                    calderon_apply(pcd, vj, int64_t(m + 1) * N, pcw, N, R, done_flags, done_stride, s);
+                    product(op, fp64, true, pcw, N, w->W, N, nullptr, 0, R, done_flags, done_stride, false, s);
+                } else {
+                    product(op, fp64, true, vj, int64_t(m + 1) * N, w->W, N, nullptr, 0, R, done_flags, done_stride,
+                            false, s);
+                }
                 arnoldi_step<double2>(w, ucols, N, w->V, m, j, o.tol, R, s);
             }
             hipLaunchKernelGGL(k_lsq, dim3(unsigned(R)), dim3(64), size_t(m) * m * sizeof(double2), s, m, w->H, w->g,
                                w->y, w->st);
-            hipLaunchKernelGGL(k_xupd<double2>, egrid, dim3(BT), 0, s, ucols, m, w->V, w->y, X, w->st);
+            if (pcd) {   // x += M (V y): V y formed in the scratch block, then one preconditioner product
+                zero_into(R * N, pcw, s);
+                hipLaunchKernelGGL(k_xupd<double2>, egrid, dim3(BT), 0, s, ucols, m, w->V, w->y, pcw, w->st);
+                calderon_apply(pcd, pcw, N, pcw + R * N, N, R, nullptr, 1, s);
+                add_into(R * N, pcw + R * N, X, s);
+            } else {
+                hipLaunchKernelGGL(k_xupd<double2>, egrid, dim3(BT), 0, s, ucols, m, w->V, w->y, X, w->st);
+            }
             BIE_HIP(hipGetLastError());
             pull_st();
             std::vector<int> cand(R, 0);

@@ -69,6 +69,9 @@ def test_null_arguments():
     assert bie._lib.bie_apply(None, None, None, 1, 0, 0, None) == bie.BIE_EINVAL
     assert bie._lib.bie_solve(None, None, None, 1, None, None, None) == bie.BIE_EINVAL
     assert bie._lib.bie_rscc_rows(10, 0, 1, None) == bie.BIE_EINVAL
+    assert bie._lib.bie_calderon_create(None, None, ctypes.byref(ctypes.c_void_p())) == bie.BIE_EINVAL
+    assert bie._lib.bie_calderon_apply(None, None, None, 1, None) == bie.BIE_EINVAL
+    assert bie._lib.bie_calderon_get_info(None, None) == bie.BIE_EINVAL
 
 
 def test_struct_layouts_match_header(tmp_path):
@@ -81,7 +84,7 @@ def test_struct_layouts_match_header(tmp_path):
     if shutil.which("gcc") is None:
         pytest.skip("gcc not available")
     structs = {"bie_fill_opts": bie.FillOpts, "bie_solve_opts": bie.SolveOpts, "bie_solve_stat": bie.SolveStat,
-               "bie_ws_opts": bie.WsOpts}
+               "bie_ws_opts": bie.WsOpts, "bie_calderon_info": bie.CalderonInfo}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "bie.h"', 'int main(void) {']
     for cname, py in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
