@@ -175,8 +175,11 @@ typedef struct {
                             operator (bie_calderon_create): GMRES then runs on
                             T M u = b with x = M u (right preconditioning, so the
                             GMRES residual and the criteria stay those of T x = b).
-                            Method BIE_GMRES and precision 0 only (BIE_EINVAL
-                            otherwise, or if it was built for another operator) */
+                            Method BIE_GMRES with precision 0, or BIE_BGMRES (the
+                            steps form T (M V_j) with two block products, split-BF16
+                            with precision 1; each cycle ends with X += M U in FP64);
+                            BIE_EINVAL otherwise, or if it was built for another
+                            operator */
 } bie_solve_opts;
 
 typedef struct {

@@ -225,8 +225,8 @@ int bie_solve(const bie_op *op, const void *B, void *X, int64_t R, const bie_sol
             if (!op->Z64) return fail(BIE_EINVAL, "block GMRES needs the FP64 matrix");
         }
         if (o.calderon) {
-            if (o.method != BIE_GMRES || o.precision != 0)
-                return fail(BIE_EINVAL, "the Calderon preconditioner takes GMRES with precision 0");
+            if (o.method == BIE_CGNR || (o.method == BIE_GMRES && o.precision != 0))
+                return fail(BIE_EINVAL, "the Calderon preconditioner takes GMRES with precision 0 or block GMRES");
             if (bie::calderon_operator(o.calderon) != op)
                 return fail(BIE_EINVAL, "the Calderon preconditioner was built for another operator");
         }

@@ -1109,10 +1109,17 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
     // whose storage already bounds orthogonality near 1e-7 against their
     // tolerance of 1e-3 .. 1e-1
     const double reorth = mixed ? 0.0 : 0.5;
+    // Calderon preconditioner on the right: each step forms T (M V_j); a cycle's
+    // solution U of T M U = residual gathers in Ux and X += M U ends the cycle
+    const bie_calderon *pcd = o.calderon;
+    bie_op *pview = pcd ? calderon_view(pcd, mixed, s) : nullptr;
 
     Bufs db;
     double2 *Rres = db.get<double2>(size_t(R) * N);
     double2 *Wb = db.get<double2>(size_t(R) * N);
+    double2 *Wt = pcd ? db.get<double2>(size_t(R) * N) : nullptr;   // M V_j
+    double2 *Ux = pcd ? db.get<double2>(size_t(R) * N) : nullptr;
+    double2 *Du = pcd ? db.get<double2>(size_t(R) * N) : nullptr;   // M U
     VT *V = db.get<VT>(size_t(m + 1) * R * N);
     const int64_t tiles = ((m + 1) * p + DT - 1) / DT + 1;   // basis tiles per group, and its Gram item
     double2 *part = db.get<double2>(size_t(Gmax * tiles + 1024) * DT * BMAX);
@@ -1312,6 +1319,7 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
             ar.flush(s);
             launch_comb<double2, VT>(ci, it.size(), N, p, s);
         }
+        if (pcd) zero_into(R * N, Ux, s);
         // (3) block Arnoldi steps; every active group advances together.  The
         // least-squares update of step j runs on the second stream beside the
         // orthogonalisation of step j + 1; its estimates are read one step late,
@@ -1388,8 +1396,18 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
                 const CItem *pc0 = A.put(ci[0]), *pc1 = A.put(ci[1]), *pcs = A.put(cs);
                 A.flush(s);
                 const VT *Vj = V + int64_t(j) * Wc * N;
-                if (mixed) gemm_product(op, Vj, N, VEC_C64, Wb, N, nullptr, 0, int64_t(cols.size()), dc, s, terms);
-                else gemm64_product(op, Vj, N, Wb, N, nullptr, 0, int64_t(cols.size()), dc, s);
+                const int64_t nc = int64_t(cols.size());
+                if (pcd && mixed) {
+                    gemm_product(pview, Vj, N, VEC_C64, Wt, N, nullptr, 0, nc, dc, s, terms);
+                    gemm_product(op, Wt, N, VEC_C128, Wb, N, nullptr, 0, nc, dc, s, terms);
+                } else if (pcd) {
+                    gemm64_product(pview, Vj, N, Wt, N, nullptr, 0, nc, dc, s);
+                    gemm64_product(op, Wt, N, Wb, N, nullptr, 0, nc, dc, s);
+                } else if (mixed) {
+                    gemm_product(op, Vj, N, VEC_C64, Wb, N, nullptr, 0, nc, dc, s, terms);
+                } else {
+                    gemm64_product(op, Vj, N, Wb, N, nullptr, 0, nc, dc, s);
+                }
                 launch_ls();
                 int64_t pairs = 0;   // basis vector x column pairs of the first pass
                 for (int g : act) pairs += int64_t(j + 1) * grp[g].r * grp[g].r;
@@ -1445,8 +1463,8 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
                     for (int g : ended) oc.push_back(A.put(grp[g].rhs));
                     for (size_t e = 0; e < ended.size(); ++e) {
                         const HGroup &h = grp[ended[e]];
-                        it.push_back(CItem{ V + int64_t(h.c0) * N, Wc, hg[ended[e]].Y, X, oc[e], nullptr, 1.0, 1.0, h.r,
-                                            h.steps * h.r, h.q, h.q });
+                        it.push_back(CItem{ V + int64_t(h.c0) * N, Wc, hg[ended[e]].Y, pcd ? Ux : X, oc[e], nullptr, 1.0,
+                                            1.0, h.r, h.steps * h.r, h.q, h.q });
                     }
                     const CItem *pit = A.put(it);
                     A.copy_to(gsteps, hsteps.data(), size_t(ng), s3);   // also uploads the tables above
@@ -1467,6 +1485,12 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
         }
         BIE_HIP(hipStreamSynchronize(s2));
         BIE_HIP(hipStreamSynchronize(s3));
+        if (pcd) {   // X += M U (zero for the columns outside this cycle), on the matrix cores: split-BF16
+                     // with 3 terms in the refinement (its 1e-5 error is far below the inner tolerance), else FP64
+            if (mixed) gemm_product(pview, Ux, N, VEC_C128, Du, N, nullptr, 0, R, nullptr, s, 3);
+            else gemm64_product(pview, Ux, N, Du, N, nullptr, 0, R, nullptr, s);
+            add_into(R * N, Du, X, s);
+        }
     }
     sync();
     int status = BIE_OK;

@@ -149,6 +149,9 @@ namespace bie {
 bie_calderon *calderon_create(const bie_op *op, hipStream_t s);
 void calderon_destroy(bie_calderon *pc);
 const bie_op *calderon_operator(const bie_calderon *pc);
+// The operator holding M (packed FP64 tiles), for products through the library's
+// kernels; split: also its split-BF16 copy (made on first use).
+bie_op *calderon_view(const bie_calderon *pc, bool split, hipStream_t s);
 // Y = M X (R complex128 vectors; columns with skip[c * sks] != 0 left untouched).
 void calderon_apply(const bie_calderon *pc, const void *X, int64_t ldx, void *Y, int64_t ldy, int64_t R,
                     const int *skip, int64_t sks, hipStream_t s);

@@ -535,6 +535,14 @@ void calderon_destroy(bie_calderon *pc)
 
 const bie_op *calderon_operator(const bie_calderon *pc) { return pc->op; }
 
+// The operator holding M (packed FP64 tiles); split: also its split-BF16 copy for
+// the block product (made on first use).
+bie_op *calderon_view(const bie_calderon *pc, bool split, hipStream_t s)
+{
+    if (split && !pc->view->Abf) split_matrix(pc->view, s);
+    return pc->view;
+}
+
 // Two R x N complex128 scratch blocks for the preconditioned solve.
 double2 *calderon_scratch(const bie_calderon *pcc, int64_t R, hipStream_t s)
 {
