@@ -55,7 +55,8 @@ def parse():
     ap.add_argument("--k", type=float, default=10.0)
     ap.add_argument("--restart", type=int, default=50)
     ap.add_argument("--tol", type=float, default=1e-6)
-    ap.add_argument("--inner-tol", type=float, default=1e-1)
+    ap.add_argument("--inner-tol", type=float, default=None,
+                    help="inner tolerance of the refinement; default 0.03 with the Calderon preconditioner, else 0.1")
     ap.add_argument("--inner-terms", type=int, default=None, choices=[2, 3],
                     help="terms of the inner split-BF16 products: 3 (hi/lo matrix x hi/lo vectors) or 2 (hi/lo "
                          "matrix x BF16 vectors); default 2 for block GMRES, 3 for column GMRES")
@@ -66,6 +67,8 @@ def parse():
                     help="inner solver of the mixed-precision forms: column GMRES as a continuous batch, or "
                          "block GMRES over groups of --block right-hand sides")
     ap.add_argument("--block", type=int, default=32)
+    ap.add_argument("--no-calderon", dest="calderon", action="store_false",
+                    help="headline without the multiplicative Calderon preconditioner (block GMRES only uses it)")
     ap.add_argument("--train-dirs", type=int, default=512)
     ap.add_argument("--test-dirs", type=int, default=256)
     ap.add_argument("--epochs", type=int, default=1500)
@@ -85,6 +88,8 @@ def parse():
     a = ap.parse_args()
     if a.inner_terms is None:
         a.inner_terms = 2 if a.method == "bgmres" else 3
+    if a.inner_tol is None:   # the preconditioned inner solves are short: a tighter tolerance saves outer cycles
+        a.inner_tol = 0.03 if (a.calderon and a.method == "bgmres" and not a.c3) else 0.1
     if a.c5:
         a.train_dirs, a.test_dirs, a.epochs = 2048, 512, 3000
     return a
@@ -114,20 +119,21 @@ def traffic_from_profiles(fname: str, kernel_src: str, N: int):
         return None
 
 
-def solver_text(args, restart):
+def solver_text(args, restart, calderon=False):
     if args.method == "bgmres":
-        return f"block GMRES({restart}) over groups of {args.block} right-hand sides"
+        pre = "Calderon-preconditioned (right, M = -G^-1 T_BC G^-T) " if calderon else ""
+        return f"{pre}block GMRES({restart}) over groups of {args.block} right-hand sides"
     return (f"GMRES({restart}), {'FP16' if args.basis == 'f16' else 'complex64'} inner Krylov basis, continuous "
             f"batch of {args.slots} slots")
 
 
-def mixed_opts(args, bie, restart):
+def mixed_opts(args, bie, restart, pc=None):
     """Options of the mixed-precision solves: column GMRES as a continuous batch
     (FP16 or complex64 basis), or block GMRES (complex64 basis, all right-hand
-    sides at once)."""
+    sides at once; right-preconditioned by pc when given)."""
     if args.method == "bgmres":
         return bie.Solve(method="bgmres", block=args.block, restart=restart, tol=args.tol, max_mvp=20000,
-                         precision="mixed", inner_tol=args.inner_tol, inner_terms=args.inner_terms)
+                         precision="mixed", inner_tol=args.inner_tol, inner_terms=args.inner_terms, calderon=pc)
     return bie.Solve(restart=restart, tol=args.tol, max_mvp=20000, precision="mixed", inner_tol=args.inner_tol,
                      slots=args.slots, inner_terms=args.inner_terms, basis=args.basis)
 
@@ -223,7 +229,16 @@ def headline_leg(args, bie, torch, V, T, k):
     sync()
     res["setup_fill_split_s"] = round(time.perf_counter() - t0, 4)
     N = op.N
-    mopts = mixed_opts(args, bie, args.restart)
+    pc = None
+    if args.calderon and args.method == "bgmres":
+        t0 = time.perf_counter()
+        pc = bie.Calderon(op)
+        sync()
+        res["setup_calderon_s"] = round(time.perf_counter() - t0, 4)
+        ci = pc.info()
+        res["calderon"] = {"refined_unknowns": ci["Nb"], "bc_nonzeros": ci["nnz_bc"], "gram_nonzeros": ci["nnz_gram"],
+                           "gram_cg_iters": ci["cg_iters"], "gram_cg_relres": max(ci["cg_relres"])}
+    mopts = mixed_opts(args, bie, args.restart, pc)
     popts = bie.Solve(restart=args.restart, tol=args.tol, max_mvp=20000)
 
     # training: solutions the method computes, then POD + MLP on the GPU
@@ -298,6 +313,19 @@ def headline_leg(args, bie, torch, V, T, k):
     sync()
     t_plain = (time.perf_counter() - t0) / ns
     Xp = torch.cat(Xp)
+    # the paper's preconditioned method in plain FP64 (column GMRES on T M u = b) on the same sample
+    plain_cal = None
+    if pc is not None:
+        copts = bie.Solve(restart=args.restart, tol=args.tol, max_mvp=20000, calderon=pc)
+        itc = []
+        sync()
+        t0 = time.perf_counter()
+        for i in idx:
+            _, s = op.solve(B[i:i + 1], copts)
+            itc.append(s[0]["iters"])
+        sync()
+        t_cal = (time.perf_counter() - t0) / ns
+        plain_cal = {"rhs": int(ns), "solves_per_s": round(1.0 / t_cal, 4), "iters_mean": float(np.mean(itc))}
     # a tight FP64 solution of the sample for the forward errors
     Xt, _ = op.solve(B[idx], bie.Solve(restart=args.restart, tol=1e-10, max_mvp=40000))
     nt = torch.linalg.vector_norm(Xt, dim=1)
@@ -319,6 +347,8 @@ def headline_leg(args, bie, torch, V, T, k):
         "plain_fp64_sample": {"rhs": int(ns), "solves_per_s": round(plain_rate, 4),
                               "iters_mean": float(np.mean([a for a, _ in itp]))},
         "speedup_vs_plain_fp64": round(value / plain_rate, 2),
+        "plain_fp64_calderon_sample": plain_cal,
+        "speedup_vs_plain_fp64_calderon": None if plain_cal is None else round(value / plain_cal["solves_per_s"], 2),
         "speedup_no_warm_start_vs_plain_fp64": round((R / t_zero) / plain_rate, 2),
         "forward_error_vs_tight_fp64": {"plain_fp64": fwd(Xp), "mixed_learned": fwd(X[idx]),
                                         "mixed_zero": fwd(Xz[idx]), "reference": "FP64 GMRES to 1e-10 on the sample"},
@@ -356,6 +386,8 @@ def headline_leg(args, bie, torch, V, T, k):
                            "share_of_step": round(ms / (t_steps * 1e3), 3)}))
     cands.sort(key=lambda c: -c[0])
     res["kernel_rooflines"] = [c[1] for c in cands]
+    if pc is not None:
+        pc.close()
     op.close()
     return res, cands[0][1], ms_step, float(np.mean([b for _, b in itp])), int(ns)
 
@@ -635,12 +667,13 @@ def main():
                                 f"{2 * args.test_dirs} held-out plane waves ({args.test_dirs} directions x theta/phi), "
                                 f"operator and warm start resident; learned warm start (POD {min(256, 2 * args.train_dirs)}, "
                                 f"MLP 4-512-512, trained on {2 * args.train_dirs} solves); "
-                                f"{solver_text(args, args.restart)} on split-BF16 MFMA products with FP64 refinement "
-                                f"to {args.tol:g} (FP64 SCC)"),
+                                f"{solver_text(args, args.restart, args.calderon)} on split-BF16 MFMA products with "
+                                f"FP64 refinement to {args.tol:g} (FP64 SCC)"),
                    "N": N, "k": k, "restart": args.restart, "inner_tol": args.inner_tol, "method": args.method,
                    "block": args.block if args.method == "bgmres" else None,
                    "slots": args.slots if args.method == "gmres" else None,
                    "inner_terms": args.inner_terms, "basis": args.basis if args.method == "gmres" else "c64",
+                   "calderon": bool(args.calderon and args.method == "bgmres"),
                    "rhs_per_step": 2 * args.test_dirs, "train_directions": args.train_dirs,
                    "test_directions": args.test_dirs, "parallelism": "single GPU"},
         "roofline": roof,
