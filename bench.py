@@ -42,6 +42,7 @@ HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
 BF16_PEAK_TFLOPS = 2500.0    # MI355X dense BF16 MFMA
 FP64_VALU_PEAK_TFLOPS = 78.6  # 256 CUs x 4 SIMDs x 16 FP64 lanes x 2 flops (FMA) x 2.4 GHz
 FP32_MFMA_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix
+FP64_MFMA_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix
 METRIC = "GMRES solves/s to 1e-6 residual: batched mixed+learned vs plain FP64; GEMV GB/s"
 
 
@@ -56,10 +57,10 @@ def parse():
     ap.add_argument("--restart", type=int, default=50)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--inner-tol", type=float, default=None,
-                    help="inner tolerance of the refinement; default 0.03 with the Calderon preconditioner, else 0.1")
+                    help="inner tolerance of the refinement; default 1e-3 with the Calderon preconditioner, else 0.1")
     ap.add_argument("--inner-terms", type=int, default=None, choices=[2, 3],
                     help="terms of the inner split-BF16 products: 3 (hi/lo matrix x hi/lo vectors) or 2 (hi/lo "
-                         "matrix x BF16 vectors); default 2 for block GMRES, 3 for column GMRES")
+                         "matrix x BF16 vectors); default 2 for unpreconditioned block GMRES, else 3")
     ap.add_argument("--basis", default="f16", choices=["f16", "c64"],
                     help="storage of the inner Krylov basis (FP16 pairs or complex64)")
     ap.add_argument("--slots", type=int, default=256)
@@ -86,10 +87,11 @@ def parse():
                     help="only launch the dense product kernels a few times at the bench sizes, and a 1 GiB "
                          "device copy as calibration, for hardware-counter runs")
     a = ap.parse_args()
-    if a.inner_terms is None:
-        a.inner_terms = 2 if a.method == "bgmres" else 3
+    cal = a.calderon and a.method == "bgmres" and not a.c3
+    if a.inner_terms is None:   # 2 terms only pay with long unpreconditioned inner solves
+        a.inner_terms = 2 if (a.method == "bgmres" and not cal) else 3
     if a.inner_tol is None:   # the preconditioned inner solves are short: a tighter tolerance saves outer cycles
-        a.inner_tol = 0.03 if (a.calderon and a.method == "bgmres" and not a.c3) else 0.1
+        a.inner_tol = 1e-3 if cal else 0.1
     if a.c5:
         a.train_dirs, a.test_dirs, a.epochs = 2048, 512, 3000
     return a
@@ -272,7 +274,7 @@ def headline_leg(args, bie, torch, V, T, k):
     for _ in range(args.warmup):
         step()
     sync()
-    for k in (0, 1, 4, 5):
+    for k in (0, 1, 2, 4, 5):
         bie.prof_read(k)
     bie.prof_enable(True)
     t0 = time.perf_counter()
@@ -281,6 +283,7 @@ def headline_leg(args, bie, torch, V, T, k):
     sync()
     t_steps = time.perf_counter() - t0
     g_launch, g_ms, g_cols = bie.prof_read(1, columns=True)
+    f_launch, f_ms, f_cols = bie.prof_read(2, columns=True)
     p_launch, p_ms = bie.prof_read(0)
     orth = {k: bie.prof_read(k, columns=True) for k in (4, 5)}
     bie.prof_enable(False)
@@ -370,6 +373,21 @@ def headline_leg(args, bie, torch, V, T, k):
     # on the complex64 basis of the refinement's inner solves, FP32 matrix cores;
     # 8 real flops per row for every basis vector x column pair
     cands = [(g_ms, roof)]
+    # the refinement's FP64 residuals B - T X (FP64 matrix cores, 8 N^2 flops per column)
+    if f_launch:
+        avg_f = f_ms / f_launch
+        alg_f = 8.0 * N * N * f_cols / f_launch
+        ach_f = alg_f / (avg_f * 1e-3) / 1e12
+        cands.append((f_ms, {"bound": "mfma", "achieved": round(ach_f, 1), "peak": FP64_MFMA_PEAK_TFLOPS,
+                             "unit": "TFLOP/s", "frac": round(ach_f / FP64_MFMA_PEAK_TFLOPS, 4),
+                             "traffic": traffic_from_profiles("gemm64_fp64_n7680_r512_counters.txt", "gemm.hip", N),
+                             "traffic_note": "HBM bytes per launch at 512 columns (counters), null if the kernel "
+                                             "changed since",
+                             "kernel": "FP64 complex block product of the refinement residuals (k_gemm64, "
+                                       "v_mfma_f64_16x16x4f64)",
+                             "alg_flops_per_launch": alg_f, "avg_columns_per_launch": round(f_cols / f_launch, 1),
+                             "avg_launch_us": round(avg_f * 1e3, 2), "launches": f_launch,
+                             "share_of_step": round(f_ms / (t_steps * 1e3), 3)}))
     names = {4: "block GMRES basis dots V^H W (k_bdots_mf + k_bdots_fin, v_mfma_f32_32x32x2f32)",
              5: "block GMRES basis update W -= V C (k_bcomb_mf, v_mfma_f32_32x32x2f32)"}
     for k, (n_l, ms, pairs) in orth.items():

@@ -875,6 +875,20 @@ __global__ void k_bzero(int64_t n, double2 *__restrict__ a)
         a[i] = make_double2(0.0, 0.0);
 }
 
+// Start-of-cycle uploads of every group in one launch: dst[0 .. n) = src, then
+// zeros up to nzero (doubles).
+struct SItem {
+    const double *src;
+    double *dst;
+    int64_t n, nzero;
+};
+
+__global__ __launch_bounds__(256) void k_bscatter(const SItem *__restrict__ items)
+{
+    const SItem t = items[blockIdx.x];
+    for (int64_t i = threadIdx.x; i < t.nzero; i += 256) t.dst[i] = i < t.n ? t.src[i] : 0.0;
+}
+
 using cd = std::complex<double>;
 
 // Device allocations released at scope exit.
@@ -1113,11 +1127,12 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
     // solution U of T M U = residual gathers in Ux and X += M U ends the cycle
     const bie_calderon *pcd = o.calderon;
     bie_op *pview = pcd ? calderon_view(pcd, mixed, s) : nullptr;
+    bie_op *ptm = pcd && mixed ? calderon_tm(pcd, s) : nullptr;   // T M as one split-BF16 operand
 
     Bufs db;
     double2 *Rres = db.get<double2>(size_t(R) * N);
     double2 *Wb = db.get<double2>(size_t(R) * N);
-    double2 *Wt = pcd ? db.get<double2>(size_t(R) * N) : nullptr;   // M V_j
+    double2 *Wt = pcd && !mixed ? db.get<double2>(size_t(R) * N) : nullptr;   // M V_j (FP64 form)
     double2 *Ux = pcd ? db.get<double2>(size_t(R) * N) : nullptr;
     double2 *Du = pcd ? db.get<double2>(size_t(R) * N) : nullptr;   // M U
     VT *V = db.get<VT>(size_t(m + 1) * R * N);
@@ -1173,6 +1188,10 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
         aux.pinned.push_back(hfl[i]);
     }
     int *gsteps = db.get<int>(size_t(Gmax));
+    double2 *gG = db.get<double2>(size_t(Gmax) * p2);   // Gram matrices of the start blocks, gathered
+    double2 *hGpin = nullptr;
+    BIE_HIP(hipHostMalloc(reinterpret_cast<void **>(&hGpin), size_t(Gmax) * p2 * sizeof(double2)));
+    aux.pinned.push_back(hGpin);
     std::vector<int> hsteps(Gmax, 0);
     auto sync = [&]() {
         BIE_HIP(hipStreamSynchronize(s));
@@ -1271,12 +1290,26 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
                                dim3(256), 0, s, N, (const double2 *)Rres, dl, Wb);
             launch_dots<double2, 1>(di, it.size(), N, part, p, s);
         }
-        std::vector<std::vector<cd>> hG(ng);
-        for (int g = 0; g < ng; ++g) {
-            hG[g].resize(size_t(grp[g].q) * grp[g].q);
-            BIE_HIP(hipMemcpyAsync(hG[g].data(), hg[g].G1, hG[g].size() * sizeof(double2), hipMemcpyDeviceToHost, s));
+        // the Gram matrices of all groups gathered on the device, then one copy to pinned memory
+        {
+            std::vector<SItem> gi;
+            for (int g = 0; g < ng; ++g) {
+                const int64_t n = 2 * int64_t(grp[g].q) * grp[g].q;
+                gi.push_back(SItem{ reinterpret_cast<const double *>(hg[g].G1),
+                                    reinterpret_cast<double *>(gG + size_t(g) * p2), n, n });
+            }
+            const SItem *dgi = ar.put(gi);
+            ar.flush(s);
+            hipLaunchKernelGGL(k_bscatter, dim3(unsigned(ng)), dim3(256), 0, s, dgi);
+            BIE_HIP(hipGetLastError());
+            BIE_HIP(hipMemcpyAsync(hGpin, gG, size_t(ng) * p2 * sizeof(double2), hipMemcpyDeviceToHost, s));
         }
         sync();
+        std::vector<std::vector<cd>> hG(ng);
+        for (int g = 0; g < ng; ++g) {
+            const cd *src = reinterpret_cast<const cd *>(hGpin) + size_t(g) * p2;
+            hG[g].assign(src, src + size_t(grp[g].q) * grp[g].q);
+        }
         int Wc = 0;
         std::vector<std::vector<cd>> T0(ng), S(ng);
         for (int g = 0; g < ng; ++g) {
@@ -1284,6 +1317,7 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
             h.scale.resize(h.q);
             for (int a = 0; a < h.q; ++a) h.scale[a] = std::sqrt(std::max(hG[g][a * h.q + a].real(), 0.0));
             h.r = rank_revealing(hG[g], h.q, h.scale, T0[g], S[g]);
+            if (h.r < 1) throw Error(BIE_ENUMERIC, "block GMRES: start block of rank 0 for unconverged right-hand sides");
             h.c0 = Wc;
             Wc += h.r;
             h.target.resize(h.q);
@@ -1301,6 +1335,7 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
         ar.copy_to(gd, hg.data(), size_t(ng), s);
         {
             std::vector<CItem> it;
+            std::vector<SItem> up;
             for (int g = 0; g < ng; ++g) {
                 const HGroup &h = grp[g];
                 std::vector<double2> t0(T0[g].size());
@@ -1309,14 +1344,19 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
                 it.push_back(CItem{ Wb + int64_t(h.qoff) * N, 0, dT, V + int64_t(h.c0) * N, nullptr, nullptr, 1.0, 0.0,
                                     h.q, h.q, h.r, h.r });
                 // E_1 S into Gv (rows 0 .. r), zeros below; column scales
-                hipLaunchKernelGGL(k_bzero, dim3(64), dim3(256), 0, s, int64_t(m + 1) * h.r * h.q, hg[g].Gv);
                 std::vector<double2> sv(S[g].size());
                 for (size_t e = 0; e < sv.size(); ++e) sv[e] = make_double2(S[g][e].real(), S[g][e].imag());
-                ar.copy_to(hg[g].Gv, sv.data(), sv.size(), s);
-                ar.copy_to(hg[g].scale, h.scale.data(), size_t(h.q), s);
+                const double2 *dS = ar.put(sv);
+                const double *dsc = ar.put(h.scale);
+                up.push_back(SItem{ reinterpret_cast<const double *>(dS), reinterpret_cast<double *>(hg[g].Gv),
+                                    2 * int64_t(sv.size()), 2 * int64_t(m + 1) * h.r * h.q });
+                up.push_back(SItem{ dsc, hg[g].scale, int64_t(h.q), int64_t(h.q) });
             }
             const CItem *ci = ar.put(it);
+            const SItem *dup = ar.put(up);
             ar.flush(s);
+            hipLaunchKernelGGL(k_bscatter, dim3(unsigned(up.size())), dim3(256), 0, s, dup);
+            BIE_HIP(hipGetLastError());
             launch_comb<double2, VT>(ci, it.size(), N, p, s);
         }
         if (pcd) zero_into(R * N, Ux, s);
@@ -1398,8 +1438,7 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
                 const VT *Vj = V + int64_t(j) * Wc * N;
                 const int64_t nc = int64_t(cols.size());
                 if (pcd && mixed) {
-                    gemm_product(pview, Vj, N, VEC_C64, Wt, N, nullptr, 0, nc, dc, s, terms);
-                    gemm_product(op, Wt, N, VEC_C128, Wb, N, nullptr, 0, nc, dc, s, terms);
+                    gemm_product(ptm, Vj, N, VEC_C64, Wb, N, nullptr, 0, nc, dc, s, terms);
                 } else if (pcd) {
                     gemm64_product(pview, Vj, N, Wt, N, nullptr, 0, nc, dc, s);
                     gemm64_product(op, Wt, N, Wb, N, nullptr, 0, nc, dc, s);

@@ -152,6 +152,10 @@ const bie_op *calderon_operator(const bie_calderon *pc);
 // The operator holding M (packed FP64 tiles), for products through the library's
 // kernels; split: also its split-BF16 copy (made on first use).
 bie_op *calderon_view(const bie_calderon *pc, bool split, hipStream_t s);
+// The product T M as one dense operator (split-BF16 copy only), for the block
+// products of the preconditioned inner solves; made by bie_calderon_create when
+// the operator has a split-BF16 copy, else on first use.
+bie_op *calderon_tm(const bie_calderon *pc, hipStream_t s);
 // Y = M X (R complex128 vectors; columns with skip[c * sks] != 0 left untouched).
 void calderon_apply(const bie_calderon *pc, const void *X, int64_t ldx, void *Y, int64_t ldy, int64_t R,
                     const int *skip, int64_t sks, hipStream_t s);
@@ -204,6 +208,8 @@ void prof_begin(int kernel, hipStream_t s, int64_t ncols);
 void prof_end(int kernel, hipStream_t s);
 // gemm.hip
 void split_matrix(bie_op *op, hipStream_t s);
+// split-BF16 operand of a general dense complex128 matrix (column-major, N = op->mesh.N)
+void split_dense(bie_op *op, const void *A, hipStream_t s);
 // vector element types of the block product's right-hand block
 enum { VEC_C128 = 0, VEC_C64 = 1, VEC_F16 = 2 };
 // complex value as two FP16 (storage of the FP16 Krylov basis)

@@ -33,6 +33,7 @@
 struct bie_calderon {
     const bie_op *op = nullptr;   // operator it was built for (mesh and k)
     bie_op *view = nullptr;       // N x N packed FP64 tiles of M, products through the packed kernels
+    bie_op *tm = nullptr;         // T M (dense, split-BF16 copy only) for the preconditioned block products
     void *tmp = nullptr;          // 2 x tmp_R x N complex128 for the preconditioned solve
     int64_t tmp_R = 0;
     bie_calderon_info info{};
@@ -189,6 +190,13 @@ __global__ __launch_bounds__(256) void k_pack_sym(int64_t n, int64_t nT, const d
         }
         tile[e] = v;
     }
+}
+
+// Columns j0 .. j0 + nc - 1 of the n x n identity, dense (n entries per column).
+__global__ __launch_bounds__(256) void k_unit_cols(int64_t n, int64_t j0, int64_t nc, double2 *__restrict__ X)
+{
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n * nc; e += int64_t(gridDim.x) * blockDim.x)
+        X[e] = make_double2(e % n == j0 + e / n ? 1.0 : 0.0, 0.0);
 }
 
 __global__ __launch_bounds__(256) void k_add_cols(int64_t n, const double2 *__restrict__ a, double2 *__restrict__ x)
@@ -447,7 +455,7 @@ bie_calderon *calderon_create(const bie_op *op, hipStream_t s)
     dG.upload(G);
     dGt.upload(Gt);
 
-    auto pc = std::make_unique<bie_calderon>();
+    std::unique_ptr<bie_calderon, void (*)(bie_calderon *)> pc(new bie_calderon(), calderon_destroy);
     pc->op = op;
     pc->info.N = N;
     pc->info.Nb = Nb;
@@ -516,19 +524,53 @@ bie_calderon *calderon_create(const bie_op *op, hipStream_t s)
                        buf[1], -1.0, (double2 *)v->Z64);
     BIE_HIP(hipGetLastError());
     BIE_HIP(hipStreamSynchronize(s));
+    if (op->Abf) calderon_tm(pc.get(), s);   // block products of the preconditioned mixed solves
     pc->info.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return pc.release();
+}
+
+bie_op *calderon_tm(const bie_calderon *pcc, hipStream_t s)
+{
+    bie_calderon *pc = const_cast<bie_calderon *>(pcc);
+    if (pc->tm) return pc->tm;
+    const bie_op *op = pc->op;
+    if (!op->Z64) throw Error(BIE_EINVAL, "Calderon preconditioner: T M needs the FP64 matrix");
+    const int64_t N = pc->info.N, ch = std::min<int64_t>(N, 512);
+    double2 *A = nullptr, *I = nullptr, *Mc = nullptr;
+    struct F3 {
+        double2 **p[3];
+        ~F3()
+        {
+            for (auto q : p)
+                if (*q) (void)hipFree(*q);
+        }
+    } guard{ { &A, &I, &Mc } };
+    BIE_HIP(hipMalloc(&A, size_t(N) * N * sizeof(double2)));
+    BIE_HIP(hipMalloc(&I, size_t(N) * ch * sizeof(double2)));
+    BIE_HIP(hipMalloc(&Mc, size_t(N) * ch * sizeof(double2)));
+    // column chunk of T M: unit vectors, M on the FP64 matrix cores, then T
+    for (int64_t j0 = 0; j0 < N; j0 += ch) {
+        const int64_t nc = std::min(ch, N - j0);
+        hipLaunchKernelGGL(k_unit_cols, dim3(2048), dim3(256), 0, s, N, j0, nc, I);
+        BIE_HIP(hipGetLastError());
+        gemm64_product(pc->view, I, N, Mc, N, nullptr, 0, nc, nullptr, s);
+        gemm64_product(op, Mc, N, A + j0 * N, N, nullptr, 0, nc, nullptr, s);
+    }
+    auto t = std::make_unique<bie_op>();
+    t->device = op->device;
+    t->k = op->k;
+    t->storage = BIE_SPLIT_BF16;
+    t->mesh.N = N;
+    split_dense(t.get(), A, s);   // synchronises
+    pc->tm = t.release();
+    return pc->tm;
 }
 
 void calderon_destroy(bie_calderon *pc)
 {
     if (!pc) return;
-    if (pc->view) {
-        free_workspace(pc->view);
-        packed_free(pc->view->pk);
-        if (pc->view->Z64) (void)hipFree(pc->view->Z64);
-        delete pc->view;
-    }
+    if (pc->view) bie_op_destroy(pc->view);   // every buffer the products made on it too
+    if (pc->tm) bie_op_destroy(pc->tm);
     if (pc->tmp) (void)hipFree(pc->tmp);
     delete pc;
 }

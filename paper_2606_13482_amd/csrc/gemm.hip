@@ -119,6 +119,34 @@ __global__ __launch_bounds__(256) void k_split_matrix(const double2 *__restrict_
     *reinterpret_cast<bf16x8 *>(Al + off) = lo;
 }
 
+// A planes from a dense complex128 N x N matrix, column-major (entry (m, n) at
+// n N + m), zero padding; one wave per tile as above.
+__global__ __launch_bounds__(256) void k_split_dense(const double2 *__restrict__ A, int64_t N, int64_t Mp, int64_t Kp,
+                                                     __bf16 *__restrict__ Ah, __bf16 *__restrict__ Al)
+{
+    const int64_t nst = Kp / GBK, tile = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    if (tile >= (Mp / 32) * nst) return;
+    int r, h;
+    slot_owner(threadIdx.x & 63, r, h);
+    const int64_t m = (tile / nst) * 32 + r, n0 = (tile % nst) * 8 + h * 4;
+    bf16x8 hi, lo;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int64_t n = n0 + e;
+        const double2 z = (m < N && n < N) ? A[n * N + m] : make_double2(0.0, 0.0);
+        __bf16 h0, l0, h1, l1;
+        split_bf16(float(z.x), h0, l0);
+        split_bf16(float(z.y), h1, l1);
+        hi[2 * e] = h0;
+        hi[2 * e + 1] = h1;
+        lo[2 * e] = l0;
+        lo[2 * e + 1] = l1;
+    }
+    const int64_t off = tile * 512 + (threadIdx.x & 63) * 8;
+    *reinterpret_cast<bf16x8 *>(Ah + off) = hi;
+    *reinterpret_cast<bf16x8 *>(Al + off) = lo;
+}
+
 // B planes (tiled, [NCp / 32][Kp / 16] tiles) from R complex vectors
 // (complex128, complex64 or FP16 pairs XT): GEMM column pair r reads the vector at X + v*ldx,
 // v = cols ? cols[r] : r.  One wave per tile.
@@ -564,6 +592,7 @@ void gemm_product(const bie_op *opc, const void *X, int64_t ldx, int vtype, void
                   int64_t ldb, int64_t R, const int *cols, hipStream_t s, int terms)
 {
     if (terms != 2 && terms != 3) throw Error(BIE_EINVAL, "the split-BF16 product has 2 or 3 terms");
+    if (R <= 0) return;
     bie_op *op = const_cast<bie_op *>(opc);
     const int64_t N = op->mesh.N, Kp = op->gemm_Kp, Mp = op->gemm_Mp, NCp = gemm_pad_cols(R);
     const size_t plane = size_t(NCp) * size_t(Kp);
@@ -609,6 +638,23 @@ void gemm_product(const bie_op *opc, const void *X, int64_t ldx, int vtype, void
     BIE_HIP(hipGetLastError());
 }
 
+// Split-BF16 operand of a general (not symmetric) dense complex128 matrix A
+// (column-major, N = op->mesh.N), for gemm_product on op.
+void split_dense(bie_op *op, const void *A, hipStream_t s)
+{
+    const int64_t N = op->mesh.N, Mp = gemm_pad_rows(N), Kp = gemm_pad_k(N);
+    const size_t plane = size_t(Mp) * size_t(Kp);
+    BIE_HIP(hipMalloc(&op->Abf, 2 * plane * sizeof(__bf16)));
+    op->gemm_Mp = Mp;
+    op->gemm_Kp = Kp;
+    __bf16 *Ah = static_cast<__bf16 *>(op->Abf), *Al = Ah + plane;
+    const int64_t tiles = (Mp / 32) * (Kp / GBK);
+    hipLaunchKernelGGL(k_split_dense, dim3(unsigned((tiles + 3) / 4)), dim3(256), 0, s, (const double2 *)A, N, Mp, Kp,
+                       Ah, Al);
+    BIE_HIP(hipGetLastError());
+    BIE_HIP(hipStreamSynchronize(s));
+}
+
 // Dense FP64 copy of the packed matrix for the FP64 block product.
 void dense64_setup(bie_op *op, hipStream_t s)
 {
@@ -628,6 +674,7 @@ void dense64_setup(bie_op *op, hipStream_t s)
 void gemm64_product(const bie_op *opc, const void *X, int64_t ldx, void *Y, int64_t ldy, const void *Bsub,
                     int64_t ldb, int64_t R, const int *cols, hipStream_t s)
 {
+    if (R <= 0) return;
     bie_op *op = const_cast<bie_op *>(opc);
     if (!op->Z64) throw Error(BIE_EINVAL, "the FP64 block product needs the FP64 matrix");
     dense64_setup(op, s);
