@@ -18,11 +18,13 @@
 //     the previous one plus the child's share of the charge;
 //   * mixed Gram matrix G_mn = <n x b_m, f_n> (host, CSR): exact with the
 //     three-edge-midpoint rule on each refined triangle (quadratic integrand);
-//   * T_BC = C Z_b C^T (device): Z_b from the FP64 fill of the refined mesh,
-//     taken in column chunks through the FP64 matrix-core product and the sparse
-//     BC map C on both sides;
+//   * T_BC = C Z_b C^T (device): Z_b from the FP64 fill of the refined mesh; in
+//     column chunks, each BC function's column of Z_b C^T gathered from the rows
+//     of Z_b's dense FP64 copy (Z_b is symmetric) that its coefficients name, then
+//     the sparse map C on the left;
 //   * G^{-1} applied to all N columns at once by CG on the normal equations
-//     (G is well conditioned), twice with a transpose in between.
+//     (G is well conditioned), twice with a transpose in between, on row-major
+//     blocks so that the sparse products read whole rows of 64 columns.
 #include <algorithm>
 #include <chrono>
 #include <memory>
@@ -94,13 +96,43 @@ __global__ __launch_bounds__(CT) void k_csr_cols(int64_t rows, const int64_t *__
     Y[int64_t(blockIdx.y) * ldy + i] = make_double2(re, im);
 }
 
-// Column c of Xc = row j0 + c of the CSR matrix, as a dense vector (Xc zeroed first).
-__global__ void k_rows_to_cols(const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
-                               const double *__restrict__ val, int64_t j0, double2 *__restrict__ Xc, int64_t ld)
+// Y = A X for a real CSR matrix A and n x nc complex matrices stored row-major
+// (entry (i, c) at i nc + c): a wave takes 64 consecutive columns of one row, so
+// each nonzero reads 1 KiB contiguously (grid: column blocks x rows).
+__global__ __launch_bounds__(CT) void k_csr_rm(const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
+                                               const double *__restrict__ val, int64_t nc, const double2 *__restrict__ X,
+                                               double2 *__restrict__ Y)
 {
-    const int64_t c = blockIdx.x;
-    for (int64_t k = ptr[j0 + c] + threadIdx.x; k < ptr[j0 + c + 1]; k += blockDim.x)
-        Xc[c * ld + idx[k]] = make_double2(val[k], 0.0);
+    const int64_t c = int64_t(blockIdx.x) * CT + threadIdx.x, i = blockIdx.y;
+    if (c >= nc) return;
+    double re = 0.0, im = 0.0;
+    for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k) {
+        const double a = val[k];
+        const double2 v = X[int64_t(idx[k]) * nc + c];
+        re += a * v.x;
+        im += a * v.y;
+    }
+    Y[i * nc + c] = make_double2(re, im);
+}
+
+// Column c of Yc = Z_b (row j0 + c of C)^T for the symmetric refined matrix Z_b, from
+// its dense FP64 operand (row e at e Kp, (Re, Im) pairs): the combination of the
+// rows e of the BC map's nonzeros, read contiguously (grid: row blocks x columns).
+__global__ __launch_bounds__(CT) void k_bc_gather(const double *__restrict__ A64, int64_t Kp, int64_t Nb,
+                                                  const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
+                                                  const double *__restrict__ val, int64_t j0, double2 *__restrict__ Yc,
+                                                  int64_t ld)
+{
+    const int64_t i = int64_t(blockIdx.x) * CT + threadIdx.x, c = blockIdx.y;
+    if (i >= Nb) return;
+    double re = 0.0, im = 0.0;
+    for (int64_t k = ptr[j0 + c]; k < ptr[j0 + c + 1]; ++k) {
+        const double a = val[k];
+        const double2 z = *reinterpret_cast<const double2 *>(A64 + int64_t(idx[k]) * Kp + 2 * i);
+        re += a * z.x;
+        im += a * z.y;
+    }
+    Yc[c * ld + i] = make_double2(re, im);
 }
 
 __global__ void k_fill0(int64_t n, double2 *__restrict__ a)
@@ -109,52 +141,60 @@ __global__ void k_fill0(int64_t n, double2 *__restrict__ a)
         a[e] = make_double2(0.0, 0.0);
 }
 
-// out[c] = sum_i |X[c][i]|^2, one block per column.
-__global__ __launch_bounds__(CT) void k_colsq(int64_t n, const double2 *__restrict__ X, double *__restrict__ out)
+// Row-major n x n: partial sums over the rows i = s, s + S, ... of |X(i, c)|^2
+// (grid: column blocks x S slices), then their sum per column.
+__global__ __launch_bounds__(CT) void k_colsq_part(int64_t n, const double2 *__restrict__ X, double *__restrict__ part)
 {
-    const double2 *x = X + int64_t(blockIdx.x) * n;
+    const int64_t c = int64_t(blockIdx.x) * CT + threadIdx.x;
+    if (c >= n) return;
     double s = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += CT) s += x[i].x * x[i].x + x[i].y * x[i].y;
-    __shared__ double red[CT / 64];
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int w = 0; w < CT / 64; ++w) t += red[w];
-        out[blockIdx.x] = t;
+    for (int64_t i = blockIdx.y; i < n; i += gridDim.y) {
+        const double2 v = X[i * n + c];
+        s += v.x * v.x + v.y * v.y;
     }
+    part[int64_t(blockIdx.y) * n + c] = s;
 }
 
-// CGNR step, per column: alpha = zz / ww; X += alpha P; R -= alpha W.
+__global__ __launch_bounds__(CT) void k_colsq_fin(int64_t n, int S, const double *__restrict__ part,
+                                                  double *__restrict__ out)
+{
+    const int64_t c = int64_t(blockIdx.x) * CT + threadIdx.x;
+    if (c >= n) return;
+    double s = 0.0;
+    for (int k = 0; k < S; ++k) s += part[int64_t(k) * n + c];
+    out[c] = s;
+}
+
+// CGNR step, per column c of row-major n x n blocks: alpha = zz / ww; X += alpha P;
+// R -= alpha W (grid-stride over the entries).
 __global__ __launch_bounds__(CT) void k_cg_xr(int64_t n, const double *__restrict__ zz, const double *__restrict__ ww,
                                               const double2 *__restrict__ P, const double2 *__restrict__ W,
                                               double2 *__restrict__ X, double2 *__restrict__ Rr)
 {
-    const int64_t i = int64_t(blockIdx.x) * CT + threadIdx.x;
-    if (i >= n) return;
-    const int64_t c = blockIdx.y, e = c * n + i;
-    const double a = ww[c] > 0.0 ? zz[c] / ww[c] : 0.0;
-    const double2 p = P[e], w = W[e];
-    double2 x = X[e], r = Rr[e];
-    x.x += a * p.x;
-    x.y += a * p.y;
-    r.x -= a * w.x;
-    r.y -= a * w.y;
-    X[e] = x;
-    Rr[e] = r;
+    for (int64_t e = int64_t(blockIdx.x) * CT + threadIdx.x; e < n * n; e += int64_t(gridDim.x) * CT) {
+        const int64_t c = e % n;
+        const double a = ww[c] > 0.0 ? zz[c] / ww[c] : 0.0;
+        const double2 p = P[e], w = W[e];
+        double2 x = X[e], r = Rr[e];
+        x.x += a * p.x;
+        x.y += a * p.y;
+        r.x -= a * w.x;
+        r.y -= a * w.y;
+        X[e] = x;
+        Rr[e] = r;
+    }
 }
 
-// CGNR direction, per column: beta = zn / zz; P = Z + beta P.
+// CGNR direction, per column c of row-major blocks: beta = zn / zz; P = Z + beta P.
 __global__ __launch_bounds__(CT) void k_cg_p(int64_t n, const double *__restrict__ zn, const double *__restrict__ zz,
                                              const double2 *__restrict__ Zv, double2 *__restrict__ P)
 {
-    const int64_t i = int64_t(blockIdx.x) * CT + threadIdx.x;
-    if (i >= n) return;
-    const int64_t c = blockIdx.y, e = c * n + i;
-    const double b = zz[c] > 0.0 ? zn[c] / zz[c] : 0.0;
-    const double2 z = Zv[e], p = P[e];
-    P[e] = make_double2(z.x + b * p.x, z.y + b * p.y);
+    for (int64_t e = int64_t(blockIdx.x) * CT + threadIdx.x; e < n * n; e += int64_t(gridDim.x) * CT) {
+        const int64_t c = e % n;
+        const double b = zz[c] > 0.0 ? zn[c] / zz[c] : 0.0;
+        const double2 z = Zv[e], p = P[e];
+        P[e] = make_double2(z.x + b * p.x, z.y + b * p.y);
+    }
 }
 
 // B = A^T for column-major n x n complex matrices (32 x 32 tiles through LDS).
@@ -380,18 +420,27 @@ void bc_and_gram(const Mesh &M, const Mesh &B, Csr &C, Csr &G, Csr &Gt)
         }
 }
 
-// G X = B for the nc = n columns of B by CG on the normal equations G^T G X = G^T B;
-// R (input B, overwritten by the residual), X, P, W are n x n column-major.
+// G X = B for the n columns of B by CG on the normal equations G^T G X = G^T B.
+// R (input B, overwritten by the residual), X, P, W are n x n row-major (entry
+// (i, c) at i n + c; column c is one right-hand side); sc holds 5 n + NSLICE n doubles.
+constexpr int NSLICE = 64;
+
 void gram_solve(const CsrDev &G, const CsrDev &Gt, int64_t n, double2 *Rr, double2 *X, double2 *P, double2 *W,
                 double *sc, hipStream_t s, int64_t &iters, double &relres)
 {
     const int64_t nn = n * n;
-    double *zz = sc, *zn = sc + n, *ww = sc + 2 * n, *rr = sc + 3 * n, *bb = sc + 4 * n;
-    const dim3 cg(unsigned((n + CT - 1) / CT), unsigned(n));
+    double *zz = sc, *zn = sc + n, *ww = sc + 2 * n, *rr = sc + 3 * n, *bb = sc + 4 * n, *part = sc + 5 * n;
+    const unsigned cb = unsigned((n + CT - 1) / CT);
+    const dim3 mm(cb, unsigned(n));                               // sparse products: column blocks x rows
+    const unsigned ew = unsigned(std::min<int64_t>((nn + CT - 1) / CT, 16384));
+    auto colsq = [&](const double2 *A, double *out) {
+        hipLaunchKernelGGL(k_colsq_part, dim3(cb, NSLICE), dim3(CT), 0, s, n, A, part);
+        hipLaunchKernelGGL(k_colsq_fin, dim3(cb), dim3(CT), 0, s, n, NSLICE, (const double *)part, out);
+    };
     hipLaunchKernelGGL(k_fill0, dim3(2048), dim3(256), 0, s, nn, X);
-    hipLaunchKernelGGL(k_colsq, dim3(unsigned(n)), dim3(CT), 0, s, n, Rr, bb);
-    hipLaunchKernelGGL(k_csr_cols, cg, dim3(CT), 0, s, n, Gt.ptr, Gt.idx, Gt.val, Rr, n, P, n);   // z = G^T r
-    hipLaunchKernelGGL(k_colsq, dim3(unsigned(n)), dim3(CT), 0, s, n, P, zz);
+    colsq(Rr, bb);
+    hipLaunchKernelGGL(k_csr_rm, mm, dim3(CT), 0, s, Gt.ptr, Gt.idx, Gt.val, n, Rr, P);   // z = G^T r
+    colsq(P, zz);
     BIE_HIP(hipGetLastError());
     std::vector<double> hb(n), hr(n);
     BIE_HIP(hipMemcpyAsync(hb.data(), bb, n * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -400,16 +449,16 @@ void gram_solve(const CsrDev &G, const CsrDev &Gt, int64_t n, double2 *Rr, doubl
     const int64_t maxit = 2000;
     relres = 1.0;
     for (iters = 1; iters <= maxit; ++iters) {
-        hipLaunchKernelGGL(k_csr_cols, cg, dim3(CT), 0, s, n, G.ptr, G.idx, G.val, P, n, W, n);      // w = G p
-        hipLaunchKernelGGL(k_colsq, dim3(unsigned(n)), dim3(CT), 0, s, n, W, ww);
-        hipLaunchKernelGGL(k_cg_xr, cg, dim3(CT), 0, s, n, zz, ww, P, W, X, Rr);
-        hipLaunchKernelGGL(k_csr_cols, cg, dim3(CT), 0, s, n, Gt.ptr, Gt.idx, Gt.val, Rr, n, W, n);  // z = G^T r
-        hipLaunchKernelGGL(k_colsq, dim3(unsigned(n)), dim3(CT), 0, s, n, W, zn);
-        hipLaunchKernelGGL(k_cg_p, cg, dim3(CT), 0, s, n, zn, zz, W, P);
+        hipLaunchKernelGGL(k_csr_rm, mm, dim3(CT), 0, s, G.ptr, G.idx, G.val, n, P, W);      // w = G p
+        colsq(W, ww);
+        hipLaunchKernelGGL(k_cg_xr, dim3(ew), dim3(CT), 0, s, n, zz, ww, P, W, X, Rr);
+        hipLaunchKernelGGL(k_csr_rm, mm, dim3(CT), 0, s, Gt.ptr, Gt.idx, Gt.val, n, Rr, W);  // z = G^T r
+        colsq(W, zn);
+        hipLaunchKernelGGL(k_cg_p, dim3(ew), dim3(CT), 0, s, n, zn, zz, W, P);
         BIE_HIP(hipGetLastError());
         std::swap(zz, zn);
         if (iters % 8 == 0 || iters == maxit) {
-            hipLaunchKernelGGL(k_colsq, dim3(unsigned(n)), dim3(CT), 0, s, n, Rr, rr);
+            colsq(Rr, rr);
             BIE_HIP(hipMemcpyAsync(hr.data(), rr, n * sizeof(double), hipMemcpyDeviceToHost, s));
             BIE_HIP(hipStreamSynchronize(s));
             relres = 0.0;
@@ -477,25 +526,25 @@ bie_calderon *calderon_create(const bie_op *op, hipStream_t s)
         }
     } guard{ buf, &scal };
     for (int i = 0; i < 4; ++i) BIE_HIP(hipMalloc(&buf[i], size_t(nn) * sizeof(double2)));
-    BIE_HIP(hipMalloc(&scal, size_t(5 * N) * sizeof(double)));
+    BIE_HIP(hipMalloc(&scal, size_t((5 + NSLICE) * N) * sizeof(double)));
 
-    // T_BC in column chunks: Xc = C^T[:, chunk], Yc = Z_b Xc, T_BC[:, chunk] = C Yc
+    // T_BC in column chunks: Yc = Z_b C^T[:, chunk] gathered from the rows of the
+    // refined matrix's dense FP64 operand (Z_b symmetric: column e = row e), then
+    // T_BC[:, chunk] = C Yc
     {
+        dense64_setup(opb, s);
         const int64_t ch = std::min<int64_t>(N, 512);
-        double2 *Xc = nullptr, *Yc = nullptr;
-        BIE_HIP(hipMalloc(&Xc, size_t(Nb * ch) * sizeof(double2)));
+        double2 *Yc = nullptr;
+        BIE_HIP(hipMalloc(&Yc, size_t(Nb * ch) * sizeof(double2)));
         struct F2 {
             double2 *p;
             ~F2() { if (p) (void)hipFree(p); }
-        } fx{ Xc };
-        BIE_HIP(hipMalloc(&Yc, size_t(Nb * ch) * sizeof(double2)));
-        F2 fy{ Yc };
+        } fy{ Yc };
         for (int64_t j0 = 0; j0 < N; j0 += ch) {
             const int64_t nc = std::min(ch, N - j0);
-            hipLaunchKernelGGL(k_fill0, dim3(2048), dim3(256), 0, s, Nb * nc, Xc);
-            hipLaunchKernelGGL(k_rows_to_cols, dim3(unsigned(nc)), dim3(64), 0, s, dC.ptr, dC.idx, dC.val, j0, Xc, Nb);
+            hipLaunchKernelGGL(k_bc_gather, dim3(unsigned((Nb + CT - 1) / CT), unsigned(nc)), dim3(CT), 0, s,
+                               (const double *)opb->A64, opb->d64_Kp, Nb, dC.ptr, dC.idx, dC.val, j0, Yc, Nb);
             BIE_HIP(hipGetLastError());
-            gemm64_product(opb, Xc, Nb, Yc, Nb, nullptr, 0, nc, nullptr, s);
             hipLaunchKernelGGL(k_csr_cols, dim3(unsigned((N + CT - 1) / CT), unsigned(nc)), dim3(CT), 0, s, N, dC.ptr,
                                dC.idx, dC.val, Yc, Nb, buf[0] + j0 * N, N);
             BIE_HIP(hipGetLastError());
