@@ -147,8 +147,12 @@ typedef struct {
     int64_t rscc_rows;   /* S, default 512 (min(S, N) used) */
     uint64_t rscc_seed;  /* default 1234 */
     int use_x0;          /* 1: X holds the initial guess on entry; 2: the same with
-                            fallback: a guess with ||b - T x0|| >= ||b|| (first FP64
-                            residual) is replaced by zero */
+                            fallback: a guess with ||b - T x0|| >= ||b|| (the solver's
+                            first residual) is replaced by zero.  That residual is FP64,
+                            except in mixed-precision block GMRES, where it only starts
+                            the first correction and is taken with the 3-term split-BF16
+                            product (a right-hand side it puts at or below
+                            max(tol, 1e-3) is taken again in FP64, which decides) */
     int precision;       /* 0: products with the stored matrix (FP64 if stored);
                             1: mixed precision with iterative refinement: outer FP64
                                residual and criterion (SCC), inner GMRES on the
@@ -291,7 +295,8 @@ typedef struct {
  * and stores M (16 N^2 / 2 bytes).  The operator must outlive the
  * preconditioner.  BIE_ENUMERIC if a Gram solve misses 1e-13. */
 int bie_calderon_create(const bie_op *op, void *stream, bie_calderon **out);
-/* Y = M X for R complex128 vectors (device, R x N each, vectors contiguous). */
+/* Y = M X for R complex128 vectors (device, R x N each, vectors contiguous); FP64
+ * throughout (packed product below 8 vectors, the FP64 matrix cores from 8). */
 int bie_calderon_apply(const bie_calderon *pc, const void *X, void *Y, int64_t R, void *stream);
 int bie_calderon_get_info(const bie_calderon *pc, bie_calderon_info *info);
 void bie_calderon_destroy(bie_calderon *pc);

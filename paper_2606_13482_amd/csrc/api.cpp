@@ -274,7 +274,11 @@ int bie_calderon_apply(const bie_calderon *pc, const void *X, void *Y, int64_t R
         if (X == Y) return fail(BIE_EINVAL, "X and Y must not alias");
         bie_calderon_info info;
         bie_calderon_get_info(pc, &info);
-        bie::calderon_apply(pc, X, info.N, Y, info.N, R, nullptr, 1, as_stream(stream));
+        if (R >= 8)   // many vectors: the FP64 matrix cores
+            bie::gemm64_product(bie::calderon_view(pc, false, as_stream(stream)), X, info.N, Y, info.N, nullptr, 0, R,
+                                nullptr, as_stream(stream));
+        else
+            bie::calderon_apply(pc, X, info.N, Y, info.N, R, nullptr, 1, as_stream(stream));
         return BIE_OK;
     });
 }

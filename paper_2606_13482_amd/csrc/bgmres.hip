@@ -869,12 +869,6 @@ __global__ __launch_bounds__(256) void k_bls_back(GDev *__restrict__ gd, const i
     for (int e = t; e < r * q; e += 256) g.Y[int64_t(I * r + e / q) * q + e % q] = cscale(g.scale[e % q], S[e / q][e % q]);
 }
 
-__global__ void k_bzero(int64_t n, double2 *__restrict__ a)
-{
-    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256)
-        a[i] = make_double2(0.0, 0.0);
-}
-
 // Start-of-cycle uploads of every group in one launch: dst[0 .. n) = src, then
 // zeros up to nzero (doubles).
 struct SItem {
@@ -1230,15 +1224,32 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
     std::vector<double> rn;
     std::vector<HGroup> grp;
     while (!live.empty()) {
-        // (1) FP64 residuals and the standard criterion
+        // (1) FP64 residuals and the standard criterion.  In refinement the residual
+        // of an initial guess only starts the first correction: it is taken with the
+        // 3-term split-BF16 product (relative error near 1e-5), and every right-hand
+        // side it puts within that product's reach of convergence (at or below
+        // max(tol, 1e-3)) is taken again in FP64, which decides
+        const bool guess_low = first && o.use_x0 && mixed;
         if (first && !o.use_x0) {
             BIE_HIP(hipMemcpyAsync(Rres, B, size_t(R) * N * sizeof(double2), hipMemcpyDeviceToDevice, s));
         } else {
             const int *dl = ar.put(live);
             ar.flush(s);
-            gemm64_product(op, X, N, Rres, N, B, N, int64_t(live.size()), dl, s);
+            if (guess_low) gemm_product(op, X, N, VEC_C128, Rres, N, B, N, int64_t(live.size()), dl, s, 3);
+            else gemm64_product(op, X, N, Rres, N, B, N, int64_t(live.size()), dl, s);
         }
         norms(Rres, live, rn);
+        if (guess_low) {
+            std::vector<int> conf;
+            for (size_t a = 0; a < live.size(); ++a)
+                if (rn[a] <= std::max(o.tol, 1e-3) * bn[live[a]]) conf.push_back(live[a]);
+            if (!conf.empty()) {
+                const int *dc = ar.put(conf);
+                ar.flush(s);
+                gemm64_product(op, X, N, Rres, N, B, N, int64_t(conf.size()), dc, s);
+                norms(Rres, live, rn);
+            }
+        }
         std::vector<int> keep;
         std::vector<double> krn;
         for (size_t a = 0; a < live.size(); ++a) {
