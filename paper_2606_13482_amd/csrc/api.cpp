@@ -272,8 +272,7 @@ int bie_calderon_apply(const bie_calderon *pc, const void *X, void *Y, int64_t R
         if (R < 0 || R > 4096) return fail(BIE_EINVAL, "R out of range (0..4096)");
         if (R == 0) return BIE_OK;
         if (X == Y) return fail(BIE_EINVAL, "X and Y must not alias");
-        bie_calderon_info info;
-        bie_calderon_get_info(pc, &info);
+        const bie_calderon_info &info = bie::calderon_info(pc);
         if (R >= 8)   // many vectors: the FP64 matrix cores
             bie::gemm64_product(bie::calderon_view(pc, false, as_stream(stream)), X, info.N, Y, info.N, nullptr, 0, R,
                                 nullptr, as_stream(stream));
@@ -281,6 +280,13 @@ int bie_calderon_apply(const bie_calderon *pc, const void *X, void *Y, int64_t R
             bie::calderon_apply(pc, X, info.N, Y, info.N, R, nullptr, 1, as_stream(stream));
         return BIE_OK;
     });
+}
+
+int bie_calderon_get_info(const bie_calderon *pc, bie_calderon_info *info)
+{
+    if (!pc || !info) return fail(BIE_EINVAL, "NULL argument");
+    *info = bie::calderon_info(pc);
+    return BIE_OK;
 }
 
 void bie_calderon_destroy(bie_calderon *pc) { bie::calderon_destroy(pc); }

@@ -149,6 +149,7 @@ namespace bie {
 bie_calderon *calderon_create(const bie_op *op, hipStream_t s);
 void calderon_destroy(bie_calderon *pc);
 const bie_op *calderon_operator(const bie_calderon *pc);
+const bie_calderon_info &calderon_info(const bie_calderon *pc);
 // The operator holding M (packed FP64 tiles), for products through the library's
 // kernels; split: also its split-BF16 copy (made on first use).
 bie_op *calderon_view(const bie_calderon *pc, bool split, hipStream_t s);

@@ -605,7 +605,7 @@ bie_op *calderon_tm(const bie_calderon *pcc, hipStream_t s)
         gemm64_product(pc->view, I, N, Mc, N, nullptr, 0, nc, nullptr, s);
         gemm64_product(op, Mc, N, A + j0 * N, N, nullptr, 0, nc, nullptr, s);
     }
-    auto t = std::make_unique<bie_op>();
+    std::unique_ptr<bie_op, void (*)(bie_op *)> t(new bie_op(), bie_op_destroy);
     t->device = op->device;
     t->k = op->k;
     t->storage = BIE_SPLIT_BF16;
@@ -625,6 +625,7 @@ void calderon_destroy(bie_calderon *pc)
 }
 
 const bie_op *calderon_operator(const bie_calderon *pc) { return pc->op; }
+const bie_calderon_info &calderon_info(const bie_calderon *pc) { return pc->info; }
 
 // The operator holding M (packed FP64 tiles); split: also its split-BF16 copy for
 // the block product (made on first use).
@@ -671,10 +672,3 @@ void zero_into(int64_t n, void *x, hipStream_t s)
 }
 
 }  // namespace bie
-
-extern "C" int bie_calderon_get_info(const bie_calderon *pc, bie_calderon_info *info)
-{
-    if (!pc || !info) return BIE_EINVAL;
-    *info = pc->info;
-    return BIE_OK;
-}
