@@ -588,6 +588,30 @@ def uneven_batch_leg(args, bie, torch):
            "relres_max_converged": float(max(s["relres_true"] for st in sts for s in st if s["converged"])),
            "sequential_s": round(t_seq, 3), "speedup_vs_sequential": round(t_seq / t_batch, 3),
            "packed_fp32_bytes_per_product": int(sum(4 * n * (n + 1) for n in Ns))}
+    if args.calderon:
+        # the same operators with the Calderon preconditioner, one after another:
+        # setup per surface, then GMRES(50) on T M u = b (FP32 T, FP64 M)
+        sync()
+        t0 = time.perf_counter()
+        pcs = [bie.Calderon(op) for op in ops]
+        sync()
+        t_pc = time.perf_counter() - t0
+        stc = []
+        t0 = time.perf_counter()
+        for op, B, pc in zip(ops, Bs, pcs):
+            stc.append(op.solve(B, bie.Solve(restart=50, tol=args.tol, calderon=pc))[1])
+        sync()
+        t_cal = time.perf_counter() - t0
+        convc = np.array([s["converged"] for st in stc for s in st], bool)
+        itsc = np.array([s["iters"] for st in stc for s in st])
+        out["calderon_sequential"] = {
+            "setup_s": round(t_pc, 3), "solve_s": round(t_cal, 3),
+            "solves_per_s": round(int(convc.sum()) / t_cal, 2),
+            "solves_per_s_with_setup": round(int(convc.sum()) / (t_cal + t_pc), 2),
+            "converged": float(convc.mean()), "iters_mean": float(itsc.mean()), "iters_max": int(itsc.max()),
+            "relres_max": float(max(s["relres_true"] for st in stc for s in st))}
+        for pc in pcs:
+            pc.close()
     for op in ops:
         op.close()
     return out

@@ -98,12 +98,14 @@ __global__ __launch_bounds__(CT) void k_csr_cols(int64_t rows, const int64_t *__
 
 // Y = A X for a real CSR matrix A and n x nc complex matrices stored row-major
 // (entry (i, c) at i nc + c): a wave takes 64 consecutive columns of one row, so
-// each nonzero reads 1 KiB contiguously (grid: column blocks x rows).
+// each nonzero reads 1 KiB contiguously.  Grid: rows x column blocks, rows
+// fastest, so that the workgroups in flight share one column slice of X (kept in
+// the last-level cache while they walk the rows).
 __global__ __launch_bounds__(CT) void k_csr_rm(const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
                                                const double *__restrict__ val, int64_t nc, const double2 *__restrict__ X,
                                                double2 *__restrict__ Y)
 {
-    const int64_t c = int64_t(blockIdx.x) * CT + threadIdx.x, i = blockIdx.y;
+    const int64_t c = int64_t(blockIdx.y) * CT + threadIdx.x, i = blockIdx.x;
     if (c >= nc) return;
     double re = 0.0, im = 0.0;
     for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k) {
@@ -431,7 +433,7 @@ void gram_solve(const CsrDev &G, const CsrDev &Gt, int64_t n, double2 *Rr, doubl
     const int64_t nn = n * n;
     double *zz = sc, *zn = sc + n, *ww = sc + 2 * n, *rr = sc + 3 * n, *bb = sc + 4 * n, *part = sc + 5 * n;
     const unsigned cb = unsigned((n + CT - 1) / CT);
-    const dim3 mm(cb, unsigned(n));                               // sparse products: column blocks x rows
+    const dim3 mm(unsigned(n), cb);                               // sparse products: rows x column blocks
     const unsigned ew = unsigned(std::min<int64_t>((nn + CT - 1) / CT, 16384));
     auto colsq = [&](const double2 *A, double *out) {
         hipLaunchKernelGGL(k_colsq_part, dim3(cb, NSLICE), dim3(CT), 0, s, n, A, part);
