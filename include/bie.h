@@ -283,7 +283,9 @@ typedef struct {
     int64_t N, Nb;             /* unknowns of the mesh and of its barycentric refinement (9 F) */
     int64_t nnz_bc;            /* nonzeros of the BC coefficient map (N x Nb) */
     int64_t nnz_gram;          /* nonzeros of G */
-    int64_t cg_iters[2];       /* CG iterations of the two Gram solves (all N columns at once) */
+    int64_t cg_iters[2];       /* iterations of the two Gram solves (all N columns at once):
+                                  Chebyshev steps, plus CG steps on the normal equations
+                                  where Chebyshev fell back */
     double cg_relres[2];       /* their final relative residuals, max over columns (<= 1e-13) */
     double setup_ms;           /* wall time of bie_calderon_create */
 } bie_calderon_info;
@@ -291,7 +293,8 @@ typedef struct {
 /* Builds M for an assembled operator (not star-split) with N <= 12288 (the
  * refined mesh's FP64 matrix and its dense copy take 864 N^2 bytes while it is
  * built, then are freed).  Fills the refined mesh on the device, forms T_BC in
- * column chunks, solves with G by CG on the normal equations for all N columns
+ * column chunks, solves with G (Chebyshev iteration, CG on the normal
+ * equations as fallback) for all N columns
  * and stores M (16 N^2 / 2 bytes).  The operator must outlive the
  * preconditioner.  BIE_ENUMERIC if a Gram solve misses 1e-13. */
 int bie_calderon_create(const bie_op *op, void *stream, bie_calderon **out);

@@ -22,9 +22,10 @@
 //     column chunks, each BC function's column of Z_b C^T gathered from the rows
 //     of Z_b's dense FP64 copy (Z_b is symmetric) that its coefficients name, then
 //     the sparse map C on the left;
-//   * G^{-1} applied to all N columns at once by CG on the normal equations
-//     (G is well conditioned), twice with a transpose in between, on row-major
-//     blocks so that the sparse products read whole rows of 64 columns.
+//   * G^{-1} applied to all N columns at once by Chebyshev iteration on the
+//     interval that holds G's spectrum (CG on the normal equations if it fails),
+//     twice with a transpose in between, on row-major blocks so that the sparse
+//     products read whole rows of 64 columns.
 #include <algorithm>
 #include <chrono>
 #include <memory>
@@ -184,6 +185,33 @@ __global__ __launch_bounds__(CT) void k_cg_xr(int64_t n, const double *__restric
         r.y -= a * w.y;
         X[e] = x;
         Rr[e] = r;
+    }
+}
+
+// Chebyshev step on row-major blocks (coefficients shared by every column):
+// X += D; R -= W (W = G D); D = c1 D + c2 R.
+__global__ __launch_bounds__(CT) void k_cheb(int64_t nn, double c1, double c2, const double2 *__restrict__ W,
+                                             double2 *__restrict__ D, double2 *__restrict__ X, double2 *__restrict__ Rr)
+{
+    for (int64_t e = int64_t(blockIdx.x) * CT + threadIdx.x; e < nn; e += int64_t(gridDim.x) * CT) {
+        const double2 d = D[e], w = W[e];
+        double2 x = X[e], r = Rr[e];
+        x.x += d.x;
+        x.y += d.y;
+        r.x -= w.x;
+        r.y -= w.y;
+        X[e] = x;
+        Rr[e] = r;
+        D[e] = make_double2(c1 * d.x + c2 * r.x, c1 * d.y + c2 * r.y);
+    }
+}
+
+__global__ __launch_bounds__(CT) void k_scale_copy(int64_t nn, double a, const double2 *__restrict__ Xs,
+                                                   double2 *__restrict__ Y)
+{
+    for (int64_t e = int64_t(blockIdx.x) * CT + threadIdx.x; e < nn; e += int64_t(gridDim.x) * CT) {
+        const double2 v = Xs[e];
+        Y[e] = make_double2(a * v.x, a * v.y);
     }
 }
 
@@ -473,6 +501,74 @@ void gram_solve(const CsrDev &G, const CsrDev &Gt, int64_t n, double2 *Rr, doubl
     iters = std::min(iters, maxit);
 }
 
+// G X = B by Chebyshev iteration on the interval [GA, GB] of the real axis (Saad,
+// Iterative Methods for Sparse Linear Systems, Sec. 12.3).  The spectrum of the
+// mixed Gram matrix lies in [1/3, 1) up to imaginary parts near 1e-3 on every mesh
+// tried (spheres, ellipsoids up to 1:2:3, rounded cubes, area ratios up to 6):
+// one sparse product per step and no reductions, about 0.3 per step.  The residual
+// is checked every 4 steps; if it has not fallen by half since the last check (a
+// spectrum outside the interval), false is returned and R, X are undefined.
+constexpr double GA = 0.30, GB = 1.05;
+
+bool gram_solve_cheb(const CsrDev &G, int64_t n, double2 *Rr, double2 *X, double2 *D, double2 *W, double *sc,
+                     hipStream_t s, int64_t &iters, double &relres)
+{
+    const int64_t nn = n * n;
+    double *rr = sc + 3 * n, *bb = sc + 4 * n, *part = sc + 5 * n;
+    const unsigned cb = unsigned((n + CT - 1) / CT);
+    const dim3 mm(unsigned(n), cb);
+    const unsigned ew = unsigned(std::min<int64_t>((nn + CT - 1) / CT, 16384));
+    auto colsq = [&](const double2 *A, double *out) {
+        hipLaunchKernelGGL(k_colsq_part, dim3(cb, NSLICE), dim3(CT), 0, s, n, A, part);
+        hipLaunchKernelGGL(k_colsq_fin, dim3(cb), dim3(CT), 0, s, n, NSLICE, (const double *)part, out);
+    };
+    const double theta = 0.5 * (GB + GA), delta = 0.5 * (GB - GA), sigma = theta / delta;
+    hipLaunchKernelGGL(k_fill0, dim3(2048), dim3(256), 0, s, nn, X);
+    colsq(Rr, bb);
+    hipLaunchKernelGGL(k_scale_copy, dim3(ew), dim3(CT), 0, s, nn, 1.0 / theta, (const double2 *)Rr, D);
+    BIE_HIP(hipGetLastError());
+    std::vector<double> hb(n), hr(n);
+    BIE_HIP(hipMemcpyAsync(hb.data(), bb, n * sizeof(double), hipMemcpyDeviceToHost, s));
+    BIE_HIP(hipStreamSynchronize(s));
+    const double target = 1e-13;
+    double rho = 1.0 / sigma, last = 1.0;
+    relres = 1.0;
+    for (iters = 1; iters <= 200; ++iters) {
+        const double rhon = 1.0 / (2.0 * sigma - rho);
+        hipLaunchKernelGGL(k_csr_rm, mm, dim3(CT), 0, s, G.ptr, G.idx, G.val, n, D, W);   // W = G D
+        hipLaunchKernelGGL(k_cheb, dim3(ew), dim3(CT), 0, s, nn, rhon * rho, 2.0 * rhon / delta, W, D, X, Rr);
+        BIE_HIP(hipGetLastError());
+        rho = rhon;
+        if (iters % 4 == 0) {
+            colsq(Rr, rr);
+            BIE_HIP(hipMemcpyAsync(hr.data(), rr, n * sizeof(double), hipMemcpyDeviceToHost, s));
+            BIE_HIP(hipStreamSynchronize(s));
+            relres = 0.0;
+            for (int64_t c = 0; c < n; ++c)
+                if (hb[c] > 0.0) relres = std::max(relres, std::sqrt(hr[c] / hb[c]));
+            if (relres <= target) return true;
+            if (!(relres < 0.5 * last)) return false;
+            last = relres;
+        }
+    }
+    return false;
+}
+
+// G X = B: Chebyshev, or CG on the normal equations from the saved B if it fails.
+void gram_solve_any(const CsrDev &G, const CsrDev &Gt, int64_t n, double2 *Rr, double2 *X, double2 *P, double2 *W,
+                    double2 *Bs, double *sc, hipStream_t s, int64_t &iters, double &relres)
+{
+    const int64_t nn = n * n;
+    const unsigned ew = unsigned(std::min<int64_t>((nn + CT - 1) / CT, 16384));
+    hipLaunchKernelGGL(k_scale_copy, dim3(ew), dim3(CT), 0, s, nn, 1.0, (const double2 *)Rr, Bs);
+    BIE_HIP(hipGetLastError());
+    if (gram_solve_cheb(G, n, Rr, X, P, W, sc, s, iters, relres)) return;
+    int64_t it2 = 0;
+    hipLaunchKernelGGL(k_scale_copy, dim3(ew), dim3(CT), 0, s, nn, 1.0, (const double2 *)Bs, Rr);
+    gram_solve(G, Gt, n, Rr, X, P, W, sc, s, it2, relres);
+    iters += it2;
+}
+
 }  // namespace
 
 // Largest N for which the preconditioner is built (the refined mesh has 6 N
@@ -515,19 +611,19 @@ bie_calderon *calderon_create(const bie_op *op, hipStream_t s)
 
     // dense work: T_BC / residual, X, P, W (n x n each) and column scalars
     const int64_t nn = N * N;
-    double2 *buf[4] = {};
+    double2 *buf[5] = {};
     double *scal = nullptr;
     struct Free {
         double2 **b;
         double **sc;
         ~Free()
         {
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < 5; ++i)
                 if (b[i]) (void)hipFree(b[i]);
             if (*sc) (void)hipFree(*sc);
         }
     } guard{ buf, &scal };
-    for (int i = 0; i < 4; ++i) BIE_HIP(hipMalloc(&buf[i], size_t(nn) * sizeof(double2)));
+    for (int i = 0; i < 5; ++i) BIE_HIP(hipMalloc(&buf[i], size_t(nn) * sizeof(double2)));
     BIE_HIP(hipMalloc(&scal, size_t((5 + NSLICE) * N) * sizeof(double)));
 
     // T_BC in column chunks: Yc = Z_b C^T[:, chunk] gathered from the rows of the
@@ -556,11 +652,13 @@ bie_calderon *calderon_create(const bie_op *op, hipStream_t s)
     hold.reset();   // the refined operator is no longer needed
 
     // A1 = G^{-1} T_BC (into buf1); M' = G^{-1} A1^T (into buf1 again, A1^T in buf0)
-    gram_solve(dG, dGt, N, buf[0], buf[1], buf[2], buf[3], scal, s, pc->info.cg_iters[0], pc->info.cg_relres[0]);
+    gram_solve_any(dG, dGt, N, buf[0], buf[1], buf[2], buf[3], buf[4], scal, s, pc->info.cg_iters[0],
+                   pc->info.cg_relres[0]);
     hipLaunchKernelGGL(k_transpose, dim3(unsigned((N + 31) / 32), unsigned((N + 31) / 32)), dim3(32, 8), 0, s, N,
                        buf[1], buf[0]);
     BIE_HIP(hipGetLastError());
-    gram_solve(dG, dGt, N, buf[0], buf[1], buf[2], buf[3], scal, s, pc->info.cg_iters[1], pc->info.cg_relres[1]);
+    gram_solve_any(dG, dGt, N, buf[0], buf[1], buf[2], buf[3], buf[4], scal, s, pc->info.cg_iters[1],
+                   pc->info.cg_relres[1]);
 
     // M = -(M' + M'^T)/2 in packed tiles
     bie_op *v = new bie_op();
