@@ -191,3 +191,20 @@ def test_refined_matrix_reproduces_rwg_matrix():
     Z = cfill.fill(rwg, 2.0)
     Zb = cfill.fill(rwgb, 2.0)
     assert np.linalg.norm(R @ Zb @ R.T - Z) <= 0.025 * np.linalg.norm(Z)
+
+
+@pytest.mark.parametrize("mesh", ["ico1", "ico2", "rcube4", "ell123"])
+def test_gram_spectrum_interval(mesh):
+    """The eigenvalues of the mixed Gram matrix lie in [1/3, 1) up to imaginary parts
+    below 1e-3 on spheres, rounded cubes and a 1:2:3 ellipsoid: the interval
+    [0.30, 1.05] on which the library runs its Chebyshev Gram solves (with a
+    monitored fallback) holds them with margin."""
+    from paper_2606_13482_amd.inputs import cube_sphere
+    V, T = {"ico1": lambda: icosphere(1), "ico2": lambda: icosphere(2),
+            "rcube4": lambda: cube_sphere(4, "rounded_cube"),
+            "ell123": lambda: cube_sphere(4, "ellipsoid", axes=(1.0, 2.0, 3.0))}[mesh]()
+    P = _built(2) if mesh == "ico2" else calderon.build(V, T, 2.0)
+    ev = np.linalg.eigvals(P["G"])
+    assert ev.real.min() >= 1 / 3 - 1e-6 and ev.real.max() < 1.0
+    assert np.abs(ev.imag).max() < 1e-3
+    assert 0.30 < ev.real.min() and ev.real.max() < 1.05
