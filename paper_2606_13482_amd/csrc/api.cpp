@@ -37,6 +37,7 @@ void destroy_op(bie_op *op)
 {
     if (!op) return;
     bie::free_workspace(op);
+    bie::free_block_cache(op);
     bie::packed_free(op->pk);
     bie::packed_free(op->pkv);
     void *ptrs[] = { op->Z64, op->Z32, op->V64, op->V32, op->star_buf, op->Abf, op->Bbf, op->gemm_part, op->A64,

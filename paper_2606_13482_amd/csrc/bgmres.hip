@@ -885,23 +885,6 @@ __global__ __launch_bounds__(256) void k_bscatter(const SItem *__restrict__ item
 
 using cd = std::complex<double>;
 
-// Device allocations released at scope exit.
-struct Bufs {
-    std::vector<void *> all;
-    template <typename T>
-    T *get(size_t n)
-    {
-        void *p = nullptr;
-        BIE_HIP(hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T)));
-        all.push_back(p);
-        return static_cast<T *>(p);
-    }
-    ~Bufs()
-    {
-        for (void *p : all) (void)hipFree(p);
-    }
-};
-
 // Small per-launch tables: staged in pinned host memory and copied to a device
 // mirror on the stream, all tables staged since the last copy in one transfer
 // (flush).  Space is reused only after a stream synchronisation, when every
@@ -1082,7 +1065,6 @@ int rank_revealing(const std::vector<cd> &G, int q, const std::vector<double> &s
 struct Aux {
     hipStream_t s2 = nullptr, s3 = nullptr;
     hipEvent_t ev[7] = {};
-    std::vector<void *> pinned;
     Aux()
     {
         BIE_HIP(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
@@ -1097,7 +1079,67 @@ struct Aux {
             if (e) (void)hipEventDestroy(e);
         if (s2) (void)hipStreamDestroy(s2);
         if (s3) (void)hipStreamDestroy(s3);
-        for (void *p : pinned) (void)hipHostFree(p);
+    }
+};
+
+// Device and pinned buffers, table arenas and side streams of the block solver,
+// kept by the operator between calls: a solve takes its buffers in a fixed order
+// and reuses the one in the same place when it is large enough (else it is
+// replaced).  A solve returns with its streams synchronised, so the next may reuse
+// everything; after a solve that ended in an error the device is synchronised
+// first.  Solves on one operator from several threads at once are not supported.
+struct BlockCache {
+    std::vector<std::pair<void *, size_t>> dev, pin;
+    size_t nd = 0, np = 0;
+    std::unique_ptr<Arena> ar[3];
+    std::unique_ptr<Aux> aux;
+    bool dirty = false;
+    void begin()
+    {
+        if (dirty) (void)hipDeviceSynchronize();
+        dirty = true;
+        nd = np = 0;
+        for (auto &a : ar) {
+            if (!a) a = std::make_unique<Arena>(size_t(8) << 20);
+            a->reset();
+        }
+        if (!aux) aux = std::make_unique<Aux>();
+    }
+    template <typename T>
+    T *get(size_t n)
+    {
+        const size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+        if (nd == dev.size()) dev.emplace_back(nullptr, 0);
+        auto &slot = dev[nd++];
+        if (slot.second < bytes) {
+            if (slot.first) (void)hipFree(slot.first);
+            slot = { nullptr, 0 };
+            BIE_HIP(hipMalloc(&slot.first, bytes));
+            slot.second = bytes;
+        }
+        return static_cast<T *>(slot.first);
+    }
+    template <typename T>
+    T *pinned(size_t n)
+    {
+        const size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+        if (np == pin.size()) pin.emplace_back(nullptr, 0);
+        auto &slot = pin[np++];
+        if (slot.second < bytes) {
+            if (slot.first) (void)hipHostFree(slot.first);
+            slot = { nullptr, 0 };
+            BIE_HIP(hipHostMalloc(&slot.first, bytes));
+            slot.second = bytes;
+        }
+        return static_cast<T *>(slot.first);
+    }
+    ~BlockCache()
+    {
+        aux.reset();
+        for (auto &d : dev)
+            if (d.first) (void)hipFree(d.first);
+        for (auto &h : pin)
+            if (h.first) (void)hipHostFree(h.first);
     }
 };
 
@@ -1123,7 +1165,9 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
     bie_op *pview = pcd ? calderon_view(pcd, mixed, s) : nullptr;
     bie_op *ptm = pcd && mixed ? calderon_tm(pcd, s) : nullptr;   // T M as one split-BF16 operand
 
-    Bufs db;
+    if (!op->bcache) op->bcache = new BlockCache();
+    BlockCache &db = *static_cast<BlockCache *>(op->bcache);
+    db.begin();
     double2 *Rres = db.get<double2>(size_t(R) * N);
     double2 *Wb = db.get<double2>(size_t(R) * N);
     double2 *Wt = pcd && !mixed ? db.get<double2>(size_t(R) * N) : nullptr;   // M V_j (FP64 form)
@@ -1162,10 +1206,9 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
         d.scale = gscale + g * BMAX;
         d.flag = gflag + 4 * g;
     }
-    Arena ar(size_t(8) << 20);
-    std::unique_ptr<Arena> arena[2] = { std::make_unique<Arena>(size_t(8) << 20),
-                                        std::make_unique<Arena>(size_t(8) << 20) };
-    Aux aux;
+    Arena &ar = *db.ar[0];
+    Arena *arena[2] = { db.ar[1].get(), db.ar[2].get() };
+    Aux &aux = *db.aux;
     hipStream_t s2 = aux.s2, s3 = aux.s3;
     hipEvent_t ev_prod = aux.ev[0], ev_ls[2] = { aux.ev[1], aux.ev[2] }, ev_arena[2] = { aux.ev[3], aux.ev[4] };
     hipEvent_t ev_s3[2] = { aux.ev[5], aux.ev[6] };
@@ -1176,16 +1219,12 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
     double *hest[2];
     int *hfl[2];
     for (int i = 0; i < 2; ++i) {
-        BIE_HIP(hipHostMalloc(reinterpret_cast<void **>(&hest[i]), size_t(Gmax) * BMAX * sizeof(double)));
-        aux.pinned.push_back(hest[i]);
-        BIE_HIP(hipHostMalloc(reinterpret_cast<void **>(&hfl[i]), size_t(Gmax) * 4 * sizeof(int)));
-        aux.pinned.push_back(hfl[i]);
+        hest[i] = db.pinned<double>(size_t(Gmax) * BMAX);
+        hfl[i] = db.pinned<int>(size_t(Gmax) * 4);
     }
     int *gsteps = db.get<int>(size_t(Gmax));
     double2 *gG = db.get<double2>(size_t(Gmax) * p2);   // Gram matrices of the start blocks, gathered
-    double2 *hGpin = nullptr;
-    BIE_HIP(hipHostMalloc(reinterpret_cast<void **>(&hGpin), size_t(Gmax) * p2 * sizeof(double2)));
-    aux.pinned.push_back(hGpin);
+    double2 *hGpin = db.pinned<double2>(size_t(Gmax) * p2);
     std::vector<int> hsteps(Gmax, 0);
     auto sync = [&]() {
         BIE_HIP(hipStreamSynchronize(s));
@@ -1543,6 +1582,9 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
         }
     }
     sync();
+    BIE_HIP(hipStreamSynchronize(s2));
+    BIE_HIP(hipStreamSynchronize(s3));
+    db.dirty = false;
     int status = BIE_OK;
     for (int64_t i = 0; i < R; ++i)
         if (!hs[i].converged) status = BIE_NOT_CONVERGED;
@@ -1550,6 +1592,12 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
 }
 
 }  // namespace
+
+void free_block_cache(bie_op *op)
+{
+    delete static_cast<BlockCache *>(op->bcache);
+    op->bcache = nullptr;
+}
 
 // Block GMRES for R right-hand sides, in consecutive chunks of `slots` (all R
 // when 0), each chunk solved to the end before the next.

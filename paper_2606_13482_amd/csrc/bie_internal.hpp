@@ -141,9 +141,13 @@ struct bie_op {
     void *d64_part = nullptr;     // its split-K partial tiles, FP64
     size_t d64_part_elems = 0;
     bie::Workspace *ws = nullptr;
+    void *bcache = nullptr;       // block GMRES buffers, arenas and side streams (bgmres.hip), kept between solves
 };
 
 namespace bie {
+
+// bgmres.hip: release the block solver's cached buffers of an operator.
+void free_block_cache(bie_op *op);
 
 // calderon.hip: the multiplicative Calderon preconditioner.
 bie_calderon *calderon_create(const bie_op *op, hipStream_t s);
