@@ -224,7 +224,10 @@ typedef struct {
  * complex64 basis and split-BF16 products, one cycle per refinement step to
  * inner_tol relative to the FP64 residual.  SCC only; slots > 0 solves the
  * right-hand sides in consecutive chunks of that many.  Counts: one iteration
- * and one product per block step for every column of the block.
+ * and one product per block step for every column of the block.  The operator
+ * keeps the block solver's device and pinned buffers and its two side streams
+ * between calls (grown when a call needs more, freed by bie_op_destroy); calls
+ * on one operator must not overlap.
  * GMRES(m): Arnoldi with classical Gram-Schmidt and selective
  * reorthogonalisation (a second pass when the first removes more than half of
  * ||w||^2), FP64 Givens rotations; a cycle ends when the estimate <= tol or j = m, then the
@@ -290,13 +293,14 @@ typedef struct {
     double setup_ms;           /* wall time of bie_calderon_create */
 } bie_calderon_info;
 
-/* Builds M for an assembled operator (not star-split) with N <= 12288 (the
- * refined mesh's FP64 matrix and its dense copy take 864 N^2 bytes while it is
- * built, then are freed).  Fills the refined mesh on the device, forms T_BC in
- * column chunks, solves with G (Chebyshev iteration, CG on the normal
- * equations as fallback) for all N columns
- * and stores M (16 N^2 / 2 bytes).  The operator must outlive the
- * preconditioner.  BIE_ENUMERIC if a Gram solve misses 1e-13. */
+/* Builds M for an assembled operator (not star-split) with N <= 12288.  Fills
+ * the refined mesh on the device (its FP64 matrix and dense copy take 864 N^2
+ * bytes while M is built, then are freed), forms T_BC in column chunks, solves
+ * with G for all N columns (Chebyshev iteration, CG on the normal equations if
+ * it fails; the environment variable BIE_CALDERON_GRAM=cgnr selects CG on the
+ * normal equations from the start, for comparison and tests) and stores M
+ * (16 N^2 / 2 bytes).  The operator must outlive the preconditioner.
+ * BIE_ENUMERIC if a Gram solve misses 1e-13. */
 int bie_calderon_create(const bie_op *op, void *stream, bie_calderon **out);
 /* Y = M X for R complex128 vectors (device, R x N each, vectors contiguous); FP64
  * throughout (packed product below 8 vectors, the FP64 matrix cores from 8). */

@@ -27,6 +27,7 @@
 //     twice with a transpose in between, on row-major blocks so that the sparse
 //     products read whole rows of 64 columns.
 #include <algorithm>
+#include <cstdlib>
 #include <chrono>
 #include <memory>
 #include <unordered_map>
@@ -560,6 +561,11 @@ void gram_solve_any(const CsrDev &G, const CsrDev &Gt, int64_t n, double2 *Rr, d
 {
     const int64_t nn = n * n;
     const unsigned ew = unsigned(std::min<int64_t>((nn + CT - 1) / CT, 16384));
+    const char *env = getenv("BIE_CALDERON_GRAM");
+    if (env && std::string(env) == "cgnr") {
+        gram_solve(G, Gt, n, Rr, X, P, W, sc, s, iters, relres);
+        return;
+    }
     hipLaunchKernelGGL(k_scale_copy, dim3(ew), dim3(CT), 0, s, nn, 1.0, (const double2 *)Rr, Bs);
     BIE_HIP(hipGetLastError());
     if (gram_solve_cheb(G, n, Rr, X, P, W, sc, s, iters, relres)) return;

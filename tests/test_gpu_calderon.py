@@ -204,3 +204,29 @@ def test_calderon_block_guess_and_fallback(bie):
     assert np.max(np.abs(np.array([s["relres_true"] for s in s2]) - res) / res) <= 1e-6
     pc.close()
     op.close()
+
+
+def test_calderon_gram_solvers_agree(bie, monkeypatch):
+    """The Gram solves by Chebyshev iteration (default) and by CG on the normal
+    equations (BIE_CALDERON_GRAM=cgnr, also the fallback) give the same M, both at
+    the oracle's within 1e-10 of its largest entry (ellipsoid cube-sphere, 648
+    unknowns)."""
+    V, T, P, Zo = _oracle("ell6", 3.0)
+    op = bie.Operator(V, T, 3.0)
+    eye = torch.eye(op.N, dtype=torch.complex128, device="cuda")
+    pc1 = bie.Calderon(op)
+    M1 = pc1.apply(eye).cpu().numpy().T
+    i1 = pc1.info()
+    pc1.close()
+    monkeypatch.setenv("BIE_CALDERON_GRAM", "cgnr")
+    pc2 = bie.Calderon(op)
+    M2 = pc2.apply(eye).cpu().numpy().T
+    i2 = pc2.info()
+    pc2.close()
+    op.close()
+    scale = np.max(np.abs(P["M"]))
+    d12, d1, d2 = (np.max(np.abs(a - b)) / scale for a, b in ((M1, M2), (M1, P["M"]), (M2, P["M"])))
+    _say(f"  Chebyshev {i1['cg_iters']} steps vs CGNR {i2['cg_iters']}: M difference {d12:.1e}; vs oracle {d1:.1e} / {d2:.1e}")
+    assert i2["cg_iters"][0] > i1["cg_iters"][0]
+    assert max(i1["cg_relres"] + i2["cg_relres"]) <= 1e-13
+    assert d12 <= 1e-10 and d1 <= 1e-10 and d2 <= 1e-10
