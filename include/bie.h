@@ -294,8 +294,9 @@ typedef struct {
 } bie_calderon_info;
 
 /* Builds M for an assembled operator (not star-split) with N <= 12288.  Fills
- * the refined mesh on the device (its FP64 matrix and dense copy take 864 N^2
- * bytes while M is built, then are freed), forms T_BC in column chunks, solves
+ * the refined mesh on the device (at most 1440 N^2 bytes while M is built: the
+ * fill's pair scratch beside the refined FP64 matrix, then that matrix and its
+ * dense copy; all freed at the end), forms T_BC in column chunks, solves
  * with G for all N columns (Chebyshev iteration, CG on the normal equations if
  * it fails; the environment variable BIE_CALDERON_GRAM=cgnr selects CG on the
  * normal equations from the start, for comparison and tests) and stores M

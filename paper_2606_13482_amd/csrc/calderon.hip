@@ -577,8 +577,10 @@ void gram_solve_any(const CsrDev &G, const CsrDev &Gt, int64_t n, double2 *Rr, d
 
 }  // namespace
 
-// Largest N for which the preconditioner is built (the refined mesh has 6 N
-// unknowns; its FP64 matrix and dense copy take 24 (6 N)^2 bytes of HBM).
+// Largest N for which the preconditioner is built.  The refined mesh has 6 N
+// unknowns and 4 N triangles: its fill's pair scratch (144 B per triangle pair,
+// 1152 N^2 bytes) beside its packed FP64 matrix (288 N^2) is the peak, 217 GB at
+// this N; then the packed matrix and its dense copy (864 N^2).
 constexpr int64_t CALDERON_MAX_N = 12288;
 
 bie_calderon *calderon_create(const bie_op *op, hipStream_t s)
@@ -615,7 +617,8 @@ bie_calderon *calderon_create(const bie_op *op, hipStream_t s)
     pc->info.nnz_bc = int64_t(C.idx.size());
     pc->info.nnz_gram = int64_t(G.idx.size());
 
-    // dense work: T_BC / residual, X, P, W (n x n each) and column scalars
+    // dense work, n x n each: T_BC / residual, X, P (Chebyshev direction), W, and the
+    // saved right-hand side for the fallback; column scalars and partial sums
     const int64_t nn = N * N;
     double2 *buf[5] = {};
     double *scal = nullptr;
