@@ -230,3 +230,35 @@ def test_calderon_gram_solvers_agree(bie, monkeypatch):
     assert i2["cg_iters"][0] > i1["cg_iters"][0]
     assert max(i1["cg_relres"] + i2["cg_relres"]) <= 1e-13
     assert d12 <= 1e-10 and d1 <= 1e-10 and d2 <= 1e-10
+
+
+def test_calderon_fp32_storage_and_chunks(bie):
+    """The preconditioner with FP32 matrix storage in column GMRES (the uneven
+    batch's form: FP32 T, FP64 M and vectors), and block GMRES in consecutive
+    chunks (slots) on one operator through its kept buffers, then a larger call:
+    every residual within tol against the oracle matrix."""
+    V, T, P, Zo = _oracle("ico2", 2.0)
+    d, e = planewave_set(random_directions(10, 66), "theta")
+    op32 = bie.Operator(V, T, 2.0, storage="c64")
+    pc32 = bie.Calderon(op32)
+    B = op32.rhs(d, e)
+    X, st = op32.solve(B, bie.Solve(restart=30, tol=1e-6, calderon=pc32))
+    Bn = B.cpu().numpy()
+    r32 = np.linalg.norm(Bn - X.cpu().numpy() @ Zo.T, axis=1) / np.linalg.norm(Bn, axis=1)
+    pc32.close()
+    op32.close()
+    op = bie.Operator(V, T, 2.0)
+    pc = bie.Calderon(op)
+    Xc, sc = op.solve(B, bie.Solve(method="bgmres", block=3, restart=10, tol=1e-8, slots=4, calderon=pc))
+    rc = np.linalg.norm(Bn - Xc.cpu().numpy() @ Zo.T, axis=1) / np.linalg.norm(Bn, axis=1)
+    B2 = torch.cat([B, B * (1 + 1j)])
+    X2, s2 = op.solve(B2, bie.Solve(method="bgmres", block=5, restart=10, tol=1e-8, calderon=pc))
+    B2n = B2.cpu().numpy()
+    r2 = np.linalg.norm(B2n - X2.cpu().numpy() @ Zo.T, axis=1) / np.linalg.norm(B2n, axis=1)
+    _say(f"  FP32 storage: iterations {max(s['iters'] for s in st)}, residual {r32.max():.2e}; chunks of 4: "
+         f"{rc.max():.2e}; then 20 right-hand sides: {r2.max():.2e}")
+    assert all(s["converged"] for s in st + sc + s2)
+    assert r32.max() <= 1e-6 * (1 + 1e-6) and max(s["iters"] for s in st) <= 20
+    assert rc.max() <= 1e-8 * (1 + 1e-6) and r2.max() <= 1e-8 * (1 + 1e-6)
+    pc.close()
+    op.close()
