@@ -334,8 +334,9 @@ int bie_rscc_rows(int64_t N, int64_t S, uint64_t seed, int64_t *out);
  * Glorot-uniform initial weights (SplitMix64(seed), in layer order, row-major
  * (out, in)) and per-epoch Fisher-Yates shuffles (SplitMix64(seed + 1 + epoch)).
  * Parameter layout (float): W1 (hidden x 4), b1, W2 (hidden x hidden), b2,
- * W3 (2K x hidden), b3.  Plain GMRES from zero stays the fallback and the
- * judge of the prediction (see bie_ws_predict). */
+ * W3 (2K x hidden), b3.  Plain GMRES from zero stays the fallback: the
+ * solver's residual of the prediction decides whether it is kept (see
+ * bie_ws_predict). */
 typedef struct bie_ws bie_ws;
 
 typedef struct {
