@@ -40,7 +40,8 @@ void destroy_op(bie_op *op)
     bie::free_block_cache(op);
     bie::packed_free(op->pk);
     bie::packed_free(op->pkv);
-    void *ptrs[] = { op->Z64, op->Z32, op->V64, op->V32, op->star_buf, op->Abf, op->Bbf, op->gemm_part, op->A64,
+    void *ptrs[] = { op->pooled ? nullptr : op->Z64, op->Z32, op->V64, op->V32, op->star_buf, op->Abf, op->Bbf,
+                     op->gemm_part, op->pooled ? nullptr : op->A64,
                      op->d64_part, op->tri.cent, op->tri.loc, op->tri.vfree, op->tri.verts, op->tri.area, op->tri.sgn,
                      op->tri.slot_m, op->tri.edges };
     for (void *p : ptrs)
@@ -84,7 +85,12 @@ int bie_op_create(const double *verts, int64_t nv, const int32_t *tris, int64_t 
             const size_t vtile_elems = op->star ? size_t(op->pkv.ntiles) * bie::TB * bie::TB : 0;
             const bool want64 = o.storage == BIE_C128 || o.storage == BIE_SPLIT_BF16 || o.keep_fp64;
             const bool want32 = o.storage == BIE_C64;
-            if (want64) BIE_HIP(hipMalloc(&op->Z64, tile_elems * 16));
+            if (want64 && bie::setup_pool_active()) {   // the refined mesh of a preconditioner setup
+                op->pooled = 1;
+                op->Z64 = bie::setup_pool_get(1, tile_elems * 16);
+            } else if (want64) {
+                BIE_HIP(hipMalloc(&op->Z64, tile_elems * 16));
+            }
             if (want32) BIE_HIP(hipMalloc(&op->Z32, tile_elems * 8));
             if (want64 && op->star) BIE_HIP(hipMalloc(&op->V64, vtile_elems * 16));
             if (want32 && op->star) BIE_HIP(hipMalloc(&op->V32, vtile_elems * 8));

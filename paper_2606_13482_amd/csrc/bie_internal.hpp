@@ -142,12 +142,19 @@ struct bie_op {
     size_t d64_part_elems = 0;
     bie::Workspace *ws = nullptr;
     void *bcache = nullptr;       // block GMRES buffers, arenas and side streams (bgmres.hip), kept between solves
+    int pooled = 0;               // Z64 and A64 belong to the preconditioner setup pool (not freed with the op)
 };
 
 namespace bie {
 
 // bgmres.hip: release the block solver's cached buffers of an operator.
 void free_block_cache(bie_op *op);
+
+// calderon.hip: the large transient buffers of preconditioner setups (slot 0 the
+// fill's pair scratch, 1 the refined packed matrix, 2 its dense copy), kept
+// between setups while any preconditioner lives.  Active only inside a setup.
+bool setup_pool_active();
+void *setup_pool_get(int slot, size_t bytes);
 
 // calderon.hip: the multiplicative Calderon preconditioner.
 bie_calderon *calderon_create(const bie_op *op, hipStream_t s);

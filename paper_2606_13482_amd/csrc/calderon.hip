@@ -29,7 +29,9 @@
 #include <algorithm>
 #include <cstdlib>
 #include <chrono>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <unordered_map>
 
 #include "bie_internal.hpp"
@@ -41,12 +43,36 @@ struct bie_calderon {
     void *tmp = nullptr;          // 2 x tmp_R x N complex128 for the preconditioned solve
     int64_t tmp_R = 0;
     bie_calderon_info info{};
+    bool counted = false;         // holds a reference on the setup pool
 };
 
 namespace bie {
 namespace {
 
 constexpr int CT = 256;
+
+// Setup pool: freeing tens of GB costs about 30 ms per GB on this runtime once
+// many buffers have come and gone, so the three largest transient buffers of a
+// setup are kept (per device) for the next one while any preconditioner lives.
+// Setups are serialised: they share these buffers.
+struct SetupPool {
+    void *buf[3] = {};
+    size_t cap[3] = {};
+};
+std::mutex g_setup_mu;        // one setup at a time
+std::mutex g_pool_mu;
+std::map<int, SetupPool> g_pool;
+int g_live = 0;               // live preconditioners
+thread_local bool g_pool_on = false;
+
+void setup_pool_release()
+{
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    for (auto &kv : g_pool)
+        for (int i = 0; i < 3; ++i)
+            if (kv.second.buf[i]) (void)hipFree(kv.second.buf[i]);
+    g_pool.clear();
+}
 
 struct Csr {
     std::vector<int64_t> ptr;
@@ -583,8 +609,40 @@ void gram_solve_any(const CsrDev &G, const CsrDev &Gt, int64_t n, double2 *Rr, d
 // this N; then the packed matrix and its dense copy (864 N^2).
 constexpr int64_t CALDERON_MAX_N = 12288;
 
+bool setup_pool_active() { return g_pool_on; }
+
+void *setup_pool_get(int slot, size_t bytes)
+{
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    int dev = 0;
+    BIE_HIP(hipGetDevice(&dev));
+    SetupPool &p = g_pool[dev];
+    if (p.cap[slot] < bytes) {
+        if (p.buf[slot]) (void)hipFree(p.buf[slot]);
+        p.buf[slot] = nullptr;
+        p.cap[slot] = 0;
+        BIE_HIP(hipMalloc(&p.buf[slot], bytes));
+        p.cap[slot] = bytes;
+    }
+    return p.buf[slot];
+}
+
 bie_calderon *calderon_create(const bie_op *op, hipStream_t s)
 {
+    std::lock_guard<std::mutex> serial(g_setup_mu);
+    struct PoolScope {
+        PoolScope() { g_pool_on = true; }
+        ~PoolScope()
+        {
+            g_pool_on = false;
+            bool none;
+            {
+                std::lock_guard<std::mutex> lk(g_pool_mu);
+                none = g_live == 0;
+            }
+            if (none) setup_pool_release();   // a failed first setup keeps nothing
+        }
+    } scope;
     const auto t0 = std::chrono::steady_clock::now();
     const Mesh &M = op->mesh;
     const int64_t N = M.N;
@@ -684,6 +742,11 @@ bie_calderon *calderon_create(const bie_op *op, hipStream_t s)
     BIE_HIP(hipStreamSynchronize(s));
     if (op->Abf) calderon_tm(pc.get(), s);   // block products of the preconditioned mixed solves
     pc->info.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        ++g_live;
+        pc->counted = true;
+    }
     return pc.release();
 }
 
@@ -730,7 +793,13 @@ void calderon_destroy(bie_calderon *pc)
     if (pc->view) bie_op_destroy(pc->view);   // every buffer the products made on it too
     if (pc->tm) bie_op_destroy(pc->tm);
     if (pc->tmp) (void)hipFree(pc->tmp);
+    bool last = false;
+    if (pc->counted) {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        last = --g_live == 0;
+    }
     delete pc;
+    if (last) setup_pool_release();
 }
 
 const bie_op *calderon_operator(const bie_calderon *pc) { return pc->op; }

@@ -654,8 +654,11 @@ void fill_matrix(bie_op *op, bool fp64_regular, bool want64, bool want32, hipStr
     void *LB = nullptr, *VS = nullptr;
     int32_t *pairs = nullptr;
     const int64_t npairs = int64_t(M.near.size() / 2);
+    const bool pooled = setup_pool_active();   // inside a preconditioner setup: kept scratch
     try {
-        BIE_HIP(hipMalloc(&LB, size_t(ntiles) * 9 * 256 * 2 * elem));
+        const size_t lb_bytes = size_t(ntiles) * 9 * 256 * 2 * elem;
+        if (pooled) LB = setup_pool_get(0, lb_bytes);
+        else BIE_HIP(hipMalloc(&LB, lb_bytes));
         if (op->star) BIE_HIP(hipMalloc(&VS, size_t(ntiles) * 256 * 2 * elem));
         if (npairs) {
             BIE_HIP(hipMalloc(&pairs, M.near.size() * sizeof(int32_t)));
@@ -671,12 +674,12 @@ void fill_matrix(bie_op *op, bool fp64_regular, bool want64, bool want32, hipStr
         BIE_HIP(hipGetLastError());
         BIE_HIP(hipStreamSynchronize(s));
     } catch (...) {
-        if (LB) hipFree(LB);
+        if (LB && !pooled) hipFree(LB);
         if (VS) hipFree(VS);
         if (pairs) hipFree(pairs);
         throw;
     }
-    hipFree(LB);
+    if (!pooled) hipFree(LB);
     if (VS) hipFree(VS);
     if (pairs) hipFree(pairs);
 }

@@ -660,7 +660,8 @@ void dense64_setup(bie_op *op, hipStream_t s)
 {
     if (op->A64) return;
     const int64_t N = op->mesh.N, Mp = (N + DBM - 1) / DBM * DBM, Kp = (2 * N + DBK - 1) / DBK * DBK;
-    BIE_HIP(hipMalloc(&op->A64, size_t(Mp) * size_t(Kp) * sizeof(double)));
+    if (op->pooled) op->A64 = setup_pool_get(2, size_t(Mp) * size_t(Kp) * sizeof(double));
+    else BIE_HIP(hipMalloc(&op->A64, size_t(Mp) * size_t(Kp) * sizeof(double)));
     op->d64_Mp = Mp;
     op->d64_Kp = Kp;
     const dim3 grid(unsigned(std::min<int64_t>((Kp / 2 + 255) / 256, 64)), unsigned(Mp));
