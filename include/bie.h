@@ -300,8 +300,10 @@ typedef struct {
  * with G for all N columns (Chebyshev iteration, CG on the normal equations if
  * it fails; the environment variable BIE_CALDERON_GRAM=cgnr selects CG on the
  * normal equations from the start, for comparison and tests) and stores M
- * (16 N^2 / 2 bytes).  The operator must outlive the preconditioner.
- * BIE_ENUMERIC if a Gram solve misses 1e-13. */
+ * (16 N^2 / 2 bytes).  The operator must outlive the preconditioner.  The
+ * setup's three largest buffers are kept per device while any preconditioner
+ * lives and reused by the next setup (freed when the last one is destroyed);
+ * setups run one at a time.  BIE_ENUMERIC if a Gram solve misses 1e-13. */
 int bie_calderon_create(const bie_op *op, void *stream, bie_calderon **out);
 /* Y = M X for R complex128 vectors (device, R x N each, vectors contiguous); FP64
  * throughout (packed product below 8 vectors, the FP64 matrix cores from 8). */
