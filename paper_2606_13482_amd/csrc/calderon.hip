@@ -799,7 +799,15 @@ void calderon_destroy(bie_calderon *pc)
         last = --g_live == 0;
     }
     delete pc;
-    if (last) setup_pool_release();
+    if (last) {   // wait for a setup in progress on another thread, which may be using the pool
+        std::lock_guard<std::mutex> serial(g_setup_mu);
+        bool none;
+        {
+            std::lock_guard<std::mutex> lk(g_pool_mu);
+            none = g_live == 0;
+        }
+        if (none) setup_pool_release();
+    }
 }
 
 const bie_op *calderon_operator(const bie_calderon *pc) { return pc->op; }
