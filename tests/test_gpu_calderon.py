@@ -262,3 +262,32 @@ def test_calderon_fp32_storage_and_chunks(bie):
     assert rc.max() <= 1e-8 * (1 + 1e-6) and r2.max() <= 1e-8 * (1 + 1e-6)
     pc.close()
     op.close()
+
+
+def test_calderon_setup_pool_reuse(bie):
+    """Setups share a pool of their largest buffers while any preconditioner lives:
+    a setup after a larger one reuses it, one after a smaller one grows it, and a
+    rebuilt preconditioner is bitwise the first (deterministic kernels); after the
+    last one is closed the pool is released and a new setup still agrees."""
+    Va, Ta = icosphere(2)
+    Vb, Tb = icosphere(1)
+    opa = bie.Operator(Va, Ta, 2.0)
+    opb = bie.Operator(Vb, Tb, 2.0)
+    ea = torch.eye(opa.N, dtype=torch.complex128, device="cuda")
+    eb = torch.eye(opb.N, dtype=torch.complex128, device="cuda")
+    pb = bie.Calderon(opb)                     # small first, then a larger one grows the pool
+    pa = bie.Calderon(opa)
+    Ma = pa.apply(ea).cpu().numpy()
+    Mb = pb.apply(eb).cpu().numpy()
+    pa.close()
+    pa2 = bie.Calderon(opa)                    # reuses the pool kept alive by pb
+    Ma2 = pa2.apply(ea).cpu().numpy()
+    pa2.close()
+    pb.close()                                 # last one: pool released
+    pb2 = bie.Calderon(opb)
+    Mb2 = pb2.apply(eb).cpu().numpy()
+    pb2.close()
+    _say(f"  pool: rebuilt M equal {np.array_equal(Ma, Ma2)} / {np.array_equal(Mb, Mb2)}")
+    assert np.array_equal(Ma, Ma2) and np.array_equal(Mb, Mb2)
+    opa.close()
+    opb.close()
