@@ -51,13 +51,21 @@ def _b_at(P, m, t, x):
     return val
 
 
-def test_bc_charge_and_fluxes():
+@pytest.mark.parametrize("mesh", ["ico1", "rcube3", "ell123"])
+def test_bc_charge_and_fluxes(mesh):
     """Divergence theorem on every child of the support, by evaluating b_m on the
     child's edges: the net outflow is +A_t/A(hi) in the dual cell of the higher
     vertex, -A_t/A(lo) in the lower one's; the flux through each half of the dual
     edge is 1/2, through the halves of edge m 0, and b_m . nu is continuous
-    across every child edge."""
-    P = _built(1)
+    across every child edge.  Also on cells of unequal areas (rounded cube,
+    1:2:3 ellipsoid), where the charge must still be uniform."""
+    from paper_2606_13482_amd.inputs import cube_sphere
+    if mesh == "ico1":
+        P = _built(1)
+    else:
+        V, T = (cube_sphere(3, "rounded_cube") if mesh == "rcube3"
+                else cube_sphere(3, "ellipsoid", axes=(1.0, 2.0, 3.0)))
+        P = calderon.build(V, T, 2.0)
     rwg, rwgb, Vb, Tb, corner = P["rwg"], P["rwgb"], P["Vb"], P["Tb"], P["corner"]
     nv, E = rwg["V"].shape[0], rwg["N"]
     Ac = np.zeros(nv)
