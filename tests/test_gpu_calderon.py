@@ -1,7 +1,8 @@
 """Calderon preconditioner on the GPU against the oracle: the matrix M entry by
 entry (icosphere with 480 unknowns: ragged last tile; an ellipsoid cube-sphere
-with 648 unknowns and unequal cell areas: two column chunks, the last ragged),
-and right-preconditioned GMRES against the oracle's."""
+with 648 unknowns and unequal cell areas: two column chunks, the last ragged; a
+rounded cube with 1152 unknowns: three chunks), and right-preconditioned GMRES
+against the oracle's."""
 import numpy as np
 import pytest
 import torch
@@ -17,7 +18,8 @@ _CACHE = {}
 
 
 def _mesh(name):
-    return {"ico2": lambda: icosphere(2), "ell6": lambda: cube_sphere(6, "ellipsoid", axes=(1.0, 1.3, 1.7))}[name]()
+    return {"ico2": lambda: icosphere(2), "ell6": lambda: cube_sphere(6, "ellipsoid", axes=(1.0, 1.3, 1.7)),
+            "rcube8": lambda: cube_sphere(8, "rounded_cube")}[name]()
 
 
 def _oracle(name, k):
@@ -32,7 +34,7 @@ def _say(*a):
     print(*a, flush=True)
 
 
-@pytest.mark.parametrize("name,k", [("ico2", 2.0), ("ell6", 3.0)])
+@pytest.mark.parametrize("name,k", [("ico2", 2.0), ("ell6", 3.0), ("rcube8", 4.0)])
 def test_calderon_matrix_matches_oracle(bie, name, k):
     """M applied to the identity equals the oracle's -G^{-1} T_BC G^{-T} within
     1e-10 of its largest entry; the Gram solves reached 1e-13; sizes and the
