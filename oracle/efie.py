@@ -83,8 +83,13 @@ def _regular_blocks(G: Geometry, pidx: np.ndarray, qidx: np.ndarray, k: float):
     return J, J0
 
 
-def singular_block(G: Geometry, p: int, q: int, k: float):
-    """Singularity-subtracted J (3,3) and J0 for one flagged pair (mean of both orderings)."""
+def singular_block(G: Geometry, p: int, q: int, k: float, orderings: bool = False):
+    """Singularity-subtracted J (3,3) and J0 for one flagged pair (mean of both orderings).
+
+    orderings: also return the static parts of the two orderings separately,
+    ((Jsp, J0sp), (Jsq, J0sq)) with p outer / q inner and q outer / p inner; they
+    are equal in exact integration, so their difference measures the outer rule's
+    error on the pair."""
     rwg = G.rwg
     w = G.w
     Xp, Xq = G.X[p], G.X[q]
@@ -107,6 +112,8 @@ def singular_block(G: Geometry, p: int, q: int, k: float):
     Ip = K1p[None, :, :] + (Xq[None, :, :] - vp[:, None, :]) * K0p[None, :, None]   # (a,j,3)
     Jsq = np.einsum("j,bjc,ajc->ab", w, Dq, Ip) / (FOUR_PI * Ap)
     J0sq = np.dot(w, K0p) / (FOUR_PI * Ap)
+    if orderings:
+        return J + 0.5 * (Jsp + Jsq), J0 + 0.5 * (J0sp + J0sq), ((Jsp, J0sp), (Jsq, J0sq))
     return J + 0.5 * (Jsp + Jsq), J0 + 0.5 * (J0sp + J0sq)
 
 

@@ -124,11 +124,29 @@ def shuffle(S: int, seed: int, epoch: int) -> np.ndarray:
     return np.array(perm)
 
 
-def train(p0, K, H, F, T, epochs, batch, lr_max, lr_min, seed):
-    """Adam on mini-batches in the shuffled order; returns the final parameters."""
+def cosine_lr(step: int, total: int, lr_max: float, lr_min: float) -> float:
+    """Learning rate of step 1..total: lr_max at the first step, lr_min at the last,
+    following half a cosine period in between."""
+    return lr_min + 0.5 * (lr_max - lr_min) * (1.0 + math.cos(math.pi * (step - 1) / max(1, total - 1)))
+
+
+def adam_update(p, m, v, g, step: int, lr: float, b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8):
+    """One Adam step (Kingma & Ba 2015, Algorithm 1): moment estimates, their bias
+    correction by 1 - beta^step, and the update.  Returns (p, m, v)."""
+    m = b1 * m + (1.0 - b1) * g
+    v = b2 * v + (1.0 - b2) * g * g
+    mh = m / (1.0 - b1 ** step)
+    vh = v / (1.0 - b2 ** step)
+    return p - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+def train(p0, K, H, F, T, epochs, batch, lr_max, lr_min, seed, D=None, E=None):
+    """Adam on mini-batches in the shuffled order; returns the final parameters.
+    With D and E (directions and polarisations) the linear-in-polarisation model
+    is trained (loss_grad_pol; F is then unused), else the base model on F."""
     p = p0.astype(np.float64).copy()
     m = np.zeros_like(p); v = np.zeros_like(p)
-    S = F.shape[0]
+    S = (F if D is None else D).shape[0]
     nb = (S + batch - 1) // batch
     total = epochs * nb
     step = 0
@@ -136,11 +154,10 @@ def train(p0, K, H, F, T, epochs, batch, lr_max, lr_min, seed):
         perm = shuffle(S, seed, ep)
         for bi in range(nb):
             idx = perm[bi * batch:(bi + 1) * batch]
-            _, g = loss_grad(p, K, H, F[idx], T[idx])
+            if D is None:
+                _, g = loss_grad(p, K, H, F[idx], T[idx])
+            else:
+                _, g = loss_grad_pol(p, K, H, D[idx], E[idx], T[idx])
             step += 1
-            lr = lr_min + 0.5 * (lr_max - lr_min) * (1.0 + math.cos(math.pi * (step - 1) / max(1, total - 1)))
-            m = 0.9 * m + 0.1 * g
-            v = 0.999 * v + 0.001 * g * g
-            mh = m / (1.0 - 0.9 ** step); vh = v / (1.0 - 0.999 ** step)
-            p = p - lr * mh / (np.sqrt(vh) + 1e-8)
+            p, m, v = adam_update(p, m, v, g, step, cosine_lr(step, total, lr_max, lr_min))
     return p

@@ -77,19 +77,75 @@ def test_regular_quadrature_convergence(ico):
     assert e7 < 2e-3
 
 
+def _touching_rwg_pairs(rwg):
+    """(m, n) with m != n whose supports share at least one vertex."""
+    T = rwg["T"]
+    verts = [set(T[rwg["tp"][m]]) | set(T[rwg["tm"][m]]) for m in range(rwg["N"])]
+    return np.array([(m, n) for m in range(rwg["N"]) for n in range(rwg["N"])
+                     if m != n and verts[m] & verts[n]])
+
+
 def test_singular_entries_converge_with_order(ico):
-    """Self and touching entries (singularity subtraction) converge as the outer
-    rule order rises; Radon-7 is within a few percent of the converged values."""
+    """Self and adjacent entries (singularity subtraction) converge as the outer
+    rule order rises (4 -> 8 -> 12 collapsed Gauss, against 16); Radon-7 is within
+    a few percent of the converged values."""
     rwg = ico(1)
     k = 2.0
-    Zs = {n: cfill.fill(rwg, k, rule=collapsed_gauss(n)) for n in (4, 8, 16)}
+    Zs = {n: cfill.fill(rwg, k, rule=collapsed_gauss(n)) for n in (4, 8, 12, 16)}
     Z7 = cfill.fill(rwg, k)
     diag = np.arange(rwg["N"])
-    d48 = np.max(np.abs(Zs[4][diag, diag] - Zs[16][diag, diag]) / np.abs(Zs[16][diag, diag]))
-    d816 = np.max(np.abs(Zs[8][diag, diag] - Zs[16][diag, diag]) / np.abs(Zs[16][diag, diag]))
-    assert d816 < d48 and d816 < 5e-3
-    e7 = np.max(np.abs(Z7[diag, diag] - Zs[16][diag, diag]) / np.abs(Zs[16][diag, diag]))
-    assert e7 < 0.05
+    adj = _touching_rwg_pairs(rwg)
+    assert len(adj) > 10 * rwg["N"]
+    for rows, cols in ((diag, diag), (adj[:, 0], adj[:, 1])):
+        ref = Zs[16][rows, cols]
+        scale = np.max(np.abs(ref))
+        err = {n: np.max(np.abs(Zs[n][rows, cols] - ref)) / scale for n in (4, 8, 12)}
+        assert err[12] < err[8] < err[4], err
+        assert err[8] < 5e-3 and err[12] < 1e-3, err
+        e7 = np.max(np.abs(Z7[rows, cols] - ref)) / scale
+        assert e7 < 0.05, e7
+
+
+def test_touching_pairs_converge_and_orderings_agree(ico):
+    """Triangle pairs that touch (p = q, a shared edge, a shared vertex): the
+    singularity-subtracted blocks converge with the outer order (each doubling of
+    the collapsed-Gauss order gains at least a factor 4), and the two orderings of
+    the static part, p outer / q inner and q outer / p inner (equal in exact
+    integration), approach each other: the un-averaged asymmetry shrinks with the
+    outer order."""
+    rwg = ico(1)
+    k = 2.0
+    T = rwg["T"]
+    sets = [set(t) for t in T]
+    classes = {"self": [], "edge": [], "vertex": []}
+    for p in range(rwg["F"]):
+        for q in range(rwg["F"]):
+            n = len(sets[p] & sets[q])
+            key = "self" if p == q else {2: "edge", 1: "vertex"}.get(n)
+            if key:
+                classes[key].append((p, q))
+    rules = {n: efie.Geometry(rwg, collapsed_gauss(n)) for n in (4, 8, 16, 32)}
+    G7 = efie.Geometry(rwg)
+    for key, pairs in classes.items():
+        assert pairs, key
+        for p, q in pairs[::max(1, len(pairs) // 8)]:
+            vals = {n: efie.singular_block(G, p, q, k, orderings=True) for n, G in rules.items()}
+            J32, J032 = vals[32][0], vals[32][1]
+
+            def err(J, J0):
+                return max(np.max(np.abs(J - J32)) / np.max(np.abs(J32)), abs(J0 - J032) / abs(J032))
+
+            def asym(v):
+                (a, a0), (b, b0) = v[2]
+                return max(np.max(np.abs(a - b)), abs(a0 - b0)) / max(np.max(np.abs(v[0])), abs(v[1]))
+
+            e = {n: err(vals[n][0], vals[n][1]) for n in (4, 8, 16)}
+            s = {n: asym(vals[n]) for n in (4, 8, 16, 32)}
+            assert e[8] < 0.25 * e[4] and e[16] < 0.25 * e[8], (key, p, q, e)
+            assert e[16] < 1e-4, (key, p, q, e)
+            assert s[32] < s[16] < s[8] < s[4], (key, p, q, s)
+            J7, J07, _ = efie.singular_block(G7, p, q, k, orderings=True)
+            assert err(J7, J07) < 0.02, (key, p, q, err(J7, J07))
 
 
 def test_fill_rows_matches_full(ico):

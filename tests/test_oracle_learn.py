@@ -92,3 +92,72 @@ def test_linear_polarisation_gradient_and_combination():
     # the output layer has 6K rows; the first layers are those of the base model
     assert learn.layout(K, H, 1)[1] == 6 * K
     assert np.array_equal(learn.glorot(K, H, 9, 1)[:learn.layout(K, H)[0][4]], learn.glorot(K, H, 9)[:learn.layout(K, H)[0][4]])
+
+
+def test_cosine_schedule_values():
+    """lr_max at the first step, lr_min at the last, their mean half-way (the
+    cosine's zero), and lr_max for a single step."""
+    assert learn.cosine_lr(1, 5, 1e-3, 1e-5) == 1e-3
+    assert abs(learn.cosine_lr(5, 5, 1e-3, 1e-5) - 1e-5) < 1e-20
+    assert abs(learn.cosine_lr(3, 5, 1e-3, 1e-5) - 5.05e-4) < 1e-18
+    assert learn.cosine_lr(1, 1, 2e-3, 1e-5) == 2e-3
+    lrs = [learn.cosine_lr(s, 50, 1e-3, 1e-5) for s in range(1, 51)]
+    assert all(a > b for a, b in zip(lrs, lrs[1:]))
+
+
+def test_adam_steps_worked_by_hand():
+    """Two Adam steps with bias correction, values worked out by hand.
+
+    Step 1: m = 0.1 g, v = 0.001 g^2, and the corrections 1 - 0.9 and 1 - 0.999
+    give m^ = g, v^ = g^2, so every coordinate moves by lr against the sign of its
+    gradient, whatever the gradient's size (up to eps / |g|).
+    Step 2 with the gradient reversed: m = 0.09 g - 0.1 g = -0.01 g and
+    m^ = -0.01 g / 0.19 = -g / 19; v = 0.000999 g^2 + 0.001 g^2 and v^ = g^2: the
+    move is lr / 19 back.  With the same gradient again: m^ = 0.19 g / 0.19 = g, a
+    full lr move.  A dropped bias correction (step 1 would move sqrt(1000)/10 lr)
+    or swapped betas (step 2 would move 5e-4 lr back) fails these."""
+    p0 = np.array([1.0, -2.0, 0.5, 3.0])
+    g = np.array([2.0, -3.0, 1e-3, -40.0])
+    m = np.zeros(4); v = np.zeros(4)
+    lr1, lr2 = 0.01, 0.02
+    p1, m1, v1 = learn.adam_update(p0, m, v, g, 1, lr1)
+    assert np.all(np.abs(p1 - (p0 - lr1 * np.sign(g))) <= lr1 * 1e-8 / np.abs(g) * 1.001)
+    p2, _, _ = learn.adam_update(p1, m1, v1, -g, 2, lr2)
+    assert np.all(np.abs(p2 - (p1 + lr2 * np.sign(g) / 19.0)) <= lr2 * 1e-8 / np.abs(g))
+    p2s, _, _ = learn.adam_update(p1, m1, v1, g, 2, lr2)
+    assert np.all(np.abs(p2s - (p1 - lr2 * np.sign(g))) <= lr2 * 1e-8 / np.abs(g) * 1.001)
+
+
+def test_train_first_steps():
+    """train() wiring: its first step is the sign step of Adam (above) at lr_max on
+    the first mini-batch of epoch 0's shuffle; over 2 steps with lr_min = 0 the second
+    step does not move (the schedule ends at lr_min), so training for 2 steps equals
+    training for 1; and the linear-in-polarisation branch does the same with its own
+    gradient."""
+    K, H = 2, 5
+    rng = np.random.default_rng(11)
+    p0 = learn.glorot(K, H, 3)
+    S, batch = 6, 3
+    F = rng.standard_normal((S, 4))
+    T = rng.standard_normal((S, 2 * K))
+    perm = learn.shuffle(S, 9, 0)
+    _, g = learn.loss_grad(p0, K, H, F[perm[:batch]], T[perm[:batch]])
+    lr = 1e-3
+    p1 = learn.train(p0, K, H, F, T, epochs=1, batch=S, lr_max=lr, lr_min=lr, seed=9)
+    _, gall = learn.loss_grad(p0, K, H, F, T)      # one mini-batch of all S: order does not matter
+    nz = np.abs(gall) > 1e-6
+    assert np.all(np.abs(p1 - (p0 - lr * np.sign(gall)))[nz] <= lr * 1e-8 / np.abs(gall[nz]) * 1.01)
+    # two mini-batches in one epoch, lr_min = 0: the first step (on perm[:3]) is the
+    # only one that moves
+    p2 = learn.train(p0, K, H, F, T, epochs=1, batch=batch, lr_max=lr, lr_min=0.0, seed=9)
+    nzg = np.abs(g) > 1e-6
+    assert np.all(np.abs(p2 - (p0 - lr * np.sign(g)))[nzg] <= lr * 1e-8 / np.abs(g[nzg]) * 1.01)
+    assert np.array_equal(learn.train(p0, K, H, F, T, epochs=2, batch=S, lr_max=lr, lr_min=0.0, seed=9), p1)
+    # linear-in-polarisation model
+    D = rng.standard_normal((S, 3)); D /= np.linalg.norm(D, axis=1, keepdims=True)
+    E = np.cross(D, [0.0, 0.0, 1.0]); E /= np.linalg.norm(E, axis=1, keepdims=True)
+    pp = learn.glorot(K, H, 4, pol_model=1)
+    _, gp = learn.loss_grad_pol(pp, K, H, D[perm], E[perm], T[perm])
+    pp1 = learn.train(pp, K, H, None, T, epochs=1, batch=S, lr_max=lr, lr_min=lr, seed=9, D=D, E=E)
+    nzp = np.abs(gp) > 1e-6
+    assert np.all(np.abs(pp1 - (pp - lr * np.sign(gp)))[nzp] <= lr * 1e-8 / np.abs(gp[nzp]) * 1.01)

@@ -112,3 +112,32 @@ def test_collapsed_gauss_degree(n):
             c = 2 * n - 2 - a - b
             got = np.sum(w * bary[:, 0] ** a * bary[:, 1] ** b * bary[:, 2] ** c)
             assert abs(got - _exact_monomial(a, b, c)) < 1e-14
+
+
+@pytest.mark.parametrize("level,fam", [(1, None), (2, None), (None, "ellipsoid")])
+def test_flagged_pairs_brute_force(level, fam):
+    """The flagged-pair matrix equals a pair-by-pair loop over the reading's
+    definition: the triangles share a vertex (p = q included), or the squared
+    centroid distance is strictly below (2 max(longest edge of p, of q))^2.  The
+    loop computes areas, centroids and longest edges from the vertices itself."""
+    from oracle.mesh import flagged_pairs
+    if fam is None:
+        V, T = icosphere(level)
+    else:
+        V, T = cube_sphere(4, fam, axes=(1.0, 1.7, 2.4))
+    rwg = rwg_table(V, T)
+    got = flagged_pairs(rwg, 2.0)
+    F = T.shape[0]
+    cent = [sum(V[v] for v in t) / 3.0 for t in T]
+    longest = [max(math.dist(V[t[a]], V[t[(a + 1) % 3]]) for a in range(3)) for t in T]
+    n_touch = n_near = 0
+    for p in range(F):
+        for q in range(F):
+            touch = len(set(T[p]) & set(T[q])) > 0
+            d2 = sum((cent[p][c] - cent[q][c]) ** 2 for c in range(3))
+            thr = 2.0 * max(longest[p], longest[q])
+            want = touch or d2 < thr * thr
+            n_touch += touch
+            n_near += want and not touch
+            assert got[p, q] == want, (p, q)
+    assert n_touch > 10 * F and n_near > 0
