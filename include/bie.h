@@ -366,6 +366,21 @@ typedef struct {
 int bie_ws_train(const bie_op *op, const double *feats, const double *pols, const void *X, int64_t S,
                  const bie_ws_opts *opts, void *stream, bie_ws **out);
 
+/* Train the network of ws on S given inputs and targets with the kernels and
+ * schedule of bie_ws_train (mini-batches of `batch` in the order of a
+ * Fisher-Yates shuffle from SplitMix64(seed + 1 + epoch), Adam (0.9, 0.999,
+ * 1e-8) with bias correction, learning rate cosine-decayed from lr_max at the
+ * first step to lr_min at the last), starting from its current parameters and
+ * fresh Adam moments.  For callers with their own coefficients, and for
+ * comparing the training with an independent implementation.
+ *   feats    host S x 4 (pol_model 1 ignores the fourth input)
+ *   pols     host S x 3 real unit polarisations (pol_model 1; else may be NULL)
+ *   targets  host S x 2K float (Re then Im of the scaled coefficients)
+ *   final_loss  host out (may be NULL): mean squared error over the last epoch
+ * The inputs are copied to the device during the call; it synchronises `stream`. */
+int bie_ws_fit(bie_ws *ws, const double *feats, const double *pols, const float *targets, int64_t S, int epochs,
+               int batch, double lr_max, double lr_min, uint64_t seed, double *final_loss, void *stream);
+
 /* Predict x0 = U c for R inputs (feats host R x 4; pols host R x 3 for
  * pol_model 1, else may be NULL) into X0 (device R x N complex128).  If B (device R x N) is given, a prediction is kept only where
  * ||b - T x0|| < ||b|| and set to 0 otherwise; used[r] (host, may be NULL)

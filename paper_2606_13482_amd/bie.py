@@ -88,6 +88,8 @@ SYMBOLS = [
     ("bie_batch_tuned", ctypes.c_int, [_P, _I64, _P]),
     ("bie_rscc_rows", ctypes.c_int, [_I64, _I64, ctypes.c_uint64, _P]),
     ("bie_ws_train", ctypes.c_int, [_P, _P, _P, _P, _I64, _P, _P, ctypes.POINTER(_P)]),
+    ("bie_ws_fit", ctypes.c_int, [_P, _P, _P, _P, _I64, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                  ctypes.c_double, ctypes.c_uint64, _P, _P]),
     ("bie_ws_predict", ctypes.c_int, [_P, _P, _P, _I64, _P, _P, _P, _P]),
     ("bie_ws_info", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     ("bie_ws_basis", ctypes.c_int, [_P, _P, _P]),
@@ -483,6 +485,20 @@ class WarmStart:
         """Network outputs: 2K, or 6K for the linear-in-polarisation model."""
         H = self.H
         return (self.nparams - 6 * H - H * H) // (H + 1)
+
+    def fit(self, feats, targets, epochs: int, batch: int, lr_max: float = 1e-3, lr_min: float = 1e-5,
+            seed: int = 555, pols=None, stream=None) -> float:
+        """Train on given inputs and targets (S x 2K) with the library's kernels
+        (bie_ws_fit); returns the mean squared error of the last epoch."""
+        f, pf = _host(feats, np.float64)
+        t, pt = _host(targets, np.float32)
+        pp = None
+        if pols is not None:
+            e, pp = _host(pols, np.float64)
+        loss = ctypes.c_double()
+        _check(_lib.bie_ws_fit(self._h, pf, pp, pt, f.shape[0], int(epochs), int(batch), float(lr_max),
+                               float(lr_min), ctypes.c_uint64(seed), ctypes.byref(loss), _stream(stream)))
+        return loss.value
 
     def forward(self, feats) -> np.ndarray:
         f, pf = _host(feats, np.float64)

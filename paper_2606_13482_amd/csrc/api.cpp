@@ -382,6 +382,22 @@ int bie_ws_train(const bie_op *op, const double *feats, const double *pols, cons
     });
 }
 
+int bie_ws_fit(bie_ws *ws, const double *feats, const double *pols, const float *targets, int64_t S, int epochs,
+               int batch, double lr_max, double lr_min, uint64_t seed, double *final_loss, void *stream)
+{
+    return guarded([&]() -> int {
+        if (!ws || !feats || !targets) return fail(BIE_EINVAL, "NULL argument");
+        if (S < 1 || S > (int64_t(1) << 31) || epochs < 0 || batch < 1 || !(lr_max > 0.0) || !(lr_min >= 0.0))
+            return fail(BIE_EINVAL, "bad training options");
+        for (int64_t i = 0; i < 4 * S; ++i)
+            if (!std::isfinite(feats[i])) return fail(BIE_ENUMERIC, "non-finite feature");
+        const double l = bie::ws_fit(ws, feats, pols, targets, S, epochs, batch, lr_max, lr_min, seed,
+                                     as_stream(stream));
+        if (final_loss) *final_loss = l;
+        return BIE_OK;
+    });
+}
+
 int bie_ws_predict(bie_ws *ws, const double *feats, const double *pols, int64_t R, const void *B, void *X0,
                    int32_t *used, void *stream)
 {

@@ -237,6 +237,8 @@ void gemm64_product(const bie_op *op, const void *X, int64_t ldx, void *Y, int64
 // warmstart.hip
 bie_ws *ws_train(const bie_op *op, const double *feats, const double *pols, const void *X, int64_t S,
                  const bie_ws_opts &o, hipStream_t s);
+double ws_fit(bie_ws *w, const double *feats, const double *pols, const float *targets, int64_t S, int epochs,
+              int batch, double lr_max, double lr_min, uint64_t seed, hipStream_t s);
 void ws_predict(bie_ws *w, const double *feats, const double *pols, int64_t R, const void *B, void *X0, int *used,
                 hipStream_t s);
 double ws_loss_grad(bie_ws *w, const double *feats, const double *pols, const float *targets, int64_t R,

@@ -515,28 +515,31 @@ __global__ __launch_bounds__(256) void k_star_scatter(int64_t N, int64_t F, cons
 }
 
 template <typename M, typename T, bool CONJ, bool SUB>
-void launch_product(const Packed &pk, const void *Z, const void *X, int64_t ldx, void *Y, int64_t ldy, const void *B,
-                    int64_t ldb, int64_t R, const int *skip, int64_t sks, hipStream_t s)
+void launch_product(const Packed &pk, void *part, const void *Z, const void *X, int64_t ldx, void *Y, int64_t ldy,
+                    const void *B, int64_t ldb, int64_t R, const int *skip, int64_t sks, hipStream_t s,
+                    bool profile = true)
 {
     const dim3 grid(unsigned(pk.nruns), unsigned(R));
-    prof::begin(0, s, R);
+    if (profile) prof::begin(0, s, R);
     // non-temporal tile loads for the FP64 matrix, cached loads for the FP32
     // one (measured: 92 vs 144 us, 52 vs 47 us at N = 7680)
     constexpr bool NT = sizeof(M) == 8;
     if (sym_prefetch())
         hipLaunchKernelGGL((k_sym_tiles<M, T, CONJ, true, NT>), grid, dim3(256), 0, s, (const M *)Z, pk.N, pk.nT,
-                           pk.units, pk.unit_ptr, pk.run_ptr, pk.seg, pk.nslots, (const T *)X, ldx, (T *)pk.part,
+                           pk.units, pk.unit_ptr, pk.run_ptr, pk.seg, pk.nslots, (const T *)X, ldx, (T *)part,
                            skip, sks);
     else
         hipLaunchKernelGGL((k_sym_tiles<M, T, CONJ, false, NT>), grid, dim3(256), 0, s, (const M *)Z, pk.N, pk.nT,
-                           pk.units, pk.unit_ptr, pk.run_ptr, pk.seg, pk.nslots, (const T *)X, ldx, (T *)pk.part,
+                           pk.units, pk.unit_ptr, pk.run_ptr, pk.seg, pk.nslots, (const T *)X, ldx, (T *)part,
                            skip, sks);
-    prof::end(0, s);
-    prof::begin(3, s, R);
+    if (profile) {
+        prof::end(0, s);
+        prof::begin(3, s, R);
+    }
     hipLaunchKernelGGL((k_sym_reduce<T, SUB>), dim3(unsigned(pk.nT), unsigned(R)), dim3(512), 0, s, pk.N, pk.seg,
-                       pk.nslots, (const T *)pk.part, (T *)Y, ldy, (const T *)B, ldb, skip, sks);
+                       pk.nslots, (const T *)part, (T *)Y, ldy, (const T *)B, ldb, skip, sks);
     BIE_HIP(hipGetLastError());
-    prof::end(3, s);
+    if (profile) prof::end(3, s);
 }
 
 }  // namespace
@@ -645,13 +648,18 @@ void packed_free(Packed &pk)
     pk.part_R = 0;
 }
 
+// part: the partial sums, R x nslots x 64 complex T (the operator's buffer, or
+// the static scratch of the allocation-free entry point, which also skips the
+// profiling events)
 template <typename M, typename T>
 void dispatch(const Packed &pk, const void *Z, const void *X, int64_t ldx, void *Y, int64_t ldy, const void *B,
-              int64_t ldb, int64_t R, const int *skip, int64_t sks, bool conj, hipStream_t s)
+              int64_t ldb, int64_t R, const int *skip, int64_t sks, bool conj, hipStream_t s, void *part = nullptr)
 {
-    if (B) launch_product<M, T, false, true>(pk, Z, X, ldx, Y, ldy, B, ldb, R, skip, sks, s);
-    else if (conj) launch_product<M, T, true, false>(pk, Z, X, ldx, Y, ldy, nullptr, 0, R, skip, sks, s);
-    else launch_product<M, T, false, false>(pk, Z, X, ldx, Y, ldy, nullptr, 0, R, skip, sks, s);
+    const bool profile = part == nullptr;
+    if (!part) part = pk.part;
+    if (B) launch_product<M, T, false, true>(pk, part, Z, X, ldx, Y, ldy, B, ldb, R, skip, sks, s, profile);
+    else if (conj) launch_product<M, T, true, false>(pk, part, Z, X, ldx, Y, ldy, nullptr, 0, R, skip, sks, s, profile);
+    else launch_product<M, T, false, false>(pk, part, Z, X, ldx, Y, ldy, nullptr, 0, R, skip, sks, s, profile);
 }
 
 // partial-sum buffer of a packed product for R vectors (sized for complex128)

@@ -123,57 +123,74 @@ __global__ __launch_bounds__(256) void k_inner(int64_t P, int64_t S, int64_t N, 
 }
 
 // ----------------------------------------------------------------------------- FP32 MLP kernels
-// C[m][n] (+)= sum_k opA(A)[m][k] opB(B)[k][n]; opA(A)[m][k] = TA ? A[k][m] : A[m][k] (lda = row length)
-template <bool TA, bool TB>
-__global__ __launch_bounds__(256) void k_sgemm(int M, int N, int K, const float *__restrict__ A, int lda,
-                                               const float *__restrict__ Bm, int ldb, float *__restrict__ C, int ldc,
-                                               int accumulate)
-{
-    __shared__ float sa[16][65], sb[16][65];
-    const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
-    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-    float acc[4][4] = { { 0 } };
-    for (int k0 = 0; k0 < K; k0 += 16) {
-        __syncthreads();
-        for (int e = threadIdx.x; e < 16 * 64; e += 256) {
-            const int kk = e / 64, mm = e % 64;
-            const int m = m0 + mm, k = k0 + kk;
-            sa[kk][mm] = (m < M && k < K) ? (TA ? A[k * lda + m] : A[m * lda + k]) : 0.f;
-            const int n = n0 + mm;
-            sb[kk][mm] = (n < N && k < K) ? (TB ? Bm[n * ldb + k] : Bm[k * ldb + n]) : 0.f;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < 16; ++kk) {
-            float a[4], b[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = sa[kk][ty * 4 + i];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = sb[kk][tx * 4 + j];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int m = m0 + ty * 4 + i, n = n0 + tx * 4 + j;
-            if (m < M && n < N) C[m * ldc + n] = (accumulate ? C[m * ldc + n] : 0.f) + acc[i][j];
-        }
-}
+// C[m][n] = epi(sum_k opA(A)[m][k] opB(B)[k][n]) on the FP32 matrix cores
+// (v_mfma_f32_32x32x2f32: A[i][k] in lane i + 32 k, B[k][j] in lane j + 32 k,
+// value q of lane l at row 8 (q / 4) + 4 (l / 32) + q % 4, column l % 32).
+// opA(A)[m][k] = TA ? A[k][m] : A[m][k] (lda = row length of A as stored), the
+// same for B.  One block computes one 32 x 32 tile of C; its four waves take
+// interleaved K chunks of 32 (staged in LDS, loads coalesced along the stored
+// rows) and their partial tiles are summed in LDS in fixed order.
+// Epilogues: EPI_STORE C = acc; EPI_BIAS_TANH C = tanh(acc + bias[n]);
+// EPI_BIAS C = acc + bias[n]; EPI_TANH_BACK C = acc (1 - X[m][n]^2) with X the
+// stored tanh output of the layer (the backward step through tanh).
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+enum { EPI_STORE = 0, EPI_BIAS_TANH = 1, EPI_BIAS = 2, EPI_TANH_BACK = 3 };
 
-// Z[b][o] += bias[o]; A = tanh(Z) when act
-__global__ void k_bias_act(int Bn, int O, float *__restrict__ Z, const float *__restrict__ bias,
-                           float *__restrict__ Aout, int act)
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void k_sgemm_mf(int M, int N, int K, const float *__restrict__ A, int lda,
+                                                  const float *__restrict__ Bm, int ldb, float *__restrict__ C, int ldc,
+                                                  int epi, const float *__restrict__ bias, const float *__restrict__ X)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= Bn * O) return;
-    const float z = Z[i] + bias[i % O];
-    Z[i] = z;
-    if (Aout) Aout[i] = act ? tanhf(z) : z;
+    __shared__ float As[4][32][33];   // per wave: [k][m] of its K chunk
+    __shared__ float Bs[4][32][33];   // per wave: [k][n]
+    __shared__ float red[3][16][64];  // partial tiles of waves 1..3
+    const int m0 = blockIdx.y * 32, n0 = blockIdx.x * 32;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    f32x16 acc;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = 0.f;
+    const int nit = (K + 127) / 128;
+    for (int it = 0; it < nit; ++it) {
+        const int kc = it * 128 + w * 32;
+#pragma unroll 4
+        for (int e = lane; e < 1024; e += 64) {
+            const int hi = e >> 5, lo = e & 31;   // lo runs along the stored row
+            int mm, kk;
+            float v;
+            if (TA) { kk = hi; mm = lo; v = (m0 + mm < M && kc + kk < K) ? A[int64_t(kc + kk) * lda + m0 + mm] : 0.f; }
+            else { mm = hi; kk = lo; v = (m0 + mm < M && kc + kk < K) ? A[int64_t(m0 + mm) * lda + kc + kk] : 0.f; }
+            As[w][kk][mm] = v;
+            int nn;
+            if (TB) { nn = hi; kk = lo; v = (n0 + nn < N && kc + kk < K) ? Bm[int64_t(n0 + nn) * ldb + kc + kk] : 0.f; }
+            else { kk = hi; nn = lo; v = (n0 + nn < N && kc + kk < K) ? Bm[int64_t(kc + kk) * ldb + n0 + nn] : 0.f; }
+            Bs[w][kk][nn] = v;
+        }
+        __syncthreads();
+        const int i = lane & 31, h = lane >> 5;
+#pragma unroll
+        for (int kk = 0; kk < 32; kk += 2)
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(As[w][kk + h][i], Bs[w][kk + h][i], acc, 0, 0, 0);
+        __syncthreads();
+    }
+    if (w > 0)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) red[w - 1][q][lane] = acc[q];
+    __syncthreads();
+    if (w != 0) return;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const float v = ((acc[q] + red[0][q][lane]) + red[1][q][lane]) + red[2][q][lane];
+        const int m = m0 + 8 * (q / 4) + 4 * (lane / 32) + q % 4, n = n0 + (lane & 31);
+        if (m >= M || n >= N) continue;
+        float o = v;
+        if (epi == EPI_BIAS_TANH) o = tanhf(v + bias[n]);
+        else if (epi == EPI_BIAS) o = v + bias[n];
+        else if (epi == EPI_TANH_BACK) {
+            const float a = X[int64_t(m) * ldc + n];
+            o = v * (1.f - a * a);
+        }
+        C[int64_t(m) * ldc + n] = o;
+    }
 }
 
 // loss partials and dL/dy = 2 (y - t) / (B O)
@@ -194,13 +211,6 @@ __global__ void k_mse(int n, const float *__restrict__ y, const float *__restric
         __syncthreads();
     }
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
-}
-
-// dZ = dA * (1 - tanh(Z)^2) with A = tanh(Z) stored
-__global__ void k_tanh_back(int n, const float *__restrict__ A, float *__restrict__ dA)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) dA[i] *= 1.f - A[i] * A[i];
 }
 
 // db[o] = sum_b dZ[b][o]
@@ -318,11 +328,11 @@ void inner(int64_t P, int64_t S, int64_t N, const double2 *A, const double2 *B, 
 }
 
 template <bool TA, bool TB>
-void sgemm(int M, int N, int K, const float *A, int lda, const float *B, int ldb, float *C, int ldc, bool acc,
-           hipStream_t s)
+void sgemm(int M, int N, int K, const float *A, int lda, const float *B, int ldb, float *C, int ldc, hipStream_t s,
+           int epi = EPI_STORE, const float *bias = nullptr, const float *X = nullptr)
 {
-    const dim3 grid(unsigned((N + 63) / 64), unsigned((M + 63) / 64));
-    hipLaunchKernelGGL((k_sgemm<TA, TB>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, int(acc));
+    const dim3 grid(unsigned((N + 31) / 32), unsigned((M + 31) / 32));
+    hipLaunchKernelGGL((k_sgemm_mf<TA, TB>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, epi, bias, X);
     BIE_HIP(hipGetLastError());
 }
 
@@ -434,14 +444,19 @@ struct bie_ws {
     // training / evaluation scratch
     float *grad = nullptr, *am = nullptr, *av = nullptr;
     int cap_batch = 0;
-    float *in = nullptr, *z1 = nullptr, *a1 = nullptr, *z2 = nullptr, *a2 = nullptr, *y = nullptr, *dy = nullptr,
+    float *in = nullptr, *a1 = nullptr, *a2 = nullptr, *y = nullptr, *dy = nullptr,
           *d2 = nullptr, *d1 = nullptr, *tgt = nullptr, *pol = nullptr, *yc = nullptr, *dyc = nullptr;
     double *lpart = nullptr;
+    // prediction scratch, grown on demand: coefficients (R x K) and, for the
+    // fallback, residuals (R x N) and squared norms (2R)
+    double2 *coef = nullptr, *res = nullptr;
+    double *nr = nullptr;
+    int64_t cap_coef = 0, cap_res = 0;
     ~bie_ws()
     {
-        for (void *p : { (void *)U, (void *)params, (void *)grad, (void *)am, (void *)av, (void *)in, (void *)z1,
-                         (void *)a1, (void *)z2, (void *)a2, (void *)y, (void *)dy, (void *)d2, (void *)d1, (void *)tgt,
-                         (void *)lpart, (void *)pol, (void *)yc, (void *)dyc })
+        for (void *p : { (void *)U, (void *)params, (void *)grad, (void *)am, (void *)av, (void *)in,
+                         (void *)a1, (void *)a2, (void *)y, (void *)dy, (void *)d2, (void *)d1, (void *)tgt,
+                         (void *)lpart, (void *)pol, (void *)yc, (void *)dyc, (void *)coef, (void *)res, (void *)nr })
             if (p) (void)hipFree(p);
     }
 };
@@ -474,15 +489,13 @@ void ws_alloc_params(bie_ws *w)
 void ws_batch_scratch(bie_ws *w, int B)
 {
     if (w->cap_batch >= B) return;
-    for (float **p : { &w->in, &w->z1, &w->a1, &w->z2, &w->a2, &w->y, &w->dy, &w->d2, &w->d1, &w->tgt, &w->pol,
+    for (float **p : { &w->in, &w->a1, &w->a2, &w->y, &w->dy, &w->d2, &w->d1, &w->tgt, &w->pol,
                        &w->yc, &w->dyc })
         if (*p) { (void)hipFree(*p); *p = nullptr; }
     if (w->lpart) { (void)hipFree(w->lpart); w->lpart = nullptr; }
     const size_t H = w->H, O = w->O;
     w->in = dmalloc<float>(size_t(B) * 4);
-    w->z1 = dmalloc<float>(size_t(B) * H);
     w->a1 = dmalloc<float>(size_t(B) * H);
-    w->z2 = dmalloc<float>(size_t(B) * H);
     w->a2 = dmalloc<float>(size_t(B) * H);
     w->y = dmalloc<float>(size_t(B) * O);
     w->dy = dmalloc<float>(size_t(B) * O);
@@ -501,14 +514,9 @@ void mlp_forward(bie_ws *w, int B, hipStream_t s)
 {
     const int H = w->H, O = w->O;
     float *P = w->params;
-    sgemm<false, true>(B, H, 4, w->in, 4, P + w->off[0], 4, w->z1, H, false, s);
-    hipLaunchKernelGGL(k_bias_act, dim3((B * H + 255) / 256), dim3(256), 0, s, B, H, w->z1, P + w->off[1], w->a1, 1);
-    sgemm<false, true>(B, H, H, w->a1, H, P + w->off[2], H, w->z2, H, false, s);
-    hipLaunchKernelGGL(k_bias_act, dim3((B * H + 255) / 256), dim3(256), 0, s, B, H, w->z2, P + w->off[3], w->a2, 1);
-    sgemm<false, true>(B, O, H, w->a2, H, P + w->off[4], H, w->y, O, false, s);
-    hipLaunchKernelGGL(k_bias_act, dim3((B * O + 255) / 256), dim3(256), 0, s, B, O, w->y, P + w->off[5],
-                       (float *)nullptr, 0);
-    BIE_HIP(hipGetLastError());
+    sgemm<false, true>(B, H, 4, w->in, 4, P + w->off[0], 4, w->a1, H, s, EPI_BIAS_TANH, P + w->off[1]);
+    sgemm<false, true>(B, H, H, w->a1, H, P + w->off[2], H, w->a2, H, s, EPI_BIAS_TANH, P + w->off[3]);
+    sgemm<false, true>(B, O, H, w->a2, H, P + w->off[4], H, w->y, O, s, EPI_BIAS, P + w->off[5]);
 }
 
 // loss partials (w->lpart[0..nb)) and gradient of the mean squared error into
@@ -531,17 +539,16 @@ int mlp_backward(bie_ws *w, int B, hipStream_t s, bool combine = false)
                            w->lpart);
     }
     // layer 3
-    sgemm<true, false>(O, H, B, w->dy, O, w->a2, H, G + w->off[4], H, false, s);   // dW3 = dy^T a2
+    sgemm<true, false>(O, H, B, w->dy, O, w->a2, H, G + w->off[4], H, s);   // dW3 = dy^T a2
     hipLaunchKernelGGL(k_colsum, dim3((O + 255) / 256), dim3(256), 0, s, B, O, w->dy, G + w->off[5]);
-    sgemm<false, false>(B, H, O, w->dy, O, P + w->off[4], H, w->d2, H, false, s);   // da2 = dy W3
-    hipLaunchKernelGGL(k_tanh_back, dim3((B * H + 255) / 256), dim3(256), 0, s, B * H, w->a2, w->d2);
+    // dZ2 = (dy W3) (1 - a2^2)
+    sgemm<false, false>(B, H, O, w->dy, O, P + w->off[4], H, w->d2, H, s, EPI_TANH_BACK, nullptr, w->a2);
     // layer 2
-    sgemm<true, false>(H, H, B, w->d2, H, w->a1, H, G + w->off[2], H, false, s);
+    sgemm<true, false>(H, H, B, w->d2, H, w->a1, H, G + w->off[2], H, s);
     hipLaunchKernelGGL(k_colsum, dim3((H + 255) / 256), dim3(256), 0, s, B, H, w->d2, G + w->off[3]);
-    sgemm<false, false>(B, H, H, w->d2, H, P + w->off[2], H, w->d1, H, false, s);
-    hipLaunchKernelGGL(k_tanh_back, dim3((B * H + 255) / 256), dim3(256), 0, s, B * H, w->a1, w->d1);
+    sgemm<false, false>(B, H, H, w->d2, H, P + w->off[2], H, w->d1, H, s, EPI_TANH_BACK, nullptr, w->a1);
     // layer 1
-    sgemm<true, false>(H, 4, B, w->d1, H, w->in, 4, G + w->off[0], 4, false, s);
+    sgemm<true, false>(H, 4, B, w->d1, H, w->in, 4, G + w->off[0], 4, s);
     hipLaunchKernelGGL(k_colsum, dim3((H + 255) / 256), dim3(256), 0, s, B, H, w->d1, G + w->off[1]);
     BIE_HIP(hipGetLastError());
     return nb;
@@ -563,6 +570,95 @@ void glorot(bie_ws *w, uint64_t seed)
 }
 
 }  // namespace
+
+// Network inputs as FP32 on the device (S x 4; the linear-in-polarisation
+// model takes the direction alone, its fourth input is 0).
+static float *upload_features(const bie_ws *w, const double *feats, int64_t S)
+{
+    std::vector<float> fh(size_t(S) * 4);
+    for (size_t i = 0; i < fh.size(); ++i) fh[i] = float(feats[i]);
+    if (w->pmodel == 1)
+        for (int64_t i = 0; i < S; ++i) fh[i * 4 + 3] = 0.f;
+    float *F = dmalloc<float>(fh.size());
+    BIE_HIP(hipMemcpy(F, fh.data(), fh.size() * sizeof(float), hipMemcpyHostToDevice));
+    return F;
+}
+
+static float *upload_pols(const double *pols, int64_t S)
+{
+    std::vector<float> eh(size_t(S) * 3);
+    for (size_t i = 0; i < eh.size(); ++i) eh[i] = float(pols[i]);
+    float *E = dmalloc<float>(eh.size());
+    BIE_HIP(hipMemcpy(E, eh.data(), eh.size() * sizeof(float), hipMemcpyHostToDevice));
+    return E;
+}
+
+// Adam on mini-batches of the device inputs F (S x 4), targets T (S x 2K) and
+// polarisations E (S x 3, linear-in-polarisation model only): per epoch a
+// Fisher-Yates shuffle from SplitMix64(seed + 1 + epoch), batches in that order,
+// learning rate cosine-decayed from lr_max (first step) to lr_min (last step),
+// Adam (0.9, 0.999, 1e-8) with bias correction 1 - beta^step.  Returns the mean
+// squared error over the last epoch (NaN for 0 epochs).
+static double ws_fit_dev(bie_ws *w, const float *F, const float *T, const float *E, int64_t S, int epochs, int batch,
+                         double lr_max, double lr_min, uint64_t seed, hipStream_t s)
+{
+    const int TW = 2 * w->K;   // target width
+    BIE_HIP(hipMemsetAsync(w->am, 0, w->nparams * sizeof(float), s));
+    BIE_HIP(hipMemsetAsync(w->av, 0, w->nparams * sizeof(float), s));
+    const int Bsz = int(std::min<int64_t>(batch, S));
+    ws_batch_scratch(w, Bsz);
+    const int64_t nbatch = (S + Bsz - 1) / Bsz;
+    const int64_t total = int64_t(epochs) * nbatch;
+    int64_t step = 0;
+    std::vector<int64_t> perm(S);
+    int64_t *dperm = dmalloc<int64_t>(size_t(S));
+    std::vector<double> lp(64);
+    double last = NAN;
+    const double PI = 3.14159265358979323846;
+    try {
+        for (int ep = 0; ep < epochs; ++ep) {
+            for (int64_t i = 0; i < S; ++i) perm[i] = i;
+            SM64 g(seed + 1 + uint64_t(ep));
+            for (int64_t i = S - 1; i > 0; --i) std::swap(perm[i], perm[g.below(uint64_t(i + 1))]);
+            BIE_HIP(hipMemcpyAsync(dperm, perm.data(), size_t(S) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+            double eloss = 0.0;
+            for (int64_t bi = 0; bi < nbatch; ++bi) {
+                const int64_t b0 = bi * Bsz;
+                const int B = int(std::min<int64_t>(Bsz, S - b0));
+                hipLaunchKernelGGL(k_gather, dim3(unsigned(B)), dim3(256), 0, s, B, TW, dperm, b0, F, T, E, w->in,
+                                   w->tgt, w->pol);
+                mlp_forward(w, B, s);
+                const int nb = mlp_backward(w, B, s, w->pmodel == 1);
+                ++step;
+                const double lr = lr_min + 0.5 * (lr_max - lr_min) *
+                                               (1.0 + std::cos(PI * double(step - 1) /
+                                                               double(std::max<int64_t>(1, total - 1))));
+                const float c1 = float(1.0 - std::pow(0.9, double(step)));
+                const float c2 = float(1.0 - std::pow(0.999, double(step)));
+                hipLaunchKernelGGL(k_adam, dim3(unsigned((w->nparams + 255) / 256)), dim3(256), 0, s,
+                                   int(w->nparams), w->params, w->grad, w->am, w->av, float(lr), 0.9f, 0.999f, 1e-8f,
+                                   c1, c2);
+                BIE_HIP(hipGetLastError());
+                if (ep == epochs - 1) {
+                    BIE_HIP(hipMemcpyAsync(lp.data(), w->lpart, nb * sizeof(double), hipMemcpyDeviceToHost, s));
+                    BIE_HIP(hipStreamSynchronize(s));
+                    double a = 0.0;
+                    for (int q = 0; q < nb; ++q) a += lp[q];
+                    eloss += a / double(B * TW) * B;
+                }
+            }
+            if (ep == epochs - 1) last = eloss / double(S);
+            // the host permutation is rewritten next epoch: wait for its upload
+            BIE_HIP(hipStreamSynchronize(s));
+        }
+    } catch (...) {
+        (void)hipFree(dperm);
+        throw;
+    }
+    (void)hipFree(dperm);
+    BIE_HIP(hipStreamSynchronize(s));
+    return last;
+}
 
 // POD basis of the S snapshots X (S x N, device) with K modes.
 static void pod_basis(bie_ws *w, const double2 *X, int64_t S, int oversample, int power, uint64_t seed, hipStream_t s)
@@ -665,77 +761,40 @@ bie_ws *ws_train(const bie_op *op, const double *feats, const double *pols, cons
     if (!(w->scale > 0.0)) w->scale = 1.0;
     hipLaunchKernelGGL(k_targets, dim3(unsigned((S * w->K + 255) / 256)), dim3(256), 0, s, int(S), w->K, C,
                        1.0 / w->scale, T);
-    const int TW = 2 * w->K;   // target width
     BIE_HIP(hipGetLastError());
     ws_alloc_params(w.get());
     glorot(w.get(), o.seed);
-    BIE_HIP(hipMemset(w->am, 0, w->nparams * sizeof(float)));
-    BIE_HIP(hipMemset(w->av, 0, w->nparams * sizeof(float)));
-    const int Bsz = int(std::min<int64_t>(o.batch, S));
-    ws_batch_scratch(w.get(), Bsz);
-    // features as FP32 on the device
-    std::vector<float> fh(size_t(S) * 4);
-    for (size_t i = 0; i < fh.size(); ++i) fh[i] = float(feats[i]);
-    if (w->pmodel == 1)
-        for (int64_t i = 0; i < S; ++i) fh[i * 4 + 3] = 0.f;   // input is the direction alone
-    float *F = dmalloc<float>(fh.size());
-    BIE_HIP(hipMemcpy(F, fh.data(), fh.size() * sizeof(float), hipMemcpyHostToDevice));
-    float *E = nullptr;
-    if (w->pmodel == 1) {
-        std::vector<float> eh(size_t(S) * 3);
-        for (size_t i = 0; i < eh.size(); ++i) eh[i] = float(pols[i]);
-        E = dmalloc<float>(eh.size());
-        BIE_HIP(hipMemcpy(E, eh.data(), eh.size() * sizeof(float), hipMemcpyHostToDevice));
+    float *F = nullptr, *E = nullptr;
+    try {
+        F = upload_features(w.get(), feats, S);
+        if (w->pmodel == 1) E = upload_pols(pols, S);
+        w->final_loss = ws_fit_dev(w.get(), F, T, E, S, o.epochs, o.batch, o.lr_max, o.lr_min, o.seed, s);
+    } catch (...) {
+        for (void *p : { (void *)C, (void *)T, (void *)F, (void *)E }) (void)hipFree(p);
+        throw;
     }
-    const int64_t nbatch = (S + Bsz - 1) / Bsz;
-    const int64_t total = int64_t(o.epochs) * nbatch;
-    int64_t step = 0;
-    std::vector<int64_t> perm(S);
-    int64_t *dperm = dmalloc<int64_t>(size_t(S));
-    std::vector<double> lp(64);
-    double last = NAN;
-    const double PI = 3.14159265358979323846;
-    for (int ep = 0; ep < o.epochs; ++ep) {
-        // Fisher-Yates shuffle with SplitMix64(seed + 1 + epoch)
-        for (int64_t i = 0; i < S; ++i) perm[i] = i;
-        SM64 g(o.seed + 1 + uint64_t(ep));
-        for (int64_t i = S - 1; i > 0; --i) std::swap(perm[i], perm[g.below(uint64_t(i + 1))]);
-        BIE_HIP(hipMemcpyAsync(dperm, perm.data(), size_t(S) * sizeof(int64_t), hipMemcpyHostToDevice, s));
-        double eloss = 0.0;
-        for (int64_t bi = 0; bi < nbatch; ++bi) {
-            const int64_t b0 = bi * Bsz;
-            const int B = int(std::min<int64_t>(Bsz, S - b0));
-            hipLaunchKernelGGL(k_gather, dim3(unsigned(B)), dim3(256), 0, s, B, TW, dperm, b0, F, T, E, w->in,
-                               w->tgt, w->pol);
-            mlp_forward(w.get(), B, s);
-            const int nb = mlp_backward(w.get(), B, s, w->pmodel == 1);
-            ++step;
-            const double lr = o.lr_min + 0.5 * (o.lr_max - o.lr_min) *
-                                             (1.0 + std::cos(PI * double(step - 1) / double(std::max<int64_t>(1, total - 1))));
-            const float c1 = float(1.0 - std::pow(0.9, double(step))), c2 = float(1.0 - std::pow(0.999, double(step)));
-            hipLaunchKernelGGL(k_adam, dim3(unsigned((w->nparams + 255) / 256)), dim3(256), 0, s, int(w->nparams),
-                               w->params, w->grad, w->am, w->av, float(lr), 0.9f, 0.999f, 1e-8f, c1, c2);
-            BIE_HIP(hipGetLastError());
-            if (ep == o.epochs - 1) {
-                BIE_HIP(hipMemcpyAsync(lp.data(), w->lpart, nb * sizeof(double), hipMemcpyDeviceToHost, s));
-                BIE_HIP(hipStreamSynchronize(s));
-                double a = 0.0;
-                for (int q = 0; q < nb; ++q) a += lp[q];
-                eloss += a / double(B * TW) * B;
-            }
-        }
-        if (ep == o.epochs - 1) last = eloss / double(S);
-        // the host permutation is rewritten next epoch: wait for its upload
-        BIE_HIP(hipStreamSynchronize(s));
-    }
-    (void)hipFree(dperm);
-    BIE_HIP(hipStreamSynchronize(s));
-    w->final_loss = last;
-    (void)hipFree(C);
-    (void)hipFree(T);
-    (void)hipFree(F);
-    if (E) (void)hipFree(E);
+    for (void *p : { (void *)C, (void *)T, (void *)F, (void *)E }) (void)hipFree(p);
     return w.release();
+}
+
+double ws_fit(bie_ws *w, const double *feats, const double *pols, const float *targets, int64_t S, int epochs,
+              int batch, double lr_max, double lr_min, uint64_t seed, hipStream_t s)
+{
+    if (w->pmodel == 1 && !pols) throw Error(BIE_EINVAL, "the linear-in-polarisation model needs the polarisations");
+    float *F = nullptr, *E = nullptr, *T = nullptr;
+    double loss = NAN;
+    try {
+        F = upload_features(w, feats, S);
+        if (w->pmodel == 1) E = upload_pols(pols, S);
+        T = dmalloc<float>(size_t(S) * 2 * w->K);
+        BIE_HIP(hipMemcpy(T, targets, size_t(S) * 2 * w->K * sizeof(float), hipMemcpyHostToDevice));
+        loss = ws_fit_dev(w, F, T, E, S, epochs, batch, lr_max, lr_min, seed, s);
+    } catch (...) {
+        for (void *p : { (void *)F, (void *)E, (void *)T }) (void)hipFree(p);
+        throw;
+    }
+    for (void *p : { (void *)F, (void *)E, (void *)T }) (void)hipFree(p);
+    return loss;
 }
 
 // Network outputs for R feature rows (host FP64 in, device FP32 out in w->y).
@@ -767,36 +826,42 @@ void ws_predict(bie_ws *w, const double *feats, const double *pols, int64_t R, c
                            w->pol, w->yc);
         out = w->yc;
     }
-    double2 *c = dmalloc<double2>(size_t(R) * w->K);
+    if (w->cap_coef < R) {
+        if (w->coef) (void)hipFree(w->coef);
+        w->coef = nullptr;
+        w->coef = dmalloc<double2>(size_t(R) * w->K);
+        w->cap_coef = R;
+    }
     hipLaunchKernelGGL(k_out_to_coef, dim3(unsigned((R * w->K + 255) / 256)), dim3(256), 0, s, int(R), w->K, out,
-                       w->scale, c);
-    lincomb(R, w->K, N, c, w->U, static_cast<double2 *>(X0), s);
-    (void)hipStreamSynchronize(s);
-    (void)hipFree(c);
+                       w->scale, w->coef);
+    lincomb(R, w->K, N, w->coef, w->U, static_cast<double2 *>(X0), s);
     if (!B) {
         if (used)
             for (int64_t r = 0; r < R; ++r) used[r] = 1;
         return;
     }
     // fallback: keep x0 only where ||b - T x0|| < ||b||
-    double2 *res = dmalloc<double2>(size_t(R) * N);
-    double *nr = dmalloc<double>(size_t(2 * R));
+    if (w->cap_res < R) {
+        for (void *p : { (void *)w->res, (void *)w->nr }) if (p) (void)hipFree(p);
+        w->res = nullptr;
+        w->nr = nullptr;
+        w->res = dmalloc<double2>(size_t(R) * N);
+        w->nr = dmalloc<double>(size_t(2 * R));
+        w->cap_res = R;
+    }
     const bool m64 = w->op->Z64 != nullptr;
-    if (m64 && R >= 8) gemm64_product(w->op, X0, N, res, N, B, N, R, nullptr, s);   // many columns: matrix cores
-    else product(w->op, m64 ? MAT64 : MAT32, true, X0, N, res, N, B, N, R, nullptr, 1, false, s);
-    hipLaunchKernelGGL(k_sqnorm, dim3(unsigned(R)), dim3(256), 0, s, N, res, nr);
-    hipLaunchKernelGGL(k_sqnorm, dim3(unsigned(R)), dim3(256), 0, s, N, static_cast<const double2 *>(B), nr + R);
+    if (m64 && R >= 8) gemm64_product(w->op, X0, N, w->res, N, B, N, R, nullptr, s);   // many columns: matrix cores
+    else product(w->op, m64 ? MAT64 : MAT32, true, X0, N, w->res, N, B, N, R, nullptr, 1, false, s);
+    hipLaunchKernelGGL(k_sqnorm, dim3(unsigned(R)), dim3(256), 0, s, N, w->res, w->nr);
+    hipLaunchKernelGGL(k_sqnorm, dim3(unsigned(R)), dim3(256), 0, s, N, static_cast<const double2 *>(B), w->nr + R);
     std::vector<double> h(size_t(2 * R));
-    BIE_HIP(hipMemcpyAsync(h.data(), nr, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    BIE_HIP(hipMemcpyAsync(h.data(), w->nr, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     BIE_HIP(hipStreamSynchronize(s));
-    (void)hipFree(res);
-    (void)hipFree(nr);
     for (int64_t r = 0; r < R; ++r) {
         const bool keep = h[r] < h[R + r];
         if (used) used[r] = keep;
         if (!keep) BIE_HIP(hipMemsetAsync(static_cast<double2 *>(X0) + r * N, 0, N * sizeof(double2), s));
     }
-    BIE_HIP(hipStreamSynchronize(s));
 }
 
 // Loss and gradient of the MSE for given inputs (R x 4; R x 3 polarisations

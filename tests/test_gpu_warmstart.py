@@ -177,3 +177,64 @@ def test_gain_linear_in_polarisation(bie, small):
          f"initial residual median {np.median(r0):.2e}")
     assert all(s["converged"] for s in stw)
     assert itw.mean() < 0.95 * itz.mean()
+
+
+@pytest.mark.parametrize("pol_model", [0, 1])
+def test_training_steps_match_oracle(bie, small, pol_model):
+    """bie_ws_fit (the library's training loop: shuffles, mini-batches, matrix-core
+    forward and backward, Adam with bias correction, cosine rate) against the
+    oracle's learn.train from the same Glorot weights on the same inputs and
+    targets: 4 epochs of 3 mini-batches.  FP32 on the device against FP64: the
+    parameters after 12 steps agree to a small fraction of how far they moved."""
+    K, H = 8, 32
+    seed = 77
+    ws = bie.WarmStart.create(small, K, H, seed, pol_model=pol_model)
+    p0 = ws.params().astype(np.float64)
+    assert np.array_equal(p0, learn.glorot(K, H, seed, pol_model).astype(np.float32).astype(np.float64))
+    rng = np.random.default_rng(21)
+    dirs, pols, F = _feats(bie, random_directions(12, 8))
+    S = F.shape[0]
+    Tt = rng.standard_normal((S, 2 * K)).astype(np.float32)
+    epochs, batch, lr_max, lr_min = 4, 8, 1e-3, 1e-4
+    loss = ws.fit(F, Tt, epochs, batch, lr_max, lr_min, seed=5, pols=pols if pol_model else None)
+    pg = ws.params().astype(np.float64)
+    if pol_model == 0:
+        po = learn.train(p0, K, H, F, Tt.astype(np.float64), epochs, batch, lr_max, lr_min, 5)
+    else:
+        po = learn.train(p0, K, H, None, Tt.astype(np.float64), epochs, batch, lr_max, lr_min, 5, D=dirs, E=pols)
+    moved = np.linalg.norm(po - p0)
+    rel = np.linalg.norm(pg - po) / moved
+    worst = np.max(np.abs(pg - po))
+    _say(f"  pol_model {pol_model}: |p_gpu - p_oracle| / |p_oracle - p0| = {rel:.2e}, max {worst:.2e} "
+         f"(lr_max {lr_max}), final loss {loss:.4e}")
+    assert moved > 12 * lr_min
+    assert rel <= 1e-4            # measured on the MI355X: 8e-6
+    assert worst <= 2e-3 * lr_max  # measured: 1.25e-7
+
+
+@pytest.mark.parametrize("pol_model", [0, 1])
+def test_forward_and_gradient_at_bench_size(bie, small, pol_model):
+    """The network of the learned warm-start workload (K = 256 modes, H = 512; 512
+    outputs, or 1536 for the linear-in-polarisation model) on 64 inputs: outputs
+    and the gradient of the loss against the oracle's FP64 backpropagation."""
+    K, H = 256, 512
+    ws = bie.WarmStart.create(small, K, H, 555, pol_model=pol_model)
+    assert ws.outputs == (6 if pol_model else 2) * K
+    rng = np.random.default_rng(8)
+    p = (learn.glorot(K, H, 555, pol_model) + 0.01 * rng.standard_normal(ws.nparams)).astype(np.float32)
+    ws.set_params(p)
+    dirs, pols, F = _feats(bie, random_directions(32, 9))
+    Tt = rng.standard_normal((F.shape[0], 2 * K)).astype(np.float32)
+    Fin = F if pol_model == 0 else np.concatenate([dirs, np.zeros((dirs.shape[0], 1))], axis=1)
+    y = ws.forward(F)
+    yo, _ = learn.forward(p.astype(np.float64), K, H, Fin, pol_model)
+    ey = np.max(np.abs(y - yo)) / np.max(np.abs(yo))
+    if pol_model == 0:
+        loss, g = ws.loss_grad(F, Tt)
+        lo, go = learn.loss_grad(p.astype(np.float64), K, H, F, Tt.astype(np.float64))
+    else:
+        loss, g = ws.loss_grad(F, Tt, pols=pols)
+        lo, go = learn.loss_grad_pol(p.astype(np.float64), K, H, dirs, pols, Tt.astype(np.float64))
+    eg = np.linalg.norm(g - go) / np.linalg.norm(go)
+    _say(f"  K={K} H={H} outputs={ws.outputs}: forward {ey:.2e}, loss {abs(loss - lo) / lo:.2e}, gradient {eg:.2e}")
+    assert ey <= 1e-5 and abs(loss - lo) <= 1e-5 * lo and eg <= 1e-5
