@@ -135,6 +135,21 @@ int bie_rhs_planewave(const bie_op *op, const double *dirs, const double *pols, 
 int bie_apply(const bie_op *op, const void *X, void *Y, int64_t R, int vec, int conj,
               void *stream);
 
+/* Allocation-free form of bie_apply, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): Y = T X (conj = 0) or T^H X (conj = 1) through the packed
+ * product, vec = BIE_C128 (FP64 matrix if stored, else FP32 with FP64
+ * accumulation) or BIE_C64 (FP32 matrix), assembled operators only.  The
+ * product's partial sums (R x P x 64 complex values, P the operator's partial
+ * slots: about 8 MB per complex128 vector at N = 7680) go to a static device
+ * array of 128 MiB that each device holds for the life of the process; larger
+ * requests return BIE_EINVAL before any launch (use fewer vectors per call).
+ * Nothing is allocated and no profiling events are recorded.  Every call on a
+ * device shares that array: calls that overlap on one device (other streams or
+ * threads) race; calls ordered on one stream do not.  The operator's device
+ * must be current.  Results are bitwise those of bie_apply. */
+int bie_apply_noalloc(const bie_op *op, const void *X, void *Y, int64_t R, int vec, int conj, void *stream);
+
 typedef enum { BIE_GMRES = 0, BIE_CGNR = 1, BIE_BGMRES = 2 } bie_method;
 typedef enum { BIE_SCC = 0, BIE_RSCC = 1, BIE_CCC = 2 } bie_crit;
 

@@ -81,6 +81,7 @@ SYMBOLS = [
     ("bie_op_matrix", ctypes.c_int, [_P, _P, ctypes.c_int, _P]),
     ("bie_rhs_planewave", ctypes.c_int, [_P, _P, _P, _I64, _P, _P]),
     ("bie_apply", ctypes.c_int, [_P, _P, _P, _I64, ctypes.c_int, ctypes.c_int, _P]),
+    ("bie_apply_noalloc", ctypes.c_int, [_P, _P, _P, _I64, ctypes.c_int, ctypes.c_int, _P]),
     ("bie_solve", ctypes.c_int, [_P, _P, _P, _I64, _P, _P, _P]),
     ("bie_farfield", ctypes.c_int, [_P, _P, _I64, _P, _I64, _P, _P]),
     ("bie_batch_solve", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P]),

@@ -206,6 +206,19 @@ int bie_apply(const bie_op *op, const void *X, void *Y, int64_t R, int vec, int 
     });
 }
 
+int bie_apply_noalloc(const bie_op *op, const void *X, void *Y, int64_t R, int vec, int conj, void *stream)
+{
+    return guarded([&]() -> int {
+        if (!op || !X || !Y) return fail(BIE_EINVAL, "NULL argument");
+        if (R < 0 || R > 65535) return fail(BIE_EINVAL, "R out of range (0..65535)");
+        if (R == 0) return BIE_OK;
+        if (vec != BIE_C128 && vec != BIE_C64)
+            return fail(BIE_EINVAL, "the allocation-free product takes complex128 or complex64 vectors");
+        bie::product_noalloc(op, vec == BIE_C128, X, Y, R, conj != 0, as_stream(stream));
+        return BIE_OK;
+    });
+}
+
 int bie_solve(const bie_op *op, const void *B, void *X, int64_t R, const bie_solve_opts *opts,
               bie_solve_stat *stats, void *stream)
 {

@@ -205,6 +205,9 @@ void packed_free(Packed &pk);
 enum { MAT64 = 0, MAT32 = 1, MATBF16 = 2 };
 void product(const bie_op *op, int mat, bool vec64, const void *X, int64_t ldx, void *Y, int64_t ldy,
              const void *B, int64_t ldb, int64_t R, const int *skip, int64_t sks, bool conj, hipStream_t s);
+// Y = T X (or T^H X) with the packed matrix, partial sums in the library's
+// static per-device scratch (no allocation); BIE_EINVAL when they do not fit.
+void product_noalloc(const bie_op *op, bool vec64, const void *X, void *Y, int64_t R, bool conj, hipStream_t s);
 // packed -> full row-major complex128
 void unpack_c128(const bie_op *op, bool from64, void *dst, hipStream_t s);
 // sampled rows of T x (complex128): out[r*S + i] = |b_i - (T x_r)_i|^2, i in rows[r*S ..]

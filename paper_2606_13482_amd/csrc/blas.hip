@@ -23,6 +23,8 @@
 #include <algorithm>
 #include <cstdlib>
 #include <utility>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "bie_internal.hpp"
@@ -729,6 +731,58 @@ void product(const bie_op *opc, int mat, bool vec64, const void *X, int64_t ldx,
     if (mat64) dispatch<double, double>(op->pk, Z, X, ldx, Y, ldy, B, ldb, R, skip, sks, conj, s);
     else if (vec64) dispatch<float, double>(op->pk, Z, X, ldx, Y, ldy, B, ldb, R, skip, sks, conj, s);
     else dispatch<float, float>(op->pk, Z, X, ldx, Y, ldy, B, ldb, R, skip, sks, conj, s);
+}
+
+// ----------------------------------------------------------------------------- allocation-free product
+// For callers that cannot allocate (graph capture, serving loops): the
+// partial sums live in this static array instead of the operator's buffer.
+// Each device holds its own copy for the life of the process; host code
+// reaches it only through the address hipGetSymbolAddress returns on that
+// device (kept in scratch_dev), never through the array's name.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void *scratch_dev[MAX_DEVICES] = { nullptr };
+
+// device address of the current device's scratch, looked up once per device
+void *noalloc_scratch(int dev)
+{
+    if (dev < 0 || dev >= MAX_DEVICES) throw Error(BIE_EDEVICE, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> g(scratch_mu);
+    if (!scratch_dev[dev]) {
+        void *p = nullptr;
+        BIE_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) throw Error(BIE_EDEVICE, "hipGetSymbolAddress returned no address for the scratch array");
+        scratch_dev[dev] = p;
+    }
+    return scratch_dev[dev];
+}
+}  // namespace
+
+void product_noalloc(const bie_op *op, bool vec64, const void *X, void *Y, int64_t R, bool conj, hipStream_t s)
+{
+    if (op->star) throw Error(BIE_EINVAL, "the allocation-free product takes an assembled operator");
+    const Packed &pk = op->pk;
+    const size_t need = size_t(R) * size_t(pk.nslots) * TB * (vec64 ? 16 : 8);
+    if (need > NOALLOC_SCRATCH_BYTES)
+        throw Error(BIE_EINVAL, "partial sums of " + std::to_string(need) + " bytes exceed the " +
+                                    std::to_string(NOALLOC_SCRATCH_BYTES) + "-byte scratch of the allocation-free "
+                                    "product: use fewer vectors per call");
+    int dev = -1;
+    BIE_HIP(hipGetDevice(&dev));
+    if (dev != op->device) throw Error(BIE_EINVAL, "the operator's device must be current");
+    void *part = noalloc_scratch(dev);
+    if (vec64) {
+        if (op->Z64) dispatch<double, double>(pk, op->Z64, X, pk.N, Y, pk.N, nullptr, 0, R, nullptr, 1, conj, s, part);
+        else if (op->Z32) dispatch<float, double>(pk, op->Z32, X, pk.N, Y, pk.N, nullptr, 0, R, nullptr, 1, conj, s, part);
+        else throw Error(BIE_EINVAL, "no packed matrix stored");
+    } else {
+        if (!op->Z32) throw Error(BIE_EINVAL, "complex64 vectors need the FP32 matrix");
+        dispatch<float, float>(pk, op->Z32, X, pk.N, Y, pk.N, nullptr, 0, R, nullptr, 1, conj, s, part);
+    }
 }
 
 void grouped_product(bool mat64, const GProb *probs, const GCols &gc, const int32_t *items, int64_t nitems, int G,
