@@ -1,34 +1,43 @@
 """Benchmark: plane-wave EFIE solves per second on one MI355X.
 
-Headline (value): batched mixed precision + learned warm start on the PEC
-sphere of radius 1 m, 5120-triangle icosphere (7680 RWG unknowns), k = 10
-rad/m.  One step serves a batch of 512 held-out plane waves (256 directions
-uniform on the sphere x theta/phi polarisation) with the operator and the
-warm start resident: RHS assembly, warm-start inference (POD basis + MLP, with
-the zero fallback), and block GMRES(50) over groups of 32 right-hand sides (one
-shared block Krylov space per group) with split-BF16 block products on the
-matrix cores and FP64 iterative refinement, to a true FP64 relative residual of
-1e-6 for every right-hand side (--method gmres: column GMRES as a continuous
-batch of 256 slots instead).
-value = right-hand sides per second over the timed steps.
+Headline (value): the learned warm-start workload on the PEC sphere of radius
+1 m, 5120-triangle icosphere (7680 RWG unknowns), k = 10 rad/m.  Training: the
+method solves 2048 directions uniform on the sphere x theta/phi polarisation
+(4096 right-hand sides); a 256-mode POD basis of those solutions and a
+4 -> 512 -> 512 -> 512 network (Re/Im of 256 coefficients) trained 3000 epochs
+on the GPU.  One timed step serves the 1024 held-out right-hand sides (512
+directions x theta/phi) with the operator and the warm start resident: RHS
+assembly, network inference with the zero fallback, and block GMRES(50) over
+groups of 32 right-hand sides (one shared block Krylov space per group) with
+split-BF16 block products on the matrix cores and FP64 iterative refinement, to
+a true FP64 relative residual of 1e-6.
+value = right-hand sides meeting that criterion per second, summed over the
+timed steps.
 
-Beside it, on the same GPU:
-  - plain FP64 GMRES(50) from zero on a sample of the same right-hand sides
-    (matrix resident) -> speedup of the headline over the plain method;
-  - the same batch without the warm start (mixed precision + batching alone);
-  - the plain FP64 whole-path step of one x-polarised plane wave from +z
-    (mesh -> fill -> RHS -> GMRES), with the packed FP64 product against the
-    HBM roofline (roofline_gemv);
-  - training of the warm start (snapshot solves, POD, MLP epochs), timed once;
+Beside it, on the same GPU and right-hand sides:
+  - plain FP64 GMRES(50) from zero, one right-hand side at a time (matrix
+    resident), on a sample -> speedup of the headline over the plain method;
+  - the same batch from zero (mixed precision + batching alone), from the
+    linear-in-polarisation network, and from the POD projection of the
+    solutions (the best any K-mode prediction can do);
+  - forward errors against a direct LU solve of the FP64 matrix, and its
+    1-norm condition number;
+  - the Calderon-preconditioned form of the same batch (own key, setup timed);
+  - the plain FP64 whole path of one x-polarised plane wave from +z, with the
+    packed FP64 product against the HBM roofline (roofline_gemv);
+  - the 30720-unknown sphere at k = 20 with the 512 plane waves of a 16 x 16
+    (theta, phi) grid (key c3; 1 warm-up and 2 timed steps);
+  - the star-split operator at low frequency, the uneven batch of 64 surfaces;
   - the CPU oracle on a bounded sample (cpu_baseline).
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--c5]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-c3]
 """
 from __future__ import annotations
 
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -40,7 +49,6 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
 BF16_PEAK_TFLOPS = 2500.0    # MI355X dense BF16 MFMA
-FP64_VALU_PEAK_TFLOPS = 78.6  # 256 CUs x 4 SIMDs x 16 FP64 lanes x 2 flops (FMA) x 2.4 GHz
 FP32_MFMA_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix
 FP64_MFMA_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix
 METRIC = "GMRES solves/s to 1e-6 residual: batched mixed+learned vs plain FP64; GEMV GB/s"
@@ -56,29 +64,20 @@ def parse():
     ap.add_argument("--k", type=float, default=10.0)
     ap.add_argument("--restart", type=int, default=50)
     ap.add_argument("--tol", type=float, default=1e-6)
-    ap.add_argument("--inner-tol", type=float, default=None,
-                    help="inner tolerance of the refinement; default 1e-3 with the Calderon preconditioner, else 0.1")
-    ap.add_argument("--inner-terms", type=int, default=None, choices=[2, 3],
+    ap.add_argument("--inner-tol", type=float, default=0.1, help="inner tolerance of the refinement")
+    ap.add_argument("--inner-terms", type=int, default=2, choices=[2, 3],
                     help="terms of the inner split-BF16 products: 3 (hi/lo matrix x hi/lo vectors) or 2 (hi/lo "
-                         "matrix x BF16 vectors); default 2 for unpreconditioned block GMRES, else 3")
-    ap.add_argument("--basis", default="f16", choices=["f16", "c64"],
-                    help="storage of the inner Krylov basis (FP16 pairs or complex64)")
-    ap.add_argument("--slots", type=int, default=256)
-    ap.add_argument("--method", default="bgmres", choices=["gmres", "bgmres"],
-                    help="inner solver of the mixed-precision forms: column GMRES as a continuous batch, or "
-                         "block GMRES over groups of --block right-hand sides")
+                         "matrix x BF16 vectors)")
     ap.add_argument("--block", type=int, default=32)
-    ap.add_argument("--no-calderon", dest="calderon", action="store_false",
-                    help="headline without the multiplicative Calderon preconditioner (block GMRES only uses it)")
-    ap.add_argument("--train-dirs", type=int, default=512)
-    ap.add_argument("--test-dirs", type=int, default=256)
-    ap.add_argument("--epochs", type=int, default=1500)
+    ap.add_argument("--train-dirs", type=int, default=2048)
+    ap.add_argument("--test-dirs", type=int, default=512)
+    ap.add_argument("--epochs", type=int, default=3000)
+    ap.add_argument("--pod-rank", type=int, default=256)
+    ap.add_argument("--hidden", type=int, default=512)
     ap.add_argument("--plain-sample", type=int, default=8)
-    ap.add_argument("--c5", action="store_true",
-                    help="full learned warm-start configuration: 2048 training / 512 test directions, 3000 epochs")
-    ap.add_argument("--c3", action="store_true",
-                    help="large-sphere workload instead: 30720 unknowns, k=20, the 512 plane waves of a 16x16 "
-                         "(theta, phi) grid x theta/phi, split-BF16 block GMRES with FP64 refinement")
+    ap.add_argument("--no-calderon", dest="calderon", action="store_false",
+                    help="skip the Calderon-preconditioned legs")
+    ap.add_argument("--no-c3", dest="c3", action="store_false", help="skip the 30720-unknown sphere leg")
     ap.add_argument("--no-batch", dest="batch", action="store_false",
                     help="skip the uneven batch of 64 surfaces (batched solves over many operators)")
     ap.add_argument("--no-star", dest="star", action="store_false",
@@ -86,15 +85,7 @@ def parse():
     ap.add_argument("--counters", action="store_true",
                     help="only launch the dense product kernels a few times at the bench sizes, and a 1 GiB "
                          "device copy as calibration, for hardware-counter runs")
-    a = ap.parse_args()
-    cal = a.calderon and a.method == "bgmres" and not a.c3
-    if a.inner_terms is None:   # 2 terms only pay with long unpreconditioned inner solves
-        a.inner_terms = 2 if (a.method == "bgmres" and not cal) else 3
-    if a.inner_tol is None:   # the preconditioned inner solves are short: a tighter tolerance saves outer cycles
-        a.inner_tol = 1e-3 if cal else 0.1
-    if a.c5:
-        a.train_dirs, a.test_dirs, a.epochs = 2048, 512, 3000
-    return a
+    return ap.parse_args()
 
 
 def source_hash(name: str) -> str:
@@ -121,23 +112,12 @@ def traffic_from_profiles(fname: str, kernel_src: str, N: int):
         return None
 
 
-def solver_text(args, restart, calderon=False):
-    if args.method == "bgmres":
-        pre = "Calderon-preconditioned (right, M = -G^-1 T_BC G^-T) " if calderon else ""
-        return f"{pre}block GMRES({restart}) over groups of {args.block} right-hand sides"
-    return (f"GMRES({restart}), {'FP16' if args.basis == 'f16' else 'complex64'} inner Krylov basis, continuous "
-            f"batch of {args.slots} slots")
-
-
-def mixed_opts(args, bie, restart, pc=None):
-    """Options of the mixed-precision solves: column GMRES as a continuous batch
-    (FP16 or complex64 basis), or block GMRES (complex64 basis, all right-hand
-    sides at once; right-preconditioned by pc when given)."""
-    if args.method == "bgmres":
-        return bie.Solve(method="bgmres", block=args.block, restart=restart, tol=args.tol, max_mvp=20000,
-                         precision="mixed", inner_tol=args.inner_tol, inner_terms=args.inner_terms, calderon=pc)
-    return bie.Solve(restart=restart, tol=args.tol, max_mvp=20000, precision="mixed", inner_tol=args.inner_tol,
-                     slots=args.slots, inner_terms=args.inner_terms, basis=args.basis)
+def mixed_opts(args, bie, restart, pc=None, inner_tol=None, terms=None):
+    """Block GMRES over groups of --block right-hand sides on split-BF16 products
+    with FP64 refinement (right-preconditioned by pc when given)."""
+    return bie.Solve(method="bgmres", block=args.block, restart=restart, tol=args.tol, max_mvp=20000,
+                     precision="mixed", inner_tol=args.inner_tol if inner_tol is None else inner_tol,
+                     inner_terms=args.inner_terms if terms is None else terms, calderon=pc)
 
 
 def planewave_batch(bie, inc):
@@ -150,11 +130,24 @@ def planewave_batch(bie, inc):
     return dirs, pols, bie.features(dirs, flags)
 
 
+def stats_of(st):
+    conv = np.array([s["converged"] for s in st], bool)
+    its = np.array([s["iters"] for s in st])
+    rel = np.array([s["relres_true"] for s in st])
+    return conv, its, rel
+
+
+def relres(torch, op, B, X):
+    """FP64 relative residuals ||b - T x|| / ||b|| (packed FP64 product)."""
+    return (torch.linalg.vector_norm(B - op.apply(X), dim=1) / torch.linalg.vector_norm(B, dim=1)).cpu().numpy()
+
+
 def plain_leg(args, bie, torch, V, T, k):
     """Plain FP64 whole path for one x-polarised plane wave from +z."""
     from paper_2606_13482_amd.inputs import planewave_set
     d, e = planewave_set(np.array([[0.0, 0.0, 1.0]]), "theta")
     opts = bie.Solve(restart=args.restart, tol=args.tol, max_mvp=20000)
+    steps = max(1, min(args.steps, 10))
 
     def step():
         op = bie.Operator(V, T, k)
@@ -162,7 +155,7 @@ def plain_leg(args, bie, torch, V, T, k):
         X, st = op.solve(B, opts)
         return op, B, X, st
 
-    for _ in range(args.warmup):
+    for _ in range(min(args.warmup, 2)):
         step()[0].close()
     torch.cuda.synchronize()
     bie.prof_read(0)
@@ -170,10 +163,10 @@ def plain_leg(args, bie, torch, V, T, k):
     bie.prof_enable(True)
     t0 = time.perf_counter()
     stats = []
-    for i in range(args.steps):
+    for i in range(steps):
         op, B, X, st = step()
         stats.append(st[0])
-        if i != args.steps - 1:
+        if i != steps - 1:
             op.close()
     torch.cuda.synchronize()
     t_steps = time.perf_counter() - t0
@@ -181,12 +174,7 @@ def plain_leg(args, bie, torch, V, T, k):
     r_launches, red_ms = bie.prof_read(3)     # reduction of its partial sums
     bie.prof_enable(False)
     N = op.N
-    relres = float(torch.linalg.vector_norm(B - op.apply(X)) / torch.linalg.vector_norm(B))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    op.solve(B, opts)
-    torch.cuda.synchronize()
-    t_solve = time.perf_counter() - t0
+    rr = float(relres(torch, op, B, X)[0])
     op.close()
     t0 = time.perf_counter()
     bie.Operator(V, T, k).close()
@@ -211,18 +199,79 @@ def plain_leg(args, bie, torch, V, T, k):
             "reduce_avg_us": round(red_avg_ms * 1e3, 2),
             "product_frac_with_reduce": round(alg_bytes / ((avg_ms + red_avg_ms) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "dense_equivalent_bytes_per_launch": N * N * 16}
-    ms_step = 1e3 * t_steps / args.steps
+    ms_step = 1e3 * t_steps / steps
     out = {"workload": f"PEC sphere, {T.shape[0]} triangles ({N} RWG), k={k:g}, 1 plane wave (x-pol, from +z), "
                        f"FP64 fill + GMRES({args.restart}) to {args.tol:g} (SCC)",
-           "solves_per_s": round(1e3 / ms_step, 4), "ms_per_step": round(ms_step, 3),
-           "iters": int(stats[-1]["iters"]), "mvps": int(stats[-1]["mvps"]), "relres_true_fp64": relres,
-           "converged": bool(stats[-1]["converged"]), "solve_only_s": round(t_solve, 4),
-           "fill_fp64_s": round(t_fill64, 4), "fill_fp32_s": round(t_fill32, 4),
-           "gemv_share_of_step": round((gemv_ms + red_ms) / (t_steps * 1e3), 3)}
+           "solves_per_s": round(1e3 / ms_step, 4), "ms_per_step": round(ms_step, 3), "steps": steps,
+           "iters": int(stats[-1]["iters"]), "mvps": int(stats[-1]["mvps"]), "relres_true_fp64": rr,
+           "converged": bool(stats[-1]["converged"]), "fill_fp64_s": round(t_fill64, 4),
+           "fill_fp32_s": round(t_fill32, 4), "gemv_share_of_step": round((gemv_ms + red_ms) / (t_steps * 1e3), 3)}
     return out, roof
 
 
+def block_rooflines(bie, N, terms, t_ms, g, f, orth):
+    """Rooflines of the block-solver kernels from the live HIP-event records:
+    the split-BF16 product (BF16 peak, algorithmic flops), the FP64 product of
+    the refinement residuals (FP64 matrix peak) and the two block-GMRES
+    orthogonalisation kernels (FP32 matrix peak); sorted by total time."""
+    cands = []
+    g_launch, g_ms, g_cols = g
+    if g_launch:
+        avg = g_ms / g_launch
+        alg = 8.0 * N * N * g_cols / g_launch   # complex product: 8 real flops per entry and column
+        ach = alg / (avg * 1e-3) / 1e12
+        cands.append((g_ms, {"bound": "mfma", "achieved": round(ach, 1), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                             "frac": round(ach / BF16_PEAK_TFLOPS, 4),
+                             "traffic": traffic_from_profiles("gemm_split_bf16_n7680_r512_counters.txt", "gemm.hip",
+                                                              N),
+                             "traffic_note": "HBM bytes per launch at 512 columns (counters), null if the kernel "
+                                             "changed since or another size",
+                             "kernel": "split-BF16 complex block product (k_gemm_split, v_mfma_f32_32x32x16_bf16)",
+                             "alg_flops_per_launch": alg, "terms": terms, "issued_tflops": round(terms * ach, 1),
+                             "issued_frac": round(terms * ach / BF16_PEAK_TFLOPS, 4),
+                             "avg_columns_per_launch": round(g_cols / g_launch, 1),
+                             "avg_launch_us": round(avg * 1e3, 2), "launches": g_launch,
+                             "share_of_step": round(g_ms / t_ms, 3)}))
+    f_launch, f_ms, f_cols = f
+    if f_launch:
+        avg = f_ms / f_launch
+        alg = 8.0 * N * N * f_cols / f_launch
+        ach = alg / (avg * 1e-3) / 1e12
+        cands.append((f_ms, {"bound": "mfma", "achieved": round(ach, 1), "peak": FP64_MFMA_PEAK_TFLOPS,
+                             "unit": "TFLOP/s", "frac": round(ach / FP64_MFMA_PEAK_TFLOPS, 4),
+                             "traffic": traffic_from_profiles("gemm64_fp64_n7680_r512_counters.txt", "gemm.hip", N),
+                             "traffic_note": "HBM bytes per launch at 512 columns (counters), null if the kernel "
+                                             "changed since or another size",
+                             "kernel": "FP64 complex block product of the refinement residuals (k_gemm64, "
+                                       "v_mfma_f64_16x16x4f64)",
+                             "alg_flops_per_launch": alg, "avg_columns_per_launch": round(f_cols / f_launch, 1),
+                             "avg_launch_us": round(avg * 1e3, 2), "launches": f_launch,
+                             "share_of_step": round(f_ms / t_ms, 3)}))
+    names = {4: "block GMRES basis dots V^H W (k_bdots_mf + k_bdots_fin, v_mfma_f32_32x32x2f32)",
+             5: "block GMRES basis update W -= V C (k_bcomb_mf, v_mfma_f32_32x32x2f32)"}
+    for kk, (n_l, ms, pairs) in orth.items():
+        if n_l == 0:
+            continue
+        avg = ms / n_l
+        alg = 8.0 * N * pairs / n_l
+        ach = alg / (avg * 1e-3) / 1e12
+        cands.append((ms, {"bound": "mfma", "achieved": round(ach, 2), "peak": FP32_MFMA_PEAK_TFLOPS,
+                           "unit": "TFLOP/s", "frac": round(ach / FP32_MFMA_PEAK_TFLOPS, 4), "traffic": None,
+                           "traffic_note": "no counter summary for this kernel",
+                           "kernel": names[kk], "alg_flops_per_launch": alg,
+                           "avg_launch_us": round(avg * 1e3, 2), "launches": n_l,
+                           "share_of_step": round(ms / t_ms, 3)}))
+    cands.sort(key=lambda c: -c[0])
+    return [c[1] for c in cands]
+
+
+def prof_reset(bie):
+    for kk in (0, 1, 2, 3, 4, 5):
+        bie.prof_read(kk)
+
+
 def headline_leg(args, bie, torch, V, T, k):
+    """The learned warm-start workload (see the module docstring)."""
     from paper_2606_13482_amd.inputs import random_directions
     sync = torch.cuda.synchronize
     res = {}
@@ -231,191 +280,209 @@ def headline_leg(args, bie, torch, V, T, k):
     sync()
     res["setup_fill_split_s"] = round(time.perf_counter() - t0, 4)
     N = op.N
-    pc = None
-    if args.calderon and args.method == "bgmres":
-        t0 = time.perf_counter()
-        pc = bie.Calderon(op)
-        sync()
-        res["setup_calderon_s"] = round(time.perf_counter() - t0, 4)
-        ci = pc.info()
-        res["calderon"] = {"refined_unknowns": ci["Nb"], "bc_nonzeros": ci["nnz_bc"], "gram_nonzeros": ci["nnz_gram"],
-                           "gram_cg_iters": ci["cg_iters"], "gram_cg_relres": max(ci["cg_relres"])}
-    mopts = mixed_opts(args, bie, args.restart, pc)
+    mopts = mixed_opts(args, bie, args.restart)
     popts = bie.Solve(restart=args.restart, tol=args.tol, max_mvp=20000)
 
-    # training: solutions the method computes, then POD + MLP on the GPU
+    # training: solutions the method computes, then POD + network on the GPU
     dtr, ptr, ftr = planewave_batch(bie, random_directions(args.train_dirs, 5))
     t0 = time.perf_counter()
     Btr = op.rhs(dtr, ptr)
     Xtr, sttr = op.solve(Btr, mopts)
     sync()
     t_snap = time.perf_counter() - t0
-    K = min(256, Xtr.shape[0])
-    t0 = time.perf_counter()
-    ws = bie.WarmStart.train(op, ftr, Xtr, pod_rank=K, hidden=512, epochs=args.epochs, batch=256,
-                             pols=ptr, pol_model=1)
-    sync()
-    t_train = time.perf_counter() - t0
-    res["training"] = {"snapshots": int(Xtr.shape[0]), "snapshot_solve_s": round(t_snap, 3),
-                       "snapshots_converged": float(np.mean([s["converged"] for s in sttr])),
-                       "pod_rank": K, "hidden": 512, "epochs": args.epochs, "train_s": round(t_train, 3),
-                       "final_loss": ws.final_loss, "model": "linear in the polarisation (inputs d; 3 x 2K outputs)"}
-    del Xtr, Btr
+    K = min(args.pod_rank, Xtr.shape[0])
+    train = {"snapshots": int(Xtr.shape[0]), "snapshot_solve_s": round(t_snap, 3),
+             "snapshots_converged": float(np.mean([s["converged"] for s in sttr])), "pod_rank": K,
+             "hidden": args.hidden, "epochs": args.epochs, "batch": 256}
+    wss = {}
+    for pm, name in ((0, "network"), (1, "linear_pol")):
+        t0 = time.perf_counter()
+        wss[pm] = bie.WarmStart.train(op, ftr, Xtr, pod_rank=K, hidden=args.hidden, epochs=args.epochs, batch=256,
+                                      pols=ptr if pm else None, pol_model=pm)
+        sync()
+        train[name] = {"train_s": round(time.perf_counter() - t0, 3), "final_loss": wss[pm].final_loss,
+                       "outputs": wss[pm].outputs,
+                       "model": ("inputs (d, s), 4 -> %d -> %d -> %d: Re/Im of %d coefficients" %
+                                 (args.hidden, args.hidden, 2 * K, K)) if pm == 0 else
+                                ("linear in the polarisation: input d, 4 -> %d -> %d -> %d (three coefficient "
+                                 "sets combined with e)" % (args.hidden, args.hidden, 6 * K))}
+    res["training"] = train
+    del Btr
+    sigma = wss[0].sigma()
+    snap_norm2 = float(torch.sum(torch.abs(Xtr) ** 2))
+    res["training"]["pod_captured_energy"] = float(np.sum(sigma ** 2) / snap_norm2)
+    del Xtr
+    ws = wss[0]
 
     dte, pte, fte = planewave_batch(bie, random_directions(args.test_dirs, 55))
     R = dte.shape[0]
 
     def step():
         B = op.rhs(dte, pte)
-        X0, _ = ws.predict(fte, None, pols=pte)
-        X, st = op.solve(B, mopts, x0=X0, x0_fallback=True)   # the fallback uses the solver's first FP64 residual
-        return B, X, X0, np.array([s["x0_kept"] for s in st], bool), st
+        X0, _ = ws.predict(fte)
+        X, st = op.solve(B, mopts, x0=X0, x0_fallback=True)   # the fallback uses the solver's first residual
+        return B, X, X0, st
 
     for _ in range(args.warmup):
         step()
     sync()
-    for k in (0, 1, 2, 4, 5):
-        bie.prof_read(k)
+    prof_reset(bie)
     bie.prof_enable(True)
+    n_conv, n_rhs, iters_all, kept_all = 0, 0, [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        B, X, X0, used, st = step()
+        B, X, X0, st = step()
+        conv, its, _ = stats_of(st)
+        n_conv += int(conv.sum())
+        n_rhs += len(st)
+        iters_all.append(its)
+        kept_all.append([s["x0_kept"] for s in st])
     sync()
     t_steps = time.perf_counter() - t0
-    g_launch, g_ms, g_cols = bie.prof_read(1, columns=True)
-    f_launch, f_ms, f_cols = bie.prof_read(2, columns=True)
-    p_launch, p_ms = bie.prof_read(0)
-    orth = {k: bie.prof_read(k, columns=True) for k in (4, 5)}
+    g = bie.prof_read(1, columns=True)
+    f = bie.prof_read(2, columns=True)
+    orth = {kk: bie.prof_read(kk, columns=True) for kk in (4, 5)}
     bie.prof_enable(False)
     ms_step = 1e3 * t_steps / args.steps
-    conv = np.array([s["converged"] for s in st], bool)
-    relres = np.array([s["relres_true"] for s in st])
-    iters_w = np.array([s["iters"] for s in st])
-    r0 = (torch.linalg.vector_norm(B - op.apply(X0), dim=1) / torch.linalg.vector_norm(B, dim=1)).cpu().numpy()
-    # independent FP64 residual of the returned solutions
-    rchk = (torch.linalg.vector_norm(B - op.apply(X), dim=1) / torch.linalg.vector_norm(B, dim=1)).cpu().numpy()
+    value = n_conv / t_steps
+    its_w = np.concatenate(iters_all)
+    rchk = relres(torch, op, B, X)            # independent FP64 residual of the last step's solutions
+    r0 = relres(torch, op, B, X0)
+    _, _, rel_last = stats_of(st)
 
-    # the same batch without the warm start
-    sync()
-    t0 = time.perf_counter()
-    Xz, stz = op.solve(B, mopts)
-    sync()
-    t_zero = time.perf_counter() - t0
-    iters_z = np.array([s["iters"] for s in stz])
+    def timed_solve(x0=None, fallback=True):
+        sync()
+        t0 = time.perf_counter()
+        Xs, sts = op.solve(B, mopts, x0=x0, x0_fallback=fallback)
+        sync()
+        dt = time.perf_counter() - t0
+        cv, it, _ = stats_of(sts)
+        return Xs, {"solves_per_s": round(int(cv.sum()) / dt, 3), "converged": float(cv.mean()),
+                    "iters_mean": float(it.mean()), "iters_max": int(it.max())}
+
+    # the same batch from zero, from the linear-in-polarisation network, and from
+    # the POD projection of the solutions (the best a K-mode prediction can do)
+    Xz, zero = timed_solve()
+    X1, _ = wss[1].predict(fte, pols=pte)
+    r1 = relres(torch, op, B, X1)
+    _, lin = timed_solve(X1)
+    lin["initial_relres_median"] = float(np.median(r1))
+    wss[1].close()
+    U = ws.basis()                                        # K x N
+    Xp = (X @ U.conj().T) @ U                              # rows: U U^H x*
+    proj_err = (torch.linalg.vector_norm(X - Xp, dim=1) / torch.linalg.vector_norm(X, dim=1)).cpu().numpy()
+    rp = relres(torch, op, B, Xp)
+    _, proj = timed_solve(Xp)
+    proj.update({"projection_error_median": float(np.median(proj_err)), "initial_relres_median": float(np.median(rp))})
+    del U, Xp, X1
 
     # plain FP64 GMRES from zero on a sample of the batch, one right-hand side at a time
     ns = min(args.plain_sample, R)
     idx = np.linspace(0, R - 1, ns).round().astype(int)
-    Xp, itp = [], []
+    Xpl, itp = [], []
     sync()
     t0 = time.perf_counter()
     for i in idx:
         x, s = op.solve(B[i:i + 1], popts)
-        Xp.append(x)
-        itp.append((s[0]["iters"], s[0]["mvps"]))
+        Xpl.append(x)
+        itp.append((s[0]["iters"], s[0]["mvps"], s[0]["converged"]))
     sync()
     t_plain = (time.perf_counter() - t0) / ns
-    Xp = torch.cat(Xp)
-    # the paper's preconditioned method in plain FP64 (column GMRES on T M u = b) on the same sample
-    plain_cal = None
-    if pc is not None:
-        copts = bie.Solve(restart=args.restart, tol=args.tol, max_mvp=20000, calderon=pc)
-        itc = []
-        sync()
-        t0 = time.perf_counter()
-        for i in idx:
-            _, s = op.solve(B[i:i + 1], copts)
-            itc.append(s[0]["iters"])
-        sync()
-        t_cal = (time.perf_counter() - t0) / ns
-        plain_cal = {"rhs": int(ns), "solves_per_s": round(1.0 / t_cal, 4), "iters_mean": float(np.mean(itc))}
-    # a tight FP64 solution of the sample for the forward errors
-    Xt, _ = op.solve(B[idx], bie.Solve(restart=args.restart, tol=1e-10, max_mvp=40000))
-    nt = torch.linalg.vector_norm(Xt, dim=1)
-    fwd = lambda Y: float((torch.linalg.vector_norm(Y - Xt, dim=1) / nt).max())
+    Xpl = torch.cat(Xpl)
+    plain_rate = sum(c for _, _, c in itp) / (t_plain * ns)
 
-    value = R / (ms_step * 1e-3)
-    plain_rate = 1.0 / t_plain
+    # forward errors against a direct LU solve of the FP64 matrix; its 1-norm condition number
+    Zd = op.matrix()
+    Xlu = torch.linalg.solve(Zd, B[idx].T).T.contiguous()
+    kappa1 = float(torch.linalg.matrix_norm(Zd, ord=1) * torch.linalg.matrix_norm(torch.linalg.inv(Zd), ord=1))
+    del Zd
+    nlu = torch.linalg.vector_norm(Xlu, dim=1)
+    fwd = lambda Y: float((torch.linalg.vector_norm(Y - Xlu, dim=1) / nlu).max())
+
     res.update({
         "rhs_per_step": R,
         "solves_per_s": round(value, 3),
-        "converged": float(conv.mean()),
-        "relres_true_fp64_max": float(relres.max()),
+        "converged": n_conv / max(1, n_rhs),
+        "relres_true_fp64_max": float(rel_last.max()),
         "relres_recomputed_fp64_max": float(rchk.max()),
-        "iters_mean": float(iters_w.mean()), "iters_max": int(iters_w.max()),
-        "warm_start": {"kept": float(used.mean()), "initial_relres_median": float(np.median(r0)),
+        "iters_mean": float(its_w.mean()), "iters_max": int(its_w.max()),
+        "warm_start": {"kept": float(np.mean(np.concatenate(kept_all))), "initial_relres_median": float(np.median(r0)),
                        "initial_relres_max": float(r0.max())},
-        "no_warm_start": {"solves_per_s": round(R / t_zero, 3), "iters_mean": float(iters_z.mean()),
-                          "iters_max": int(iters_z.max())},
+        "no_warm_start": zero,
+        "linear_pol_warm_start": lin,
+        "pod_projection_start": proj,
         "plain_fp64_sample": {"rhs": int(ns), "solves_per_s": round(plain_rate, 4),
-                              "iters_mean": float(np.mean([a for a, _ in itp]))},
+                              "iters_mean": float(np.mean([a for a, _, _ in itp]))},
         "speedup_vs_plain_fp64": round(value / plain_rate, 2),
-        "plain_fp64_calderon_sample": plain_cal,
-        "speedup_vs_plain_fp64_calderon": None if plain_cal is None else round(value / plain_cal["solves_per_s"], 2),
-        "speedup_no_warm_start_vs_plain_fp64": round((R / t_zero) / plain_rate, 2),
-        "forward_error_vs_tight_fp64": {"plain_fp64": fwd(Xp), "mixed_learned": fwd(X[idx]),
-                                        "mixed_zero": fwd(Xz[idx]), "reference": "FP64 GMRES to 1e-10 on the sample"},
-        "packed_fp64_share_of_step": round(p_ms / (t_steps * 1e3), 3),
+        "speedup_no_warm_start_vs_plain_fp64": round(zero["solves_per_s"] / plain_rate, 2),
+        "forward_error_vs_lu": {"plain_fp64": fwd(Xpl), "mixed_learned": fwd(X[idx]), "mixed_zero": fwd(Xz[idx]),
+                                "reference": "direct LU (torch.linalg.solve, FP64) of the operator's FP64 matrix on "
+                                             "the sample", "kappa1": kappa1},
     })
-    avg = g_ms / max(1, g_launch)
-    alg_flops = 8.0 * N * N * g_cols / max(1, g_launch)   # per launch: complex product, 8 real flops per entry and column
-    achieved = alg_flops / (avg * 1e-3) / 1e12
-    roof = {"bound": "mfma", "achieved": round(achieved, 1), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / BF16_PEAK_TFLOPS, 4),
-            "traffic": traffic_from_profiles("gemm_split_bf16_n7680_r512_counters.txt", "gemm.hip", N),
-            "traffic_note": "HBM bytes per launch at 512 columns (counters), null if the kernel changed since",
-            "kernel": "split-BF16 complex block product (k_gemm_split, v_mfma_f32_32x32x16_bf16)",
-            "alg_flops_per_launch": alg_flops, "issued_tflops": round(3 * achieved, 1),
-            "avg_columns_per_launch": round(g_cols / max(1, g_launch), 1),
-            "avg_launch_us": round(avg * 1e3, 2), "launches": g_launch,
-            "gemm_share_of_step": round(g_ms / (t_steps * 1e3), 3)}
-    # block GMRES orthogonalisation (first pass): dots V^H W and update W -= V C
-    # on the complex64 basis of the refinement's inner solves, FP32 matrix cores;
-    # 8 real flops per row for every basis vector x column pair
-    cands = [(g_ms, roof)]
-    # the refinement's FP64 residuals B - T X (FP64 matrix cores, 8 N^2 flops per column)
-    if f_launch:
-        avg_f = f_ms / f_launch
-        alg_f = 8.0 * N * N * f_cols / f_launch
-        ach_f = alg_f / (avg_f * 1e-3) / 1e12
-        cands.append((f_ms, {"bound": "mfma", "achieved": round(ach_f, 1), "peak": FP64_MFMA_PEAK_TFLOPS,
-                             "unit": "TFLOP/s", "frac": round(ach_f / FP64_MFMA_PEAK_TFLOPS, 4),
-                             "traffic": traffic_from_profiles("gemm64_fp64_n7680_r512_counters.txt", "gemm.hip", N),
-                             "traffic_note": "HBM bytes per launch at 512 columns (counters), null if the kernel "
-                                             "changed since",
-                             "kernel": "FP64 complex block product of the refinement residuals (k_gemm64, "
-                                       "v_mfma_f64_16x16x4f64)",
-                             "alg_flops_per_launch": alg_f, "avg_columns_per_launch": round(f_cols / f_launch, 1),
-                             "avg_launch_us": round(avg_f * 1e3, 2), "launches": f_launch,
-                             "share_of_step": round(f_ms / (t_steps * 1e3), 3)}))
-    names = {4: "block GMRES basis dots V^H W (k_bdots_mf + k_bdots_fin, v_mfma_f32_32x32x2f32)",
-             5: "block GMRES basis update W -= V C (k_bcomb_mf, v_mfma_f32_32x32x2f32)"}
-    for k, (n_l, ms, pairs) in orth.items():
-        if n_l == 0:
-            continue
-        avg_o = ms / n_l
-        alg_o = 8.0 * N * pairs / n_l
-        ach_o = alg_o / (avg_o * 1e-3) / 1e12
-        cands.append((ms, {"bound": "mfma", "achieved": round(ach_o, 2), "peak": FP32_MFMA_PEAK_TFLOPS,
-                           "unit": "TFLOP/s", "frac": round(ach_o / FP32_MFMA_PEAK_TFLOPS, 4), "traffic": None,
-                           "traffic_note": "no counter summary for this kernel",
-                           "kernel": names[k], "alg_flops_per_launch": alg_o,
-                           "avg_launch_us": round(avg_o * 1e3, 2), "launches": n_l,
-                           "share_of_step": round(ms / (t_steps * 1e3), 3)}))
-    cands.sort(key=lambda c: -c[0])
-    res["kernel_rooflines"] = [c[1] for c in cands]
-    if pc is not None:
-        pc.close()
-    op.close()
-    return res, cands[0][1], ms_step, float(np.mean([b for _, b in itp])), int(ns)
+    kr = block_rooflines(bie, N, args.inner_terms, t_steps * 1e3, g, f, orth)
+    res["kernel_rooflines"] = kr
+    plain_mvps = float(np.mean([b for _, b, _ in itp]))
+    return op, ws, res, kr[0], ms_step, plain_mvps, (B, fte, idx, popts)
 
 
-def c3_run(args, bie, torch):
-    """Large sphere: 20480-triangle icosphere (30720 RWG), k = 20, 512 plane waves
-    (16 x 16 (theta, phi) grid x theta/phi) per step, operator resident; GMRES(30)
-    with split-BF16 block products and FP64 refinement (block GMRES over groups of
-    --block right-hand sides, or column GMRES as a continuous batch of --slots) to
-    FP64 SCC 1e-6; plain FP64 GMRES(30) on a sample of the same waves."""
+def calderon_leg(args, bie, torch, op, ws, batch):
+    """The same held-out batch with the multiplicative Calderon preconditioner:
+    right-preconditioned mixed block GMRES (T M products split to BF16, 3 terms,
+    inner tolerance 1e-3, FP64 refinement) from the network's prediction; setup
+    timed; the preconditioned plain FP64 column GMRES on the sample."""
+    B, fte, idx, popts = batch
+    sync = torch.cuda.synchronize
+    R = B.shape[0]
+    t0 = time.perf_counter()
+    pc = bie.Calderon(op)
+    sync()
+    t_setup = time.perf_counter() - t0
+    ci = pc.info()
+    copts = mixed_opts(args, bie, args.restart, pc=pc, inner_tol=1e-3, terms=3)
+    X0, _ = ws.predict(fte)
+    op.solve(B, copts, x0=X0, x0_fallback=True)
+    reps = 3
+    n_conv, its = 0, []
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        X0, _ = ws.predict(fte)
+        X, st = op.solve(B, copts, x0=X0, x0_fallback=True)
+        conv, it, _ = stats_of(st)
+        n_conv += int(conv.sum())
+        its.append(it)
+    sync()
+    t_solve = (time.perf_counter() - t0) / reps
+    rr = relres(torch, op, B, X)
+    itc = []
+    cpl = bie.Solve(restart=args.restart, tol=args.tol, max_mvp=20000, calderon=pc)
+    sync()
+    t0 = time.perf_counter()
+    for i in idx:
+        _, s = op.solve(B[i:i + 1], cpl)
+        itc.append(s[0]["iters"])
+    sync()
+    t_cal = (time.perf_counter() - t0) / len(idx)
+    pc.close()
+    its = np.concatenate(its)
+    rate = n_conv / reps / t_solve
+    return {"workload": f"the headline's {R} held-out right-hand sides, right-preconditioned by "
+                        "M = -G^-1 T_BC G^-T (Buffa-Christiansen functions on the barycentric refinement)",
+            "setup_s": round(t_setup, 3), "refined_unknowns": ci["Nb"], "gram_iters": ci["cg_iters"],
+            "gram_relres": max(ci["cg_relres"]), "solves_per_s": round(rate, 2),
+            "solves_per_s_with_setup": round(n_conv / reps / (t_solve + t_setup), 2),
+            "converged": n_conv / reps / R, "relres_recomputed_fp64_max": float(rr.max()),
+            "iters_mean": float(its.mean()), "iters_max": int(its.max()),
+            "plain_fp64_calderon_sample": {"rhs": len(idx), "solves_per_s": round(1.0 / t_cal, 3),
+                                           "iters_mean": float(np.mean(itc))}}
+
+
+def c3_leg(args, bie, torch):
+    """Large sphere: 20480-triangle icosphere (30720 RWG), k = 20, the 512 plane
+    waves of a 16 x 16 (theta, phi) grid x theta/phi per step, operator resident;
+    block GMRES(30) over groups of 32 with 2-term split-BF16 block products and
+    FP64 refinement to FP64 SCC 1e-6; 1 warm-up and 2 timed steps; plain FP64
+    GMRES(30) on 2 of the waves."""
     from paper_2606_13482_amd.inputs import grid_planewaves, icosphere
     sync = torch.cuda.synchronize
     V, T = icosphere(5)
@@ -427,31 +494,34 @@ def c3_run(args, bie, torch):
     N = op.N
     dirs, pols = grid_planewaves(16, 16)
     R = dirs.shape[0]
-    mopts = mixed_opts(args, bie, 30)
+    mopts = mixed_opts(args, bie, 30, terms=2)
 
     def step():
         B = op.rhs(dirs, pols)
         X, st = op.solve(B, mopts)
         return B, X, st
 
-    for _ in range(args.warmup):
-        step()
+    step()
     sync()
-    bie.prof_read(1)
+    prof_reset(bie)
     bie.prof_enable(True)
+    steps, n_conv, its = 2, 0, []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         B, X, st = step()
+        conv, it, _ = stats_of(st)
+        n_conv += int(conv.sum())
+        its.append(it)
     sync()
     t_steps = time.perf_counter() - t0
-    g_launch, g_ms, g_cols = bie.prof_read(1, columns=True)
+    g = bie.prof_read(1, columns=True)
+    f = bie.prof_read(2, columns=True)
+    orth = {kk: bie.prof_read(kk, columns=True) for kk in (4, 5)}
     bie.prof_enable(False)
-    ms_step = 1e3 * t_steps / args.steps
-    its = np.array([s["iters"] for s in st])
-    conv = np.array([s["converged"] for s in st], bool)
+    rr = relres(torch, op, B, X)
+    popts = bie.Solve(restart=30, tol=args.tol, max_mvp=20000)
     ns = 2
     idx = np.linspace(0, R - 1, ns).round().astype(int)
-    popts = bie.Solve(restart=30, tol=args.tol, max_mvp=20000)
     sync()
     t0 = time.perf_counter()
     itp = []
@@ -460,35 +530,72 @@ def c3_run(args, bie, torch):
         itp.append(s[0]["iters"])
     sync()
     t_plain = (time.perf_counter() - t0) / ns
-    avg = g_ms / max(1, g_launch)
-    alg = 8.0 * N * N * g_cols / max(1, g_launch)
-    ach = alg / (avg * 1e-3) / 1e12
-    value = R / (ms_step * 1e-3)
-    out = {
-        "metric": METRIC, "value": round(value, 3), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "split-bf16 products (f32 accumulate) + f64 refinement", "data": "synthetic",
-        "config": {"workload": (f"PEC sphere r=1 m, icosphere {T.shape[0]} triangles ({N} RWG), k={k:g}; {R} plane "
-                                f"waves (16x16 theta/phi grid x theta/phi) per step, operator resident; "
-                                f"{solver_text(args, 30)} on split-BF16 MFMA products with FP64 refinement to "
-                                f"{args.tol:g} (FP64 SCC)"),
-                   "N": N, "k": k, "restart": 30, "inner_tol": args.inner_tol, "method": args.method,
-                   "block": args.block if args.method == "bgmres" else None,
-                   "slots": args.slots if args.method == "gmres" else None,
-                   "rhs_per_step": R, "parallelism": "single GPU"},
-        "roofline": {"bound": "mfma", "achieved": round(ach, 1), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(ach / BF16_PEAK_TFLOPS, 4), "traffic": None,
-                     "kernel": "split-BF16 complex block product (k_gemm_split)", "alg_flops_per_launch": alg,
-                     "issued_tflops": round(3 * ach, 1), "avg_columns_per_launch": round(g_cols / max(1, g_launch), 1),
-                     "avg_launch_us": round(avg * 1e3, 2), "launches": g_launch,
-                     "gemm_share_of_step": round(g_ms / (t_steps * 1e3), 3)},
-        "c3": {"fill_and_split_s": round(t_fill, 3), "converged": float(conv.mean()),
-               "relres_true_fp64_max": float(max(s["relres_true"] for s in st)), "iters_mean": float(its.mean()),
-               "iters_max": int(its.max()), "plain_fp64_sample": {"rhs": ns, "solves_per_s": round(1.0 / t_plain, 4),
-                                                                  "iters": itp},
-               "speedup_vs_plain_fp64": round(value * t_plain, 2)},
-    }
     op.close()
+    its = np.concatenate(its)
+    value = n_conv / t_steps
+    kr = block_rooflines(bie, N, 2, t_steps * 1e3, g, f, orth)
+    return {"workload": (f"PEC sphere r=1 m, icosphere {T.shape[0]} triangles ({N} RWG), k={k:g}; {R} plane waves "
+                         f"(16x16 theta/phi grid x theta/phi) per step, operator resident; block GMRES(30) over groups "
+                         f"of {args.block} on 2-term split-BF16 MFMA products with FP64 refinement to {args.tol:g} "
+                         f"(FP64 SCC)"),
+            "steps": steps, "warmup": 1, "ms_per_step": round(1e3 * t_steps / steps, 3),
+            "solves_per_s": round(value, 3), "fill_and_split_s": round(t_fill, 3), "converged": n_conv / (steps * R),
+            "relres_recomputed_fp64_max": float(rr.max()), "iters_mean": float(its.mean()),
+            "iters_max": int(its.max()),
+            "plain_fp64_sample": {"rhs": ns, "solves_per_s": round(1.0 / t_plain, 4), "iters": itp},
+            "speedup_vs_plain_fp64": round(value * t_plain, 2), "kernel_rooflines": kr}
+
+
+def counters_from_profiles(fname: str, kernel_src: str):
+    """key = value lines of a committed counter summary taken on the current kernel
+    source, else None."""
+    path = os.path.join(ROOT, "profiles", fname)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256_16") != source_hash(kernel_src):
+        return None
+    return kv
+
+
+def fill_leg(args, bie, torch):
+    """The fill kernels at full size (HIP events around each launch): regular
+    triangle pairs (49 point pairs each, Radon 7 x 7) in FP64 and FP32, the flagged
+    pairs (always FP64), the assembly into packed tiles; at 7680 and 30720 unknowns."""
+    from paper_2606_13482_amd.inputs import icosphere
+    sync = torch.cuda.synchronize
+    out = {}
+    for level, k in ((4, 10.0), (5, 20.0)):
+        V, T = icosphere(level)
+        row = {}
+        for storage, rec in (("c128", 6), ("c64", 9)):
+            bie.Operator(V, T, k, storage=storage).close()      # warm-up (code objects, tables)
+            sync()
+            for kk in (6, 7, 8, 9):
+                bie.prof_read(kk)
+            bie.prof_enable(True)
+            t0 = time.perf_counter()
+            op = bie.Operator(V, T, k, storage=storage)
+            sync()
+            t_create = time.perf_counter() - t0
+            bie.prof_enable(False)
+            n_r, ms_r, pairs = bie.prof_read(rec, columns=True)
+            n_s, ms_s, npairs = bie.prof_read(7, columns=True)
+            n_a, ms_a = bie.prof_read(8)
+            N = op.N
+            op.close()
+            row[storage] = {"regular_pairs_ms": round(ms_r, 3), "triangle_pairs": pairs,
+                            "point_pairs_per_s": round(49 * pairs / (ms_r * 1e-3), 1),
+                            "flagged_pairs_ms": round(ms_s, 3), "flagged_pairs": npairs,
+                            "assembly_ms": round(ms_a, 3), "operator_create_s": round(t_create, 4)}
+        out[f"N{N}"] = row
+    kv = counters_from_profiles("fill_pairs_regular_n7680_counters.txt", "fill.hip")
+    if kv:
+        out["counters_n7680"] = {k: kv[k] for k in kv if k.startswith(("valu", "lds", "fp64", "fp32"))}
     return out
 
 
@@ -515,10 +622,10 @@ def star_leg(args, bie, torch, V, T):
         X, st = op.solve(B, opts)
         sync()
         t = time.perf_counter() - t0
+        conv, its, rel = stats_of(st)
         out["star" if star else "assembled"] = {
-            "solves_per_s": round(B.shape[0] / t, 2), "iters_mean": float(np.mean([s["iters"] for s in st])),
-            "converged": float(np.mean([s["converged"] for s in st])),
-            "relres_true_fp64_max": float(max(s["relres_true"] for s in st))}
+            "solves_per_s": round(int(conv.sum()) / t, 2), "iters_mean": float(its.mean()),
+            "converged": float(conv.mean()), "relres_true_fp64_max": float(rel.max())}
         op.close()
     out["speedup_star_vs_assembled"] = round(out["star"]["solves_per_s"] / out["assembled"]["solves_per_s"], 2)
     # FP64 product times at the bench wavenumber
@@ -646,8 +753,10 @@ def counters_probe(args, bie, torch):
 
 def cpu_baseline(level: int, k: float, restart: int, plain_mvps: float):
     """The oracle (C fill with OpenMP + numpy GMRES) on a bounded sample: the full
-    FP64 fill and one GMRES(restart) cycle; a solve with the matrix resident is
-    extrapolated to the mean number of products plain FP64 GMRES needed on the GPU."""
+    FP64 fill and one GMRES(restart) cycle with all host threads, and one cycle
+    with a single thread; a solve with the matrix resident is extrapolated to the
+    mean number of products plain FP64 GMRES needed on the GPU sample."""
+    from threadpoolctl import threadpool_info, threadpool_limits
     from oracle import cfill, efie, krylov
     from oracle.mesh import rwg_table
     from paper_2606_13482_amd.inputs import icosphere, planewave_set
@@ -658,17 +767,25 @@ def cpu_baseline(level: int, k: float, restart: int, plain_mvps: float):
     d, e = planewave_set(np.array([[0.0, 0.0, 1.0]]), "theta")
     b = efie.rhs(rwg, k, d, e)[0]
     t_fill = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    _, st = krylov.gmres(Z, b, m=restart, tol=1e-30, max_mvp=restart)
-    t_cycle = time.perf_counter() - t0
-    t_mvp = t_cycle / max(1, st.mvps)
-    t_solve = plain_mvps * t_mvp
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": round(1.0 / t_solve, 4), "unit": "solves/s", "cores": threads, "kind": "oracle",
-            "sample": (f"full oracle FP64 fill of the {rwg['N']}-unknown matrix ({t_fill:.2f} s) and one "
-                       f"GMRES({restart}) cycle ({t_mvp * 1e3:.1f} ms per iteration); a matrix-resident solve "
-                       f"extrapolated to the {plain_mvps:.0f} products plain FP64 GMRES took on the GPU sample"),
-            "fill_s": round(t_fill, 3)}
+    pools = threadpool_info()
+    threads = max([p.get("num_threads", 1) for p in pools] + [1])
+
+    def cycle():
+        t0 = time.perf_counter()
+        _, st = krylov.gmres(Z, b, m=restart, tol=1e-30, max_mvp=restart)
+        return (time.perf_counter() - t0) / max(1, st.mvps)
+
+    t_mvp = cycle()
+    with threadpool_limits(limits=1):
+        t_mvp1 = cycle()
+    return {"value": round(1.0 / (plain_mvps * t_mvp), 4), "unit": "solves/s", "cores": threads, "kind": "oracle",
+            "sample": (f"full oracle FP64 fill of the {rwg['N']}-unknown matrix ({t_fill:.2f} s, {threads} threads) "
+                       f"and one GMRES({restart}) cycle ({t_mvp * 1e3:.1f} ms per iteration); a matrix-resident "
+                       f"solve extrapolated to the {plain_mvps:.0f} products plain FP64 GMRES took on the GPU sample"),
+            "fill_s": round(t_fill, 3),
+            "single_thread": {"value": round(1.0 / (plain_mvps * t_mvp1), 5), "cores": 1,
+                              "sample": f"one GMRES({restart}) cycle on one thread ({t_mvp1 * 1e3:.1f} ms per "
+                                        f"iteration), extrapolated the same way"}}
 
 
 def main():
@@ -684,14 +801,15 @@ def main():
     if args.counters:
         counters_probe(args, bie, torch)
         return
-    if args.c3:
-        print(json.dumps(c3_run(args, bie, torch)), flush=True)
-        return
     V, T = icosphere(args.level)
     k = args.k
-    plain, roof_gemv = plain_leg(args, bie, torch, V, T, k)
-    head, roof, ms_step, plain_mvps, ns = headline_leg(args, bie, torch, V, T, k)
     N = 3 * T.shape[0] // 2
+    plain, roof_gemv = plain_leg(args, bie, torch, V, T, k)
+    print(json.dumps({"progress": "plain leg done", "solves_per_s": plain["solves_per_s"]}), file=sys.stderr,
+          flush=True)
+    op, ws, head, roof, ms_step, plain_mvps, batch = headline_leg(args, bie, torch, V, T, k)
+    print(json.dumps({"progress": "headline done", "solves_per_s": head["solves_per_s"]}), file=sys.stderr, flush=True)
+    K = head["training"]["pod_rank"]
     out = {
         "metric": METRIC,
         "value": head["solves_per_s"],
@@ -705,28 +823,40 @@ def main():
         "vs_baseline": None,
         "dtype": "split-bf16 products (f32 accumulate) + f64 refinement",
         "data": "synthetic",
-        "config": {"workload": (f"PEC sphere r=1 m, icosphere {T.shape[0]} triangles ({N} RWG), k={k:g}; batches of "
-                                f"{2 * args.test_dirs} held-out plane waves ({args.test_dirs} directions x theta/phi), "
-                                f"operator and warm start resident; learned warm start (POD {min(256, 2 * args.train_dirs)}, "
-                                f"MLP 4-512-512, trained on {2 * args.train_dirs} solves); "
-                                f"{solver_text(args, args.restart, args.calderon)} on split-BF16 MFMA products with "
-                                f"FP64 refinement to {args.tol:g} (FP64 SCC)"),
-                   "N": N, "k": k, "restart": args.restart, "inner_tol": args.inner_tol, "method": args.method,
-                   "block": args.block if args.method == "bgmres" else None,
-                   "slots": args.slots if args.method == "gmres" else None,
-                   "inner_terms": args.inner_terms, "basis": args.basis if args.method == "gmres" else "c64",
-                   "calderon": bool(args.calderon and args.method == "bgmres"),
+        "config": {"workload": (f"learned warm start on the PEC sphere r=1 m, icosphere {T.shape[0]} triangles ({N} "
+                                f"RWG), k={k:g}: trained on {2 * args.train_dirs} solves ({args.train_dirs} directions "
+                                f"x theta/phi), POD {K} modes, MLP 4-{args.hidden}-{args.hidden}-{2 * K} "
+                                f"({args.epochs} epochs); each step serves {2 * args.test_dirs} held-out plane waves "
+                                f"({args.test_dirs} directions x theta/phi) with operator and warm start resident: "
+                                f"block GMRES({args.restart}) over groups of {args.block} on {args.inner_terms}-term "
+                                f"split-BF16 MFMA products with FP64 refinement to {args.tol:g} (FP64 SCC), "
+                                f"unpreconditioned"),
+                   "N": N, "k": k, "restart": args.restart, "inner_tol": args.inner_tol, "method": "bgmres",
+                   "block": args.block, "inner_terms": args.inner_terms, "calderon": False,
                    "rhs_per_step": 2 * args.test_dirs, "train_directions": args.train_dirs,
-                   "test_directions": args.test_dirs, "parallelism": "single GPU"},
+                   "test_directions": args.test_dirs, "pod_rank": K, "hidden": args.hidden, "epochs": args.epochs,
+                   "parallelism": "single GPU"},
         "roofline": roof,
         "roofline_gemv": roof_gemv,
         "headline": head,
         "plain_fp64_step": plain,
     }
+    if args.calderon:
+        out["calderon"] = calderon_leg(args, bie, torch, op, ws, batch)
+    ws.close()
+    op.close()
+    del batch
+    torch.cuda.empty_cache()
+    if args.c3:
+        out["c3"] = c3_leg(args, bie, torch)
+        print(json.dumps({"progress": "c3 done", "solves_per_s": out["c3"]["solves_per_s"]}), file=sys.stderr,
+              flush=True)
+    out["fill"] = fill_leg(args, bie, torch)
     if args.star:
         out["star_split"] = star_leg(args, bie, torch, V, T)
     if args.batch:
         out["uneven_batch"] = uneven_batch_leg(args, bie, torch)
+        print(json.dumps({"progress": "uneven batch done"}), file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.level, k, args.restart, plain_mvps)
     print(json.dumps(out), flush=True)

@@ -309,9 +309,12 @@ typedef struct {
 } bie_calderon_info;
 
 /* Builds M for an assembled operator (not star-split) with N <= 12288.  Fills
- * the refined mesh on the device (at most 1440 N^2 bytes while M is built: the
- * fill's pair scratch beside the refined FP64 matrix, then that matrix and its
- * dense copy; all freed at the end), forms T_BC in column chunks, solves
+ * the refined mesh on the device (the fill's pair scratch, 1152 N^2 bytes,
+ * beside the refined FP64 matrix, 288 N^2; then that matrix, its dense copy,
+ * 576 N^2, and five N x N work matrices; the pair scratch stays allocated
+ * through the rest of the setup only when free device memory allows, else it
+ * is freed after the fill, so the peak is at most 1440 N^2 bytes when memory
+ * is short), forms T_BC in column chunks, solves
  * with G for all N columns (Chebyshev iteration, CG on the normal equations if
  * it fails; the environment variable BIE_CALDERON_GRAM=cgnr selects CG on the
  * normal equations from the start, for comparison and tests) and stores M
@@ -333,6 +336,16 @@ void bie_calderon_destroy(bie_calderon *pc);
  *   X    device R x N complex128;  obs  host M x 3;  F  device R x M x 3 complex128. */
 int bie_farfield(const bie_op *op, const void *X, int64_t R, const double *obs, int64_t M,
                  void *F, void *stream);
+
+/* Bistatic radar cross section (m^2) of the solutions X for a plane wave of
+ * unit amplitude: sigma(r) = (k^2 / (4 pi)) |r x F(r)|^2 with F the radiation
+ * vector above (the unknown is the current times the wave impedance, Sec. II,
+ * so no further factor enters).
+ *   X      device R x N complex128
+ *   obs    host M x 3 unit directions (|r| = 1 to 1e-9, else BIE_EINVAL)
+ *   sigma  device R x M double (row r: the M directions for solution r).
+ * Synchronises `stream`. */
+int bie_rcs(const bie_op *op, const void *X, int64_t R, const double *obs, int64_t M, double *sigma, void *stream);
 
 /* Row sample of the random-sampling criterion: S distinct sorted indices in
  * [0, N) for `seed` (host out, S int64).  Exposed so callers can reproduce the
@@ -433,8 +446,11 @@ void bie_ws_destroy(bie_ws *ws);
  * recorded events of `kernel` (0: tile pass of the packed symmetric product,
  * 1: split-BF16 block product, 2: FP64 block product, 3: reduction of the
  * packed product's partial sums, 4: block GMRES first-pass dots V^H W with
- * their reduction, 5: block GMRES first-pass update W -= V C; BIE_EINVAL
- * otherwise) and returns the number of launches, their summed duration in
+ * their reduction, 5: block GMRES first-pass update W -= V C, 6: regular
+ * triangle pairs of an FP64 fill (columns: triangle pairs p <= q), 7: flagged
+ * triangle pairs of a fill (columns: flagged pairs), 8: assembly of the packed
+ * matrix (columns: unknowns), 9: regular triangle pairs of an FP32 fill;
+ * BIE_EINVAL otherwise) and returns the number of launches, their summed duration in
  * ms and (columns, may be NULL) the summed number of right-hand sides of those
  * launches (the packed product counts every column of its grid, skipped ones
  * included; records 4 and 5 count basis vector x column pairs, sum of K r over

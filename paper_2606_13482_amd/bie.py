@@ -84,6 +84,7 @@ SYMBOLS = [
     ("bie_apply_noalloc", ctypes.c_int, [_P, _P, _P, _I64, ctypes.c_int, ctypes.c_int, _P]),
     ("bie_solve", ctypes.c_int, [_P, _P, _P, _I64, _P, _P, _P]),
     ("bie_farfield", ctypes.c_int, [_P, _P, _I64, _P, _I64, _P, _P]),
+    ("bie_rcs", ctypes.c_int, [_P, _P, _I64, _P, _I64, _P, _P]),
     ("bie_batch_solve", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P]),
     ("bie_batch_config", ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
     ("bie_batch_tuned", ctypes.c_int, [_P, _I64, _P]),
@@ -301,12 +302,14 @@ class Operator:
                                  _dev(F, torch.complex128), _stream(stream)))
         return F
 
-    def rcs(self, X: torch.Tensor, obs) -> np.ndarray:
-        """Bistatic RCS (k^2/4pi)|r x F|^2 for unit-amplitude incidence."""
-        obs = np.atleast_2d(np.asarray(obs, np.float64))
-        F = self.farfield(X, obs).cpu().numpy()
-        tang = F - np.sum(obs[None] * F, axis=2, keepdims=True) * obs[None]
-        return self.k ** 2 / (4 * np.pi) * np.sum(np.abs(tang) ** 2, axis=2)
+    def rcs(self, X: torch.Tensor, obs, stream=None) -> torch.Tensor:
+        """Bistatic RCS (m^2) for unit-amplitude incidence (bie_rcs): R x M, device."""
+        X2 = X.reshape(-1, self.N)
+        o, po = _host(np.atleast_2d(obs), np.float64)
+        S = torch.empty((X2.shape[0], o.shape[0]), dtype=torch.float64, device="cuda")
+        _check(_lib.bie_rcs(self._h, _dev(X2, torch.complex128), X2.shape[0], po, o.shape[0],
+                            _dev(S, torch.float64), _stream(stream)))
+        return S
 
 
 class Calderon:

@@ -370,7 +370,22 @@ int bie_farfield(const bie_op *op, const void *X, int64_t R, const double *obs, 
         if (!op || !X || !obs || !F) return fail(BIE_EINVAL, "NULL argument");
         if (R < 0 || R > 65535 || M < 0 || M > (int64_t(1) << 31)) return fail(BIE_EINVAL, "size out of range");
         if (R == 0 || M == 0) return BIE_OK;
-        bie::farfield(op, X, R, obs, M, F, as_stream(stream));
+        bie::farfield(op, X, R, obs, M, F, false, as_stream(stream));
+        return BIE_OK;
+    });
+}
+
+int bie_rcs(const bie_op *op, const void *X, int64_t R, const double *obs, int64_t M, double *sigma, void *stream)
+{
+    return guarded([&]() -> int {
+        if (!op || !X || !obs || !sigma) return fail(BIE_EINVAL, "NULL argument");
+        if (R < 0 || R > 65535 || M < 0 || M > (int64_t(1) << 31)) return fail(BIE_EINVAL, "size out of range");
+        for (int64_t m = 0; m < M; ++m) {
+            const double n2 = obs[3 * m] * obs[3 * m] + obs[3 * m + 1] * obs[3 * m + 1] + obs[3 * m + 2] * obs[3 * m + 2];
+            if (!(std::fabs(n2 - 1.0) <= 1e-9)) return fail(BIE_EINVAL, "observation directions must be unit vectors");
+        }
+        if (R == 0 || M == 0) return BIE_OK;
+        bie::farfield(op, X, R, obs, M, sigma, true, as_stream(stream));
         return BIE_OK;
     });
 }

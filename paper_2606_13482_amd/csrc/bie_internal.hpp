@@ -181,7 +181,8 @@ void upload_triangles(bie_op *op, hipStream_t s);
 void fill_matrix(bie_op *op, bool fp64_regular, bool want64, bool want32, hipStream_t s);
 void rhs_planewave(const bie_op *op, const double *dirs, const double *pols, int64_t R, void *B,
                    hipStream_t s);
-void farfield(const bie_op *op, const void *X, int64_t R, const double *obs, int64_t M, void *F,
+// radiation vectors (R x M x 3 complex128), or with rcs the bistatic RCS (R x M double)
+void farfield(const bie_op *op, const void *X, int64_t R, const double *obs, int64_t M, void *out, bool rcs,
               hipStream_t s);
 
 // blas.hip: products with the packed symmetric matrix.

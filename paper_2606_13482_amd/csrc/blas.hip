@@ -43,7 +43,7 @@ struct Rec {
     size_t used = 0;
     int64_t cols = 0;   // right-hand sides over the recorded launches
 };
-Rec rec[6];
+Rec rec[10];
 
 void begin(int k, hipStream_t s, int64_t ncols)
 {
@@ -74,7 +74,7 @@ void prof_end(int kernel, hipStream_t s) { prof::end(kernel, s); }
 
 void prof_read(int kernel, int64_t *launches, double *total_ms, int64_t *columns)
 {
-    if (kernel < 0 || kernel > 5) throw Error(BIE_EINVAL, "unknown kernel record");
+    if (kernel < 0 || kernel > 9) throw Error(BIE_EINVAL, "unknown kernel record");
     prof::Rec &r = prof::rec[kernel];
     double t = 0.0;
     for (size_t i = 0; i < r.used; ++i) {

@@ -65,6 +65,19 @@ std::map<int, SetupPool> g_pool;
 int g_live = 0;               // live preconditioners
 thread_local bool g_pool_on = false;
 
+// frees one slot of this device's pool (the next setup that needs it allocates it again)
+void setup_pool_drop(int slot)
+{
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    int dev = 0;
+    BIE_HIP(hipGetDevice(&dev));
+    auto it = g_pool.find(dev);
+    if (it == g_pool.end() || !it->second.buf[slot]) return;
+    (void)hipFree(it->second.buf[slot]);
+    it->second.buf[slot] = nullptr;
+    it->second.cap[slot] = 0;
+}
+
 void setup_pool_release()
 {
     std::lock_guard<std::mutex> lk(g_pool_mu);
@@ -605,8 +618,12 @@ void gram_solve_any(const CsrDev &G, const CsrDev &Gt, int64_t n, double2 *Rr, d
 
 // Largest N for which the preconditioner is built.  The refined mesh has 6 N
 // unknowns and 4 N triangles: its fill's pair scratch (144 B per triangle pair,
-// 1152 N^2 bytes) beside its packed FP64 matrix (288 N^2) is the peak, 217 GB at
-// this N; then the packed matrix and its dense copy (864 N^2).
+// 1152 N^2 bytes) beside its packed FP64 matrix (288 N^2) is the peak of the
+// fill, 217 GB at this N; then the packed matrix and its dense copy (864 N^2)
+// with five N x N work matrices (80 N^2).  The pool keeps the pair scratch for
+// the next setup only while the rest of the setup fits beside it (checked with
+// hipMemGetInfo after the fill); otherwise it is freed first, so the peak stays
+// max(1440, 944) N^2 bytes.
 constexpr int64_t CALDERON_MAX_N = 12288;
 
 bool setup_pool_active() { return g_pool_on; }
@@ -660,6 +677,16 @@ bie_calderon *calderon_create(const bie_op *op, hipStream_t s)
     std::unique_ptr<bie_op, void (*)(bie_op *)> hold(opb, bie_op_destroy);
     const int64_t Nb = opb->mesh.N;
     if (Nb != 9 * M.F) throw Error(BIE_EMESH, "refined mesh has an unexpected edge count");
+    {
+        // the fill's pair scratch (pool slot 0) is not read again in this setup:
+        // keep it for the next one only if the refined matrix's dense copy, the
+        // work matrices and M's storage still fit beside it
+        size_t freeb = 0, totb = 0;
+        BIE_HIP(hipMemGetInfo(&freeb, &totb));
+        const double n2 = double(N) * double(N);
+        const double later = 16.0 * double(Nb) * double(Nb) + (5 * 16 + 8 + 16 + 8 + 16) * n2 + double(size_t(4) << 30);
+        if (double(freeb) < later) setup_pool_drop(0);
+    }
 
     Csr C, G, Gt;
     bc_and_gram(M, opb->mesh, C, G, Gt);

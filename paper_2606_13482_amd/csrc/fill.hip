@@ -512,12 +512,15 @@ __global__ __launch_bounds__(256) void k_rhs(int64_t N, int64_t R, const int4 *_
 
 // Radiation vector F(o) = int j(y) exp(jk o.y) dS = sum_t sum_i w_i J_t(y_i) exp(jk o.y_i),
 // J_t(y) = sum_a x_{m(t,a)} s_a (y - v_a)/2.  One block per (vector, direction).
+// RCS: write the bistatic RCS (k^2 / (4 pi)) |r x F|^2 of direction r (unit)
+// instead of F: the part of F transverse to r, squared.
+template <bool RCS>
 __global__ __launch_bounds__(256) void k_farfield(int64_t F, int64_t N, int64_t M,
                                                   const int32_t *__restrict__ slot_m,
                                                   const int8_t *__restrict__ sgn, const double *__restrict__ cent,
                                                   const double *__restrict__ loc, const double *__restrict__ vfree,
                                                   const double *__restrict__ obs, double k,
-                                                  const double2 *__restrict__ X, double2 *__restrict__ out)
+                                                  const double2 *__restrict__ X, void *__restrict__ outv)
 {
     const int64_t mo = blockIdx.x, r = blockIdx.y;
     const double o[3] = { obs[3 * mo], obs[3 * mo + 1], obs[3 * mo + 2] };
@@ -555,8 +558,25 @@ __global__ __launch_bounds__(256) void k_farfield(int64_t F, int64_t N, int64_t 
             for (int c = 0; c < 6; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x < 3)
-        out[(r * M + mo) * 3 + threadIdx.x] = make_double2(red[2 * threadIdx.x][0], red[2 * threadIdx.x + 1][0]);
+    if (RCS) {
+        if (threadIdx.x == 0) {
+            // r . F, then |F - (r . F) r|^2
+            double dr = 0.0, di = 0.0;
+            for (int c = 0; c < 3; ++c) {
+                dr += o[c] * red[2 * c][0];
+                di += o[c] * red[2 * c + 1][0];
+            }
+            double t2 = 0.0;
+            for (int c = 0; c < 3; ++c) {
+                const double tr = red[2 * c][0] - dr * o[c], ti = red[2 * c + 1][0] - di * o[c];
+                t2 += tr * tr + ti * ti;
+            }
+            static_cast<double *>(outv)[r * M + mo] = k * k / (4.0 * M_PI) * t2;
+        }
+    } else if (threadIdx.x < 3) {
+        static_cast<double2 *>(outv)[(r * M + mo) * 3 + threadIdx.x] =
+            make_double2(red[2 * threadIdx.x][0], red[2 * threadIdx.x + 1][0]);
+    }
 }
 
 template <typename T>
@@ -629,14 +649,23 @@ static void fill_launch(bie_op *op, int64_t nT, int64_t ntiles, const int32_t *p
 {
     const Mesh &M = op->mesh;
     const TriDev &D = op->tri;
+    // measurement records: 6 regular pairs (columns = triangle pairs p <= q), 7
+    // flagged pairs, 8 assembly (columns = unknowns)
+    const int rec_reg = sizeof(R) == 8 ? 6 : 9;
+    prof_begin(rec_reg, s, M.F * (M.F + 1) / 2);
     hipLaunchKernelGGL((k_pairs_regular<R, SPLIT>), dim3(unsigned(ntiles)), dim3(256), 0, s, M.F, nT, ntiles, D.cent,
                        D.loc, D.vfree, D.sgn, op->k, (R *)LB, (R *)VS);
+    prof_end(rec_reg, s);
+    prof_begin(7, s, npairs);
     if (npairs)
         hipLaunchKernelGGL((k_pairs_singular<R, SPLIT>), dim3(unsigned((npairs + 127) / 128)), dim3(128), 0, s, npairs,
                            nT, pairs, D.cent, D.loc, D.vfree, D.verts, D.area, D.sgn, op->k, (R *)LB, (R *)VS);
+    prof_end(7, s);
+    prof_begin(8, s, M.N);
     hipLaunchKernelGGL(k_assemble<R>, dim3(unsigned(op->pk.ntiles)), dim3(256), 0, s, M.N, nT, op->pk.nT,
                        (const int4 *)D.edges, (const R *)LB, want64 ? (double2 *)op->Z64 : nullptr,
                        want32 ? (float2 *)op->Z32 : nullptr);
+    prof_end(8, s);
     if (SPLIT)
         hipLaunchKernelGGL(k_assemble_v<R>, dim3(unsigned(op->pkv.ntiles)), dim3(256), 0, s, M.F, nT, op->pkv.nT,
                            (const R *)VS, want64 ? (double2 *)op->V64 : nullptr, want32 ? (float2 *)op->V32 : nullptr);
@@ -699,17 +728,24 @@ void rhs_planewave(const bie_op *op, const double *dirs, const double *pols, int
     hipFree(dd);
 }
 
-void farfield(const bie_op *op, const void *X, int64_t R, const double *obs, int64_t M, void *Fout, hipStream_t s)
+void farfield(const bie_op *op, const void *X, int64_t R, const double *obs, int64_t M, void *out, bool rcs,
+              hipStream_t s)
 {
     double *dobs = nullptr;
     BIE_HIP(hipMalloc(&dobs, 3 * M * sizeof(double)));
     BIE_HIP(hipMemcpy(dobs, obs, 3 * M * sizeof(double), hipMemcpyHostToDevice));
     const TriDev &D = op->tri;
-    hipLaunchKernelGGL(k_farfield, dim3(unsigned(M), unsigned(R)), dim3(256), 0, s, op->mesh.F, op->mesh.N, M,
-                       D.slot_m, D.sgn, D.cent, D.loc, D.vfree, dobs, op->k, (const double2 *)X, (double2 *)Fout);
-    BIE_HIP(hipGetLastError());
-    BIE_HIP(hipStreamSynchronize(s));
-    hipFree(dobs);
+    if (rcs)
+        hipLaunchKernelGGL(k_farfield<true>, dim3(unsigned(M), unsigned(R)), dim3(256), 0, s, op->mesh.F, op->mesh.N,
+                           M, D.slot_m, D.sgn, D.cent, D.loc, D.vfree, dobs, op->k, (const double2 *)X, out);
+    else
+        hipLaunchKernelGGL(k_farfield<false>, dim3(unsigned(M), unsigned(R)), dim3(256), 0, s, op->mesh.F, op->mesh.N,
+                           M, D.slot_m, D.sgn, D.cent, D.loc, D.vfree, dobs, op->k, (const double2 *)X, out);
+    const hipError_t e = hipGetLastError();
+    const hipError_t e2 = hipStreamSynchronize(s);
+    (void)hipFree(dobs);
+    BIE_HIP(e);
+    BIE_HIP(e2);
 }
 
 }  // namespace bie

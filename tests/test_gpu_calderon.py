@@ -284,12 +284,16 @@ def test_calderon_setup_pool_reuse(bie):
     pa.close()
     pa2 = bie.Calderon(opa)                    # reuses the pool kept alive by pb
     Ma2 = pa2.apply(ea).cpu().numpy()
+    pb3 = bie.Calderon(opb)                    # a smaller setup on buffers grown by the larger one
+    Mb3 = pb3.apply(eb).cpu().numpy()
+    pb3.close()
     pa2.close()
     pb.close()                                 # last one: pool released
     pb2 = bie.Calderon(opb)
     Mb2 = pb2.apply(eb).cpu().numpy()
     pb2.close()
-    _say(f"  pool: rebuilt M equal {np.array_equal(Ma, Ma2)} / {np.array_equal(Mb, Mb2)}")
-    assert np.array_equal(Ma, Ma2) and np.array_equal(Mb, Mb2)
+    _say(f"  pool: rebuilt M equal {np.array_equal(Ma, Ma2)} / {np.array_equal(Mb, Mb2)} / "
+         f"smaller on grown buffers {np.array_equal(Mb, Mb3)}")
+    assert np.array_equal(Ma, Ma2) and np.array_equal(Mb, Mb2) and np.array_equal(Mb, Mb3)
     opa.close()
     opb.close()

@@ -33,11 +33,12 @@ def _maxrel(a, b):
     return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
 
 
-@pytest.mark.parametrize("level,k,nrows", [(4, 10.0, 6), (5, 20.0, 3)])
-def test_full_size_sampled_rows(bie, level, k, nrows):
+@pytest.mark.parametrize("level,k,nrows,ncols", [(4, 10.0, 6, 1024), (5, 20.0, 3, 512)])
+def test_full_size_sampled_rows(bie, level, k, nrows, ncols):
     """FP64 and FP32 fills, the packed FP64 product (one vector) and the split-BF16
-    and FP64 block products (256 columns, the bench's launch shape) at full size,
-    compared on sampled rows with the oracle's rows."""
+    and FP64 block products at full size, compared on sampled rows with the
+    oracle's rows.  The block products take as many columns as the bench's widest
+    launches: 1024 held-out waves at 7680 unknowns, 512 grid waves at 30720."""
     V, T, rwg, flags = _mesh(level)
     N = rwg["N"]
     rng = np.random.default_rng(1000 + level)
@@ -53,9 +54,9 @@ def test_full_size_sampled_rows(bie, level, k, nrows):
     x = complex_gaussian(N, 7)
     y = op.apply(torch.from_numpy(x).cuda().reshape(1, -1)).cpu().numpy()[0]
     e_gemv = _maxrel(y[rows], Ro @ x)
-    # block products, 256 columns
-    X = complex_gaussian(N, 11, cols=256)
-    ref = X @ Ro.T                                                            # (256, S)
+    # block products at the bench's widest launch
+    X = complex_gaussian(N, 11, cols=ncols)
+    ref = X @ Ro.T                                                            # (ncols, S)
     Xd = torch.from_numpy(X).cuda()
     e_bf16 = _maxrel(op.apply(Xd, block=True).cpu().numpy()[:, rows], ref)
     e_f64 = _maxrel(op.apply(Xd, block="fp64").cpu().numpy()[:, rows], ref)
@@ -64,15 +65,15 @@ def test_full_size_sampled_rows(bie, level, k, nrows):
     e_fill32 = _maxrel(op32.apply(torch.from_numpy(E.astype(np.complex64)).cuda()).cpu().numpy(), Ro)
     op32.close()
     _say(f"  N={N} rows {rows.tolist()}: fill FP64 {e_fill:.1e}, FP32 {e_fill32:.1e}; packed product {e_gemv:.1e}; "
-         f"block split-BF16 {e_bf16:.1e}, FP64 {e_f64:.1e}")
+         f"block products ({ncols} columns) split-BF16 {e_bf16:.1e}, FP64 {e_f64:.1e}")
     assert e_fill <= 1e-12 and e_gemv <= 1e-12 and e_f64 <= 1e-12
     assert e_fill32 <= 1e-6
     assert e_bf16 <= 3e-5
 
 
 def test_full_size_headline_solve(bie):
-    """The headline form (split-BF16 block products, FP16 inner basis, FP64
-    refinement, continuous batch) on 16 plane waves at 7680 unknowns: every
+    """The column-GMRES mixed form (split-BF16 block products, FP16 inner basis,
+    FP64 refinement, continuous batch) on 16 plane waves at 7680 unknowns: every
     solution meets SCC 1e-6 against the oracle's full matrix, and the residual the
     solver reports is that SCC."""
     V, T, rwg, _ = _mesh(4)
@@ -119,8 +120,8 @@ def test_full_size_large_sphere_solve(bie):
 
 @pytest.mark.parametrize("terms", [2, 3])
 def test_full_size_headline_block_solve(bie, terms):
-    """The bench's default mixed form (block GMRES(50) over groups of 32 on
-    split-BF16 products, 2 terms by default, FP64 refinement) on 64 plane waves at
+    """The bench's headline form (block GMRES(50) over groups of 32 on split-BF16
+    products, 2 terms in the bench, FP64 refinement) on 64 plane waves at
     7680 unknowns: every residual at most 1e-6 against the oracle's full matrix and
     equal to the reported SCC."""
     V, T, rwg, _ = _mesh(4)
@@ -143,7 +144,7 @@ def test_full_size_headline_block_solve(bie, terms):
 
 
 def test_full_size_calderon_block_solve(bie):
-    """The bench's default form: Calderon-preconditioned mixed block GMRES(50)
+    """The bench's Calderon leg: Calderon-preconditioned mixed block GMRES(50)
     (groups of 32, split-BF16 products of T M with 3 terms, inner tolerance 1e-3,
     FP64 refinement) on 64 plane waves at 7680 unknowns, k = 10: every residual at most
     1e-6 against the oracle's full matrix and equal to the reported SCC; the
@@ -179,3 +180,76 @@ def test_full_size_calderon_block_solve(bie):
     assert all(s["converged"] for s in st)
     assert res.max() <= 1e-6 * (1 + 1e-6)
     assert np.max(np.abs(rep - res) / res) <= 1e-7
+
+
+def test_full_size_large_sphere_block_form(bie):
+    """The large sphere's timed form: block GMRES(30) over groups of 32 with 2-term
+    split-BF16 products and FP64 refinement, on the first 64 waves of the 16 x 16
+    (theta, phi) grid at 30720 unknowns, k = 20: every column converges, and the FP64
+    residual behind the reported criterion agrees on sampled rows with the
+    oracle's rows."""
+    from paper_2606_13482_amd.inputs import grid_planewaves
+    V, T, rwg, flags = _mesh(5)
+    N = rwg["N"]
+    op = bie.Operator(V, T, 20.0, storage="split_bf16")
+    dirs, pols = grid_planewaves(16, 16)
+    B = op.rhs(dirs[:64], pols[:64])
+    X, st = op.solve(B, bie.Solve(method="bgmres", block=32, restart=30, tol=1e-6, precision="mixed",
+                                  inner_tol=0.1, inner_terms=2, max_mvp=20000))
+    conv = [s["converged"] for s in st]
+    Rg = (B - op.apply(X)).cpu().numpy()
+    rows = np.array([1, N // 3, N - 1])
+    Ro = efie.fill_rows(rwg, 20.0, rows, flags=flags)
+    Bn, Xn = B.cpu().numpy(), X.cpu().numpy()
+    ro = Bn[:, rows] - Xn @ Ro.T
+    scale = np.linalg.norm(Bn, axis=1)[:, None]
+    err = float(np.max(np.abs(Rg[:, rows] - ro) / scale))
+    rel = np.linalg.norm(Rg, axis=1) / np.linalg.norm(Bn, axis=1)
+    rep = np.array([s["relres_true"] for s in st])
+    _say(f"  large sphere, block form (2 terms), 64 grid waves: converged {np.mean(conv):.3f}, max residual "
+         f"{rel.max():.3e} (reported {rep.max():.3e}), iterations {np.mean([s['iters'] for s in st]):.0f} mean; "
+         f"sampled-row residual difference {err:.1e} of |b|")
+    assert all(conv) and rel.max() <= 1e-6 * (1 + 1e-6)
+    assert np.max(np.abs(rep - rel) / rel) <= 1e-6
+    assert err <= 1e-12
+    op.close()
+
+
+def test_pod_at_workload_size(bie):
+    """POD of the learned warm-start workload's size: 256 modes from 1024 solutions
+    (512 directions x theta/phi) at 7680 unknowns, k = 10.  The randomised range
+    finder's singular values and projection error against the exact SVD of the same
+    snapshots (the Eckart-Young optimum)."""
+    from oracle import learn
+    V, T, rwg, _ = _mesh(4)
+    op = bie.Operator(V, T, 10.0, storage="split_bf16")
+    inc = random_directions(512, 5)
+    d1, e1 = planewave_set(inc, "theta")
+    d2, e2 = planewave_set(inc, "phi")
+    dirs, pols = np.concatenate([d1, d2]), np.concatenate([e1, e2])
+    B = op.rhs(dirs, pols)
+    X, st = op.solve(B, bie.Solve(method="bgmres", block=32, restart=50, tol=1e-6, precision="mixed", inner_tol=0.1,
+                                  inner_terms=2, max_mvp=20000))
+    assert all(s["converged"] for s in st)
+    feats = bie.features(dirs, np.concatenate([np.ones(512), -np.ones(512)]))
+    K = 256
+    ws = bie.WarmStart.train(op, feats, X, pod_rank=K, hidden=16, epochs=0, batch=256)
+    U = ws.basis().cpu().numpy()
+    sg = ws.sigma()
+    Xn = X.cpu().numpy()
+    _, so = learn.pod(Xn, K)
+    err = np.linalg.norm(Xn - (Xn @ U.conj().T) @ U)
+    opt = np.sqrt(np.sum(so[K:] ** 2))
+    orth = np.max(np.abs(U @ U.conj().T - np.eye(K)))
+    rel = np.abs(sg - so[:K]) / so[:K]
+    _say(f"  POD 256 of 1024 at 7680 unknowns: orthonormality {orth:.1e}, singular values: first 64 {rel[:64].max():.1e}, "
+         f"first 128 {rel[:128].max():.1e}, all {rel.max():.1e}; projection error {err / np.linalg.norm(Xn):.4e} of "
+         f"|X| (optimum {opt / np.linalg.norm(Xn):.4e}), sigma_257/sigma_1 {so[K] / so[0]:.2e}")
+    # the spectrum decays slowly (sigma_257 is a quarter of sigma_1): the range
+    # finder's trailing singular values are within a few per cent, the leading ones
+    # exact, and the subspace it returns is within 1 % of the best rank-256 one
+    assert orth <= 1e-10
+    assert rel[:64].max() <= 1e-6 and rel.max() <= 3e-2
+    assert err <= opt * 1.01
+    ws.close()
+    op.close()

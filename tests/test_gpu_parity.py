@@ -89,6 +89,13 @@ def test_rhs_and_farfield(bie):
     for r in range(2):
         Fo = efie.radiation_vector(rwg, k, x[r], obs)
         assert np.max(np.abs(F[r] - Fo)) / np.max(np.abs(Fo)) < 1e-12
+    # bistatic RCS (bie_rcs) against the oracle's, and non-unit directions refused
+    S = op.rcs(torch.from_numpy(x).cuda(), obs).cpu().numpy()
+    for r in range(2):
+        So = efie.rcs(rwg, k, x[r], obs)
+        assert np.max(np.abs(S[r] - So)) / np.max(So) < 1e-12
+    with pytest.raises(bie.BieError):
+        op.rcs(torch.from_numpy(x).cuda(), 2.0 * obs)
 
 
 @pytest.mark.parametrize("R", [1, 3, 6])
