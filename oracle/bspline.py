@@ -1,0 +1,297 @@
+"""Tensor-product B-spline interpolation of the Green's function and the
+single-level far field built on it (oracle, FP64).  TEST INFRASTRUCTURE ONLY:
+only tests/, the entry point's smoke() and the benchmark's CPU baseline use it.
+
+What the paper states, restated plainly:
+
+  * Degree-p B-splines on an open, equidistant knot vector of s splines on
+    [0, 1] (Sec. III-A, eq:eqknots), evaluated by the Cox-de Boor recursion.
+  * Interpolation of g between the boxes of a test and a trial function
+    (Sec. III-A, eq:TAfactor): with B[i, m] = b_i(x_m) the splines at the
+    equispaced interpolation points, the weights are W = B^-T G B^-1, G the
+    samples of g between the two point grids, so that
+        [T_A]_mn ~ sum_d m_{d,m}^T W m_{d,n},   m_{d,n}[i] = int f_{n,d} b_i.
+    With transformed moments m~ = B^-1 m the same value is
+        sum_d m~_{d,m}^T G m~_{d,n}                              (eq:TAfactorBspline)
+    and the scalar potential takes the same form with the divergence moments.
+  * Buffer knots (Sec. III-B): the knot vector is extended by s_b knots of the
+    same spacing on each side so that the supports of all basis functions of
+    the box lie inside the enlarged interpolation domain;
+    s_b = ceil(max relative protrusion / du), du = 1/(s - p).
+  * Stabilisation (Sec. V-B): r interior knots next to each end of the
+    equidistant knot vector are removed (r from the paper's table: 0, 0, 1, 1,
+    2, 2 for p = 1..6); the stabilised splines interpolate at as many
+    equispaced points; moments are taken with the equidistant splines and
+    mapped to the stabilised ones by knot insertion, W_stab = S^T B_s^-T G B_s^-1 S
+    (S = the insertion matrix C below).
+  * Knot insertion (Sec. IV-B, Boehm's algorithm): inserting u- into the
+    interval [u_k, u_k+1) gives the coefficients w-_i = a_i w_i + (1 - a_i) w_i-1
+    with a_i = 1 (i <= k - p), (u- - u_i)/(u_i+p - u_i) (k - p < i <= k), 0
+    (i > k).  Inserting every knot of a finer vector into the unit-coefficient
+    curve of coarse spline j gives row j of the refinement matrix C:
+    b_j^coarse = sum_i C[j, i] b_i^fine.
+  * Error bound (Sec. V-A, eq:errorapprox):
+        ||Pi f - f||_inf,B <= du^(p+1) C2^(d-1) (h/2)^(p+1) sum_k ||d_k^(p+1) f||_inf,B
+    with C2 <= ||B^-1||_inf (max row sum).
+
+Readings where the paper is silent (listed in the design doc): the interpolation
+points are s' equispaced points spanning the (buffered) interpolation domain,
+s' the number of (stabilised) splines, end points included; an RWG function
+belongs to the box that contains the mean of its two triangle centroids; two
+boxes are far when their indices differ by more than one along some axis; the
+moments use the fill's Radon 7-point rule on each triangle.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from .efie import Geometry, green
+
+KNOTS_TO_REMOVE = {1: 0, 2: 0, 3: 1, 4: 1, 5: 2, 6: 2}   # paper's table, per side
+
+
+# ----------------------------------------------------------------------------- 1D splines
+def open_knots(n: int, p: int, lo: float = 0.0, hi: float = 1.0) -> np.ndarray:
+    """Open equidistant knot vector of n splines of degree p on [lo, hi]
+    (eq:eqknots mapped to [lo, hi]): p+1 copies of each end, n-p-1 interior
+    knots at spacing (hi - lo)/(n - p)."""
+    if n < p + 1:
+        raise ValueError("need at least p + 1 splines")
+    inner = [lo + (hi - lo) * (i - p - 1) / (n - p) for i in range(p + 2, n + 1)]
+    return np.array([lo] * (p + 1) + inner + [hi] * (p + 1), dtype=np.float64)
+
+
+def averaged_knots(n: int, p: int) -> np.ndarray:
+    """Averaged knot vector for n equispaced interpolation points on [0, 1] (eq:avgknots)."""
+    inner = [(2 * i - p - 3) / (2 * (n - 1)) for i in range(p + 2, n + 1)]
+    return np.array([0.0] * (p + 1) + inner + [1.0] * (p + 1), dtype=np.float64)
+
+
+def remove_boundary_knots(u: np.ndarray, p: int, r: int) -> np.ndarray:
+    """The knot vector with the r interior knots nearest each end removed (Sec. V-B)."""
+    if r == 0:
+        return u.copy()
+    inner = u[p + 1:len(u) - p - 1]
+    if len(inner) < 2 * r:
+        raise ValueError("not enough interior knots to remove")
+    return np.concatenate([u[:p + 1], inner[r:len(inner) - r], u[len(u) - p - 1:]])
+
+
+def basis(u: np.ndarray, p: int, x) -> np.ndarray:
+    """Values of all n = len(u) - p - 1 B-splines of degree p at the points x
+    (Cox-de Boor recursion, 0/0 taken as 0); (len(x), n).  The interval ending at
+    the last knot is closed on the right."""
+    x = np.atleast_1d(np.asarray(x, dtype=np.float64))
+    m = len(u)
+    N = np.zeros((x.size, m - 1))
+    last = np.max(np.nonzero(u[1:] > u[:-1])[0])          # last non-empty knot interval
+    for i in range(m - 1):
+        if u[i + 1] > u[i]:
+            inside = (x >= u[i]) & (x < u[i + 1])
+            if i == last:
+                inside |= x == u[i + 1]
+            N[:, i] = inside
+    for d in range(1, p + 1):
+        M = np.zeros((x.size, m - 1 - d))
+        for i in range(m - 1 - d):
+            a = u[i + d] - u[i]
+            b = u[i + d + 1] - u[i + 1]
+            if a > 0:
+                M[:, i] += (x - u[i]) / a * N[:, i]
+            if b > 0:
+                M[:, i] += (u[i + d + 1] - x) / b * N[:, i + 1]
+        N = M
+    return N
+
+
+def sampling_matrix(u: np.ndarray, p: int, pts) -> np.ndarray:
+    """B[i, m] = b_i(x_m)."""
+    return basis(u, p, pts).T.copy()
+
+
+def equispaced(n: int, lo: float = 0.0, hi: float = 1.0) -> np.ndarray:
+    """n equispaced points on [lo, hi], the ends exactly lo and hi."""
+    if n == 1:
+        return np.array([0.5 * (lo + hi)])
+    t = np.array([lo + (hi - lo) * m / (n - 1) for m in range(n)])
+    t[0], t[-1] = lo, hi
+    return t
+
+
+def insert_knot(u: np.ndarray, p: int, w: np.ndarray, ubar: float):
+    """Boehm's insertion of one knot (Sec. IV-B): the knot vector and the
+    coefficients of the same spline curve on it."""
+    n = len(u) - p - 1
+    k = int(np.searchsorted(u, ubar, side="right")) - 1          # u[k] <= ubar < u[k+1]
+    wb = np.zeros(n + 1)
+    for i in range(n + 1):
+        if i <= k - p:
+            a = 1.0
+        elif i <= k:
+            a = (ubar - u[i]) / (u[i + p] - u[i])
+        else:
+            a = 0.0
+        wb[i] = (a * w[i] if i < n else 0.0) + ((1.0 - a) * w[i - 1] if i >= 1 else 0.0)
+    return np.insert(u, k + 1, ubar), wb
+
+
+def refinement_matrix(u_coarse: np.ndarray, u_fine: np.ndarray, p: int) -> np.ndarray:
+    """C (n_coarse x n_fine) with b_j^coarse = sum_i C[j, i] b_i^fine: every knot of
+    the fine vector missing from the coarse one is inserted into the curve with
+    unit coefficient j (Sec. IV-B)."""
+    extra = list(u_fine)
+    for v in u_coarse:                                  # multiset difference
+        for t, e in enumerate(extra):
+            if e == v:
+                del extra[t]
+                break
+        else:
+            raise ValueError("coarse knot vector not contained in the fine one")
+    n = len(u_coarse) - p - 1
+    C = np.zeros((n, len(u_fine) - p - 1))
+    for j in range(n):
+        u, w = u_coarse.copy(), np.eye(n)[j]
+        for e in sorted(extra):
+            u, w = insert_knot(u, p, w, e)
+        assert np.array_equal(u, np.sort(u_fine))
+        C[j] = w
+    return C
+
+
+# ----------------------------------------------------------------------------- one box's spline space
+class BoxSplines:
+    """The spline spaces of one box level along one axis, in the box's parameter
+    coordinate t = (x - lo) / a (the box is t in [0, 1]): the equidistant knot
+    vector of s splines extended by sb buffer knots per side, its stabilised
+    version with r knots removed per side, the equispaced interpolation points,
+    and the map A = B_stab^-1 C from equidistant-spline moments to transformed
+    stabilised moments (m~ = A m along each axis)."""
+
+    def __init__(self, s: int, p: int, sb: int = 0, stabilise: bool = True):
+        self.s, self.p, self.sb = s, p, sb
+        self.du = 1.0 / (s - p)
+        self.lo, self.hi = -sb * self.du, 1.0 + sb * self.du
+        self.n = s + 2 * sb
+        self.u_eq = open_knots(self.n, p, self.lo, self.hi)
+        self.r = KNOTS_TO_REMOVE[p] if stabilise else 0
+        self.u_st = remove_boundary_knots(self.u_eq, p, self.r)
+        self.n_st = len(self.u_st) - p - 1
+        self.t = equispaced(self.n_st, self.lo, self.hi)                # interpolation points
+        self.B = sampling_matrix(self.u_st, p, self.t)                   # B[i, m] = b_i^stab(t_m)
+        self.C = refinement_matrix(self.u_st, self.u_eq, p)              # stab in terms of eq
+        self.A = np.linalg.solve(self.B, self.C)                         # n_st x n
+
+    def eq_basis(self, t) -> np.ndarray:
+        return basis(self.u_eq, self.p, t)
+
+
+# ----------------------------------------------------------------------------- single level
+def box_level(rwg: dict, a: float, origin=None):
+    """Uniform boxes of side a: the box index (3 ints) of every RWG function (the
+    box holding the mean of its triangle centroids), the boxes' lower corners,
+    and the largest protrusion of a support beyond its box relative to a."""
+    V, T = rwg["V"], rwg["T"]
+    if origin is None:
+        origin = V.min(axis=0) - 1e-9 * a
+    c = 0.5 * (rwg["cent"][rwg["tp"]] + rwg["cent"][rwg["tm"]])
+    idx = np.floor((c - origin) / a).astype(np.int64)
+    lo = origin + idx * a
+    prot = 0.0
+    for m in range(rwg["N"]):
+        pts = V[np.concatenate([T[rwg["tp"][m]], T[rwg["tm"][m]]])]
+        prot = max(prot, float(np.max((lo[m] - pts) / a)), float(np.max((pts - lo[m] - a) / a)))
+    return idx, lo, max(prot, 0.0), np.asarray(origin)
+
+
+def buffer_knots(prot_rel: float, s: int, p: int) -> int:
+    """s_b = ceil(max relative protrusion / du) (Sec. III-B)."""
+    return int(math.ceil(prot_rel * (s - p) - 1e-12)) if prot_rel > 0 else 0
+
+
+def moments(rwg: dict, sp: BoxSplines, a: float, lo: np.ndarray, rule=None) -> np.ndarray:
+    """Transformed moments m~ (N, 4, n_st, n_st, n_st): components d = x, y, z of
+    int f_m b~ and the divergence moment int div f_m b~, with b~ the transformed
+    stabilised splines of the function's box (lo: its lower corner, (N, 3)) and
+    the fill's quadrature rule."""
+    G = Geometry(rwg, rule)
+    N = rwg["N"]
+    n = sp.n_st
+    out = np.zeros((N, 4, n, n, n))
+    for m in range(N):
+        for t, vfree, sgn in ((rwg["tp"][m], rwg["vp"][m], 1.0), (rwg["tm"][m], rwg["vm"][m], -1.0)):
+            X = G.X[t]                                              # (nq, 3)
+            tt = (X - lo[m]) / a                                    # parameter coordinates
+            bx = sp.eq_basis(tt[:, 0]) @ sp.A.T                     # (nq, n_st): b~ along x
+            by = sp.eq_basis(tt[:, 1]) @ sp.A.T
+            bz = sp.eq_basis(tt[:, 2]) @ sp.A.T
+            prod = np.einsum("qi,qj,qk->qijk", bx, by, bz)          # (nq, n, n, n)
+            D = X - rwg["V"][vfree]                                 # (nq, 3)
+            for d in range(3):
+                out[m, d] += 0.5 * sgn * np.einsum("q,qijk->ijk", G.w * D[:, d], prod)
+            out[m, 3] += sgn * np.einsum("q,qijk->ijk", G.w, prod)
+    return out
+
+
+def grid_points(sp: BoxSplines, a: float, lo_box: np.ndarray) -> np.ndarray:
+    """The box's interpolation points in space, (n_st^3, 3), index order (i, j, k)."""
+    t = lo_box[None, :] + a * sp.t[:, None]
+    gx, gy, gz = np.meshgrid(t[:, 0], t[:, 1], t[:, 2], indexing="ij")
+    return np.stack([gx.ravel(), gy.ravel(), gz.ravel()], axis=1)
+
+
+def far_pairs(box_idx: np.ndarray):
+    """Distinct boxes (rows of unique indices) and the far pairs among them
+    (Chebyshev distance of the indices > 1)."""
+    boxes, inv = np.unique(box_idx, axis=0, return_inverse=True)
+    d = np.max(np.abs(boxes[:, None, :] - boxes[None, :, :]), axis=2)
+    return boxes, inv.ravel(), d > 1
+
+
+def far_block(mt: np.ndarray, rows, cols, sp: BoxSplines, a: float, lo_x, lo_y, k: float) -> np.ndarray:
+    """Interpolated entries Z~_mn for test functions `rows` (all in the box at
+    lo_x) and trial functions `cols` (box at lo_y):
+    jk sum_d m~_d,m^T G m~_d,n + (1/jk) m~_4,m^T G m~_4,n (eq:TAfactorBspline)."""
+    Px, Py = grid_points(sp, a, lo_x), grid_points(sp, a, lo_y)
+    R = np.linalg.norm(Px[:, None, :] - Py[None, :, :], axis=2)
+    Gm = green(R, k)
+    A = mt[rows].reshape(len(rows), 4, -1)
+    B = mt[cols].reshape(len(cols), 4, -1)
+    jk = 1j * k
+    out = np.zeros((len(rows), len(cols)), np.complex128)
+    for d in range(4):
+        out += (jk if d < 3 else 1.0 / jk) * (A[:, d, :] @ Gm @ B[:, d, :].T)
+    return out
+
+
+def far_product(rwg: dict, k: float, x: np.ndarray, a: float, s: int, p: int, stabilise: bool = True,
+                origin=None):
+    """y = Z~_far x: the single-level far field (every pair of far boxes) of the
+    RWG functions with coefficients x (N,) or (R, N); returns y and the level's
+    data (boxes, far mask, splines) for checks."""
+    idx, lo, prot, origin = box_level(rwg, a, origin)
+    sb = buffer_knots(prot, s, p)
+    if 2 * sb >= s - p:
+        # the buffered domains of two boxes two apart would touch: g is not smooth there
+        raise ValueError("buffer knots reach half a box: use larger boxes or more splines")
+    sp = BoxSplines(s, p, sb, stabilise)
+    mt = moments(rwg, sp, a, lo)
+    boxes, inv, far = far_pairs(idx)
+    X = np.atleast_2d(x)
+    Y = np.zeros_like(X, dtype=np.complex128)
+    members = [np.nonzero(inv == b)[0] for b in range(len(boxes))]
+    box_lo = origin + boxes * a
+    for bx in range(len(boxes)):
+        rows = members[bx]
+        for by in np.nonzero(far[bx])[0]:
+            cols = members[by]
+            Zb = far_block(mt, rows, cols, sp, a, box_lo[bx], box_lo[by], k)
+            Y[:, rows] += X[:, cols] @ Zb.T
+    return (Y[0] if np.ndim(x) == 1 else Y), dict(boxes=boxes, inv=inv, far=far, sb=sb, splines=sp, moments=mt,
+                                                   box_lo=box_lo, members=members, prot=prot)
+
+
+def far_mask(inv: np.ndarray, far: np.ndarray) -> np.ndarray:
+    """(N, N) boolean: the entries (m, n) whose boxes are far apart."""
+    return far[inv][:, inv]
