@@ -599,6 +599,51 @@ def fill_leg(args, bie, torch):
     return out
 
 
+def far_leg(args, bie, torch, V, T, k):
+    """The single-level B-spline far field (Sec. III) on the bench sphere: cubes of
+    0.4 m, cubic splines, s = 8; setup (moments, table of g) and the far product
+    of one vector (HIP events on the current stream), against the dense packed
+    product of the same operator."""
+    sync = torch.cuda.synchronize
+    from paper_2606_13482_amd.inputs import complex_gaussian
+    op = bie.Operator(V, T, k)
+    t0 = time.perf_counter()
+    far = bie.FarField(op, 0.4, 8, 3)
+    sync()
+    t_setup = time.perf_counter() - t0
+    info = far.info()
+    x = torch.from_numpy(complex_gaussian(op.N, 7)).cuda().reshape(1, -1)
+    y = far.apply(x)
+    yd = op.apply(x)
+    sync()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    ev0.record()
+    for _ in range(reps):
+        far.apply(x, out=y)
+    ev1.record()
+    sync()
+    ms = ev0.elapsed_time(ev1) / reps
+    ev0.record()
+    for _ in range(reps):
+        op.apply(x, out=yd)
+    ev1.record()
+    sync()
+    ms_dense = ev0.elapsed_time(ev1) / reps
+    n3 = info["points_per_axis"] ** 3
+    pairs = info["far_pairs"] * n3 * n3
+    # translation: 4 complex multiply-adds (32 flops) per pair of interpolation points
+    tf = 32.0 * pairs / (ms * 1e-3) / 1e12
+    far.close()
+    op.close()
+    return {"workload": f"PEC sphere, {T.shape[0]} triangles, k={k:g}: cubes 0.4 m, p = 3, s = 8 (single level)",
+            "setup_s": round(t_setup, 3), "cubes": info["boxes"], "far_cube_pairs": info["far_pairs"],
+            "points_per_cube": n3, "buffer_knots": info["buffer_knots"], "ms_per_far_product": round(ms, 3),
+            "point_pairs_per_s": round(pairs / (ms * 1e-3), 1), "translation_tflops": round(tf, 2),
+            "translation_frac_fp64_vector_peak": round(tf / FP64_MFMA_PEAK_TFLOPS, 4),
+            "ms_per_dense_packed_product": round(ms_dense, 4)}
+
+
 def star_leg(args, bie, torch, V, T):
     """Star-split operator (Sec. VI-A: T = jk T_A + Sigma V Sigma^T / (jk)) against
     the assembled one on the bench sphere: (1) mixed precision with FP32 storage at
@@ -852,6 +897,7 @@ def main():
         print(json.dumps({"progress": "c3 done", "solves_per_s": out["c3"]["solves_per_s"]}), file=sys.stderr,
               flush=True)
     out["fill"] = fill_leg(args, bie, torch)
+    out["far_field"] = far_leg(args, bie, torch, V, T, k)
     if args.star:
         out["star_split"] = star_leg(args, bie, torch, V, T)
     if args.batch:

@@ -347,6 +347,49 @@ int bie_farfield(const bie_op *op, const void *X, int64_t R, const double *obs, 
  * Synchronises `stream`. */
 int bie_rcs(const bie_op *op, const void *X, int64_t R, const double *obs, int64_t M, double *sigma, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Single-level far field by tensor-product B-spline interpolation of g (the
+ * paper's Sec. III: eq:TAfactor, eq:TAfactorBspline; buffer knots, Sec. III-B;
+ * stabilised knots, Sec. V-B; knot insertion, Sec. IV-B).  The operator's mesh
+ * is covered by cubes of side `box`; an RWG function belongs to the cube that
+ * holds the mean of its two triangle centroids; two cubes are far when their
+ * indices differ by more than one along some axis.  Each cube carries degree-p
+ * splines (p odd: 1, 3 or 5) on an open equidistant knot vector of s splines
+ * per axis extended by buffer knots covering the supports that protrude, with
+ * (p - 1)/2 knots removed next to each end; their interpolation points lie on
+ * one lattice, so g between cubes is read from one table.  The product is
+ *   [Z~_far x]_m = sum over far cubes of  jk sum_d m~_d,m^T G m~_d,n x_n
+ *                                         + (1/(jk)) m~_div,m^T G m~_div,n x_n
+ * with m~ the moments of the RWG function (vector components and divergence)
+ * against the splines, taken with the fill's quadrature rule and mapped by
+ * B_stab^-1 C.  Only the far part is applied (near cubes: the dense matrix). */
+typedef struct bie_far bie_far;
+typedef struct {
+    double box;            /* cube side (m), > 0 */
+    int s;                 /* splines per axis over one cube side, >= p + 1 + (p - 1) */
+    int p;                 /* degree: 1, 3 or 5 */
+} bie_far_opts;
+typedef struct {
+    int64_t boxes;         /* non-empty cubes */
+    int64_t far_pairs;     /* ordered pairs of far cubes */
+    int64_t buffer_knots;  /* per side */
+    int64_t splines;       /* equidistant splines per axis, buffer included */
+    int64_t points_per_axis;  /* interpolation points per axis (stabilised splines) */
+    double protrusion;     /* largest protrusion of a support beyond its cube, in cube sides */
+    double origin[3];      /* lower corner of cube (0, 0, 0) */
+} bie_far_info;
+/* Builds the cube level, the moments (device kernels) and the table of g.
+ * BIE_EINVAL for bad options, a star-split operator, buffers that reach half a
+ * cube (the buffered domains of cubes two apart would touch: use larger cubes
+ * or more splines) or more than 24 splines per axis. */
+int bie_far_create(const bie_op *op, const bie_far_opts *opts, void *stream, bie_far **out);
+/* Y = Z~_far X for R complex128 vectors (device, R x N each). */
+int bie_far_apply(bie_far *far, const void *X, void *Y, int64_t R, void *stream);
+int bie_far_get_info(const bie_far *far, bie_far_info *info);
+/* Cube index (3 x int32, host out, N rows) of every RWG function. */
+int bie_far_boxes(const bie_far *far, int32_t *out);
+void bie_far_destroy(bie_far *far);
+
 /* Row sample of the random-sampling criterion: S distinct sorted indices in
  * [0, N) for `seed` (host out, S int64).  Exposed so callers can reproduce the
  * rows a given check used. */

@@ -60,6 +60,16 @@ class WsOpts(ctypes.Structure):
                 ("pol_model", ctypes.c_int)]
 
 
+class FarOpts(ctypes.Structure):
+    _fields_ = [("box", ctypes.c_double), ("s", ctypes.c_int), ("p", ctypes.c_int)]
+
+
+class FarInfo(ctypes.Structure):
+    _fields_ = [("boxes", ctypes.c_int64), ("far_pairs", ctypes.c_int64), ("buffer_knots", ctypes.c_int64),
+                ("splines", ctypes.c_int64), ("points_per_axis", ctypes.c_int64), ("protrusion", ctypes.c_double),
+                ("origin", ctypes.c_double * 3)]
+
+
 class SolveStat(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int64), ("mvps", ctypes.c_int64), ("relres_est", ctypes.c_double),
                 ("relres_true", ctypes.c_double), ("converged", ctypes.c_int), ("checks", ctypes.c_int),
@@ -89,6 +99,11 @@ SYMBOLS = [
     ("bie_batch_config", ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
     ("bie_batch_tuned", ctypes.c_int, [_P, _I64, _P]),
     ("bie_rscc_rows", ctypes.c_int, [_I64, _I64, ctypes.c_uint64, _P]),
+    ("bie_far_create", ctypes.c_int, [_P, _P, _P, ctypes.POINTER(_P)]),
+    ("bie_far_apply", ctypes.c_int, [_P, _P, _P, _I64, _P]),
+    ("bie_far_get_info", ctypes.c_int, [_P, _P]),
+    ("bie_far_boxes", ctypes.c_int, [_P, _P]),
+    ("bie_far_destroy", None, [_P]),
     ("bie_ws_train", ctypes.c_int, [_P, _P, _P, _P, _I64, _P, _P, ctypes.POINTER(_P)]),
     ("bie_ws_fit", ctypes.c_int, [_P, _P, _P, _P, _I64, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_uint64, _P, _P]),
@@ -341,6 +356,48 @@ class Calderon:
     def close(self):
         if getattr(self, "_h", None):
             _lib.bie_calderon_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class FarField:
+    """Single-level far field of an operator by B-spline interpolation of g
+    (bie_far_create): apply() gives Z~_far X for the pairs of far cubes."""
+
+    def __init__(self, op: Operator, box: float, s: int, p: int = 3, stream=None):
+        h = ctypes.c_void_p()
+        o = FarOpts(float(box), int(s), int(p))
+        _check(_lib.bie_far_create(op._h, ctypes.byref(o), _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self.op = op
+        self.N = op.N
+
+    def apply(self, X: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        X2 = X.reshape(-1, self.N)
+        Y = torch.empty_like(X2) if out is None else out
+        _check(_lib.bie_far_apply(self._h, _dev(X2, torch.complex128), _dev(Y, torch.complex128, X2.shape),
+                                  X2.shape[0], _stream(stream)))
+        return Y.reshape(X.shape)
+
+    def info(self) -> dict:
+        i = FarInfo()
+        _check(_lib.bie_far_get_info(self._h, ctypes.byref(i)))
+        return dict(boxes=i.boxes, far_pairs=i.far_pairs, buffer_knots=i.buffer_knots, splines=i.splines,
+                    points_per_axis=i.points_per_axis, protrusion=i.protrusion, origin=list(i.origin))
+
+    def boxes(self) -> np.ndarray:
+        out = np.zeros((self.N, 3), np.int32)
+        _check(_lib.bie_far_boxes(self._h, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.bie_far_destroy(self._h)
             self._h = None
 
     def __del__(self):

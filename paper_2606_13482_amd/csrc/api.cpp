@@ -390,6 +390,46 @@ int bie_rcs(const bie_op *op, const void *X, int64_t R, const double *obs, int64
     });
 }
 
+int bie_far_create(const bie_op *op, const bie_far_opts *opts, void *stream, bie_far **out)
+{
+    return guarded([&]() -> int {
+        if (!op || !opts || !out) return fail(BIE_EINVAL, "NULL argument");
+        *out = nullptr;
+        *out = bie::far_create(op, opts->box, opts->s, opts->p, as_stream(stream));
+        return BIE_OK;
+    });
+}
+
+int bie_far_apply(bie_far *far, const void *X, void *Y, int64_t R, void *stream)
+{
+    return guarded([&]() -> int {
+        if (!far || !X || !Y) return fail(BIE_EINVAL, "NULL argument");
+        if (R < 0 || R > 64) return fail(BIE_EINVAL, "R out of range (0..64)");
+        if (R == 0) return BIE_OK;
+        bie::far_apply(far, X, Y, R, as_stream(stream));
+        return BIE_OK;
+    });
+}
+
+int bie_far_get_info(const bie_far *far, bie_far_info *info)
+{
+    if (!far || !info) return fail(BIE_EINVAL, "NULL argument");
+    bie::far_info(far, info);
+    return BIE_OK;
+}
+
+int bie_far_boxes(const bie_far *far, int32_t *out)
+{
+    if (!far || !out) return fail(BIE_EINVAL, "NULL argument");
+    bie::far_boxes(far, out);
+    return BIE_OK;
+}
+
+void bie_far_destroy(bie_far *far)
+{
+    if (far) bie::far_destroy(far);
+}
+
 int bie_ws_train(const bie_op *op, const double *feats, const double *pols, const void *X, int64_t S,
                  const bie_ws_opts *opts, void *stream, bie_ws **out)
 {

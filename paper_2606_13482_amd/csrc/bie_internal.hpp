@@ -115,6 +115,7 @@ __host__ __device__ inline void tile_decode(int64_t b, int64_t nT, int64_t &I, i
 }  // namespace bie
 
 struct bie_ws;   // learned warm start (warmstart.hip)
+struct bie_far;  // single-level B-spline far field (bspline.hip)
 
 struct bie_op {
     int device = 0;
@@ -177,6 +178,8 @@ void add_into(int64_t n, const void *a, void *x, hipStream_t s);   // x += a (n 
 void zero_into(int64_t n, void *x, hipStream_t s);
 
 // fill.hip
+constexpr int QPTS = 7;               // points of the triangle rule (Radon's degree-5 rule)
+void quad_weights(double *w);         // its weights, relative to the triangle area
 void upload_triangles(bie_op *op, hipStream_t s);
 void fill_matrix(bie_op *op, bool fp64_regular, bool want64, bool want32, hipStream_t s);
 void rhs_planewave(const bie_op *op, const double *dirs, const double *pols, int64_t R, void *B,
@@ -255,6 +258,13 @@ void ws_save(const bie_ws *w, const char *path);
 bie_ws *ws_load(const bie_op *op, const char *path);
 void ws_destroy(bie_ws *w);
 void ws_info(const bie_ws *w, int64_t *K, int64_t *H, int64_t *nparams, double *scale, double *loss, double *sigma);
+
+// bspline.hip
+bie_far *far_create(const bie_op *op, double a, int s, int p, hipStream_t st);
+void far_apply(bie_far *f, const void *X, void *Y, int64_t R, hipStream_t st);
+void far_info(const bie_far *f, bie_far_info *info);
+void far_boxes(const bie_far *f, int32_t *out);
+void far_destroy(bie_far *f);
 
 // krylov.hip
 int solve_batch(const bie_op *const *ops, int64_t P, const void *const *B, void *const *X, const int64_t *R,

@@ -589,6 +589,14 @@ T *dev_alloc(size_t n)
 
 }  // namespace
 
+// Weights of the triangle rule (relative to the area), for other kernels that
+// integrate over the same quadrature points.
+void quad_weights(double *w)
+{
+    const Rule rule = make_rule();
+    for (int i = 0; i < NQ; ++i) w[i] = rule.w[i];
+}
+
 // Per-triangle tables on the device.  Quadrature points and free vertices
 // relative to the triangle centroid (keeps FP32 local arithmetic accurate).
 void upload_triangles(bie_op *op, hipStream_t s)

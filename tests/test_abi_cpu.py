@@ -84,7 +84,8 @@ def test_struct_layouts_match_header(tmp_path):
     if shutil.which("gcc") is None:
         pytest.skip("gcc not available")
     structs = {"bie_fill_opts": bie.FillOpts, "bie_solve_opts": bie.SolveOpts, "bie_solve_stat": bie.SolveStat,
-               "bie_ws_opts": bie.WsOpts, "bie_calderon_info": bie.CalderonInfo}
+               "bie_ws_opts": bie.WsOpts, "bie_calderon_info": bie.CalderonInfo, "bie_far_opts": bie.FarOpts,
+               "bie_far_info": bie.FarInfo}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "bie.h"', 'int main(void) {']
     for cname, py in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')

@@ -1,0 +1,102 @@
+"""The single-level B-spline far field on the GPU (bie_far_*) against the
+oracle (oracle/bspline.py): the same cubes (integer-equal), the same buffer,
+the far product to FP64 rounding, and both within the interpolation error of
+the dense oracle's far entries."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import bspline as bs
+from oracle import cfill, efie
+from oracle.mesh import flagged_pairs, rwg_table
+from paper_2606_13482_amd.inputs import complex_gaussian, icosphere
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.parametrize("p,s", [(3, 8), (1, 6), (5, 10)])
+def test_far_product_matches_oracle(bie, p, s):
+    V, T = icosphere(3)
+    rwg = rwg_table(V, T)
+    k, a = 2.0, 0.7
+    op = bie.Operator(V, T, k)
+    far = bie.FarField(op, a, s, p)
+    info = far.info()
+    idx, lo, prot, origin = bs.box_level(rwg, a)
+    assert np.array_equal(far.boxes(), idx)
+    assert abs(info["protrusion"] - prot) <= 1e-12 and info["buffer_knots"] == bs.buffer_knots(prot, s, p)
+    X = complex_gaussian(op.N, 21, cols=3)
+    Y = far.apply(torch.from_numpy(X).cuda()).cpu().numpy()
+    Yo, oi = bs.far_product(rwg, k, X, a, s, p)
+    err = np.linalg.norm(Y - Yo) / np.linalg.norm(Yo)
+    Y1 = far.apply(torch.from_numpy(X[1:2].copy()).cuda()).cpu().numpy()[0]
+    msg = f"  p={p} s={s}: {info['boxes']} cubes, {info['far_pairs']} far pairs, buffer {info['buffer_knots']}, " \
+          f"{info['points_per_axis']} points per axis; GPU vs oracle {err:.2e}"
+    if p == 3:
+        Z = cfill.fill(rwg, k)
+        F = bs.far_mask(oi["inv"], oi["far"])
+        Yd = X @ (Z * F).T
+        e_dense = np.linalg.norm(Y - Yd) / np.linalg.norm(Yd)
+        msg += f", vs dense far entries {e_dense:.2e}"
+        assert e_dense <= 1e-3
+    _say(msg)
+    assert err <= 1e-12
+    assert np.array_equal(Y1, Y[1])          # columns are independent
+    far.close()
+    op.close()
+
+
+def test_far_product_workload_sphere(bie):
+    """The 7680-unknown sphere at k = 10 with cubes of 0.4 m (s = 8, p = 3): the GPU
+    far product on two sampled target cubes against the oracle's interpolated
+    blocks, and on sampled rows against the dense oracle's far entries."""
+    V, T = icosphere(4)
+    rwg = rwg_table(V, T)
+    k, a, s, p = 10.0, 0.4, 8, 3
+    op = bie.Operator(V, T, k)
+    far = bie.FarField(op, a, s, p)
+    info = far.info()
+    x = complex_gaussian(op.N, 22)
+    y = far.apply(torch.from_numpy(x).cuda().reshape(1, -1)).cpu().numpy()[0]
+    idx, lo, prot, origin = bs.box_level(rwg, a)
+    assert np.array_equal(far.boxes(), idx)
+    sb = bs.buffer_knots(prot, s, p)
+    sp = bs.BoxSplines(s, p, sb)
+    boxes, inv, farm = bs.far_pairs(idx)
+    members = [np.nonzero(inv == b)[0] for b in range(len(boxes))]
+    rng = np.random.default_rng(5)
+    targets = rng.choice(len(boxes), 2, replace=False)
+    mt = bs.moments(rwg, sp, a, lo)
+    box_lo = origin + boxes * a
+    err_o, err_d = [], []
+    flags = flagged_pairs(rwg, 2.0)
+    for t in targets:
+        rows = members[t]
+        yo = np.zeros(rows.size, np.complex128)
+        for b in np.nonzero(farm[t])[0]:
+            yo += bs.far_block(mt, rows, members[b], sp, a, box_lo[t], box_lo[b], k) @ x[members[b]]
+        err_o.append(np.linalg.norm(y[rows] - yo) / np.linalg.norm(yo))
+        sample = rows[:3]
+        Zr = efie.fill_rows(rwg, k, sample, flags=flags)
+        fcols = np.isin(inv, np.nonzero(farm[t])[0])
+        yd = Zr[:, fcols] @ x[fcols]
+        err_d.append(np.linalg.norm(y[sample] - yd) / np.linalg.norm(yd))
+    _say(f"  7680 unknowns, k = 10, cubes 0.4 m: {info['boxes']} cubes, {info['far_pairs']} far pairs, buffer "
+         f"{info['buffer_knots']}; GPU vs oracle {max(err_o):.2e}, vs dense far entries {max(err_d):.2e}")
+    assert max(err_o) <= 1e-12
+    assert max(err_d) <= 5e-3
+    far.close()
+    op.close()
+
+
+def test_far_rejections(bie):
+    V, T = icosphere(2)
+    op = bie.Operator(V, T, 2.0)
+    for box, s, p in ((0.7, 8, 2), (0.7, 3, 3), (-1.0, 8, 3), (0.4, 6, 3)):
+        with pytest.raises(bie.BieError):
+            bie.FarField(op, box, s, p)
+    op.close()
