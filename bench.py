@@ -796,6 +796,25 @@ def counters_probe(args, bie, torch):
     op.close()
 
 
+def autotune_summary(rep: dict) -> dict:
+    """The autotuner's choices by kind: packed-product units per size, the
+    block products' (wave tile, K slices) and K slices counted over the shapes
+    met, and the batch layouts (tiles per unit, columns per item)."""
+    out = {"entries": len(rep)}
+    for kind in ("sym", "gemm_split", "gemm64", "batch"):
+        sel = {k: v for k, v in rep.items() if k.split(":")[0] == kind}
+        if not sel:
+            continue
+        if kind in ("sym", "batch"):
+            out[kind] = sel
+        else:
+            counts = {}
+            for v in sel.values():
+                counts[str(v)] = counts.get(str(v), 0) + 1
+            out[kind] = {"shapes": len(sel), "choices": counts}
+    return out
+
+
 def cpu_baseline(level: int, k: float, restart: int, plain_mvps: float):
     """The oracle (C fill with OpenMP + numpy GMRES) on a bounded sample: the full
     FP64 fill and one GMRES(restart) cycle with all host threads, and one cycle
@@ -905,6 +924,9 @@ def main():
         print(json.dumps({"progress": "uneven batch done"}), file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.level, k, args.restart, plain_mvps)
+    # launch shapes the autotuner chose in this run (packed product units per
+    # size; block products' wave tiles and K slices per shape; batch units)
+    out["autotune"] = autotune_summary(bie.autotune_report())
     print(json.dumps(out), flush=True)
 
 

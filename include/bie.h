@@ -483,6 +483,23 @@ int bie_ws_save(const bie_ws *ws, const char *path);
 int bie_ws_load(const bie_op *op, const char *path, bie_ws **out);
 void bie_ws_destroy(bie_ws *ws);
 
+/* Autotuner (launch shapes chosen by timing on the device): with on != 0 (the
+ * default; the environment variable BIE_AUTOTUNE=0 starts with it off) the
+ * packed product's work units (4, 8 or 16 tiles, or balanced runs) are chosen
+ * per matrix size and precision when an operator is created, and the
+ * split-BF16 block product's wave tiles (128 x 64, 64 x 128, 128 x 128) and K
+ * slices, and the FP64 block product's K slices, per matrix and column shape
+ * at their first launch of that shape (not while the stream is being
+ * captured); each choice is kept for the process (and, with BIE_AUTOTUNE_CACHE
+ * naming a file, appended there and read by later processes).  Off: the fixed
+ * defaults.  The batched solves' units and column groups are chosen the same
+ * way (bie_batch_config).  Results differ between shapes only in the order of
+ * floating-point sums. */
+int bie_autotune(int on);
+/* The choices so far, one line "key value..." each, NUL-terminated into buf
+ * (at most cap bytes, may be NULL); returns the length needed. */
+int64_t bie_autotune_report(char *buf, int64_t cap);
+
 /* Measurement support (not part of the method): with on != 0 every launch of
  * the dense product kernels (from bie_apply and inside bie_solve) is bracketed
  * by HIP events on the stream it runs on.  bie_prof_read waits for the

@@ -118,6 +118,8 @@ SYMBOLS = [
     ("bie_ws_save", ctypes.c_int, [_P, ctypes.c_char_p]),
     ("bie_ws_load", ctypes.c_int, [_P, ctypes.c_char_p, ctypes.POINTER(_P)]),
     ("bie_ws_destroy", None, [_P]),
+    ("bie_autotune", ctypes.c_int, [ctypes.c_int]),
+    ("bie_autotune_report", _I64, [_P, _I64]),
     ("bie_prof_enable", ctypes.c_int, [ctypes.c_int]),
     ("bie_prof_read", ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(_I64)]),
@@ -187,6 +189,24 @@ def prof_read(kernel: int = 0, columns: bool = False):
     n = ctypes.c_int64(); ms = ctypes.c_double(); c = ctypes.c_int64()
     _check(_lib.bie_prof_read(int(kernel), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(c)))
     return (n.value, ms.value, c.value) if columns else (n.value, ms.value)
+
+
+def autotune(on: bool = True):
+    """Autotuner on (default) or off (fixed launch shapes)."""
+    _check(_lib.bie_autotune(int(on)))
+
+
+def autotune_report() -> dict:
+    """Launch shapes chosen so far: {key: [values]}."""
+    n = int(_lib.bie_autotune_report(None, 0))
+    buf = ctypes.create_string_buffer(n)
+    _lib.bie_autotune_report(buf, n)
+    out = {}
+    for line in buf.value.decode().splitlines():
+        parts = line.split()
+        if parts:
+            out[parts[0]] = [int(v) for v in parts[1:]]
+    return out
 
 
 @dataclass

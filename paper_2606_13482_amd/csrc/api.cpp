@@ -108,6 +108,7 @@ int bie_op_create(const double *verts, int64_t nv, const int32_t *tris, int64_t 
             } else {
                 bie::fill_matrix(op, false, false, true, s);          // FP32 regular, FP64 singular
             }
+            if (!bie::setup_pool_active()) bie::tune_packed(op, s);   // work units of the packed product
         } catch (...) {
             destroy_op(op);
             throw;
@@ -557,6 +558,23 @@ int bie_ws_load(const bie_op *op, const char *path, bie_ws **out)
 void bie_ws_destroy(bie_ws *ws)
 {
     if (ws) bie::ws_destroy(ws);
+}
+
+int bie_autotune(int on)
+{
+    bie::tune_set_enabled(on != 0);
+    return BIE_OK;
+}
+
+int64_t bie_autotune_report(char *buf, int64_t cap)
+{
+    const std::string r = bie::tune_report();
+    if (buf && cap > 0) {
+        const size_t n = std::min<size_t>(r.size(), size_t(cap - 1));
+        std::memcpy(buf, r.data(), n);
+        buf[n] = 0;
+    }
+    return int64_t(r.size()) + 1;
 }
 
 int bie_prof_enable(int on)

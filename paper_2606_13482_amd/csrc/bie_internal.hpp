@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <functional>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -79,6 +80,7 @@ struct Packed {
     void *part = nullptr;          // device partial sums of the product, sized for part_R vectors
     int64_t part_R = 0;
     size_t part_elem = 0;          // bytes per complex element of the partials buffer
+    int unit_len = -1;             // tiles per work unit (0: balanced runs)
 };
 // One problem of a grouped (several-operator) packed product.
 struct GProb {
@@ -147,6 +149,19 @@ struct bie_op {
 };
 
 namespace bie {
+
+// tune.cpp: the autotuner's registry of chosen launch shapes.
+bool tune_enabled();
+void tune_set_enabled(bool on);
+bool tune_get(const std::string &key, std::vector<int> &v);
+void tune_put(const std::string &key, const std::vector<int> &v);
+std::string tune_report();
+bool stream_capturing(hipStream_t s);
+float time_launches(hipStream_t s, int reps, const std::function<void()> &fn);
+
+// blas.hip: choose the packed product's work units for the operator by timing
+// (once per matrix size and precision; no-op when tuning is off).
+void tune_packed(bie_op *op, hipStream_t s);
 
 // bgmres.hip: release the block solver's cached buffers of an operator.
 void free_block_cache(bie_op *op);

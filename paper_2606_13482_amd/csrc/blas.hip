@@ -606,15 +606,18 @@ void build_runs(int64_t nT, int64_t nb, std::vector<int32_t> &units, std::vector
     unit_rows(nT, units, uptr, seg);
 }
 
-void packed_setup(Packed &pk, int64_t n)
+// Tables of the packed n x n tiles with units of U tiles (U >= 1) or balanced
+// runs (U = 0).
+static void packed_setup_units(Packed &pk, int64_t n, int U)
 {
     pk.N = n;
     pk.nT = (pk.N + TB - 1) / TB;
     pk.ntiles = pk.nT * (pk.nT + 1) / 2;
+    pk.unit_len = U;
     std::vector<int32_t> units, uptr, rptr;
     std::vector<int64_t> seg;
-    if (unit_tiles() > 0) {
-        build_units(pk.nT, unit_tiles(), units, uptr, seg);
+    if (U > 0) {
+        build_units(pk.nT, U, units, uptr, seg);
         rptr.resize(units.size() / 3 + 1);
         for (size_t b = 0; b < rptr.size(); ++b) rptr[b] = int32_t(b);
     } else {   // 512 runs, or fewer for small matrices: at least 8 tiles per run
@@ -635,6 +638,8 @@ void packed_setup(Packed &pk, int64_t n)
     pk.h_unit_ptr = std::move(uptr);
     pk.h_seg = std::move(seg);
 }
+
+void packed_setup(Packed &pk, int64_t n) { packed_setup_units(pk, n, unit_tiles()); }
 
 void packed_free(Packed &pk)
 {
@@ -674,6 +679,68 @@ static void ensure_part(Packed &pk, int64_t R, hipStream_t s)
     pk.part_R = 0;
     BIE_HIP(hipMalloc(&pk.part, size_t(R) * size_t(pk.nslots) * TB * 16));
     pk.part_R = R;
+}
+
+// The packed product's work units for this operator: the autotuner's choice
+// for (N, matrix precision) among units of 4, 8, 16 tiles and balanced runs,
+// timed (tile pass and reduction of one vector) the first time the size
+// occurs; the operator's tables are rebuilt if the choice is not the default.
+// Fixed by BIE_SYM_UNIT (measurement) or with tuning off.
+void tune_packed(bie_op *op, hipStream_t s)
+{
+    if (op->star || getenv("BIE_SYM_UNIT") || !tune_enabled() || stream_capturing(s)) return;
+    const bool mat64 = op->Z64 != nullptr;
+    const void *Z = mat64 ? op->Z64 : op->Z32;
+    if (!Z) return;
+    const int64_t N = op->mesh.N;
+    const std::string key = "sym:" + std::to_string(N) + (mat64 ? ":f64" : ":f32");
+    std::vector<int> v;
+    if (!tune_get(key, v) || v.size() != 1 || v[0] < 0 || v[0] > 64) {
+        void *x = nullptr, *y = nullptr;
+        BIE_HIP(hipMalloc(&x, size_t(N) * 16));
+        try {
+            BIE_HIP(hipMalloc(&y, size_t(N) * 16));
+            BIE_HIP(hipMemsetAsync(x, 0, size_t(N) * 16, s));
+            float best = 0.f;
+            v = { unit_tiles() };
+            for (int U : { 8, 0, 4, 16 }) {
+                Packed c;
+                try {
+                    packed_setup_units(c, N, U);
+                    ensure_part(c, 1, s);
+                    const float ms = time_launches(s, 3, [&]() {
+                        if (mat64)
+                            launch_product<double, double, false, false>(c, c.part, Z, x, N, y, N, nullptr, 0, 1,
+                                                                         nullptr, 1, s, false);
+                        else
+                            launch_product<float, double, false, false>(c, c.part, Z, x, N, y, N, nullptr, 0, 1,
+                                                                        nullptr, 1, s, false);
+                    });
+                    if (best == 0.f || ms < best) {
+                        best = ms;
+                        v = { U };
+                    }
+                } catch (...) {
+                    packed_free(c);
+                    throw;
+                }
+                packed_free(c);
+            }
+        } catch (...) {
+            (void)hipFree(x);
+            if (y) (void)hipFree(y);
+            throw;
+        }
+        BIE_HIP(hipStreamSynchronize(s));
+        (void)hipFree(x);
+        (void)hipFree(y);
+        tune_put(key, v);
+    }
+    if (v[0] != op->pk.unit_len) {
+        BIE_HIP(hipStreamSynchronize(s));
+        packed_free(op->pk);
+        packed_setup_units(op->pk, N, v[0]);
+    }
 }
 
 // T x (conj: conj(T) x; B: B - T x) for the star-split operator: u = Sigma^T x,

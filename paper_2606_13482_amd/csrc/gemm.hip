@@ -39,6 +39,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <string>
 #include <cstdint>
 #include <cstdlib>
 
@@ -523,15 +524,19 @@ __global__ __launch_bounds__(256) void k_gemm64(const double *__restrict__ A, in
         }
 }
 
-// Slices of K per launch: enough blocks for the 256 compute units, at least
-// 8 stages per slice; BIE_GEMM_SPLITK overrides (measurement).
-int gemm_splitk(int64_t blocks, int64_t nst)
+int env_int(const char *name, int def)
 {
-    static const int env = [] {
-        const char *e = getenv("BIE_GEMM_SPLITK");
-        return e ? atoi(e) : 0;
-    }();
-    int64_t ks = env > 0 ? env : std::max<int64_t>(1, 256 / blocks);
+    const char *e = getenv(name);
+    return e ? atoi(e) : def;
+}
+
+// Slices of K per launch: enough blocks for the 256 compute units, at least
+// 8 stages per slice (the default; the autotuner also tries half and twice);
+// BIE_GEMM_SPLITK overrides (measurement).
+int gemm_splitk(int64_t blocks, int64_t nst, int want = 0)
+{
+    static const int env = env_int("BIE_GEMM_SPLITK", 0);
+    int64_t ks = want > 0 ? want : (env > 0 ? env : std::max<int64_t>(1, 256 / blocks));
     ks = std::min<int64_t>(ks, std::max<int64_t>(1, nst / 8));
     return int(std::max<int64_t>(1, std::min<int64_t>(ks, 64)));
 }
@@ -550,17 +555,70 @@ void launch_split(int terms, dim3 grid, hipStream_t s, const __bf16 *Ah, const _
 typedef void (*SplitLaunch)(int, dim3, hipStream_t, const __bf16 *, const __bf16 *, const __bf16 *, const __bf16 *,
                             int64_t, int64_t, int64_t, float *);
 // wave tiles of the 256 x 256 block: 128 x 64 (default), 64 x 128, 128 x 128
-// (accumulators in AGPRs); BIE_GEMM_CFG = 0, 1, 2 selects one (measurement)
+// (accumulators in AGPRs); BIE_GEMM_CFG = 0, 1, 2 fixes one (measurement),
+// else the autotuner picks per shape
 const SplitLaunch kSplitLaunch[] = { launch_split<128, 64, 4>, launch_split<64, 128, 4>, launch_split<128, 128, 4> };
+constexpr int kSplitCfgs = int(sizeof(kSplitLaunch) / sizeof(kSplitLaunch[0]));
 
-SplitLaunch split_launch()
+int split_cfg_env()
 {
-    static const int idx = [] {
-        const char *e = getenv("BIE_GEMM_CFG");
-        const int v = e ? atoi(e) : 0;
-        return v >= 0 && v < int(sizeof(kSplitLaunch) / sizeof(kSplitLaunch[0])) ? v : 0;
-    }();
-    return kSplitLaunch[idx];
+    static const int v = env_int("BIE_GEMM_CFG", -1);
+    return v >= 0 && v < kSplitCfgs ? v : -1;
+}
+
+// Wave-tile form and K slices of a split-BF16 product of this shape: the
+// environment's if set; else the autotuner's choice for (Mp, Kp, NCp, terms),
+// timing every form with the default, half and twice the default K slices on
+// the staged operands the first time the shape occurs (not while the stream is
+// being captured); else the defaults.
+void split_choice(int64_t Mp, int64_t Kp, int64_t NCp, int terms, hipStream_t s, const __bf16 *Ah, const __bf16 *Al,
+                  const __bf16 *Bh, const __bf16 *Bl, bie_op *op, int &cfg, int &ks)
+{
+    const int64_t blocks = (Mp / GBM) * (NCp / GBN), nst = Kp / GBK;
+    cfg = split_cfg_env();
+    ks = gemm_splitk(blocks, nst);
+    const bool env_fixed = cfg >= 0 || env_int("BIE_GEMM_SPLITK", 0) > 0;
+    if (cfg < 0) cfg = 0;
+    if (env_fixed || !tune_enabled() || stream_capturing(s)) return;
+    const std::string key = "gemm_split:" + std::to_string(Mp) + "x" + std::to_string(Kp) + ":" +
+                            std::to_string(NCp) + ":t" + std::to_string(terms);
+    std::vector<int> v;
+    if (!tune_get(key, v) || v.size() != 2 || v[0] < 0 || v[0] >= kSplitCfgs || v[1] < 1) {
+        std::vector<int> kss;
+        for (int want : { ks / 2, ks, 2 * ks }) {
+            const int k2 = gemm_splitk(blocks, nst, std::max(1, want));
+            if (std::find(kss.begin(), kss.end(), k2) == kss.end()) kss.push_back(k2);
+        }
+        const int kmax = *std::max_element(kss.begin(), kss.end());
+        const size_t pelems = size_t(kmax) * size_t(Mp) * size_t(NCp);
+        if (op->gemm_part_elems < pelems) {
+            BIE_HIP(hipStreamSynchronize(s));
+            if (op->gemm_part) (void)hipFree(op->gemm_part);
+            op->gemm_part = nullptr;
+            op->gemm_part_elems = 0;
+            BIE_HIP(hipMalloc(&op->gemm_part, pelems * sizeof(float)));
+            op->gemm_part_elems = pelems;
+        }
+        float *P = static_cast<float *>(op->gemm_part);
+        float best = 0.f;
+        v = { 0, ks };
+        for (int c = 0; c < kSplitCfgs; ++c)
+            for (int k2 : kss) {
+                // the split-K reduction reads KS partial tiles: charged at 5 TB/s
+                const float red = float(double(k2) * Mp * NCp * 4.0 / 5e12 * 1e3);
+                const float ms = time_launches(s, 2, [&]() {
+                    kSplitLaunch[c](terms, dim3(unsigned(Mp / GBM), unsigned(NCp / GBN), unsigned(k2)), s, Ah, Al, Bh,
+                                    Bl, Kp, Mp, NCp, P);
+                }) + red;
+                if (best == 0.f || ms < best) {
+                    best = ms;
+                    v = { c, k2 };
+                }
+            }
+        tune_put(key, v);
+    }
+    cfg = v[0];
+    ks = v[1];
 }
 
 }  // namespace
@@ -604,20 +662,8 @@ void gemm_product(const bie_op *opc, const void *X, int64_t ldx, int vtype, void
         BIE_HIP(hipMalloc(&op->Bbf, 2 * plane * sizeof(__bf16)));
         op->bstage_cols = NCp;
     }
-    const int64_t blocks = (Mp / GBM) * (NCp / GBN);
-    const int KS = gemm_splitk(blocks, Kp / GBK);
-    const size_t pelems = size_t(KS) * size_t(Mp) * size_t(NCp);
-    if (op->gemm_part_elems < pelems) {
-        BIE_HIP(hipStreamSynchronize(s));
-        if (op->gemm_part) (void)hipFree(op->gemm_part);
-        op->gemm_part = nullptr;
-        op->gemm_part_elems = 0;
-        BIE_HIP(hipMalloc(&op->gemm_part, pelems * sizeof(float)));
-        op->gemm_part_elems = pelems;
-    }
     __bf16 *Bh = static_cast<__bf16 *>(op->Bbf), *Bl = Bh + plane;
     const __bf16 *Ah = static_cast<const __bf16 *>(op->Abf), *Al = Ah + size_t(Mp) * size_t(Kp);
-    float *P = static_cast<float *>(op->gemm_part);
     const int64_t btiles = (NCp / 32) * (Kp / GBK);
     const dim3 sgrid(unsigned((btiles + 3) / 4));
     if (vtype == VEC_F16)
@@ -629,9 +675,21 @@ void gemm_product(const bie_op *opc, const void *X, int64_t ldx, int vtype, void
     else
         hipLaunchKernelGGL(k_split_vectors<double2>, sgrid, dim3(256), 0, s, (const double2 *)X, ldx, cols, N, R, NCp,
                            Kp, Bh, Bl, terms == 3);
+    int cfg = 0, KS = 1;
+    split_choice(Mp, Kp, NCp, terms, s, Ah, Al, Bh, Bl, op, cfg, KS);
+    const size_t pelems = size_t(KS) * size_t(Mp) * size_t(NCp);
+    if (op->gemm_part_elems < pelems) {
+        BIE_HIP(hipStreamSynchronize(s));
+        if (op->gemm_part) (void)hipFree(op->gemm_part);
+        op->gemm_part = nullptr;
+        op->gemm_part_elems = 0;
+        BIE_HIP(hipMalloc(&op->gemm_part, pelems * sizeof(float)));
+        op->gemm_part_elems = pelems;
+    }
+    float *P = static_cast<float *>(op->gemm_part);
     prof_begin(1, s, R);
-    split_launch()(terms, dim3(unsigned(Mp / GBM), unsigned(NCp / GBN), unsigned(KS)), s, Ah, Al, Bh, Bl, Kp, Mp,
-                   NCp, P);
+    kSplitLaunch[cfg](terms, dim3(unsigned(Mp / GBM), unsigned(NCp / GBN), unsigned(KS)), s, Ah, Al, Bh, Bl, Kp, Mp,
+                      NCp, P);
     prof_end(1, s);
     hipLaunchKernelGGL(k_gemm_reduce<float>, dim3(unsigned(Mp / 64), unsigned(NCp / 64)), dim3(256), 0, s, P, KS, Mp,
                        NCp, N, R, cols, (double2 *)Y, ldy, (const double2 *)Bsub, ldb);
@@ -681,8 +739,46 @@ void gemm64_product(const bie_op *opc, const void *X, int64_t ldx, void *Y, int6
     dense64_setup(op, s);
     const int64_t N = op->mesh.N, Mp = op->d64_Mp, Kp = op->d64_Kp, NCp = (2 * R + DBN - 1) / DBN * DBN;
     const int64_t blocks = (Mp / DBM) * (NCp / DBN), nst = Kp / DBK;
-    int64_t ks = std::max<int64_t>(1, 256 / blocks);
-    ks = std::max<int64_t>(1, std::min<int64_t>({ ks, nst / 16, 64 }));
+    auto clampks = [&](int64_t want) { return std::max<int64_t>(1, std::min<int64_t>({ want, nst / 16, 64 })); };
+    int64_t ks = clampks(std::max<int64_t>(1, 256 / blocks));
+    // K slices: the autotuner's choice for (Mp, Kp, NCp) among half, the
+    // default and twice the default, timed the first time the shape occurs
+    if (tune_enabled() && !stream_capturing(s)) {
+        const std::string key = "gemm64:" + std::to_string(Mp) + "x" + std::to_string(Kp) + ":" + std::to_string(NCp);
+        std::vector<int> v;
+        if (!tune_get(key, v) || v.size() != 1 || v[0] < 1) {
+            std::vector<int64_t> kss;
+            for (int64_t want : { ks / 2, ks, 2 * ks }) {
+                const int64_t k2 = clampks(std::max<int64_t>(1, want));
+                if (std::find(kss.begin(), kss.end(), k2) == kss.end()) kss.push_back(k2);
+            }
+            const size_t pmax = size_t(*std::max_element(kss.begin(), kss.end())) * size_t(Mp) * size_t(NCp);
+            if (op->d64_part_elems < pmax) {
+                BIE_HIP(hipStreamSynchronize(s));
+                if (op->d64_part) (void)hipFree(op->d64_part);
+                op->d64_part = nullptr;
+                op->d64_part_elems = 0;
+                BIE_HIP(hipMalloc(&op->d64_part, pmax * sizeof(double)));
+                op->d64_part_elems = pmax;
+            }
+            double *Pt = static_cast<double *>(op->d64_part);
+            float best = 0.f;
+            v = { int(ks) };
+            for (int64_t k2 : kss) {
+                const float red = float(double(k2) * Mp * NCp * 8.0 / 5e12 * 1e3);
+                const float ms = time_launches(s, 2, [&]() {
+                    hipLaunchKernelGGL(k_gemm64, dim3(unsigned(Mp / DBM), unsigned(NCp / DBN), unsigned(k2)), dim3(256), 0,
+                                       s, (const double *)op->A64, Kp, N, (const double2 *)X, ldx, cols, R, Mp, NCp, Pt);
+                }) + red;
+                if (best == 0.f || ms < best) {
+                    best = ms;
+                    v = { int(k2) };
+                }
+            }
+            tune_put(key, v);
+        }
+        ks = clampks(v[0]);
+    }
     const size_t pelems = size_t(ks) * size_t(Mp) * size_t(NCp);
     if (op->d64_part_elems < pelems) {
         BIE_HIP(hipStreamSynchronize(s));

@@ -28,6 +28,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <fstream>
 #include <map>
@@ -1806,39 +1807,28 @@ std::unique_ptr<GLayout> make_layout(const bie_op *const *ops, int64_t P, const 
     return L;
 }
 
-// Autotuner cache: batch shape -> tiles per unit (in memory; also appended to
-// the file named by BIE_AUTOTUNE_CACHE and read from it on first use).
-std::mutex g_tune_mu;
-std::map<std::string, std::pair<int, int>> g_tune;   // (U, G)
-bool g_tune_loaded = false;
-
+// Autotuner choices of batched solves: batch shape -> (tiles per unit,
+// columns per item), kept in the library's tuning registry (tune.cpp).
+// The key names the precision, the number of operators and right-hand sides,
+// and a 64-bit FNV-1a hash of the (N_p, R_p) list.
 std::string batch_key(const bie_op *const *ops, int64_t P, const int64_t *R, bool mat64)
 {
-    std::string k = mat64 ? "f64" : "f32";
-    for (int64_t p = 0; p < P; ++p) k += ":" + std::to_string(ops[p]->mesh.N) + "x" + std::to_string(R[p]);
-    return k;
-}
-
-void tune_cache_load()
-{
-    if (g_tune_loaded) return;
-    g_tune_loaded = true;
-    const char *path = getenv("BIE_AUTOTUNE_CACHE");
-    if (!path) return;
-    std::ifstream f(path);
-    std::string key;
-    int U, G;
-    while (f >> key >> U >> G)
-        if (U >= 1 && U <= 64 && G >= 1 && G <= 4096) g_tune[key] = { U, G };
-}
-
-void tune_cache_store(const std::string &key, int U, int G)
-{
-    g_tune[key] = { U, G };
-    if (const char *path = getenv("BIE_AUTOTUNE_CACHE")) {
-        std::ofstream f(path, std::ios::app);
-        f << key << " " << U << " " << G << "\n";
+    uint64_t h = 1469598103934665603ull;
+    int64_t nr = 0;
+    auto mix = [&](int64_t v) {
+        for (int b = 0; b < 8; ++b) {
+            h ^= uint64_t(v >> (8 * b)) & 0xff;
+            h *= 1099511628211ull;
+        }
+    };
+    for (int64_t p = 0; p < P; ++p) {
+        mix(ops[p]->mesh.N);
+        mix(R[p]);
+        nr += R[p];
     }
+    char hex[17];
+    snprintf(hex, sizeof hex, "%016llx", (unsigned long long)h);
+    return std::string(mat64 ? "batch:f64" : "batch:f32") + ":P" + std::to_string(P) + ":R" + std::to_string(nr) + ":" + hex;
 }
 
 }  // namespace
@@ -1947,13 +1937,12 @@ int solve_batch(const bie_op *const *ops, int64_t P, const void *const *Bp, void
     std::unique_ptr<GLayout> L;
     const std::string key = batch_key(ops, P, Rp, mat64);
     int U = g_batch.unit, G = 8;
+    if (U == 0 && !tune_enabled()) U = 8;   // tuning off: the fixed default units
     if (U == 0) {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        tune_cache_load();
-        auto it = g_tune.find(key);
-        if (it != g_tune.end()) {
-            U = it->second.first;
-            G = it->second.second;
+        std::vector<int> v;
+        if (tune_get(key, v) && v.size() == 2 && v[0] >= 1 && v[0] <= 64 && v[1] >= 1 && v[1] <= 4096) {
+            U = v[0];
+            G = v[1];
         }
     }
     auto layout_cols = [&](const GLayout &gl, const int64_t *xoff, int64_t xstep) {
@@ -1987,8 +1976,7 @@ int solve_batch(const bie_op *const *ops, int64_t P, const void *const *Bp, void
             }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        tune_cache_store(key, L->U, L->G);
+        tune_put(key, { L->U, L->G });
     } else {
         L = make_layout(ops, P, Rp, U, G, mat64);
     }
@@ -2229,9 +2217,9 @@ void batch_config(int unit, int graph)
 
 int batch_unit_chosen(const bie_op *const *ops, int64_t P, const int64_t *R)
 {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tune.find(batch_key(ops, P, R, ops[0]->Z64 != nullptr));
-    return it == g_tune.end() ? 0 : it->second.first;
+    std::vector<int> v;
+    if (!tune_get(batch_key(ops, P, R, ops[0]->Z64 != nullptr), v) || v.empty()) return 0;
+    return v[0];
 }
 
 int solve(const bie_op *op, const void *B, void *X, int64_t R, const bie_solve_opts &o, bie_solve_stat *stats,
