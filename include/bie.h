@@ -256,9 +256,14 @@ int bie_solve(const bie_op *op, const void *B, void *X, int64_t R, const bie_sol
               bie_solve_stat *stats, void *stream);
 
 /* Batched solves: the right-hand sides of nops operators of different sizes
- * (meshes, wavenumbers) solved together with GMRES(m) on the stored matrices
- * (all FP64 or all FP32) to the standard criterion (method BIE_GMRES,
- * precision 0, crit BIE_SCC; other options as in bie_solve, use_x0 0/1/2).
+ * (meshes, wavenumbers) solved together with GMRES(m) to the standard
+ * criterion (method BIE_GMRES, crit BIE_SCC; other options as in bie_solve,
+ * use_x0 0/1/2).  Precision 0: products with the stored matrices (all FP64 or
+ * all FP32), residuals on the same.  Precision 1 (every operator stored as
+ * BIE_C64 with keep_fp64): the Arnoldi products on the FP32 tiles, every
+ * residual -- the vector each restart cycle starts from and the criterion --
+ * on the FP64 tiles, so a cycle is one step of iterative refinement and the
+ * criterion is certified in FP64.
  * Every right-hand side keeps its own Krylov basis, Hessenberg matrix and
  * criterion; the products of all operators share one grouped launch per
  * iteration and each restart cycle is replayed as one captured HIP graph.
@@ -273,6 +278,22 @@ int bie_solve(const bie_op *op, const void *B, void *X, int64_t R, const bie_sol
 int bie_batch_solve(const bie_op *const *ops, int64_t nops, const void *const *B, void *const *X,
                     const int64_t *R, const bie_solve_opts *opts, bie_solve_stat *stats, void *stream);
 
+/* Batched solves as bie_batch_solve, right-preconditioned per operator with the
+ * multiplicative Calderon preconditioner of Sec. VI-A and VII (M = -G^-1 T_BC
+ * G^-T, see bie_calderon_create): GMRES on T_p M_p u = b with x = M_p u, so residuals and
+ * criterion stay those of T_p x = b.  Each Arnoldi step forms T (M v) with two
+ * grouped launches (M of every operator, then T); each cycle ends with
+ * x += M (V y).  M is applied in the precision of the Arnoldi products: its
+ * FP64 tiles with FP64 matrices, an FP32 copy of them (made on first use and
+ * kept with the preconditioner) with FP32 matrices or precision 1.
+ *   pcs    host array of nops preconditioners, pcs[p] built for ops[p]; NULL
+ *          gives bie_batch_solve.  opts->calderon must be NULL.
+ * Other arguments, results and errors as in bie_batch_solve; BIE_EINVAL for a
+ * NULL entry or a preconditioner built for another operator. */
+int bie_batch_solve_pc(const bie_op *const *ops, const struct bie_calderon *const *pcs, int64_t nops,
+                       const void *const *B, void *const *X, const int64_t *R, const bie_solve_opts *opts,
+                       bie_solve_stat *stats, void *stream);
+
 /* Batched solves, for measurement and tests: tiles per work unit of the
  * grouped product (0, the default: tiles per unit in {4, 8, 16} and columns per
  * work item in {4, 8, 32} chosen per batch shape by timing the candidates on
@@ -282,7 +303,9 @@ int bie_batch_solve(const bie_op *const *ops, int64_t nops, const void *const *B
  * which makes every column bitwise equal to its single solve) and graph replay
  * (1: default).  BIE_EINVAL outside -1..64. */
 int bie_batch_config(int unit_tiles, int use_graph);
-/* Tiles per unit chosen for this batch shape so far (0: none). */
+/* Tiles per unit chosen for this batch shape so far (0: none); for operators
+ * holding both matrices, the choice for FP64 products if one was made, else the
+ * one for FP32 products. */
 int bie_batch_tuned(const bie_op *const *ops, int64_t nops, const int64_t *R);
 
 /* ---------------------------------------------------------------------------

@@ -96,6 +96,7 @@ SYMBOLS = [
     ("bie_farfield", ctypes.c_int, [_P, _P, _I64, _P, _I64, _P, _P]),
     ("bie_rcs", ctypes.c_int, [_P, _P, _I64, _P, _I64, _P, _P]),
     ("bie_batch_solve", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P]),
+    ("bie_batch_solve_pc", ctypes.c_int, [_P, _P, _I64, _P, _P, _P, _P, _P, _P]),
     ("bie_batch_config", ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
     ("bie_batch_tuned", ctypes.c_int, [_P, _I64, _P]),
     ("bie_rscc_rows", ctypes.c_int, [_I64, _I64, ctypes.c_uint64, _P]),
@@ -427,11 +428,15 @@ class FarField:
             pass
 
 
-def batch_solve(ops, Bs, opts: Solve | None = None, x0s=None, x0_fallback: bool = False, stream=None):
+def batch_solve(ops, Bs, opts: Solve | None = None, x0s=None, x0_fallback: bool = False, stream=None,
+                pcs=None):
     """Solve T_p X_p = B_p for several operators at once (bie_batch_solve):
-    grouped products, one captured graph per restart cycle.  Returns the list of
+    grouped products, one captured graph per restart cycle.  pcs: one Calderon
+    preconditioner per operator (bie_batch_solve_pc).  Returns the list of
     solutions and the list of per-operator statistics lists."""
     opts = opts or Solve()
+    if opts.calderon is not None:
+        raise ValueError("batched solves take their preconditioners per operator (pcs=...)")
     P = len(ops)
     Bs = [b.reshape(-1, op.N) for b, op in zip(Bs, ops)]
     R = np.array([b.shape[0] for b in Bs], np.int64)
@@ -445,8 +450,15 @@ def batch_solve(ops, Bs, opts: Solve | None = None, x0s=None, x0_fallback: bool 
     st = (SolveStat * int(max(1, R.sum())))()
     use = 0 if x0s is None else (2 if x0_fallback else 1)
     co = opts.c(use)
-    rc = _lib.bie_batch_solve(oph, P, bp, xp, R.ctypes.data_as(ctypes.c_void_p), ctypes.byref(co), st,
-                              _stream(stream))
+    if pcs is None:
+        rc = _lib.bie_batch_solve(oph, P, bp, xp, R.ctypes.data_as(ctypes.c_void_p), ctypes.byref(co), st,
+                                  _stream(stream))
+    else:
+        if len(pcs) != P:
+            raise ValueError("one preconditioner per operator")
+        pch = (ctypes.c_void_p * P)(*[pc._h.value for pc in pcs])
+        rc = _lib.bie_batch_solve_pc(oph, pch, P, bp, xp, R.ctypes.data_as(ctypes.c_void_p), ctypes.byref(co), st,
+                                     _stream(stream))
     _check(rc, allow_nc=True)
     out, k = [], 0
     for r in R:

@@ -312,17 +312,18 @@ int bie_calderon_get_info(const bie_calderon *pc, bie_calderon_info *info)
 
 void bie_calderon_destroy(bie_calderon *pc) { bie::calderon_destroy(pc); }
 
-int bie_batch_solve(const bie_op *const *ops, int64_t nops, const void *const *B, void *const *X,
-                    const int64_t *R, const bie_solve_opts *opts, bie_solve_stat *stats, void *stream)
+int bie_batch_solve_pc(const bie_op *const *ops, const bie_calderon *const *pcs, int64_t nops,
+                       const void *const *B, void *const *X, const int64_t *R, const bie_solve_opts *opts,
+                       bie_solve_stat *stats, void *stream)
 {
     return guarded([&]() -> int {
         if (!ops || !B || !X || !R) return fail(BIE_EINVAL, "NULL argument");
         if (nops < 1 || nops > 4096) return fail(BIE_EINVAL, "nops out of range (1..4096)");
         bie_solve_opts o{ BIE_GMRES, 30, 1e-6, 10000, BIE_SCC, 512, 1234, 0, 0, 0.0, 0, 0, 0, 0, nullptr };
         if (opts) o = *opts;
-        if (o.method != BIE_GMRES || o.precision != 0 || o.crit != BIE_SCC || o.basis != 0)
-            return fail(BIE_EINVAL, "batched solves take GMRES, precision 0 and the standard criterion");
-        if (o.calderon) return fail(BIE_EINVAL, "batched solves take no preconditioner");
+        if (o.method != BIE_GMRES || (o.precision != 0 && o.precision != 1) || o.crit != BIE_SCC || o.basis != 0)
+            return fail(BIE_EINVAL, "batched solves take GMRES, precision 0 or 1 and the standard criterion");
+        if (o.calderon) return fail(BIE_EINVAL, "batched solves take their preconditioners per operator (pcs)");
         if (o.restart < 1 || o.restart > 64) return fail(BIE_EINVAL, "restart must be 1..64");
         if (!(o.tol > 0.0)) return fail(BIE_EINVAL, "tol must be > 0");
         if (o.max_mvp < 1) return fail(BIE_EINVAL, "max_mvp must be >= 1");
@@ -332,6 +333,9 @@ int bie_batch_solve(const bie_op *const *ops, int64_t nops, const void *const *B
         for (int64_t p = 0; p < nops; ++p) {
             if (!ops[p]) return fail(BIE_EINVAL, "NULL operator");
             if (ops[p]->star) return fail(BIE_EINVAL, "batched solves take assembled operators");
+            if (pcs && !pcs[p]) return fail(BIE_EINVAL, "NULL preconditioner");
+            if (pcs && bie::calderon_operator(pcs[p]) != ops[p])
+                return fail(BIE_EINVAL, "a preconditioner was built for another operator");
             if (R[p] < 0 || R[p] > 4096) return fail(BIE_EINVAL, "R out of range (0..4096)");
             if (R[p] > 0 && (!B[p] || !X[p])) return fail(BIE_EINVAL, "NULL vector pointer");
             total += R[p];
@@ -342,10 +346,16 @@ int bie_batch_solve(const bie_op *const *ops, int64_t nops, const void *const *B
         }
         if (total == 0) return BIE_OK;
         if (total > 65535) return fail(BIE_EINVAL, "at most 65535 right-hand sides per batch");
-        const int rc = bie::solve_batch(ops, nops, B, X, R, o, stats, s);
+        const int rc = bie::solve_batch(ops, pcs, nops, B, X, R, o, stats, s);
         if (rc == BIE_NOT_CONVERGED) g_err = "not converged within max_mvp";
         return rc;
     });
+}
+
+int bie_batch_solve(const bie_op *const *ops, int64_t nops, const void *const *B, void *const *X,
+                    const int64_t *R, const bie_solve_opts *opts, bie_solve_stat *stats, void *stream)
+{
+    return bie_batch_solve_pc(ops, nullptr, nops, B, X, R, opts, stats, stream);
 }
 
 int bie_batch_config(int unit_tiles, int use_graph)

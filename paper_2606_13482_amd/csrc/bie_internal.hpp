@@ -180,6 +180,7 @@ const bie_calderon_info &calderon_info(const bie_calderon *pc);
 // The operator holding M (packed FP64 tiles), for products through the library's
 // kernels; split: also its split-BF16 copy (made on first use).
 bie_op *calderon_view(const bie_calderon *pc, bool split, hipStream_t s);
+bie_op *calderon_view32(const bie_calderon *pc, hipStream_t s);
 // The product T M as one dense operator (split-BF16 copy only), for the block
 // products of the preconditioned inner solves; made by bie_calderon_create when
 // the operator has a split-BF16 copy, else on first use.
@@ -282,8 +283,8 @@ void far_boxes(const bie_far *f, int32_t *out);
 void far_destroy(bie_far *f);
 
 // krylov.hip
-int solve_batch(const bie_op *const *ops, int64_t P, const void *const *B, void *const *X, const int64_t *R,
-                const bie_solve_opts &o, bie_solve_stat *stats, hipStream_t s);
+int solve_batch(const bie_op *const *ops, const bie_calderon *const *pcs, int64_t P, const void *const *B,
+                void *const *X, const int64_t *R, const bie_solve_opts &o, bie_solve_stat *stats, hipStream_t s);
 void batch_config(int unit, int graph);
 int batch_unit_chosen(const bie_op *const *ops, int64_t P, const int64_t *R);
 int solve(const bie_op *op, const void *B, void *X, int64_t R, const bie_solve_opts &o,

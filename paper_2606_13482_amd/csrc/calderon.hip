@@ -848,6 +848,22 @@ bie_op *calderon_view(const bie_calderon *pc, bool split, hipStream_t s)
     return pc->view;
 }
 
+// The operator holding M with an FP32 copy of its packed tiles as well (made on
+// first use, freed with the preconditioner), for products in FP32 storage.
+bie_op *calderon_view32(const bie_calderon *pc, hipStream_t s)
+{
+    bie_op *v = pc->view;
+    if (!v->Z32) {
+        const int64_t n = v->pk.ntiles * TB * TB;
+        void *z = nullptr;
+        BIE_HIP(hipMalloc(&z, size_t(n) * sizeof(float2)));
+        convert_c128_to_c64(v->Z64, z, n, s);
+        BIE_HIP(hipStreamSynchronize(s));
+        v->Z32 = z;
+    }
+    return v;
+}
+
 // Two R x N complex128 scratch blocks for the preconditioned solve.
 double2 *calderon_scratch(const bie_calderon *pcc, int64_t R, hipStream_t s)
 {

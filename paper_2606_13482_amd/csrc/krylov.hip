@@ -685,6 +685,22 @@ __global__ __launch_bounds__(BT) void k_xupd(Cols cl, int m, const VT *__restric
     }
 }
 
+// X += Z for the active columns (the preconditioned update x += M (V y)).
+__global__ __launch_bounds__(BT) void k_add_active(Cols cl, const double2 *__restrict__ Z, double2 *__restrict__ X,
+                                                   const ColStat *__restrict__ st)
+{
+    const int r = blockIdx.y;
+    if (!st[r].active) return;
+    const int64_t N = cl.len(r), o = cl.wo(r);
+    for (int64_t e = int64_t(blockIdx.x) * BT + threadIdx.x; e < N; e += int64_t(gridDim.x) * BT) {
+        const double2 z = Z[o + e];
+        double2 x = X[o + e];
+        x.x += z.x;
+        x.y += z.y;
+        X[o + e] = x;
+    }
+}
+
 // ||v||^2 per column with last-block finish; writes sqrt into the field at `off`.
 __global__ __launch_bounds__(BT) void k_norm(Cols cl, const double2 *__restrict__ Vb, double *__restrict__ part,
                                              unsigned *__restrict__ counters, ColStat *__restrict__ st, int field,
@@ -1720,7 +1736,19 @@ struct GLayout {
     int64_t *gpoff = nullptr;   // partial-vector offset per column
     double2 *gpart = nullptr;   // partial vectors of all columns
     std::vector<int32_t> h_items, h_ritems, h_c0, h_c1;   // host copies: items, reduce items, columns of each problem
+    std::vector<GProb> h_probs;
 };
+
+// The problems of layout L with other matrices of the same sizes and units
+// (the FP64 copies for the residuals, the preconditioners' matrices).
+GProb *probs_on(DevBufs &db, const GLayout &L, const std::vector<const void *> &Z)
+{
+    std::vector<GProb> q = L.h_probs;
+    for (size_t p = 0; p < q.size(); ++p) q[p].Z = Z[p];
+    GProb *d = db.get<GProb>(q.size());
+    BIE_HIP(hipMemcpy(d, q.data(), q.size() * sizeof(GProb), hipMemcpyHostToDevice));
+    return d;
+}
 
 std::unique_ptr<GLayout> make_layout(const bie_op *const *ops, int64_t P, const int64_t *R, int U, int G, bool mat64)
 {
@@ -1800,6 +1828,7 @@ std::unique_ptr<GLayout> make_layout(const bie_op *const *ops, int64_t P, const 
     BIE_HIP(hipMemcpy(L->gpoff, gpoff.data(), gpoff.size() * sizeof(int64_t), hipMemcpyHostToDevice));
     L->h_items = std::move(items);
     L->h_ritems = std::move(ritems);
+    L->h_probs = probs;
     for (int64_t p = 0; p < P; ++p) {
         L->h_c0.push_back(probs[p].c0);
         L->h_c1.push_back(probs[p].c1);
@@ -1833,16 +1862,27 @@ std::string batch_key(const bie_op *const *ops, int64_t P, const int64_t *R, boo
 
 }  // namespace
 
-int solve_batch(const bie_op *const *ops, int64_t P, const void *const *Bp, void *const *Xp, const int64_t *Rp,
-                const bie_solve_opts &o, bie_solve_stat *stats, hipStream_t user)
+int solve_batch(const bie_op *const *ops, const bie_calderon *const *pcs, int64_t P, const void *const *Bp,
+                void *const *Xp, const int64_t *Rp, const bie_solve_opts &o, bie_solve_stat *stats, hipStream_t user)
 {
-    if (o.method != BIE_GMRES || o.precision != 0 || o.crit != BIE_SCC)
-        throw Error(BIE_EINVAL, "batched solves take GMRES, the stored matrices and the standard criterion");
-    const bool mat64 = ops[0]->Z64 != nullptr;
+    if (o.method != BIE_GMRES || (o.precision != 0 && o.precision != 1) || o.crit != BIE_SCC)
+        throw Error(BIE_EINVAL, "batched solves take GMRES, precision 0 or 1 and the standard criterion");
+    // precision 1: the cycles on the FP32 tiles, every residual (restart vector
+    // and criterion) on the FP64 tiles of the same operator
+    const bool prec1 = o.precision == 1;
+    const bool mat64 = !prec1 && ops[0]->Z64 != nullptr;
+    const bool res64 = prec1 || mat64;
     for (int64_t p = 0; p < P; ++p) {
-        if ((ops[p]->Z64 != nullptr) != mat64 || (!mat64 && !ops[p]->Z32))
+        if (prec1) {
+            if (!ops[p]->Z64 || !ops[p]->Z32)
+                throw Error(BIE_EINVAL, "precision 1 needs the FP32 and the FP64 matrix of every operator "
+                                        "(storage BIE_C64 with keep_fp64)");
+        } else if ((ops[p]->Z64 != nullptr) != mat64 || (!mat64 && !ops[p]->Z32)) {
             throw Error(BIE_EINVAL, "all operators of a batch need the same stored matrix (FP64 or FP32)");
+        }
         if (ops[p]->device != ops[0]->device) throw Error(BIE_EINVAL, "all operators of a batch on one device");
+        if (pcs && (!pcs[p] || calderon_operator(pcs[p]) != ops[p]))
+            throw Error(BIE_EINVAL, "preconditioner " + std::to_string(p) + " is missing or was built for another operator");
     }
     const int m = o.restart;
     // column tables
@@ -1981,6 +2021,36 @@ int solve_batch(const bie_op *const *ops, int64_t P, const void *const *Bp, void
         L = make_layout(ops, P, Rp, U, G, mat64);
     }
     const GCols gres = layout_cols(*L, dwo, 0);
+    // the residuals' matrices (FP64 tiles under precision 1)
+    const GProb *probs_res = L->probs;
+    if (res64 != mat64) {
+        std::vector<const void *> Z(P);
+        for (int64_t p = 0; p < P; ++p) Z[p] = ops[p]->Z64;
+        probs_res = probs_on(db, *L, Z);
+    }
+    // the preconditioners' matrices M, in the precision of the cycles' products;
+    // their unit tables are those of the operators' layout (the same sizes)
+    // unless the layout uses each operator's own units
+    const GProb *probs_m = nullptr;
+    std::unique_ptr<GLayout> LM;
+    double2 *Wz = nullptr;
+    if (pcs) {
+        std::vector<const bie_op *> views(P);
+        std::vector<const void *> Z(P);
+        for (int64_t p = 0; p < P; ++p) {
+            views[p] = mat64 ? calderon_view(pcs[p], false, s) : calderon_view32(pcs[p], s);
+            Z[p] = mat64 ? views[p]->Z64 : views[p]->Z32;
+        }
+        if (L->U >= 1) {
+            probs_m = probs_on(db, *L, Z);
+        } else {
+            LM = make_layout(views.data(), P, Rp, L->U, L->G, mat64);
+            probs_m = LM->probs;
+        }
+        Wz = db.get<double2>(size_t(nw));
+    }
+    // partial vectors and items of the preconditioner's products
+    const GLayout &LMr = LM ? *LM : *L;
     // Live work: the tile items with at least one live column and the reduce
     // items of live columns, rebuilt (and the cycle graph captured again) when
     // the live columns have dropped by a quarter since the last build, so that
@@ -2012,7 +2082,7 @@ int solve_batch(const bie_op *const *ops, int64_t P, const void *const *Bp, void
     std::vector<int> all_live(C, 1);
     build_live(all_live);
     auto full_residual = [&](const int *skipdev) {   // Res = B - T X for the columns not skipped
-        grouped_product(mat64, L->probs, gres, litems, nlitems, L->G, lritems, nlritems, Xw, L->gpart, w->Res, Bw,
+        grouped_product(res64, probs_res, gres, litems, nlitems, L->G, lritems, nlritems, Xw, L->gpart, w->Res, Bw,
                         skipdev, 1, s);
     };
 
@@ -2096,9 +2166,21 @@ int solve_batch(const bie_op *const *ops, int64_t P, const void *const *Bp, void
     const int64_t done_stride = sizeof(ColStat) / sizeof(int);
     auto cycle_body = [&]() {
         for (int j = 0; j < m; ++j) {
-            const GCols gv = layout_cols(*L, dvo, j);
-            grouped_product(mat64, L->probs, gv, litems, nlitems, L->G, lritems, nlritems, w->V, L->gpart, w->W,
-                            nullptr, done_flags, done_stride, s);
+            if (pcs) {   // w = T (M v_j)
+                const GCols gm = layout_cols(LMr, dvo, j);
+                if (LM)
+                    grouped_product(mat64, probs_m, gm, LM->items, LM->nitems, LM->G, LM->ritems, LM->nritems, w->V,
+                                    LM->gpart, Wz, nullptr, done_flags, done_stride, s);
+                else
+                    grouped_product(mat64, probs_m, gm, litems, nlitems, L->G, lritems, nlritems, w->V, L->gpart, Wz,
+                                    nullptr, done_flags, done_stride, s);
+                grouped_product(mat64, L->probs, gres, litems, nlitems, L->G, lritems, nlritems, Wz, L->gpart, w->W,
+                                nullptr, done_flags, done_stride, s);
+            } else {
+                const GCols gv = layout_cols(*L, dvo, j);
+                grouped_product(mat64, L->probs, gv, litems, nlitems, L->G, lritems, nlritems, w->V, L->gpart, w->W,
+                                nullptr, done_flags, done_stride, s);
+            }
             arnoldi_step<double2>(w, cl, Nmax, w->V, m, j, o.tol, C, s);
         }
     };
@@ -2160,7 +2242,22 @@ int solve_batch(const bie_op *const *ops, int64_t P, const void *const *Bp, void
         else cycle_body();
         hipLaunchKernelGGL(k_lsq, dim3(unsigned(C)), dim3(64), size_t(m) * m * sizeof(double2), s, m, w->H, w->g,
                            w->y, w->st);
-        hipLaunchKernelGGL(k_xupd<double2>, egrid, dim3(BT), 0, s, cl, m, w->V, w->y, Xw, w->st);
+        if (pcs) {   // x += M (V y) for the active columns
+            hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, s, nw, Wz);
+            hipLaunchKernelGGL(k_xupd<double2>, egrid, dim3(BT), 0, s, cl, m, w->V, w->y, Wz, w->st);
+            for (int64_t c = 0; c < C; ++c) skip[c] = active[c] ? 0 : 1;
+            push_mask(skip);
+            const GCols gz = layout_cols(LMr, dwo, 0);
+            if (LM)
+                grouped_product(mat64, probs_m, gz, LM->items, LM->nitems, LM->G, LM->ritems, LM->nritems, Wz,
+                                LM->gpart, w->W, nullptr, w->mask, 1, s);
+            else
+                grouped_product(mat64, probs_m, gz, litems, nlitems, L->G, lritems, nlritems, Wz, L->gpart, w->W,
+                                nullptr, w->mask, 1, s);
+            hipLaunchKernelGGL(k_add_active, egrid, dim3(BT), 0, s, cl, (const double2 *)w->W, Xw, w->st);
+        } else {
+            hipLaunchKernelGGL(k_xupd<double2>, egrid, dim3(BT), 0, s, cl, m, w->V, w->y, Xw, w->st);
+        }
         BIE_HIP(hipGetLastError());
         pull_st();
         std::vector<int> nd(C, 0);
@@ -2218,8 +2315,9 @@ void batch_config(int unit, int graph)
 int batch_unit_chosen(const bie_op *const *ops, int64_t P, const int64_t *R)
 {
     std::vector<int> v;
-    if (!tune_get(batch_key(ops, P, R, ops[0]->Z64 != nullptr), v) || v.empty()) return 0;
-    return v[0];
+    if (ops[0]->Z64 && tune_get(batch_key(ops, P, R, true), v) && !v.empty()) return v[0];
+    if (ops[0]->Z32 && tune_get(batch_key(ops, P, R, false), v) && !v.empty()) return v[0];
+    return 0;
 }
 
 int solve(const bie_op *op, const void *B, void *X, int64_t R, const bie_solve_opts &o, bie_solve_stat *stats,

@@ -113,3 +113,102 @@ def test_batch_guesses_and_edges(bie):
     assert sts[0][0]["x0_kept"] == 1 and sts[0][0]["iters"] == 0
     for p in (0, 1, 3):
         assert all(s["converged"] for s in sts[p])
+
+
+def _ops_keep64(bie):
+    ops, Bs = [], []
+    for pr in _problems():
+        op = bie.Operator(pr["V"], pr["T"], pr["k"], storage="c64", keep_fp64=True)
+        ops.append(op)
+        Bs.append(op.rhs(pr["d"], pr["e"]))
+    return ops, Bs
+
+
+def _oracle_res(p, B, X):
+    Zo = _problems()[p]["Zo"]
+    Bn, Xn = B.cpu().numpy(), X.cpu().numpy()
+    return np.linalg.norm(Bn - Xn @ Zo.T, axis=1) / np.linalg.norm(Bn, axis=1)
+
+
+def test_batch_precision1_certified_fp64(bie):
+    """Precision 1: the cycles on the FP32 tiles, every residual on the FP64
+    tiles.  Every column reaches the criterion on its FP64 residual, and that
+    residual, recomputed with the oracle's FP64 matrix, is at the tolerance (the
+    FP32-only batch is only within the FP32 rounding of the matrix)."""
+    ops, Bs = _ops_keep64(bie)
+    opts = bie.Solve(restart=30, tol=1e-6, precision="mixed")
+    Xs, sts = bie.batch_solve(ops, Bs, opts)
+    for p in range(len(ops)):
+        assert all(s["converged"] for s in sts[p]), p
+        assert max(s["relres_true"] for s in sts[p]) <= 1e-6
+        res = _oracle_res(p, Bs[p], Xs[p])
+        assert res.max() <= 1e-6 * (1 + 1e-6), (p, res)
+    # iterations stay those of the FP32 batch within a restart cycle or two
+    ops32, _ = _ops(bie, "c64")
+    _, sts32 = bie.batch_solve(ops32, Bs, bie.Solve(restart=30, tol=1e-6))
+    for p in range(len(ops)):
+        for a, b in zip(sts[p], sts32[p]):
+            assert a["iters"] <= b["iters"] + 60, (p, a["iters"], b["iters"])
+
+
+def test_batch_calderon_equals_single_bitwise(bie):
+    """Per-operator Calderon preconditioners (bie_batch_solve_pc), FP64
+    matrices, the single-operator units: every column equals the single
+    preconditioned solve bitwise (the same products in the same order), and the
+    preconditioner cuts the iterations."""
+    ops, Bs = _ops(bie, "c128")
+    pcs = [bie.Calderon(op) for op in ops]
+    opts = bie.Solve(restart=20, tol=1e-8)
+    bie.batch_config(-1, True)
+    try:
+        Xs, sts = bie.batch_solve(ops, Bs, opts, pcs=pcs)
+    finally:
+        bie.batch_config(0, True)
+    _, st0 = bie.batch_solve(ops, Bs, opts)
+    for p, op in enumerate(ops):
+        X1, st1 = op.solve(Bs[p], bie.Solve(restart=20, tol=1e-8, calderon=pcs[p]))
+        assert [s["iters"] for s in sts[p]] == [s["iters"] for s in st1], p
+        assert torch.equal(Xs[p], X1), p
+        assert all(s["converged"] for s in sts[p])
+        assert _oracle_res(p, Bs[p], Xs[p]).max() <= 1e-8 * (1 + 1e-6)
+        assert sum(s["iters"] for s in sts[p]) < sum(s["iters"] for s in st0[p]), p
+    for pc in pcs:
+        pc.close()
+
+
+def test_batch_calderon_precision1(bie):
+    """The uneven-batch form: FP32 tiles for the cycles (T and an FP32 copy of
+    M), FP64 residuals, autotuned units: converged, certified against the
+    oracle's FP64 matrix, and within 1e-3 of the oracle's LU solution (the
+    tolerance times the conditioning of these small surfaces)."""
+    ops, Bs = _ops_keep64(bie)
+    pcs = [bie.Calderon(op) for op in ops]
+    opts = bie.Solve(restart=30, tol=1e-6, precision="mixed")
+    Xs, sts = bie.batch_solve(ops, Bs, opts, pcs=pcs)
+    for p in range(len(ops)):
+        assert all(s["converged"] for s in sts[p]), p
+        assert max(s["relres_true"] for s in sts[p]) <= 1e-6
+        assert _oracle_res(p, Bs[p], Xs[p]).max() <= 1e-6 * (1 + 1e-6)
+        Zo = _problems()[p]["Zo"]
+        for i, b in enumerate(Bs[p].cpu().numpy()):
+            xe = krylov.lu_solve(Zo, b)
+            err = np.linalg.norm(Xs[p][i].cpu().numpy() - xe) / np.linalg.norm(xe)
+            assert err < 1e-3, (p, i, err)
+    for pc in pcs:
+        pc.close()
+
+
+def test_batch_pc_rejections(bie):
+    """A preconditioner of another operator, a missing FP64 copy under precision
+    1, and the single-solve preconditioner field are refused."""
+    ops, Bs = _ops(bie, "c128")
+    pcs = [bie.Calderon(op) for op in ops]
+    with pytest.raises(RuntimeError):
+        bie.batch_solve(ops, Bs, bie.Solve(restart=20), pcs=pcs[::-1])
+    with pytest.raises(ValueError):
+        bie.batch_solve(ops, Bs, bie.Solve(restart=20, calderon=pcs[0]))
+    ops32, B32 = _ops(bie, "c64")
+    with pytest.raises(RuntimeError):
+        bie.batch_solve(ops32, B32, bie.Solve(restart=20, precision="mixed"))
+    for pc in pcs:
+        pc.close()
