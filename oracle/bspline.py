@@ -210,22 +210,24 @@ def buffer_knots(prot_rel: float, s: int, p: int) -> int:
     return int(math.ceil(prot_rel * (s - p) - 1e-12)) if prot_rel > 0 else 0
 
 
-def moments(rwg: dict, sp: BoxSplines, a: float, lo: np.ndarray, rule=None) -> np.ndarray:
+def moments(rwg: dict, sp: BoxSplines, a: float, lo: np.ndarray, rule=None, transformed: bool = True) -> np.ndarray:
     """Transformed moments m~ (N, 4, n_st, n_st, n_st): components d = x, y, z of
     int f_m b~ and the divergence moment int div f_m b~, with b~ the transformed
     stabilised splines of the function's box (lo: its lower corner, (N, 3)) and
-    the fill's quadrature rule."""
+    the fill's quadrature rule.  transformed=False: the moments m with the
+    buffered equidistant splines themselves, (N, 4, n, n, n)."""
     G = Geometry(rwg, rule)
     N = rwg["N"]
-    n = sp.n_st
+    n = sp.n_st if transformed else sp.n
+    T1 = sp.A.T if transformed else np.eye(sp.n)
     out = np.zeros((N, 4, n, n, n))
     for m in range(N):
         for t, vfree, sgn in ((rwg["tp"][m], rwg["vp"][m], 1.0), (rwg["tm"][m], rwg["vm"][m], -1.0)):
             X = G.X[t]                                              # (nq, 3)
             tt = (X - lo[m]) / a                                    # parameter coordinates
-            bx = sp.eq_basis(tt[:, 0]) @ sp.A.T                     # (nq, n_st): b~ along x
-            by = sp.eq_basis(tt[:, 1]) @ sp.A.T
-            bz = sp.eq_basis(tt[:, 2]) @ sp.A.T
+            bx = sp.eq_basis(tt[:, 0]) @ T1                         # (nq, n_st): b~ along x
+            by = sp.eq_basis(tt[:, 1]) @ T1
+            bz = sp.eq_basis(tt[:, 2]) @ T1
             prod = np.einsum("qi,qj,qk->qijk", bx, by, bz)          # (nq, n, n, n)
             D = X - rwg["V"][vfree]                                 # (nq, 3)
             for d in range(3):
@@ -295,3 +297,220 @@ def far_product(rwg: dict, k: float, x: np.ndarray, a: float, s: int, p: int, st
 def far_mask(inv: np.ndarray, far: np.ndarray) -> np.ndarray:
     """(N, N) boolean: the entries (m, n) whose boxes are far apart."""
     return far[inv][:, inv]
+
+
+# ----------------------------------------------------------------------------- multilevel (Sec. IV)
+def restriction_matrix(u_par: np.ndarray, p: int, u_ch: np.ndarray, tol: float = 1e-12) -> np.ndarray:
+    """C (n_par x n_ch) with b_j^par(x) = sum_i C[j, i] b_i^ch(x) on the child's
+    interval [u_ch[0], u_ch[-1]] (Sec. IV-B): every knot of the child vector that
+    the parent vector lacks is inserted into the unit-coefficient curve of parent
+    spline j, the two ends up to multiplicity p + 1, and the coefficients of the
+    splines of the refined vector that live on the child's interval are row j.
+    Requires the parent's knots inside the interval to be child knots (nested
+    spaces); knots closer than tol are taken as equal."""
+    a, b = u_ch[0], u_ch[-1]
+    par = [float(v) for v in u_par]
+    extra = []
+    inner_par = [v for v in par if a - tol < v < b + tol]
+    pool = list(inner_par)
+    for v in u_ch:
+        for t, e in enumerate(pool):
+            if abs(e - v) <= tol:
+                del pool[t]
+                break
+        else:
+            extra.append(float(v))
+    # parent knots strictly inside the interval must all be child knots
+    if any(a + tol < v < b - tol for v in pool):
+        raise ValueError("parent knots not contained in the child's knot vector")
+    n_par = len(u_par) - p - 1
+    n_ch = len(u_ch) - p - 1
+    C = np.zeros((n_par, n_ch))
+    for j in range(n_par):
+        u, w = np.array(par), np.eye(n_par)[j]
+        for e in sorted(extra):
+            u, w = insert_knot(u, p, w, e)
+        # the child's splines: the refined splines from the first copy of a on
+        k0 = int(np.nonzero(np.abs(u - a) <= tol)[0][0])
+        assert np.max(np.abs(u[k0:k0 + len(u_ch)] - u_ch)) <= 10 * tol
+        C[j] = w[k0:k0 + n_ch]
+    return C
+
+
+def level_configs(s: int, p: int, sb: int, a_leaf: float, levels: int, k: float, stabilise: bool = True):
+    """Spline spaces from the leaf level (index 0) up: the parent of a level keeps
+    s and takes ceil(sb / 2) buffer knots when its boxes are smaller than half a
+    wavelength (Sec. IV-C), and otherwise takes 2 s - p splines (the same physical
+    knot spacing) and the same sb (Sec. IV-D); there are no leaves above level 0."""
+    lam = 2.0 * math.pi / k
+    cfg = [BoxSplines(s, p, sb, stabilise)]
+    for l in range(1, levels):
+        a_par = a_leaf * 2 ** l
+        prev = cfg[-1]
+        if a_par < 0.5 * lam:
+            cfg.append(BoxSplines(prev.s, p, -(-prev.sb // 2), stabilise))
+        else:
+            cfg.append(BoxSplines(2 * prev.s - p, p, prev.sb, stabilise))
+    return cfg
+
+
+def transfer_matrices(child: BoxSplines, parent: BoxSplines):
+    """The two 1D transfer matrices (child at the lower / upper half of the
+    parent): parent equidistant splines in terms of the child's, both knot
+    vectors in the parent's parameter coordinate."""
+    out = []
+    for c in (0, 1):
+        u_ch = 0.5 * c + 0.5 * child.u_eq
+        out.append(restriction_matrix(parent.u_eq, parent.p, u_ch))
+    return out
+
+
+def apply3(A: np.ndarray, B: np.ndarray, Cm: np.ndarray, M: np.ndarray) -> np.ndarray:
+    """(A (x) B (x) C) applied to the last three axes of M."""
+    return np.einsum("ia,jb,kc,...abc->...ijk", A, B, Cm, M, optimize=True)
+
+
+def translation_kernel(sp: BoxSplines, a: float, offset: np.ndarray, k: float) -> np.ndarray:
+    """K[d] = g(|offset + h d|), d in [-(n-1), n-1]^3 (z fastest), h the spacing
+    of the level's interpolation points: G_XY[i, j] = K[i - j] for boxes whose
+    lower corners differ by offset (three-level Toeplitz, Sec. III-C)."""
+    n = sp.n_st
+    h = a * (sp.t[1] - sp.t[0]) if n > 1 else 0.0
+    d = np.arange(-(n - 1), n)
+    D = np.stack(np.meshgrid(d, d, d, indexing="ij"), -1)
+    R = np.linalg.norm(offset[None, None, None, :] + h * D, axis=-1)
+    return green(R, k)
+
+
+def translate_fft(K: np.ndarray, Mt: np.ndarray) -> np.ndarray:
+    """sum_j K[i - j] Mt[..., j] for i in [0, n)^3 by FFT (linear convolution:
+    sizes 2n - 1 per axis)."""
+    n = Mt.shape[-1]
+    L = 2 * n - 1
+    Kc = np.zeros((L, L, L), np.complex128)
+    idx = np.arange(-(n - 1), n) % L
+    Kc[np.ix_(idx, idx, idx)] = K
+    Mp = np.zeros(Mt.shape[:-3] + (L, L, L), np.complex128)
+    Mp[..., :n, :n, :n] = Mt
+    out = np.fft.ifftn(np.fft.fftn(Kc)[None] * np.fft.fftn(Mp, axes=(-3, -2, -1)), axes=(-3, -2, -1))
+    return out[..., :n, :n, :n]
+
+
+def translate_direct(sp: BoxSplines, a: float, lo_x: np.ndarray, lo_y: np.ndarray, k: float,
+                     Mt: np.ndarray) -> np.ndarray:
+    """G_XY Mt with G sampled point by point (the plain form of eq:TAfactorBspline)."""
+    Px, Py = grid_points(sp, a, lo_x), grid_points(sp, a, lo_y)
+    Gm = green(np.linalg.norm(Px[:, None, :] - Py[None, :, :], axis=2), k)
+    n = sp.n_st
+    return (Mt.reshape(Mt.shape[:-3] + (n ** 3,)) @ Gm.T).reshape(Mt.shape)
+
+
+def interaction_lists(leaf_idx: np.ndarray, levels: int):
+    """Per level (0 = leaf): the distinct boxes (integer indices at that level),
+    the box of every leaf box's ancestor, and the pairs (X, Y) translated there:
+    X, Y far (Chebyshev distance of the indices > 1) and their parents near, or
+    every far pair at the top level."""
+    out = []
+    idx = np.unique(leaf_idx, axis=0)
+    anc = np.arange(len(idx))
+    for l in range(levels):
+        boxes, inv = np.unique(idx >> l, axis=0, return_inverse=True)
+        inv = inv.ravel()
+        d = np.max(np.abs(boxes[:, None, :] - boxes[None, :, :]), axis=2)
+        far = d > 1
+        if l + 1 < levels:
+            par = boxes >> 1
+            dp = np.max(np.abs(par[:, None, :] - par[None, :, :]), axis=2)
+            far &= dp <= 1
+        out.append(dict(boxes=boxes, leaf_to_box=inv, pairs=np.argwhere(far)))
+    return idx, out
+
+
+def ml_far_product(rwg: dict, k: float, x: np.ndarray, a_leaf: float, levels: int, s: int, p: int,
+                   stabilise: bool = True, origin=None, fft: bool = True):
+    """y = Z~_far x with the multilevel scheme (Sec. IV): equidistant-spline
+    moments of the leaf boxes, moved up by the knot-insertion transfers
+    (eq:interleveltransfer), transformed at every level (m~ = B^-1 C m along each
+    axis), translated between the pairs of each level's interaction list
+    (eq:TAfactorBspline; by FFT, or point by point), and brought down by the
+    transposed maps to the test functions.  Covers exactly the pairs of leaf
+    boxes that are far apart."""
+    idx, lo, prot, origin = box_level(rwg, a_leaf, origin)
+    sb = buffer_knots(prot, s, p)
+    cfg = level_configs(s, p, sb, a_leaf, levels, k, stabilise)
+    for c in cfg:
+        if 2 * c.sb >= c.s - p:
+            raise ValueError("buffer knots reach half a box: use larger boxes or more splines")
+    leaf_boxes, lists = interaction_lists(idx, levels)
+    X = np.atleast_2d(x).astype(np.complex128)
+    R = X.shape[0]
+    m_eq = moments(rwg, cfg[0], a_leaf, lo, transformed=False)          # (N, 4, n, n, n)
+    # leaf box of every function (row of leaf_boxes)
+    _, finv = np.unique(np.concatenate([leaf_boxes, idx]), axis=0, return_inverse=True)
+    finv = finv.ravel()
+    leaf_of = finv[len(leaf_boxes):]
+    assert np.array_equal(finv[:len(leaf_boxes)], np.arange(len(leaf_boxes)))
+    n0 = cfg[0].n
+    M = [np.zeros((R, len(leaf_boxes), 4, n0, n0, n0), np.complex128)]
+    for m in range(rwg["N"]):
+        M[0][:, leaf_of[m]] += X[:, m, None, None, None, None] * m_eq[m][None]
+    per_level_M = []
+    Ml = M[0]
+    box_of_leaf = [lists[l]["leaf_to_box"] for l in range(levels)]
+    # level-0 boxes are the leaf boxes themselves (identity numbering)
+    assert np.array_equal(box_of_leaf[0], np.arange(len(leaf_boxes)))
+    for l in range(levels):
+        if l > 0:
+            child_boxes = lists[l - 1]["boxes"]
+            par_of_child = np.unique(np.concatenate([lists[l]["boxes"], child_boxes >> 1]), axis=0,
+                                     return_inverse=True)[1].ravel()[len(lists[l]["boxes"]):]
+            Cm = transfer_matrices(cfg[l - 1], cfg[l])
+            n = cfg[l].n
+            Mp = np.zeros((R, len(lists[l]["boxes"]), 4, n, n, n), np.complex128)
+            for cb in range(len(child_boxes)):
+                c = child_boxes[cb] & 1
+                Mp[:, par_of_child[cb]] += apply3(Cm[c[0]], Cm[c[1]], Cm[c[2]], per_level_M[-1][:, cb])
+            Ml = Mp
+        per_level_M.append(Ml)
+    # translations per level (weights jk for the vector parts, 1/jk for the divergence)
+    w = np.array([1j * k] * 3 + [1.0 / (1j * k)])
+    Lq = []
+    for l in range(levels):
+        sp = cfg[l]
+        a = a_leaf * 2 ** l
+        boxes = lists[l]["boxes"]
+        Mt = apply3(sp.A, sp.A, sp.A, per_level_M[l])                  # (R, B, 4, n', n', n')
+        Zt = np.zeros_like(Mt)
+        kern = {}
+        for bx, by in lists[l]["pairs"]:
+            off = (boxes[bx] - boxes[by]) * a
+            if fft:
+                key = tuple(boxes[bx] - boxes[by])
+                if key not in kern:
+                    kern[key] = translation_kernel(sp, a, off.astype(np.float64), k)
+                Zt[:, bx] += translate_fft(kern[key], Mt[:, by])
+            else:
+                lo_x = origin + boxes[bx] * a
+                lo_y = origin + boxes[by] * a
+                Zt[:, bx] += translate_direct(sp, a, lo_x, lo_y, k, Mt[:, by])
+        Zt *= w[None, None, :, None, None, None]
+        Lq.append(apply3(sp.A.T, sp.A.T, sp.A.T, Zt))                 # (R, B, 4, n, n, n)
+    # downward: the parents' local coefficients through the transposed transfers
+    for l in range(levels - 2, -1, -1):
+        child_boxes = lists[l]["boxes"]
+        par_of_child = np.unique(np.concatenate([lists[l + 1]["boxes"], child_boxes >> 1]), axis=0,
+                                 return_inverse=True)[1].ravel()[len(lists[l + 1]["boxes"]):]
+        Cm = transfer_matrices(cfg[l], cfg[l + 1])
+        for cb in range(len(child_boxes)):
+            c = child_boxes[cb] & 1
+            Lq[l][:, cb] += apply3(Cm[c[0]].T, Cm[c[1]].T, Cm[c[2]].T, Lq[l + 1][:, par_of_child[cb]])
+    Y = np.einsum("mdijk,rmdijk->rm", m_eq, Lq[0][:, leaf_of], optimize=True)
+    info = dict(configs=cfg, lists=lists, leaf_boxes=leaf_boxes, leaf_of=leaf_of, sb=sb, prot=prot, origin=origin,
+                moments_eq=m_eq, level_moments=per_level_M)
+    return (Y[0] if np.ndim(x) == 1 else Y), info
+
+
+def leaf_far_mask(leaf_of: np.ndarray, leaf_boxes: np.ndarray) -> np.ndarray:
+    """(N, N) boolean: the entries whose leaf boxes are far apart."""
+    d = np.max(np.abs(leaf_boxes[:, None, :] - leaf_boxes[None, :, :]), axis=2) > 1
+    return d[leaf_of][:, leaf_of]
