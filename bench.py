@@ -82,6 +82,8 @@ def parse():
                     help="skip the uneven batch of 64 surfaces (batched solves over many operators)")
     ap.add_argument("--no-star", dest="star", action="store_false",
                     help="skip the star-split operator leg (low-frequency mixed precision, product times)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only the uneven batch of 64 surfaces (its JSON object on one line)")
     ap.add_argument("--counters", action="store_true",
                     help="only launch the dense product kernels a few times at the bench sizes, and a 1 GiB "
                          "device copy as calibration, for hardware-counter runs")
@@ -785,12 +787,18 @@ def uneven_batch_leg(args, bie, torch):
 
 
 def counters_probe(args, bie, torch):
-    """Kernels for the HBM traffic counters: 5 launches each of the packed FP64
+    """Kernels for the hardware counters: 5 launches each of the packed FP64
     product (one column), the split-BF16 block product and the FP64 block product
-    (512 columns, the headline's 16 groups of 32) on the bench operator, and 3
-    plain copies of 1 GiB (FETCH_SIZE / WRITE_SIZE calibration)."""
-    from paper_2606_13482_amd.inputs import icosphere, complex_gaussian
+    (512 columns, the headline's 16 groups of 32) on the bench operator; the
+    fill of that operator in FP64 and in FP32; the grouped products of the uneven
+    batch (FP32 matrices, all 1069 columns, the autotuned layout: the candidates'
+    timing launches, then one restart cycle of 1 step and its residual); and 3
+    plain copies of 1 GiB (FETCH_SIZE / WRITE_SIZE
+    calibration)."""
+    from paper_2606_13482_amd.inputs import icosphere, complex_gaussian, uneven_batch
     V, T = icosphere(args.level)
+    for storage in ("c128", "c64"):
+        bie.Operator(V, T, args.k, storage=storage).close()
     op = bie.Operator(V, T, args.k, storage="split_bf16")
     x = torch.from_numpy(complex_gaussian(op.N, 7)).cuda().reshape(1, -1)
     Xb = torch.from_numpy(complex_gaussian(op.N, 7, cols=512)).cuda()
@@ -800,14 +808,26 @@ def counters_probe(args, bie, torch):
         op.apply(Xb, block=True)
     for _ in range(5):
         op.apply(Xb, block="fp64")
+    probs = uneven_batch()
+    ops = [bie.Operator(p["V"], p["T"], p["k"], storage="c64") for p in probs]
+    Bs = [o.rhs(p["dirs"], p["pols"]) for o, p in zip(ops, probs)]
+    bie.batch_config(0, False)       # the autotuned layout, cycles launched one by one
+    try:
+        bie.batch_solve(ops, Bs, bie.Solve(restart=1, tol=1e-6, max_mvp=2))
+    finally:
+        bie.batch_config(0, True)
     a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     for _ in range(3):
         b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"counters_probe": {"N": op.N, "packed_fp64_launches": 5, "block_launches": 5,
-                                         "block_columns": 512, "copy_bytes": a.numel() * 4, "copies": 3}}),
+                                         "block_columns": 512, "copy_bytes": a.numel() * 4, "copies": 3,
+                                         "batch_packed_fp32_bytes": int(sum(4 * o.N * (o.N + 1) for o in ops)),
+                                         "batch_columns": int(sum(b.shape[0] for b in Bs))}}),
           flush=True)
+    for o in ops:
+        o.close()
     op.close()
 
 
@@ -879,6 +899,9 @@ def main():
     torch.cuda.set_device(torch.device("cuda:0"))
     if args.counters:
         counters_probe(args, bie, torch)
+        return
+    if args.batch_only:
+        print(json.dumps({"uneven_batch": uneven_batch_leg(args, bie, torch)}), flush=True)
         return
     V, T = icosphere(args.level)
     k = args.k

@@ -296,8 +296,8 @@ int bie_batch_solve_pc(const bie_op *const *ops, const struct bie_calderon *cons
 
 /* Batched solves, for measurement and tests: tiles per work unit of the
  * grouped product (0, the default: tiles per unit in {4, 8, 16} and columns per
- * work item in {4, 8, 32} chosen per batch shape by timing the candidates on
- * the batch; the choices are kept for the process and appended to the file
+ * work item in {4, 8, 16, 32} chosen per batch shape by timing the candidates
+ * on the batch; the choices are kept for the process and appended to the file
  * named by BIE_AUTOTUNE_CACHE if set; > 0: that many tiles per unit, 8 columns
  * per item; -1: each operator's own single-product units, 8 columns per item,
  * which makes every column bitwise equal to its single solve) and graph replay
@@ -412,6 +412,42 @@ int bie_far_get_info(const bie_far *far, bie_far_info *info);
 /* Cube index (3 x int32, host out, N rows) of every RWG function. */
 int bie_far_boxes(const bie_far *far, int32_t *out);
 void bie_far_destroy(bie_far *far);
+
+/* Multilevel B-spline far field (Sec. IV; FFT translations, Sec. III-C).  A
+ * regular octree over the cubes of side `box` of bie_far_create (level 0, the
+ * leaves); the cube of level l holding leaf cube (i, j, k) is (i, j, k) >> l,
+ * up to `levels` levels.  Each level has its own splines: while the parent's
+ * cubes are smaller than half a wavelength it keeps s and takes ceil(sb/2)
+ * buffer knots (Sec. IV-C), otherwise 2 s - p splines and the same sb
+ * (Sec. IV-D).  Moments of the leaves (equidistant splines) move up by the
+ * knot-insertion transfers of eq:interleveltransfer (exact: nested knot
+ * vectors), are translated on each level between the cube pairs whose cubes
+ * are far and whose parents are near (every far pair on the top level), with
+ * G applied as a three-level Toeplitz convolution by FFT (eq:TAfactorBspline:
+ * one symbol per cube offset), and come down by the transposed transfers to
+ * the test functions.  The product covers exactly the pairs of far leaf cubes,
+ * the same set as bie_far with the same box.  p odd (1, 3, 5); at most 18
+ * equidistant splines and 16 interpolation points per axis on any level.
+ * Memory per level: about 4 (2 L^3 + 2 n^3 + nst^3) x 16 B per cube (L = 16 or
+ * 32, the FFT size) plus L^3 x 16 B per distinct cube offset. */
+typedef struct bie_farml bie_farml;
+typedef struct {
+    double box;            /* leaf cube side (m), > 0 */
+    int levels;            /* octree levels used, 1..12 (1: single level) */
+    int s;                 /* splines per axis over one leaf cube side */
+    int p;                 /* degree: 1, 3 or 5 */
+} bie_farml_opts;
+/* BIE_EINVAL for bad options, buffers that reach half a cube on some level,
+ * or too many splines or points per axis on some level. */
+int bie_farml_create(const bie_op *op, const bie_farml_opts *opts, void *stream, bie_farml **out);
+/* Y = Z~_far X for R complex128 vectors (device, R x N each), one vector after
+ * another. */
+int bie_farml_apply(bie_farml *f, const void *X, void *Y, int64_t R, void *stream);
+/* Per level (0 = leaves): cubes, pairs translated there (far_pairs), buffer
+ * knots, equidistant splines and interpolation points per axis; protrusion and
+ * origin as for the leaves. */
+int bie_farml_level_info(const bie_farml *f, int level, bie_far_info *info);
+void bie_farml_destroy(bie_farml *f);
 
 /* Row sample of the random-sampling criterion: S distinct sorted indices in
  * [0, N) for `seed` (host out, S int64).  Exposed so callers can reproduce the

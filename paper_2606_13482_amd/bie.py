@@ -64,6 +64,10 @@ class FarOpts(ctypes.Structure):
     _fields_ = [("box", ctypes.c_double), ("s", ctypes.c_int), ("p", ctypes.c_int)]
 
 
+class FarMLOpts(ctypes.Structure):
+    _fields_ = [("box", ctypes.c_double), ("levels", ctypes.c_int), ("s", ctypes.c_int), ("p", ctypes.c_int)]
+
+
 class FarInfo(ctypes.Structure):
     _fields_ = [("boxes", ctypes.c_int64), ("far_pairs", ctypes.c_int64), ("buffer_knots", ctypes.c_int64),
                 ("splines", ctypes.c_int64), ("points_per_axis", ctypes.c_int64), ("protrusion", ctypes.c_double),
@@ -105,6 +109,10 @@ SYMBOLS = [
     ("bie_far_get_info", ctypes.c_int, [_P, _P]),
     ("bie_far_boxes", ctypes.c_int, [_P, _P]),
     ("bie_far_destroy", None, [_P]),
+    ("bie_farml_create", ctypes.c_int, [_P, _P, _P, ctypes.POINTER(_P)]),
+    ("bie_farml_apply", ctypes.c_int, [_P, _P, _P, _I64, _P]),
+    ("bie_farml_level_info", ctypes.c_int, [_P, ctypes.c_int, _P]),
+    ("bie_farml_destroy", None, [_P]),
     ("bie_ws_train", ctypes.c_int, [_P, _P, _P, _P, _I64, _P, _P, ctypes.POINTER(_P)]),
     ("bie_ws_fit", ctypes.c_int, [_P, _P, _P, _P, _I64, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_uint64, _P, _P]),
@@ -377,6 +385,45 @@ class Calderon:
     def close(self):
         if getattr(self, "_h", None):
             _lib.bie_calderon_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class FarFieldML:
+    """Multilevel far field of an operator (bie_farml_create): knot-insertion
+    transfers between the octree levels, FFT translations; apply() gives Z~_far X
+    for the pairs of far leaf cubes."""
+
+    def __init__(self, op: Operator, box: float, levels: int, s: int, p: int = 3, stream=None):
+        h = ctypes.c_void_p()
+        o = FarMLOpts(float(box), int(levels), int(s), int(p))
+        _check(_lib.bie_farml_create(op._h, ctypes.byref(o), _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self.op = op
+        self.N = op.N
+        self.levels = int(levels)
+
+    def apply(self, X: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        X2 = X.reshape(-1, self.N)
+        Y = torch.empty_like(X2) if out is None else out
+        _check(_lib.bie_farml_apply(self._h, _dev(X2, torch.complex128), _dev(Y, torch.complex128, X2.shape),
+                                    X2.shape[0], _stream(stream)))
+        return Y.reshape(X.shape)
+
+    def level_info(self, level: int) -> dict:
+        i = FarInfo()
+        _check(_lib.bie_farml_level_info(self._h, int(level), ctypes.byref(i)))
+        return dict(boxes=i.boxes, far_pairs=i.far_pairs, buffer_knots=i.buffer_knots, splines=i.splines,
+                    points_per_axis=i.points_per_axis, protrusion=i.protrusion, origin=list(i.origin))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.bie_farml_destroy(self._h)
             self._h = None
 
     def __del__(self):

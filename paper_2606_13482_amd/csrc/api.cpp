@@ -422,6 +422,38 @@ int bie_far_apply(bie_far *far, const void *X, void *Y, int64_t R, void *stream)
     });
 }
 
+int bie_farml_create(const bie_op *op, const bie_farml_opts *opts, void *stream, bie_farml **out)
+{
+    return guarded([&]() -> int {
+        if (!op || !opts || !out) return fail(BIE_EINVAL, "NULL argument");
+        *out = nullptr;
+        *out = bie::farml_create(op, opts->box, opts->levels, opts->s, opts->p, as_stream(stream));
+        return BIE_OK;
+    });
+}
+
+int bie_farml_apply(bie_farml *f, const void *X, void *Y, int64_t R, void *stream)
+{
+    return guarded([&]() -> int {
+        if (!f || !X || !Y) return fail(BIE_EINVAL, "NULL argument");
+        if (R < 0 || R > 64) return fail(BIE_EINVAL, "R out of range (0..64)");
+        if (R == 0) return BIE_OK;
+        bie::farml_apply(f, X, Y, R, as_stream(stream));
+        return BIE_OK;
+    });
+}
+
+int bie_farml_level_info(const bie_farml *f, int level, bie_far_info *info)
+{
+    return guarded([&]() -> int {
+        if (!f || !info) return fail(BIE_EINVAL, "NULL argument");
+        bie::farml_level_info(f, level, info);
+        return BIE_OK;
+    });
+}
+
+void bie_farml_destroy(bie_farml *f) { bie::farml_destroy(f); }
+
 int bie_far_get_info(const bie_far *far, bie_far_info *info)
 {
     if (!far || !info) return fail(BIE_EINVAL, "NULL argument");

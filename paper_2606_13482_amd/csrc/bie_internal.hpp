@@ -117,7 +117,8 @@ __host__ __device__ inline void tile_decode(int64_t b, int64_t nT, int64_t &I, i
 }  // namespace bie
 
 struct bie_ws;   // learned warm start (warmstart.hip)
-struct bie_far;  // single-level B-spline far field (bspline.hip)
+struct bie_far;    // single-level B-spline far field (bspline.hip)
+struct bie_farml;  // multilevel B-spline far field (bspline.hip)
 
 struct bie_op {
     int device = 0;
@@ -281,6 +282,10 @@ void far_apply(bie_far *f, const void *X, void *Y, int64_t R, hipStream_t st);
 void far_info(const bie_far *f, bie_far_info *info);
 void far_boxes(const bie_far *f, int32_t *out);
 void far_destroy(bie_far *f);
+bie_farml *farml_create(const bie_op *op, double a, int levels, int s, int p, hipStream_t st);
+void farml_apply(bie_farml *f, const void *X, void *Y, int64_t R, hipStream_t st);
+void farml_level_info(const bie_farml *f, int level, bie_far_info *info);
+void farml_destroy(bie_farml *f);
 
 // krylov.hip
 int solve_batch(const bie_op *const *ops, const bie_calderon *const *pcs, int64_t P, const void *const *B,

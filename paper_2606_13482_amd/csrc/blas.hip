@@ -309,7 +309,10 @@ __device__ inline int64_t uniform64(int64_t v)
 // Grouped tile pass over several problems: block b is the work item (problem
 // p, unit u, column group g) and goes through columns c0 + gG .. of p in turn,
 // skipping finished ones; the unit's tiles come from memory for the first
-// column and from the caches for the others.  Items are ordered longest first.
+// column and from the caches for the others.  A barrier separates the columns:
+// the column-sum buffers of the tile pass start again at parity 0, and the
+// last tile's buffer may still be read by another wave.  Items are ordered
+// longest first.
 template <typename M, typename T, bool PREFETCH>
 __global__ __launch_bounds__(256) void k_sym_tiles_g(const GProb *__restrict__ probs, GCols gc,
                                                      const int32_t *__restrict__ items, int G, const T *__restrict__ X,
@@ -327,8 +330,11 @@ __global__ __launch_bounds__(256) void k_sym_tiles_g(const GProb *__restrict__ p
     const int32_t J1 = __builtin_amdgcn_readfirstlane(P.units[3 * u + 2]);
     const int32_t uo = __builtin_amdgcn_readfirstlane(u - P.unit_ptr[I]);
     const int32_t cb = P.c0 + g * G, ce = min(P.c1, cb + G);
+    bool first = true;
     for (int32_t c = cb; c < ce; ++c) {
         if (skip && skip[int64_t(c) * sks]) continue;   // uniform over the block
+        if (!first) __syncthreads();
+        first = false;
         const int64_t xo = uniform64(gc.xoff[c] + gc.xstep * P.N), po = uniform64(gc.poff[c] * TB);
         tile_pass<M, T, false, PREFETCH, false>(static_cast<const M *>(P.Z), P.N, P.nT, I, J0, J1, uo, P.seg,
                                                 reinterpret_cast<const V2 *>(X) + xo,

@@ -1995,7 +1995,7 @@ int solve_batch(const bie_op *const *ops, const bie_calderon *const *pcs, int64_
         BIE_HIP(hipEventCreate(&e1));
         float best = 0.f;
         for (int cu : { 4, 8, 16 })
-            for (int cg : { 4, 8, 32 }) {
+            for (int cg : { 4, 8, 16, 32 }) {
                 auto Lc = make_layout(ops, P, Rp, cu, cg, mat64);
                 const GCols gc = layout_cols(*Lc, dwo, 0);
                 auto run = [&]() {

@@ -100,3 +100,84 @@ def test_far_rejections(bie):
         with pytest.raises(bie.BieError):
             bie.FarField(op, box, s, p)
     op.close()
+
+
+# ----------------------------------------------------------------------------- multilevel (bie_farml_*)
+@pytest.mark.parametrize("k,pairs", [(2.0, [5256, 386]), (6.0, [5256, 386])])
+def test_multilevel_matches_oracle(bie, k, pairs):
+    """Two levels (cubes of 0.35 m and 0.7 m) on the 1920-unknown sphere, cubic
+    splines, s = 8: k = 2 keeps s on the parent level (Sec. IV-C), k = 6 doubles
+    it to 2 s - p (Sec. IV-D); the GPU product (knot-insertion transfers, FFT
+    translations of sizes 16 and 32) against the oracle's multilevel product to
+    FP64 rounding, the level data equal, and within the interpolation error of
+    the dense oracle's entries between far leaf cubes."""
+    V, T = icosphere(3)
+    rwg = rwg_table(V, T)
+    a, s, p = 0.35, 8, 3
+    op = bie.Operator(V, T, k)
+    far = bie.FarFieldML(op, a, 2, s, p)
+    X = complex_gaussian(op.N, 31, cols=2)
+    Y = far.apply(torch.from_numpy(X).cuda()).cpu().numpy()
+    Yo, oi = bs.ml_far_product(rwg, k, X, a, 2, s, p)
+    err = np.linalg.norm(Y - Yo) / np.linalg.norm(Yo)
+    infos = [far.level_info(l) for l in range(2)]
+    for l, (inf, cfg, L) in enumerate(zip(infos, oi["configs"], oi["lists"])):
+        assert inf["boxes"] == len(L["boxes"]) and inf["far_pairs"] == len(L["pairs"]) == pairs[l]
+        assert inf["buffer_knots"] == cfg.sb and inf["splines"] == cfg.n and inf["points_per_axis"] == cfg.n_st
+    Z = cfill.fill(rwg, k)
+    F = bs.leaf_far_mask(oi["leaf_of"], oi["leaf_boxes"])
+    Yd = X @ (Z * F).T
+    e_dense = np.linalg.norm(Y - Yd) / np.linalg.norm(Yd)
+    _say(f"  k={k:g}: levels {[(i['boxes'], i['far_pairs'], i['splines'], i['points_per_axis']) for i in infos]}; "
+         f"GPU vs oracle {err:.2e}, vs dense far entries {e_dense:.2e}")
+    assert err <= 1e-12
+    assert e_dense <= 2e-3
+    far.close()
+    op.close()
+
+
+def test_multilevel_one_level_is_single_level(bie):
+    """One level: the multilevel product (FFT translations) equals the
+    single-level far field (lattice-table translations) to FP64 rounding."""
+    V, T = icosphere(3)
+    k, a, s, p = 2.0, 0.7, 8, 3
+    op = bie.Operator(V, T, k)
+    f1 = bie.FarField(op, a, s, p)
+    fm = bie.FarFieldML(op, a, 1, s, p)
+    x = torch.from_numpy(complex_gaussian(op.N, 32, cols=1)).cuda()
+    y1, ym = f1.apply(x).cpu().numpy(), fm.apply(x).cpu().numpy()
+    assert np.linalg.norm(y1 - ym) <= 1e-12 * np.linalg.norm(y1)
+    assert fm.level_info(0)["far_pairs"] == f1.info()["far_pairs"]
+    f1.close()
+    fm.close()
+    op.close()
+
+
+def test_multilevel_three_levels_against_dense(bie):
+    """Three levels (cubes of 0.2, 0.4 and 0.8 m) on the 7680-unknown sphere at
+    k = 2: the far product against the operator's own dense FP64 matrix masked
+    to the far leaf cubes (cubes from the oracle's box rule), within 2e-3; every
+    level translates pairs, the pairs of all levels cover the far leaf pairs."""
+    V, T = icosphere(4)
+    rwg = rwg_table(V, T)
+    k, a, s, p = 2.0, 0.2, 8, 3
+    op = bie.Operator(V, T, k)
+    far = bie.FarFieldML(op, a, 3, s, p)
+    infos = [far.level_info(l) for l in range(3)]
+    assert all(i["far_pairs"] > 0 for i in infos)
+    idx, lo, prot, origin = bs.box_level(rwg, a)
+    leaf_boxes, lists = bs.interaction_lists(idx, 3)
+    assert [len(L["pairs"]) for L in lists] == [i["far_pairs"] for i in infos]
+    _, finv = np.unique(np.concatenate([leaf_boxes, idx]), axis=0, return_inverse=True)
+    leaf_of = finv.ravel()[len(leaf_boxes):]
+    F = torch.from_numpy(bs.leaf_far_mask(leaf_of, leaf_boxes)).cuda()
+    Z = op.matrix()
+    X = torch.from_numpy(complex_gaussian(op.N, 33, cols=2)).cuda()
+    Yd = X @ (Z * F).T
+    Y = far.apply(X)
+    err = float(torch.linalg.norm(Y - Yd) / torch.linalg.norm(Yd))
+    _say(f"  3 levels: {[(i['boxes'], i['far_pairs'], i['splines'], i['points_per_axis']) for i in infos]}; "
+         f"vs dense far entries {err:.2e}")
+    assert err <= 2e-3
+    far.close()
+    op.close()
