@@ -643,7 +643,62 @@ def far_leg(args, bie, torch, V, T, k):
             "points_per_cube": n3, "buffer_knots": info["buffer_knots"], "ms_per_far_product": round(ms, 3),
             "point_pairs_per_s": round(pairs / (ms * 1e-3), 1), "translation_tflops": round(tf, 2),
             "translation_frac_fp64_vector_peak": round(tf / FP64_MFMA_PEAK_TFLOPS, 4),
-            "ms_per_dense_packed_product": round(ms_dense, 4)}
+            "ms_per_dense_packed_product": round(ms_dense, 4),
+            "multilevel": far_ml_leg(bie, torch, V, T, k)}
+
+
+def far_ml_leg(bie, torch, V, T, k, box=0.2, levels=2, s=8, p=3):
+    """The multilevel far field (Sec. IV) on the bench sphere: leaf cubes of 0.2 m,
+    two levels, cubic splines, s = 8 (the parent level doubles s: its cubes exceed
+    half a wavelength); time per far product (HIP events), per-level data, the
+    error against the operator's dense FP64 matrix masked to the far leaf cubes
+    (cube indices from the library), and the single-level far field on the same
+    leaf cubes (one product) for comparison."""
+    from paper_2606_13482_amd.inputs import complex_gaussian
+    sync = torch.cuda.synchronize
+    op = bie.Operator(V, T, k)
+    t0 = time.perf_counter()
+    fm = bie.FarFieldML(op, box, levels, s, p)
+    sync()
+    t_setup = time.perf_counter() - t0
+    lv = [fm.level_info(l) for l in range(levels)]
+    x = torch.from_numpy(complex_gaussian(op.N, 8, cols=1)).cuda()
+    y = fm.apply(x)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    sync()
+    ev0.record()
+    for _ in range(reps):
+        fm.apply(x, out=y)
+    ev1.record()
+    sync()
+    ms = ev0.elapsed_time(ev1) / reps
+    f1 = bie.FarField(op, box, s, p)
+    y1 = f1.apply(x)
+    sync()
+    ev0.record()
+    f1.apply(x, out=y1)
+    ev1.record()
+    sync()
+    ms1 = ev0.elapsed_time(ev1)
+    cubes = f1.boxes()
+    _, inv = np.unique(cubes, axis=0, return_inverse=True)
+    uc = np.unique(cubes, axis=0)
+    far = (np.max(np.abs(uc[:, None, :] - uc[None, :, :]), axis=2) > 1)[inv.ravel()][:, inv.ravel()]
+    Z = op.matrix()
+    yd = x @ (Z * torch.from_numpy(far).cuda()).T
+    err = float(torch.linalg.norm(y - yd) / torch.linalg.norm(yd))
+    err1 = float(torch.linalg.norm(y1 - yd) / torch.linalg.norm(yd))
+    del Z
+    f1.close()
+    fm.close()
+    op.close()
+    return {"workload": f"leaf cubes {box:g} m, {levels} levels, p = {p}, s = {s} on the leaves",
+            "setup_s": round(t_setup, 3), "ms_per_far_product": round(ms, 3),
+            "levels": [{"cubes": l["boxes"], "pairs": l["far_pairs"], "splines": l["splines"],
+                        "points_per_axis": l["points_per_axis"], "buffer_knots": l["buffer_knots"]} for l in lv],
+            "relerr_vs_dense_far": err, "far_fraction_of_entries": float(far.mean()),
+            "single_level_same_cubes": {"ms_per_far_product": round(ms1, 3), "relerr_vs_dense_far": err1}}
 
 
 def star_leg(args, bie, torch, V, T):

@@ -256,9 +256,13 @@ int bie_solve(const bie_op *op, const void *B, void *X, int64_t R, const bie_sol
               bie_solve_stat *stats, void *stream);
 
 /* Batched solves: the right-hand sides of nops operators of different sizes
- * (meshes, wavenumbers) solved together with GMRES(m) to the standard
- * criterion (method BIE_GMRES, crit BIE_SCC; other options as in bie_solve,
- * use_x0 0/1/2).  Precision 0: products with the stored matrices (all FP64 or
+ * (meshes, wavenumbers) solved together with GMRES(m) (method BIE_GMRES; other
+ * options as in bie_solve, use_x0 0/1/2).  Criteria: SCC, or RSCC / CCC as in
+ * bie_solve (S = min(rscc_rows, N_p, 4096) rows per right-hand side, drawn per
+ * check; needs the FP64 matrices: FP64 storage or precision 1): at the end of a
+ * cycle whose estimate meets tol, RSCC accepts on the sampled value, CCC
+ * confirms a sampled acceptance on the full residual; an initial guess is
+ * checked on its full residual.  Precision 0: products with the stored matrices (all FP64 or
  * all FP32), residuals on the same.  Precision 1 (every operator stored as
  * BIE_C64 with keep_fp64): the Arnoldi products on the FP32 tiles, every
  * residual -- the vector each restart cycle starts from and the criterion --

@@ -321,8 +321,10 @@ int bie_batch_solve_pc(const bie_op *const *ops, const bie_calderon *const *pcs,
         if (nops < 1 || nops > 4096) return fail(BIE_EINVAL, "nops out of range (1..4096)");
         bie_solve_opts o{ BIE_GMRES, 30, 1e-6, 10000, BIE_SCC, 512, 1234, 0, 0, 0.0, 0, 0, 0, 0, nullptr };
         if (opts) o = *opts;
-        if (o.method != BIE_GMRES || (o.precision != 0 && o.precision != 1) || o.crit != BIE_SCC || o.basis != 0)
-            return fail(BIE_EINVAL, "batched solves take GMRES, precision 0 or 1 and the standard criterion");
+        if (o.method != BIE_GMRES || (o.precision != 0 && o.precision != 1) || o.basis != 0)
+            return fail(BIE_EINVAL, "batched solves take GMRES with precision 0 or 1");
+        if (o.crit != BIE_SCC && o.crit != BIE_RSCC && o.crit != BIE_CCC) return fail(BIE_EINVAL, "unknown criterion");
+        if (o.crit != BIE_SCC && o.rscc_rows < 1) return fail(BIE_EINVAL, "rscc_rows must be >= 1");
         if (o.calderon) return fail(BIE_EINVAL, "batched solves take their preconditioners per operator (pcs)");
         if (o.restart < 1 || o.restart > 64) return fail(BIE_EINVAL, "restart must be 1..64");
         if (!(o.tol > 0.0)) return fail(BIE_EINVAL, "tol must be > 0");

@@ -579,11 +579,13 @@ void split_choice(int64_t Mp, int64_t Kp, int64_t NCp, int terms, hipStream_t s,
     ks = gemm_splitk(blocks, nst);
     const bool env_fixed = cfg >= 0 || env_int("BIE_GEMM_SPLITK", 0) > 0;
     if (cfg < 0) cfg = 0;
-    if (env_fixed || !tune_enabled() || stream_capturing(s)) return;
+    if (env_fixed || !tune_enabled()) return;
     const std::string key = "gemm_split:" + std::to_string(Mp) + "x" + std::to_string(Kp) + ":" +
                             std::to_string(NCp) + ":t" + std::to_string(terms);
     std::vector<int> v;
-    if (!tune_get(key, v) || v.size() != 2 || v[0] < 0 || v[0] >= kSplitCfgs || v[1] < 1) {
+    const bool have = tune_get(key, v) && v.size() == 2 && v[0] >= 0 && v[0] < kSplitCfgs && v[1] >= 1;
+    if (!have && stream_capturing(s)) return;   // no timing inside a captured graph: the defaults
+    if (!have) {
         std::vector<int> kss;
         for (int want : { ks / 2, ks, 2 * ks }) {
             const int k2 = gemm_splitk(blocks, nst, std::max(1, want));
@@ -655,6 +657,10 @@ void gemm_product(const bie_op *opc, const void *X, int64_t ldx, int vtype, void
     const int64_t N = op->mesh.N, Kp = op->gemm_Kp, Mp = op->gemm_Mp, NCp = gemm_pad_cols(R);
     const size_t plane = size_t(NCp) * size_t(Kp);
     if (op->bstage_cols < NCp) {
+        if (stream_capturing(s))
+            throw Error(BIE_EINVAL, "split-BF16 product: vector staging for " + std::to_string(NCp) + " columns (have " +
+                                        std::to_string(op->bstage_cols) + ", N " + std::to_string(N) +
+                                        ") cannot grow inside a captured graph");
         BIE_HIP(hipStreamSynchronize(s));
         if (op->Bbf) (void)hipFree(op->Bbf);
         op->Bbf = nullptr;
@@ -679,6 +685,10 @@ void gemm_product(const bie_op *opc, const void *X, int64_t ldx, int vtype, void
     split_choice(Mp, Kp, NCp, terms, s, Ah, Al, Bh, Bl, op, cfg, KS);
     const size_t pelems = size_t(KS) * size_t(Mp) * size_t(NCp);
     if (op->gemm_part_elems < pelems) {
+        if (stream_capturing(s))
+            throw Error(BIE_EINVAL, "split-BF16 product: partial sums of " + std::to_string(pelems) + " (have " +
+                                        std::to_string(op->gemm_part_elems) + ", K slices " + std::to_string(KS) +
+                                        ", N " + std::to_string(N) + ") cannot grow inside a captured graph");
         BIE_HIP(hipStreamSynchronize(s));
         if (op->gemm_part) (void)hipFree(op->gemm_part);
         op->gemm_part = nullptr;

@@ -1865,18 +1865,29 @@ std::string batch_key(const bie_op *const *ops, int64_t P, const int64_t *R, boo
 int solve_batch(const bie_op *const *ops, const bie_calderon *const *pcs, int64_t P, const void *const *Bp,
                 void *const *Xp, const int64_t *Rp, const bie_solve_opts &o, bie_solve_stat *stats, hipStream_t user)
 {
-    if (o.method != BIE_GMRES || (o.precision != 0 && o.precision != 1) || o.crit != BIE_SCC)
-        throw Error(BIE_EINVAL, "batched solves take GMRES, precision 0 or 1 and the standard criterion");
+    if (o.method != BIE_GMRES || (o.precision != 0 && o.precision != 1))
+        throw Error(BIE_EINVAL, "batched solves take GMRES with precision 0 or 1");
+    if (o.crit != BIE_SCC && o.crit != BIE_RSCC && o.crit != BIE_CCC) throw Error(BIE_EINVAL, "unknown criterion");
     // precision 1: the cycles on the FP32 tiles, every residual (restart vector
     // and criterion) on the FP64 tiles of the same operator
     const bool prec1 = o.precision == 1;
+    // split: precision 1 with split-BF16 operators: the cycles' products are the
+    // split-BF16 block products of each operator (matrix cores, every column of
+    // the operator at once), the residuals the grouped FP64 tile pass
+    const bool split = prec1 && ops[0]->Abf != nullptr;
     const bool mat64 = !prec1 && ops[0]->Z64 != nullptr;
     const bool res64 = prec1 || mat64;
+    const bool lay64 = split || mat64;   // tiles of the grouped layout
+    if (o.crit != BIE_SCC && !res64)
+        throw Error(BIE_EINVAL, "the random-sampling criterion needs the FP64 matrices (FP64 storage or precision 1)");
     for (int64_t p = 0; p < P; ++p) {
-        if (prec1) {
+        if (split) {
+            if (!ops[p]->Z64 || !ops[p]->Abf)
+                throw Error(BIE_EINVAL, "all operators of a split-BF16 batch need storage BIE_SPLIT_BF16");
+        } else if (prec1) {
             if (!ops[p]->Z64 || !ops[p]->Z32)
                 throw Error(BIE_EINVAL, "precision 1 needs the FP32 and the FP64 matrix of every operator "
-                                        "(storage BIE_C64 with keep_fp64)");
+                                        "(storage BIE_C64 with keep_fp64, or BIE_SPLIT_BF16)");
         } else if ((ops[p]->Z64 != nullptr) != mat64 || (!mat64 && !ops[p]->Z32)) {
             throw Error(BIE_EINVAL, "all operators of a batch need the same stored matrix (FP64 or FP32)");
         }
@@ -1975,7 +1986,7 @@ int solve_batch(const bie_op *const *ops, const bie_calderon *const *pcs, int64_
 
     // grouped product layout: tiles per unit and columns per item from the autotuner
     std::unique_ptr<GLayout> L;
-    const std::string key = batch_key(ops, P, Rp, mat64);
+    const std::string key = batch_key(ops, P, Rp, lay64);
     int U = g_batch.unit, G = 8;
     if (U == 0 && !tune_enabled()) U = 8;   // tuning off: the fixed default units
     if (U == 0) {
@@ -1996,10 +2007,10 @@ int solve_batch(const bie_op *const *ops, const bie_calderon *const *pcs, int64_
         float best = 0.f;
         for (int cu : { 4, 8, 16 })
             for (int cg : { 4, 8, 16, 32 }) {
-                auto Lc = make_layout(ops, P, Rp, cu, cg, mat64);
+                auto Lc = make_layout(ops, P, Rp, cu, cg, lay64);
                 const GCols gc = layout_cols(*Lc, dwo, 0);
                 auto run = [&]() {
-                    grouped_product(mat64, Lc->probs, gc, Lc->items, Lc->nitems, Lc->G, Lc->ritems, Lc->nritems, Bw,
+                    grouped_product(lay64, Lc->probs, gc, Lc->items, Lc->nitems, Lc->G, Lc->ritems, Lc->nritems, Bw,
                                     Lc->gpart, w->W, nullptr, nullptr, 1, s);
                 };
                 run();
@@ -2018,12 +2029,12 @@ int solve_batch(const bie_op *const *ops, const bie_calderon *const *pcs, int64_
         (void)hipEventDestroy(e1);
         tune_put(key, { L->U, L->G });
     } else {
-        L = make_layout(ops, P, Rp, U, G, mat64);
+        L = make_layout(ops, P, Rp, U, G, lay64);
     }
     const GCols gres = layout_cols(*L, dwo, 0);
     // the residuals' matrices (FP64 tiles under precision 1)
     const GProb *probs_res = L->probs;
-    if (res64 != mat64) {
+    if (res64 != lay64) {
         std::vector<const void *> Z(P);
         for (int64_t p = 0; p < P; ++p) Z[p] = ops[p]->Z64;
         probs_res = probs_on(db, *L, Z);
@@ -2034,8 +2045,11 @@ int solve_batch(const bie_op *const *ops, const bie_calderon *const *pcs, int64_
     const GProb *probs_m = nullptr;
     std::unique_ptr<GLayout> LM;
     double2 *Wz = nullptr;
-    if (pcs) {
-        std::vector<const bie_op *> views(P);
+    std::vector<const bie_op *> views(P, nullptr);
+    if (pcs && split) {
+        for (int64_t p = 0; p < P; ++p) views[p] = calderon_view(pcs[p], true, s);
+        Wz = db.get<double2>(size_t(nw));
+    } else if (pcs) {
         std::vector<const void *> Z(P);
         for (int64_t p = 0; p < P; ++p) {
             views[p] = mat64 ? calderon_view(pcs[p], false, s) : calderon_view32(pcs[p], s);
@@ -2051,6 +2065,24 @@ int solve_batch(const bie_op *const *ops, const bie_calderon *const *pcs, int64_
     }
     // partial vectors and items of the preconditioner's products
     const GLayout &LMr = LM ? *LM : *L;
+    // split mode: first column of every problem, the problems the captured
+    // cycle covers, and one uncaptured product of every operator (and
+    // preconditioner) so that its staging buffers exist and its launch shape is
+    // tuned before any capture
+    std::vector<int64_t> pc0(P, 0);
+    for (int64_t p = 1; p < P; ++p) pc0[p] = pc0[p - 1] + Rp[p - 1];
+    std::vector<int> live_prob(P, 0);
+    int64_t probs_built = -1;
+    auto split_product = [&](const bie_op *op, int64_t p, const double2 *X0, int64_t ldx, double2 *Y0) {
+        gemm_product(op, X0, ldx, VEC_C128, Y0, ops[p]->mesh.N, nullptr, 0, Rp[p], nullptr, s, 3);
+    };
+    if (split)
+        for (int64_t p = 0; p < P; ++p) {
+            if (Rp[p] == 0) continue;
+            const int64_t c0 = pc0[p], N = ops[p]->mesh.N;
+            split_product(ops[p], p, Bw + woff[c0], N, w->W + woff[c0]);
+            if (pcs) split_product(views[p], p, Bw + woff[c0], N, w->W + woff[c0]);
+        }
     // Live work: the tile items with at least one live column and the reduce
     // items of live columns, rebuilt (and the cycle graph captured again) when
     // the live columns have dropped by a quarter since the last build, so that
@@ -2161,12 +2193,75 @@ int solve_batch(const bie_op *const *ops, const bie_calderon *const *pcs, int64_
                 hs[c].relres_est = hs[c].relres_true = st[c].rnorm / st[c].bnorm;
             }
 
+    // Random-sampling criterion (RSCC, and the gate of CCC) of the columns in
+    // `on`: S_p rows of problem p drawn for each column from rscc_seed plus its
+    // number of earlier checks, |b_i - (T x)_i|^2 on the FP64 tiles; the value
+    // goes to relres_true, S_p / N_p of a product (rounded up) to its count.
+    std::vector<int64_t> ncheck(C, 0);
+    const int64_t Smax = std::min<int64_t>(std::max<int64_t>(o.rscc_rows, 1), MAX_RSCC_ROWS);
+    int64_t *drows = nullptr;
+    double *drs = nullptr;
+    if (o.crit != BIE_SCC) {
+        drows = db.get<int64_t>(size_t(C) * Smax);
+        drs = db.get<double>(size_t(C) * Smax);
+    }
+    auto sampled_check = [&](const std::vector<int> &on) {
+        std::vector<int64_t> rows(size_t(C) * Smax, 0);
+        std::vector<int64_t> Sof(P, 0), c0of(P, 0);
+        for (int64_t p = 0, c0 = 0; p < P; c0 += Rp[p], ++p) {
+            c0of[p] = c0;
+            Sof[p] = std::min<int64_t>(Smax, ops[p]->mesh.N);
+            for (int64_t r = 0; r < Rp[p]; ++r)
+                if (on[c0 + r]) {
+                    const auto v = rscc_rows(ops[p]->mesh.N, Sof[p], o.rscc_seed + uint64_t(ncheck[c0 + r]));
+                    std::copy(v.begin(), v.end(), rows.begin() + c0 * Smax + r * Sof[p]);
+                }
+        }
+        BIE_HIP(hipMemcpyAsync(drows, rows.data(), rows.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        push_mask(on);
+        for (int64_t p = 0; p < P; ++p) {
+            const int64_t c0 = c0of[p];
+            bool any = false;
+            for (int64_t r = 0; r < Rp[p] && !any; ++r) any = on[c0 + r] != 0;
+            if (!any) continue;
+            sampled_residual(ops[p], Bw + woff[c0], Xw + woff[c0], Rp[p], Sof[p], drows + c0 * Smax, drs + c0 * Smax,
+                             w->mask + c0, s);
+        }
+        std::vector<double> rs(size_t(C) * Smax);
+        BIE_HIP(hipMemcpyAsync(rs.data(), drs, rs.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        pull_st();
+        for (int64_t p = 0; p < P; ++p)
+            for (int64_t r = 0; r < Rp[p]; ++r) {
+                const int64_t c = c0of[p] + r;
+                if (!on[c]) continue;
+                double sum = 0.0;
+                for (int64_t i = 0; i < Sof[p]; ++i) sum += rs[c0of[p] * Smax + r * Sof[p] + i];
+                const int64_t N = ops[p]->mesh.N;
+                hs[c].relres_true = std::sqrt(double(N) / double(Sof[p]) * sum) / st[c].bnorm;
+                hs[c].checks += 1;
+                ncheck[c] += 1;
+                hs[c].mvps += (Sof[p] + N - 1) / N;
+            }
+    };
+
     // the m iterations of a cycle, captured once, replayed per cycle
     const int *done_flags = &w->st[0].done;
     const int64_t done_stride = sizeof(ColStat) / sizeof(int);
     auto cycle_body = [&]() {
         for (int j = 0; j < m; ++j) {
-            if (pcs) {   // w = T (M v_j)
+            if (split) {   // per operator: all its columns in one split-BF16 block product
+                for (int64_t p = 0; p < P; ++p) {
+                    if (!live_prob[p]) continue;
+                    const int64_t c0 = pc0[p], N = ops[p]->mesh.N;
+                    const double2 *vj = w->V + voff[c0] + int64_t(j) * N;
+                    if (pcs) {
+                        split_product(views[p], p, vj, int64_t(m + 1) * N, Wz + woff[c0]);
+                        split_product(ops[p], p, Wz + woff[c0], N, w->W + woff[c0]);
+                    } else {
+                        split_product(ops[p], p, vj, int64_t(m + 1) * N, w->W + woff[c0]);
+                    }
+                }
+            } else if (pcs) {   // w = T (M v_j)
                 const GCols gm = layout_cols(LMr, dvo, j);
                 if (LM)
                     grouped_product(mat64, probs_m, gm, LM->items, LM->nitems, LM->G, LM->ritems, LM->nritems, w->V,
@@ -2209,7 +2304,7 @@ int solve_batch(const bie_op *const *ops, const bie_calderon *const *pcs, int64_
         BIE_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
         prof_enable(prof_was);
     };
-    if (use_graph) capture();
+    if (use_graph && !split) capture();
 
     while (true) {
         bool any = false;
@@ -2222,7 +2317,24 @@ int solve_batch(const bie_op *const *ops, const bie_calderon *const *pcs, int64_
         for (int64_t c = 0; c < C; ++c) nlive += active[c] != 0;
         if (4 * nlive <= 3 * live_built) {
             build_live(active);
-            if (use_graph) capture();
+            if (use_graph && !split) capture();
+        }
+        if (split) {   // the cycle covers the problems with live columns; recaptured when they drop by a quarter
+            int64_t nlp = 0;
+            for (int64_t p = 0; p < P; ++p) {
+                bool any = false;
+                for (int64_t r = 0; r < Rp[p] && !any; ++r) any = active[pc0[p] + r] != 0;
+                nlp += any;
+            }
+            if (probs_built < 0 || 4 * nlp <= 3 * probs_built) {
+                for (int64_t p = 0; p < P; ++p) {
+                    bool any = false;
+                    for (int64_t r = 0; r < Rp[p] && !any; ++r) any = active[pc0[p] + r] != 0;
+                    live_prob[p] = any;
+                }
+                probs_built = nlp;
+                if (use_graph) capture();
+            }
         }
         for (int64_t c = 0; c < C; ++c) {
             ColStat &q = st[c];
@@ -2242,7 +2354,14 @@ int solve_batch(const bie_op *const *ops, const bie_calderon *const *pcs, int64_
         else cycle_body();
         hipLaunchKernelGGL(k_lsq, dim3(unsigned(C)), dim3(64), size_t(m) * m * sizeof(double2), s, m, w->H, w->g,
                            w->y, w->st);
-        if (pcs) {   // x += M (V y) for the active columns
+        if (pcs && split) {   // x += M (V y) for the active columns, M in split-BF16
+            hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, s, nw, Wz);
+            hipLaunchKernelGGL(k_xupd<double2>, egrid, dim3(BT), 0, s, cl, m, w->V, w->y, Wz, w->st);
+            for (int64_t p = 0; p < P; ++p)
+                if (live_prob[p])
+                    split_product(views[p], p, Wz + woff[pc0[p]], ops[p]->mesh.N, w->W + woff[pc0[p]]);
+            hipLaunchKernelGGL(k_add_active, egrid, dim3(BT), 0, s, cl, (const double2 *)w->W, Xw, w->st);
+        } else if (pcs) {   // x += M (V y) for the active columns
             hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, s, nw, Wz);
             hipLaunchKernelGGL(k_xupd<double2>, egrid, dim3(BT), 0, s, cl, m, w->V, w->y, Wz, w->st);
             for (int64_t c = 0; c < C; ++c) skip[c] = active[c] ? 0 : 1;
@@ -2260,14 +2379,32 @@ int solve_batch(const bie_op *const *ops, const bie_calderon *const *pcs, int64_
         }
         BIE_HIP(hipGetLastError());
         pull_st();
-        std::vector<int> nd(C, 0);
-        bool anyr = false;
+        std::vector<int> nd(C, 0), cand(C, 0), sampled_met(C, 0);
+        bool anyr = false, anyc = false;
         for (int64_t c = 0; c < C; ++c) {
             if (!active[c]) continue;
             hs[c].iters += st[c].jend;
             hs[c].mvps += st[c].jend;
             hs[c].relres_est = st[c].est;
-            if (hs[c].mvps < o.max_mvp || st[c].est <= o.tol || st[c].brk) {
+            cand[c] = st[c].est <= o.tol || st[c].brk;
+            anyc = anyc || cand[c];
+        }
+        if (o.crit != BIE_SCC && anyc) {
+            // the candidates' sampled residuals (FP64 rows); RSCC accepts on them,
+            // CCC confirms them on the full residual below
+            sampled_check(cand);
+            for (int64_t c = 0; c < C; ++c)
+                if (cand[c]) {
+                    sampled_met[c] = hs[c].relres_true <= o.tol;
+                    if (o.crit == BIE_RSCC && sampled_met[c]) {
+                        active[c] = 0;
+                        hs[c].converged = 1;
+                    }
+                }
+        }
+        for (int64_t c = 0; c < C; ++c) {
+            if (!active[c]) continue;
+            if (hs[c].mvps < o.max_mvp || cand[c]) {
                 nd[c] = 1;   // true residual: the criterion, or the restart
                 anyr = true;
             }
@@ -2276,9 +2413,9 @@ int solve_batch(const bie_op *const *ops, const bie_calderon *const *pcs, int64_
         pull_st();
         for (int64_t c = 0; c < C; ++c) {
             if (!active[c] || !nd[c]) continue;
-            const bool cand = st[c].est <= o.tol || st[c].brk;
-            if (cand) {
-                hs[c].checks += 1;
+            const bool decide = o.crit == BIE_SCC ? cand[c] != 0 : (o.crit == BIE_CCC && sampled_met[c]);
+            if (decide) {
+                if (o.crit == BIE_SCC) hs[c].checks += 1;
                 hs[c].relres_true = st[c].rnorm / st[c].bnorm;
                 if (hs[c].relres_true <= o.tol) {
                     active[c] = 0;

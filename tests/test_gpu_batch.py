@@ -212,3 +212,80 @@ def test_batch_pc_rejections(bie):
         bie.batch_solve(ops32, B32, bie.Solve(restart=20, precision="mixed"))
     for pc in pcs:
         pc.close()
+
+
+def test_batch_rscc_all_rows_equals_scc(bie):
+    """RSCC on every row (S >= N) is the SCC up to the order of the sums: the
+    batch takes the same decisions, iterations and solutions as with the SCC,
+    and every reported value agrees with the SCC value to the rounding of a
+    residual 1e-8 below the right-hand side (about 1e-16 / 1e-8)."""
+    ops, Bs = _ops(bie, "c128")
+    bie.batch_config(8, True)
+    try:
+        Xa, sa = bie.batch_solve(ops, Bs, bie.Solve(restart=20, tol=1e-8))
+        Xb, sb = bie.batch_solve(ops, Bs, bie.Solve(restart=20, tol=1e-8, crit="rscc", rscc_rows=4096))
+    finally:
+        bie.batch_config(0, True)
+    for p in range(len(ops)):
+        assert [s["iters"] for s in sa[p]] == [s["iters"] for s in sb[p]], p
+        assert torch.equal(Xa[p], Xb[p]), p
+        for x, y in zip(sa[p], sb[p]):
+            assert y["converged"] and abs(x["relres_true"] - y["relres_true"]) <= 1e-6 * x["relres_true"]
+
+
+def test_batch_ccc_precision1_with_preconditioner(bie):
+    """The uneven-batch form with the combined criterion (512 sampled rows gate,
+    the full FP64 residual confirms): converged and certified against the oracle
+    matrix like the SCC form; RSCC alone, on the same rows, converges with its
+    sampled value at the tolerance and the full residual within a small factor."""
+    ops, Bs = _ops_keep64(bie)
+    pcs = [bie.Calderon(op) for op in ops]
+    Xc, sc = bie.batch_solve(ops, Bs, bie.Solve(restart=30, tol=1e-6, precision="mixed", crit="ccc", rscc_rows=64),
+                             pcs=pcs)
+    Xr, sr = bie.batch_solve(ops, Bs, bie.Solve(restart=30, tol=1e-6, precision="mixed", crit="rscc", rscc_rows=64),
+                             pcs=pcs)
+    for p in range(len(ops)):
+        assert all(s["converged"] for s in sc[p]) and all(s["converged"] for s in sr[p])
+        assert max(s["relres_true"] for s in sc[p]) <= 1e-6
+        assert _oracle_res(p, Bs[p], Xc[p]).max() <= 1e-6 * (1 + 1e-6)
+        assert max(s["relres_true"] for s in sr[p]) <= 1e-6
+        assert _oracle_res(p, Bs[p], Xr[p]).max() <= 5e-6
+    for pc in pcs:
+        pc.close()
+
+
+def test_batch_rscc_needs_fp64(bie):
+    ops, Bs = _ops(bie, "c64")
+    with pytest.raises(RuntimeError):
+        bie.batch_solve(ops, Bs, bie.Solve(restart=20, crit="rscc"))
+
+
+@pytest.mark.parametrize("with_pc", [False, True])
+def test_batch_split_bf16_precision1(bie, with_pc):
+    """Precision 1 with split-BF16 operators: every operator's columns go through
+    its split-BF16 block product on the matrix cores (the preconditioner's too),
+    the residuals through the FP64 tiles: converged and certified against the
+    oracle matrix; graph replay and plain launches give bitwise the same result."""
+    ops, Bs = [], []
+    for pr in _problems():
+        op = bie.Operator(pr["V"], pr["T"], pr["k"], storage="split_bf16")
+        ops.append(op)
+        Bs.append(op.rhs(pr["d"], pr["e"]))
+    pcs = [bie.Calderon(op) for op in ops] if with_pc else None
+    opts = bie.Solve(restart=30, tol=1e-6, precision="mixed")
+    out = []
+    for graph in (True, False):
+        bie.batch_config(0, graph)
+        try:
+            out.append(bie.batch_solve(ops, Bs, opts, pcs=pcs))
+        finally:
+            bie.batch_config(0, True)
+    (Xs, sts), (X2, st2) = out
+    for p in range(len(ops)):
+        assert all(s["converged"] for s in sts[p]), p
+        assert max(s["relres_true"] for s in sts[p]) <= 1e-6
+        assert _oracle_res(p, Bs[p], Xs[p]).max() <= 1e-6 * (1 + 1e-6)
+        assert torch.equal(Xs[p], X2[p]) and [s["iters"] for s in sts[p]] == [s["iters"] for s in st2[p]]
+    if pcs:
+        for pc in pcs:
+            pc.close()
