@@ -774,7 +774,8 @@ def uneven_batch_leg(args, bie, torch):
     Ns = [op.N for op in ops]
     Rs = [b.shape[0] for b in Bs]
     nrhs = int(sum(Rs))
-    opts = bie.Solve(restart=50, tol=args.tol, precision="mixed")
+    # the combined criterion: 512 sampled FP64 rows gate each check, the full FP64 residual confirms
+    opts = bie.Solve(restart=50, tol=args.tol, precision="mixed", crit="ccc", rscc_rows=512)
 
     def summary(sts, t):
         conv = np.array([s["converged"] for st in sts for s in st], bool)
@@ -819,7 +820,8 @@ def uneven_batch_leg(args, bie, torch):
     seq = summary(stq, t_seq)
     out = {"workload": (f"{len(ops)} surfaces, N {min(Ns)}..{max(Ns)}, {nrhs} plane waves; GMRES(50) on the FP32 "
                         f"matrices right-preconditioned per surface (Calderon, FP32 copy of M), every residual on "
-                        f"the FP64 matrices, to {args.tol:g} (FP64 SCC), max 10000 products per right-hand side"),
+                        f"the FP64 matrices, to {args.tol:g} (CCC: 512 sampled FP64 rows gate, the FP64 SCC "
+                        f"confirms), max 10000 products per right-hand side"),
            **{k: v for k, v in main.items() if k != "s"}, "batch_s": main["s"], "relres_recomputed_fp64_max": rec,
            "first_call_s_with_autotune": round(t_first, 3), "fill_s": round(t_fill, 3),
            "calderon_setup_s": round(t_pc, 3),

@@ -96,6 +96,35 @@ int bie_op_create(const double *verts, int64_t nv, const int32_t *tris, int64_t 
                   double k, const bie_fill_opts *opts, void *stream, bie_op **out);
 void bie_op_destroy(bie_op *op);
 
+/* Fast operator (the paper's method, Sec. III-V): T x = N x + F x with no dense
+ * matrix.  F is the multilevel B-spline far field of bie_farml_create (leaf
+ * cubes of side `box`, `levels` octree levels, s splines of degree p on the
+ * leaves) over the pairs of far leaf cubes; N holds the entries T_mn between
+ * the RWG functions of near leaf cubes (index distance <= 1), computed as the
+ * dense fill computes them (Radon 7-point rule on both triangles, the singular
+ * treatment on the pairs flagged by near_factor, as bie_op_create) and kept in
+ * CSR.  The operator serves bie_apply (complex128, no conjugate), bie_solve
+ * (GMRES, precision 0, SCC, no preconditioner), bie_rhs_planewave, bie_farfield,
+ * bie_rcs and the far-field entry points; the calls that need a stored matrix
+ * (bie_op_matrix, the allocation-free product, batched solves, the Calderon
+ * preconditioner, block GMRES, CGNR, RSCC) return BIE_EINVAL.  Memory: 20 B per
+ * near entry, 144 B per flagged pair, and the far field's. */
+typedef struct {
+    double box;            /* leaf cube side (m) */
+    int levels;            /* octree levels of the far field, 1..12 */
+    int s;                 /* splines per axis on a leaf cube */
+    int p;                 /* spline degree: 1, 3 or 5 */
+    double near_factor;    /* flagged pairs as in bie_fill_opts (default 2) */
+} bie_fast_opts;
+typedef struct {
+    int64_t near_entries;  /* stored near entries (ordered pairs m, n) */
+    int64_t leaf_cubes;    /* non-empty leaf cubes */
+    int levels;
+} bie_fast_info;
+int bie_op_create_fast(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, double k,
+                       const bie_fast_opts *opts, void *stream, bie_op **out);
+int bie_op_fast_info(const bie_op *op, bie_fast_info *info);
+
 /* Number of unknowns N (= number of edges = 3 nt / 2). */
 int64_t bie_op_n(const bie_op *op);
 

@@ -64,6 +64,15 @@ class FarOpts(ctypes.Structure):
     _fields_ = [("box", ctypes.c_double), ("s", ctypes.c_int), ("p", ctypes.c_int)]
 
 
+class FastOpts(ctypes.Structure):
+    _fields_ = [("box", ctypes.c_double), ("levels", ctypes.c_int), ("s", ctypes.c_int), ("p", ctypes.c_int),
+                ("near_factor", ctypes.c_double)]
+
+
+class FastInfo(ctypes.Structure):
+    _fields_ = [("near_entries", ctypes.c_int64), ("leaf_cubes", ctypes.c_int64), ("levels", ctypes.c_int)]
+
+
 class FarMLOpts(ctypes.Structure):
     _fields_ = [("box", ctypes.c_double), ("levels", ctypes.c_int), ("s", ctypes.c_int), ("p", ctypes.c_int)]
 
@@ -89,6 +98,8 @@ _I64 = ctypes.c_int64
 SYMBOLS = [
     ("bie_op_create", ctypes.c_int, [_P, _I64, _P, _I64, ctypes.c_double, _P, _P, ctypes.POINTER(_P)]),
     ("bie_op_destroy", None, [_P]),
+    ("bie_op_create_fast", ctypes.c_int, [_P, _I64, _P, _I64, ctypes.c_double, _P, _P, ctypes.POINTER(_P)]),
+    ("bie_op_fast_info", ctypes.c_int, [_P, _P]),
     ("bie_op_n", _I64, [_P]),
     ("bie_op_edges", ctypes.c_int, [_P, _P]),
     ("bie_op_near_pairs", _I64, [_P, _P, _I64]),
@@ -392,6 +403,32 @@ class Calderon:
             self.close()
         except Exception:
             pass
+
+
+class FastOperator(Operator):
+    """The paper's fast operator (bie_op_create_fast): near entries between the
+    RWG functions of near leaf cubes, stored sparse, plus the multilevel B-spline
+    far field; no dense matrix.  apply() and solve() (GMRES, plain precision,
+    SCC) as for Operator."""
+
+    def __init__(self, V, T, k: float, box: float, levels: int, s: int, p: int = 3, near_factor: float = 2.0,
+                 stream=None):
+        V, pv = _host(V, np.float64)
+        T, pt = _host(T, np.int32)
+        o = FastOpts(float(box), int(levels), int(s), int(p), float(near_factor))
+        h = ctypes.c_void_p()
+        _check(_lib.bie_op_create_fast(pv, V.shape[0], pt, T.shape[0], float(k), ctypes.byref(o), _stream(stream),
+                                       ctypes.byref(h)))
+        self._h = h
+        self.k = float(k)
+        self.storage = "fast"
+        self.star = False
+        self.N = int(_lib.bie_op_n(h))
+
+    def fast_info(self) -> dict:
+        i = FastInfo()
+        _check(_lib.bie_op_fast_info(self._h, ctypes.byref(i)))
+        return dict(near_entries=i.near_entries, leaf_cubes=i.leaf_cubes, levels=i.levels)
 
 
 class FarFieldML:

@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbie.so")
-SOURCES = ["api.cpp", "mesh.cpp", "rng.cpp", "tune.cpp", "fill.hip", "blas.hip", "gemm.hip", "krylov.hip", "bgmres.hip", "calderon.hip", "warmstart.hip", "bspline.hip"]
+SOURCES = ["api.cpp", "mesh.cpp", "rng.cpp", "tune.cpp", "fill.hip", "blas.hip", "gemm.hip", "krylov.hip", "bgmres.hip", "calderon.hip", "warmstart.hip", "bspline.hip", "fast.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -36,6 +36,7 @@ hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
 void destroy_op(bie_op *op)
 {
     if (!op) return;
+    if (op->fast) bie::fast_destroy(op->fast);
     bie::free_workspace(op);
     bie::free_block_cache(op);
     bie::packed_free(op->pk);
@@ -118,6 +119,42 @@ int bie_op_create(const double *verts, int64_t nv, const int32_t *tris, int64_t 
     });
 }
 
+int bie_op_create_fast(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, double k,
+                       const bie_fast_opts *opts, void *stream, bie_op **out)
+{
+    return guarded([&]() -> int {
+        if (!out) return fail(BIE_EINVAL, "out is NULL");
+        *out = nullptr;
+        if (!verts || !tris || !opts) return fail(BIE_EINVAL, "NULL argument");
+        if (!(k > 0.0) || !std::isfinite(k)) return fail(BIE_EINVAL, "wavenumber must be positive and finite");
+        if (!(opts->near_factor >= 0.0)) return fail(BIE_EINVAL, "near_factor must be >= 0");
+        bie::Mesh mesh = bie::build_mesh(verts, nv, tris, nt, opts->near_factor);   // host only: EMESH first
+        bie_op *op = new bie_op();
+        try {
+            op->mesh = std::move(mesh);
+            BIE_HIP(hipGetDevice(&op->device));
+            op->k = k;
+            op->storage = BIE_C128;
+            hipStream_t s = as_stream(stream);
+            bie::upload_triangles(op, s);
+            bie::fast_setup(op, opts->box, opts->levels, opts->s, opts->p, s);
+        } catch (...) {
+            destroy_op(op);
+            throw;
+        }
+        *out = op;
+        return BIE_OK;
+    });
+}
+
+int bie_op_fast_info(const bie_op *op, bie_fast_info *info)
+{
+    if (!op || !info) return fail(BIE_EINVAL, "NULL argument");
+    if (!op->fast) return fail(BIE_EINVAL, "not a fast operator");
+    bie::fast_info(op, info);
+    return BIE_OK;
+}
+
 void bie_op_destroy(bie_op *op) { destroy_op(op); }
 
 int64_t bie_op_n(const bie_op *op) { return op ? op->mesh.N : int64_t(BIE_EINVAL); }
@@ -142,6 +179,7 @@ int bie_op_matrix(const bie_op *op, void *dst, int dtype, void *stream)
     return guarded([&]() -> int {
         if (!op || !dst) return fail(BIE_EINVAL, "NULL argument");
         if (op->star) return fail(BIE_EINVAL, "a star-split operator holds no assembled matrix");
+        if (op->fast) return fail(BIE_EINVAL, "a fast operator holds no dense matrix");
         hipStream_t s = as_stream(stream);
         if (dtype == BIE_C128) {
             bie::unpack_c128(op, op->Z64 != nullptr, dst, s);
@@ -183,6 +221,11 @@ int bie_apply(const bie_op *op, const void *X, void *Y, int64_t R, int vec, int 
         if (R == 0) return BIE_OK;
         const int64_t N = op->mesh.N;
         hipStream_t s = as_stream(stream);
+        if (op->fast) {
+            if (vec != BIE_C128 || conj) return fail(BIE_EINVAL, "the fast operator takes complex128 vectors, no conjugate");
+            bie::fast_product(op, X, N, Y, N, nullptr, 0, R, s);
+            return BIE_OK;
+        }
         if (vec == BIE_C128) {
             // FP64 matrix if stored, else the FP32 matrix with FP64 accumulation
             bie::product(op, op->Z64 ? bie::MAT64 : bie::MAT32, true, X, N, Y, N, nullptr, 0, R, nullptr, 1, conj != 0,
@@ -215,6 +258,7 @@ int bie_apply_noalloc(const bie_op *op, const void *X, void *Y, int64_t R, int v
         if (R == 0) return BIE_OK;
         if (vec != BIE_C128 && vec != BIE_C64)
             return fail(BIE_EINVAL, "the allocation-free product takes complex128 or complex64 vectors");
+        if (op->fast) return fail(BIE_EINVAL, "the allocation-free product takes an operator with a stored matrix");
         bie::product_noalloc(op, vec == BIE_C128, X, Y, R, conj != 0, as_stream(stream));
         return BIE_OK;
     });
@@ -281,6 +325,7 @@ int bie_calderon_create(const bie_op *op, void *stream, bie_calderon **out)
     return guarded([&]() -> int {
         if (!op || !out) return fail(BIE_EINVAL, "NULL argument");
         *out = nullptr;
+        if (op->fast) return fail(BIE_EINVAL, "the Calderon preconditioner needs an operator with a stored matrix");
         *out = bie::calderon_create(op, as_stream(stream));
         return BIE_OK;
     });

@@ -62,6 +62,7 @@ struct TriDev {
 };
 
 struct Workspace;  // solver workspaces (krylov.hip)
+struct FastOp;     // fast operator (fast.hip)
 
 // Packed symmetric storage of T (T = T^T exactly): only tiles (I, J) with
 // I <= J of TB x TB entries are stored, each tile row-major and contiguous,
@@ -147,6 +148,7 @@ struct bie_op {
     bie::Workspace *ws = nullptr;
     void *bcache = nullptr;       // block GMRES buffers, arenas and side streams (bgmres.hip), kept between solves
     int pooled = 0;               // Z64 and A64 belong to the preconditioner setup pool (not freed with the op)
+    bie::FastOp *fast = nullptr;  // fast operator: sparse near field + multilevel far field (fast.hip)
 };
 
 namespace bie {
@@ -286,6 +288,15 @@ bie_farml *farml_create(const bie_op *op, double a, int levels, int s, int p, hi
 void farml_apply(bie_farml *f, const void *X, void *Y, int64_t R, hipStream_t st);
 void farml_level_info(const bie_farml *f, int level, bie_far_info *info);
 void farml_destroy(bie_farml *f);
+void farml_leaves(const bie_farml *f, std::vector<int32_t> &box_of, std::vector<int32_t> &ijk);
+// fill.hip: the flagged pairs' local blocks, compact (18 doubles per pair)
+void singular_blocks(const bie_op *op, const int32_t *pairs, int64_t npairs, double *out, hipStream_t s);
+// fast.hip
+void fast_setup(bie_op *op, double box, int levels, int s, int p, hipStream_t st);
+void fast_product(const bie_op *op, const void *X, int64_t ldx, void *Y, int64_t ldy, const void *B, int64_t ldb,
+                  int64_t R, hipStream_t st);
+void fast_info(const bie_op *op, bie_fast_info *info);
+void fast_destroy(FastOp *f);
 
 // krylov.hip
 int solve_batch(const bie_op *const *ops, const bie_calderon *const *pcs, int64_t P, const void *const *B,

@@ -782,6 +782,11 @@ void product(const bie_op *opc, int mat, bool vec64, const void *X, int64_t ldx,
              const void *B, int64_t ldb, int64_t R, const int *skip, int64_t sks, bool conj, hipStream_t s)
 {
     bie_op *op = const_cast<bie_op *>(opc);
+    if (op->fast) {   // near entries + multilevel far field; every vector computed (no skip)
+        if (!vec64 || conj) throw Error(BIE_EINVAL, "the fast operator takes complex128 vectors, no conjugate");
+        fast_product(op, X, ldx, Y, ldy, B, ldb, R, s);
+        return;
+    }
     if (mat == MATBF16) {
         if (!op->Abf) throw Error(BIE_EINVAL, "no split-BF16 matrix stored");
         if (!vec64 || conj) throw Error(BIE_EINVAL, "the block product takes complex128 vectors, no conjugate");

@@ -1296,6 +1296,12 @@ void farml_level_info(const bie_farml *f, int level, bie_far_info *info)
     for (int d = 0; d < 3; ++d) info->origin[d] = f->origin[d];
 }
 
+void farml_leaves(const bie_farml *f, std::vector<int32_t> &box_of, std::vector<int32_t> &ijk)
+{
+    box_of = f->h_box_of;
+    ijk = f->lv[0].h_ijk;
+}
+
 void farml_destroy(bie_farml *f) { delete f; }
 
 }  // namespace bie

@@ -285,7 +285,8 @@ __global__ __launch_bounds__(128) void k_pairs_singular(int64_t npairs, int64_t 
                                                         const double *__restrict__ verts,
                                                         const double *__restrict__ area,
                                                         const int8_t *__restrict__ sgn, double k,
-                                                        R *__restrict__ LB, R *__restrict__ VS)
+                                                        R *__restrict__ LB, R *__restrict__ VS,
+                                                        double *__restrict__ compact = nullptr)
 {
     const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (idx >= npairs) return;
@@ -386,6 +387,15 @@ __global__ __launch_bounds__(128) void k_pairs_singular(int64_t npairs, int64_t 
                 Jr_[a][b] = Jr_[b][a] = mr;
                 Ji_[a][b] = Ji_[b][a] = mi;
             }
+    }
+    if (compact) {   // the pair's 3 x 3 block, pair after pair (near field of the fast operator)
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                const double ss = double(sgn[p * 3 + a] * sgn[q * 3 + b]);
+                compact[idx * 18 + (a * 3 + b) * 2 + 0] = ss * (-k4 * Ji_[a][b] + ik * j0i);
+                compact[idx * 18 + (a * 3 + b) * 2 + 1] = ss * (k4 * Jr_[a][b] - ik * j0r);
+            }
+        return;
     }
     for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b) {
@@ -591,6 +601,19 @@ T *dev_alloc(size_t n)
 
 // Weights of the triangle rule (relative to the area), for other kernels that
 // integrate over the same quadrature points.
+// The local 3 x 3 blocks L(p, a, q, b) of the flagged pairs (p <= q) of the
+// mesh's list, pair after pair (18 doubles each: re, im of (a, b) row-major),
+// with the fill's singular treatment.
+void singular_blocks(const bie_op *op, const int32_t *pairs, int64_t npairs, double *out, hipStream_t s)
+{
+    if (npairs == 0) return;
+    const TriDev &D = op->tri;
+    hipLaunchKernelGGL((k_pairs_singular<double, false>), dim3(unsigned((npairs + 127) / 128)), dim3(128), 0, s, npairs,
+                       int64_t(0), pairs, D.cent, D.loc, D.vfree, D.verts, D.area, D.sgn, op->k, (double *)nullptr,
+                       (double *)nullptr, out);
+    BIE_HIP(hipGetLastError());
+}
+
 void quad_weights(double *w)
 {
     const Rule rule = make_rule();

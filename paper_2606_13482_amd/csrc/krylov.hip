@@ -2460,6 +2460,11 @@ int batch_unit_chosen(const bie_op *const *ops, int64_t P, const int64_t *R)
 int solve(const bie_op *op, const void *B, void *X, int64_t R, const bie_solve_opts &o, bie_solve_stat *stats,
           hipStream_t s)
 {
+    if (op->fast) {
+        if (o.method != BIE_GMRES || o.precision != 0 || o.crit != BIE_SCC || o.calderon)
+            throw Error(BIE_EINVAL, "the fast operator solves with GMRES, precision 0 and the standard criterion");
+        return solve_impl(op, B, X, R, o, stats, s, MAT64, false);
+    }
     if (o.precision == 1) {
         if (!op->Z64 || !(op->Z32 || op->Abf))
             throw Error(BIE_EINVAL, "mixed precision needs the FP64 matrix and a low-precision copy "

@@ -85,7 +85,7 @@ def test_struct_layouts_match_header(tmp_path):
         pytest.skip("gcc not available")
     structs = {"bie_fill_opts": bie.FillOpts, "bie_solve_opts": bie.SolveOpts, "bie_solve_stat": bie.SolveStat,
                "bie_ws_opts": bie.WsOpts, "bie_calderon_info": bie.CalderonInfo, "bie_far_opts": bie.FarOpts,
-               "bie_far_info": bie.FarInfo, "bie_farml_opts": bie.FarMLOpts}
+               "bie_far_info": bie.FarInfo, "bie_farml_opts": bie.FarMLOpts, "bie_fast_opts": bie.FastOpts, "bie_fast_info": bie.FastInfo}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "bie.h"', 'int main(void) {']
     for cname, py in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
