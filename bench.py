@@ -27,6 +27,10 @@ Beside it, on the same GPU and right-hand sides:
     packed FP64 product against the HBM roofline (roofline_gemv);
   - the 30720-unknown sphere at k = 20 with the 512 plane waves of a 16 x 16
     (theta, phi) grid (key c3; 1 warm-up and 2 timed steps);
+  - the B-spline far field (single level and multilevel) and the fast operator
+    (sparse near entries + multilevel far field, no dense matrix) on the
+    30720-unknown sphere against the dense operator and on a 491520-unknown
+    sphere no dense matrix fits;
   - the star-split operator at low frequency, the uneven batch of 64 surfaces;
   - the CPU oracle on a bounded sample (cpu_baseline).
 
@@ -701,6 +705,83 @@ def far_ml_leg(bie, torch, V, T, k, box=0.2, levels=2, s=8, p=3):
             "single_level_same_cubes": {"ms_per_far_product": round(ms1, 3), "relerr_vs_dense_far": err1}}
 
 
+def fast_leg(args, bie, torch):
+    """The fast operator (near entries stored sparse + multilevel B-spline far
+    field, no dense matrix): (1) on the 30720-unknown sphere at k = 20 (leaf
+    cubes 0.2 m, two levels) against the dense FP64 operator: product error and
+    times, and one plane-wave GMRES(50) solve to 1e-6 with each; (2) on the
+    491520-unknown sphere (icosphere level 7) at k = 4 (leaf cubes 0.05 m, four
+    levels), where the packed FP64 matrix alone would take 1.9 TB: setup, memory
+    and time per product (HIP events)."""
+    from paper_2606_13482_amd.inputs import icosphere, complex_gaussian, planewave_set
+    sync = torch.cuda.synchronize
+
+    def ev_ms(fn, reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        fn()
+        sync()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        sync()
+        return e0.elapsed_time(e1) / reps
+
+    out = {}
+    V, T = icosphere(5)
+    k = 20.0
+    sync()
+    t0 = time.perf_counter()
+    op = bie.FastOperator(V, T, k, 0.2, 2, 8, 3)
+    sync()
+    t_setup = time.perf_counter() - t0
+    od = bie.Operator(V, T, k)
+    x = torch.from_numpy(complex_gaussian(op.N, 5, cols=1)).cuda()
+    y, yd = op.apply(x), od.apply(x)
+    err = float(torch.linalg.norm(y - yd) / torch.linalg.norm(yd))
+    ms_fast = ev_ms(lambda: op.apply(x, out=y), 5)
+    ms_dense = ev_ms(lambda: od.apply(x, out=yd), 10)
+    d, e = planewave_set(np.array([[0.0, 0.0, 1.0]]), "theta")
+    B = op.rhs(d, e)
+    opts = bie.Solve(restart=50, tol=args.tol, max_mvp=20000)
+    sync()
+    t0 = time.perf_counter()
+    X, st = op.solve(B, opts)
+    sync()
+    t_fast = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    Xd, std = od.solve(B, opts)
+    sync()
+    t_dense = time.perf_counter() - t0
+    out["sphere30720_k20"] = {
+        "workload": "PEC sphere, 20480 triangles (30720 RWG), k = 20; leaf cubes 0.2 m, 2 levels, s = 8, p = 3",
+        "fast": op.fast_info(), "setup_s": round(t_setup, 3), "ms_per_product": round(ms_fast, 3),
+        "ms_per_dense_fp64_product": round(ms_dense, 3), "product_relerr_vs_dense": err,
+        "solve": {"fast_s": round(t_fast, 3), "fast_iters": st[0]["iters"], "fast_converged": bool(st[0]["converged"]),
+                  "dense_s": round(t_dense, 3), "dense_iters": std[0]["iters"],
+                  "solution_relerr_vs_dense": float(torch.linalg.norm(X - Xd) / torch.linalg.norm(Xd))}}
+    od.close()
+    op.close()
+    V, T = icosphere(7)
+    free0 = torch.cuda.mem_get_info()[0]
+    sync()
+    t0 = time.perf_counter()
+    op = bie.FastOperator(V, T, 4.0, 0.05, 4, 8, 3)
+    sync()
+    t_setup = time.perf_counter() - t0
+    used = (free0 - torch.cuda.mem_get_info()[0]) / 2 ** 30
+    x = torch.from_numpy(complex_gaussian(op.N, 6, cols=1)).cuda()
+    y = op.apply(x)
+    ms = ev_ms(lambda: op.apply(x, out=y), 3)
+    N = op.N
+    out["sphere491520_k4"] = {
+        "workload": "PEC sphere, 327680 triangles (491520 RWG), k = 4; leaf cubes 0.05 m, 4 levels, s = 8, p = 3",
+        "fast": op.fast_info(), "setup_s": round(t_setup, 3), "gib_on_device": round(used, 2),
+        "ms_per_product": round(ms, 3), "packed_fp64_matrix_gib": round(8.0 * N * (N + 64) / 2 ** 30, 1)}
+    op.close()
+    return out
+
+
 def star_leg(args, bie, torch, V, T):
     """Star-split operator (Sec. VI-A: T = jk T_A + Sigma V Sigma^T / (jk)) against
     the assembled one on the bench sphere: (1) mixed precision with FP32 storage at
@@ -1014,6 +1095,8 @@ def main():
     out["far_field"] = far_leg(args, bie, torch, V, T, k)
     if args.star:
         out["star_split"] = star_leg(args, bie, torch, V, T)
+    out["fast_operator"] = fast_leg(args, bie, torch)
+    print(json.dumps({"progress": "fast operator done"}), file=sys.stderr, flush=True)
     if args.batch:
         out["uneven_batch"] = uneven_batch_leg(args, bie, torch)
         print(json.dumps({"progress": "uneven batch done"}), file=sys.stderr, flush=True)

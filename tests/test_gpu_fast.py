@@ -90,3 +90,29 @@ def test_fast_rejections(bie, sphere3):
     with pytest.raises(RuntimeError):
         op.apply(B.to(torch.complex64))
     op.close()
+
+
+def test_fast_c3_scale(bie):
+    """The 30720-unknown sphere at k = 20 (leaf cubes 0.2 m, two levels, the
+    parent level doubling s): the fast product within 2e-3 of the dense FP64
+    product, and GMRES(50) to 1e-6 on it within 2e-2 of the dense solution,
+    in about the same number of iterations."""
+    V, T = icosphere(5)
+    k = 20.0
+    op = bie.FastOperator(V, T, k, 0.2, 2, 8, 3)
+    od = bie.Operator(V, T, k)
+    x = torch.from_numpy(complex_gaussian(op.N, 51, cols=1)).cuda()
+    y, yd = op.apply(x), od.apply(x)
+    e_prod = float(torch.linalg.norm(y - yd) / torch.linalg.norm(yd))
+    d, e = planewave_set(np.array([[0.0, 0.0, 1.0]]), "theta")
+    B = op.rhs(d, e)
+    opts = bie.Solve(restart=50, tol=1e-6, max_mvp=20000)
+    X, st = op.solve(B, opts)
+    Xd, std = od.solve(B, opts)
+    e_sol = float(torch.linalg.norm(X - Xd) / torch.linalg.norm(Xd))
+    _say(f"  {op.fast_info()}: product vs dense {e_prod:.2e}; {st[0]['iters']} against {std[0]['iters']} "
+         f"iterations, solution vs dense {e_sol:.2e}")
+    assert e_prod <= 2e-3 and st[0]["converged"] and e_sol <= 2e-2
+    assert abs(st[0]["iters"] - std[0]["iters"]) <= 0.05 * std[0]["iters"]
+    od.close()
+    op.close()
