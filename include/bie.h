@@ -333,9 +333,13 @@ int bie_batch_solve_pc(const bie_op *const *ops, const struct bie_calderon *cons
  * on the batch; the choices are kept for the process and appended to the file
  * named by BIE_AUTOTUNE_CACHE if set; > 0: that many tiles per unit, 8 columns
  * per item; -1: each operator's own single-product units, 8 columns per item,
- * which makes every column bitwise equal to its single solve) and graph replay
- * (1: default).  BIE_EINVAL outside -1..64. */
-int bie_batch_config(int unit_tiles, int use_graph);
+ * which makes every column bitwise equal to its single solve), graph replay
+ * (1: default) and, for precision 1 on FP32 tiles, the grouped products on the
+ * FP32 matrix cores (matrix_cores 1, the default: every work item takes up to 32
+ * columns of its unit at once, vectors rounded to FP32 and FP32 accumulation
+ * within a unit, partial sums and their reduction in FP64; 0: the VALU pass with
+ * FP64 accumulation).  BIE_EINVAL outside -1..64. */
+int bie_batch_config(int unit_tiles, int use_graph, int matrix_cores);
 /* Tiles per unit chosen for this batch shape so far (0: none); for operators
  * holding both matrices, the choice for FP64 products if one was made, else the
  * one for FP32 products. */

@@ -112,7 +112,7 @@ SYMBOLS = [
     ("bie_rcs", ctypes.c_int, [_P, _P, _I64, _P, _I64, _P, _P]),
     ("bie_batch_solve", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P]),
     ("bie_batch_solve_pc", ctypes.c_int, [_P, _P, _I64, _P, _P, _P, _P, _P, _P]),
-    ("bie_batch_config", ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
+    ("bie_batch_config", ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     ("bie_batch_tuned", ctypes.c_int, [_P, _I64, _P]),
     ("bie_rscc_rows", ctypes.c_int, [_I64, _I64, ctypes.c_uint64, _P]),
     ("bie_far_create", ctypes.c_int, [_P, _P, _P, ctypes.POINTER(_P)]),
@@ -551,10 +551,11 @@ def batch_solve(ops, Bs, opts: Solve | None = None, x0s=None, x0_fallback: bool 
     return Xs, out
 
 
-def batch_config(unit_tiles: int = 0, graph: bool = True):
+def batch_config(unit_tiles: int = 0, graph: bool = True, matrix_cores: bool = True):
     """Tiles per unit of the grouped product (0: autotune; -1: each operator's own
-    single-product units, bitwise equal to single solves) and graph replay of batched solves."""
-    _check(_lib.bie_batch_config(int(unit_tiles), int(graph)))
+    single-product units, bitwise equal to single solves), graph replay, and the
+    FP32 matrix cores for the grouped products of precision-1 batches."""
+    _check(_lib.bie_batch_config(int(unit_tiles), int(graph), int(matrix_cores)))
 
 
 def batch_tuned(ops, R) -> int:

@@ -405,11 +405,11 @@ int bie_batch_solve(const bie_op *const *ops, int64_t nops, const void *const *B
     return bie_batch_solve_pc(ops, nullptr, nops, B, X, R, opts, stats, stream);
 }
 
-int bie_batch_config(int unit_tiles, int use_graph)
+int bie_batch_config(int unit_tiles, int use_graph, int matrix_cores)
 {
     return guarded([&]() -> int {
         if (unit_tiles < -1 || unit_tiles > 64) return fail(BIE_EINVAL, "unit_tiles must be -1..64");
-        bie::batch_config(unit_tiles, use_graph != 0);
+        bie::batch_config(unit_tiles, use_graph != 0, matrix_cores != 0);
         return BIE_OK;
     });
 }

@@ -216,9 +216,11 @@ void build_units(int64_t nT, int U, std::vector<int32_t> &units, std::vector<int
 // several problems: one tile launch over (problem, unit, group of G columns)
 // items, each going through its columns, and one reduce launch over (column,
 // row block) items.  mat64: FP64 tiles, else FP32.
+// mfma: the FP32 tiles on the FP32 matrix cores (FP32 vectors and
+// accumulation within a unit; at most 32 columns per item)
 void grouped_product(bool mat64, const GProb *probs, const GCols &gc, const int32_t *items, int64_t nitems, int G,
                      const int32_t *ritems, int64_t nritems, const void *X, void *part, void *Y, const void *B,
-                     const int *skip, int64_t sks, hipStream_t s);        // unit table (host -> device)
+                     const int *skip, int64_t sks, hipStream_t s, bool mfma = false);        // unit table (host -> device)
 void packed_free(Packed &pk);
 // Y = T X, T^H X (conj) or B - T X (B != NULL) for R vectors with the FP64
 // (mat64) or FP32 matrix; vectors complex128 (vec64, FP64 accumulation) or
@@ -301,7 +303,7 @@ void fast_destroy(FastOp *f);
 // krylov.hip
 int solve_batch(const bie_op *const *ops, const bie_calderon *const *pcs, int64_t P, const void *const *B,
                 void *const *X, const int64_t *R, const bie_solve_opts &o, bie_solve_stat *stats, hipStream_t s);
-void batch_config(int unit, int graph);
+void batch_config(int unit, int graph, int mfma);
 int batch_unit_chosen(const bie_op *const *ops, int64_t P, const int64_t *R);
 int solve(const bie_op *op, const void *B, void *X, int64_t R, const bie_solve_opts &o,
           bie_solve_stat *stats, hipStream_t s);

@@ -342,6 +342,108 @@ __global__ __launch_bounds__(256) void k_sym_tiles_g(const GProb *__restrict__ p
     }
 }
 
+// Grouped tile pass on the FP32 matrix cores (batches certified by FP64
+// residuals): block b is the work item (problem p, unit u, column group g of
+// at most 32 columns, padded with zeros to 32).  Per tile (I, J) of the unit
+// the complex products Y_I += Z X_J (rows of block I, accumulated over the
+// unit) and, for J != I, Y_J = Z^T X_I (written per tile) are four real
+// 32 x 32 x 2 chains of v_mfma_f32_32x32x2f32 per wave: wave w = 2 h + part
+// computes rows (or tile columns) 32 h .. 32 h + 31 of the real (part 0) or the
+// imaginary (part 1) output.  The tile (rows padded to 65 entries) and the two
+// vector blocks are staged in LDS in FP32 (the vectors rounded from FP64);
+// accumulation is FP32 within the unit; the partial vectors go to the same
+// FP64 slots as the VALU tile pass's, so the same reduction sums them.
+typedef float f32x16g __attribute__((ext_vector_type(16)));
+
+__global__ __launch_bounds__(256) void k_sym_tiles_gm(const GProb *__restrict__ probs, GCols gc,
+                                                      const int32_t *__restrict__ items, int G,
+                                                      const double *__restrict__ X, double *__restrict__ part,
+                                                      const int *__restrict__ skip, int64_t sks)
+{
+    __shared__ float2 sZ[TB][TB + 1];
+    __shared__ float2 sXI[TB][32];
+    __shared__ float2 sXJ[TB][32];
+    __shared__ int32_t live[32];
+    const int64_t b = blockIdx.x;
+    const int32_t p = items[3 * b], u = items[3 * b + 1], g = items[3 * b + 2];
+    const GProb P = probs[p];
+    const int32_t I = __builtin_amdgcn_readfirstlane(P.units[3 * u]);
+    const int32_t J0 = __builtin_amdgcn_readfirstlane(P.units[3 * u + 1]);
+    const int32_t J1 = __builtin_amdgcn_readfirstlane(P.units[3 * u + 2]);
+    const int32_t uo = __builtin_amdgcn_readfirstlane(u - P.unit_ptr[I]);
+    const int32_t cb = P.c0 + g * G, ce = min(min(P.c1, cb + G), cb + 32);
+    const int nc = ce - cb;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, h = w >> 1, prt = w & 1, li = lane & 31, lk = lane >> 5;
+    if (t < 32) live[t] = (t < nc && !(skip && skip[int64_t(cb + t) * sks])) ? 1 : 0;
+    __syncthreads();
+    bool any = false;
+    for (int c = 0; c < nc; ++c) any = any || live[c] != 0;
+    if (!any) return;   // uniform over the block
+    const float2 *Z = static_cast<const float2 *>(P.Z);
+    const double2 *Xc = reinterpret_cast<const double2 *>(X);
+    auto stage_x = [&](float2 (*dst)[32], int32_t blk) {
+        for (int e = t; e < TB * 32; e += 256) {
+            const int r = e >> 5, c = e & 31;
+            const int64_t row = int64_t(blk) * TB + r;
+            float2 v = make_float2(0.f, 0.f);
+            if (live[c] && row < P.N) {
+                const double2 xv = Xc[gc.xoff[cb + c] + gc.xstep * P.N + row];
+                v = make_float2(float(xv.x), float(xv.y));
+            }
+            dst[r][c] = v;
+        }
+    };
+    // one real 32 x 32 output of the complex product, k over the 64 entries
+    // (A from the tile, B from a vector block)
+    auto chain = [&](f32x16g acc, bool transposed, float2 (*xs)[32]) {
+#pragma unroll 8
+        for (int k0 = 0; k0 < TB; k0 += 2) {
+            const float2 z = transposed ? sZ[k0 + lk][32 * h + li] : sZ[32 * h + li][k0 + lk];
+            const float2 x = xs[k0 + lk][li];
+            if (prt == 0) {
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(z.x, x.x, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(-z.y, x.y, acc, 0, 0, 0);
+            } else {
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(z.x, x.y, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(z.y, x.x, acc, 0, 0, 0);
+            }
+        }
+        return acc;
+    };
+    // value q of lane l: row 32 h + 8 (q / 4) + 4 (l / 32) + q % 4, column l % 32
+    auto store = [&](const f32x16g &acc, int64_t slot) {
+        if (!live[li]) return;
+        double *pv = part + (gc.poff[cb + li] * TB + slot * TB) * 2 + prt;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int r = 32 * h + 8 * (q >> 2) + 4 * lk + (q & 3);
+            pv[2 * r] = double(acc[q]);
+        }
+    };
+    stage_x(sXI, I);
+    f32x16g arow;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) arow[q] = 0.f;
+    for (int32_t J = J0; J < J1; ++J) {
+        __syncthreads();   // the previous tile's reads are done
+        {
+            const float2 *tile = Z + tile_of(I, J, P.nT) * TB * TB;
+            for (int e = t; e < TB * TB; e += 256) sZ[e >> 6][e & 63] = tile[e];
+        }
+        stage_x(sXJ, J);
+        __syncthreads();
+        arow = chain(arow, false, sXJ);
+        if (J != I) {
+            f32x16g acol;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acol[q] = 0.f;
+            acol = chain(acol, true, sXI);
+            store(acol, P.seg[J] + I);
+        }
+    }
+    store(arow, P.seg[I] + I + uo);
+}
+
 // y_I = sum of the partial vectors of row block I (column sums of tiles
 // (J < I, I), then row sums of the units of tile row I), stored contiguously.
 // Eight waves split the vectors (every eighth one) and their sums are added in
@@ -865,11 +967,15 @@ void product_noalloc(const bie_op *op, bool vec64, const void *X, void *Y, int64
 
 void grouped_product(bool mat64, const GProb *probs, const GCols &gc, const int32_t *items, int64_t nitems, int G,
                      const int32_t *ritems, int64_t nritems, const void *X, void *part, void *Y, const void *B,
-                     const int *skip, int64_t sks, hipStream_t s)
+                     const int *skip, int64_t sks, hipStream_t s, bool mfma)
 {
     if (nitems == 0) return;
     const bool pf = sym_prefetch() != 0;
-    if (mat64) {
+    if (mfma) {
+        if (mat64 || G > 32) throw Error(BIE_EINVAL, "the matrix-core grouped pass takes FP32 tiles and at most 32 columns");
+        hipLaunchKernelGGL(k_sym_tiles_gm, dim3(unsigned(nitems)), dim3(256), 0, s, probs, gc, items, G,
+                           (const double *)X, (double *)part, skip, sks);
+    } else if (mat64) {
         if (pf) hipLaunchKernelGGL((k_sym_tiles_g<double, double, true>), dim3(unsigned(nitems)), dim3(256), 0, s, probs,
                                    gc, items, G, (const double *)X, (double *)part, skip, sks);
         else hipLaunchKernelGGL((k_sym_tiles_g<double, double, false>), dim3(unsigned(nitems)), dim3(256), 0, s,

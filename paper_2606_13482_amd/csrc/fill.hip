@@ -78,6 +78,15 @@ struct TriLDS {
     R loc[NQ][3];
     R vf[3][3];
 };
+// FP64: one double of padding (31 per triangle), so that the 16 triangles of a
+// tile read in one instruction start in 16 different bank pairs (30 doubles put
+// triangles 8 apart in the same banks: a two-way conflict on every read).
+template <>
+struct TriLDS<double> {
+    double loc[NQ][3];
+    double vf[3][3];
+    double pad;
+};
 
 template <typename R>
 __device__ inline void sincos_t(R x, R *s, R *c);

@@ -1722,6 +1722,7 @@ namespace {
 struct BatchConfig {
     int unit = 0;      // tiles per work unit; 0: autotune
     int graph = 1;     // replay the cycles as a HIP graph
+    int mfma = 1;      // precision 1, FP32 tiles: the grouped products on the matrix cores
 };
 BatchConfig g_batch;
 
@@ -1840,7 +1841,7 @@ std::unique_ptr<GLayout> make_layout(const bie_op *const *ops, int64_t P, const 
 // columns per item), kept in the library's tuning registry (tune.cpp).
 // The key names the precision, the number of operators and right-hand sides,
 // and a 64-bit FNV-1a hash of the (N_p, R_p) list.
-std::string batch_key(const bie_op *const *ops, int64_t P, const int64_t *R, bool mat64)
+std::string batch_key(const bie_op *const *ops, int64_t P, const int64_t *R, bool mat64, bool mfma = false)
 {
     uint64_t h = 1469598103934665603ull;
     int64_t nr = 0;
@@ -1857,7 +1858,8 @@ std::string batch_key(const bie_op *const *ops, int64_t P, const int64_t *R, boo
     }
     char hex[17];
     snprintf(hex, sizeof hex, "%016llx", (unsigned long long)h);
-    return std::string(mat64 ? "batch:f64" : "batch:f32") + ":P" + std::to_string(P) + ":R" + std::to_string(nr) + ":" + hex;
+    return std::string(mat64 ? "batch:f64" : (mfma ? "batch:f32mf" : "batch:f32")) + ":P" + std::to_string(P) + ":R" +
+           std::to_string(nr) + ":" + hex;
 }
 
 }  // namespace
@@ -1878,6 +1880,9 @@ int solve_batch(const bie_op *const *ops, const bie_calderon *const *pcs, int64_
     const bool mat64 = !prec1 && ops[0]->Z64 != nullptr;
     const bool res64 = prec1 || mat64;
     const bool lay64 = split || mat64;   // tiles of the grouped layout
+    // precision 1 on FP32 tiles: the cycles' grouped products on the FP32 matrix
+    // cores (the FP64 residuals keep the certification)
+    const bool mf = prec1 && !split && g_batch.mfma != 0;
     if (o.crit != BIE_SCC && !res64)
         throw Error(BIE_EINVAL, "the random-sampling criterion needs the FP64 matrices (FP64 storage or precision 1)");
     for (int64_t p = 0; p < P; ++p) {
@@ -1986,7 +1991,7 @@ int solve_batch(const bie_op *const *ops, const bie_calderon *const *pcs, int64_
 
     // grouped product layout: tiles per unit and columns per item from the autotuner
     std::unique_ptr<GLayout> L;
-    const std::string key = batch_key(ops, P, Rp, lay64);
+    const std::string key = batch_key(ops, P, Rp, lay64, mf);
     int U = g_batch.unit, G = 8;
     if (U == 0 && !tune_enabled()) U = 8;   // tuning off: the fixed default units
     if (U == 0) {
@@ -2011,7 +2016,7 @@ int solve_batch(const bie_op *const *ops, const bie_calderon *const *pcs, int64_
                 const GCols gc = layout_cols(*Lc, dwo, 0);
                 auto run = [&]() {
                     grouped_product(lay64, Lc->probs, gc, Lc->items, Lc->nitems, Lc->G, Lc->ritems, Lc->nritems, Bw,
-                                    Lc->gpart, w->W, nullptr, nullptr, 1, s);
+                                    Lc->gpart, w->W, nullptr, nullptr, 1, s, mf);
                 };
                 run();
                 BIE_HIP(hipEventRecord(e0, s));
@@ -2265,16 +2270,16 @@ int solve_batch(const bie_op *const *ops, const bie_calderon *const *pcs, int64_
                 const GCols gm = layout_cols(LMr, dvo, j);
                 if (LM)
                     grouped_product(mat64, probs_m, gm, LM->items, LM->nitems, LM->G, LM->ritems, LM->nritems, w->V,
-                                    LM->gpart, Wz, nullptr, done_flags, done_stride, s);
+                                    LM->gpart, Wz, nullptr, done_flags, done_stride, s, mf);
                 else
                     grouped_product(mat64, probs_m, gm, litems, nlitems, L->G, lritems, nlritems, w->V, L->gpart, Wz,
-                                    nullptr, done_flags, done_stride, s);
+                                    nullptr, done_flags, done_stride, s, mf);
                 grouped_product(mat64, L->probs, gres, litems, nlitems, L->G, lritems, nlritems, Wz, L->gpart, w->W,
-                                nullptr, done_flags, done_stride, s);
+                                nullptr, done_flags, done_stride, s, mf);
             } else {
                 const GCols gv = layout_cols(*L, dvo, j);
                 grouped_product(mat64, L->probs, gv, litems, nlitems, L->G, lritems, nlritems, w->V, L->gpart, w->W,
-                                nullptr, done_flags, done_stride, s);
+                                nullptr, done_flags, done_stride, s, mf);
             }
             arnoldi_step<double2>(w, cl, Nmax, w->V, m, j, o.tol, C, s);
         }
@@ -2369,10 +2374,10 @@ int solve_batch(const bie_op *const *ops, const bie_calderon *const *pcs, int64_
             const GCols gz = layout_cols(LMr, dwo, 0);
             if (LM)
                 grouped_product(mat64, probs_m, gz, LM->items, LM->nitems, LM->G, LM->ritems, LM->nritems, Wz,
-                                LM->gpart, w->W, nullptr, w->mask, 1, s);
+                                LM->gpart, w->W, nullptr, w->mask, 1, s, mf);
             else
                 grouped_product(mat64, probs_m, gz, litems, nlitems, L->G, lritems, nlritems, Wz, L->gpart, w->W,
-                                nullptr, w->mask, 1, s);
+                                nullptr, w->mask, 1, s, mf);
             hipLaunchKernelGGL(k_add_active, egrid, dim3(BT), 0, s, cl, (const double2 *)w->W, Xw, w->st);
         } else {
             hipLaunchKernelGGL(k_xupd<double2>, egrid, dim3(BT), 0, s, cl, m, w->V, w->y, Xw, w->st);
@@ -2443,16 +2448,18 @@ int solve_batch(const bie_op *const *ops, const bie_calderon *const *pcs, int64_
     return status;
 }
 
-void batch_config(int unit, int graph)
+void batch_config(int unit, int graph, int mfma)
 {
     g_batch.unit = unit;
     g_batch.graph = graph;
+    g_batch.mfma = mfma;
 }
 
 int batch_unit_chosen(const bie_op *const *ops, int64_t P, const int64_t *R)
 {
     std::vector<int> v;
     if (ops[0]->Z64 && tune_get(batch_key(ops, P, R, true), v) && !v.empty()) return v[0];
+    if (ops[0]->Z32 && tune_get(batch_key(ops, P, R, false, true), v) && !v.empty()) return v[0];
     if (ops[0]->Z32 && tune_get(batch_key(ops, P, R, false), v) && !v.empty()) return v[0];
     return 0;
 }

@@ -289,3 +289,33 @@ def test_batch_split_bf16_precision1(bie, with_pc):
     if pcs:
         for pc in pcs:
             pc.close()
+
+
+@pytest.mark.parametrize("with_pc", [False, True])
+def test_batch_matrix_cores_precision1(bie, with_pc):
+    """Precision 1 on FP32 tiles with the grouped products on the FP32 matrix
+    cores (the default) against the FP64-accumulating VALU pass: both converge,
+    both are certified against the oracle's FP64 matrix, the iterations differ
+    by a few per restart cycle at most, and the solutions agree to the
+    tolerance times the conditioning."""
+    ops, Bs = _ops_keep64(bie)
+    pcs = [bie.Calderon(op) for op in ops] if with_pc else None
+    opts = bie.Solve(restart=30, tol=1e-6, precision="mixed")
+    out = []
+    for mc in (True, False):
+        bie.batch_config(0, True, mc)
+        try:
+            out.append(bie.batch_solve(ops, Bs, opts, pcs=pcs))
+        finally:
+            bie.batch_config(0, True, True)
+    (Xm, sm), (Xv, sv) = out
+    for p in range(len(ops)):
+        assert all(s["converged"] for s in sm[p]) and all(s["converged"] for s in sv[p])
+        assert _oracle_res(p, Bs[p], Xm[p]).max() <= 1e-6 * (1 + 1e-6)
+        for a, b in zip(sm[p], sv[p]):
+            assert a["iters"] <= b["iters"] + 10, (p, a["iters"], b["iters"])
+        d = torch.linalg.vector_norm(Xm[p] - Xv[p], dim=1) / torch.linalg.vector_norm(Xv[p], dim=1)
+        assert float(d.max()) <= 1e-3, (p, d)
+    if pcs:
+        for pc in pcs:
+            pc.close()
