@@ -381,20 +381,32 @@ __global__ __launch_bounds__(256) void k_sym_tiles_gm(const GProb *__restrict__ 
     if (!any) return;   // uniform over the block
     const float2 *Z = static_cast<const float2 *>(P.Z);
     const double2 *Xc = reinterpret_cast<const double2 *>(X);
-    auto stage_x = [&](float2 (*dst)[32], int32_t blk) {
-        for (int e = t; e < TB * 32; e += 256) {
-            const int r = e >> 5, c = e & 31;
-            const int64_t row = int64_t(blk) * TB + r;
-            float2 v = make_float2(0.f, 0.f);
-            if (live[c] && row < P.N) {
-                const double2 xv = Xc[gc.xoff[cb + c] + gc.xstep * P.N + row];
-                v = make_float2(float(xv.x), float(xv.y));
-            }
-            dst[r][c] = v;
+    // staging: thread t always moves column t & 31 of the vectors (rows t/32 + 8 i)
+    // and entries t + 256 i of the tile (row t/64 + 4 i, column t & 63)
+    const int sc = t & 31, sr = t >> 5;
+    const bool slive = live[sc] != 0;
+    const int64_t sxo = slive ? gc.xoff[cb + sc] + gc.xstep * P.N : 0;
+    auto load_x = [&](double2 (&xv)[8], int32_t blk) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int64_t row = int64_t(blk) * TB + sr + 8 * q;
+            xv[q] = (slive && row < P.N) ? Xc[sxo + row] : make_double2(0.0, 0.0);
         }
     };
-    // one real 32 x 32 output of the complex product, k over the 64 entries
-    // (A from the tile, B from a vector block)
+    auto put_x = [&](float2 (*dst)[32], const double2 (&xv)[8]) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) dst[sr + 8 * q][sc] = make_float2(float(xv[q].x), float(xv[q].y));
+    };
+    auto load_z = [&](float2 (&zv)[16], int32_t J) {
+        const float2 *tile = Z + tile_of(I, J, P.nT) * TB * TB + t;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) zv[q] = tile[256 * q];
+    };
+    auto put_z = [&](const float2 (&zv)[16]) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) sZ[(t >> 6) + 4 * q][t & 63] = zv[q];
+    };
+    // one real 32 x 32 output of the complex product over the 64 entries of k
     auto chain = [&](f32x16g acc, bool transposed, float2 (*xs)[32]) {
 #pragma unroll 8
         for (int k0 = 0; k0 < TB; k0 += 2) {
@@ -411,27 +423,35 @@ __global__ __launch_bounds__(256) void k_sym_tiles_gm(const GProb *__restrict__ 
         return acc;
     };
     // value q of lane l: row 32 h + 8 (q / 4) + 4 (l / 32) + q % 4, column l % 32
+    const bool olive = live[li] != 0;
+    const int64_t opo = olive ? gc.poff[cb + li] * TB : 0;
     auto store = [&](const f32x16g &acc, int64_t slot) {
-        if (!live[li]) return;
-        double *pv = part + (gc.poff[cb + li] * TB + slot * TB) * 2 + prt;
+        if (!olive) return;
+        double *pv = part + (opo + slot * TB) * 2 + prt;
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int r = 32 * h + 8 * (q >> 2) + 4 * lk + (q & 3);
             pv[2 * r] = double(acc[q]);
         }
     };
-    stage_x(sXI, I);
+    double2 xv[8];
+    float2 zv[16];
+    load_x(xv, I);
+    put_x(sXI, xv);
+    load_z(zv, J0);
+    load_x(xv, J0);
     f32x16g arow;
 #pragma unroll
     for (int q = 0; q < 16; ++q) arow[q] = 0.f;
     for (int32_t J = J0; J < J1; ++J) {
-        __syncthreads();   // the previous tile's reads are done
-        {
-            const float2 *tile = Z + tile_of(I, J, P.nT) * TB * TB;
-            for (int e = t; e < TB * TB; e += 256) sZ[e >> 6][e & 63] = tile[e];
-        }
-        stage_x(sXJ, J);
+        __syncthreads();   // the previous tile's LDS reads are done
+        put_z(zv);
+        put_x(sXJ, xv);
         __syncthreads();
+        if (J + 1 < J1) {   // the next tile's loads go out before this tile's products
+            load_z(zv, J + 1);
+            load_x(xv, J + 1);
+        }
         arow = chain(arow, false, sXJ);
         if (J != I) {
             f32x16g acol;
