@@ -938,8 +938,10 @@ def counters_probe(args, bie, torch):
     product (one column), the split-BF16 block product and the FP64 block product
     (512 columns, the headline's 16 groups of 32) on the bench operator; the
     fill of that operator in FP64 and in FP32; the grouped products of the uneven
-    batch (FP32 matrices, all 1069 columns, the autotuned layout: the candidates'
-    timing launches, then one restart cycle of 1 step and its residual); and 3
+    batch (FP32 and FP64 matrices, all 1069 columns, the autotuned layouts: the
+    candidates' timing launches, then one restart cycle of 1 step on the FP32
+    tiles and its residuals on the FP64 tiles, once with the vector-unit pass and
+    once with the matrix-core pass); and 3
     plain copies of 1 GiB (FETCH_SIZE / WRITE_SIZE
     calibration)."""
     from paper_2606_13482_amd.inputs import icosphere, complex_gaussian, uneven_batch
@@ -956,11 +958,13 @@ def counters_probe(args, bie, torch):
     for _ in range(5):
         op.apply(Xb, block="fp64")
     probs = uneven_batch()
-    ops = [bie.Operator(p["V"], p["T"], p["k"], storage="c64") for p in probs]
+    ops = [bie.Operator(p["V"], p["T"], p["k"], storage="c64", keep_fp64=True) for p in probs]
     Bs = [o.rhs(p["dirs"], p["pols"]) for o, p in zip(ops, probs)]
-    bie.batch_config(0, False)       # the autotuned layout, cycles launched one by one
+    one = bie.Solve(restart=1, tol=1e-6, max_mvp=2, precision="mixed")
     try:
-        bie.batch_solve(ops, Bs, bie.Solve(restart=1, tol=1e-6, max_mvp=2))
+        for mfma in (False, True):      # the autotuned layout, cycles launched one by one
+            bie.batch_config(0, False, matrix_cores=mfma)
+            bie.batch_solve(ops, Bs, one)
     finally:
         bie.batch_config(0, True)
     a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
