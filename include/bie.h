@@ -327,6 +327,29 @@ int bie_batch_solve_pc(const bie_op *const *ops, const struct bie_calderon *cons
                        const void *const *B, void *const *X, const int64_t *R, const bie_solve_opts *opts,
                        bie_solve_stat *stats, void *stream);
 
+/* The grouped product of the batched solves on its own (Sec. I/II: the O(N^2)
+ * product T x, here for several operators of different sizes at once):
+ * Y_p = T_p X_p for the R[p] columns of every operator p, all in one tile
+ * launch over (operator, unit of tiles, group of columns) work items and one
+ * reduce launch, as inside bie_batch_solve.
+ *   ops    host array of nops assembled dense operators (one device)
+ *   X, Y   host arrays of nops device pointers: R[p] x N_p complex128 each,
+ *          each column contiguous (X read, Y written; distinct buffers)
+ *   R      host array of nops column counts (0 allowed; sum at most 65535)
+ *   mat    0: the FP64 tiles (FP64 accumulation); 1: the FP32 tiles on the
+ *          vector units (FP64 accumulation); 2: the FP32 tiles on the FP32
+ *          matrix cores (vectors rounded to FP32, FP32 accumulation within a
+ *          unit, partial sums and their reduction in FP64)
+ *   unit_tiles     tiles per work unit, 1..64 (0: 8)
+ *   cols_per_item  columns per work item, 1..4096, at most 32 with mat 2
+ *                  (0: 8, or 32 with mat 2)
+ * The columns go through library buffers (allocated per call); the call
+ * returns when Y is written.  BIE_EINVAL for a NULL argument, a star-split or
+ * fast operator, a missing matrix of the requested precision, operators on
+ * several devices or sizes out of range. */
+int bie_batch_apply(const bie_op *const *ops, int64_t nops, const void *const *X, void *const *Y, const int64_t *R,
+                    int mat, int unit_tiles, int cols_per_item, void *stream);
+
 /* Batched solves, for measurement and tests: tiles per work unit of the
  * grouped product (0, the default: tiles per unit in {4, 8, 16} and columns per
  * work item in {4, 8, 16, 32} chosen per batch shape by timing the candidates

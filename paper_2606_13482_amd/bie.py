@@ -112,6 +112,7 @@ SYMBOLS = [
     ("bie_rcs", ctypes.c_int, [_P, _P, _I64, _P, _I64, _P, _P]),
     ("bie_batch_solve", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P]),
     ("bie_batch_solve_pc", ctypes.c_int, [_P, _P, _I64, _P, _P, _P, _P, _P, _P]),
+    ("bie_batch_apply", ctypes.c_int, [_P, _I64, _P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P]),
     ("bie_batch_config", ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     ("bie_batch_tuned", ctypes.c_int, [_P, _I64, _P]),
     ("bie_rscc_rows", ctypes.c_int, [_I64, _I64, ctypes.c_uint64, _P]),
@@ -549,6 +550,28 @@ def batch_solve(ops, Bs, opts: Solve | None = None, x0s=None, x0_fallback: bool 
         out.append([st[k + i].as_dict() for i in range(int(r))])
         k += int(r)
     return Xs, out
+
+
+_BATCH_MAT = {"fp64": 0, "fp32": 1, "fp32_mfma": 2}
+
+
+def batch_apply(ops, Xs, mat: str = "fp64", unit_tiles: int = 0, cols_per_item: int = 0, stream=None):
+    """Y_p = T_p X_p for several operators in one grouped launch
+    (bie_batch_apply).  mat: "fp64" (FP64 tiles), "fp32" (FP32 tiles, vector
+    units) or "fp32_mfma" (FP32 tiles on the matrix cores).  Returns the list of
+    products (R_p x N_p complex128 each)."""
+    if mat not in _BATCH_MAT:
+        raise ValueError(f"mat must be one of {sorted(_BATCH_MAT)}")
+    P = len(ops)
+    Xs = [x.reshape(-1, op.N) for x, op in zip(Xs, ops)]
+    R = np.array([x.shape[0] for x in Xs], np.int64)
+    Ys = [torch.empty_like(x) for x in Xs]
+    oph = (ctypes.c_void_p * P)(*[op._h.value for op in ops])
+    xp = (ctypes.c_void_p * P)(*[_dev(x, torch.complex128).value for x in Xs])
+    yp = (ctypes.c_void_p * P)(*[_dev(y, torch.complex128, x.shape).value for y, x in zip(Ys, Xs)])
+    _check(_lib.bie_batch_apply(oph, P, xp, yp, R.ctypes.data_as(ctypes.c_void_p), _BATCH_MAT[mat], int(unit_tiles),
+                                int(cols_per_item), _stream(stream)))
+    return Ys
 
 
 def batch_config(unit_tiles: int = 0, graph: bool = True, matrix_cores: bool = True):

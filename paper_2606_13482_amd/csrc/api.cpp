@@ -357,6 +357,26 @@ int bie_calderon_get_info(const bie_calderon *pc, bie_calderon_info *info)
 
 void bie_calderon_destroy(bie_calderon *pc) { bie::calderon_destroy(pc); }
 
+int bie_batch_apply(const bie_op *const *ops, int64_t nops, const void *const *X, void *const *Y, const int64_t *R,
+                    int mat, int unit_tiles, int cols_per_item, void *stream)
+{
+    return guarded([&]() -> int {
+        if (!ops || !X || !Y || !R) return fail(BIE_EINVAL, "NULL argument");
+        if (nops < 1 || nops > 4096) return fail(BIE_EINVAL, "nops out of range (1..4096)");
+        int64_t total = 0;
+        for (int64_t p = 0; p < nops; ++p) {
+            if (!ops[p]) return fail(BIE_EINVAL, "NULL operator");
+            if (ops[p]->star || ops[p]->fast) return fail(BIE_EINVAL, "grouped products take assembled dense operators");
+            if (R[p] < 0 || R[p] > 4096) return fail(BIE_EINVAL, "R out of range (0..4096)");
+            if (R[p] > 0 && (!X[p] || !Y[p])) return fail(BIE_EINVAL, "NULL vector pointer");
+            total += R[p];
+        }
+        if (total > 65535) return fail(BIE_EINVAL, "at most 65535 columns per call");
+        bie::batch_apply(ops, nops, X, Y, R, mat, unit_tiles, cols_per_item, as_stream(stream));
+        return BIE_OK;
+    });
+}
+
 int bie_batch_solve_pc(const bie_op *const *ops, const bie_calderon *const *pcs, int64_t nops,
                        const void *const *B, void *const *X, const int64_t *R, const bie_solve_opts *opts,
                        bie_solve_stat *stats, void *stream)

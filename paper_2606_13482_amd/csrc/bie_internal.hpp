@@ -305,6 +305,10 @@ int solve_batch(const bie_op *const *ops, const bie_calderon *const *pcs, int64_
                 void *const *X, const int64_t *R, const bie_solve_opts &o, bie_solve_stat *stats, hipStream_t s);
 void batch_config(int unit, int graph, int mfma);
 int batch_unit_chosen(const bie_op *const *ops, int64_t P, const int64_t *R);
+// grouped product of several operators outside a solve (mat 0: FP64 tiles, 1:
+// FP32 tiles, 2: FP32 tiles on the matrix cores; unit/G 0: defaults)
+void batch_apply(const bie_op *const *ops, int64_t P, const void *const *X, void *const *Y, const int64_t *R,
+                 int mat, int unit, int G, hipStream_t s);
 int solve(const bie_op *op, const void *B, void *X, int64_t R, const bie_solve_opts &o,
           bie_solve_stat *stats, hipStream_t s);
 void free_workspace(bie_op *op);

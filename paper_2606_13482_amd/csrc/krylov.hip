@@ -2455,6 +2455,64 @@ void batch_config(int unit, int graph, int mfma)
     g_batch.mfma = mfma;
 }
 
+// The batched solves' grouped product on its own: Y_p = T_p X_p for the
+// columns of all operators in one tile launch and one reduce launch, through
+// column buffers of the library (inputs copied in, outputs copied out).
+void batch_apply(const bie_op *const *ops, int64_t P, const void *const *X, void *const *Y, const int64_t *R,
+                 int mat, int unit, int G, hipStream_t s)
+{
+    if (mat < 0 || mat > 2)
+        throw Error(BIE_EINVAL, "mat must be 0 (FP64 tiles), 1 (FP32 tiles) or 2 (FP32 tiles on the matrix cores)");
+    const bool m64 = mat == 0, mf = mat == 2;
+    if (unit == 0) unit = 8;
+    if (G == 0) G = mf ? 32 : 8;
+    if (unit < 1 || unit > 64) throw Error(BIE_EINVAL, "tiles per unit must be 1..64");
+    if (G < 1 || G > (mf ? 32 : 4096))
+        throw Error(BIE_EINVAL, mf ? "the matrix-core pass takes 1..32 columns per item" : "columns per item must be 1..4096");
+    std::vector<int32_t> prob;
+    std::vector<int64_t> off;
+    int64_t nw = 0;
+    for (int64_t p = 0; p < P; ++p) {
+        const bie_op *op = ops[p];
+        if (op->device != ops[0]->device) throw Error(BIE_EINVAL, "all operators on one device");
+        if (!(m64 ? op->Z64 : op->Z32))
+            throw Error(BIE_EINVAL, m64 ? "operator " + std::to_string(p) + " holds no FP64 matrix"
+                                        : "operator " + std::to_string(p) + " holds no FP32 matrix");
+        for (int64_t r = 0; r < R[p]; ++r) {
+            prob.push_back(int32_t(p));
+            off.push_back(nw);
+            nw += op->mesh.N;
+        }
+    }
+    const int64_t C = int64_t(prob.size());
+    if (C == 0) return;
+    auto L = make_layout(ops, P, R, unit, G, m64);
+    DevBufs db;
+    double2 *Xw = db.get<double2>(size_t(nw)), *Yw = db.get<double2>(size_t(nw));
+    int32_t *dprob = db.get<int32_t>(size_t(C));
+    int64_t *doff = db.get<int64_t>(size_t(C));
+    BIE_HIP(hipMemcpy(dprob, prob.data(), size_t(C) * sizeof(int32_t), hipMemcpyHostToDevice));
+    BIE_HIP(hipMemcpy(doff, off.data(), size_t(C) * sizeof(int64_t), hipMemcpyHostToDevice));
+    int64_t c = 0;
+    for (int64_t p = 0; p < P; ++p) {
+        if (R[p] == 0) continue;
+        BIE_HIP(hipMemcpyAsync(Xw + off[c], X[p], size_t(R[p]) * ops[p]->mesh.N * sizeof(double2),
+                               hipMemcpyDeviceToDevice, s));
+        c += R[p];
+    }
+    const GCols gc{ dprob, doff, doff, L->gpoff, 0 };
+    grouped_product(m64, L->probs, gc, L->items, L->nitems, L->G, L->ritems, L->nritems, Xw, L->gpart, Yw, nullptr,
+                    nullptr, 1, s, mf);
+    c = 0;
+    for (int64_t p = 0; p < P; ++p) {
+        if (R[p] == 0) continue;
+        BIE_HIP(hipMemcpyAsync(Y[p], Yw + off[c], size_t(R[p]) * ops[p]->mesh.N * sizeof(double2),
+                               hipMemcpyDeviceToDevice, s));
+        c += R[p];
+    }
+    BIE_HIP(hipStreamSynchronize(s));   // the column buffers are freed on return
+}
+
 int batch_unit_chosen(const bie_op *const *ops, int64_t P, const int64_t *R)
 {
     std::vector<int> v;

@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 import torch
 
+from bounds import product_bound
 from oracle import cfill, efie
 from oracle.mesh import flagged_pairs, rwg_table
 from paper_2606_13482_amd.inputs import complex_gaussian, icosphere, planewave_set, random_directions
@@ -253,3 +254,38 @@ def test_pod_at_workload_size(bie):
     assert err <= opt * 1.01
     ws.close()
     op.close()
+
+
+def test_full_size_uneven_batch_products(bie):
+    """The uneven batch at full size (64 surfaces, 648..5832 unknowns, their 1069
+    plane-wave counts as columns): the grouped product of each pass in the
+    batched solves' layout (16 tiles per unit; 8 columns per item on the vector
+    units, 32 on the matrix cores), on sampled rows (first, last and one random
+    row of every surface) against the oracle's rows, element by element within
+    the bound of each pass's arithmetic (tests/bounds.py)."""
+    from paper_2606_13482_amd.inputs import uneven_batch
+    probs = uneven_batch()
+    ops = [bie.Operator(p["V"], p["T"], p["k"], storage="c64", keep_fp64=True) for p in probs]
+    Xs = [torch.from_numpy(complex_gaussian(op.N, 500 + i, cols=len(p["dirs"])).reshape(-1, op.N)).cuda()
+          for i, (op, p) in enumerate(zip(ops, probs))]
+    out = {mat: [y.cpu().numpy() for y in bie.batch_apply(ops, Xs, mat=mat, unit_tiles=16, cols_per_item=cols)]
+           for mat, cols in (("fp64", 8), ("fp32", 8), ("fp32_mfma", 32))}
+    worst = {mat: 0.0 for mat in out}
+    rng = np.random.default_rng(77)
+    for i, (op, p) in enumerate(zip(ops, probs)):
+        rwg = rwg_table(p["V"], p["T"])
+        N = rwg["N"]
+        rows = np.unique([0, int(rng.integers(1, N - 1)), N - 1])
+        Ro = efie.fill_rows(rwg, p["k"], rows, flags=flagged_pairs(rwg, 2.0))       # (S, N)
+        X = Xs[i].cpu().numpy()
+        ref = X @ Ro.T
+        # the bound's S_i and e64 on the sampled rows: |T| restricted to them
+        for mat, Y in out.items():
+            b = product_bound(mat, 16, np.abs(Ro), np.abs(X))
+            e = np.abs(Y[i][:, rows] - ref)
+            worst[mat] = max(worst[mat], float((e / b).max()))
+            assert np.all(e <= b), (i, mat, float((e / b).max()))
+    _say("  uneven batch, 64 surfaces, 1069 columns: worst error / bound " +
+         ", ".join(f"{m} {w:.3f}" for m, w in worst.items()))
+    for op in ops:
+        op.close()
