@@ -150,22 +150,34 @@ __global__ __launch_bounds__(256) void k_sgemm_mf(int M, int N, int K, const flo
 #pragma unroll
     for (int q = 0; q < 16; ++q) acc[q] = 0.f;
     const int nit = (K + 127) / 128;
-    for (int it = 0; it < nit; ++it) {
+    // the wave's 32 x 32 chunks of A and B for one iteration, all 32 loads of a
+    // lane issued together (element e = lane + 64 j: e / 32 across, e % 32
+    // along the stored row); the next iteration's are loaded during the
+    // current one's products
+    float ra[16], rb[16];
+    auto load = [&](int it) {
         const int kc = it * 128 + w * 32;
-#pragma unroll 4
-        for (int e = lane; e < 1024; e += 64) {
-            const int hi = e >> 5, lo = e & 31;   // lo runs along the stored row
-            int mm, kk;
-            float v;
-            if (TA) { kk = hi; mm = lo; v = (m0 + mm < M && kc + kk < K) ? A[int64_t(kc + kk) * lda + m0 + mm] : 0.f; }
-            else { mm = hi; kk = lo; v = (m0 + mm < M && kc + kk < K) ? A[int64_t(m0 + mm) * lda + kc + kk] : 0.f; }
-            As[w][kk][mm] = v;
-            int nn;
-            if (TB) { nn = hi; kk = lo; v = (n0 + nn < N && kc + kk < K) ? Bm[int64_t(n0 + nn) * ldb + kc + kk] : 0.f; }
-            else { kk = hi; nn = lo; v = (n0 + nn < N && kc + kk < K) ? Bm[int64_t(kc + kk) * ldb + n0 + nn] : 0.f; }
-            Bs[w][kk][nn] = v;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int e = lane + 64 * j, hi = e >> 5, lo = e & 31;
+            if (TA) ra[j] = (m0 + lo < M && kc + hi < K) ? A[int64_t(kc + hi) * lda + m0 + lo] : 0.f;
+            else ra[j] = (m0 + hi < M && kc + lo < K) ? A[int64_t(m0 + hi) * lda + kc + lo] : 0.f;
+            if (TB) rb[j] = (n0 + hi < N && kc + lo < K) ? Bm[int64_t(n0 + hi) * ldb + kc + lo] : 0.f;
+            else rb[j] = (n0 + lo < N && kc + hi < K) ? Bm[int64_t(kc + hi) * ldb + n0 + lo] : 0.f;
+        }
+    };
+    load(0);
+    for (int it = 0; it < nit; ++it) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int e = lane + 64 * j, hi = e >> 5, lo = e & 31;
+            if (TA) As[w][hi][lo] = ra[j];
+            else As[w][lo][hi] = ra[j];
+            if (TB) Bs[w][lo][hi] = rb[j];
+            else Bs[w][hi][lo] = rb[j];
         }
         __syncthreads();
+        if (it + 1 < nit) load(it + 1);
         const int i = lane & 31, h = lane >> 5;
 #pragma unroll
         for (int kk = 0; kk < 32; kk += 2)
@@ -213,14 +225,35 @@ __global__ void k_mse(int n, const float *__restrict__ y, const float *__restric
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-// db[o] = sum_b dZ[b][o]
-__global__ void k_colsum(int Bn, int O, const float *__restrict__ dZ, float *__restrict__ db)
+// db[o] = sum_b dZ[b][o]: 64 columns per block of 16 waves, wave v summing the
+// rows b = v, v + 16, ... (all its loads issued together), the 16 partial sums
+// of a column then added in a fixed order
+__global__ __launch_bounds__(1024) void k_colsum(int Bn, int O, const float *__restrict__ dZ, float *__restrict__ db)
 {
-    const int o = blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= O) return;
+    __shared__ float red[16][64];
+    const int lane = threadIdx.x & 63, v = threadIdx.x >> 6;
+    const int o = blockIdx.x * 64 + lane;
     float s = 0.f;
-    for (int b = 0; b < Bn; ++b) s += dZ[b * O + o];
-    db[o] = s;
+    if (o < O) {
+        float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
+        int b = v;
+        for (; b + 48 < Bn; b += 64) {
+            p0 += dZ[int64_t(b) * O + o];
+            p1 += dZ[int64_t(b + 16) * O + o];
+            p2 += dZ[int64_t(b + 32) * O + o];
+            p3 += dZ[int64_t(b + 48) * O + o];
+        }
+        for (; b < Bn; b += 16) p0 += dZ[int64_t(b) * O + o];
+        s = (p0 + p1) + (p2 + p3);
+    }
+    red[v][lane] = s;
+    __syncthreads();
+    if (v == 0 && o < O) {
+        float a = 0.f;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) a += red[u][lane];
+        db[o] = a;
+    }
 }
 
 __global__ void k_adam(int n, float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m,
@@ -540,16 +573,16 @@ int mlp_backward(bie_ws *w, int B, hipStream_t s, bool combine = false)
     }
     // layer 3
     sgemm<true, false>(O, H, B, w->dy, O, w->a2, H, G + w->off[4], H, s);   // dW3 = dy^T a2
-    hipLaunchKernelGGL(k_colsum, dim3((O + 255) / 256), dim3(256), 0, s, B, O, w->dy, G + w->off[5]);
+    hipLaunchKernelGGL(k_colsum, dim3((O + 63) / 64), dim3(1024), 0, s, B, O, w->dy, G + w->off[5]);
     // dZ2 = (dy W3) (1 - a2^2)
     sgemm<false, false>(B, H, O, w->dy, O, P + w->off[4], H, w->d2, H, s, EPI_TANH_BACK, nullptr, w->a2);
     // layer 2
     sgemm<true, false>(H, H, B, w->d2, H, w->a1, H, G + w->off[2], H, s);
-    hipLaunchKernelGGL(k_colsum, dim3((H + 255) / 256), dim3(256), 0, s, B, H, w->d2, G + w->off[3]);
+    hipLaunchKernelGGL(k_colsum, dim3((H + 63) / 64), dim3(1024), 0, s, B, H, w->d2, G + w->off[3]);
     sgemm<false, false>(B, H, H, w->d2, H, P + w->off[2], H, w->d1, H, s, EPI_TANH_BACK, nullptr, w->a1);
     // layer 1
     sgemm<true, false>(H, 4, B, w->d1, H, w->in, 4, G + w->off[0], 4, s);
-    hipLaunchKernelGGL(k_colsum, dim3((H + 255) / 256), dim3(256), 0, s, B, H, w->d1, G + w->off[1]);
+    hipLaunchKernelGGL(k_colsum, dim3((H + 63) / 64), dim3(1024), 0, s, B, H, w->d1, G + w->off[1]);
     BIE_HIP(hipGetLastError());
     return nb;
 }
