@@ -34,6 +34,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <vector>
@@ -399,6 +400,266 @@ __global__ __launch_bounds__(256) void k_bcomb_mf(const CItem *__restrict__ item
             orr = mfma32(-a.y, c.y, orr);
             oi = mfma32(a.x, c.y, oi);
             oi = mfma32(a.y, c.x, oi);
+        }
+    }
+    const int col = lane & 31;
+    if (col >= it.nb) return;
+    double2 *out = static_cast<double2 *>(it.out);
+    const int64_t ob = int64_t(it.ocol ? it.ocol[col] : col) * N;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int64_t n = n0 + 32 * w + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+        if (n < N) {
+            double2 y = make_double2(it.alpha * double(orr[q]), it.alpha * double(oi[q]));
+            if (it.beta != 0.0) y = cadd(y, cscale(it.beta, out[ob + n]));
+            out[ob + n] = y;
+        }
+    }
+}
+
+// BF16 matrix-core forms of the same dots and update: every FP32 operand value
+// v is split into hi = rne_bf16(v) and lo = rne_bf16(v - hi), and each real
+// product is taken as hi*hi + hi*lo + lo*hi (about 16 significant bits, FP32
+// accumulation) with v_mfma_f32_32x32x16_bf16, whose rate is 16 times that of
+// the FP32 matrix-core instruction: the complex64 basis is then read at the
+// memory rate instead of the FP32 matrix cores' rate.  The complex products
+// are real GEMMs with re/im interleaved along K (K' = 2 k + part).
+// Fragment layout of the instruction: A[i][k] is element k % 8 of lane
+// i + 32 (k / 8), B[k][j] element k % 8 of lane j + 32 (k / 8); the output as
+// for the FP32 instruction.  LDS planes hold rows of 64 K' values (one stage,
+// 4 instruction K steps) with a stride of 72 (16-byte fragment reads of 16
+// consecutive rows start in 16 distinct 4-bank groups).
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+constexpr int SPL = 72;
+
+__device__ inline f32x16 mfma_bf(bf16x8 a, bf16x8 b, f32x16 c)
+{
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+__device__ inline void split_bf(float v, __bf16 &hi, __bf16 &lo)
+{
+    hi = (__bf16)v;
+    lo = (__bf16)(v - (float)hi);
+}
+
+// Dots C = V^H W over a chunk of L rows as k_bdots_mf (128 basis vectors per
+// block, one 32 x 32 output tile per wave, up to 32 columns, the same partials):
+// A[v][2 n + p] = (Re, Im) V_v[n], B_re[2 n + p][b] = (Re, Im) W_b[n] (C_re),
+// B_im[2 n + p][b] = (Im, -Re) W_b[n] (C_im); 32 complex rows per stage.
+__global__ __launch_bounds__(256) void k_bdots_bf(const DItem *__restrict__ items, int64_t N, int nchunks, int64_t L,
+                                                  double2 *__restrict__ part)
+{
+    constexpr int MS = 32;
+    const DItem it = items[blockIdx.y];
+    if (it.flag && *it.flag == 0) return;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int64_t n0 = int64_t(blockIdx.x) * L, n1 = min(N, n0 + L);
+    __shared__ __attribute__((aligned(16))) __bf16 Ah[128 * SPL], Al[128 * SPL];
+    __shared__ __attribute__((aligned(16))) __bf16 Bh[2][32 * SPL], Bl[2][32 * SPL];
+    __shared__ int64_t Aoff[128];
+    if (t < 128) {
+        const int k = it.k0 + t;
+        Aoff[t] = t < it.kc ? (int64_t(k / it.ar) * it.astride + k % it.ar) * N : 0;
+    }
+    f32x16 cr, ci;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) cr[q] = ci[q] = 0.f;
+    const float2 *A = static_cast<const float2 *>(it.A);
+    // staging: thread t takes rows 2 (t % 16) and 2 (t % 16) + 1 of basis
+    // vectors t / 16 + 16 u (u < 8), and rows 4 (t % 8) .. + 3 of column t / 8
+    const int ar = 2 * (t & 15), av = t >> 4, bc = t >> 3, br = 4 * (t & 7);
+    float2 ra[16];
+    double2 rb[4];
+    auto gload = [&](int64_t ns) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int v = av + 16 * u;
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int64_t n = ns + ar + e;
+                ra[2 * u + e] = (v < it.kc && n < n1) ? A[Aoff[v] + n] : make_float2(0.f, 0.f);
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t n = ns + br + e;
+            rb[e] = (bc < it.nb && n < n1) ? it.Bm[int64_t(bc) * N + n] : make_double2(0.0, 0.0);
+        }
+    };
+    __syncthreads();   // Aoff
+    if (n0 < n1) gload(n0);
+    for (int64_t ns = n0; ns < n1; ns += MS) {
+        __syncthreads();   // the previous stage's fragment reads are done
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            bf16x4 h, l;
+            const float f[4] = { ra[2 * u].x, ra[2 * u].y, ra[2 * u + 1].x, ra[2 * u + 1].y };
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                __bf16 hh, ll;
+                split_bf(f[e], hh, ll);
+                h[e] = hh;
+                l[e] = ll;
+            }
+            const int o = (av + 16 * u) * SPL + 2 * ar;
+            *reinterpret_cast<bf16x4 *>(&Ah[o]) = h;
+            *reinterpret_cast<bf16x4 *>(&Al[o]) = l;
+        }
+        {
+            bf16x8 rh, rl, ih, il;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                __bf16 hr, lr, hi, li;
+                split_bf(float(rb[e].x), hr, lr);
+                split_bf(float(rb[e].y), hi, li);
+                rh[2 * e] = hr;
+                rh[2 * e + 1] = hi;
+                rl[2 * e] = lr;
+                rl[2 * e + 1] = li;
+                ih[2 * e] = hi;
+                ih[2 * e + 1] = -hr;
+                il[2 * e] = li;
+                il[2 * e + 1] = -lr;
+            }
+            const int o = bc * SPL + 2 * br;
+            *reinterpret_cast<bf16x8 *>(&Bh[0][o]) = rh;
+            *reinterpret_cast<bf16x8 *>(&Bl[0][o]) = rl;
+            *reinterpret_cast<bf16x8 *>(&Bh[1][o]) = ih;
+            *reinterpret_cast<bf16x8 *>(&Bl[1][o]) = il;
+        }
+        __syncthreads();
+        if (ns + MS < n1) gload(ns + MS);
+        const int fa = (32 * w + (lane & 31)) * SPL + 8 * (lane >> 5), fb = (lane & 31) * SPL + 8 * (lane >> 5);
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const bf16x8 ah = *reinterpret_cast<const bf16x8 *>(&Ah[fa + 16 * ks]);
+            const bf16x8 al = *reinterpret_cast<const bf16x8 *>(&Al[fa + 16 * ks]);
+            const bf16x8 brh = *reinterpret_cast<const bf16x8 *>(&Bh[0][fb + 16 * ks]);
+            const bf16x8 brl = *reinterpret_cast<const bf16x8 *>(&Bl[0][fb + 16 * ks]);
+            const bf16x8 bih = *reinterpret_cast<const bf16x8 *>(&Bh[1][fb + 16 * ks]);
+            const bf16x8 bil = *reinterpret_cast<const bf16x8 *>(&Bl[1][fb + 16 * ks]);
+            cr = mfma_bf(ah, brh, cr);
+            ci = mfma_bf(ah, bih, ci);
+            cr = mfma_bf(ah, brl, cr);
+            ci = mfma_bf(ah, bil, ci);
+            cr = mfma_bf(al, brh, cr);
+            ci = mfma_bf(al, bih, ci);
+        }
+    }
+    double2 *o = part + (int64_t(blockIdx.y) * nchunks + blockIdx.x) * 128 * BMAX;
+    const int col = lane & 31;
+    if (col < it.nb) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int v = 32 * w + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+            if (v < it.kc) o[v * BMAX + col] = make_double2(double(cr[q]), double(ci[q]));
+        }
+    }
+}
+
+// Update out_b = beta out_b + alpha (V C)_b as k_bcomb_mf (128 rows per block,
+// one 32 x 32 output tile per wave, 32 basis vectors per stage):
+// A[n][2 k + p] = (Re, Im) V_k[n], B_re[2 k + p][b] = (Re, -Im) C[k][b],
+// B_im[2 k + p][b] = (Im, Re) C[k][b].
+__global__ __launch_bounds__(256) void k_bcomb_bf(const CItem *__restrict__ items, int64_t N)
+{
+    constexpr int KS = 32;
+    const CItem it = items[blockIdx.y];
+    if (it.flag && *it.flag == 0) return;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int64_t n0 = int64_t(blockIdx.x) * 128;
+    __shared__ __attribute__((aligned(16))) __bf16 Ah[128 * SPL], Al[128 * SPL];
+    __shared__ __attribute__((aligned(16))) __bf16 Bh[2][32 * SPL], Bl[2][32 * SPL];
+    __shared__ int64_t Aoff[KS];
+    f32x16 orr, oi;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) orr[q] = oi[q] = 0.f;
+    const float2 *A = static_cast<const float2 *>(it.A);
+    // staging: thread t takes row t % 128 of basis vectors 16 (t / 128) .. + 15,
+    // and coefficients k = 4 (t / 32) .. + 3 of column t % 32
+    const int an = t & 127, ak = 16 * (t >> 7), cb = t & 31, ck = 4 * (t >> 5);
+    float2 ra[16];
+    double2 rc[4];
+    auto offs = [&](int k0) {
+        if (t < KS) {
+            const int k = k0 + t;
+            Aoff[t] = k < it.K ? (int64_t(k / it.ar) * it.astride + k % it.ar) * N : 0;
+        }
+    };
+    auto gload = [&](int k0) {
+        const int64_t nn = n0 + an;
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+            ra[u] = (k0 + ak + u < it.K && nn < N) ? A[Aoff[ak + u] + nn] : make_float2(0.f, 0.f);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = k0 + ck + u;
+            rc[u] = (k < it.K && cb < it.nb) ? it.C[int64_t(k) * it.ldc + cb] : make_double2(0.0, 0.0);
+        }
+    };
+    offs(0);
+    __syncthreads();
+    gload(0);
+    for (int k0 = 0; k0 < it.K; k0 += KS) {
+        __syncthreads();   // previous stage's fragment reads and Aoff reads done
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            bf16x8 h, l;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                __bf16 hr, lr, hi, li;
+                split_bf(ra[4 * g + e].x, hr, lr);
+                split_bf(ra[4 * g + e].y, hi, li);
+                h[2 * e] = hr;
+                h[2 * e + 1] = hi;
+                l[2 * e] = lr;
+                l[2 * e + 1] = li;
+            }
+            const int o = an * SPL + 2 * (ak + 4 * g);
+            *reinterpret_cast<bf16x8 *>(&Ah[o]) = h;
+            *reinterpret_cast<bf16x8 *>(&Al[o]) = l;
+        }
+        {
+            bf16x8 rh, rl, ih, il;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                __bf16 hr, lr, hi, li;
+                split_bf(float(rc[e].x), hr, lr);
+                split_bf(float(rc[e].y), hi, li);
+                rh[2 * e] = hr;
+                rh[2 * e + 1] = -hi;
+                rl[2 * e] = lr;
+                rl[2 * e + 1] = -li;
+                ih[2 * e] = hi;
+                ih[2 * e + 1] = hr;
+                il[2 * e] = li;
+                il[2 * e + 1] = lr;
+            }
+            const int o = cb * SPL + 2 * ck;
+            *reinterpret_cast<bf16x8 *>(&Bh[0][o]) = rh;
+            *reinterpret_cast<bf16x8 *>(&Bl[0][o]) = rl;
+            *reinterpret_cast<bf16x8 *>(&Bh[1][o]) = ih;
+            *reinterpret_cast<bf16x8 *>(&Bl[1][o]) = il;
+        }
+        offs(k0 + KS);
+        __syncthreads();
+        if (k0 + KS < it.K) gload(k0 + KS);
+        const int fa = (32 * w + (lane & 31)) * SPL + 8 * (lane >> 5), fb = (lane & 31) * SPL + 8 * (lane >> 5);
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const bf16x8 ah = *reinterpret_cast<const bf16x8 *>(&Ah[fa + 16 * ks]);
+            const bf16x8 al = *reinterpret_cast<const bf16x8 *>(&Al[fa + 16 * ks]);
+            const bf16x8 brh = *reinterpret_cast<const bf16x8 *>(&Bh[0][fb + 16 * ks]);
+            const bf16x8 brl = *reinterpret_cast<const bf16x8 *>(&Bl[0][fb + 16 * ks]);
+            const bf16x8 bih = *reinterpret_cast<const bf16x8 *>(&Bh[1][fb + 16 * ks]);
+            const bf16x8 bil = *reinterpret_cast<const bf16x8 *>(&Bl[1][fb + 16 * ks]);
+            orr = mfma_bf(ah, brh, orr);
+            oi = mfma_bf(ah, bih, oi);
+            orr = mfma_bf(ah, brl, orr);
+            oi = mfma_bf(ah, bil, oi);
+            orr = mfma_bf(al, brh, orr);
+            oi = mfma_bf(al, bih, oi);
         }
     }
     const int col = lane & 31;
@@ -976,13 +1237,27 @@ void launch_comb(const CItem *d, size_t ni, int64_t N, int nbmax, hipStream_t s)
     BIE_HIP(hipGetLastError());
 }
 
+// the basis kernels' matrix cores: BF16 with three-term splits (default) or
+// FP32 (BIE_BASIS_MFMA=fp32, for comparison)
+bool basis_fp32()
+{
+    static const bool v = [] {
+        const char *e = getenv("BIE_BASIS_MFMA");
+        return e && std::strcmp(e, "fp32") == 0;
+    }();
+    return v;
+}
+
 void launch_dots_mf(const DItem *d, size_t ni, int64_t N, double2 *part, hipStream_t s)
 {
     if (ni == 0) return;
     const int64_t nch = std::max<int64_t>(1, std::min<int64_t>((1024 + int64_t(ni) - 1) / int64_t(ni), (N + 127) / 128));
     const int64_t L = ((N + nch - 1) / nch + 31) / 32 * 32;
     const int nchunks = int((N + L - 1) / L);
-    hipLaunchKernelGGL(k_bdots_mf, dim3(unsigned(nchunks), unsigned(ni)), dim3(256), 0, s, d, N, nchunks, L, part);
+    if (basis_fp32())
+        hipLaunchKernelGGL(k_bdots_mf, dim3(unsigned(nchunks), unsigned(ni)), dim3(256), 0, s, d, N, nchunks, L, part);
+    else
+        hipLaunchKernelGGL(k_bdots_bf, dim3(unsigned(nchunks), unsigned(ni)), dim3(256), 0, s, d, N, nchunks, L, part);
     hipLaunchKernelGGL(k_bdots_fin, dim3(unsigned(ni), unsigned((128 * BMAX) / 64)), dim3(256), 0, s, d, nchunks, 128,
                        (const double2 *)part);
     BIE_HIP(hipGetLastError());
@@ -991,7 +1266,8 @@ void launch_dots_mf(const DItem *d, size_t ni, int64_t N, double2 *part, hipStre
 void launch_comb_mf(const CItem *d, size_t ni, int64_t N, hipStream_t s)
 {
     if (ni == 0) return;
-    hipLaunchKernelGGL(k_bcomb_mf, dim3(unsigned((N + 127) / 128), unsigned(ni)), dim3(256), 0, s, d, N);
+    if (basis_fp32()) hipLaunchKernelGGL(k_bcomb_mf, dim3(unsigned((N + 127) / 128), unsigned(ni)), dim3(256), 0, s, d, N);
+    else hipLaunchKernelGGL(k_bcomb_bf, dim3(unsigned((N + 127) / 128), unsigned(ni)), dim3(256), 0, s, d, N);
     BIE_HIP(hipGetLastError());
 }
 
