@@ -73,6 +73,8 @@ def parse():
                     help="terms of the inner split-BF16 products: 3 (hi/lo matrix x hi/lo vectors) or 2 (hi/lo "
                          "matrix x BF16 vectors)")
     ap.add_argument("--block", type=int, default=32)
+    ap.add_argument("--basis", default="f16", choices=["c64", "f16"],
+                    help="inner Krylov basis of the unpreconditioned mixed block solves (FP16 pairs or complex64)")
     ap.add_argument("--train-dirs", type=int, default=2048)
     ap.add_argument("--test-dirs", type=int, default=512)
     ap.add_argument("--epochs", type=int, default=3000)
@@ -118,12 +120,14 @@ def traffic_from_profiles(fname: str, kernel_src: str, N: int):
         return None
 
 
-def mixed_opts(args, bie, restart, pc=None, inner_tol=None, terms=None):
+def mixed_opts(args, bie, restart, pc=None, inner_tol=None, terms=None, basis=None):
     """Block GMRES over groups of --block right-hand sides on split-BF16 products
-    with FP64 refinement (right-preconditioned by pc when given)."""
+    with FP64 refinement (right-preconditioned by pc when given), inner basis
+    --basis unless given."""
     return bie.Solve(method="bgmres", block=args.block, restart=restart, tol=args.tol, max_mvp=20000,
                      precision="mixed", inner_tol=args.inner_tol if inner_tol is None else inner_tol,
-                     inner_terms=args.inner_terms if terms is None else terms, calderon=pc)
+                     inner_terms=args.inner_terms if terms is None else terms, calderon=pc,
+                     basis=args.basis if basis is None else basis)
 
 
 def planewave_batch(bie, inc):
@@ -444,7 +448,7 @@ def calderon_leg(args, bie, torch, op, ws, batch):
     sync()
     t_setup = time.perf_counter() - t0
     ci = pc.info()
-    copts = mixed_opts(args, bie, args.restart, pc=pc, inner_tol=1e-3, terms=3)
+    copts = mixed_opts(args, bie, args.restart, pc=pc, inner_tol=1e-3, terms=3, basis="c64")
     X0, _ = ws.predict(fte)
     op.solve(B, copts, x0=X0, x0_fallback=True)
     reps = 3
@@ -1085,7 +1089,7 @@ def main():
                                 f"split-BF16 MFMA products with FP64 refinement to {args.tol:g} (FP64 SCC), "
                                 f"unpreconditioned"),
                    "N": N, "k": k, "restart": args.restart, "inner_tol": args.inner_tol, "method": "bgmres",
-                   "block": args.block, "inner_terms": args.inner_terms, "calderon": False,
+                   "block": args.block, "inner_terms": args.inner_terms, "inner_basis": args.basis, "calderon": False,
                    "rhs_per_step": 2 * args.test_dirs, "train_directions": args.train_dirs,
                    "test_directions": args.test_dirs, "pod_rank": K, "hidden": args.hidden, "epochs": args.epochs,
                    "parallelism": "single GPU"},

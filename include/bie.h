@@ -211,10 +211,12 @@ typedef struct {
                             (hi/lo matrix x BF16 vector; the inner tolerance is then
                             raised to at least 1e-2, the rounding of the vectors
                             bounding what the inner solve can attain); 0: default 3 */
-    int basis;           /* precision 1, split-BF16: storage of the inner Krylov basis,
-                            0 complex64 (default) or 1 FP16 pairs (half the traffic of
-                            the Arnoldi kernels; the 3-term split of an FP16 vector into
-                            BF16 hi/lo is exact).  BIE_EINVAL for 1 with another
+    int basis;           /* precision 1, split-BF16: storage of the inner Krylov basis
+                            (column and block GMRES), 0 complex64 (default) or 1 FP16
+                            pairs (half the traffic of the Arnoldi kernels; the 3-term
+                            split of an FP16 vector into BF16 hi/lo is exact; the
+                            basis is orthonormal to about 1e-3, for inner tolerances
+                            of 1e-2 and above).  BIE_EINVAL for 1 with another
                             precision or storage */
     int block;           /* BIE_BGMRES: right-hand sides per block Krylov space
                             (1..32); 0: 32 */

@@ -284,7 +284,6 @@ int bie_solve(const bie_op *op, const void *B, void *X, int64_t R, const bie_sol
             if (o.block < 0 || o.block > 32) return fail(BIE_EINVAL, "block must be 0..32");
             if (o.crit != BIE_SCC) return fail(BIE_EINVAL, "block GMRES decides convergence by the standard criterion");
             if (op->star) return fail(BIE_EINVAL, "block GMRES needs an assembled operator");
-            if (o.basis != 0) return fail(BIE_EINVAL, "block GMRES keeps a complex64 or FP64 basis");
             if (o.precision == 1 && !op->Abf)
                 return fail(BIE_EINVAL, "mixed-precision block GMRES needs split-BF16 storage");
             if (!op->Z64) return fail(BIE_EINVAL, "block GMRES needs the FP64 matrix");

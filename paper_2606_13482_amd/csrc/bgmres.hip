@@ -35,6 +35,7 @@
 #include <cmath>
 #include <complex>
 #include <cstdlib>
+#include <type_traits>
 #include <cstring>
 #include <memory>
 #include <vector>
@@ -55,6 +56,45 @@ template <>
 __device__ inline double2 from_d2<double2>(double2 v) { return v; }
 template <>
 __device__ inline float2 from_d2<float2>(double2 v) { return make_float2(float(v.x), float(v.y)); }
+__device__ inline double2 to_d2(c32h v) { return make_double2(double(v.x), double(v.y)); }
+template <>
+__device__ inline c32h from_d2<c32h>(double2 v) { return c32h{ (_Float16)v.x, (_Float16)v.y }; }
+// Basis entries as loaded (raw) and as two floats: complex64, or an FP16 pair
+// read as one 4-byte vector.  The loads name the global address space: a
+// generic (flat) load also counts against the LDS wait counter, so waiting for
+// the LDS fragment reads would wait for the prefetch of the next stage too.
+typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef double d2v __attribute__((ext_vector_type(2)));
+template <typename V>
+__device__ inline V ld_vec(const void *p, int64_t i)
+{
+    return ((const __attribute__((address_space(1))) V *)p)[i];
+}
+__device__ inline float2 ld_global(const float2 *p, int64_t i)
+{
+    const f2v v = ld_vec<f2v>(p, i);
+    return make_float2(v[0], v[1]);
+}
+__device__ inline double2 ld_global(const double2 *p, int64_t i)
+{
+    const d2v v = ld_vec<d2v>(p, i);
+    return make_double2(v[0], v[1]);
+}
+__device__ inline h2v ld_global(const h2v *p, int64_t i) { return ld_vec<h2v>(p, i); }
+template <typename AT> struct BasisRaw;
+template <> struct BasisRaw<float2> {
+    typedef float2 type;
+    static __device__ inline type load(const void *A, int64_t i) { return ld_global((const float2 *)A, i); }
+    static __device__ inline type zero() { return make_float2(0.f, 0.f); }
+    static __device__ inline float2 f2(type v) { return v; }
+};
+template <> struct BasisRaw<c32h> {
+    typedef h2v type;
+    static __device__ inline type load(const void *A, int64_t i) { return ld_global((const h2v *)A, i); }
+    static __device__ inline type zero() { return h2v{ (_Float16)0.f, (_Float16)0.f }; }
+    static __device__ inline float2 f2(type v) { return make_float2(float(v[0]), float(v[1])); }
+};
 
 __device__ inline double2 cmul(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
 __device__ inline double2 cmulc(double2 a, double2 b)   // conj(a) * b
@@ -447,6 +487,7 @@ __device__ inline void split_bf(float v, __bf16 &hi, __bf16 &lo)
 // block, one 32 x 32 output tile per wave, up to 32 columns, the same partials):
 // A[v][2 n + p] = (Re, Im) V_v[n], B_re[2 n + p][b] = (Re, Im) W_b[n] (C_re),
 // B_im[2 n + p][b] = (Im, -Re) W_b[n] (C_im); 32 complex rows per stage.
+template <typename AT>
 __global__ __launch_bounds__(256) void k_bdots_bf(const DItem *__restrict__ items, int64_t N, int nchunks, int64_t L,
                                                   double2 *__restrict__ part)
 {
@@ -465,12 +506,13 @@ __global__ __launch_bounds__(256) void k_bdots_bf(const DItem *__restrict__ item
     f32x16 cr, ci;
 #pragma unroll
     for (int q = 0; q < 16; ++q) cr[q] = ci[q] = 0.f;
-    const float2 *A = static_cast<const float2 *>(it.A);
+    typedef BasisRaw<AT> BR;
     // staging: thread t takes rows 2 (t % 16) and 2 (t % 16) + 1 of basis
     // vectors t / 16 + 16 u (u < 8), and rows 4 (t % 8) .. + 3 of column t / 8
     const int ar = 2 * (t & 15), av = t >> 4, bc = t >> 3, br = 4 * (t & 7);
-    float2 ra[16];
+    typename BR::type ra[16];   // raw: converted when written to LDS, so the prefetch stays in flight
     double2 rb[4];
+    int64_t ao[8];              // offsets of the thread's 8 basis vectors
     auto gload = [&](int64_t ns) {
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
@@ -478,23 +520,26 @@ __global__ __launch_bounds__(256) void k_bdots_bf(const DItem *__restrict__ item
 #pragma unroll
             for (int e = 0; e < 2; ++e) {
                 const int64_t n = ns + ar + e;
-                ra[2 * u + e] = (v < it.kc && n < n1) ? A[Aoff[v] + n] : make_float2(0.f, 0.f);
+                ra[2 * u + e] = (v < it.kc && n < n1) ? BR::load(it.A, ao[u] + n) : BR::zero();
             }
         }
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int64_t n = ns + br + e;
-            rb[e] = (bc < it.nb && n < n1) ? it.Bm[int64_t(bc) * N + n] : make_double2(0.0, 0.0);
+            rb[e] = (bc < it.nb && n < n1) ? ld_global(it.Bm, int64_t(bc) * N + n) : make_double2(0.0, 0.0);
         }
     };
     __syncthreads();   // Aoff
+#pragma unroll
+    for (int u = 0; u < 8; ++u) ao[u] = Aoff[av + 16 * u];
     if (n0 < n1) gload(n0);
     for (int64_t ns = n0; ns < n1; ns += MS) {
         __syncthreads();   // the previous stage's fragment reads are done
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             bf16x4 h, l;
-            const float f[4] = { ra[2 * u].x, ra[2 * u].y, ra[2 * u + 1].x, ra[2 * u + 1].y };
+            const float2 f0 = BR::f2(ra[2 * u]), f1 = BR::f2(ra[2 * u + 1]);
+            const float f[4] = { f0.x, f0.y, f1.x, f1.y };
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 __bf16 hh, ll;
@@ -562,6 +607,7 @@ __global__ __launch_bounds__(256) void k_bdots_bf(const DItem *__restrict__ item
 // one 32 x 32 output tile per wave, 32 basis vectors per stage):
 // A[n][2 k + p] = (Re, Im) V_k[n], B_re[2 k + p][b] = (Re, -Im) C[k][b],
 // B_im[2 k + p][b] = (Im, Re) C[k][b].
+template <typename AT>
 __global__ __launch_bounds__(256) void k_bcomb_bf(const CItem *__restrict__ items, int64_t N)
 {
     constexpr int KS = 32;
@@ -575,11 +621,11 @@ __global__ __launch_bounds__(256) void k_bcomb_bf(const CItem *__restrict__ item
     f32x16 orr, oi;
 #pragma unroll
     for (int q = 0; q < 16; ++q) orr[q] = oi[q] = 0.f;
-    const float2 *A = static_cast<const float2 *>(it.A);
+    typedef BasisRaw<AT> BR;
     // staging: thread t takes row t % 128 of basis vectors 16 (t / 128) .. + 15,
     // and coefficients k = 4 (t / 32) .. + 3 of column t % 32
     const int an = t & 127, ak = 16 * (t >> 7), cb = t & 31, ck = 4 * (t >> 5);
-    float2 ra[16];
+    typename BR::type ra[16];   // raw: converted when written to LDS
     double2 rc[4];
     auto offs = [&](int k0) {
         if (t < KS) {
@@ -589,13 +635,16 @@ __global__ __launch_bounds__(256) void k_bcomb_bf(const CItem *__restrict__ item
     };
     auto gload = [&](int k0) {
         const int64_t nn = n0 + an;
+        int64_t ao[16];   // the stage's offsets read from LDS first, then all loads issued
+#pragma unroll
+        for (int u = 0; u < 16; ++u) ao[u] = Aoff[ak + u];
 #pragma unroll
         for (int u = 0; u < 16; ++u)
-            ra[u] = (k0 + ak + u < it.K && nn < N) ? A[Aoff[ak + u] + nn] : make_float2(0.f, 0.f);
+            ra[u] = (k0 + ak + u < it.K && nn < N) ? BR::load(it.A, ao[u] + nn) : BR::zero();
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int k = k0 + ck + u;
-            rc[u] = (k < it.K && cb < it.nb) ? it.C[int64_t(k) * it.ldc + cb] : make_double2(0.0, 0.0);
+            rc[u] = (k < it.K && cb < it.nb) ? ld_global(it.C, int64_t(k) * it.ldc + cb) : make_double2(0.0, 0.0);
         }
     };
     offs(0);
@@ -609,8 +658,9 @@ __global__ __launch_bounds__(256) void k_bcomb_bf(const CItem *__restrict__ item
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 __bf16 hr, lr, hi, li;
-                split_bf(ra[4 * g + e].x, hr, lr);
-                split_bf(ra[4 * g + e].y, hi, li);
+                const float2 f = BR::f2(ra[4 * g + e]);
+                split_bf(f.x, hr, lr);
+                split_bf(f.y, hi, li);
                 h[2 * e] = hr;
                 h[2 * e + 1] = hi;
                 l[2 * e] = lr;
@@ -1248,42 +1298,46 @@ bool basis_fp32()
     return v;
 }
 
+template <typename VT>
 void launch_dots_mf(const DItem *d, size_t ni, int64_t N, double2 *part, hipStream_t s)
 {
     if (ni == 0) return;
     const int64_t nch = std::max<int64_t>(1, std::min<int64_t>((1024 + int64_t(ni) - 1) / int64_t(ni), (N + 127) / 128));
     const int64_t L = ((N + nch - 1) / nch + 31) / 32 * 32;
     const int nchunks = int((N + L - 1) / L);
-    if (basis_fp32())
+    if (std::is_same<VT, float2>::value && basis_fp32())
         hipLaunchKernelGGL(k_bdots_mf, dim3(unsigned(nchunks), unsigned(ni)), dim3(256), 0, s, d, N, nchunks, L, part);
     else
-        hipLaunchKernelGGL(k_bdots_bf, dim3(unsigned(nchunks), unsigned(ni)), dim3(256), 0, s, d, N, nchunks, L, part);
+        hipLaunchKernelGGL(k_bdots_bf<VT>, dim3(unsigned(nchunks), unsigned(ni)), dim3(256), 0, s, d, N, nchunks, L,
+                           part);
     hipLaunchKernelGGL(k_bdots_fin, dim3(unsigned(ni), unsigned((128 * BMAX) / 64)), dim3(256), 0, s, d, nchunks, 128,
                        (const double2 *)part);
     BIE_HIP(hipGetLastError());
 }
 
+template <typename VT>
 void launch_comb_mf(const CItem *d, size_t ni, int64_t N, hipStream_t s)
 {
     if (ni == 0) return;
-    if (basis_fp32()) hipLaunchKernelGGL(k_bcomb_mf, dim3(unsigned((N + 127) / 128), unsigned(ni)), dim3(256), 0, s, d, N);
-    else hipLaunchKernelGGL(k_bcomb_bf, dim3(unsigned((N + 127) / 128), unsigned(ni)), dim3(256), 0, s, d, N);
+    if (std::is_same<VT, float2>::value && basis_fp32())
+        hipLaunchKernelGGL(k_bcomb_mf, dim3(unsigned((N + 127) / 128), unsigned(ni)), dim3(256), 0, s, d, N);
+    else hipLaunchKernelGGL(k_bcomb_bf<VT>, dim3(unsigned((N + 127) / 128), unsigned(ni)), dim3(256), 0, s, d, N);
     BIE_HIP(hipGetLastError());
 }
 
-// basis dots and updates: FP32 matrix cores for the complex64 basis, FP64 vector
-// ALUs for the FP64 basis
+// basis dots and updates: matrix cores (BF16 splits) for the complex64 and the
+// FP16-pair bases, FP64 vector ALUs for the FP64 basis
 template <typename VT>
 void basis_dots(const DItem *d, size_t ni, int64_t N, double2 *part, int nbmax, hipStream_t s)
 {
-    if constexpr (sizeof(VT) == 8) launch_dots_mf(d, ni, N, part, s);
-    else launch_dots<VT>(d, ni, N, part, nbmax, s);
+    if constexpr (std::is_same<VT, double2>::value) launch_dots<VT>(d, ni, N, part, nbmax, s);
+    else launch_dots_mf<VT>(d, ni, N, part, s);
 }
 template <typename VT>
 void basis_comb(const CItem *d, size_t ni, int64_t N, int nbmax, hipStream_t s)
 {
-    if constexpr (sizeof(VT) == 8) launch_comb_mf(d, ni, N, s);
-    else launch_comb<VT, double2>(d, ni, N, nbmax, s);
+    if constexpr (std::is_same<VT, double2>::value) launch_comb<VT, double2>(d, ni, N, nbmax, s);
+    else launch_comb_mf<VT>(d, ni, N, s);
 }
 
 // Rank-revealing orthonormalisation of the unit-scaled residual block from its
@@ -1418,6 +1472,13 @@ struct BlockCache {
             if (h.first) (void)hipHostFree(h.first);
     }
 };
+
+// element type of a basis block as the right-hand block of a split-BF16 product
+template <typename VT>
+constexpr int vec_type()
+{
+    return std::is_same<VT, c32h>::value ? VEC_F16 : std::is_same<VT, float2>::value ? VEC_C64 : VEC_C128;
+}
 
 template <typename VT>
 int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_solve_opts &o, bie_solve_stat *hs,
@@ -1764,12 +1825,12 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
                 const VT *Vj = V + int64_t(j) * Wc * N;
                 const int64_t nc = int64_t(cols.size());
                 if (pcd && mixed) {
-                    gemm_product(ptm, Vj, N, VEC_C64, Wb, N, nullptr, 0, nc, dc, s, terms);
+                    gemm_product(ptm, Vj, N, vec_type<VT>(), Wb, N, nullptr, 0, nc, dc, s, terms);
                 } else if (pcd) {
                     gemm64_product(pview, Vj, N, Wt, N, nullptr, 0, nc, dc, s);
                     gemm64_product(op, Wt, N, Wb, N, nullptr, 0, nc, dc, s);
                 } else if (mixed) {
-                    gemm_product(op, Vj, N, VEC_C64, Wb, N, nullptr, 0, nc, dc, s, terms);
+                    gemm_product(op, Vj, N, vec_type<VT>(), Wb, N, nullptr, 0, nc, dc, s, terms);
                 } else {
                     gemm64_product(op, Vj, N, Wb, N, nullptr, 0, nc, dc, s);
                 }
@@ -1889,8 +1950,9 @@ int solve_block(const bie_op *opc, const void *Bv, void *Xv, int64_t R, const bi
     int status = BIE_OK;
     for (int64_t c0 = 0; c0 < R; c0 += W) {
         const int64_t n = std::min(W, R - c0);
-        const int rc = o.precision == 1 ? solve_chunk<float2>(op, B + c0 * N, X + c0 * N, n, o, hs.data() + c0, s)
-                                        : solve_chunk<double2>(op, B + c0 * N, X + c0 * N, n, o, hs.data() + c0, s);
+        const int rc = o.precision != 1 ? solve_chunk<double2>(op, B + c0 * N, X + c0 * N, n, o, hs.data() + c0, s)
+                       : o.basis == 1   ? solve_chunk<c32h>(op, B + c0 * N, X + c0 * N, n, o, hs.data() + c0, s)
+                                        : solve_chunk<float2>(op, B + c0 * N, X + c0 * N, n, o, hs.data() + c0, s);
         if (rc != BIE_OK) status = rc;
     }
     if (stats)

@@ -253,7 +253,7 @@ void split_dense(bie_op *op, const void *A, hipStream_t s);
 // vector element types of the block product's right-hand block
 enum { VEC_C128 = 0, VEC_C64 = 1, VEC_F16 = 2 };
 // complex value as two FP16 (storage of the FP16 Krylov basis)
-struct c32h {
+struct alignas(4) c32h {
     _Float16 x, y;
 };
 void gemm_product(const bie_op *op, const void *X, int64_t ldx, int vtype, void *Y, int64_t ldy, const void *Bsub,

@@ -113,23 +113,29 @@ def test_bgmres_zero_rhs_and_initial_guess(bie):
     assert s2[0]["iters"] < st[0]["iters"]
 
 
-def test_bgmres_mixed_precision(bie):
-    """Mixed precision (split-BF16 products, complex64 basis, FP64 refinement) on
-    1920 unknowns at k = 6 with 32 plane waves: every residual at most 1e-6
-    against the oracle matrix, in fewer products per right-hand side than the
-    column GMRES of the same mixed form."""
+@pytest.mark.parametrize("basis", ["c64", "f16"])
+def test_bgmres_mixed_precision(bie, basis):
+    """Mixed precision (split-BF16 products, complex64 or FP16-pair inner basis,
+    FP64 refinement) on 1920 unknowns at k = 6 with 32 plane waves: every
+    residual at most 1e-6 against the oracle matrix, in fewer products per
+    right-hand side than the column GMRES of the same mixed form; the FP16 basis
+    within a fifth more products than the complex64 one."""
     V, T, rwg, Zo = _case(3, 6.0)
     op = bie.Operator(V, T, 6.0, storage="split_bf16")
     B = _rhs(op, 32, 44)
     X, st = op.solve(B, bie.Solve(method="bgmres", block=16, restart=30, tol=1e-6, precision="mixed",
-                                  inner_tol=0.1))
+                                  inner_tol=0.1, basis=basis))
     Xc, sc = op.solve(B, bie.Solve(restart=30, tol=1e-6, precision="mixed", inner_tol=0.1))
     res = _res(Zo, B, X)
     mb, mc = np.mean([s["mvps"] for s in st]), np.mean([s["mvps"] for s in sc])
-    _say(f"  mixed: block max residual {res.max():.2e}, products per RHS {mb:.0f} (column GMRES {mc:.0f})")
+    _say(f"  mixed, {basis} basis: block max residual {res.max():.2e}, products per RHS {mb:.0f} (column GMRES {mc:.0f})")
     assert all(s["converged"] for s in st)
     assert res.max() <= 1e-6 * (1 + 1e-6)
     assert mb < mc
+    if basis == "f16":
+        _, s64 = op.solve(B, bie.Solve(method="bgmres", block=16, restart=30, tol=1e-6, precision="mixed",
+                                       inner_tol=0.1))
+        assert mb <= 1.2 * np.mean([s["mvps"] for s in s64])
 
 
 def test_bgmres_rejections(bie):
