@@ -354,6 +354,26 @@ __global__ __launch_bounds__(256) void k_sym_tiles_g(const GProb *__restrict__ p
 // accumulation is FP32 within the unit; the partial vectors go to the same
 // FP64 slots as the VALU tile pass's, so the same reduction sums them.
 typedef float f32x16g __attribute__((ext_vector_type(16)));
+// Loads that name the global address space.  Pointers read from the problem
+// table are generic, and a generic (flat) load also counts against the LDS wait
+// counter: the waits for the LDS fragment reads would then wait for the next
+// tile's prefetch as well.
+typedef float gf2v __attribute__((ext_vector_type(2)));
+typedef double gd2v __attribute__((ext_vector_type(2)));
+__device__ inline float2 gload_f2(const float2 *p, int64_t i)
+{
+    const gf2v v = ((const __attribute__((address_space(1))) gf2v *)p)[i];
+    return make_float2(v[0], v[1]);
+}
+__device__ inline double2 gload_d2(const double2 *p, int64_t i)
+{
+    const gd2v v = ((const __attribute__((address_space(1))) gd2v *)p)[i];
+    return make_double2(v[0], v[1]);
+}
+__device__ inline int64_t gload_i64(const int64_t *p, int64_t i)
+{
+    return ((const __attribute__((address_space(1))) int64_t *)p)[i];
+}
 
 __global__ __launch_bounds__(256) void k_sym_tiles_gm(const GProb *__restrict__ probs, GCols gc,
                                                       const int32_t *__restrict__ items, int G,
@@ -390,7 +410,7 @@ __global__ __launch_bounds__(256) void k_sym_tiles_gm(const GProb *__restrict__ 
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int64_t row = int64_t(blk) * TB + sr + 8 * q;
-            xv[q] = (slive && row < P.N) ? Xc[sxo + row] : make_double2(0.0, 0.0);
+            xv[q] = (slive && row < P.N) ? gload_d2(Xc, sxo + row) : make_double2(0.0, 0.0);
         }
     };
     auto put_x = [&](float2 (*dst)[32], const double2 (&xv)[8]) {
@@ -400,7 +420,7 @@ __global__ __launch_bounds__(256) void k_sym_tiles_gm(const GProb *__restrict__ 
     auto load_z = [&](float2 (&zv)[16], int32_t J) {
         const float2 *tile = Z + tile_of(I, J, P.nT) * TB * TB + t;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) zv[q] = tile[256 * q];
+        for (int q = 0; q < 16; ++q) zv[q] = gload_f2(tile, 256 * q);
     };
     auto put_z = [&](const float2 (&zv)[16]) {
 #pragma unroll
@@ -458,10 +478,10 @@ __global__ __launch_bounds__(256) void k_sym_tiles_gm(const GProb *__restrict__ 
 #pragma unroll
             for (int q = 0; q < 16; ++q) acol[q] = 0.f;
             acol = chain(acol, true, sXI);
-            store(acol, P.seg[J] + I);
+            store(acol, gload_i64(P.seg, J) + I);
         }
     }
-    store(arow, P.seg[I] + I + uo);
+    store(arow, gload_i64(P.seg, I) + I + uo);
 }
 
 // y_I = sum of the partial vectors of row block I (column sums of tiles
