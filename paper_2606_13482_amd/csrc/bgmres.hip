@@ -82,16 +82,33 @@ __device__ inline double2 ld_global(const double2 *p, int64_t i)
     return make_double2(v[0], v[1]);
 }
 __device__ inline h2v ld_global(const h2v *p, int64_t i) { return ld_vec<h2v>(p, i); }
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef _Float16 h8v __attribute__((ext_vector_type(8)));
+// load16: the P16 entries i .. i + P16 - 1 (i a multiple of P16, 16-byte aligned) in one load
 template <typename AT> struct BasisRaw;
 template <> struct BasisRaw<float2> {
     typedef float2 type;
+    static constexpr int P16 = 2;
     static __device__ inline type load(const void *A, int64_t i) { return ld_global((const float2 *)A, i); }
+    static __device__ inline void load16(const void *A, int64_t i, type *o)
+    {
+        const f4v v = ld_vec<f4v>(A, i >> 1);
+        o[0] = make_float2(v[0], v[1]);
+        o[1] = make_float2(v[2], v[3]);
+    }
     static __device__ inline type zero() { return make_float2(0.f, 0.f); }
     static __device__ inline float2 f2(type v) { return v; }
 };
 template <> struct BasisRaw<c32h> {
     typedef h2v type;
+    static constexpr int P16 = 4;
     static __device__ inline type load(const void *A, int64_t i) { return ld_global((const h2v *)A, i); }
+    static __device__ inline void load16(const void *A, int64_t i, type *o)
+    {
+        const h8v v = ld_vec<h8v>(A, i >> 2);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) o[j] = h2v{ v[2 * j], v[2 * j + 1] };
+    }
     static __device__ inline type zero() { return h2v{ (_Float16)0.f, (_Float16)0.f }; }
     static __device__ inline float2 f2(type v) { return make_float2(float(v[0]), float(v[1])); }
 };
@@ -727,6 +744,247 @@ __global__ __launch_bounds__(256) void k_bcomb_bf(const CItem *__restrict__ item
     }
 }
 
+// The same dots with the basis read straight into the matrix-core operands
+// (no LDS for it): the order of the real K values is permuted (any order
+// serves, as long as both operands take the same one) so that in a stage of 32
+// rows lane l of a wave holds rows 16 (l / 32) .. + 15 of its basis vector, read
+// as 16-byte loads, and instruction K step ks takes its rows 4 ks .. 4 ks + 3.
+// The columns W stay in LDS in natural order (K' = 2 row + part), where the
+// fragment of (ks, l / 32) is the 8 values at 32 (l / 32) + 8 ks.  Needs
+// N % 4 == 0 (16-byte alignment of every lane's rows).
+template <typename AT>
+__global__ __launch_bounds__(256) void k_bdots_bd(const DItem *__restrict__ items, int64_t N, int nchunks, int64_t L,
+                                                  double2 *__restrict__ part)
+{
+    constexpr int MS = 32;
+    typedef BasisRaw<AT> BR;
+    const DItem it = items[blockIdx.y];
+    if (it.flag && *it.flag == 0) return;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, h = lane >> 5;
+    const int64_t n0 = int64_t(blockIdx.x) * L, n1 = min(N, n0 + L);
+    __shared__ __attribute__((aligned(16))) __bf16 Bh[2][32 * SPL], Bl[2][32 * SPL];
+    const int v = 32 * w + (lane & 31);
+    const bool vlive = v < it.kc;
+    const int64_t aoff = vlive ? (int64_t((it.k0 + v) / it.ar) * it.astride + (it.k0 + v) % it.ar) * N : 0;
+    f32x16 cr, ci;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) cr[q] = ci[q] = 0.f;
+    // column staging: rows 4 (t % 8) .. + 3 of column t / 8
+    const int bc = t >> 3, br = 4 * (t & 7);
+    typename BR::type ra[16];   // the lane's 16 rows, raw
+    double2 rb[4];
+    auto gload = [&](int64_t ns) {
+        const int64_t r0 = ns + 16 * h;
+        if (ns + MS <= n1) {
+#pragma unroll
+            for (int c = 0; c < 16 / BR::P16; ++c) {
+                if (vlive) BR::load16(it.A, aoff + r0 + BR::P16 * c, &ra[BR::P16 * c]);
+                else
+#pragma unroll
+                    for (int j = 0; j < BR::P16; ++j) ra[BR::P16 * c + j] = BR::zero();
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) ra[e] = (vlive && r0 + e < n1) ? BR::load(it.A, aoff + r0 + e) : BR::zero();
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t n = ns + br + e;
+            rb[e] = (bc < it.nb && n < n1) ? ld_global(it.Bm, int64_t(bc) * N + n) : make_double2(0.0, 0.0);
+        }
+    };
+    if (n0 < n1) gload(n0);
+    for (int64_t ns = n0; ns < n1; ns += MS) {
+        __syncthreads();   // the previous stage's fragment reads are done
+        {
+            bf16x8 rh, rl, ih, il;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                __bf16 hr, lr, hi, li;
+                split_bf(float(rb[e].x), hr, lr);
+                split_bf(float(rb[e].y), hi, li);
+                rh[2 * e] = hr;
+                rh[2 * e + 1] = hi;
+                rl[2 * e] = lr;
+                rl[2 * e + 1] = li;
+                ih[2 * e] = hi;
+                ih[2 * e + 1] = -hr;
+                il[2 * e] = li;
+                il[2 * e + 1] = -lr;
+            }
+            const int o = bc * SPL + 2 * br;
+            *reinterpret_cast<bf16x8 *>(&Bh[0][o]) = rh;
+            *reinterpret_cast<bf16x8 *>(&Bl[0][o]) = rl;
+            *reinterpret_cast<bf16x8 *>(&Bh[1][o]) = ih;
+            *reinterpret_cast<bf16x8 *>(&Bl[1][o]) = il;
+        }
+        // the lane's basis fragments of the 4 K steps, split into BF16 hi / lo
+        bf16x8 fh[4], fl[4];
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float2 f = BR::f2(ra[4 * ks + e]);
+                __bf16 a, b, c, d;
+                split_bf(f.x, a, b);
+                split_bf(f.y, c, d);
+                fh[ks][2 * e] = a;
+                fl[ks][2 * e] = b;
+                fh[ks][2 * e + 1] = c;
+                fl[ks][2 * e + 1] = d;
+            }
+        __syncthreads();
+        if (ns + MS < n1) gload(ns + MS);
+        const int fb = (lane & 31) * SPL + 32 * h;
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const bf16x8 brh = *reinterpret_cast<const bf16x8 *>(&Bh[0][fb + 8 * ks]);
+            const bf16x8 brl = *reinterpret_cast<const bf16x8 *>(&Bl[0][fb + 8 * ks]);
+            const bf16x8 bih = *reinterpret_cast<const bf16x8 *>(&Bh[1][fb + 8 * ks]);
+            const bf16x8 bil = *reinterpret_cast<const bf16x8 *>(&Bl[1][fb + 8 * ks]);
+            cr = mfma_bf(fh[ks], brh, cr);
+            ci = mfma_bf(fh[ks], bih, ci);
+            cr = mfma_bf(fh[ks], brl, cr);
+            ci = mfma_bf(fh[ks], bil, ci);
+            cr = mfma_bf(fl[ks], brh, cr);
+            ci = mfma_bf(fl[ks], bih, ci);
+        }
+    }
+    double2 *o = part + (int64_t(blockIdx.y) * nchunks + blockIdx.x) * 128 * BMAX;
+    const int col = lane & 31;
+    if (col < it.nb) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int vv = 32 * w + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+            if (vv < it.kc) o[vv * BMAX + col] = make_double2(double(cr[q]), double(ci[q]));
+        }
+    }
+}
+
+// The update with the basis read straight into the matrix-core operands: the
+// transposed product out^T = C^T V^T, whose right operand is V (column n of a
+// wave's 32 rows, K' = 2 k + part along the basis index k), so that lane l reads
+// entry n of 4 basis vectors per instruction K step (the lanes of a half-wave:
+// 32 consecutive entries of one vector), and whose left operand C^T (the
+// coefficients, as the planes of k_bcomb_bf) comes from LDS.  Output value q of
+// lane l: column b = 8 (q / 4) + 4 (l / 32) + q % 4, row n = l % 32 of the wave.
+template <typename AT>
+__global__ __launch_bounds__(256) void k_bcomb_bd(const CItem *__restrict__ items, int64_t N)
+{
+    constexpr int KS = 32;
+    typedef BasisRaw<AT> BR;
+    const CItem it = items[blockIdx.y];
+    if (it.flag && *it.flag == 0) return;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, h = lane >> 5;
+    const int64_t nn = int64_t(blockIdx.x) * 128 + 32 * w + (lane & 31);
+    const bool nlive = nn < N;
+    __shared__ __attribute__((aligned(16))) __bf16 Ch[2][32 * SPL], Cl[2][32 * SPL];
+    __shared__ int64_t Aoff[KS];
+    f32x16 orr, oi;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) orr[q] = oi[q] = 0.f;
+    // coefficient staging: k = 4 (t / 32) .. + 3 of column t % 32
+    const int cb = t & 31, ck = 4 * (t >> 5);
+    typename BR::type ra[16];   // entry nn of basis vectors 8 ks + 4 h + j (ks, j < 4), raw
+    double2 rc[4];
+    auto offs = [&](int k0) {
+        if (t < KS) {
+            const int k = k0 + t;
+            Aoff[t] = k < it.K ? (int64_t(k / it.ar) * it.astride + k % it.ar) * N : 0;
+        }
+    };
+    auto gload = [&](int k0) {
+        int64_t ao[16];
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) ao[4 * ks + j] = Aoff[8 * ks + 4 * h + j];
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int k = k0 + 8 * ks + 4 * h + j;
+                ra[4 * ks + j] = (k < it.K && nlive) ? BR::load(it.A, ao[4 * ks + j] + nn) : BR::zero();
+            }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = k0 + ck + u;
+            rc[u] = (k < it.K && cb < it.nb) ? ld_global(it.C, int64_t(k) * it.ldc + cb) : make_double2(0.0, 0.0);
+        }
+    };
+    offs(0);
+    __syncthreads();
+    gload(0);
+    for (int k0 = 0; k0 < it.K; k0 += KS) {
+        __syncthreads();   // previous stage's fragment reads and Aoff reads done
+        {
+            bf16x8 rh, rl, ih, il;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                __bf16 hr, lr, hi, li;
+                split_bf(float(rc[e].x), hr, lr);
+                split_bf(float(rc[e].y), hi, li);
+                rh[2 * e] = hr;
+                rh[2 * e + 1] = -hi;
+                rl[2 * e] = lr;
+                rl[2 * e + 1] = -li;
+                ih[2 * e] = hi;
+                ih[2 * e + 1] = hr;
+                il[2 * e] = li;
+                il[2 * e + 1] = lr;
+            }
+            const int o = cb * SPL + 2 * ck;
+            *reinterpret_cast<bf16x8 *>(&Ch[0][o]) = rh;
+            *reinterpret_cast<bf16x8 *>(&Cl[0][o]) = rl;
+            *reinterpret_cast<bf16x8 *>(&Ch[1][o]) = ih;
+            *reinterpret_cast<bf16x8 *>(&Cl[1][o]) = il;
+        }
+        bf16x8 fh[4], fl[4];
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float2 f = BR::f2(ra[4 * ks + j]);
+                __bf16 a, b, c, d;
+                split_bf(f.x, a, b);
+                split_bf(f.y, c, d);
+                fh[ks][2 * j] = a;
+                fl[ks][2 * j] = b;
+                fh[ks][2 * j + 1] = c;
+                fl[ks][2 * j + 1] = d;
+            }
+        offs(k0 + KS);
+        __syncthreads();
+        if (k0 + KS < it.K) gload(k0 + KS);
+        const int fa = (lane & 31) * SPL + 8 * h;
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const bf16x8 arh = *reinterpret_cast<const bf16x8 *>(&Ch[0][fa + 16 * ks]);
+            const bf16x8 arl = *reinterpret_cast<const bf16x8 *>(&Cl[0][fa + 16 * ks]);
+            const bf16x8 aih = *reinterpret_cast<const bf16x8 *>(&Ch[1][fa + 16 * ks]);
+            const bf16x8 ail = *reinterpret_cast<const bf16x8 *>(&Cl[1][fa + 16 * ks]);
+            orr = mfma_bf(arh, fh[ks], orr);
+            oi = mfma_bf(aih, fh[ks], oi);
+            orr = mfma_bf(arh, fl[ks], orr);
+            oi = mfma_bf(aih, fl[ks], oi);
+            orr = mfma_bf(arl, fh[ks], orr);
+            oi = mfma_bf(ail, fh[ks], oi);
+        }
+    }
+    if (!nlive) return;
+    double2 *out = static_cast<double2 *>(it.out);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int b = 8 * (q >> 2) + 4 * h + (q & 3);
+        if (b < it.nb) {
+            const int64_t ob = int64_t(it.ocol ? it.ocol[b] : b) * N;
+            double2 y = make_double2(it.alpha * double(orr[q]), it.alpha * double(oi[q]));
+            if (it.beta != 0.0) y = cadd(y, cscale(it.beta, out[ob + nn]));
+            out[ob + nn] = y;
+        }
+    }
+}
+
 // dst[i * N + n] = src[cols[i] * N + n]
 __global__ __launch_bounds__(256) void k_bgather(int64_t N, const double2 *__restrict__ src, const int *__restrict__ cols,
                                                  double2 *__restrict__ dst)
@@ -1277,7 +1535,7 @@ template <typename AT, typename OT>
 void launch_comb(const CItem *d, size_t ni, int64_t N, int nbmax, hipStream_t s)
 {
     if (ni == 0) return;
-    const dim3 grid(unsigned((N + 127) / 128), unsigned(ni));
+    const dim3 grid{ unsigned((N + 127) / 128), unsigned(ni) };
     switch (pick_nb(nbmax)) {
     case 4: hipLaunchKernelGGL((k_bcomb<AT, OT, 4>), grid, dim3(256), 0, s, d, N); break;
     case 8: hipLaunchKernelGGL((k_bcomb<AT, OT, 8>), grid, dim3(256), 0, s, d, N); break;
@@ -1287,13 +1545,18 @@ void launch_comb(const CItem *d, size_t ni, int64_t N, int nbmax, hipStream_t s)
     BIE_HIP(hipGetLastError());
 }
 
-// the basis kernels' matrix cores: BF16 with three-term splits (default) or
-// FP32 (BIE_BASIS_MFMA=fp32, for comparison)
-bool basis_fp32()
+// the basis kernels: BF16 three-term splits with the basis read straight into
+// the operands (default), the same with the basis staged in LDS
+// (BIE_BASIS_MFMA=lds, and the dots whenever N % 4 != 0), or the FP32 matrix
+// cores (BIE_BASIS_MFMA=fp32, complex64 basis); the choices for comparison
+enum { BASIS_DIRECT = 0, BASIS_LDS = 1, BASIS_FP32 = 2 };
+int basis_mode()
 {
-    static const bool v = [] {
+    static const int v = [] {
         const char *e = getenv("BIE_BASIS_MFMA");
-        return e && std::strcmp(e, "fp32") == 0;
+        if (e && std::strcmp(e, "fp32") == 0) return int(BASIS_FP32);
+        if (e && std::strcmp(e, "lds") == 0) return int(BASIS_LDS);
+        return int(BASIS_DIRECT);
     }();
     return v;
 }
@@ -1305,11 +1568,12 @@ void launch_dots_mf(const DItem *d, size_t ni, int64_t N, double2 *part, hipStre
     const int64_t nch = std::max<int64_t>(1, std::min<int64_t>((1024 + int64_t(ni) - 1) / int64_t(ni), (N + 127) / 128));
     const int64_t L = ((N + nch - 1) / nch + 31) / 32 * 32;
     const int nchunks = int((N + L - 1) / L);
-    if (std::is_same<VT, float2>::value && basis_fp32())
-        hipLaunchKernelGGL(k_bdots_mf, dim3(unsigned(nchunks), unsigned(ni)), dim3(256), 0, s, d, N, nchunks, L, part);
-    else
-        hipLaunchKernelGGL(k_bdots_bf<VT>, dim3(unsigned(nchunks), unsigned(ni)), dim3(256), 0, s, d, N, nchunks, L,
-                           part);
+    const dim3 grid{ unsigned(nchunks), unsigned(ni) };
+    if (std::is_same<VT, float2>::value && basis_mode() == BASIS_FP32)
+        hipLaunchKernelGGL(k_bdots_mf, grid, dim3(256), 0, s, d, N, nchunks, L, part);
+    else if (basis_mode() == BASIS_DIRECT && N % 4 == 0)
+        hipLaunchKernelGGL(k_bdots_bd<VT>, grid, dim3(256), 0, s, d, N, nchunks, L, part);
+    else hipLaunchKernelGGL(k_bdots_bf<VT>, grid, dim3(256), 0, s, d, N, nchunks, L, part);
     hipLaunchKernelGGL(k_bdots_fin, dim3(unsigned(ni), unsigned((128 * BMAX) / 64)), dim3(256), 0, s, d, nchunks, 128,
                        (const double2 *)part);
     BIE_HIP(hipGetLastError());
@@ -1319,9 +1583,11 @@ template <typename VT>
 void launch_comb_mf(const CItem *d, size_t ni, int64_t N, hipStream_t s)
 {
     if (ni == 0) return;
-    if (std::is_same<VT, float2>::value && basis_fp32())
-        hipLaunchKernelGGL(k_bcomb_mf, dim3(unsigned((N + 127) / 128), unsigned(ni)), dim3(256), 0, s, d, N);
-    else hipLaunchKernelGGL(k_bcomb_bf<VT>, dim3(unsigned((N + 127) / 128), unsigned(ni)), dim3(256), 0, s, d, N);
+    const dim3 grid{ unsigned((N + 127) / 128), unsigned(ni) };
+    if (std::is_same<VT, float2>::value && basis_mode() == BASIS_FP32)
+        hipLaunchKernelGGL(k_bcomb_mf, grid, dim3(256), 0, s, d, N);
+    else if (basis_mode() == BASIS_DIRECT) hipLaunchKernelGGL(k_bcomb_bd<VT>, grid, dim3(256), 0, s, d, N);
+    else hipLaunchKernelGGL(k_bcomb_bf<VT>, grid, dim3(256), 0, s, d, N);
     BIE_HIP(hipGetLastError());
 }
 
