@@ -1086,8 +1086,8 @@ def main():
                                 f"({args.epochs} epochs); each step serves {2 * args.test_dirs} held-out plane waves "
                                 f"({args.test_dirs} directions x theta/phi) with operator and warm start resident: "
                                 f"block GMRES({args.restart}) over groups of {args.block} on {args.inner_terms}-term "
-                                f"split-BF16 MFMA products with FP64 refinement to {args.tol:g} (FP64 SCC), "
-                                f"unpreconditioned"),
+                                f"split-BF16 MFMA products, {'FP16-pair' if args.basis == 'f16' else 'complex64'} "
+                                f"inner basis, FP64 refinement to {args.tol:g} (FP64 SCC), unpreconditioned"),
                    "N": N, "k": k, "restart": args.restart, "inner_tol": args.inner_tol, "method": "bgmres",
                    "block": args.block, "inner_terms": args.inner_terms, "inner_basis": args.basis, "calderon": False,
                    "rhs_per_step": 2 * args.test_dirs, "train_directions": args.train_dirs,
