@@ -219,11 +219,12 @@ def plain_leg(args, bie, torch, V, T, k):
     return out, roof
 
 
-def block_rooflines(bie, N, terms, t_ms, g, f, orth):
+def block_rooflines(bie, N, terms, t_ms, g, f, orth, basis_bytes):
     """Rooflines of the block-solver kernels from the live HIP-event records:
     the split-BF16 product (BF16 peak, algorithmic flops), the FP64 product of
     the refinement residuals (FP64 matrix peak) and the two block-GMRES
-    orthogonalisation kernels (FP32 matrix peak); sorted by total time."""
+    orthogonalisation kernels (HBM: the basis they read, basis_bytes per entry;
+    their 3-term BF16 matrix-core rate beside it); sorted by total time."""
     cands = []
     g_launch, g_ms, g_cols = g
     if g_launch:
@@ -257,20 +258,29 @@ def block_rooflines(bie, N, terms, t_ms, g, f, orth):
                              "alg_flops_per_launch": alg, "avg_columns_per_launch": round(f_cols / f_launch, 1),
                              "avg_launch_us": round(avg * 1e3, 2), "launches": f_launch,
                              "share_of_step": round(f_ms / t_ms, 3)}))
-    names = {4: "block GMRES basis dots V^H W (k_bdots_mf + k_bdots_fin, v_mfma_f32_32x32x2f32)",
-             5: "block GMRES basis update W -= V C (k_bcomb_mf, v_mfma_f32_32x32x2f32)"}
-    for kk, (n_l, ms, pairs) in orth.items():
-        if n_l == 0:
-            continue
-        avg = ms / n_l
-        alg = 8.0 * N * pairs / n_l
-        ach = alg / (avg * 1e-3) / 1e12
-        cands.append((ms, {"bound": "mfma", "achieved": round(ach, 2), "peak": FP32_MFMA_PEAK_TFLOPS,
-                           "unit": "TFLOP/s", "frac": round(ach / FP32_MFMA_PEAK_TFLOPS, 4), "traffic": None,
-                           "traffic_note": "no counter summary for this kernel",
-                           "kernel": names[kk], "alg_flops_per_launch": alg,
-                           "avg_launch_us": round(avg * 1e3, 2), "launches": n_l,
-                           "share_of_step": round(ms / t_ms, 3)}))
+    names = {4: "block GMRES basis dots V^H W (k_bdots_bd + k_bdots_fin, v_mfma_f32_32x32x16_bf16, 3-term splits)",
+             5: "block GMRES basis update W -= V C (k_bcomb_bd, v_mfma_f32_32x32x16_bf16, 3-term splits)"}
+    n4, _, pairs = orth.get(4, (0, 0.0, 0))
+    n5, _, vecs = orth.get(5, (0, 0.0, 0))
+    if n4 and n5:
+        # both kernels of a step read the same basis vectors: sum of K over the groups
+        bytes_l = float(vecs) / n5 * N * basis_bytes
+        flops_l = 8.0 * N * pairs / n4
+        for kk in (4, 5):
+            n_l, ms, _ = orth[kk]
+            avg = ms / n_l
+            ach = bytes_l / (avg * 1e-3) / 1e9
+            fr = flops_l / (avg * 1e-3) / 1e12
+            cands.append((ms, {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                               "traffic_note": "no counter summary for this kernel",
+                               "kernel": names[kk], "alg_bytes_per_launch": round(bytes_l),
+                               "alg_bytes_note": "the basis entries read (sum of K N entries); the columns W add "
+                                                 "16 B per row and column",
+                               "alg_flops_per_launch": flops_l, "alg_tflops": round(fr, 2),
+                               "issued_frac_bf16": round(3 * fr / BF16_PEAK_TFLOPS, 4),
+                               "avg_launch_us": round(avg * 1e3, 2), "launches": n_l,
+                               "share_of_step": round(ms / t_ms, 3)}))
     cands.sort(key=lambda c: -c[0])
     return [c[1] for c in cands]
 
@@ -429,7 +439,7 @@ def headline_leg(args, bie, torch, V, T, k):
                                 "reference": "direct LU (torch.linalg.solve, FP64) of the operator's FP64 matrix on "
                                              "the sample", "kappa1": kappa1},
     })
-    kr = block_rooflines(bie, N, args.inner_terms, t_steps * 1e3, g, f, orth)
+    kr = block_rooflines(bie, N, args.inner_terms, t_steps * 1e3, g, f, orth, 4 if args.basis == "f16" else 8)
     res["kernel_rooflines"] = kr
     plain_mvps = float(np.mean([b for _, b, _ in itp]))
     return op, ws, res, kr[0], ms_step, plain_mvps, (B, fte, idx, popts)
@@ -543,10 +553,11 @@ def c3_leg(args, bie, torch):
     op.close()
     its = np.concatenate(its)
     value = n_conv / t_steps
-    kr = block_rooflines(bie, N, 2, t_steps * 1e3, g, f, orth)
+    kr = block_rooflines(bie, N, 2, t_steps * 1e3, g, f, orth, 4 if args.basis == "f16" else 8)
     return {"workload": (f"PEC sphere r=1 m, icosphere {T.shape[0]} triangles ({N} RWG), k={k:g}; {R} plane waves "
                          f"(16x16 theta/phi grid x theta/phi) per step, operator resident; block GMRES(30) over groups "
-                         f"of {args.block} on 2-term split-BF16 MFMA products with FP64 refinement to {args.tol:g} "
+                         f"of {args.block} on 2-term split-BF16 MFMA products, "
+                         f"{'FP16-pair' if args.basis == 'f16' else 'complex64'} inner basis, FP64 refinement to {args.tol:g} "
                          f"(FP64 SCC)"),
             "steps": steps, "warmup": 1, "ms_per_step": round(1e3 * t_steps / steps, 3),
             "solves_per_s": round(value, 3), "fill_and_split_s": round(t_fill, 3), "converged": n_conv / (steps * R),

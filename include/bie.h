@@ -634,8 +634,9 @@ int64_t bie_autotune_report(char *buf, int64_t cap);
  * BIE_EINVAL otherwise) and returns the number of launches, their summed duration in
  * ms and (columns, may be NULL) the summed number of right-hand sides of those
  * launches (the packed product counts every column of its grid, skipped ones
- * included; records 4 and 5 count basis vector x column pairs, sum of K r over
- * the groups) since the previous read, then clears that record. */
+ * included; record 4 counts basis vector x column pairs, sum of K r over the
+ * groups, record 5 the basis vectors read, sum of K) since the previous read,
+ * then clears that record. */
 int bie_prof_enable(int on);
 int bie_prof_read(int kernel, int64_t *launches, double *total_ms, int64_t *columns);
 

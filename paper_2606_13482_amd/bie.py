@@ -206,7 +206,7 @@ def prof_read(kernel: int = 0, columns: bool = False):
     (0: packed symmetric product, 1: split-BF16 block product, 2: FP64 block
     product, 3: reduction of the packed product, 4: block GMRES basis dots, 5:
     block GMRES basis update); columns = summed right-hand sides of those launches
-    (4, 5: basis vector x column pairs)."""
+    (4: basis vector x column pairs; 5: basis vectors read)."""
     n = ctypes.c_int64(); ms = ctypes.c_double(); c = ctypes.c_int64()
     _check(_lib.bie_prof_read(int(kernel), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(c)))
     return (n.value, ms.value, c.value) if columns else (n.value, ms.value)

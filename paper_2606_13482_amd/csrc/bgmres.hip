@@ -2101,13 +2101,16 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
                     gemm64_product(op, Vj, N, Wb, N, nullptr, 0, nc, dc, s);
                 }
                 launch_ls();
-                int64_t pairs = 0;   // basis vector x column pairs of the first pass
-                for (int g : act) pairs += int64_t(j + 1) * grp[g].r * grp[g].r;
+                int64_t pairs = 0, vecs = 0;   // basis vector x column pairs, basis vectors of the first pass
+                for (int g : act) {
+                    pairs += int64_t(j + 1) * grp[g].r * grp[g].r;
+                    vecs += int64_t(j + 1) * grp[g].r;
+                }
                 prof_begin(4, s, pairs);
                 basis_dots<VT>(pv0, dv[0].size(), N, part, p, s);
                 prof_end(4, s);
                 if (reorth > 0.0) launch_dots<double2, 1>(ppre, dpre.size(), N, part, p, s);   // G1 for the second-pass test
-                prof_begin(5, s, pairs);
+                prof_begin(5, s, vecs);
                 basis_comb<VT>(pc0, ci[0].size(), N, p, s);
                 prof_end(5, s);
                 launch_dots<double2, 1>(pp0, dpost[0].size(), N, part, p, s);
