@@ -354,6 +354,7 @@ __global__ __launch_bounds__(256) void k_sym_tiles_g(const GProb *__restrict__ p
 // accumulation is FP32 within the unit; the partial vectors go to the same
 // FP64 slots as the VALU tile pass's, so the same reduction sums them.
 typedef float f32x16g __attribute__((ext_vector_type(16)));
+typedef float f32x4g __attribute__((ext_vector_type(4)));
 // Loads that name the global address space.  Pointers read from the problem
 // table are generic, and a generic (flat) load also counts against the LDS wait
 // counter: the waits for the LDS fragment reads would then wait for the next
@@ -396,9 +397,12 @@ __global__ __launch_bounds__(256) void k_sym_tiles_gm(const GProb *__restrict__ 
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, h = w >> 1, prt = w & 1, li = lane & 31, lk = lane >> 5;
     if (t < 32) live[t] = (t < nc && !(skip && skip[int64_t(cb + t) * sks])) ? 1 : 0;
     __syncthreads();
-    bool any = false;
-    for (int c = 0; c < nc; ++c) any = any || live[c] != 0;
-    if (!any) return;   // uniform over the block
+    int hi = 0;   // one past the last live column
+    for (int c = 0; c < nc; ++c)
+        if (live[c]) hi = c + 1;
+    if (hi == 0) return;   // uniform over the block
+    // at most 16 live leading columns: 16 x 16 products (half the matrix-core work)
+    const bool narrow = hi <= 16;
     const float2 *Z = static_cast<const float2 *>(P.Z);
     const double2 *Xc = reinterpret_cast<const double2 *>(X);
     // staging: thread t always moves column t & 31 of the vectors (rows t/32 + 8 i)
@@ -454,6 +458,33 @@ __global__ __launch_bounds__(256) void k_sym_tiles_gm(const GProb *__restrict__ 
             pv[2 * r] = double(acc[q]);
         }
     };
+    // narrow form: wave w takes rows 16 w .. + 15 of the tile and both parts;
+    // v_mfma_f32_16x16x4f32: A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k,
+    // output value q of lane l at row 4 (l / 16) + q, column l % 16
+    const int ni = lane & 15, nk = lane >> 4;
+    auto chain16 = [&](f32x4g &ar, f32x4g &ai, bool transposed, float2 (*xs)[32]) {
+#pragma unroll 4
+        for (int k0 = 0; k0 < TB; k0 += 4) {
+            const float2 z = transposed ? sZ[k0 + nk][16 * w + ni] : sZ[16 * w + ni][k0 + nk];
+            const float2 x = xs[k0 + nk][ni];
+            ar = __builtin_amdgcn_mfma_f32_16x16x4f32(z.x, x.x, ar, 0, 0, 0);
+            ar = __builtin_amdgcn_mfma_f32_16x16x4f32(-z.y, x.y, ar, 0, 0, 0);
+            ai = __builtin_amdgcn_mfma_f32_16x16x4f32(z.x, x.y, ai, 0, 0, 0);
+            ai = __builtin_amdgcn_mfma_f32_16x16x4f32(z.y, x.x, ai, 0, 0, 0);
+        }
+    };
+    const bool nlive = live[ni] != 0;
+    const int64_t npo = nlive ? gc.poff[cb + ni] * TB : 0;
+    auto store16 = [&](const f32x4g &ar, const f32x4g &ai, int64_t slot) {
+        if (!nlive) return;
+        double *pv = part + (npo + slot * TB) * 2;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = 16 * w + 4 * nk + q;
+            pv[2 * r] = double(ar[q]);
+            pv[2 * r + 1] = double(ai[q]);
+        }
+    };
     double2 xv[8];
     float2 zv[16];
     load_x(xv, I);
@@ -461,8 +492,11 @@ __global__ __launch_bounds__(256) void k_sym_tiles_gm(const GProb *__restrict__ 
     load_z(zv, J0);
     load_x(xv, J0);
     f32x16g arow;
+    f32x4g nrr, nri;
 #pragma unroll
     for (int q = 0; q < 16; ++q) arow[q] = 0.f;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) nrr[q] = nri[q] = 0.f;
     for (int32_t J = J0; J < J1; ++J) {
         __syncthreads();   // the previous tile's LDS reads are done
         put_z(zv);
@@ -472,16 +506,28 @@ __global__ __launch_bounds__(256) void k_sym_tiles_gm(const GProb *__restrict__ 
             load_z(zv, J + 1);
             load_x(xv, J + 1);
         }
-        arow = chain(arow, false, sXJ);
-        if (J != I) {
-            f32x16g acol;
+        if (narrow) {
+            chain16(nrr, nri, false, sXJ);
+            if (J != I) {
+                f32x4g cr, ci;
 #pragma unroll
-            for (int q = 0; q < 16; ++q) acol[q] = 0.f;
-            acol = chain(acol, true, sXI);
-            store(acol, gload_i64(P.seg, J) + I);
+                for (int q = 0; q < 4; ++q) cr[q] = ci[q] = 0.f;
+                chain16(cr, ci, true, sXI);
+                store16(cr, ci, gload_i64(P.seg, J) + I);
+            }
+        } else {
+            arow = chain(arow, false, sXJ);
+            if (J != I) {
+                f32x16g acol;
+#pragma unroll
+                for (int q = 0; q < 16; ++q) acol[q] = 0.f;
+                acol = chain(acol, true, sXI);
+                store(acol, gload_i64(P.seg, J) + I);
+            }
         }
     }
-    store(arow, gload_i64(P.seg, I) + I + uo);
+    if (narrow) store16(nrr, nri, gload_i64(P.seg, I) + I + uo);
+    else store(arow, gload_i64(P.seg, I) + I + uo);
 }
 
 // y_I = sum of the partial vectors of row block I (column sums of tiles
