@@ -68,7 +68,7 @@ def parse():
     ap.add_argument("--k", type=float, default=10.0)
     ap.add_argument("--restart", type=int, default=50)
     ap.add_argument("--tol", type=float, default=1e-6)
-    ap.add_argument("--inner-tol", type=float, default=0.1, help="inner tolerance of the refinement")
+    ap.add_argument("--inner-tol", type=float, default=0.01, help="inner tolerance of the refinement")
     ap.add_argument("--inner-terms", type=int, default=2, choices=[2, 3],
                     help="terms of the inner split-BF16 products: 3 (hi/lo matrix x hi/lo vectors) or 2 (hi/lo "
                          "matrix x BF16 vectors)")

@@ -119,25 +119,25 @@ def test_full_size_large_sphere_solve(bie):
     op.close()
 
 
-@pytest.mark.parametrize("terms,basis", [(2, "f16"), (2, "c64"), (3, "c64")])
-def test_full_size_headline_block_solve(bie, terms, basis):
+@pytest.mark.parametrize("terms,basis,itol", [(2, "f16", 0.01), (2, "c64", 0.1), (3, "c64", 0.1)])
+def test_full_size_headline_block_solve(bie, terms, basis, itol):
     """The bench's headline form (block GMRES(50) over groups of 32 on split-BF16
-    products, 2 terms and the FP16-pair inner basis in the bench, FP64
-    refinement) on 64 plane waves at 7680 unknowns: every residual at most 1e-6
-    against the oracle's full matrix and equal to the reported SCC."""
+    products, 2 terms, the FP16-pair inner basis and inner tolerance 1e-2 in the
+    bench, FP64 refinement) on 64 plane waves at 7680 unknowns: every residual at
+    most 1e-6 against the oracle's full matrix and equal to the reported SCC."""
     V, T, rwg, _ = _mesh(4)
     op = bie.Operator(V, T, 10.0, storage="split_bf16")
     d, e = planewave_set(random_directions(32, 80), "theta")
     d2, e2 = planewave_set(random_directions(32, 80), "phi")
     B = op.rhs(np.concatenate([d, d2]), np.concatenate([e, e2]))
-    X, st = op.solve(B, bie.Solve(method="bgmres", block=32, restart=50, tol=1e-6, precision="mixed", inner_tol=0.1,
+    X, st = op.solve(B, bie.Solve(method="bgmres", block=32, restart=50, tol=1e-6, precision="mixed", inner_tol=itol,
                                   inner_terms=terms, basis=basis))
     op.close()
     Zo = cfill.fill(rwg, 10.0)
     Bn, Xn = B.cpu().numpy(), X.cpu().numpy()
     res = np.linalg.norm(Bn - Xn @ Zo.T, axis=1) / np.linalg.norm(Bn, axis=1)
     rep = np.array([s["relres_true"] for s in st])
-    _say(f"  block form ({terms} terms, {basis} basis), 7680 unknowns: max residual {res.max():.3e}, reported {rep.max():.3e}, "
+    _say(f"  block form ({terms} terms, {basis} basis, inner {itol:g}), 7680 unknowns: max residual {res.max():.3e}, reported {rep.max():.3e}, "
          f"iterations {int(np.mean([s['iters'] for s in st]))} mean")
     assert all(s["converged"] for s in st)
     assert res.max() <= 1e-6 * (1 + 1e-6)
@@ -185,7 +185,7 @@ def test_full_size_calderon_block_solve(bie):
 
 def test_full_size_large_sphere_block_form(bie):
     """The large sphere's timed form: block GMRES(30) over groups of 32 with 2-term
-    split-BF16 products, the FP16-pair inner basis and FP64 refinement, on the first 64 waves of the 16 x 16
+    split-BF16 products, the FP16-pair inner basis and FP64 refinement (inner tolerance 1e-2), on the first 64 waves of the 16 x 16
     (theta, phi) grid at 30720 unknowns, k = 20: every column converges, and the FP64
     residual behind the reported criterion agrees on sampled rows with the
     oracle's rows."""
@@ -196,7 +196,7 @@ def test_full_size_large_sphere_block_form(bie):
     dirs, pols = grid_planewaves(16, 16)
     B = op.rhs(dirs[:64], pols[:64])
     X, st = op.solve(B, bie.Solve(method="bgmres", block=32, restart=30, tol=1e-6, precision="mixed",
-                                  inner_tol=0.1, inner_terms=2, max_mvp=20000, basis="f16"))
+                                  inner_tol=0.01, inner_terms=2, max_mvp=20000, basis="f16"))
     conv = [s["converged"] for s in st]
     Rg = (B - op.apply(X)).cpu().numpy()
     rows = np.array([1, N // 3, N - 1])
