@@ -341,10 +341,12 @@ int bie_batch_solve_pc(const bie_op *const *ops, const struct bie_calderon *cons
  *   mat    0: the FP64 tiles (FP64 accumulation); 1: the FP32 tiles on the
  *          vector units (FP64 accumulation); 2: the FP32 tiles on the FP32
  *          matrix cores (vectors rounded to FP32, FP32 accumulation within a
- *          unit, partial sums and their reduction in FP64)
+ *          unit, partial sums and their reduction in FP64); 3: the FP64 tiles
+ *          on the FP64 matrix cores (FP64 throughout; the residual pass of
+ *          precision-1 batches with matrix cores on)
  *   unit_tiles     tiles per work unit, 1..64 (0: 8)
- *   cols_per_item  columns per work item, 1..4096, at most 32 with mat 2
- *                  (0: 8, or 32 with mat 2)
+ *   cols_per_item  columns per work item, 1..4096, at most 32 with mat 2 or 3
+ *                  (0: 8, or 32 with mat 2 or 3)
  * The columns go through library buffers (allocated per call); the call
  * returns when Y is written.  BIE_EINVAL for a NULL argument, a star-split or
  * fast operator, a missing matrix of the requested precision, operators on
@@ -362,8 +364,9 @@ int bie_batch_apply(const bie_op *const *ops, int64_t nops, const void *const *X
  * (1: default) and, for precision 1 on FP32 tiles, the grouped products on the
  * FP32 matrix cores (matrix_cores 1, the default: every work item takes up to 32
  * columns of its unit at once, vectors rounded to FP32 and FP32 accumulation
- * within a unit, partial sums and their reduction in FP64; 0: the VALU pass with
- * FP64 accumulation).  BIE_EINVAL outside -1..64. */
+ * within a unit, partial sums and their reduction in FP64; the FP64 residuals
+ * then on the FP64 matrix cores; 0: the VALU passes with FP64 accumulation).
+ * BIE_EINVAL outside -1..64. */
 int bie_batch_config(int unit_tiles, int use_graph, int matrix_cores);
 /* Tiles per unit chosen for this batch shape so far (0: none); for operators
  * holding both matrices, the choice for FP64 products if one was made, else the

@@ -552,13 +552,14 @@ def batch_solve(ops, Bs, opts: Solve | None = None, x0s=None, x0_fallback: bool 
     return Xs, out
 
 
-_BATCH_MAT = {"fp64": 0, "fp32": 1, "fp32_mfma": 2}
+_BATCH_MAT = {"fp64": 0, "fp32": 1, "fp32_mfma": 2, "fp64_mfma": 3}
 
 
 def batch_apply(ops, Xs, mat: str = "fp64", unit_tiles: int = 0, cols_per_item: int = 0, stream=None):
     """Y_p = T_p X_p for several operators in one grouped launch
     (bie_batch_apply).  mat: "fp64" (FP64 tiles), "fp32" (FP32 tiles, vector
-    units) or "fp32_mfma" (FP32 tiles on the matrix cores).  Returns the list of
+    units), "fp32_mfma" (FP32 tiles on the matrix cores) or "fp64_mfma" (FP64
+    tiles on the FP64 matrix cores).  Returns the list of
     products (R_p x N_p complex128 each)."""
     if mat not in _BATCH_MAT:
         raise ValueError(f"mat must be one of {sorted(_BATCH_MAT)}")

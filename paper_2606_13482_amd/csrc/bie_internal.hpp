@@ -216,8 +216,8 @@ void build_units(int64_t nT, int U, std::vector<int32_t> &units, std::vector<int
 // several problems: one tile launch over (problem, unit, group of G columns)
 // items, each going through its columns, and one reduce launch over (column,
 // row block) items.  mat64: FP64 tiles, else FP32.
-// mfma: the FP32 tiles on the FP32 matrix cores (FP32 vectors and
-// accumulation within a unit; at most 32 columns per item)
+// mfma: the matrix cores, at most 32 columns per item (FP32 tiles: FP32
+// vectors and accumulation within a unit; FP64 tiles: FP64 throughout)
 void grouped_product(bool mat64, const GProb *probs, const GCols &gc, const int32_t *items, int64_t nitems, int G,
                      const int32_t *ritems, int64_t nritems, const void *X, void *part, void *Y, const void *B,
                      const int *skip, int64_t sks, hipStream_t s, bool mfma = false);        // unit table (host -> device)
@@ -306,7 +306,8 @@ int solve_batch(const bie_op *const *ops, const bie_calderon *const *pcs, int64_
 void batch_config(int unit, int graph, int mfma);
 int batch_unit_chosen(const bie_op *const *ops, int64_t P, const int64_t *R);
 // grouped product of several operators outside a solve (mat 0: FP64 tiles, 1:
-// FP32 tiles, 2: FP32 tiles on the matrix cores; unit/G 0: defaults)
+// FP32 tiles, 2: FP32 tiles on the matrix cores, 3: FP64 tiles on the matrix
+// cores; unit/G 0: defaults)
 void batch_apply(const bie_op *const *ops, int64_t P, const void *const *X, void *const *Y, const int64_t *R,
                  int mat, int unit, int G, hipStream_t s);
 int solve(const bie_op *op, const void *B, void *X, int64_t R, const bie_solve_opts &o,

@@ -530,6 +530,131 @@ __global__ __launch_bounds__(256) void k_sym_tiles_gm(const GProb *__restrict__ 
     else store(arow, gload_i64(P.seg, I) + I + uo);
 }
 
+// The same grouped pass on FP64 tiles with the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64: A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k,
+// output value q of lane l at row l / 16 + 4 q, column l % 16 -- rows
+// interleaved, unlike the FP32 16 x 16 x 4 form): wave w takes
+// rows 16 w .. + 15 of the tile, both parts, and the item's columns in halves of
+// 16 (one half when the live columns fit in it).  The tile (64 KB) and the two
+// vector blocks stay FP64 in LDS; FP64 accumulation throughout.
+typedef double f64x4g __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_sym_tiles_gm64(const GProb *__restrict__ probs, GCols gc,
+                                                        const int32_t *__restrict__ items, int G,
+                                                        const double *__restrict__ X, double *__restrict__ part,
+                                                        const int *__restrict__ skip, int64_t sks)
+{
+    __shared__ double2 sZ[TB][TB + 1];
+    __shared__ double2 sXI[TB][32];
+    __shared__ double2 sXJ[TB][32];
+    __shared__ int32_t live[32];
+    const int64_t b = blockIdx.x;
+    const int32_t p = items[3 * b], u = items[3 * b + 1], g = items[3 * b + 2];
+    const GProb P = probs[p];
+    const int32_t I = __builtin_amdgcn_readfirstlane(P.units[3 * u]);
+    const int32_t J0 = __builtin_amdgcn_readfirstlane(P.units[3 * u + 1]);
+    const int32_t J1 = __builtin_amdgcn_readfirstlane(P.units[3 * u + 2]);
+    const int32_t uo = __builtin_amdgcn_readfirstlane(u - P.unit_ptr[I]);
+    const int32_t cb = P.c0 + g * G, ce = min(min(P.c1, cb + G), cb + 32);
+    const int nc = ce - cb;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, ni = lane & 15, nk = lane >> 4;
+    if (t < 32) live[t] = (t < nc && !(skip && skip[int64_t(cb + t) * sks])) ? 1 : 0;
+    __syncthreads();
+    int hi = 0;
+    for (int c = 0; c < nc; ++c)
+        if (live[c]) hi = c + 1;
+    if (hi == 0) return;   // uniform over the block
+    const int halves = hi <= 16 ? 1 : 2;
+    const double2 *Z = static_cast<const double2 *>(P.Z);
+    const double2 *Xc = reinterpret_cast<const double2 *>(X);
+    // staging as in the FP32 pass: column t & 31 of the vectors (rows t/32 + 8 i),
+    // entries t + 256 i of the tile
+    const int sc = t & 31, sr = t >> 5;
+    const bool slive = live[sc] != 0;
+    const int64_t sxo = slive ? gc.xoff[cb + sc] + gc.xstep * P.N : 0;
+    auto load_x = [&](double2 (&xv)[8], int32_t blk) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int64_t row = int64_t(blk) * TB + sr + 8 * q;
+            xv[q] = (slive && row < P.N) ? gload_d2(Xc, sxo + row) : make_double2(0.0, 0.0);
+        }
+    };
+    auto put_x = [&](double2 (*dst)[32], const double2 (&xv)[8]) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) dst[sr + 8 * q][sc] = xv[q];
+    };
+    auto load_z = [&](double2 (&zv)[16], int32_t J) {
+        const double2 *tile = Z + tile_of(I, J, P.nT) * TB * TB + t;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) zv[q] = gload_d2(tile, 256 * q);
+    };
+    auto put_z = [&](const double2 (&zv)[16]) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) sZ[(t >> 6) + 4 * q][t & 63] = zv[q];
+    };
+    auto chain = [&](f64x4g (&ar)[2], f64x4g (&ai)[2], bool transposed, double2 (*xs)[32]) {
+        for (int k0 = 0; k0 < TB; k0 += 4) {
+            const double2 z = transposed ? sZ[k0 + nk][16 * w + ni] : sZ[16 * w + ni][k0 + nk];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                if (c >= halves) break;
+                const double2 x = xs[k0 + nk][16 * c + ni];
+                ar[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(z.x, x.x, ar[c], 0, 0, 0);
+                ar[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(-z.y, x.y, ar[c], 0, 0, 0);
+                ai[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(z.x, x.y, ai[c], 0, 0, 0);
+                ai[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(z.y, x.x, ai[c], 0, 0, 0);
+            }
+        }
+    };
+    auto store = [&](const f64x4g (&ar)[2], const f64x4g (&ai)[2], int64_t slot) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            if (c >= halves) break;
+            const int col = 16 * c + ni;
+            if (!live[col]) continue;
+            double *pv = part + (gc.poff[cb + col] * TB + slot * TB) * 2;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = 16 * w + nk + 4 * q;
+                pv[2 * r] = ar[c][q];
+                pv[2 * r + 1] = ai[c][q];
+            }
+        }
+    };
+    double2 xv[8];
+    double2 zv[16];
+    load_x(xv, I);
+    put_x(sXI, xv);
+    load_z(zv, J0);
+    load_x(xv, J0);
+    f64x4g rr[2], ri[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) rr[c][q] = ri[c][q] = 0.0;
+    for (int32_t J = J0; J < J1; ++J) {
+        __syncthreads();   // the previous tile's LDS reads are done
+        put_z(zv);
+        put_x(sXJ, xv);
+        __syncthreads();
+        if (J + 1 < J1) {   // the next tile's loads go out before this tile's products
+            load_z(zv, J + 1);
+            load_x(xv, J + 1);
+        }
+        chain(rr, ri, false, sXJ);
+        if (J != I) {
+            f64x4g cr[2], ci[2];
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) cr[c][q] = ci[c][q] = 0.0;
+            chain(cr, ci, true, sXI);
+            store(cr, ci, gload_i64(P.seg, J) + I);
+        }
+    }
+    store(rr, ri, gload_i64(P.seg, I) + I + uo);
+}
+
 // y_I = sum of the partial vectors of row block I (column sums of tiles
 // (J < I, I), then row sums of the units of tile row I), stored contiguously.
 // Eight waves split the vectors (every eighth one) and their sums are added in
@@ -1058,9 +1183,13 @@ void grouped_product(bool mat64, const GProb *probs, const GCols &gc, const int3
     if (nitems == 0) return;
     const bool pf = sym_prefetch() != 0;
     if (mfma) {
-        if (mat64 || G > 32) throw Error(BIE_EINVAL, "the matrix-core grouped pass takes FP32 tiles and at most 32 columns");
-        hipLaunchKernelGGL(k_sym_tiles_gm, dim3(unsigned(nitems)), dim3(256), 0, s, probs, gc, items, G,
-                           (const double *)X, (double *)part, skip, sks);
+        if (G > 32) throw Error(BIE_EINVAL, "the matrix-core grouped pass takes at most 32 columns per item");
+        if (mat64)
+            hipLaunchKernelGGL(k_sym_tiles_gm64, dim3(unsigned(nitems)), dim3(256), 0, s, probs, gc, items, G,
+                               (const double *)X, (double *)part, skip, sks);
+        else
+            hipLaunchKernelGGL(k_sym_tiles_gm, dim3(unsigned(nitems)), dim3(256), 0, s, probs, gc, items, G,
+                               (const double *)X, (double *)part, skip, sks);
     } else if (mat64) {
         if (pf) hipLaunchKernelGGL((k_sym_tiles_g<double, double, true>), dim3(unsigned(nitems)), dim3(256), 0, s, probs,
                                    gc, items, G, (const double *)X, (double *)part, skip, sks);

@@ -2120,7 +2120,7 @@ int solve_batch(const bie_op *const *ops, const bie_calderon *const *pcs, int64_
     build_live(all_live);
     auto full_residual = [&](const int *skipdev) {   // Res = B - T X for the columns not skipped
         grouped_product(res64, probs_res, gres, litems, nlitems, L->G, lritems, nlritems, Xw, L->gpart, w->Res, Bw,
-                        skipdev, 1, s);
+                        skipdev, 1, s, mf);
     };
 
     std::vector<bie_solve_stat> hs(C, bie_solve_stat{ 0, 0, NAN, NAN, 0, 0, o.use_x0 ? 1 : 0 });
@@ -2461,14 +2461,15 @@ void batch_config(int unit, int graph, int mfma)
 void batch_apply(const bie_op *const *ops, int64_t P, const void *const *X, void *const *Y, const int64_t *R,
                  int mat, int unit, int G, hipStream_t s)
 {
-    if (mat < 0 || mat > 2)
-        throw Error(BIE_EINVAL, "mat must be 0 (FP64 tiles), 1 (FP32 tiles) or 2 (FP32 tiles on the matrix cores)");
-    const bool m64 = mat == 0, mf = mat == 2;
+    if (mat < 0 || mat > 3)
+        throw Error(BIE_EINVAL, "mat must be 0 (FP64 tiles), 1 (FP32 tiles), 2 (FP32 tiles on the matrix cores) or "
+                                "3 (FP64 tiles on the matrix cores)");
+    const bool m64 = mat == 0 || mat == 3, mf = mat >= 2;
     if (unit == 0) unit = 8;
     if (G == 0) G = mf ? 32 : 8;
     if (unit < 1 || unit > 64) throw Error(BIE_EINVAL, "tiles per unit must be 1..64");
     if (G < 1 || G > (mf ? 32 : 4096))
-        throw Error(BIE_EINVAL, mf ? "the matrix-core pass takes 1..32 columns per item" : "columns per item must be 1..4096");
+        throw Error(BIE_EINVAL, mf ? "the matrix-core passes take 1..32 columns per item" : "columns per item must be 1..4096");
     std::vector<int32_t> prob;
     std::vector<int64_t> off;
     int64_t nw = 0;

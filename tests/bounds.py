@@ -11,7 +11,8 @@ def product_bound(mat, unit, Zabs, Xabs):
     from the arithmetic of each pass, with S_i = sum_j |T_ij| |x_j| (oracle
     magnitudes) and e64 = 1e-12 max|T| sum_j |x_j| for the difference between
     the library's and the oracle's FP64 fills:
-      fp64       e64 (FP64 tiles and accumulation);
+      fp64, fp64_mfma   e64 (FP64 tiles and accumulation, vector units or
+                 FP64 matrix cores);
       fp32       sqrt(2) u S_i + e64 (each FP32 entry is the FP64 entry rounded:
                  re and im each within u relative; FP64 accumulation);
       fp32_mfma  (2 sqrt(2) u + 5 sqrt(n) u) S_i + e64: entries and vector
@@ -22,7 +23,7 @@ def product_bound(mat, unit, Zabs, Xabs):
     Zabs (N x N) and Xabs (R x N) are |T_oracle| and |X|; returns R x N."""
     S = Xabs @ Zabs.T
     e64 = 1e-12 * Zabs.max() * Xabs.sum(axis=1, keepdims=True)
-    if mat == "fp64":
+    if mat in ("fp64", "fp64_mfma"):
         return e64 + 0 * S
     if mat == "fp32":
         return np.sqrt(2) * U32 * S + e64

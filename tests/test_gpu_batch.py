@@ -323,7 +323,7 @@ def test_batch_matrix_cores_precision1(bie, with_pc):
 
 
 
-@pytest.mark.parametrize("mat", ["fp64", "fp32", "fp32_mfma"])
+@pytest.mark.parametrize("mat", ["fp64", "fp32", "fp32_mfma", "fp64_mfma"])
 @pytest.mark.parametrize("unit,cols", [(1, 1), (3, 5), (0, 0), (16, 32)])
 def test_batch_apply_parity(bie, mat, unit, cols):
     """The grouped product of the batched solves (bie_batch_apply) against the

@@ -260,7 +260,7 @@ def test_full_size_uneven_batch_products(bie):
     """The uneven batch at full size (64 surfaces, 648..5832 unknowns, their 1069
     plane-wave counts as columns): the grouped product of each pass in the
     batched solves' layout (16 tiles per unit; 8 columns per item on the vector
-    units, 32 on the matrix cores), on sampled rows (first, last and one random
+    units, 32 on the matrix cores, FP32 and FP64), on sampled rows (first, last and one random
     row of every surface) against the oracle's rows, element by element within
     the bound of each pass's arithmetic (tests/bounds.py)."""
     from paper_2606_13482_amd.inputs import uneven_batch
@@ -269,7 +269,7 @@ def test_full_size_uneven_batch_products(bie):
     Xs = [torch.from_numpy(complex_gaussian(op.N, 500 + i, cols=len(p["dirs"])).reshape(-1, op.N)).cuda()
           for i, (op, p) in enumerate(zip(ops, probs))]
     out = {mat: [y.cpu().numpy() for y in bie.batch_apply(ops, Xs, mat=mat, unit_tiles=16, cols_per_item=cols)]
-           for mat, cols in (("fp64", 8), ("fp32", 8), ("fp32_mfma", 32))}
+           for mat, cols in (("fp64", 8), ("fp32", 8), ("fp32_mfma", 32), ("fp64_mfma", 32))}
     worst = {mat: 0.0 for mat in out}
     rng = np.random.default_rng(77)
     for i, (op, p) in enumerate(zip(ops, probs)):
