@@ -1111,25 +1111,24 @@ __global__ __launch_bounds__(256) void k_bchol(GDev *__restrict__ gd, const int 
         brk = 0;
     }
     __syncthreads();
-    // right-looking Cholesky of the lower triangle of Gs (G2 = L L^H): pivot,
-    // column k, then the trailing update of the columns after k
+    // right-looking Cholesky of the lower triangle of Gs (G2 = L L^H), one
+    // barrier per column: every thread reads the pivot, column k of L and the
+    // trailing update G(i, l) -= G(i, k) conj(G(l, k)) / G(k, k) (l > k, the
+    // columns the update writes) come from column k of Gs in the same phase
     for (int k = 0; k < r; ++k) {
-        if (t == 0) {
-            const double p = Gs[k][k].x;
-            if (!(p > delta * delta * gmax)) {
-                brk = 1;
-                L[k][k] = make_double2(0.0, 0.0);
-            } else {
-                L[k][k] = make_double2(std::sqrt(p), 0.0);
+        const double p = Gs[k][k].x;
+        const bool ok = p > delta * delta * gmax;
+        const double d = ok ? std::sqrt(p) : 0.0;
+        if (t == 0 && !ok) brk = 1;
+        if (t >= k && t < r)
+            L[t][k] = t == k ? make_double2(d, 0.0) : (ok ? cscale(1.0 / d, Gs[t][k]) : make_double2(0.0, 0.0));
+        if (ok) {
+            const double ip = 1.0 / p;
+            for (int e = t; e < r * r; e += 256) {
+                const int i = e / r, l = e % r;
+                if (l > k && l <= i)
+                    Gs[i][l] = csub(Gs[i][l], cscale(ip, cmul(Gs[i][k], make_double2(Gs[l][k].x, -Gs[l][k].y))));
             }
-        }
-        __syncthreads();
-        const double d = L[k][k].x;
-        if (t > k && t < r) L[t][k] = d > 0.0 ? cscale(1.0 / d, Gs[t][k]) : make_double2(0.0, 0.0);
-        __syncthreads();
-        for (int e = t; e < r * r; e += 256) {
-            const int i = e / r, l = e % r;
-            if (l > k && l <= i) Gs[i][l] = csub(Gs[i][l], cmul(L[i][k], make_double2(L[l][k].x, -L[l][k].y)));
         }
         __syncthreads();
     }
