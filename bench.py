@@ -9,8 +9,9 @@ on the GPU.  One timed step serves the 1024 held-out right-hand sides (512
 directions x theta/phi) with the operator and the warm start resident: RHS
 assembly, network inference with the zero fallback, and block GMRES(50) over
 groups of 32 right-hand sides (one shared block Krylov space per group) with
-split-BF16 block products on the matrix cores and FP64 iterative refinement, to
-a true FP64 relative residual of 1e-6.
+2-term split-BF16 block products on the matrix cores, an FP16-pair inner basis
+and FP64 iterative refinement (inner tolerance 1e-2), to a true FP64 relative
+residual of 1e-6.
 value = right-hand sides meeting that criterion per second, summed over the
 timed steps.
 
@@ -924,7 +925,8 @@ def uneven_batch_leg(args, bie, torch):
     ccc = summary(stc, time.perf_counter() - t0)
     out = {"workload": (f"{len(ops)} surfaces, N {min(Ns)}..{max(Ns)}, {nrhs} plane waves; GMRES(50) on the FP32 "
                         f"matrices (grouped products on the FP32 matrix cores) right-preconditioned per surface "
-                        f"(Calderon, FP32 copy of M), every residual on the FP64 matrices, to {args.tol:g} (FP64 SCC; "
+                        f"(Calderon, FP32 copy of M), every residual on the FP64 matrices (FP64 matrix cores), to "
+                        f"{args.tol:g} (FP64 SCC; "
                         f"key ccc: 512 sampled FP64 rows gate, the FP64 SCC confirms), max 10000 products per "
                         f"right-hand side"),
            **{k: v for k, v in main.items() if k != "s"}, "batch_s": main["s"], "relres_recomputed_fp64_max": rec,
