@@ -89,6 +89,7 @@ template <typename AT> struct BasisRaw;
 template <> struct BasisRaw<float2> {
     typedef float2 type;
     static constexpr int P16 = 2;
+    static constexpr int MINB = 1;   // workgroups per CU asked of the compiler for the update (more would spill)
     static __device__ inline type load(const void *A, int64_t i) { return ld_global((const float2 *)A, i); }
     static __device__ inline void load16(const void *A, int64_t i, type *o)
     {
@@ -101,6 +102,7 @@ template <> struct BasisRaw<float2> {
 };
 template <> struct BasisRaw<c32h> {
     typedef h2v type;
+    static constexpr int MINB = 4;   // the update's 4 waves per SIMD fit in the registers without spills
     static constexpr int P16 = 4;
     static __device__ inline type load(const void *A, int64_t i) { return ld_global((const h2v *)A, i); }
     static __device__ inline void load16(const void *A, int64_t i, type *o)
@@ -754,14 +756,26 @@ __global__ __launch_bounds__(256) void k_bcomb_bf(const CItem *__restrict__ item
 // N % 4 == 0 (16-byte alignment of every lane's rows).
 template <typename AT>
 __global__ __launch_bounds__(256) void k_bdots_bd(const DItem *__restrict__ items, int64_t N, int nchunks, int64_t L,
-                                                  double2 *__restrict__ part)
+                                                  double2 *__restrict__ part, int xcd)
 {
     constexpr int MS = 32;
     typedef BasisRaw<AT> BR;
-    const DItem it = items[blockIdx.y];
+    int chunk = blockIdx.x, item = blockIdx.y;
+    if (xcd) {
+        // workgroups go to the 8 XCDs in turn: give each XCD a contiguous run of
+        // (chunk, item) pairs, items fastest, so that the tiles of one group on
+        // one chunk of rows follow each other on one XCD and its L2 keeps the
+        // chunk of the columns W they all read
+        const int total = gridDim.x * gridDim.y, lin = blockIdx.x + gridDim.x * blockIdx.y;
+        const int x = lin & 7, per = total >> 3, extra = total & 7;
+        const int wi = x * per + min(x, extra) + (lin >> 3);
+        chunk = wi / gridDim.y;
+        item = wi % gridDim.y;
+    }
+    const DItem it = items[item];
     if (it.flag && *it.flag == 0) return;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, h = lane >> 5;
-    const int64_t n0 = int64_t(blockIdx.x) * L, n1 = min(N, n0 + L);
+    const int64_t n0 = int64_t(chunk) * L, n1 = min(N, n0 + L);
     __shared__ __attribute__((aligned(16))) __bf16 Bh[2][32 * SPL], Bl[2][32 * SPL];
     const int v = 32 * w + (lane & 31);
     const bool vlive = v < it.kc;
@@ -850,7 +864,7 @@ __global__ __launch_bounds__(256) void k_bdots_bd(const DItem *__restrict__ item
             ci = mfma_bf(fl[ks], bih, ci);
         }
     }
-    double2 *o = part + (int64_t(blockIdx.y) * nchunks + blockIdx.x) * 128 * BMAX;
+    double2 *o = part + (int64_t(item) * nchunks + chunk) * 128 * BMAX;
     const int col = lane & 31;
     if (col < it.nb) {
 #pragma unroll
@@ -869,7 +883,7 @@ __global__ __launch_bounds__(256) void k_bdots_bd(const DItem *__restrict__ item
 // coefficients, as the planes of k_bcomb_bf) comes from LDS.  Output value q of
 // lane l: column b = 8 (q / 4) + 4 (l / 32) + q % 4, row n = l % 32 of the wave.
 template <typename AT>
-__global__ __launch_bounds__(256) void k_bcomb_bd(const CItem *__restrict__ items, int64_t N)
+__global__ __launch_bounds__(256, BasisRaw<AT>::MINB) void k_bcomb_bd(const CItem *__restrict__ items, int64_t N)
 {
     constexpr int KS = 32;
     typedef BasisRaw<AT> BR;
@@ -982,6 +996,159 @@ __global__ __launch_bounds__(256) void k_bcomb_bd(const CItem *__restrict__ item
             if (it.beta != 0.0) y = cadd(y, cscale(it.beta, out[ob + nn]));
             out[ob + nn] = y;
         }
+    }
+}
+
+// The update of an item whose K <= 32 vectors are FP64 (the scaling of a new
+// block, V_{j+1} = W T^{-1}, and the first block of a cycle) on the FP64 matrix
+// cores: v_mfma_f64_16x16x4f64 (A[i][k] in lane i + 16 k, B[k][j] in lane j + 16
+// k, output value q of lane l at row l / 16 + 4 q, column l % 16), complex
+// products as four real ones, exact FP64 products with FP64 accumulation.  Wave
+// w of a workgroup takes rows 16 w .. + 15 of its 64 and all 32 columns (two
+// tiles of 16); lane l reads entry n of vector k = 4 ks + l / 16 straight into
+// the operand, and the coefficients from global memory (one small matrix per
+// item, cached); no LDS and no barriers.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename OT>
+__global__ __launch_bounds__(256) void k_bcomb64(const CItem *__restrict__ items, int64_t N)
+{
+    const CItem it = items[blockIdx.y];
+    if (it.flag && *it.flag == 0) return;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
+    const int64_t nrow = int64_t(blockIdx.x) * 64 + 16 * w + li;   // the row this lane reads
+    const double2 *A = static_cast<const double2 *>(it.A);
+    f64x4 orr[2], oi[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) orr[c][q] = oi[c][q] = 0.0;
+    double2 a[8], b[8][2];
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {   // all operands of the item's K <= 32 issued first
+        const int k = 4 * ks + lk;
+        const bool kl = k < it.K;
+        a[ks] = (kl && nrow < N) ? ld_global(A, (int64_t(k / it.ar) * it.astride + k % it.ar) * N + nrow)
+                                 : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int col = 16 * c + li;
+            b[ks][c] = (kl && col < it.nb) ? ld_global(it.C, int64_t(k) * it.ldc + col) : make_double2(0.0, 0.0);
+        }
+    }
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            orr[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks].x, b[ks][c].x, orr[c], 0, 0, 0);
+            orr[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[ks].y, b[ks][c].y, orr[c], 0, 0, 0);
+            oi[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks].x, b[ks][c].y, oi[c], 0, 0, 0);
+            oi[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks].y, b[ks][c].x, oi[c], 0, 0, 0);
+        }
+    OT *out = static_cast<OT *>(it.out);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const int col = 16 * c + li;
+        if (col >= it.nb) continue;
+        const int64_t ob = int64_t(it.ocol ? it.ocol[col] : col) * N;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t n = int64_t(blockIdx.x) * 64 + 16 * w + lk + 4 * q;
+            if (n < N) {
+                double2 y = make_double2(it.alpha * orr[c][q], it.alpha * oi[c][q]);
+                if (it.beta != 0.0) y = cadd(y, cscale(it.beta, to_d2(out[ob + n])));
+                out[ob + n] = from_d2<OT>(y);
+            }
+        }
+    }
+}
+
+// Gram matrix G = W^H W of an item's r <= 32 FP64 columns (A and Bm the same
+// vectors) over a chunk of L rows on the FP64 matrix cores, partial sums laid
+// out as k_bdots' with 32 vectors per tile (summed by k_bdots_fin).  Lane l
+// reads entry n = ns + l / 16 of column l % 16 (and of column 16 + l % 16): the
+// same register is the A operand (conj(W) as rows) and the B operand (W as
+// columns), so one load feeds both.  Tiles (0,0), (0,1), (1,1) of 16 x 16 are
+// formed (the last two only when r > 16), (1,0) is written as the conjugate
+// transpose of (0,1).  Wave w takes every fourth step of 4 rows; the waves'
+// sums are added through LDS in a fixed order.
+__global__ __launch_bounds__(256) void k_bgram64(const DItem *__restrict__ items, int64_t N, int nchunks, int64_t L,
+                                                 double2 *__restrict__ part)
+{
+    const DItem it = items[blockIdx.y];
+    if (it.flag && *it.flag == 0) return;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, li = lane & 15, lk = lane >> 4;
+    const int r = it.kc;
+    const bool two = r > 16;
+    const int64_t n0 = int64_t(blockIdx.x) * L, n1 = min(N, n0 + L);
+    const double2 *A = static_cast<const double2 *>(it.A);
+    auto voff = [&](int v) { return (int64_t((it.k0 + v) / it.ar) * it.astride + (it.k0 + v) % it.ar) * N; };
+    const bool l0 = li < r, l1 = 16 + li < r;
+    const int64_t o0 = l0 ? voff(li) : 0, o1 = l1 ? voff(16 + li) : 0;
+    f64x4 g[6];   // (0,0) re, im; (0,1) re, im; (1,1) re, im
+#pragma unroll
+    for (int e = 0; e < 6; ++e)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) g[e][q] = 0.0;
+    auto step = [&](double2 x0, double2 x1) {
+        // conj(a) b: re = a.x b.x + a.y b.y, im = a.x b.y - a.y b.x
+        g[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0.x, x0.x, g[0], 0, 0, 0);
+        g[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0.y, x0.y, g[0], 0, 0, 0);
+        g[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0.x, x0.y, g[1], 0, 0, 0);
+        g[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(-x0.y, x0.x, g[1], 0, 0, 0);
+        if (two) {
+            g[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0.x, x1.x, g[2], 0, 0, 0);
+            g[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0.y, x1.y, g[2], 0, 0, 0);
+            g[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0.x, x1.y, g[3], 0, 0, 0);
+            g[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(-x0.y, x1.x, g[3], 0, 0, 0);
+            g[4] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1.x, x1.x, g[4], 0, 0, 0);
+            g[4] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1.y, x1.y, g[4], 0, 0, 0);
+            g[5] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1.x, x1.y, g[5], 0, 0, 0);
+            g[5] = __builtin_amdgcn_mfma_f64_16x16x4f64(-x1.y, x1.x, g[5], 0, 0, 0);
+        }
+    };
+    const double2 z = make_double2(0.0, 0.0);
+    int64_t ns = n0 + 4 * w;
+    for (; ns + 52 <= n1; ns += 64) {   // four whole steps per trip (rows up to ns + 51), loads first
+        double2 x0[4], x1[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t n = ns + 16 * u + lk;
+            x0[u] = l0 ? ld_global(A, o0 + n) : z;
+            x1[u] = (two && l1) ? ld_global(A, o1 + n) : z;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) step(x0[u], x1[u]);
+    }
+    for (; ns < n1; ns += 16) {
+        const int64_t n = ns + lk;
+        const bool nl = n < n1;
+        step((nl && l0) ? ld_global(A, o0 + n) : z, (nl && two && l1) ? ld_global(A, o1 + n) : z);
+    }
+    __shared__ double red[3][24][64];
+    if (w > 0)
+#pragma unroll
+        for (int e = 0; e < 6; ++e)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) red[w - 1][4 * e + q][lane] = g[e][q];
+    __syncthreads();
+    if (w > 0) return;
+#pragma unroll 1
+    for (int v = 0; v < 3; ++v)
+#pragma unroll
+        for (int e = 0; e < 6; ++e)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) g[e][q] += red[v][4 * e + q][lane];
+    double2 *o = part + (int64_t(blockIdx.y) * nchunks + blockIdx.x) * 32 * BMAX;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int v = lk + 4 * q;   // output row of value q, column li
+        if (v < r && l0) o[v * BMAX + li] = make_double2(g[0][q], g[1][q]);
+        if (two && v < r && l1) {
+            o[v * BMAX + 16 + li] = make_double2(g[2][q], g[3][q]);
+            o[(16 + li) * BMAX + v] = make_double2(g[2][q], -g[3][q]);
+        }
+        if (two && 16 + v < r && l1) o[(16 + v) * BMAX + 16 + li] = make_double2(g[4][q], g[5][q]);
     }
 }
 
@@ -1544,6 +1711,41 @@ void launch_comb(const CItem *d, size_t ni, int64_t N, int nbmax, hipStream_t s)
     BIE_HIP(hipGetLastError());
 }
 
+// Gram matrices W^H W of FP64 columns (items with A == Bm, kc == nb <= 32): the
+// FP64 matrix cores, or the vector ALUs with BIE_COMB64=valu (for comparison)
+void launch_gram64(const DItem *d, size_t ni, int64_t N, double2 *part, int nbmax, hipStream_t s)
+{
+    static const bool valu = [] {
+        const char *e = getenv("BIE_COMB64");
+        return e && std::strcmp(e, "valu") == 0;
+    }();
+    if (ni == 0) return;
+    if (valu) return launch_dots<double2, 1>(d, ni, N, part, nbmax, s);
+    const int64_t nch = std::max<int64_t>(1, std::min<int64_t>((N + 63) / 64, (768 + int64_t(ni) - 1) / int64_t(ni)));
+    const int64_t L = ((N + nch - 1) / nch + 15) / 16 * 16;
+    const int nchunks = int((N + L - 1) / L);
+    hipLaunchKernelGGL(k_bgram64, dim3(unsigned(nchunks), unsigned(ni)), dim3(256), 0, s, d, N, nchunks, L, part);
+    hipLaunchKernelGGL(k_bdots_fin, dim3(unsigned(ni), unsigned((32 * BMAX) / 64)), dim3(256), 0, s, d, nchunks, 32,
+                       (const double2 *)part);
+    BIE_HIP(hipGetLastError());
+}
+
+// Update whose vectors are FP64 and whose items have K <= 32 (every item of the
+// block solver's scalings): the FP64 matrix cores, or the vector ALUs with
+// BIE_COMB64=valu (for comparison)
+template <typename OT>
+void launch_comb64(const CItem *d, size_t ni, int64_t N, int nbmax, hipStream_t s)
+{
+    static const bool valu = [] {
+        const char *e = getenv("BIE_COMB64");
+        return e && std::strcmp(e, "valu") == 0;
+    }();
+    if (ni == 0) return;
+    if (valu) return launch_comb<double2, OT>(d, ni, N, nbmax, s);
+    hipLaunchKernelGGL(k_bcomb64<OT>, dim3(unsigned((N + 63) / 64), unsigned(ni)), dim3(256), 0, s, d, N);
+    BIE_HIP(hipGetLastError());
+}
+
 // the basis kernels: BF16 three-term splits with the basis read straight into
 // the operands (default), the same with the basis staged in LDS
 // (BIE_BASIS_MFMA=lds, and the dots whenever N % 4 != 0), or the FP32 matrix
@@ -1560,18 +1762,71 @@ int basis_mode()
     return v;
 }
 
+// XCD-aware order of the basis dots' workgroups (BIE_BDOTS_XCD=0 keeps the
+// launch order, for comparison)
+int bdots_xcd()
+{
+    static const int v = [] {
+        const char *e = getenv("BIE_BDOTS_XCD");
+        return (e && std::strcmp(e, "0") == 0) ? 0 : 1;
+    }();
+    return v;
+}
+
+// workgroups of the direct basis dots resident on the whole GPU at once
+// (one device type per process)
+template <typename VT>
+int64_t bdots_slots()
+{
+    static const int64_t v = [] {
+        int dev = 0, cus = 0, nb = 0;
+        BIE_HIP(hipGetDevice(&dev));
+        BIE_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        BIE_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bdots_bd<VT>, 256, 0));
+        return std::max<int64_t>(1, int64_t(cus) * std::max(nb, 1));
+    }();
+    return v;
+}
+
+// Row chunks per basis-dots item: every workgroup does the same work, so the
+// count of workgroups is chosen to fill whole rounds of the resident slots
+// (the last round of a plain count can run nearly empty); among counts of at
+// least the slots' worth of workgroups (or all 128-row chunks) and at most
+// twice it, the one with the best filled fraction, then the fewest chunks;
+// one chunk when the items alone exceed that.  ni * chunks <= ni + 2 slots
+// (the partial sums' buffer is sized for that).
+int64_t dots_chunks(int64_t ni, int64_t N, int64_t slots)
+{
+    const int64_t maxch = std::max<int64_t>(1, (N + 127) / 128);
+    const int64_t need = std::min(slots, ni * maxch);
+    int64_t best = 1;
+    double beff = -1.0;
+    for (int64_t c = 1; c <= maxch && ni * c <= 2 * slots; ++c) {
+        const int64_t tot = ni * c;
+        if (tot < need) continue;
+        const double eff = double(tot) / double(((tot + slots - 1) / slots) * slots);
+        if (eff > beff + 1e-9) {
+            beff = eff;
+            best = c;
+        }
+    }
+    return best;
+}
+
 template <typename VT>
 void launch_dots_mf(const DItem *d, size_t ni, int64_t N, double2 *part, hipStream_t s)
 {
     if (ni == 0) return;
-    const int64_t nch = std::max<int64_t>(1, std::min<int64_t>((1024 + int64_t(ni) - 1) / int64_t(ni), (N + 127) / 128));
+    const bool direct = basis_mode() == BASIS_DIRECT && N % 4 == 0;
+    int64_t nch = std::max<int64_t>(1, std::min<int64_t>((1024 + int64_t(ni) - 1) / int64_t(ni), (N + 127) / 128));
+    if (direct) nch = dots_chunks(int64_t(ni), N, bdots_slots<VT>());
     const int64_t L = ((N + nch - 1) / nch + 31) / 32 * 32;
     const int nchunks = int((N + L - 1) / L);
     const dim3 grid{ unsigned(nchunks), unsigned(ni) };
     if (std::is_same<VT, float2>::value && basis_mode() == BASIS_FP32)
         hipLaunchKernelGGL(k_bdots_mf, grid, dim3(256), 0, s, d, N, nchunks, L, part);
-    else if (basis_mode() == BASIS_DIRECT && N % 4 == 0)
-        hipLaunchKernelGGL(k_bdots_bd<VT>, grid, dim3(256), 0, s, d, N, nchunks, L, part);
+    else if (direct)
+        hipLaunchKernelGGL(k_bdots_bd<VT>, grid, dim3(256), 0, s, d, N, nchunks, L, part, bdots_xcd());
     else hipLaunchKernelGGL(k_bdots_bf<VT>, grid, dim3(256), 0, s, d, N, nchunks, L, part);
     hipLaunchKernelGGL(k_bdots_fin, dim3(unsigned(ni), unsigned((128 * BMAX) / 64)), dim3(256), 0, s, d, nchunks, 128,
                        (const double2 *)part);
@@ -1777,7 +2032,9 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
     double2 *Du = pcd ? db.get<double2>(size_t(R) * N) : nullptr;   // M U
     VT *V = db.get<VT>(size_t(m + 1) * R * N);
     const int64_t tiles = ((m + 1) * p + DT - 1) / DT + 1;   // basis tiles per group, and its Gram item
-    double2 *part = db.get<double2>(size_t(Gmax * tiles + 1024) * DT * BMAX);
+    int64_t slack = 1024;   // workgroups of a basis-dots launch beyond one per item
+    if constexpr (!std::is_same<VT, double2>::value) slack = std::max<int64_t>(slack, 2 * bdots_slots<VT>());
+    double2 *part = db.get<double2>(size_t(Gmax * tiles + slack) * DT * BMAX);
     const int nparts = int(std::min<int64_t>(64, (N + 255) / 256));
     double *npart = db.get<double>(size_t(R) * nparts);
     double *nrm = db.get<double>(size_t(R));
@@ -2009,7 +2266,8 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
             ar.flush(s);
             hipLaunchKernelGGL(k_bscatter, dim3(unsigned(up.size())), dim3(256), 0, s, dup);
             BIE_HIP(hipGetLastError());
-            launch_comb<double2, VT>(ci, it.size(), N, p, s);
+            if constexpr (std::is_same<VT, double2>::value) launch_comb<double2, VT>(ci, it.size(), N, p, s);
+            else launch_comb64<VT>(ci, it.size(), N, p, s);   // K = q <= 32
         }
         if (pcd) zero_into(R * N, Ux, s);
         // (3) block Arnoldi steps; every active group advances together.  The
@@ -2100,6 +2358,11 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
                     gemm64_product(op, Vj, N, Wb, N, nullptr, 0, nc, dc, s);
                 }
                 launch_ls();
+                // Gram matrices of W: FP64 matrix cores in the mixed forms
+                auto gram = [&](const DItem *gi, size_t n) {
+                    if constexpr (std::is_same<VT, double2>::value) launch_dots<double2, 1>(gi, n, N, part, p, s);
+                    else launch_gram64(gi, n, N, part, p, s);
+                };
                 int64_t pairs = 0, vecs = 0;   // basis vector x column pairs, basis vectors of the first pass
                 for (int g : act) {
                     pairs += int64_t(j + 1) * grp[g].r * grp[g].r;
@@ -2108,19 +2371,20 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
                 prof_begin(4, s, pairs);
                 basis_dots<VT>(pv0, dv[0].size(), N, part, p, s);
                 prof_end(4, s);
-                if (reorth > 0.0) launch_dots<double2, 1>(ppre, dpre.size(), N, part, p, s);   // G1 for the second-pass test
+                if (reorth > 0.0) gram(ppre, dpre.size());   // G1 for the second-pass test
                 prof_begin(5, s, vecs);
                 basis_comb<VT>(pc0, ci[0].size(), N, p, s);
                 prof_end(5, s);
-                launch_dots<double2, 1>(pp0, dpost[0].size(), N, part, p, s);
+                gram(pp0, dpost[0].size());
                 hipLaunchKernelGGL(k_bflag, dim3(unsigned(na)), dim3(64), 0, s, gd, dg, reorth);
                 if (reorth > 0.0) {
                     basis_dots<VT>(pv1, dv[1].size(), N, part, p, s);
                     basis_comb<VT>(pc1, ci[1].size(), N, p, s);
-                    launch_dots<double2, 1>(pp1, dpost[1].size(), N, part, p, s);
+                    gram(pp1, dpost[1].size());
                 }
                 hipLaunchKernelGGL(k_bchol, dim3(unsigned(na)), dim3(256), 0, s, gd, dg, j, m, DELTA);
-                launch_comb<double2, VT>(pcs, cs.size(), N, p, s);
+                if constexpr (std::is_same<VT, double2>::value) launch_comb<double2, VT>(pcs, cs.size(), N, p, s);
+                else launch_comb64<VT>(pcs, cs.size(), N, p, s);   // K = r <= 32
             }
             launch_ls();   // no step j: the update of step prev right away
             if (prev >= 0) {
