@@ -1246,6 +1246,18 @@ __global__ __launch_bounds__(256) void k_bchol(GDev *__restrict__ gd, const int 
         double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
         if (a < r) {
             int k = part;
+            for (; k + 120 < K; k += 128) {   // 16 rows per trip, all loads issued first
+                double2 h[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) h[u] = H[int64_t(k + 8 * u) * r + a];
+#pragma unroll
+                for (int u = 0; u < 16; u += 4) {
+                    s0 += h[u].x * h[u].x + h[u].y * h[u].y;
+                    s1 += h[u + 1].x * h[u + 1].x + h[u + 1].y * h[u + 1].y;
+                    s2 += h[u + 2].x * h[u + 2].x + h[u + 2].y * h[u + 2].y;
+                    s3 += h[u + 3].x * h[u + 3].x + h[u + 3].y * h[u + 3].y;
+                }
+            }
             for (; k + 24 < K; k += 32) {
                 const double2 h0 = H[int64_t(k) * r + a], h1 = H[int64_t(k + 8) * r + a];
                 const double2 h2 = H[int64_t(k + 16) * r + a], h3 = H[int64_t(k + 24) * r + a];
