@@ -1007,10 +1007,12 @@ __global__ __launch_bounds__(256, BasisRaw<AT>::MINB) void k_bcomb_bd(const CIte
 // w of a workgroup takes rows 16 w .. + 15 of its 64 and all 32 columns (two
 // tiles of 16); lane l reads entry n of vector k = 4 ks + l / 16 straight into
 // the operand, and the coefficients from global memory (one small matrix per
-// item, cached); no LDS and no barriers.
+// item, cached); no LDS and no barriers.  UPPER: every coefficient matrix
+// is upper triangular (C[k][b] = 0 for k > b), so columns 0 .. 15 take only
+// vectors 0 .. 15 (the products skipped are exact zeros).
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-template <typename OT>
+template <typename OT, bool UPPER>
 __global__ __launch_bounds__(256) void k_bcomb64(const CItem *__restrict__ items, int64_t N)
 {
     const CItem it = items[blockIdx.y];
@@ -1033,13 +1035,15 @@ __global__ __launch_bounds__(256) void k_bcomb64(const CItem *__restrict__ items
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
             const int col = 16 * c + li;
-            b[ks][c] = (kl && col < it.nb) ? ld_global(it.C, int64_t(k) * it.ldc + col) : make_double2(0.0, 0.0);
+            b[ks][c] = (kl && col < it.nb && !(UPPER && c == 0 && ks >= 4)) ? ld_global(it.C, int64_t(k) * it.ldc + col)
+                                                                             : make_double2(0.0, 0.0);
         }
     }
 #pragma unroll
     for (int ks = 0; ks < 8; ++ks)
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
+            if (UPPER && c == 0 && ks >= 4) continue;
             orr[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks].x, b[ks][c].x, orr[c], 0, 0, 0);
             orr[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[ks].y, b[ks][c].y, orr[c], 0, 0, 0);
             oi[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks].x, b[ks][c].y, oi[c], 0, 0, 0);
@@ -1746,7 +1750,7 @@ void launch_gram64(const DItem *d, size_t ni, int64_t N, double2 *part, int nbma
 // block solver's scalings): the FP64 matrix cores, or the vector ALUs with
 // BIE_COMB64=valu (for comparison)
 template <typename OT>
-void launch_comb64(const CItem *d, size_t ni, int64_t N, int nbmax, hipStream_t s)
+void launch_comb64(const CItem *d, size_t ni, int64_t N, int nbmax, hipStream_t s, bool upper)
 {
     static const bool valu = [] {
         const char *e = getenv("BIE_COMB64");
@@ -1754,7 +1758,9 @@ void launch_comb64(const CItem *d, size_t ni, int64_t N, int nbmax, hipStream_t 
     }();
     if (ni == 0) return;
     if (valu) return launch_comb<double2, OT>(d, ni, N, nbmax, s);
-    hipLaunchKernelGGL(k_bcomb64<OT>, dim3(unsigned((N + 63) / 64), unsigned(ni)), dim3(256), 0, s, d, N);
+    const dim3 grid{ unsigned((N + 63) / 64), unsigned(ni) };
+    if (upper) hipLaunchKernelGGL((k_bcomb64<OT, true>), grid, dim3(256), 0, s, d, N);
+    else hipLaunchKernelGGL((k_bcomb64<OT, false>), grid, dim3(256), 0, s, d, N);
     BIE_HIP(hipGetLastError());
 }
 
@@ -2279,7 +2285,7 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
             hipLaunchKernelGGL(k_bscatter, dim3(unsigned(up.size())), dim3(256), 0, s, dup);
             BIE_HIP(hipGetLastError());
             if constexpr (std::is_same<VT, double2>::value) launch_comb<double2, VT>(ci, it.size(), N, p, s);
-            else launch_comb64<VT>(ci, it.size(), N, p, s);   // K = q <= 32
+            else launch_comb64<VT>(ci, it.size(), N, p, s, false);   // K = q <= 32
         }
         if (pcd) zero_into(R * N, Ux, s);
         // (3) block Arnoldi steps; every active group advances together.  The
@@ -2396,7 +2402,7 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
                 }
                 hipLaunchKernelGGL(k_bchol, dim3(unsigned(na)), dim3(256), 0, s, gd, dg, j, m, DELTA);
                 if constexpr (std::is_same<VT, double2>::value) launch_comb<double2, VT>(pcs, cs.size(), N, p, s);
-                else launch_comb64<VT>(pcs, cs.size(), N, p, s);   // K = r <= 32
+                else launch_comb64<VT>(pcs, cs.size(), N, p, s, true);   // K = r <= 32, R^{-1} upper triangular
             }
             launch_ls();   // no step j: the update of step prev right away
             if (prev >= 0) {
