@@ -958,10 +958,12 @@ def counters_probe(args, bie, torch):
     batch (FP32 and FP64 matrices, all 1069 columns, the autotuned layouts: the
     candidates' timing launches, then one restart cycle of 1 step on the FP32
     tiles and its residuals on the FP64 tiles, once with the vector-unit pass and
-    once with the matrix-core pass); and 3
+    once with the matrix-core pass); one solve of the headline's batch from zero (1024
+    right-hand sides of 512 directions, the headline's mixed block GMRES: 2-term
+    products, FP16-pair basis; the kernels at the shapes the bench times); and 3
     plain copies of 1 GiB (FETCH_SIZE / WRITE_SIZE
     calibration)."""
-    from paper_2606_13482_amd.inputs import icosphere, complex_gaussian, uneven_batch
+    from paper_2606_13482_amd.inputs import icosphere, complex_gaussian, uneven_batch, random_directions
     V, T = icosphere(args.level)
     for storage in ("c128", "c64"):
         bie.Operator(V, T, args.k, storage=storage).close()
@@ -974,6 +976,8 @@ def counters_probe(args, bie, torch):
         op.apply(Xb, block=True)
     for _ in range(5):
         op.apply(Xb, block="fp64")
+    dte, pte, _ = planewave_batch(bie, random_directions(args.test_dirs, 55))
+    _, sth = op.solve(op.rhs(dte, pte), mixed_opts(args, bie, args.restart))
     probs = uneven_batch()
     ops = [bie.Operator(p["V"], p["T"], p["k"], storage="c64", keep_fp64=True) for p in probs]
     Bs = [o.rhs(p["dirs"], p["pols"]) for o, p in zip(ops, probs)]
@@ -991,6 +995,8 @@ def counters_probe(args, bie, torch):
     torch.cuda.synchronize()
     print(json.dumps({"counters_probe": {"N": op.N, "packed_fp64_launches": 5, "block_launches": 5,
                                          "block_columns": 512, "copy_bytes": a.numel() * 4, "copies": 3,
+                                         "headline_solve_rhs": len(sth),
+                                         "headline_solve_converged": float(np.mean([s["converged"] for s in sth])),
                                          "batch_packed_fp32_bytes": int(sum(4 * o.N * (o.N + 1) for o in ops)),
                                          "batch_columns": int(sum(b.shape[0] for b in Bs))}}),
           flush=True)
