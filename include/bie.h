@@ -193,15 +193,19 @@ typedef struct {
     int use_x0;          /* 1: X holds the initial guess on entry; 2: the same with
                             fallback: a guess with ||b - T x0|| >= ||b|| (the solver's
                             first residual) is replaced by zero.  That residual is FP64,
-                            except in mixed-precision block GMRES, where it only starts
-                            the first correction and is taken with the 3-term split-BF16
-                            product (a right-hand side it puts at or below
-                            max(tol, 1e-3) is taken again in FP64, which decides) */
+                            except in mixed-precision block GMRES, where every residual
+                            of the refinement is taken with the 3-term split-BF16
+                            product (see precision) */
     int precision;       /* 0: products with the stored matrix (FP64 if stored);
                             1: mixed precision with iterative refinement: outer FP64
                                residual and criterion (SCC), inner GMRES on the
                                split-BF16 matrix (storage BIE_SPLIT_BF16) or on the
-                               FP32 matrix (storage BIE_C64 with keep_fp64) */
+                               FP32 matrix (storage BIE_C64 with keep_fp64).  Block
+                               GMRES takes each outer residual first with the 3-term
+                               split-BF16 product (relative error near 1e-5): a
+                               right-hand side above max(tol, 1e-3) only starts its
+                               next correction from it, one at or below is taken again
+                               in FP64, which decides convergence */
     double inner_tol;    /* precision 1: inner tolerance relative to the outer residual
                             (0: default 1e-3) */
     int64_t slots;       /* precision 1: right-hand sides in flight (continuous batch:

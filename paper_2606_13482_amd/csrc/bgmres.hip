@@ -2140,12 +2140,12 @@ int solve_chunk(bie_op *op, const double2 *B, double2 *X, int64_t R, const bie_s
     std::vector<double> rn;
     std::vector<HGroup> grp;
     while (!live.empty()) {
-        // (1) FP64 residuals and the standard criterion.  In refinement the residual
-        // of an initial guess only starts the first correction: it is taken with the
-        // 3-term split-BF16 product (relative error near 1e-5), and every right-hand
-        // side it puts within that product's reach of convergence (at or below
-        // max(tol, 1e-3)) is taken again in FP64, which decides
-        const bool guess_low = first && o.use_x0 && mixed;
+        // (1) FP64 residuals and the standard criterion.  In refinement a residual
+        // far from convergence only starts the next correction: every residual is
+        // taken with the 3-term split-BF16 product (relative error near 1e-5), and
+        // every right-hand side it puts within that product's reach of convergence
+        // (at or below max(tol, 1e-3)) is taken again in FP64, which decides
+        const bool guess_low = mixed && !(first && !o.use_x0);
         if (first && !o.use_x0) {
             BIE_HIP(hipMemcpyAsync(Rres, B, size_t(R) * N * sizeof(double2), hipMemcpyDeviceToDevice, s));
         } else {
