@@ -378,7 +378,7 @@ __device__ inline int64_t gload_i64(const int64_t *p, int64_t i)
 
 __global__ __launch_bounds__(256) void k_sym_tiles_gm(const GProb *__restrict__ probs, GCols gc,
                                                       const int32_t *__restrict__ items, int G,
-                                                      const double *__restrict__ X, double *__restrict__ part,
+                                                      const double *__restrict__ X, float *__restrict__ part,
                                                       const int *__restrict__ skip, int64_t sks)
 {
     __shared__ float2 sZ[TB][TB + 1];
@@ -451,11 +451,11 @@ __global__ __launch_bounds__(256) void k_sym_tiles_gm(const GProb *__restrict__ 
     const int64_t opo = olive ? gc.poff[cb + li] * TB : 0;
     auto store = [&](const f32x16g &acc, int64_t slot) {
         if (!olive) return;
-        double *pv = part + (opo + slot * TB) * 2 + prt;
+        float *pv = part + (opo + slot * TB) * 2 + prt;
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int r = 32 * h + 8 * (q >> 2) + 4 * lk + (q & 3);
-            pv[2 * r] = double(acc[q]);
+            pv[2 * r] = acc[q];
         }
     };
     // narrow form: wave w takes rows 16 w .. + 15 of the tile and both parts;
@@ -477,12 +477,12 @@ __global__ __launch_bounds__(256) void k_sym_tiles_gm(const GProb *__restrict__ 
     const int64_t npo = nlive ? gc.poff[cb + ni] * TB : 0;
     auto store16 = [&](const f32x4g &ar, const f32x4g &ai, int64_t slot) {
         if (!nlive) return;
-        double *pv = part + (npo + slot * TB) * 2;
+        float *pv = part + (npo + slot * TB) * 2;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int r = 16 * w + 4 * nk + q;
-            pv[2 * r] = double(ar[q]);
-            pv[2 * r + 1] = double(ai[q]);
+            pv[2 * r] = ar[q];
+            pv[2 * r + 1] = ai[q];
         }
     };
     double2 xv[8];
@@ -685,6 +685,37 @@ __device__ inline void reduce_rows(int64_t N, const int64_t *__restrict__ seg, i
     }
 }
 
+// The same with FP32 partial sums (the matrix-core pass stores its FP32
+// accumulators as they are), added in FP64.
+template <bool SUB>
+__device__ inline void reduce_rows_f(int64_t N, const int64_t *__restrict__ seg, int64_t I,
+                                     const float2 *__restrict__ pv, double2 *__restrict__ y,
+                                     const double2 *__restrict__ b)
+{
+    const int r = threadIdx.x & 63, w = threadIdx.x >> 6;
+    pv += seg[I] * TB;
+    const int64_t K = seg[I + 1] - seg[I];
+    double2 a = { 0, 0 };
+#pragma unroll 4
+    for (int64_t q = w; q < K; q += 8) {
+        const float2 v = pv[q * TB + r];
+        a.x += double(v.x);
+        a.y += double(v.y);
+    }
+    __shared__ double2 red[8][TB];
+    red[w][r] = a;
+    __syncthreads();
+    if (w != 0) return;
+    a = red[0][r];
+#pragma unroll
+    for (int q = 1; q < 8; ++q) a += red[q][r];
+    const int64_t m = I * TB + r;
+    if (m < N) {
+        if (SUB) y[m] = b[m] - a;
+        else y[m] = a;
+    }
+}
+
 template <typename T, bool SUB>
 __global__ __launch_bounds__(512) void k_sym_reduce(int64_t N, const int64_t *__restrict__ seg, int64_t nslots,
                                                     const T *__restrict__ part, T *__restrict__ Y, int64_t ldy,
@@ -713,6 +744,21 @@ __global__ __launch_bounds__(512) void k_sym_reduce_g(const GProb *__restrict__ 
     reduce_rows<T, SUB>(P.N, P.seg, I, reinterpret_cast<const V2 *>(part) + gc.poff[c] * TB,
                         reinterpret_cast<V2 *>(Y) + gc.yoff[c],
                         SUB ? reinterpret_cast<const V2 *>(B) + gc.yoff[c] : nullptr);
+}
+
+// Grouped reduce of the matrix-core pass's FP32 partial sums (FP64 sums, FP64 vectors)
+template <bool SUB>
+__global__ __launch_bounds__(512) void k_sym_reduce_gf(const GProb *__restrict__ probs, GCols gc,
+                                                       const int32_t *__restrict__ items, const float *__restrict__ part,
+                                                       double *__restrict__ Y, const double *__restrict__ B,
+                                                       const int *__restrict__ skip, int64_t sks)
+{
+    const int64_t b = blockIdx.x;
+    const int32_t c = items[2 * b], I = items[2 * b + 1];
+    if (skip && skip[int64_t(c) * sks]) return;
+    const GProb P = probs[gc.prob[c]];
+    reduce_rows_f<SUB>(P.N, P.seg, I, reinterpret_cast<const float2 *>(part) + gc.poff[c] * TB,
+                       reinterpret_cast<double2 *>(Y) + gc.yoff[c], SUB ? reinterpret_cast<const double2 *>(B) + gc.yoff[c] : nullptr);
 }
 
 template <typename T>
@@ -1187,9 +1233,16 @@ void grouped_product(bool mat64, const GProb *probs, const GCols &gc, const int3
         if (mat64)
             hipLaunchKernelGGL(k_sym_tiles_gm64, dim3(unsigned(nitems)), dim3(256), 0, s, probs, gc, items, G,
                                (const double *)X, (double *)part, skip, sks);
-        else
+        else {   // FP32 partial sums, reduced here
             hipLaunchKernelGGL(k_sym_tiles_gm, dim3(unsigned(nitems)), dim3(256), 0, s, probs, gc, items, G,
-                               (const double *)X, (double *)part, skip, sks);
+                               (const double *)X, (float *)part, skip, sks);
+            if (B) hipLaunchKernelGGL(k_sym_reduce_gf<true>, dim3(unsigned(nritems)), dim3(512), 0, s, probs, gc, ritems,
+                                      (const float *)part, (double *)Y, (const double *)B, skip, sks);
+            else hipLaunchKernelGGL(k_sym_reduce_gf<false>, dim3(unsigned(nritems)), dim3(512), 0, s, probs, gc, ritems,
+                                    (const float *)part, (double *)Y, nullptr, skip, sks);
+            BIE_HIP(hipGetLastError());
+            return;
+        }
     } else if (mat64) {
         if (pf) hipLaunchKernelGGL((k_sym_tiles_g<double, double, true>), dim3(unsigned(nitems)), dim3(256), 0, s, probs,
                                    gc, items, G, (const double *)X, (double *)part, skip, sks);
