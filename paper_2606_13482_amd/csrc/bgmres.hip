@@ -1399,6 +1399,7 @@ __global__ __launch_bounds__(256) void k_bls_apply(GDev *__restrict__ gd, const 
     double2 *H = g.Rt + int64_t(j) * (m + 1) * r * r;
     const int nu = 2 * r * r;   // entries of U (and of M) per block column, <= 2048
     double2 pu[8], pm[8];
+    double2 ph = make_double2(0.0, 0.0);   // the row entry t of the next lower half (r nc <= 256 entries)
     auto fetch = [&](int i) {
         const double2 *Ui = g.U + int64_t(i) * nu, *Mi = g.Mw + int64_t(i) * nu;
 #pragma unroll
@@ -1407,6 +1408,9 @@ __global__ __launch_bounds__(256) void k_bls_apply(GDev *__restrict__ gd, const 
             pu[u] = e < nu ? Ui[e] : make_double2(0.0, 0.0);
             pm[u] = e < nu ? Mi[e] : make_double2(0.0, 0.0);
         }
+        // rows (i + 1) r .. + r of the column block, the lower half of block i's window
+        // (untouched until then: this workgroup writes only rows below the window)
+        if (i + 1 <= j && t < r * nc) ph = H[int64_t((i + 1) * r + t / nc) * r + c0 + t % nc];
     };
     fetch(0);
     for (int e = t; e < 2 * r * nc; e += 256) X[e / nc][e % nc] = H[int64_t(e / nc) * r + c0 + e % nc];
@@ -1451,13 +1455,14 @@ __global__ __launch_bounds__(256) void k_bls_apply(GDev *__restrict__ gd, const 
             X[row][c] = csub(X[row][c], cadd(cadd(s0, s1), cadd(s2, s3)));
         }
         __syncthreads();
-        // rows ir .. ir + r are final; shift the lower half up and load the next rows
+        // rows ir .. ir + r are final; shift the lower half up and take the next rows
+        // (fetched with block i + 1's reflectors)
         if (i + 1 < j) {
-            for (int e = t; e < r * nc; e += 256) {
-                const int row = e / nc, c = e % nc;
+            if (t < r * nc) {
+                const int row = t / nc, c = t % nc;
                 H[int64_t(i * r + row) * r + c0 + c] = X[row][c];
                 X[row][c] = X[r + row][c];
-                X[r + row][c] = H[int64_t((i + 2) * r + row) * r + c0 + c];
+                X[r + row][c] = ph;
             }
         } else {
             for (int e = t; e < 2 * r * nc; e += 256) H[int64_t(i * r + e / nc) * r + c0 + e % nc] = X[e / nc][e % nc];
