@@ -1380,6 +1380,7 @@ __device__ void wy_apply(double2 (*X)[XC], double2 (*Us)[BMAX + 1], double2 (*Ts
 }
 
 constexpr int CS = 8;   // columns of the new block column per workgroup of k_bls_apply
+static_assert(BMAX * CS <= 256, "k_bls_apply keeps one entry of the r x CS row window per thread");
 
 // The reflectors of block columns 0 .. j-1 applied, in order, to the new block
 // column of Hbar as x -= M_i (U_i^H x); the columns are independent, CS of them
