@@ -977,7 +977,15 @@ def counters_probe(args, bie, torch):
     for _ in range(5):
         op.apply(Xb, block="fp64")
     dte, pte, _ = planewave_batch(bie, random_directions(args.test_dirs, 55))
-    _, sth = op.solve(op.rhs(dte, pte), mixed_opts(args, bie, args.restart))
+    Bh = op.rhs(dte, pte)
+    torch.cuda.synchronize()
+    bie.prof_enable(True)
+    prof_reset(bie)
+    _, sth = op.solve(Bh, mixed_opts(args, bie, args.restart))
+    torch.cuda.synchronize()
+    orth = {kk: bie.prof_read(kk, columns=True) for kk in (4, 5)}   # launches, ms, basis pairs / vectors
+    bie.prof_enable(False)
+    del Bh
     probs = uneven_batch()
     ops = [bie.Operator(p["V"], p["T"], p["k"], storage="c64", keep_fp64=True) for p in probs]
     Bs = [o.rhs(p["dirs"], p["pols"]) for o, p in zip(ops, probs)]
@@ -997,6 +1005,11 @@ def counters_probe(args, bie, torch):
                                          "block_columns": 512, "copy_bytes": a.numel() * 4, "copies": 3,
                                          "headline_solve_rhs": len(sth),
                                          "headline_solve_converged": float(np.mean([s["converged"] for s in sth])),
+                                         "headline_solve_basis_dots": {"launches": orth[4][0],
+                                                                       "basis_vector_column_pairs": orth[4][2]},
+                                         "headline_solve_basis_update": {"launches": orth[5][0],
+                                                                         "basis_vectors_read": orth[5][2],
+                                                                         "basis_bytes_per_entry": 4},
                                          "batch_packed_fp32_bytes": int(sum(4 * o.N * (o.N + 1) for o in ops)),
                                          "batch_columns": int(sum(b.shape[0] for b in Bs))}}),
           flush=True)
